@@ -1,0 +1,530 @@
+"""Pins of the FP64 oracle against closed forms, invariants and brute force.
+
+Each test fixes something the paper or plain mathematics determines, so that a
+plausible slip in the oracle (a dropped term, a wrong sign or index, a transposed
+operand) fails at least one of them:
+  P-a  one isotropic Gaussian on the optical axis: eq. 2-3 and eq. 7-9 in closed form
+  P-b  off-axis isotropic EWA covariance in closed form; q and -q; isotropic => dL/dq = 0
+  P-c  two Gaussians: front-to-back order and its swap (eq. 7)
+  P-d  sum of weights = 1 - T_final <= 1, linearity in features, one-hot logits
+  P-e  tiled == brute force, bitwise; cut-off-free mode == eq. 7-9 written out
+  P-f  sort stage == lexicographic sort; ranges consistent
+  P-g  loss values by hand, CE gradient, box pyramid of a constant
+  P-h  analytic gradient == FP64 central finite differences; rigid-motion identity
+  P-i  scaling the world and the camera scales depth only
+  P-j  head with identity-like weights returns its input
+  P-k  pyramid levels: projected means scale by exactly 2^-l
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_01217_amd import scenes
+
+
+def make_scene(mean, log_scale, quat, opac, rgb, sem):
+    f = lambda a: np.asarray(a, np.float64)  # noqa: E731  (kept in double for exact pins)
+    sem = f(sem)
+    return scenes.Scene(f(mean), f(log_scale), f(quat), f(opac), f(rgb), sem, None, sem.shape[1])
+
+
+def view(W=64, H=48, f=50.0, cx=None, cy=None, R=None, t=None, levels=1):
+    return scenes.View(np.eye(3) if R is None else np.asarray(R, float),
+                       np.zeros(3) if t is None else np.asarray(t, float), f, f,
+                       W / 2 if cx is None else cx, H / 2 if cy is None else cy, W, H, levels)
+
+
+def planes(img, K, W, H, pix0=0):
+    return img[pix0 * K: pix0 * K + K * W * H].reshape(K, H, W)
+
+
+def pixel_grid(W, H):
+    u, v = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+    return u, v
+
+
+# ---------------------------------------------------------------- P-a
+def test_single_gaussian_on_axis_closed_form():
+    z, r, a = 3.0, 0.05, 0.3
+    sc = make_scene([[0, 0, z]], [[math.log(r)] * 3], [[0.3, 0.5, -0.2, 0.7]], [a],
+                    [[0.2, 0.7, 0.9]], [[1.5, -0.5, 0.25]])
+    W, H, f = 64, 48, 80.0
+    v = view(W, H, f)
+    cfg = oracle.Config(eps=0.0).exact()
+    out = oracle.render(cfg, sc, [v])
+    I = planes(out["img"], 7, W, H)
+    u, vv = pixel_grid(W, H)
+    r2d = f * r / z                          # eq. 2
+    o = 1 / (1 + math.exp(-a))
+    g2d = o * np.exp(-((u - W / 2) ** 2 + (vv - H / 2) ** 2) / (2 * r2d ** 2))   # eq. 3
+    for c, val in enumerate([0.2, 0.7, 0.9]):
+        np.testing.assert_allclose(I[c], val * g2d, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(I[3], z * g2d, rtol=1e-12, atol=1e-15)
+    for c, val in enumerate([1.5, -0.5, 0.25]):
+        np.testing.assert_allclose(I[4 + c], val * g2d, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(out["T"].reshape(H, W), 1 - g2d, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- P-b
+def test_off_axis_isotropic_ewa_closed_form():
+    rng = np.random.default_rng(5)
+    n = 20
+    mean = np.stack([rng.uniform(-0.8, 0.8, n), rng.uniform(-0.6, 0.6, n), rng.uniform(1.5, 4, n)], 1)
+    r = np.exp(rng.normal(-3, 0.3, n))
+    quat = rng.normal(size=(n, 4))
+    sc = make_scene(mean, np.log(r)[:, None].repeat(3, 1), quat, np.zeros(n), np.ones((n, 3)), np.zeros((n, 1)))
+    f, eps = 60.0, 0.3
+    v = view(128, 96, f)
+    pp = oracle.preprocess(oracle.Config(eps=eps).exact(), sc, [v])
+    x, y, z = mean.T
+    s2 = (r * f / z) ** 2
+    a = s2 * (1 + x ** 2 / z ** 2) + eps
+    b = s2 * (x * y / z ** 2)
+    c = s2 * (1 + y ** 2 / z ** 2) + eps
+    det = a * c - b * b
+    np.testing.assert_allclose(pp["conic"], np.stack([c / det, -b / det, a / det], 1), rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(pp["m2"], np.stack([f * x / z + 64, f * y / z + 48], 1), rtol=1e-14)
+    np.testing.assert_allclose(pp["depth"], z, rtol=1e-15)
+    # radius: 3 standard deviations along the major axis (eigenvalue of the 2x2
+    # covariance), at least 3*sqrt(mid + sqrt(0.1)); rect = tiles meeting [m-r, m+r]^2
+    lam = np.array([np.linalg.eigvalsh(np.array([[a[i], b[i]], [b[i], c[i]]])).max() for i in range(n)])
+    mid = 0.5 * (a + c)
+    expect_r = np.ceil(3 * np.sqrt(np.maximum(lam, mid + math.sqrt(0.1))))
+    np.testing.assert_array_equal(pp["radius"], expect_r.astype(np.int32))
+    mx, my = f * x / z + 64, f * y / z + 48
+    cfg_r = oracle.Config(eps=eps)
+    pr = oracle.preprocess(cfg_r, sc, [v])
+    x0 = np.clip(np.floor((mx - expect_r) / 16), 0, 8)
+    x1 = np.clip(np.floor((mx + expect_r) / 16) + 1, 0, 8)
+    y0 = np.clip(np.floor((my - expect_r) / 16), 0, 6)
+    y1 = np.clip(np.floor((my + expect_r) / 16) + 1, 0, 6)
+    np.testing.assert_array_equal(pr["rect"], np.stack([x0, y0, x1, y1], 1).astype(np.int32))
+
+
+def test_quaternion_sign_and_isotropic_rotation_invariance():
+    rng = np.random.default_rng(6)
+    n = 12
+    mean = np.stack([rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n), rng.uniform(2, 3, n)], 1)
+    ls = rng.normal(-2.5, 0.3, (n, 3))
+    q = rng.normal(size=(n, 4))
+    sc = make_scene(mean, ls, q, rng.normal(size=n), rng.uniform(size=(n, 3)), rng.normal(size=(n, 2)))
+    sc_neg = make_scene(mean, ls, -q, sc.opacity, sc.rgb, sc.sem)
+    v = view(48, 40, 40.0)
+    cfg = oracle.Config()
+    a = oracle.render(cfg, sc, [v])["img"]
+    b = oracle.render(cfg, sc_neg, [v])["img"]
+    np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-15)
+    # isotropic => the render does not depend on q, so dL/dq = 0
+    iso = make_scene(mean, np.repeat(ls[:, :1], 3, 1), q, sc.opacity, sc.rgb, sc.sem)
+    gimg = rng.normal(size=a.shape)
+    g = oracle.backward(cfg, iso, [v], gimg)
+    assert np.abs(g["quat"]).max() < 1e-12 * max(1.0, np.abs(g["mean"]).max())
+
+
+# ---------------------------------------------------------------- P-c
+def test_two_gaussian_order():
+    W, H, f = 32, 32, 40.0
+    def two(z1, z2):
+        return make_scene([[0, 0, z1], [0.01, 0, z2]], [[math.log(0.05)] * 3] * 2, [[1, 0, 0, 0]] * 2,
+                          [0.5, -0.2], [[1, 0, 0], [0, 1, 0]], [[1.0], [-1.0]])
+    cfg = oracle.Config(eps=0.0).exact()
+    v = view(W, H, f)
+    pp = oracle.preprocess(cfg, two(2.0, 3.0), [v])
+    u, vv = pixel_grid(W, H)
+    def alpha(k):
+        m, cn, o = pp["m2"][k], pp["conic"][k], pp["opacity"][k]
+        dx, dy = u - m[0], vv - m[1]
+        return o * np.exp(-0.5 * (cn[0] * dx * dx + cn[2] * dy * dy) - cn[1] * dx * dy)
+    a1, a2 = alpha(0), alpha(1)
+    I = planes(oracle.render(cfg, two(2.0, 3.0), [v])["img"], 5, W, H)
+    np.testing.assert_allclose(I[0], a1, rtol=1e-12, atol=1e-15)            # front one unattenuated
+    np.testing.assert_allclose(I[1], a2 * (1 - a1), rtol=1e-12, atol=1e-15)  # back one behind it
+    np.testing.assert_allclose(I[4], a1 - a2 * (1 - a1), rtol=1e-11, atol=1e-14)
+    # swap the depths: the roles swap (footprints change with depth, so recompute)
+    sc2 = two(3.0, 2.0)
+    pp2 = oracle.preprocess(cfg, sc2, [v])
+    pp = pp2
+    b1, b2 = alpha(0), alpha(1)
+    I2 = planes(oracle.render(cfg, sc2, [v])["img"], 5, W, H)
+    np.testing.assert_allclose(I2[1], b2, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(I2[0], b1 * (1 - b2), rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------- P-d
+def test_weights_sum_and_linearity():
+    sc, views = scenes.config_tiny()
+    cfg = oracle.Config()
+    ones = scenes.Scene(sc.mean, sc.log_scale, sc.quat, sc.opacity, np.ones_like(sc.rgb),
+                        np.zeros((sc.n, 3)), None, 3)
+    e = np.zeros((sc.n, 3)); e[:, 1] = 1.0
+    out = oracle.render(cfg, ones, views, sem=e)
+    W, H = 128, 96
+    I = planes(out["img"], 7, W, H)
+    T = out["T"].reshape(H, W)
+    assert np.all(T >= 0) and np.all(T <= 1)
+    np.testing.assert_allclose(I[0], 1 - T, rtol=1e-12, atol=1e-14)     # sum of weights
+    assert np.all(I[0] <= 1 + 1e-12)
+    np.testing.assert_allclose(I[5], 1 - T, rtol=1e-12, atol=1e-14)     # one-hot logits
+    np.testing.assert_array_equal(I[4], 0)
+    # linearity in features: render(a f1 + b f2) = a render(f1) + b render(f2)
+    rng = np.random.default_rng(1)
+    s1, s2 = rng.normal(size=(sc.n, 2)), rng.normal(size=(sc.n, 2))
+    r1 = planes(oracle.render(cfg, sc, views, sem=s1)["img"], 6, W, H)[4:]
+    r2 = planes(oracle.render(cfg, sc, views, sem=s2)["img"], 6, W, H)[4:]
+    r3 = planes(oracle.render(cfg, sc, views, sem=2 * s1 - 3 * s2)["img"], 6, W, H)[4:]
+    np.testing.assert_allclose(r3, 2 * r1 - 3 * r2, rtol=1e-10, atol=1e-12)
+
+
+def test_transmittance_monotone_along_list():
+    # rendering with t_min = 0 and truncating the scene to the k front-most Gaussians
+    # gives a non-increasing T as k grows
+    sc, views = scenes.config_tiny()
+    order = np.argsort(sc.mean[:, 2])
+    cfg = oracle.Config(t_min=0.0)
+    prev = None
+    for k in (50, 200, 800, 2000):
+        idx = np.sort(order[:k])
+        sub = scenes.Scene(sc.mean[idx], sc.log_scale[idx], sc.quat[idx], sc.opacity[idx], sc.rgb[idx],
+                           sc.sem[idx], None, 8)
+        T = oracle.render(cfg, sub, views)["T"]
+        if prev is not None:
+            assert np.all(T <= prev + 1e-15)
+        prev = T
+
+
+# ---------------------------------------------------------------- P-e
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (16, 8)])
+def test_tiled_equals_brute_force(tile):
+    rng = np.random.default_rng(7)
+    n = 64
+    mean = np.stack([rng.uniform(-1, 1, n), rng.uniform(-0.8, 0.8, n), rng.uniform(1, 4, n)], 1)
+    sc = make_scene(mean, rng.normal(-2.5, 0.5, (n, 3)), rng.normal(size=(n, 4)), rng.normal(size=n),
+                    rng.uniform(size=(n, 3)), rng.normal(size=(n, 3)))
+    sc.mean[5, 2] = sc.mean[9, 2]              # an exact depth tie: broken by index
+    cfg = oracle.Config(tile_w=tile[0], tile_h=tile[1])
+    v = view(64, 48, 40.0)
+    a = oracle.render(cfg, sc, [v])
+    b = oracle.render(cfg, sc, [v], brute=True)
+    for k in ("img", "T", "n_contrib"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_exact_mode_matches_eq7_written_out():
+    rng = np.random.default_rng(8)
+    n = 24
+    mean = np.stack([rng.uniform(-0.7, 0.7, n), rng.uniform(-0.5, 0.5, n), rng.uniform(1.5, 4, n)], 1)
+    sc = make_scene(mean, rng.normal(-2.2, 0.4, (n, 3)), rng.normal(size=(n, 4)), rng.normal(size=n) - 1,
+                    rng.uniform(size=(n, 3)), rng.normal(size=(n, 2)))
+    W, H = 40, 32
+    v = view(W, H, 30.0)
+    cfg = oracle.Config().exact()
+    pp = oracle.preprocess(cfg, sc, [v])
+    I = planes(oracle.render(cfg, sc, [v])["img"], 6, W, H)
+    u, vv = pixel_grid(W, H)
+    order = sorted(range(n), key=lambda i: (np.float32(pp["depth"][i]), i))
+    g = []
+    for i in order:
+        m, cn, o = pp["m2"][i], pp["conic"][i], pp["opacity"][i]
+        dx, dy = u - m[0], vv - m[1]
+        g.append(np.minimum(0.99, o * np.exp(np.minimum(0, -0.5 * (cn[0] * dx * dx + cn[2] * dy * dy) - cn[1] * dx * dy))))
+    feats = [np.concatenate([sc.rgb[i], [pp["depth"][i]], sc.sem[i]]) for i in order]
+    ref = np.zeros((6, H, W))
+    for k in range(n):                        # eq. 7-9: sum_i f_i g_i prod_{j<i} (1 - g_j)
+        prod = np.ones((H, W))
+        for j in range(k):
+            prod = prod * (1 - g[j])
+        ref += feats[k][:, None, None] * (g[k] * prod)[None]
+    np.testing.assert_allclose(I, ref, rtol=1e-11, atol=1e-14)
+
+
+# ---------------------------------------------------------------- P-f
+def test_sort_stage_is_lexicographic():
+    rng = np.random.default_rng(9)
+    views = [view(100, 60, 50.0, levels=2), view(64, 64, 40.0, levels=1)]
+    n_items, _, tiles = oracle.layout(views)
+    n = 300
+    m2hi = rng.uniform(-20, 120, (n_items * n, 2)).astype(np.float32)
+    m2lo = (rng.normal(size=(n_items * n, 2)) * 1e-6).astype(np.float32)
+    radius = rng.integers(0, 25, n_items * n).astype(np.int32)
+    depth = rng.choice(np.float32([1.0, 1.5, 2.25, 3.0]), n_items * n).astype(np.float32)  # many ties
+    keys, vals, ranges = oracle.sort_stage(views, n, m2hi, m2lo, radius, depth)
+    assert np.all((keys[1:] > keys[:-1]) | ((keys[1:] == keys[:-1]) & (vals[1:] > vals[:-1])))
+    assert int((ranges[:, 1] - ranges[:, 0]).sum()) == len(keys)
+    its = oracle.items(views)
+    counts = np.zeros(tiles, np.int64)
+    for k, it in enumerate(its):
+        for i in range(n):
+            q = k * n + i
+            r = int(radius[q])
+            if r <= 0:
+                continue
+            mx = float(m2hi[q, 0]) + float(m2lo[q, 0])
+            my = float(m2hi[q, 1]) + float(m2lo[q, 1])
+            x0 = min(it["ntx"], max(0, math.floor((mx - r) / 16)))
+            x1 = min(it["ntx"], max(0, math.floor((mx + r) / 16) + 1))
+            y0 = min(it["nty"], max(0, math.floor((my - r) / 16)))
+            y1 = min(it["nty"], max(0, math.floor((my + r) / 16) + 1))
+            for ty in range(y0, y1):
+                for tx in range(x0, x1):
+                    counts[it["tile0"] + ty * it["ntx"] + tx] += 1
+    np.testing.assert_array_equal(ranges[:, 1] - ranges[:, 0], counts)
+    for t in range(tiles):
+        s, e = ranges[t]
+        assert np.all((keys[s:e] >> np.uint64(32)) == t)
+
+
+# ---------------------------------------------------------------- P-g
+def test_loss_hand_values_and_gradient():
+    v = view(4, 2, 4.0)
+    S = 3
+    img = np.zeros((7, 2, 4))
+    img[0] = 0.5; img[1] = 0.25; img[2] = 1.0
+    img[3] = [[1, 2, 3, 4], [0, 0, 1, 1]]
+    img[4:] = np.arange(3)[:, None, None] * 1.0
+    t_rgb = np.zeros((3, 8)); t_rgb[0] = 1.0
+    t_depth = np.array([1, 0, 2, 4, 0, 0, 0, 3.0])
+    t_lab = np.array([0, 1, 2, 0, 1, 2, 0, 1])
+    ls, g = oracle.loss([v], S, img.reshape(-1), t_rgb.reshape(-1), t_depth, t_lab, w=(1, 1, 1))
+    # rgb: |0.5-1| + |0.25| + |1| per pixel over 3*8 values
+    assert ls[0, 0] == pytest.approx((0.5 + 0.25 + 1.0) * 8 / 24)
+    # depth: valid pixels 0,2,3,7: |1-1| + |3-2| + |4-4| + |1-3| over 4
+    assert ls[0, 1] == pytest.approx(3.0 / 4)
+    lse = math.log(1 + math.e + math.e ** 2)
+    assert ls[0, 2] == pytest.approx(np.mean([lse - t for t in t_lab]))
+    G = g.reshape(7, 8)
+    sm = np.exp(np.arange(3) - lse)
+    for p in range(8):
+        oh = np.eye(3)[t_lab[p]]
+        np.testing.assert_allclose(G[4:, p], (sm - oh) / 8, rtol=1e-13)
+        assert abs(G[4:, p].sum()) < 1e-15
+    assert G[0, 0] == pytest.approx(-1 / 24) and G[1, 0] == pytest.approx(1 / 24)
+    assert G[3, 1] == 0 and G[3, 0] == 0 and G[3, 7] == pytest.approx(-1 / 4)
+
+
+def test_loss_gradient_finite_difference():
+    rng = np.random.default_rng(10)
+    v = view(8, 6, 4.0)
+    S = 4
+    img = rng.normal(size=(4 + S) * 48)
+    t_rgb, t_depth, t_lab = rng.uniform(size=3 * 48), rng.uniform(0, 2, 48), rng.integers(0, S, 48)
+    t_depth[::5] = 0
+    w = (0.7, 1.3, 0.9)
+    ls, g = oracle.loss([v], S, img, t_rgb, t_depth, t_lab, w=w)
+    L = lambda x: float(np.dot(w, oracle.loss([v], S, x, t_rgb, t_depth, t_lab)[0][0]))  # noqa: E731
+    h = 1e-6
+    for j in rng.choice(len(img), 40, replace=False):
+        e = np.zeros_like(img); e[j] = h
+        fd = (L(img + e) - L(img - e)) / (2 * h)
+        assert fd == pytest.approx(g[j], rel=1e-6, abs=1e-9)
+
+
+def test_box_pyramid_of_constant_is_constant():
+    v = view(32, 16, 10.0, levels=3)
+    S = 2
+    n_items, P, _ = oracle.layout([v])
+    img = np.zeros(P * 6)
+    its = oracle.items([v])
+    base = planes(img, 6, 32, 16)
+    vals = [0.3, -1.0, 2.0, 1.5, 0.0, 4.0]
+    for c, val in enumerate(vals):
+        base[c] = val
+    out, lab = oracle.downsample([v], S, img)
+    for it in its[1:]:
+        I = planes(out, 6, it["W"], it["H"], it["pix0"])
+        for c, val in enumerate(vals):
+            np.testing.assert_allclose(I[c], val, rtol=0, atol=1e-15)
+        np.testing.assert_array_equal(lab[it["pix0"]: it["pix0"] + it["W"] * it["H"]], 1)
+    # depth uses only positive children
+    img2 = img.copy()
+    b = planes(img2, 6, 32, 16)
+    b[3, 0, 0] = 0.0
+    out2, _ = oracle.downsample([v], S, img2)
+    assert planes(out2, 6, 16, 8, its[1]["pix0"])[3, 0, 0] == pytest.approx(1.5)
+
+
+# ---------------------------------------------------------------- P-h
+def _fd_scene(seed, n=10, clamp_one=False):
+    rng = np.random.default_rng(seed)
+    mean = np.stack([rng.uniform(-0.5, 0.5, n), rng.uniform(-0.4, 0.4, n), rng.uniform(1.5, 3, n)], 1)
+    if clamp_one:
+        mean[0] = [2.5, 0.1, 2.0]             # outside the guard band in x
+    sc = make_scene(mean, rng.normal(-2.3, 0.3, (n, 3)), rng.normal(size=(n, 4)), rng.normal(size=n) - 0.5,
+                    rng.uniform(size=(n, 3)), rng.normal(size=(n, 3)))
+    return sc, rng
+
+
+def _rodrigues(phi):
+    th = np.linalg.norm(phi)
+    Kx = np.array([[0, -phi[2], phi[1]], [phi[2], 0, -phi[0]], [-phi[1], phi[0], 0]])
+    if th < 1e-300:
+        return np.eye(3) + Kx
+    return np.eye(3) + math.sin(th) / th * Kx + (1 - math.cos(th)) / th ** 2 * Kx @ Kx
+
+
+def _exp_se3(xi):
+    rho, phi = xi[:3], xi[3:]
+    th = np.linalg.norm(phi)
+    R = _rodrigues(phi)
+    Kx = np.array([[0, -phi[2], phi[1]], [phi[2], 0, -phi[0]], [-phi[1], phi[0], 0]])
+    if th < 1e-12:
+        V = np.eye(3) + 0.5 * Kx
+    else:
+        V = np.eye(3) + (1 - math.cos(th)) / th ** 2 * Kx + (th - math.sin(th)) / th ** 3 * Kx @ Kx
+    return R, V @ rho
+
+
+@pytest.mark.parametrize("clamp_one", [False, True])
+def test_backward_matches_central_differences(clamp_one):
+    sc, rng = _fd_scene(11, clamp_one=clamp_one)
+    Rv = _rodrigues(np.array([0.05, -0.1, 0.08]))
+    v = view(40, 32, 30.0, R=Rv, t=[0.05, -0.02, 0.1])
+    cfg = oracle.Config().exact()
+    K = 7
+    out = oracle.render(cfg, sc, [v])
+    gimg = rng.normal(size=out["img"].shape)
+    g = oracle.backward(cfg, sc, [v], gimg)
+
+    def L(s, vv=v):
+        return float(np.dot(gimg, oracle.render(cfg, s, [vv])["img"]))
+
+    h = 1e-6
+    # central differences lose about eps*|L|/h to rounding: part of the allowance
+    fd_round = 50 * np.finfo(float).eps * abs(L(sc)) / h
+    fields = ["mean", "log_scale", "quat", "opacity", "rgb", "sem"]
+    for name in fields:
+        arr = getattr(sc, name)
+        for idx in np.ndindex(arr.shape):
+            sp, sm = sc.copy(), sc.copy()
+            getattr(sp, name)[idx] += h
+            getattr(sm, name)[idx] -= h
+            fd = (L(sp) - L(sm)) / (2 * h)
+            an = g[name][idx]
+            scale = max(abs(fd), 1e-3 * np.abs(g[name]).max(), 1e-9)
+            assert abs(an - fd) <= 1e-6 * scale + fd_round, (name, idx, an, fd)
+    # pose tangent, left perturbation Exp(xi) T_cw
+    for j in range(6):
+        xi = np.zeros(6); xi[j] = h
+        Rp, tp = _exp_se3(xi)
+        Rm, tm = _exp_se3(-xi)
+        vp = view(40, 32, 30.0, R=Rp @ v.R, t=Rp @ v.t + tp)
+        vm = view(40, 32, 30.0, R=Rm @ v.R, t=Rm @ v.t + tm)
+        fd = (L(sc, vp) - L(sc, vm)) / (2 * h)
+        an = g["pose"][0, j]
+        assert abs(an - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g["pose"]).max()) + fd_round, (j, an, fd)
+    # rigid-motion identity: translating the camera == translating every mean by -R^T rho
+    np.testing.assert_allclose(g["pose"][0, :3], v.R @ g["mean"].sum(0), rtol=1e-10, atol=1e-13)
+    assert K == out["K"]
+
+
+def test_backward_with_cutoffs_matches_differences_on_smooth_parameters():
+    # With the default cut-offs the render is piecewise smooth; colour gradients are
+    # exact (the render is linear in features) and geometry gradients match FD away
+    # from the thresholds.
+    sc, views = scenes.config_tiny()
+    sc = scenes.Scene(*(np.asarray(getattr(sc, f), np.float64) for f in
+                        ("mean", "log_scale", "quat", "opacity", "rgb", "sem")), None, 8)
+    cfg = oracle.Config()
+    rng = np.random.default_rng(12)
+    out = oracle.render(cfg, sc, views)
+    gimg = rng.normal(size=out["img"].shape)
+    g = oracle.backward(cfg, sc, views, gimg)
+    # linear in rgb / sem: gradient = sum_p w_p gimg_p, checked through a second render
+    base = float(np.dot(gimg, out["img"]))
+    d_rgb = rng.normal(size=sc.rgb.shape)
+    s2 = sc.copy(); s2.rgb = sc.rgb + d_rgb
+    np.testing.assert_allclose(float(np.dot(gimg, oracle.render(cfg, s2, views)["img"])) - base,
+                               float((g["rgb"] * d_rgb).sum()), rtol=1e-9)
+    h = 1e-7
+    good = bad = 0
+    for i in rng.choice(sc.n, 40, replace=False):
+        if g["gflag"][i]:
+            continue
+        for name, shape in (("mean", 3), ("log_scale", 3), ("opacity", None)):
+            for c in (range(shape) if shape else [None]):
+                idx = (i, c) if shape else (i,)
+                sp, sm = sc.copy(), sc.copy()
+                getattr(sp, name)[idx] += h
+                getattr(sm, name)[idx] -= h
+                # difference image first: pixels the Gaussian does not touch cancel exactly
+                diff = oracle.render(cfg, sp, views)["img"] - oracle.render(cfg, sm, views)["img"]
+                fd = float(np.dot(gimg, diff)) / (2 * h)
+                an = g[name][idx]
+                if abs(an - fd) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(g[name]).max()) + 1e-8:
+                    good += 1
+                else:
+                    bad += 1     # a cut-off crossed inside [-h, h]
+    assert good > 150 and bad <= 0.02 * (good + bad), (good, bad)
+
+
+# ---------------------------------------------------------------- P-i
+def test_scaling_world_and_camera_scales_depth_only():
+    sc, views = scenes.config_tiny()
+    sc = scenes.Scene(*(np.asarray(getattr(sc, f), np.float64) for f in
+                        ("mean", "log_scale", "quat", "opacity", "rgb", "sem")), None, 8)
+    v = view(128, 96, 100.0, R=_rodrigues(np.array([0.02, 0.03, -0.01])), t=[0.1, -0.05, 0.3])
+    s = 2.5
+    big = sc.copy()
+    big.mean = sc.mean * s
+    big.log_scale = sc.log_scale + math.log(s)
+    vb = view(128, 96, 100.0, R=v.R, t=np.asarray(v.t) * s)
+    cfg = oracle.Config()
+    a = planes(oracle.render(cfg, sc, [v])["img"], 12, 128, 96)
+    b = planes(oracle.render(cfg, big, [vb])["img"], 12, 128, 96)
+    np.testing.assert_allclose(b[[0, 1, 2] + list(range(4, 12))], a[[0, 1, 2] + list(range(4, 12))],
+                               rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(b[3], s * a[3], rtol=1e-9, atol=1e-12)
+
+
+# ---------------------------------------------------------------- P-j
+def test_head_identity_weights():
+    rng = np.random.default_rng(13)
+    E = rng.normal(size=(50, 16))
+    W1 = np.zeros((64, 16)); W1[:16] = np.eye(16); W1[16:32] = -np.eye(16)
+    W2 = np.zeros((16, 64)); W2[:, :16] = np.eye(16); W2[:, 16:32] = -np.eye(16)
+    out = oracle.head_forward(E, W1, np.zeros(64), W2, np.zeros(16))
+    np.testing.assert_allclose(out, E, rtol=0, atol=1e-15)
+    # and against a dense FP64 matmul of the same values
+    W1r, W2r = rng.normal(size=(64, 16)), rng.normal(size=(52, 64))
+    b1, b2 = rng.normal(size=64), rng.normal(size=52)
+    ref = np.maximum(E @ W1r.T + b1, 0) @ W2r.T + b2
+    np.testing.assert_allclose(oracle.head_forward(E, W1r, b1, W2r, b2), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_head_backward_finite_difference():
+    rng = np.random.default_rng(14)
+    E = rng.normal(size=(6, 16))
+    W1, b1, W2, b2 = rng.normal(size=(64, 16)), rng.normal(size=64), rng.normal(size=(5, 64)), rng.normal(size=5)
+    G = rng.normal(size=(6, 5))
+    g = oracle.head_backward(E, W1, b1, W2, G)
+    L = lambda E, W1, b1, W2, b2: float((oracle.head_forward(E, W1, b1, W2, b2) * G).sum())  # noqa
+    h = 1e-6
+    args = dict(E=E, W1=W1, b1=b1, W2=W2, b2=b2)
+    for name in args:
+        a = args[name]
+        for idx in list(np.ndindex(a.shape))[:: max(1, a.size // 25)]:
+            p = {k: v.copy() for k, v in args.items()}
+            m = {k: v.copy() for k, v in args.items()}
+            p[name][idx] += h
+            m[name][idx] -= h
+            fd = (L(**p) - L(**m)) / (2 * h)
+            assert g[name][idx] == pytest.approx(fd, rel=1e-6, abs=1e-8), (name, idx)
+
+
+# ---------------------------------------------------------------- P-k
+def test_pyramid_levels_scale_projection_exactly():
+    sc, views = scenes.config_room(n=20000, n_classes=4)
+    v = views[0]
+    pp = oracle.preprocess(oracle.Config(), sc, [v])
+    n = sc.n
+    m0 = pp["m2"][:n]
+    vis0 = pp["radius"][:n] > 0
+    its = oracle.items([v])
+    assert [(i["W"], i["H"]) for i in its] == [(1200, 680), (600, 340), (300, 170)]
+    for l in (1, 2):
+        ml = pp["m2"][l * n:(l + 1) * n]
+        both = vis0 & (pp["radius"][l * n:(l + 1) * n] > 0)
+        assert both.sum() > 100
+        np.testing.assert_array_equal(ml[both], m0[both] * 2.0 ** -l)
+        np.testing.assert_array_equal(pp["depth"][l * n:(l + 1) * n][both], pp["depth"][:n][both])
