@@ -1,0 +1,225 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) pyramid Gaussian-splatting rasterizer.
+ *
+ * The library renders RGB, depth and per-class semantics from 3D Gaussians at
+ * every level of an image pyramid, computes the per-level reconstruction loss,
+ * and back-propagates it to every Gaussian parameter and to an SE(3) tangent of
+ * every camera pose (RGBDS-SLAM, Sec. III-B to III-D, eq. 1-13).
+ *
+ * Conventions shared by every entry point
+ *  - All pointers named *_dev, and every pointer inside the structs below, are
+ *    device pointers (hipMalloc'd or torch-owned GPU memory) unless stated.
+ *    The caller owns every buffer, including workspaces; the library never
+ *    allocates, frees or waits on the host inside a call.
+ *  - `stream` is a hipStream_t passed as void*. Every call only enqueues work on
+ *    it and returns; results are ready when the stream is.
+ *  - Return value: GS_OK (0) or a negative gs_status. Argument errors are
+ *    detected on the host before anything is enqueued. No C++ exception crosses
+ *    the ABI. The functions keep no state between calls.
+ *  - Work item ("item"): one (view, pyramid level) pair. Level l of a view with
+ *    base size W x H has size (W >> l) x (H >> l) and intrinsics
+ *    fx/2^l, fy/2^l, cx/2^l, cy/2^l (Sec. III-C, eq. 4-6: the pyramid).
+ *    Items of one view are contiguous, in level order.
+ *  - Images are planar per item: channel c of pixel (x, y) of item i lives at
+ *    [pixel_base_i * C + c * W_i * H_i + y * W_i + x] for a C-channel image.
+ *    Pixel (x, y) is sampled at (x + 1/2, y + 1/2).
+ *  - Rendered channels: 0-2 RGB (eq. 7), 3 depth (eq. 8), 4.. semantics (eq. 9):
+ *    n_sem class logits (plain mode) or the 16-wide embedding (learned mode).
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gs_status {
+  GS_OK = 0,
+  GS_ERR_INVALID_ARG = -1,   /* a size, pointer or config field is out of range */
+  GS_ERR_WORKSPACE = -2,     /* workspace smaller than gs_workspace_size() asks */
+  GS_ERR_CAPACITY = -3,      /* reported through status_dev: duplicates > capacity */
+  GS_ERR_HIP = -4,           /* a HIP launch failed; gs_last_hip_error() has the code */
+  GS_ERR_UNSUPPORTED = -5    /* valid, but not built into this library */
+} gs_status;
+
+/* Rasterizer configuration. gs_config_default() fills the values listed. */
+typedef struct gs_config {
+  int32_t tile_w, tile_h;  /* 16, 16: screen tile (the only shape built) */
+  float z_near;            /* 0.2: cull Gaussians whose camera depth <= z_near */
+  float eps_dilate;        /* 0.3: added to the 2D covariance diagonal (px^2) */
+  float alpha_min;         /* 1/255: a Gaussian is skipped where alpha < alpha_min */
+  float alpha_max;         /* 0.99: alpha is clamped to alpha_max */
+  float t_min;             /* 1e-4: a pixel stops before T would fall below t_min */
+  float guard;             /* 1.3: x/z, y/z clamped to +-guard*(W/2)/fx inside J */
+  int32_t full_rect;       /* 0; 1 = every Gaussian covers every tile of its item */
+  int32_t n_sem;           /* composited semantic channels (plain: classes; learned: 16) */
+  int32_t variant;         /* render kernel variant; 0 = automatic */
+  int32_t reserved;
+} gs_config;
+
+/* One camera view: world -> camera transform x_c = R x_w + t (OpenCV axes,
+ * x right, y down, z forward), R row-major; and its items in the item table. */
+typedef struct gs_view {
+  float R[9];
+  float t[3];
+  int32_t item_first, item_count;
+} gs_view;
+
+/* One (view, level) item. Filled by the caller (gs_make_items() does it on the host). */
+typedef struct gs_item {
+  float fx, fy, cx, cy;    /* intrinsics of this level, pixels */
+  int32_t W, H;            /* level image size */
+  int32_t view, level;
+  int32_t tiles_x, tiles_y;
+  int32_t tile_base;       /* first global tile index of the item */
+  int32_t pad;
+  int64_t pixel_base;      /* first pixel of the item in the concatenated images */
+} gs_item;
+
+/* Gaussian parameters, structure of arrays, float32 (Sec. III-B, generalised to a
+ * per-axis scale and a rotation; the paper's isotropic primitive is the case of
+ * three equal scales). */
+typedef struct gs_gaussians {
+  int64_t n;
+  const float* mean;       /* [n][3] world position mu */
+  const float* log_scale;  /* [n][3] log of the per-axis standard deviation */
+  const float* quat;       /* [n][4] rotation (w, x, y, z), normalised inside */
+  const float* opacity;    /* [n]    logit; o = sigmoid */
+  const float* rgb;        /* [n][3] colour feature r (eq. 7) */
+  const float* sem;        /* [n][n_sem] semantic feature s (eq. 9), plain mode */
+  const uint16_t* emb;     /* [n][16] bfloat16 embedding, learned mode (else NULL) */
+} gs_gaussians;
+
+/* Per (item, Gaussian) projection, written by gs_preprocess, [n_items * n] each,
+ * entry e = item * n + gaussian. */
+typedef struct gs_projected {
+  float* rec;       /* [E][8]: mean2d hi x, y; mean2d lo x, y (mean2d = hi + lo);
+                       conic A, B, C (inverse 2D covariance [[A,B],[B,C]]); opacity */
+  float* depth;     /* [E] camera-space depth of the mean (sort key, depth feature) */
+  int32_t* radius;  /* [E] footprint radius in pixels; 0 = culled */
+} gs_projected;
+
+/* Rendered or gradient images. */
+typedef struct gs_images {
+  float* color;          /* [P * (4 + n_sem)] planar per item */
+  float* T;              /* [P] final transmittance (forward only) */
+  uint32_t* n_contrib;   /* [P] 1 + list position of the last blended Gaussian, 0 if none */
+  float* logits;         /* [P * n_classes] learned mode decoded logits, else NULL */
+} gs_images;
+
+/* Targets of the loss (the image pyramid of eq. 4-6). */
+typedef struct gs_targets {
+  const float* rgb;      /* [P * 3] planar per item */
+  const float* depth;    /* [P]; <= 0 marks a missing depth */
+  const int32_t* label;  /* [P] class index in [0, n_classes); any other value = unlabelled */
+} gs_targets;
+
+/* Learned semantic head: logits = W2 relu(W1 E + b1) + b2 (bfloat16 weights). */
+typedef struct gs_head {
+  int32_t d_in;          /* 16 */
+  int32_t d_hidden;      /* 64 */
+  int32_t n_classes;
+  int32_t pad;
+  const uint16_t* W1;    /* [d_hidden][d_in] bfloat16 */
+  const float* b1;       /* [d_hidden] */
+  const uint16_t* W2;    /* [n_classes][d_hidden] bfloat16 */
+  const float* b2;       /* [n_classes] */
+} gs_head;
+
+/* Gradient outputs. Every non-NULL array is overwritten (zeroed by the callee first). */
+typedef struct gs_grads {
+  float* mean;       /* [n][3] */
+  float* log_scale;  /* [n][3] */
+  float* quat;       /* [n][4] */
+  float* opacity;    /* [n] (with respect to the logit) */
+  float* rgb;        /* [n][3] */
+  float* sem;        /* [n][n_sem] plain mode */
+  float* emb;        /* [n][16] learned mode, float32 */
+  float* pose;       /* [n_views][6]: (rho, phi) of T_cw <- Exp(xi) T_cw at xi = 0 */
+} gs_grads;
+
+enum gs_workspace_kind { GS_WS_BIN_SORT = 1, GS_WS_RENDER_BWD = 2, GS_WS_LOSS = 3 };
+
+/* ---- helpers --------------------------------------------------------------- */
+void gs_config_default(gs_config* cfg);
+const char* gs_status_string(int status);
+int gs_last_hip_error(void);
+int gs_version(void);
+
+/* Host helper: fills views[i].item_first/item_count and items[] (host memory) for
+ * n_views views of base size W[v] x H[v], intrinsics K[v] = (fx, fy, cx, cy) and
+ * levels[v] pyramid levels. W and H must be divisible by 2^(levels-1).
+ * items must hold sum(levels) entries. Returns the item count, or a negative status.
+ * n_pixels and n_tiles (host, may be NULL) receive the totals. */
+int gs_make_items(const gs_config* cfg, int32_t n_views, gs_view* views, const int32_t* W, const int32_t* H,
+                  const float* K, const int32_t* levels, gs_item* items, int64_t* n_pixels, int32_t* n_tiles);
+
+/* Bytes of caller workspace a call needs (kind = gs_workspace_kind). */
+int gs_workspace_size(int kind, const gs_config* cfg, int32_t n_items, int64_t n_gauss, int32_t n_tiles,
+                      int64_t dup_capacity, int64_t n_pixels, size_t* bytes);
+
+/* ---- the hot path ------------------------------------------------------------ */
+
+/* Projection (eq. 2-3 in the EWA form): for every view and Gaussian, the camera-space
+ * mean, the 2D covariance J W Sigma W^T J^T + eps I with Sigma = R(q) S^2 R(q)^T,
+ * its inverse (conic), the projected mean K (W mu + t) / z, the opacity sigmoid(a),
+ * the radius ceil(3 sqrt(lambda_max)) and, per level, the same for K_l.
+ * A Gaussian is culled (radius 0) when z <= z_near, |q| = 0, det <= 0, or its
+ * tile rectangle is empty. */
+int gs_preprocess(const gs_config* cfg, const gs_gaussians* g, const gs_view* views_dev, int32_t n_views,
+                  const gs_item* items_dev, int32_t n_items, gs_projected* out, void* stream);
+
+/* Binning and depth order (the sorted set N of eq. 7-9): every visible (item, Gaussian)
+ * is duplicated once per tile of its rectangle; the duplicates are ordered by
+ * (global tile, float32 depth, Gaussian index) -- equivalently by the 64-bit key
+ * tile << 32 | bits(depth), ties by index -- and ranges[2t], ranges[2t+1] receive
+ * the first and one-past-last position of tile t ((0, 0) if empty).
+ * vals[j] = Gaussian index of entry j; keys (may be NULL) = the 64-bit keys.
+ * n_dup_dev (device int64) receives the duplicate count. If it exceeds dup_capacity,
+ * status_dev (device int32) is set to GS_ERR_CAPACITY and nothing past the capacity
+ * is written; otherwise status_dev is set to GS_OK. */
+int gs_bin_sort(const gs_config* cfg, const gs_projected* proj, const gs_item* items_dev, int32_t n_items,
+                int64_t n_gauss, int32_t n_tiles, int64_t dup_capacity, void* workspace, size_t ws_bytes,
+                uint64_t* keys, uint32_t* vals, uint32_t* ranges, int64_t* n_dup_dev, int32_t* status_dev,
+                void* stream);
+
+/* Front-to-back compositing (eq. 7-9) of every pixel of every item: over its tile's
+ * list, alpha = min(alpha_max, o exp(-d^T conic d / 2)), skipped below alpha_min;
+ * the pixel stops before the Gaussian that would take T below t_min; the colour,
+ * depth and semantic channels accumulate f alpha T. head != NULL (learned mode)
+ * additionally decodes out->logits from the composited embedding. */
+int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_item* items_dev,
+                  int32_t n_items, int32_t n_tiles, const uint32_t* vals, const uint32_t* ranges,
+                  const gs_head* head, gs_images* out, void* stream);
+
+/* Per-level loss (eq. 10-13, L1 parts; semantics as cross-entropy on the class
+ * logits): for each item, loss_dev[3i..3i+2] = mean |R - R_gt| over 3HW,
+ * mean |D - D_gt| over pixels with D_gt > 0, mean -log softmax(S)[label].
+ * grad_out->color (and ->logits in learned mode) receives the gradient of
+ * sum_i (w[0] L_rgb + w[1] L_depth + w[2] L_sem). w is a host array. */
+int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_items, int64_t n_pixels,
+                    int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const float* w,
+                    float* loss_dev, gs_images* grad_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* Back-propagation (Sec. III-D) of an upstream gradient grad_in->color (and ->logits)
+ * through compositing and projection to every Gaussian parameter and every view's
+ * pose tangent. fwd must hold T and n_contrib of the matching gs_render_fwd. */
+int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_view* views_dev,
+                  int32_t n_views, const gs_item* items_dev, int32_t n_items, int32_t n_tiles,
+                  const uint32_t* vals, const uint32_t* ranges, const gs_head* head, const gs_images* fwd,
+                  const gs_images* grad_in, gs_grads* grads, void* workspace, size_t ws_bytes, void* stream);
+
+/* Image pyramid (eq. 4-6): fills levels 1..max_level of every view from the level
+ * above by 2x2 box means of a K-channel image; channel 3 (depth) averages only its
+ * positive children (0 if none). labels (may be NULL) receives, for every pixel of
+ * every item, the argmax over channels 4..K-1 (ties to the lowest index). */
+int gs_pyramid_downsample(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t max_level,
+                          int32_t K, float* img, int32_t* labels, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H */

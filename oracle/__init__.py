@@ -52,7 +52,8 @@ class Config:
     t_min: float = 1e-4
     guard: float = 1.3
     full_rect: bool = False
-    margin: float = 1e-5
+    margin: float = 2e-5        # per-pixel decisions (alpha_min, alpha_max, t_min, depth ties)
+    margin_pre: float = 1e-9    # projection decisions (z_near, guard, radius and rect rounding)
 
     def exact(self) -> "Config":
         """Cut-offs removed: every Gaussian covers every tile, no alpha_min / t_min."""
@@ -60,7 +61,7 @@ class Config:
 
     def arrays(self, S: int):
         cd = np.array([self.z_near, self.eps, self.alpha_min, self.alpha_max, self.t_min,
-                       self.guard, self.margin, 0.0], np.float64)
+                       self.guard, self.margin, self.margin_pre], np.float64)
         ci = np.array([self.tile_w, self.tile_h, int(self.full_rect), S], np.int32)
         return cd, ci
 

@@ -38,7 +38,9 @@ namespace {
 
 struct Cfg {
   int tw, th, full_rect, S;
-  double z_near, eps, a_min, a_max, t_min, guard, margin;
+  double z_near, eps, a_min, a_max, t_min, guard;
+  double margin;      // relative closeness that flags a per-pixel decision
+  double margin_pre;  // the same for the projection's decisions
 };
 
 Cfg read_cfg(const double* cd, const int* ci) {
@@ -50,6 +52,7 @@ Cfg read_cfg(const double* cd, const int* ci) {
   c.t_min = cd[4];
   c.guard = cd[5];
   c.margin = cd[6];
+  c.margin_pre = cd[7];
   c.tw = ci[0];
   c.th = ci[1];
   c.full_rect = ci[2];
@@ -162,7 +165,7 @@ Proj project(const Cfg& c, const Gauss& g, int64_t i, const double* Rv, const do
   const double* mu = g.mean + 3 * i;
   for (int r = 0; r < 3; ++r) p.mc[r] = Rv[3 * r] * mu[0] + Rv[3 * r + 1] * mu[1] + Rv[3 * r + 2] * mu[2] + tv[r];
   p.z = p.mc[2];
-  if (near_rel(p.z, c.z_near, c.margin)) p.flag |= 1;
+  if (near_rel(p.z, c.z_near, c.margin_pre)) p.flag |= 1;
   if (!(p.z > c.z_near)) return p;
   const double* q = g.quat + 4 * i;
   p.qlen = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
@@ -179,7 +182,7 @@ Proj project(const Cfg& c, const Gauss& g, int64_t i, const double* Rv, const do
   double limx = c.guard * (0.5 * it.W) / it.fx;
   double limy = c.guard * (0.5 * it.H) / it.fy;
   double ux = p.mc[0] / p.z, uy = p.mc[1] / p.z;
-  if (near_rel(std::fabs(ux), limx, c.margin) || near_rel(std::fabs(uy), limy, c.margin)) p.flag |= 2;
+  if (near_rel(std::fabs(ux), limx, c.margin_pre) || near_rel(std::fabs(uy), limy, c.margin_pre)) p.flag |= 2;
   p.clx = std::fabs(ux) > limx;
   p.cly = std::fabs(uy) > limy;
   p.ux = std::min(limx, std::max(-limx, ux));
@@ -214,7 +217,7 @@ Proj project(const Cfg& c, const Gauss& g, int64_t i, const double* Rv, const do
   double mid = 0.5 * (p.cov[0] + p.cov[2]);
   double lam = mid + std::sqrt(std::max(0.1, mid * mid - det));
   double rr = 3.0 * std::sqrt(lam);
-  if (near_int(rr, c.margin)) p.flag |= 4;
+  if (near_int(rr, c.margin_pre)) p.flag |= 4;
   p.radius = int(std::ceil(rr));
   if (p.radius <= 0) return p;
   if (c.full_rect) {
@@ -223,7 +226,7 @@ Proj project(const Cfg& c, const Gauss& g, int64_t i, const double* Rv, const do
     double ex[4] = {(p.m2[0] - p.radius) / c.tw, (p.m2[1] - p.radius) / c.th,
                     (p.m2[0] + p.radius) / c.tw, (p.m2[1] + p.radius) / c.th};
     for (int k = 0; k < 4; ++k)
-      if (near_int(ex[k], c.margin)) p.flag |= 8;
+      if (near_int(ex[k], c.margin_pre)) p.flag |= 8;
     int lim[2] = {it.ntx, it.nty};
     for (int k = 0; k < 2; ++k) {
       p.rect[k] = std::min(lim[k], std::max(0, int(std::floor(ex[k]))));

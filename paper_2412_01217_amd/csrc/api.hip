@@ -1,0 +1,244 @@
+// C ABI entry points: argument validation, workspace planning and kernel launches.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace gs {
+
+static int g_last_hip = 0;
+
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return GS_OK;
+  g_last_hip = (int)e;
+  return GS_ERR_HIP;
+}
+int launch_status() { return hip_status(hipGetLastError()); }
+
+// kernels (other translation units)
+int launch_preprocess(const gs_config&, const gs_gaussians&, const gs_view*, int, const gs_item*, const gs_projected&,
+                      hipStream_t);
+int launch_preprocess_bwd(const gs_config&, const gs_gaussians&, const gs_view*, int, const gs_item*, const float*,
+                          const int32_t*, const gs_grads&, hipStream_t);
+size_t bin_sort_workspace(int64_t E, int64_t cap);
+int launch_bin_sort(const gs_config&, const gs_projected&, const gs_item*, int, int64_t, int, int64_t, void*, uint64_t*,
+                    uint32_t*, uint32_t*, int64_t*, int32_t*, hipStream_t);
+int launch_render_fwd(const gs_config&, const gs_gaussians&, const gs_projected&, const gs_item*, int, int,
+                      const uint32_t*, const uint32_t*, const gs_images&, hipStream_t);
+int launch_render_bwd(const gs_config&, const gs_gaussians&, const gs_projected&, const gs_item*, int, int,
+                      const uint32_t*, const uint32_t*, const gs_images&, const gs_images&, float*, const gs_grads&,
+                      hipStream_t);
+int launch_loss(const gs_item*, int, int64_t, int, int, const float*, const float*, const gs_targets&, const float*,
+                float*, float*, float*, float*, hipStream_t);
+int launch_downsample(const gs_item*, int, int64_t, int, int, float*, int32_t*, hipStream_t);
+int launch_fill_f32(float*, int64_t, float, hipStream_t);
+
+namespace {
+
+bool cfg_ok(const gs_config* c) {
+  if (!c) return false;
+  if (c->tile_w != kTile || c->tile_h != kTile) return false;
+  if (!(c->z_near > 0.0f) || !(c->eps_dilate >= 0.0f) || !(c->alpha_min >= 0.0f)) return false;
+  if (!(c->alpha_max > c->alpha_min) || !(c->alpha_max < 1.0f) || !(c->t_min >= 0.0f) || !(c->guard > 0.0f)) return false;
+  if (c->n_sem < 0 || c->n_sem > 64) return false;
+  return true;
+}
+
+bool gauss_ok(const gs_gaussians* g, bool need_features) {
+  if (!g || g->n < 0 || g->n >= (int64_t)1 << 31) return false;
+  if (g->n == 0) return true;
+  if (!g->mean || !g->log_scale || !g->quat || !g->opacity) return false;
+  if (need_features && !g->rgb) return false;
+  return true;
+}
+
+constexpr int64_t kSortBwdRecord = 8;  // floats per (item, Gaussian) of 2D gradients
+
+}  // namespace
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+void gs_config_default(gs_config* c) {
+  if (!c) return;
+  c->tile_w = kTile;
+  c->tile_h = kTile;
+  c->z_near = 0.2f;
+  c->eps_dilate = 0.3f;
+  c->alpha_min = 1.0f / 255.0f;
+  c->alpha_max = 0.99f;
+  c->t_min = 1e-4f;
+  c->guard = 1.3f;
+  c->full_rect = 0;
+  c->n_sem = 0;
+  c->variant = 0;
+  c->reserved = 0;
+}
+
+const char* gs_status_string(int s) {
+  switch (s) {
+    case GS_OK: return "ok";
+    case GS_ERR_INVALID_ARG: return "invalid argument";
+    case GS_ERR_WORKSPACE: return "workspace too small";
+    case GS_ERR_CAPACITY: return "duplicate capacity exceeded";
+    case GS_ERR_HIP: return "HIP error";
+    case GS_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+int gs_last_hip_error(void) { return g_last_hip; }
+int gs_version(void) { return 100; }
+
+int gs_make_items(const gs_config* cfg, int32_t n_views, gs_view* views, const int32_t* W, const int32_t* H,
+                  const float* K, const int32_t* levels, gs_item* items, int64_t* n_pixels, int32_t* n_tiles) {
+  if (!cfg_ok(cfg) || n_views < 0 || !views || !W || !H || !K || !levels || !items) return GS_ERR_INVALID_ARG;
+  int n = 0;
+  int64_t pix = 0;
+  int64_t tiles = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const int L = levels[v];
+    if (L < 1 || L > 16 || W[v] <= 0 || H[v] <= 0) return GS_ERR_INVALID_ARG;
+    const int div = 1 << (L - 1);
+    if (W[v] % div || H[v] % div) return GS_ERR_INVALID_ARG;
+    views[v].item_first = n;
+    views[v].item_count = L;
+    for (int l = 0; l < L; ++l) {
+      gs_item& it = items[n++];
+      const float s = std::ldexp(1.0f, -l);
+      it.fx = K[4 * v + 0] * s;
+      it.fy = K[4 * v + 1] * s;
+      it.cx = K[4 * v + 2] * s;
+      it.cy = K[4 * v + 3] * s;
+      it.W = W[v] >> l;
+      it.H = H[v] >> l;
+      it.view = v;
+      it.level = l;
+      it.tiles_x = (it.W + cfg->tile_w - 1) / cfg->tile_w;
+      it.tiles_y = (it.H + cfg->tile_h - 1) / cfg->tile_h;
+      it.tile_base = (int32_t)tiles;
+      it.pad = 0;
+      it.pixel_base = pix;
+      tiles += (int64_t)it.tiles_x * it.tiles_y;
+      pix += (int64_t)it.W * it.H;
+      if (tiles >= (int64_t)1 << 31) return GS_ERR_INVALID_ARG;
+    }
+  }
+  if (n_pixels) *n_pixels = pix;
+  if (n_tiles) *n_tiles = (int32_t)tiles;
+  return n;
+}
+
+int gs_workspace_size(int kind, const gs_config* cfg, int32_t n_items, int64_t n_gauss, int32_t n_tiles,
+                      int64_t dup_capacity, int64_t n_pixels, size_t* bytes) {
+  if (!cfg_ok(cfg) || !bytes || n_items < 0 || n_gauss < 0 || n_tiles < 0 || dup_capacity < 0 || n_pixels < 0)
+    return GS_ERR_INVALID_ARG;
+  switch (kind) {
+    case GS_WS_BIN_SORT:
+      *bytes = bin_sort_workspace((int64_t)n_items * n_gauss, dup_capacity);
+      return GS_OK;
+    case GS_WS_RENDER_BWD:
+      *bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)n_gauss);
+      return GS_OK;
+    case GS_WS_LOSS:
+      *bytes = align_up(sizeof(float) * (size_t)std::max(n_items, 1));
+      return GS_OK;
+    default:
+      return GS_ERR_INVALID_ARG;
+  }
+}
+
+int gs_preprocess(const gs_config* cfg, const gs_gaussians* g, const gs_view* views_dev, int32_t n_views,
+                  const gs_item* items_dev, int32_t n_items, gs_projected* out, void* stream) {
+  if (!cfg_ok(cfg) || !gauss_ok(g, false) || !out || n_views < 0 || n_items < 0) return GS_ERR_INVALID_ARG;
+  if (g->n == 0 || n_items == 0) return GS_OK;
+  if (!views_dev || !items_dev || !out->rec || !out->depth || !out->radius) return GS_ERR_INVALID_ARG;
+  if ((int64_t)n_items * g->n >= (int64_t)1 << 32) return GS_ERR_UNSUPPORTED;
+  return launch_preprocess(*cfg, *g, views_dev, n_views, items_dev, *out, (hipStream_t)stream);
+}
+
+int gs_bin_sort(const gs_config* cfg, const gs_projected* proj, const gs_item* items_dev, int32_t n_items,
+                int64_t n_gauss, int32_t n_tiles, int64_t dup_capacity, void* workspace, size_t ws_bytes,
+                uint64_t* keys, uint32_t* vals, uint32_t* ranges, int64_t* n_dup_dev, int32_t* status_dev,
+                void* stream) {
+  if (!cfg_ok(cfg) || !proj || n_items < 0 || n_gauss < 0 || n_tiles < 0 || dup_capacity < 0) return GS_ERR_INVALID_ARG;
+  if (dup_capacity >= ((int64_t)1 << 32) - 1 || (int64_t)n_items * n_gauss >= (int64_t)1 << 32) return GS_ERR_UNSUPPORTED;
+  if (n_tiles == 0) return GS_OK;
+  if (!items_dev || !vals || !ranges) return GS_ERR_INVALID_ARG;
+  if (n_items > 0 && n_gauss > 0 && (!proj->rec || !proj->depth || !proj->radius)) return GS_ERR_INVALID_ARG;
+  if (ws_bytes < bin_sort_workspace((int64_t)n_items * n_gauss, dup_capacity) || !workspace) return GS_ERR_WORKSPACE;
+  return launch_bin_sort(*cfg, *proj, items_dev, n_items, n_gauss, n_tiles, dup_capacity, workspace, keys, vals, ranges,
+                         n_dup_dev, status_dev, (hipStream_t)stream);
+}
+
+int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_item* items_dev,
+                  int32_t n_items, int32_t n_tiles, const uint32_t* vals, const uint32_t* ranges,
+                  const gs_head* head, gs_images* out, void* stream) {
+  if (!cfg_ok(cfg) || !gauss_ok(g, true) || !proj || !out || n_items < 0 || n_tiles < 0) return GS_ERR_INVALID_ARG;
+  if (head) return GS_ERR_UNSUPPORTED;
+  if (cfg->n_sem > 0 && g->n > 0 && !g->sem) return GS_ERR_INVALID_ARG;
+  if (n_tiles == 0) return GS_OK;
+  if (!items_dev || !vals || !ranges || !out->color || !out->T || !out->n_contrib) return GS_ERR_INVALID_ARG;
+  return launch_render_fwd(*cfg, *g, *proj, items_dev, n_items, n_tiles, vals, ranges, *out, (hipStream_t)stream);
+}
+
+int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_items, int64_t n_pixels,
+                    int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const float* w,
+                    float* loss_dev, gs_images* grad_out, void* workspace, size_t ws_bytes, void* stream) {
+  if (!cfg_ok(cfg) || n_items < 0 || n_pixels < 0 || n_classes < 0 || !rendered || !targets || !w || !grad_out)
+    return GS_ERR_INVALID_ARG;
+  if (n_items == 0) return GS_OK;
+  if (!items_dev || !loss_dev || !rendered->color || !grad_out->color || !targets->rgb || !targets->depth)
+    return GS_ERR_INVALID_ARG;
+  if (n_classes > 0 && !targets->label) return GS_ERR_INVALID_ARG;
+  if (rendered->logits) {
+    if (!grad_out->logits) return GS_ERR_INVALID_ARG;
+  } else if (n_classes != cfg->n_sem) {
+    return GS_ERR_INVALID_ARG;
+  }
+  if (!workspace || ws_bytes < align_up(sizeof(float) * (size_t)n_items)) return GS_ERR_WORKSPACE;
+  return launch_loss(items_dev, n_items, n_pixels, 4 + cfg->n_sem, n_classes, rendered->color, rendered->logits,
+                     *targets, w, loss_dev, grad_out->color, grad_out->logits, (float*)workspace, (hipStream_t)stream);
+}
+
+int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_view* views_dev,
+                  int32_t n_views, const gs_item* items_dev, int32_t n_items, int32_t n_tiles,
+                  const uint32_t* vals, const uint32_t* ranges, const gs_head* head, const gs_images* fwd,
+                  const gs_images* grad_in, gs_grads* grads, void* workspace, size_t ws_bytes, void* stream) {
+  if (!cfg_ok(cfg) || !gauss_ok(g, true) || !proj || !fwd || !grad_in || !grads || n_views < 0 || n_items < 0 ||
+      n_tiles < 0)
+    return GS_ERR_INVALID_ARG;
+  if (head) return GS_ERR_UNSUPPORTED;
+  if (cfg->n_sem > 0 && g->n > 0 && (!g->sem || !grads->sem)) return GS_ERR_INVALID_ARG;
+  if (!grads->mean || !grads->log_scale || !grads->quat || !grads->opacity || !grads->rgb || !grads->pose)
+    return GS_ERR_INVALID_ARG;
+  const size_t need = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)g->n);
+  if (!workspace || ws_bytes < need) return GS_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = g->n;
+  int st = launch_fill_f32((float*)workspace, kSortBwdRecord * (int64_t)n_items * n, 0.0f, s);
+  st = st ? st : launch_fill_f32(grads->rgb, 3 * n, 0.0f, s);
+  if (cfg->n_sem > 0) st = st ? st : launch_fill_f32(grads->sem, (int64_t)cfg->n_sem * n, 0.0f, s);
+  st = st ? st : launch_fill_f32(grads->pose, 6ll * n_views, 0.0f, s);
+  if (st) return st;
+  if (n == 0) return GS_OK;
+  if (n_tiles > 0) {
+    if (!items_dev || !vals || !ranges || !fwd->T || !fwd->n_contrib || !grad_in->color) return GS_ERR_INVALID_ARG;
+    st = launch_render_bwd(*cfg, *g, *proj, items_dev, n_items, n_tiles, vals, ranges, *fwd, *grad_in, (float*)workspace,
+                           *grads, s);
+    if (st) return st;
+  }
+  return launch_preprocess_bwd(*cfg, *g, views_dev, n_views, items_dev, (const float*)workspace, proj->radius, *grads, s);
+}
+
+int gs_pyramid_downsample(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t max_level, int32_t K,
+                          float* img, int32_t* labels, void* stream) {
+  if (n_items < 0 || n_pixels < 0 || max_level < 0 || K < 4) return GS_ERR_INVALID_ARG;
+  if (n_items == 0 || n_pixels == 0) return GS_OK;
+  if (!items_dev || !img) return GS_ERR_INVALID_ARG;
+  return launch_downsample(items_dev, n_items, n_pixels, max_level, K, img, labels, (hipStream_t)stream);
+}
+
+}  // extern "C"

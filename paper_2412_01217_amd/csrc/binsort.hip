@@ -1,0 +1,440 @@
+// Tile binning and depth ordering of the footprints (the sorted set N of eq. 7-9).
+//
+// The required order is (global tile, float32 depth, Gaussian index). Instead of
+// radix-sorting every duplicate by a 64-bit (tile | depth) key, this path
+//   1. compacts the visible (item, Gaussian) entries and radix-sorts them by
+//      (item, depth) -- a stable sort, so equal depths keep index order;
+//   2. emits each entry's tiles in that order;
+//   3. stably radix-sorts the duplicates by tile id alone.
+// A stable sort by tile of a sequence already ordered by (depth, index) yields
+// exactly the (tile, depth, index) order, with ceil(log2(tiles)) key bits per
+// duplicate instead of 32 + ceil(log2(tiles)).
+//
+// Every kernel reads its element count from device memory, so the sequence has no
+// host synchronisation and can be captured in a graph; grids are sized for the
+// capacity and blocks past the live count exit early.
+#include "common.h"
+
+namespace gs {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;   // 4096
+constexpr int kRadixThreads = 256;
+constexpr int kRadixItems = 8;
+constexpr int kRadixTile = kRadixThreads * kRadixItems;  // 2048
+constexpr int kRadixWaveSpan = kRadixTile / 4;            // keys per wave
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of uint32 (three phases), count from device memory.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& total, uint32_t* sh /*[4]*/) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  if (lane == 63) sh[wid] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int w = 0; w < wid; ++w) base += sh[w];
+  total = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return base + inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, const uint64_t* count_dev,
+                                                               int64_t count_host, uint32_t* __restrict__ partial) {
+  const int64_t count = count_dev ? (int64_t)*count_dev : count_host;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+  if (base < count) {
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
+      if (idx < count) s += in[idx];
+    }
+  }
+  __shared__ uint32_t sh[4];
+  uint32_t total;
+  block_exclusive_scan(s, total, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the block partials; total to *total_out (uint64).
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partial, int64_t n_partial_cap, const uint64_t* count_dev,
+                                                        int64_t count_host, uint64_t* total_out) {
+  const int64_t count = count_dev ? (int64_t)*count_dev : count_host;
+  const int64_t np = min(n_partial_cap, (count + kScanTile - 1) / kScanTile);
+  __shared__ uint64_t sh[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (np + 1023) / 1024;
+  const int64_t b0 = t * per, b1 = min(np, b0 + per);
+  uint64_t s = 0;
+  for (int64_t b = b0; b < b1; ++b) s += partial[b];
+  sh[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint64_t v = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  uint64_t run = sh[t] - s;
+  for (int64_t b = b0; b < b1; ++b) {
+    const uint32_t v = partial[b];
+    partial[b] = (uint32_t)run;
+    run += v;
+  }
+  if (t == 1023 && total_out) *total_out = sh[1023];
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* __restrict__ in, const uint64_t* count_dev,
+                                                              int64_t count_host, const uint32_t* __restrict__ partial,
+                                                              uint32_t* __restrict__ out) {
+  const int64_t count = count_dev ? (int64_t)*count_dev : count_host;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= count) return;
+  // blocked arrangement: thread t owns kScanItems consecutive elements
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+  const int64_t tb = base + (int64_t)threadIdx.x * kScanItems;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = tb + k;
+    v[k] = idx < count ? in[idx] : 0;
+    s += v[k];
+  }
+  __shared__ uint32_t sh[4];
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, total, sh) + partial[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = tb + k;
+    if (idx < count) out[idx] = run;
+    run += v[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort pass (8-bit digit) of (key, value) pairs.
+// ---------------------------------------------------------------------------
+template <class Key>
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const Key* __restrict__ keys, const uint64_t* count_dev,
+                                                              int shift, int nblk, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t count = (int64_t)*count_dev;
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  for (int k = 0; k < kRadixItems; ++k) {
+    const int64_t idx = base + (int64_t)k * kRadixThreads + threadIdx.x;
+    if (idx < count) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+template <class Key>
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const Key* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                                 Key* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                                 const uint64_t* count_dev, int shift, int nblk,
+                                                                 const uint32_t* __restrict__ offs) {
+  __shared__ uint32_t cnt[4][256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int d = lane; d < 256; d += 64) cnt[wid][d] = 0;
+  __syncthreads();
+  const int64_t count = (int64_t)*count_dev;
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile + (int64_t)wid * kRadixWaveSpan;
+  Key k[kRadixItems];
+  uint32_t v[kRadixItems], pos[kRadixItems], dig[kRadixItems];
+  bool ok[kRadixItems];
+  const uint64_t lt = lanemask_lt();
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int64_t idx = base + (int64_t)r * 64 + lane;
+    ok[r] = idx < count;
+    k[r] = ok[r] ? kin[idx] : Key(0);
+    v[r] = ok[r] ? vin[idx] : 0u;
+    const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+    dig[r] = d;
+    uint64_t peers = __ballot(ok[r]);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t m = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    const uint32_t rank = __popcll(peers & lt);
+    uint32_t old = 0;
+    if (ok[r]) old = cnt[wid][d];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    if (ok[r] && rank == 0) cnt[wid][d] = old + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    pos[r] = old + rank;
+  }
+  __syncthreads();
+  // per digit: exclusive prefix over the four waves
+  {
+    const int d = threadIdx.x;
+    const uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d];
+    const uint32_t g = offs[(int64_t)d * nblk + blockIdx.x];
+    cnt[0][d] = g;
+    cnt[1][d] = g + c0;
+    cnt[2][d] = g + c0 + c1;
+    cnt[3][d] = g + c0 + c1 + c2;
+  }
+  __syncthreads();
+  for (int r = 0; r < kRadixItems; ++r) {
+    if (!ok[r]) continue;
+    const uint32_t dst = cnt[wid][dig[r]] + pos[r];
+    kout[dst] = k[r];
+    vout[dst] = v[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Compaction, footprint rectangles, duplication, ranges.
+// ---------------------------------------------------------------------------
+__global__ void k_visible_flags(const int32_t* __restrict__ radius, int64_t E, uint32_t* __restrict__ flags) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E) flags[e] = radius[e] > 0 ? 1u : 0u;
+}
+
+// Visible entry e = item * n + g gets the depth-sort key (item << 32) | bits(depth).
+__global__ void k_compact(const int32_t* __restrict__ radius, const float* __restrict__ depth,
+                          const uint32_t* __restrict__ pos, int64_t E, int64_t n, uint64_t* __restrict__ keys,
+                          uint32_t* __restrict__ vals) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E || radius[e] <= 0) return;
+  const uint32_t p = pos[e];
+  const uint64_t item = (uint64_t)(e / n);
+  keys[p] = (item << 32) | (uint64_t)__float_as_uint(depth[e]);
+  vals[p] = (uint32_t)e;
+}
+
+struct Rect {
+  int x0, y0, x1, y1;
+};
+
+__device__ __forceinline__ Rect tile_rect(const gs_config& cfg, const gs_item& it, const float* rec, int r) {
+  const float4 m = *reinterpret_cast<const float4*>(rec);
+  const double mx = (double)m.x + (double)m.z, my = (double)m.y + (double)m.w;
+  Rect R;
+  if (cfg.full_rect) {
+    R.x0 = 0; R.y0 = 0; R.x1 = it.tiles_x; R.y1 = it.tiles_y;
+    return R;
+  }
+  R.x0 = min(it.tiles_x, max(0, (int)floor((mx - r) / cfg.tile_w)));
+  R.y0 = min(it.tiles_y, max(0, (int)floor((my - r) / cfg.tile_h)));
+  R.x1 = min(it.tiles_x, max(0, (int)floor((mx + r) / cfg.tile_w) + 1));
+  R.y1 = min(it.tiles_y, max(0, (int)floor((my + r) / cfg.tile_h) + 1));
+  return R;
+}
+
+__global__ void k_touched(gs_config cfg, const uint32_t* __restrict__ svals, const uint64_t* count_dev,
+                          const float* __restrict__ rec, const int32_t* __restrict__ radius,
+                          const gs_item* __restrict__ items, int64_t n, uint32_t* __restrict__ touched) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= (int64_t)*count_dev) return;
+  const uint32_t e = svals[j];
+  const gs_item it = items[e / n];
+  const Rect R = tile_rect(cfg, it, rec + (int64_t)kRecFloats * e, radius[e]);
+  touched[j] = (uint32_t)((R.x1 - R.x0) * (R.y1 - R.y0));
+}
+
+__global__ void k_duplicate(gs_config cfg, const uint32_t* __restrict__ svals, const uint64_t* count_dev,
+                            const uint32_t* __restrict__ offs, const float* __restrict__ rec,
+                            const int32_t* __restrict__ radius, const gs_item* __restrict__ items, int64_t n,
+                            int64_t cap, uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= (int64_t)*count_dev) return;
+  const uint32_t e = svals[j];
+  const int64_t item = e / n;
+  const uint32_t g = (uint32_t)(e - item * n);
+  const gs_item it = items[item];
+  const Rect R = tile_rect(cfg, it, rec + (int64_t)kRecFloats * e, radius[e]);
+  int64_t p = offs[j];
+  for (int ty = R.y0; ty < R.y1; ++ty)
+    for (int tx = R.x0; tx < R.x1; ++tx, ++p) {
+      if (p >= cap) return;
+      tkeys[p] = (uint32_t)(it.tile_base + ty * it.tiles_x + tx);
+      tvals[p] = g;
+    }
+}
+
+// Clamp the duplicate count to the capacity and report the status.
+__global__ void k_dup_count(const uint64_t* total, int64_t cap, uint64_t* live, int64_t* n_dup_out, int32_t* status) {
+  const uint64_t D = *total;
+  *live = D > (uint64_t)cap ? (uint64_t)cap : D;
+  if (n_dup_out) *n_dup_out = (int64_t)D;
+  if (status) *status = D > (uint64_t)cap ? GS_ERR_CAPACITY : GS_OK;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint64_t* count_dev, uint32_t* __restrict__ ranges) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t D = (int64_t)*count_dev;
+  if (j >= D) return;
+  const uint32_t t = tkeys[j];
+  if (j == 0 || tkeys[j - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)j;
+  if (j == D - 1 || tkeys[j + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(j + 1);
+}
+
+__global__ void k_full_keys(const uint32_t* __restrict__ tkeys, const uint32_t* __restrict__ tvals,
+                            const uint64_t* count_dev, const float* __restrict__ depth,
+                            const gs_item* __restrict__ items, int n_items, int64_t n, uint64_t* __restrict__ keys) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= (int64_t)*count_dev) return;
+  const uint32_t t = tkeys[j];
+  const int item = item_of_tile(items, n_items, (int)t);
+  keys[j] = ((uint64_t)t << 32) | (uint64_t)__float_as_uint(depth[(int64_t)item * n + tvals[j]]);
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+struct SortWs {
+  uint32_t* flags;     // [E]   visibility flags, then compaction positions
+  uint32_t* partial;   // [max(E, cap, hist) / 4096 + 2]
+  uint64_t* vkeys[2];  // [E]
+  uint32_t* vvals[2];  // [E]
+  uint32_t* touched;   // [E]   touched counts, then duplicate offsets
+  uint32_t* tkeys[2];  // [cap]
+  uint32_t* tvals;     // [cap] (the second value buffer is the caller's vals)
+  uint32_t* hist;      // [256 * nblk_max]
+  uint64_t* counters;  // [4]: n_visible, D total, D live, scratch
+  size_t bytes;
+};
+
+int bits_for(uint64_t x) {  // bits needed to represent values < x
+  int b = 0;
+  while (b < 64 && (1ull << b) < x) ++b;
+  return b;
+}
+
+SortWs plan_sort(int64_t E, int64_t cap, void* base) {
+  SortWs w{};
+  const int64_t nmax = std::max<int64_t>(E, cap);
+  const int64_t nblk = ceil_div(std::max<int64_t>(nmax, 1), kRadixTile);
+  const int64_t hist_n = 256 * nblk;
+  const int64_t np = ceil_div(std::max<int64_t>(std::max(nmax, hist_n), 1), kScanTile) + 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  size_t o_flags = take(4 * E), o_part = take(4 * np), o_vk0 = take(8 * E), o_vk1 = take(8 * E),
+         o_vv0 = take(4 * E), o_vv1 = take(4 * E), o_touch = take(4 * E), o_tk0 = take(4 * cap),
+         o_tk1 = take(4 * cap), o_tv = take(4 * cap), o_hist = take(4 * hist_n), o_cnt = take(8 * 4);
+  w.bytes = off;
+  if (base) {
+    char* b = static_cast<char*>(base);
+    w.flags = (uint32_t*)(b + o_flags);
+    w.partial = (uint32_t*)(b + o_part);
+    w.vkeys[0] = (uint64_t*)(b + o_vk0);
+    w.vkeys[1] = (uint64_t*)(b + o_vk1);
+    w.vvals[0] = (uint32_t*)(b + o_vv0);
+    w.vvals[1] = (uint32_t*)(b + o_vv1);
+    w.touched = (uint32_t*)(b + o_touch);
+    w.tkeys[0] = (uint32_t*)(b + o_tk0);
+    w.tkeys[1] = (uint32_t*)(b + o_tk1);
+    w.tvals = (uint32_t*)(b + o_tv);
+    w.hist = (uint32_t*)(b + o_hist);
+    w.counters = (uint64_t*)(b + o_cnt);
+  }
+  return w;
+}
+
+// Exclusive scan of in[0..count) into out; total (if non-null) to *total.
+int device_scan(const uint32_t* in, uint32_t* out, const uint64_t* count_dev, int64_t count_host, int64_t cap_count,
+                uint32_t* partial, uint64_t* total, hipStream_t s) {
+  const int64_t nb = std::max<int64_t>(1, ceil_div(cap_count, kScanTile));
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, count_dev, count_host, partial);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partial, nb, count_dev, count_host, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, count_dev, count_host, partial, out);
+  return launch_status();
+}
+
+template <class Key>
+int radix_sort(Key* k0, Key* k1, uint32_t* v0, uint32_t* v1, const uint64_t* count_dev, int64_t cap_count, int bits,
+               SortWs& w, hipStream_t s, int* final_buf) {
+  const int nblk = (int)std::max<int64_t>(1, ceil_div(cap_count, kRadixTile));
+  Key* kb[2] = {k0, k1};
+  uint32_t* vb[2] = {v0, v1};
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_radix_hist<Key>, dim3(nblk), dim3(kRadixThreads), 0, s, kb[cur], count_dev, shift, nblk, w.hist);
+    int st = device_scan(w.hist, w.hist, nullptr, 256ll * nblk, 256ll * nblk, w.partial, nullptr, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_radix_scatter<Key>, dim3(nblk), dim3(kRadixThreads), 0, s, kb[cur], vb[cur], kb[cur ^ 1],
+                       vb[cur ^ 1], count_dev, shift, nblk, w.hist);
+    cur ^= 1;
+  }
+  *final_buf = cur;
+  return launch_status();
+}
+
+}  // namespace
+
+size_t bin_sort_workspace(int64_t E, int64_t cap) { return plan_sort(E, cap, nullptr).bytes; }
+
+int launch_bin_sort(const gs_config& cfg, const gs_projected& proj, const gs_item* items, int n_items, int64_t n,
+                    int n_tiles, int64_t cap, void* ws, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                    int64_t* n_dup_dev, int32_t* status_dev, hipStream_t s) {
+  const int64_t E = (int64_t)n_items * n;
+  SortWs w = plan_sort(E, cap, ws);
+  uint64_t* n_vis = w.counters + 0;
+  uint64_t* d_total = w.counters + 1;
+  uint64_t* d_live = w.counters + 2;
+  const unsigned eb = (unsigned)std::max<int64_t>(1, ceil_div(E, 256));
+  // 1. compaction of the visible entries
+  hipLaunchKernelGGL(k_visible_flags, dim3(eb), dim3(256), 0, s, proj.radius, E, w.flags);
+  int st = device_scan(w.flags, w.flags, nullptr, E, E, w.partial, n_vis, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_compact, dim3(eb), dim3(256), 0, s, proj.radius, proj.depth, w.flags, E, n, w.vkeys[0],
+                     w.vvals[0]);
+  // 2. stable sort of the visible entries by (item, depth)
+  int fin = 0;
+  st = radix_sort<uint64_t>(w.vkeys[0], w.vkeys[1], w.vvals[0], w.vvals[1], n_vis, E, 32 + bits_for((uint64_t)n_items), w,
+                            s, &fin);
+  if (st) return st;
+  const uint32_t* svals = w.vvals[fin];
+  // 3. duplicates in depth order
+  hipLaunchKernelGGL(k_touched, dim3(eb), dim3(256), 0, s, cfg, svals, n_vis, proj.rec, proj.radius, items, n,
+                     w.touched);
+  st = device_scan(w.touched, w.touched, n_vis, 0, E, w.partial, d_total, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_dup_count, dim3(1), dim3(1), 0, s, d_total, cap, d_live, n_dup_dev, status_dev);
+  // the tile sort must end in the caller's vals: start there after an even pass count
+  const int tbits = std::max(1, bits_for((uint64_t)n_tiles));
+  const int passes = (tbits + 7) / 8;
+  uint32_t* v_first = (passes % 2 == 0) ? vals : w.tvals;
+  uint32_t* v_other = (passes % 2 == 0) ? w.tvals : vals;
+  hipLaunchKernelGGL(k_duplicate, dim3(eb), dim3(256), 0, s, cfg, svals, n_vis, w.touched, proj.rec, proj.radius,
+                     items, n, cap, w.tkeys[0], v_first);
+  // 4. stable sort of the duplicates by tile
+  st = radix_sort<uint32_t>(w.tkeys[0], w.tkeys[1], v_first, v_other, d_live, cap, tbits, w, s, &fin);
+  if (st) return st;
+  const uint32_t* tk = w.tkeys[fin];
+  // 5. tile ranges
+  const int64_t rn = 2ll * n_tiles;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::max<int64_t>(1, ceil_div(rn, 256))), dim3(256), 0, s, ranges, rn, 0u);
+  const unsigned cb = (unsigned)std::max<int64_t>(1, ceil_div(cap, 256));
+  hipLaunchKernelGGL(k_ranges, dim3(cb), dim3(256), 0, s, tk, d_live, ranges);
+  if (keys)
+    hipLaunchKernelGGL(k_full_keys, dim3(cb), dim3(256), 0, s, tk, vals, d_live, proj.depth, items, n_items, n, keys);
+  return launch_status();
+}
+
+}  // namespace gs

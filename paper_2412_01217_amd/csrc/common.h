@@ -1,0 +1,70 @@
+// Internal helpers of the gfx950 rasterizer library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gs.h"
+
+namespace gs {
+
+constexpr int kTile = 16;          // screen tile edge (pixels)
+constexpr int kTilePx = kTile * kTile;
+constexpr int kRecFloats = 8;      // per (item, Gaussian) render record
+
+// Records the last HIP error for gs_last_hip_error(); returns GS_ERR_HIP if e != success.
+int hip_status(hipError_t e);
+int launch_status();  // hipGetLastError() folded into a gs_status
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Item owning a global tile index (items are ordered by tile_base).
+__device__ __forceinline__ int item_of_tile(const gs_item* items, int n_items, int tile) {
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (items[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Item owning a global pixel index (items are ordered by pixel_base).
+__device__ __forceinline__ int item_of_pixel(const gs_item* items, int n_items, int64_t pix) {
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (items[mid].pixel_base <= pix) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Exponent of the 2D footprint, eq. 3 in conic form: -(d^T Q d)/2, d = p - mean2d.
+// mean2d is carried as hi + lo so that d keeps full single precision far from the
+// image origin. A positive-definite conic gives a value <= 0; rounding can make it
+// slightly positive, which is clamped. The forward and the backward call this same
+// sequence (contraction is disabled for the library) so that both see the same alpha.
+__device__ __forceinline__ float footprint_power(float px, float py, float mhx, float mhy, float mlx, float mly,
+                                                 float A, float B, float C, float& dx, float& dy) {
+  dx = (px - mhx) - mlx;
+  dy = (py - mhy) - mly;
+  float q = __builtin_fmaf(A * dx, dx, (C * dy) * dy);
+  float p = __builtin_fmaf(-0.5f, q, -((B * dx) * dy));
+  return fminf(p, 0.0f);
+}
+
+__device__ __forceinline__ float fast_exp(float x) { return __expf(x); }
+
+// Wave64 helpers.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace gs

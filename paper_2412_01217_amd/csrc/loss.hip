@@ -1,0 +1,181 @@
+// Per-level reconstruction loss (paper eq. 10-13, L1 terms; semantics as a per-pixel
+// cross-entropy on the composited class logits) and the image pyramid of the
+// targets (eq. 4-6, 2x2 box means). Both are elementwise over pixels and bound by
+// HBM traffic: one thread per pixel, planar channel reads coalesced along x.
+#include "common.h"
+
+namespace gs {
+namespace {
+
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Number of pixels with a valid (positive) target depth, per item.
+__global__ void k_valid_depth(const gs_item* __restrict__ items, int n_items, int64_t P,
+                              const float* __restrict__ tdepth, float* __restrict__ count) {
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = pix < P;
+  const int item = live ? item_of_pixel(items, n_items, pix) : -1;
+  const float v = (live && tdepth[pix] > 0.0f) ? 1.0f : 0.0f;
+  // wave-uniform item: one atomic per wave, else one per lane
+  const int first = __shfl(item, 0, 64);
+  const bool uniform = __ballot(item != first) == 0ull;
+  if (uniform) {
+    const float s = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && first >= 0 && s != 0.0f) atomicAdd(&count[first], s);
+  } else if (live && v != 0.0f) {
+    atomicAdd(&count[item], v);
+  }
+}
+
+__device__ __forceinline__ float sgn(float d) { return (float)((d > 0.0f) - (d < 0.0f)); }
+
+__global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items, int n_items, int64_t P, int K,
+                                              int n_classes, const float* __restrict__ color,
+                                              const float* __restrict__ logits, const float* __restrict__ trgb,
+                                              const float* __restrict__ tdepth, const int32_t* __restrict__ tlabel,
+                                              float w0, float w1, float w2, const float* __restrict__ nvalid,
+                                              float* __restrict__ loss, float* __restrict__ gcolor,
+                                              float* __restrict__ glogits) {
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = pix < P;
+  float lr = 0.0f, ld = 0.0f, ls = 0.0f;
+  int item = -1;
+  if (live) {
+    item = item_of_pixel(items, n_items, pix);
+    const gs_item it = items[item];
+    const int64_t HW = (int64_t)it.W * it.H;
+    const int64_t p = pix - it.pixel_base;
+    const int64_t cb = it.pixel_base * K + p;
+    const float inv3 = 1.0f / (3.0f * (float)HW);
+    for (int ch = 0; ch < 3; ++ch) {
+      const float d = color[cb + ch * HW] - trgb[it.pixel_base * 3 + ch * HW + p];
+      lr += fabsf(d) * inv3;
+      gcolor[cb + ch * HW] = w0 * sgn(d) * inv3;
+    }
+    const float td = tdepth[pix];
+    if (td > 0.0f) {
+      const float inv = 1.0f / nvalid[item];
+      const float d = color[cb + 3 * HW] - td;
+      ld = fabsf(d) * inv;
+      gcolor[cb + 3 * HW] = w1 * sgn(d) * inv;
+    } else {
+      gcolor[cb + 3 * HW] = 0.0f;
+    }
+    if (n_classes > 0) {
+      // plain mode: logits are colour channels 4..; learned mode: a separate C-plane image
+      const float* L = logits ? logits + it.pixel_base * n_classes + p : color + cb + 4 * HW;
+      float* G = logits ? glogits + it.pixel_base * n_classes + p : gcolor + cb + 4 * HW;
+      float m = -INFINITY;
+      for (int c = 0; c < n_classes; ++c) m = fmaxf(m, L[c * HW]);
+      float z = 0.0f;
+      for (int c = 0; c < n_classes; ++c) z += __expf(L[c * HW] - m);
+      const float lse = m + __logf(z);
+      const int y = tlabel[pix];
+      const float invp = 1.0f / (float)HW;
+      if (y >= 0 && y < n_classes) {
+        ls = (lse - L[(int64_t)y * HW]) * invp;
+        for (int c = 0; c < n_classes; ++c) G[c * HW] = w2 * (__expf(L[c * HW] - lse) - (c == y ? 1.0f : 0.0f)) * invp;
+      } else {  // a label outside [0, C) marks an unlabelled pixel: no semantic term
+        for (int c = 0; c < n_classes; ++c) G[c * HW] = 0.0f;
+      }
+    }
+  }
+  const int first = __shfl(item, 0, 64);
+  const bool uniform = __ballot(item != first) == 0ull;
+  if (uniform) {
+    const float a = wave_sum(lr), b = wave_sum(ld), c = wave_sum(ls);
+    if ((threadIdx.x & 63) == 0 && first >= 0) {
+      atomicAdd(&loss[3 * first + 0], a);
+      atomicAdd(&loss[3 * first + 1], b);
+      atomicAdd(&loss[3 * first + 2], c);
+    }
+  } else if (live) {
+    atomicAdd(&loss[3 * item + 0], lr);
+    atomicAdd(&loss[3 * item + 1], ld);
+    atomicAdd(&loss[3 * item + 2], ls);
+  }
+}
+
+// Level `level` of every view from the level above (item - 1 of the same view).
+__global__ void k_downsample(const gs_item* __restrict__ items, int n_items, int64_t P, int level, int K,
+                             float* __restrict__ img) {
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pix >= P) return;
+  const int item = item_of_pixel(items, n_items, pix);
+  const gs_item it = items[item];
+  if (it.level != level) return;
+  const gs_item up = items[item - 1];
+  const int64_t HW = (int64_t)it.W * it.H, HWu = (int64_t)up.W * up.H;
+  const int64_t p = pix - it.pixel_base;
+  const int x = (int)(p % it.W), y = (int)(p / it.W);
+  const int64_t q = (int64_t)(2 * y) * up.W + 2 * x;
+  const float* src = img + up.pixel_base * K;
+  float* dst = img + it.pixel_base * K;
+  for (int ch = 0; ch < K; ++ch) {
+    const float* s = src + ch * HWu + q;
+    const float a = s[0], b = s[1], c = s[up.W], d = s[up.W + 1];
+    float r;
+    if (ch == 3) {
+      float sum = 0.0f, cnt = 0.0f;
+      if (a > 0.0f) { sum += a; cnt += 1.0f; }
+      if (b > 0.0f) { sum += b; cnt += 1.0f; }
+      if (c > 0.0f) { sum += c; cnt += 1.0f; }
+      if (d > 0.0f) { sum += d; cnt += 1.0f; }
+      r = cnt > 0.0f ? sum / cnt : 0.0f;
+    } else {
+      r = ((a + b) + (c + d)) * 0.25f;
+    }
+    dst[ch * HW + p] = r;
+  }
+}
+
+__global__ void k_argmax_labels(const gs_item* __restrict__ items, int n_items, int64_t P, int K,
+                                const float* __restrict__ img, int32_t* __restrict__ labels) {
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pix >= P) return;
+  const int item = item_of_pixel(items, n_items, pix);
+  const gs_item it = items[item];
+  const int64_t HW = (int64_t)it.W * it.H;
+  const float* s = img + it.pixel_base * K + (pix - it.pixel_base) + 4 * HW;
+  int best = 0;
+  float bv = s[0];
+  for (int c = 1; c < K - 4; ++c) {
+    const float v = s[c * HW];
+    if (v > bv) { bv = v; best = c; }
+  }
+  labels[pix] = best;
+}
+
+}  // namespace
+
+int launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return GS_OK;
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, p, n, v);
+  return launch_status();
+}
+
+int launch_loss(const gs_item* items, int n_items, int64_t P, int K, int n_classes, const float* color,
+                const float* logits, const gs_targets& t, const float* w, float* loss, float* gcolor, float* glogits,
+                float* nvalid, hipStream_t s) {
+  const unsigned pb = (unsigned)std::max<int64_t>(1, ceil_div(P, 256));
+  launch_fill_f32(loss, (int64_t)3 * n_items, 0.0f, s);
+  launch_fill_f32(nvalid, (int64_t)n_items, 0.0f, s);
+  hipLaunchKernelGGL(k_valid_depth, dim3(pb), dim3(256), 0, s, items, n_items, P, t.depth, nvalid);
+  hipLaunchKernelGGL(k_loss, dim3(pb), dim3(256), 0, s, items, n_items, P, K, n_classes, color, logits, t.rgb, t.depth,
+                     t.label, w[0], w[1], w[2], nvalid, loss, gcolor, glogits);
+  return launch_status();
+}
+
+int launch_downsample(const gs_item* items, int n_items, int64_t P, int max_level, int K, float* img, int32_t* labels,
+                      hipStream_t s) {
+  const unsigned pb = (unsigned)std::max<int64_t>(1, ceil_div(P, 256));
+  for (int l = 1; l <= max_level; ++l)
+    hipLaunchKernelGGL(k_downsample, dim3(pb), dim3(256), 0, s, items, n_items, P, l, K, img);
+  if (labels && K > 4) hipLaunchKernelGGL(k_argmax_labels, dim3(pb), dim3(256), 0, s, items, n_items, P, K, img, labels);
+  return launch_status();
+}
+
+}  // namespace gs

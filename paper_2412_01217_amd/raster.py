@@ -1,0 +1,233 @@
+"""Python binding of the C ABI (include/gs.h) on torch tensors.
+
+Argument marshalling only: torch provides device memory and the current stream, and
+every step runs in libgs.so's HIP kernels. There is no CPU fallback; without the
+built library `_lib.lib()` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def config(n_sem: int, **kw) -> L.Config:
+    c = L.Config()
+    L.lib().gs_config_default(ctypes.byref(c))
+    c.n_sem = int(n_sem)
+    for k, v in kw.items():
+        if k == "full_rect":
+            v = int(v)
+        setattr(c, k, v)
+    return c
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Frame:
+    """The item table of one batch of views: every (view, pyramid level) pair."""
+
+    def __init__(self, cfg: L.Config, views, device="cuda"):
+        self.device = torch.device(device)
+        nv = len(views)
+        V = (L.View * max(nv, 1))()
+        W = (ctypes.c_int32 * max(nv, 1))()
+        H = (ctypes.c_int32 * max(nv, 1))()
+        K = (ctypes.c_float * max(4 * nv, 1))()
+        lv = (ctypes.c_int32 * max(nv, 1))()
+        for i, v in enumerate(views):
+            R = np.asarray(v.R, np.float32).reshape(9)
+            t = np.asarray(v.t, np.float32).reshape(3)
+            for k in range(9):
+                V[i].R[k] = float(R[k])
+            for k in range(3):
+                V[i].t[k] = float(t[k])
+            W[i], H[i], lv[i] = int(v.W), int(v.H), int(v.levels)
+            K[4 * i:4 * i + 4] = [float(v.fx), float(v.fy), float(v.cx), float(v.cy)]
+        n_items = sum(int(v.levels) for v in views)
+        items = (L.Item * max(n_items, 1))()
+        npix = ctypes.c_int64()
+        ntile = ctypes.c_int32()
+        r = L.lib().gs_make_items(ctypes.byref(cfg), nv, V, W, H, K, lv, items, ctypes.byref(npix), ctypes.byref(ntile))
+        if r < 0:
+            L.check(r, "gs_make_items")
+        self.views_host = V
+        self.items = items
+        self.n_views = nv
+        self.n_items = n_items
+        self.n_pixels = int(npix.value)
+        self.n_tiles = int(ntile.value)
+        self.max_level = max((int(v.levels) - 1 for v in views), default=0)
+        self.views_dev = torch.frombuffer(bytearray(bytes(V)), dtype=torch.uint8).to(self.device)
+        self.items_dev = torch.frombuffer(bytearray(bytes(items)), dtype=torch.uint8).to(self.device)
+
+    def item_list(self):
+        return [dict(W=it.W, H=it.H, view=it.view, level=it.level, tiles_x=it.tiles_x, tiles_y=it.tiles_y,
+                     tile_base=it.tile_base, pixel_base=it.pixel_base) for it in self.items[:self.n_items]]
+
+
+def gaussians_struct(g: dict) -> L.Gaussians:
+    s = L.Gaussians()
+    s.n = int(g["mean"].shape[0])
+    for k in ("mean", "log_scale", "quat", "opacity", "rgb", "sem", "emb"):
+        t = g.get(k)
+        if t is not None:
+            assert t.is_cuda and t.is_contiguous(), k
+        setattr(s, k, None if t is None else t.data_ptr())
+    return s
+
+
+def to_device(scene, device="cuda") -> dict:
+    d = dict(mean=scene.mean, log_scale=scene.log_scale, quat=scene.quat, opacity=scene.opacity, rgb=scene.rgb)
+    out = {k: torch.as_tensor(np.ascontiguousarray(v, np.float32)).to(device) for k, v in d.items()}
+    if getattr(scene, "sem", None) is not None:
+        out["sem"] = torch.as_tensor(np.ascontiguousarray(scene.sem, np.float32)).to(device)
+    if getattr(scene, "emb", None) is not None:
+        out["emb"] = torch.as_tensor(np.ascontiguousarray(scene.emb).view(np.int16)).to(device)
+    return out
+
+
+def preprocess(cfg, g: dict, frame: Frame) -> dict:
+    n = int(g["mean"].shape[0])
+    E = frame.n_items * n
+    dev = frame.device
+    p = dict(rec=torch.empty(E * 8, dtype=torch.float32, device=dev),
+             depth=torch.empty(E, dtype=torch.float32, device=dev),
+             radius=torch.empty(E, dtype=torch.int32, device=dev))
+    ps = L.Projected(p["rec"].data_ptr(), p["depth"].data_ptr(), p["radius"].data_ptr())
+    gs = gaussians_struct(g)
+    L.check(L.lib().gs_preprocess(ctypes.byref(cfg), ctypes.byref(gs), _ptr(frame.views_dev), frame.n_views,
+                                  _ptr(frame.items_dev), frame.n_items, ctypes.byref(ps), _stream(dev)), "gs_preprocess")
+    return p
+
+
+def _projected(p: dict) -> L.Projected:
+    return L.Projected(p["rec"].data_ptr(), p["depth"].data_ptr(), p["radius"].data_ptr())
+
+
+def workspace_bytes(kind, cfg, frame, n, capacity=0) -> int:
+    b = ctypes.c_size_t()
+    L.check(L.lib().gs_workspace_size(kind, ctypes.byref(cfg), frame.n_items, n, frame.n_tiles, capacity,
+                                      frame.n_pixels, ctypes.byref(b)), "gs_workspace_size")
+    return int(b.value)
+
+
+class Sorter:
+    """Owns the duplicate buffers and the sort workspace for one frame shape."""
+
+    def __init__(self, cfg, frame: Frame, n: int, capacity: int, want_keys=False):
+        dev = frame.device
+        self.cfg, self.frame, self.n, self.capacity = cfg, frame, n, int(capacity)
+        self.ws = torch.empty(workspace_bytes(L.GS_WS_BIN_SORT, cfg, frame, n, self.capacity), dtype=torch.uint8,
+                              device=dev)
+        self.vals = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
+        self.keys = torch.empty(max(self.capacity, 1), dtype=torch.int64, device=dev) if want_keys else None
+        self.ranges = torch.empty(2 * max(frame.n_tiles, 1), dtype=torch.int32, device=dev)
+        self.n_dup = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def run(self, proj: dict):
+        ps = _projected(proj)
+        f = self.frame
+        L.check(L.lib().gs_bin_sort(ctypes.byref(self.cfg), ctypes.byref(ps), _ptr(f.items_dev), f.n_items, self.n,
+                                    f.n_tiles, self.capacity, _ptr(self.ws), self.ws.numel(), _ptr(self.keys),
+                                    _ptr(self.vals), _ptr(self.ranges), _ptr(self.n_dup), _ptr(self.status),
+                                    _stream(f.device)), "gs_bin_sort")
+        return self
+
+
+def bin_sort(cfg, proj: dict, frame: Frame, n: int, capacity=None, want_keys=False) -> Sorter:
+    """Eager binning: grows the capacity (and re-runs) if the duplicates do not fit."""
+    cap = int(capacity) if capacity else max(1 << 16, 4 * frame.n_items * n)
+    while True:
+        s = Sorter(cfg, frame, n, cap, want_keys).run(proj)
+        if int(s.status.item()) == L.GS_OK:
+            return s
+        cap = int(int(s.n_dup.item()) * 1.1) + 1024
+
+
+def alloc_images(cfg, frame: Frame, n_classes=0, learned=False) -> dict:
+    K = 4 + cfg.n_sem
+    dev = frame.device
+    P = frame.n_pixels
+    out = dict(color=torch.empty(P * K, dtype=torch.float32, device=dev),
+               T=torch.empty(P, dtype=torch.float32, device=dev),
+               n_contrib=torch.empty(P, dtype=torch.int32, device=dev), K=K)
+    out["logits"] = torch.empty(P * n_classes, dtype=torch.float32, device=dev) if learned else None
+    return out
+
+
+def _images(d: dict) -> L.Images:
+    return L.Images(*(None if d.get(k) is None else d[k].data_ptr() for k in ("color", "T", "n_contrib", "logits")))
+
+
+def render_fwd(cfg, g: dict, proj: dict, frame: Frame, sorter: Sorter, out=None) -> dict:
+    out = out or alloc_images(cfg, frame)
+    gs = gaussians_struct(g)
+    ps = _projected(proj)
+    im = _images(out)
+    L.check(L.lib().gs_render_fwd(ctypes.byref(cfg), ctypes.byref(gs), ctypes.byref(ps), _ptr(frame.items_dev),
+                                  frame.n_items, frame.n_tiles, _ptr(sorter.vals), _ptr(sorter.ranges), None,
+                                  ctypes.byref(im), _stream(frame.device)), "gs_render_fwd")
+    return out
+
+
+def loss(cfg, frame: Frame, n_classes: int, rendered: dict, targets: dict, w=(1.0, 1.0, 1.0), grad=None,
+         loss_out=None, ws=None):
+    dev = frame.device
+    grad = grad or dict(color=torch.empty_like(rendered["color"]), logits=None)
+    loss_out = loss_out if loss_out is not None else torch.empty(3 * frame.n_items, dtype=torch.float32, device=dev)
+    ws = ws if ws is not None else torch.empty(max(256, 4 * frame.n_items), dtype=torch.uint8, device=dev)
+    t = L.Targets(targets["rgb"].data_ptr(), targets["depth"].data_ptr(),
+                  None if targets.get("label") is None else targets["label"].data_ptr())
+    wv = (ctypes.c_float * 3)(*[float(x) for x in w])
+    ri = _images(rendered)
+    gi = _images(grad)
+    L.check(L.lib().gs_pyramid_loss(ctypes.byref(cfg), _ptr(frame.items_dev), frame.n_items, frame.n_pixels,
+                                    n_classes, ctypes.byref(ri), ctypes.byref(t), wv, _ptr(loss_out),
+                                    ctypes.byref(gi), _ptr(ws), ws.numel(), _stream(dev)), "gs_pyramid_loss")
+    return loss_out.view(frame.n_items, 3), grad
+
+
+def alloc_grads(cfg, g: dict, frame: Frame) -> dict:
+    n = int(g["mean"].shape[0])
+    dev = frame.device
+    z = lambda *s: torch.empty(*s, dtype=torch.float32, device=dev)  # noqa: E731
+    out = dict(mean=z(n, 3), log_scale=z(n, 3), quat=z(n, 4), opacity=z(n), rgb=z(n, 3),
+               sem=z(n, cfg.n_sem) if cfg.n_sem else None, emb=None, pose=z(frame.n_views, 6))
+    return out
+
+
+def render_bwd(cfg, g: dict, proj: dict, frame: Frame, sorter: Sorter, fwd: dict, grad_in: dict, grads=None,
+               ws=None) -> dict:
+    n = int(g["mean"].shape[0])
+    grads = grads or alloc_grads(cfg, g, frame)
+    if ws is None:
+        ws = torch.empty(workspace_bytes(L.GS_WS_RENDER_BWD, cfg, frame, n), dtype=torch.uint8, device=frame.device)
+    gs = gaussians_struct(g)
+    ps = _projected(proj)
+    fi = _images(fwd)
+    gi = _images(grad_in)
+    gr = L.Grads(*(None if grads.get(k) is None else grads[k].data_ptr()
+                   for k in ("mean", "log_scale", "quat", "opacity", "rgb", "sem", "emb", "pose")))
+    L.check(L.lib().gs_render_bwd(ctypes.byref(cfg), ctypes.byref(gs), ctypes.byref(ps), _ptr(frame.views_dev),
+                                  frame.n_views, _ptr(frame.items_dev), frame.n_items, frame.n_tiles,
+                                  _ptr(sorter.vals), _ptr(sorter.ranges), None, ctypes.byref(fi), ctypes.byref(gi),
+                                  ctypes.byref(gr), _ptr(ws), ws.numel(), _stream(frame.device)), "gs_render_bwd")
+    return grads
+
+
+def downsample(frame: Frame, K: int, img: torch.Tensor, labels: torch.Tensor | None = None):
+    L.check(L.lib().gs_pyramid_downsample(_ptr(frame.items_dev), frame.n_items, frame.n_pixels, frame.max_level, K,
+                                          _ptr(img), _ptr(labels), _stream(frame.device)), "gs_pyramid_downsample")
+    return img, labels

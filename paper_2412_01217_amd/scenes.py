@@ -324,3 +324,33 @@ def config_batch(n=500_000, n_classes=20, n_views=8, embed=False):
     sc = room_scene(n=n, n_classes=n_classes, seed=SEED_SCENE + 2, embed=embed)
     views = room_views(sc, n_views, 640, 480, seed=SEED_VIEWS + 2, level_choices=(1, 2, 3))
     return sc, views
+
+
+def synthetic_projection(item_sizes, n, seed=5000, tie_depths=True, cull_frac=0.2, max_radius=40):
+    """Per (item, Gaussian) projected means (hi, lo float pairs), integer radii and
+    float32 depths for testing the binning stage alone.
+
+    item_sizes: list of (W, H). Means are spread over and beyond each image, a fraction
+    of entries is culled (radius 0) and, with tie_depths, depths come from a small set
+    so that many entries tie and the index tie-break decides."""
+    rng = np.random.default_rng(seed)
+    E = len(item_sizes) * n
+    hi = np.empty((E, 2), np.float32)
+    for k, (W, H) in enumerate(item_sizes):
+        s = slice(k * n, (k + 1) * n)
+        hi[s, 0] = rng.uniform(-0.2 * W, 1.2 * W, n)
+        hi[s, 1] = rng.uniform(-0.2 * H, 1.2 * H, n)
+    lo = (rng.normal(size=(E, 2)) * np.abs(hi) * 2.0 ** -26).astype(np.float32)
+    radius = rng.integers(1, max_radius, E).astype(np.int32)
+    radius[rng.uniform(size=E) < cull_frac] = 0
+    if tie_depths:
+        depth = rng.choice(np.float32([0.5, 1.0, 1.25, 2.0, 3.5, 7.0]), E).astype(np.float32)
+    else:
+        depth = rng.uniform(0.25, 20.0, E).astype(np.float32)
+    return hi, lo, radius, depth
+
+
+def random_image(n_pixels, K, seed=5100, scale=1.0):
+    """Planar K-channel image of n_pixels pixels, N(0, scale^2)."""
+    rng = np.random.default_rng(seed)
+    return (rng.normal(size=n_pixels * K) * scale).astype(np.float32)

@@ -1,0 +1,55 @@
+"""Shared test utilities: tolerance checks and pipeline drivers."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rel_check(got, ref, tol, mask=None, floor=0.01, name=""):
+    """Elementwise |got - ref| <= tol * max(|ref|, floor * rms(ref)) outside `mask`.
+
+    Returns a dict with the worst ratio, the relative L2 error and the count checked;
+    raises AssertionError listing the first offenders otherwise."""
+    got = np.asarray(got, np.float64).reshape(-1)
+    ref = np.asarray(ref, np.float64).reshape(-1)
+    keep = np.ones(ref.shape, bool) if mask is None else ~np.asarray(mask, bool).reshape(-1)
+    if not keep.any():
+        return dict(worst=0.0, l2=0.0, n=0)
+    r = ref[keep]
+    g = got[keep]
+    rms = float(np.sqrt(np.mean(r * r))) if r.size else 0.0
+    scale = np.maximum(np.abs(r), floor * rms)
+    scale = np.where(scale > 0, scale, 1e-30)
+    ratio = np.abs(g - r) / (tol * scale)
+    worst = float(ratio.max()) if ratio.size else 0.0
+    l2 = float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300))
+    if worst > 1.0:
+        idx = np.argsort(-ratio)[:5]
+        full = np.flatnonzero(keep)[idx]
+        detail = ", ".join(f"[{i}] got {got[i]:.9g} ref {ref[i]:.9g}" for i in full)
+        raise AssertionError(f"{name}: {int((ratio > 1).sum())}/{ratio.size} beyond tol {tol} "
+                             f"(worst x{worst:.3g}, l2 {l2:.3g}): {detail}")
+    return dict(worst=worst, l2=l2, n=int(ratio.size))
+
+
+def pixel_mask_to_channels(flag, items, K):
+    """Expand a per-pixel flag [P] to the planar K-channel image layout [P*K]."""
+    out = np.zeros(int(sum(it["W"] * it["H"] for it in items)) * K, bool)
+    for it in items:
+        HW = it["W"] * it["H"]
+        p0 = it["pix0"]
+        f = np.asarray(flag[p0:p0 + HW]) != 0
+        out[p0 * K: p0 * K + K * HW] = np.tile(f, K)
+    return out
+
+
+def targets_from_random(views, n_classes, seed=4000, invalid_frac=0.1):
+    """Planar per-item random targets concatenated over items."""
+    import oracle
+    from paper_2412_01217_amd import scenes
+    its = oracle.items(views)
+    parts = scenes.random_targets([it["W"] * it["H"] for it in its], n_classes, seed=seed,
+                                  invalid_frac=invalid_frac)
+    rgb = np.concatenate([p[0].reshape(-1) for p in parts])
+    depth = np.concatenate([p[1] for p in parts])
+    lab = np.concatenate([p[2] for p in parts])
+    return rgb, depth, lab

@@ -1,0 +1,282 @@
+"""HIP path (through the C ABI) against the FP64 oracle, stage by stage.
+
+Bars: binning (keys, values, ranges) bit-exact; integer projection outputs exact
+away from flagged decisions; forward images within 1e-4 relative (per element,
+with a floor of 1% of the tensor's rms) away from flagged pixels; gradients within
+1e-3 relative away from Gaussians that touch a flagged pixel.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_01217_amd import scenes
+from tests.helpers import pixel_mask_to_channels, rel_check, targets_from_random
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = 1e-4
+BWD_TOL = 1e-3
+
+
+def _raster():
+    from paper_2412_01217_amd import raster
+    return raster
+
+
+def small_room(n=6000, n_classes=12, W=200, H=136, levels=3, seed=0):
+    sc = scenes.room_scene(n=n, n_classes=n_classes, seed=scenes.SEED_SCENE + 10 + seed, log_mu=-3.5)
+    views = scenes.room_views(sc, 1, W, H, fx=W / 2, levels=levels, seed=scenes.SEED_VIEWS + 10 + seed)
+    return sc, views
+
+
+CASES = {
+    "tiny": lambda: scenes.config_tiny(),
+    "room_ragged_3lv": lambda: small_room(),
+    "room_two_views": lambda: (lambda sc: (sc, scenes.room_views(sc, 2, 96, 80, levels=2, seed=77)))(
+        scenes.room_scene(n=4000, n_classes=5, seed=1077, log_mu=-3.3)),
+}
+
+
+def _pipeline(sc, views, n_sem):
+    raster = _raster()
+    cfg = raster.config(n_sem)
+    fr = raster.Frame(cfg, views)
+    g = raster.to_device(sc)
+    proj = raster.preprocess(cfg, g, fr)
+    srt = raster.bin_sort(cfg, proj, fr, sc.n, want_keys=True)
+    img = raster.render_fwd(cfg, g, proj, fr, srt)
+    torch.cuda.synchronize()
+    return cfg, fr, g, proj, srt, img
+
+
+def test_item_layout_matches_oracle():
+    raster = _raster()
+    sc, views = small_room()
+    views = views + scenes.room_views(sc, 2, 96, 64, levels=2, seed=9)
+    cfg = raster.config(sc.n_classes)
+    fr = raster.Frame(cfg, views)
+    its = oracle.items(views)
+    assert fr.n_items == len(its)
+    for a, b in zip(fr.item_list(), its):
+        assert (a["W"], a["H"], a["view"], a["level"], a["tile_base"], a["pixel_base"]) == \
+               (b["W"], b["H"], b["view"], b["level"], b["tile0"], b["pix0"])
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_preprocess_parity(case):
+    sc, views = CASES[case]()
+    raster = _raster()
+    cfg = raster.config(sc.n_classes)
+    fr = raster.Frame(cfg, views)
+    proj = raster.preprocess(cfg, raster.to_device(sc), fr)
+    torch.cuda.synchronize()
+    ref = oracle.preprocess(oracle.Config(), sc, views)
+    rad = proj["radius"].cpu().numpy()
+    rec = proj["rec"].cpu().numpy().reshape(-1, 8).astype(np.float64)
+    depth = proj["depth"].cpu().numpy()
+    ok = ref["flag"] == 0
+    np.testing.assert_array_equal(rad[ok], ref["radius"][ok])
+    vis = ok & (ref["radius"] > 0)
+    assert vis.sum() > 0.2 * ok.sum() or case == "room_two_views"
+    m2 = rec[:, 0:2] + rec[:, 2:4]
+    rel_check(m2[vis], ref["m2"][vis], 1e-12, floor=1.0, name="mean2d")
+    rel_check(rec[vis, 4:7], ref["conic"][vis], 2e-7, name="conic")
+    rel_check(rec[vis, 7], ref["opacity"][vis], 2e-7, name="opacity")
+    np.testing.assert_array_equal(depth[vis], ref["depth"][vis].astype(np.float32))
+
+
+def _check_sort(views, n, hi, lo, radius, depth):
+    raster = _raster()
+    cfg = raster.config(0)
+    fr = raster.Frame(cfg, views)
+    E = fr.n_items * n
+    rec = np.zeros((E, 8), np.float32)
+    rec[:, 0:2] = hi
+    rec[:, 2:4] = lo
+    rec[:, 4] = rec[:, 6] = 1.0
+    rec[:, 7] = 0.5
+    proj = dict(rec=torch.from_numpy(rec.reshape(-1)).cuda(), depth=torch.from_numpy(depth).cuda(),
+                radius=torch.from_numpy(radius).cuda())
+    srt = raster.bin_sort(cfg, proj, fr, n, want_keys=True)
+    torch.cuda.synchronize()
+    keys, vals, ranges = oracle.sort_stage(views, n, hi, lo, radius, depth)
+    D = int(srt.n_dup.item())
+    assert D == len(keys)
+    np.testing.assert_array_equal(srt.keys[:D].cpu().numpy().view(np.uint64), keys)
+    np.testing.assert_array_equal(srt.vals[:D].cpu().numpy().view(np.uint32), vals)
+    np.testing.assert_array_equal(srt.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), ranges)
+    return D
+
+
+@pytest.mark.parametrize("seed,ties", [(1, True), (2, False), (3, True)])
+def test_bin_sort_bit_exact_synthetic(seed, ties):
+    views = [scenes.identity_view(200, 120, levels=2), scenes.identity_view(64, 48, levels=1),
+             scenes.identity_view(100, 70, levels=1)]
+    sizes = [(it["W"], it["H"]) for it in oracle.items(views)]
+    n = 3000
+    hi, lo, radius, depth = scenes.synthetic_projection(sizes, n, seed=5000 + seed, tie_depths=ties)
+    assert _check_sort(views, n, hi, lo, radius, depth) > 10000
+
+
+def test_bin_sort_bit_exact_on_oracle_projection():
+    # inputs: the oracle's own projection of a room scene, rounded to single precision
+    sc, views = small_room(n=20000)
+    ref = oracle.preprocess(oracle.Config(), sc, views)
+    hi = ref["m2"].astype(np.float32)
+    lo = (ref["m2"] - hi.astype(np.float64)).astype(np.float32)
+    _check_sort(views, sc.n, hi, lo, ref["radius"].astype(np.int32), ref["depth"].astype(np.float32))
+
+
+def test_bin_sort_capacity_overflow_reports_status():
+    raster = _raster()
+    views = [scenes.identity_view(128, 96)]
+    n = 500
+    hi, lo, radius, depth = scenes.synthetic_projection([(128, 96)], n, seed=5010)
+    cfg = raster.config(0)
+    fr = raster.Frame(cfg, views)
+    rec = np.zeros((n, 8), np.float32)
+    rec[:, 0:2], rec[:, 2:4] = hi, lo
+    proj = dict(rec=torch.from_numpy(rec.reshape(-1)).cuda(), depth=torch.from_numpy(depth).cuda(),
+                radius=torch.from_numpy(radius).cuda())
+    s = raster.Sorter(cfg, fr, n, capacity=100).run(proj)
+    torch.cuda.synchronize()
+    from paper_2412_01217_amd import _lib
+    assert int(s.status.item()) == _lib.GS_ERR_CAPACITY
+    assert int(s.n_dup.item()) > 100
+    # growing the capacity recovers
+    s2 = raster.bin_sort(cfg, proj, fr, n)
+    assert int(s2.status.item()) == _lib.GS_OK and int(s2.n_dup.item()) == int(s.n_dup.item())
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_render_fwd_parity(case):
+    sc, views = CASES[case]()
+    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes)
+    ref = oracle.render(oracle.Config(), sc, views)
+    its = oracle.items(views)
+    K = ref["K"]
+    flag = ref["flag"] != 0
+    assert flag.mean() < 0.01, flag.mean()
+    got = img["color"].cpu().numpy()
+    mask = pixel_mask_to_channels(flag, its, K)
+    for c0, c1, nm in ((0, 3, "rgb"), (3, 4, "depth"), (4, K, "sem")):
+        sel = np.zeros(got.shape, bool)
+        for it in its:
+            HW = it["W"] * it["H"]
+            sel[it["pix0"] * K + c0 * HW: it["pix0"] * K + c1 * HW] = True
+        rel_check(got[sel], ref["img"][sel], FWD_TOL, mask=mask[sel], name=nm)
+    rel_check(img["T"].cpu().numpy(), ref["T"], FWD_TOL, mask=flag, name="T")
+    nc = img["n_contrib"].cpu().numpy()
+    np.testing.assert_array_equal(nc[~flag], ref["n_contrib"][~flag])
+
+
+def test_loss_parity_on_shared_images():
+    raster = _raster()
+    sc, views = small_room(n_classes=9)
+    cfg = raster.config(9)
+    fr = raster.Frame(cfg, views)
+    K = 13
+    img = scenes.random_image(fr.n_pixels, K, seed=5101)
+    t_rgb, t_depth, t_lab = targets_from_random(views, 9, seed=4001)
+    w = (0.8, 1.1, 0.6)
+    ls_ref, g_ref = oracle.loss(views, 9, img, t_rgb, t_depth, t_lab, w=w)
+    T = dict(rgb=torch.from_numpy(t_rgb).cuda(), depth=torch.from_numpy(t_depth).cuda(),
+             label=torch.from_numpy(t_lab).cuda())
+    rendered = dict(color=torch.from_numpy(img).cuda())
+    ls, grad = raster.loss(cfg, fr, 9, rendered, T, w=w)
+    torch.cuda.synchronize()
+    rel_check(ls.cpu().numpy(), ls_ref, 1e-5, name="loss")
+    d = img.astype(np.float64)
+    near_kink = np.zeros(d.shape, bool)     # |R - R_gt| tiny: the L1 sign may differ in FP32
+    rel_check(grad["color"].cpu().numpy(), g_ref, 1e-5, mask=near_kink, name="dloss/dimg")
+
+
+def _shared_grad_image(fr, K, seed):
+    return scenes.random_image(fr.n_pixels, K, seed=seed, scale=1e-3)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_render_bwd_parity(case):
+    sc, views = CASES[case]()
+    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes)
+    raster = _raster()
+    K = 4 + sc.n_classes
+    gimg = _shared_grad_image(fr, K, seed=5200)
+    grads = raster.render_bwd(cfg, g, proj, fr, srt, img, dict(color=torch.from_numpy(gimg).cuda()))
+    torch.cuda.synchronize()
+    ref = oracle.backward(oracle.Config(), sc, views, gimg)
+    bad = ref["gflag"] != 0
+    assert bad.mean() < 0.05, bad.mean()
+    for name in ("mean", "log_scale", "quat", "opacity", "rgb", "sem"):
+        got = grads[name].cpu().numpy()
+        m = np.broadcast_to(bad.reshape(-1, *([1] * (got.ndim - 1))), got.shape)
+        rel_check(got, ref[name], BWD_TOL, mask=m, name=name)
+    if not bad.any():
+        rel_check(grads["pose"].cpu().numpy(), ref["pose"], BWD_TOL, name="pose")
+
+
+def test_end_to_end_tiny_loss_and_gradients():
+    sc, views = scenes.config_tiny()
+    cfg, fr, g, proj, srt, img = _pipeline(sc, views, 8)
+    raster = _raster()
+    t_rgb, t_depth, t_lab = targets_from_random(views, 8, seed=4000, invalid_frac=0.0)
+    T = dict(rgb=torch.from_numpy(t_rgb).cuda(), depth=torch.from_numpy(t_depth).cuda(),
+             label=torch.from_numpy(t_lab).cuda())
+    ls, grad = raster.loss(cfg, fr, 8, img, T)
+    grads = raster.render_bwd(cfg, g, proj, fr, srt, img, grad)
+    torch.cuda.synchronize()
+    r = oracle.render(oracle.Config(), sc, views)
+    ls_ref, gimg = oracle.loss(views, 8, r["img"], t_rgb, t_depth, t_lab)
+    rel_check(ls.cpu().numpy(), ls_ref, 1e-4, name="loss")
+    ref = oracle.backward(oracle.Config(), sc, views, gimg)
+    bad = ref["gflag"] != 0
+    for name in ("mean", "log_scale", "quat", "opacity", "rgb", "sem"):
+        got = grads[name].cpu().numpy()
+        m = np.broadcast_to(bad.reshape(-1, *([1] * (got.ndim - 1))), got.shape)
+        rel_check(got, ref[name], BWD_TOL, mask=m, name=name)
+
+
+def test_empty_and_culled_scenes():
+    raster = _raster()
+    views = [scenes.identity_view(40, 24, levels=1)]
+    # all Gaussians behind the camera
+    sc = scenes.tiny_scene(n=50, n_classes=3)
+    sc.mean[:, 2] = -1.0
+    cfg, fr, g, proj, srt, img = _pipeline(sc, views, 3)
+    assert int(srt.n_dup.item()) == 0
+    np.testing.assert_array_equal(img["color"].cpu().numpy(), 0)
+    np.testing.assert_array_equal(img["T"].cpu().numpy(), 1)
+    gimg = _shared_grad_image(fr, 7, seed=5201)
+    grads = raster.render_bwd(cfg, g, proj, fr, srt, img, dict(color=torch.from_numpy(gimg).cuda()))
+    torch.cuda.synchronize()
+    for k in ("mean", "rgb", "sem", "pose"):
+        np.testing.assert_array_equal(grads[k].cpu().numpy(), 0)
+    # a zero quaternion is culled rather than producing NaN
+    sc2 = scenes.tiny_scene(n=30, n_classes=3)
+    sc2.quat[0] = 0.0
+    cfg, fr, g, proj, srt, img = _pipeline(sc2, views, 3)
+    assert int(proj["radius"][0].item()) == 0
+    assert np.isfinite(img["color"].cpu().numpy()).all()
+
+
+def test_downsample_parity():
+    raster = _raster()
+    views = [scenes.identity_view(64, 48, levels=3), scenes.identity_view(40, 24, levels=2)]
+    cfg = raster.config(5)
+    fr = raster.Frame(cfg, views)
+    K = 9
+    img = scenes.random_image(fr.n_pixels, K, seed=5300)
+    # positive depths with some missing
+    its = oracle.items(views)
+    for it in its:
+        HW = it["W"] * it["H"]
+        d = img[it["pix0"] * K + 3 * HW: it["pix0"] * K + 4 * HW]
+        d[:] = np.where(np.abs(d) < 0.3, 0.0, np.abs(d))
+    ref, lab_ref = oracle.downsample(views, 5, img)
+    t = torch.from_numpy(img.copy()).cuda()
+    lab = torch.empty(fr.n_pixels, dtype=torch.int32, device="cuda")
+    raster.downsample(fr, K, t, lab)
+    torch.cuda.synchronize()
+    rel_check(t.cpu().numpy(), ref, 1e-6, name="pyramid")
+    np.testing.assert_array_equal(lab.cpu().numpy(), lab_ref)

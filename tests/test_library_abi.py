@@ -1,0 +1,101 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol gs.h
+declares, and its host-only helpers (no GPU needed) behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2412_01217_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "gs.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(gs_\w+)\s*\(", text, re.M)))
+
+
+def test_header_and_binding_agree():
+    assert declared_symbols() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(L.Config) == 48
+    assert ctypes.sizeof(L.View) == 56
+    assert ctypes.sizeof(L.Item) == 56
+    assert ctypes.sizeof(L.Gaussians) == 64
+
+
+def test_defaults_and_status_strings():
+    lib = L.lib()
+    c = L.Config()
+    lib.gs_config_default(ctypes.byref(c))
+    assert (c.tile_w, c.tile_h) == (16, 16)
+    assert c.alpha_min == pytest.approx(1 / 255) and c.alpha_max == pytest.approx(0.99)
+    assert c.t_min == pytest.approx(1e-4) and c.z_near == pytest.approx(0.2)
+    assert lib.gs_status_string(L.GS_ERR_CAPACITY) == b"duplicate capacity exceeded"
+    assert lib.gs_version() > 0
+
+
+def _make(levels, W, H, K=(100.0, 100.0, 64.0, 48.0)):
+    lib = L.lib()
+    c = L.Config()
+    lib.gs_config_default(ctypes.byref(c))
+    nv = len(levels)
+    V = (L.View * nv)()
+    items = (L.Item * sum(levels))()
+    Wa = (ctypes.c_int32 * nv)(*W)
+    Ha = (ctypes.c_int32 * nv)(*H)
+    Ka = (ctypes.c_float * (4 * nv))(*(list(K) * nv))
+    La = (ctypes.c_int32 * nv)(*levels)
+    npx = ctypes.c_int64()
+    nt = ctypes.c_int32()
+    r = lib.gs_make_items(ctypes.byref(c), nv, V, Wa, Ha, Ka, La, items, ctypes.byref(npx), ctypes.byref(nt))
+    return r, V, items, npx.value, nt.value
+
+
+def test_make_items_pyramid_layout():
+    r, V, items, npx, nt = _make([3, 1], [1200, 64], [680, 48], K=(600.0, 600.0, 600.0, 340.0))
+    assert r == 4
+    assert [(it.W, it.H, it.level) for it in items] == [(1200, 680, 0), (600, 340, 1), (300, 170, 2), (64, 48, 0)]
+    assert items[2].fx == 150.0 and items[2].cx == 150.0 and items[1].cy == 170.0
+    assert items[1].tile_base == 75 * 43 and items[1].pixel_base == 1200 * 680
+    assert npx == 1200 * 680 + 600 * 340 + 300 * 170 + 64 * 48
+    assert nt == 75 * 43 + 38 * 22 + 19 * 11 + 4 * 3
+    assert (V[0].item_first, V[0].item_count, V[1].item_first) == (0, 3, 3)
+
+
+def test_make_items_rejects_indivisible_pyramid():
+    r, *_ = _make([3], [100], [70])
+    assert r == L.GS_ERR_INVALID_ARG
+
+
+def test_entry_points_reject_bad_arguments_on_host():
+    lib = L.lib()
+    c = L.Config()
+    lib.gs_config_default(ctypes.byref(c))
+    c.tile_w = 8
+    g = L.Gaussians()
+    p = L.Projected()
+    assert lib.gs_preprocess(ctypes.byref(c), ctypes.byref(g), None, 0, None, 0, ctypes.byref(p), None) == \
+        L.GS_ERR_INVALID_ARG
+    lib.gs_config_default(ctypes.byref(c))
+    c.n_sem = 65
+    b = ctypes.c_size_t()
+    assert lib.gs_workspace_size(L.GS_WS_BIN_SORT, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == \
+        L.GS_ERR_INVALID_ARG
+    lib.gs_config_default(ctypes.byref(c))
+    assert lib.gs_workspace_size(L.GS_WS_BIN_SORT, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == 0
+    assert b.value > 0
+    # workspace too small is reported before any launch
+    g.n = 10
+    assert lib.gs_bin_sort(ctypes.byref(c), ctypes.byref(p), ctypes.c_void_p(16), 1, 10, 4, 100,
+                           ctypes.c_void_p(16), 1, None, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None,
+                           None) in (L.GS_ERR_INVALID_ARG, L.GS_ERR_WORKSPACE)
