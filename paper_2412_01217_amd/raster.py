@@ -97,18 +97,25 @@ def to_device(scene, device="cuda") -> dict:
     return out
 
 
-def preprocess(cfg, g: dict, frame: Frame) -> dict:
-    n = int(g["mean"].shape[0])
+def alloc_projected(frame: Frame, n: int) -> dict:
     E = frame.n_items * n
     dev = frame.device
-    p = dict(rec=torch.empty(E * 8, dtype=torch.float32, device=dev),
-             depth=torch.empty(E, dtype=torch.float32, device=dev),
-             radius=torch.empty(E, dtype=torch.int32, device=dev))
+    return dict(rec=torch.empty(E * 8, dtype=torch.float32, device=dev),
+                depth=torch.empty(E, dtype=torch.float32, device=dev),
+                radius=torch.empty(E, dtype=torch.int32, device=dev))
+
+
+def preprocess_into(cfg, g: dict, frame: Frame, p: dict) -> dict:
     ps = L.Projected(p["rec"].data_ptr(), p["depth"].data_ptr(), p["radius"].data_ptr())
     gs = gaussians_struct(g)
     L.check(L.lib().gs_preprocess(ctypes.byref(cfg), ctypes.byref(gs), _ptr(frame.views_dev), frame.n_views,
-                                  _ptr(frame.items_dev), frame.n_items, ctypes.byref(ps), _stream(dev)), "gs_preprocess")
+                                  _ptr(frame.items_dev), frame.n_items, ctypes.byref(ps), _stream(frame.device)),
+            "gs_preprocess")
     return p
+
+
+def preprocess(cfg, g: dict, frame: Frame) -> dict:
+    return preprocess_into(cfg, g, frame, alloc_projected(frame, int(g["mean"].shape[0])))
 
 
 def _projected(p: dict) -> L.Projected:

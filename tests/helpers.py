@@ -4,8 +4,12 @@ from __future__ import annotations
 import numpy as np
 
 
-def rel_check(got, ref, tol, mask=None, floor=0.01, name=""):
-    """Elementwise |got - ref| <= tol * max(|ref|, floor * rms(ref)) outside `mask`.
+def rel_check(got, ref, tol, mask=None, floor=0.01, name="", scale=None):
+    """Elementwise |got - ref| <= tol * max(|ref|, floor * rms(ref), scale) outside `mask`.
+
+    `scale` (optional, same shape) is a per-element magnitude such as the sum of the
+    absolute values of the terms that make up ref: a sum with cancellation cannot be
+    expected to hold more relative precision than its terms.
 
     Returns a dict with the worst ratio, the relative L2 error and the count checked;
     raises AssertionError listing the first offenders otherwise."""
@@ -17,8 +21,10 @@ def rel_check(got, ref, tol, mask=None, floor=0.01, name=""):
     r = ref[keep]
     g = got[keep]
     rms = float(np.sqrt(np.mean(r * r))) if r.size else 0.0
-    scale = np.maximum(np.abs(r), floor * rms)
-    scale = np.where(scale > 0, scale, 1e-30)
+    mag = np.maximum(np.abs(r), floor * rms)
+    if scale is not None:
+        mag = np.maximum(mag, np.abs(np.asarray(scale, np.float64).reshape(-1)[keep]))
+    scale = np.where(mag > 0, mag, 1e-30)
     ratio = np.abs(g - r) / (tol * scale)
     worst = float(ratio.max()) if ratio.size else 0.0
     l2 = float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300))
