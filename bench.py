@@ -70,44 +70,6 @@ def build_workload(name, device):
     return dict(scene=sc, views=views, cfg=cfg, frame=fr, g=g, targets=targets, C=C, K=K, desc=desc)
 
 
-class Step:
-    """Buffers allocated once; run() enqueues one full forward + loss + backward."""
-
-    def __init__(self, wl, device):
-        import torch
-        from paper_2412_01217_amd import raster
-        self.raster = raster
-        self.wl = wl
-        cfg, fr, g = wl["cfg"], wl["frame"], wl["g"]
-        n = int(g["mean"].shape[0])
-        self.proj = raster.preprocess(cfg, g, fr)
-        probe = raster.bin_sort(cfg, self.proj, fr, n)
-        D = int(probe.n_dup.item())
-        self.sorter = raster.Sorter(cfg, fr, n, capacity=int(D * 1.15) + 4096)
-        self.img = raster.alloc_images(cfg, fr)
-        self.grad = dict(color=torch.empty_like(self.img["color"]), logits=None)
-        self.loss = torch.empty(3 * fr.n_items, dtype=torch.float32, device=device)
-        self.loss_ws = torch.empty(max(256, 4 * fr.n_items), dtype=torch.uint8, device=device)
-        self.grads = raster.alloc_grads(cfg, g, fr)
-        self.bwd_ws = torch.empty(raster.workspace_bytes(raster.L.GS_WS_RENDER_BWD, cfg, fr, n), dtype=torch.uint8,
-                                  device=device)
-        self.n_dup = D
-
-    def run(self, ev=None):
-        r, wl = self.raster, self.wl
-        cfg, fr, g = wl["cfg"], wl["frame"], wl["g"]
-        r.preprocess_into(cfg, g, fr, self.proj)
-        if ev: ev[0].record()
-        self.sorter.run(self.proj)
-        if ev: ev[1].record()
-        r.render_fwd(cfg, g, self.proj, fr, self.sorter, out=self.img)
-        if ev: ev[2].record()
-        r.loss(cfg, fr, wl["C"], self.img, wl["targets"], grad=self.grad, loss_out=self.loss, ws=self.loss_ws)
-        if ev: ev[3].record()
-        r.render_bwd(cfg, g, self.proj, fr, self.sorter, self.img, self.grad, grads=self.grads, ws=self.bwd_ws)
-        if ev: ev[4].record()
-
-
 def cpu_baseline(wl, budget_s=15.0):
     """The FP64 oracle (single thread) on a bounded sample of the same workload:
     forward + loss + backward restricted to a set of tiles of the first item."""
@@ -145,6 +107,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="room")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant", type=int, default=0, help="render kernels: 0 auto, 1 VALU, 2 MFMA")
+    ap.add_argument("--eager", action="store_true", help="time eager calls instead of graph replays")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -154,22 +118,23 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     wl = build_workload(args.workload, dev)
-    step = Step(wl, dev)
+    wl["cfg"].variant = args.variant
+    from paper_2412_01217_amd.step import MappingStep
+    step = MappingStep(wl["cfg"], wl["frame"], wl["g"], wl["targets"], wl["C"])
     fr = wl["frame"]
     for _ in range(args.warmup):
         step.run()
     torch.cuda.synchronize()
+    # eager pass with events between the library calls: per-stage times on the launch stream
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
     for k in range(args.steps):
         step.run(evs[k])
-    stop.record()
+    t1.record()
     torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
-    ms = total_ms / args.steps
+    eager_ms = t0.elapsed_time(t1) / args.steps
     stage = {"bin_sort": [], "render_fwd": [], "loss": [], "render_bwd": []}
     for e in evs:
         stage["bin_sort"].append(e[0].elapsed_time(e[1]))
@@ -177,26 +142,47 @@ def main():
         stage["loss"].append(e[2].elapsed_time(e[3]))
         stage["render_bwd"].append(e[3].elapsed_time(e[4]))
     stage_ms = {k: float(np.mean(v)) for k, v in stage.items()}
-    stage_ms["preprocess_and_gaps"] = ms - sum(stage_ms.values())
+    stage_ms["preprocess_and_gaps"] = eager_ms - sum(stage_ms.values())
+    # the whole step captured once in a HIP graph and replayed: the timed region
+    from paper_2412_01217_amd import raster
+    graph = raster.Graph(step.run, dev) if not args.eager else None
+    run = (lambda: graph.launch()) if graph else step.run
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(args.steps):
+        run()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
     mp = fr.n_pixels / 1e6
-    # algorithmic work of the forward compositing kernel: pairs iterated per pixel
+    # algorithmic work of the compositing kernels, per (pixel, Gaussian) pair iterated up to each
+    # pixel's stop point (E = sum of n_contrib): forward 18 + 2K flop, backward 45 + 6K flop
     nc = step.img["n_contrib"].to(torch.int64).sum().item()
     K = wl["K"]
-    fwd_flops = nc * (18 + 2 * K)
-    fwd_ms = stage_ms["render_fwd"]
-    achieved = fwd_flops / (fwd_ms * 1e-3) / 1e12
+    kern = {}
+    for name, stage_name, per_pair in (("k_render_fwd", "render_fwd", 18 + 2 * K),
+                                       ("k_render_bwd", "render_bwd", 45 + 6 * K)):
+        flops = nc * per_pair
+        t = stage_ms[stage_name]
+        ach = flops / (t * 1e-3) / 1e12
+        kern[name] = {"bound": "alu", "kernel": name, "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": ach / VALU_PEAK_TFLOPS, "frac_unpacked_peak": ach / VALU_PEAK_UNPACKED_TFLOPS,
+                      "traffic": None, "flops_per_launch": flops, "avg_launch_ms": t,
+                      "timed_call": "gs_" + stage_name}
+    dominant = max(kern, key=lambda k: kern[k]["avg_launch_ms"])
     out = {
         "metric": METRIC, "value": mp / (ms * 1e-3), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl["desc"], "gaussians": int(wl["g"]["mean"].shape[0]), "classes": wl["C"],
-                   "pixels_per_step": fr.n_pixels, "items": fr.n_items, "duplicates": step.n_dup,
-                   "pairs_iterated": int(nc), "semantic_mode": "plain"},
+                   "pixels_per_step": fr.n_pixels, "items": fr.n_items, "duplicates": step.n_dup_probe,
+                   "pairs_iterated": int(nc), "semantic_mode": "plain", "render_variant": args.variant},
+        "eager_ms_per_step": eager_ms, "timed": "eager calls" if args.eager else "HIP graph replay of the whole step",
         "stage_ms": stage_ms,
-        "roofline": {"bound": "alu", "kernel": "k_render_fwd", "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS,
-                     "frac_unpacked_peak": achieved / VALU_PEAK_UNPACKED_TFLOPS, "traffic": None,
-                     "flops_per_launch": fwd_flops, "avg_launch_ms": fwd_ms},
+        "roofline": kern[dominant],
+        "roofline_other": {k: v for k, v in kern.items() if k != dominant},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -55,8 +55,8 @@ typedef struct gs_config {
   float t_min;             /* 1e-4: a pixel stops before T would fall below t_min */
   float guard;             /* 1.3: x/z, y/z clamped to +-guard*(W/2)/fx inside J */
   int32_t full_rect;       /* 0; 1 = every Gaussian covers every tile of its item */
-  int32_t n_sem;           /* composited semantic channels (plain: classes; learned: 16) */
-  int32_t variant;         /* render kernel variant; 0 = automatic */
+  int32_t n_sem;           /* composited semantic channels, 0..60 (plain: classes; learned: 16) */
+  int32_t variant;         /* render kernels: 0 automatic, 1 per-lane FMA (VALU), 2 matrix cores (MFMA) */
   int32_t reserved;
 } gs_config;
 
@@ -218,6 +218,18 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
  * every item, the argmax over channels 4..K-1 (ties to the lowest index). */
 int gs_pyramid_downsample(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t max_level,
                           int32_t K, float* img, int32_t* labels, void* stream);
+
+/* ---- graph capture of a whole step (Sec. III-C/D: one mapping iteration) ----
+ * Every hot-path call above only enqueues kernels and never synchronises, so a full
+ * step (preprocess, bin_sort, render_fwd, pyramid_loss, render_bwd) can be captured
+ * once and replayed. gs_graph_begin starts a capture of `stream` (relaxed mode);
+ * gs_graph_end ends it and instantiates the graph into *graph_exec (host memory owned
+ * by the library until gs_graph_destroy). Buffers referenced by the captured calls
+ * must stay allocated and keep their addresses while the graph is replayed. */
+int gs_graph_begin(void* stream);
+int gs_graph_end(void* stream, void** graph_exec);
+int gs_graph_launch(void* graph_exec, void* stream);
+int gs_graph_destroy(void* graph_exec);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,8 @@ GS_WS_LOSS = 3
 EXPORTS = (
     "gs_config_default", "gs_status_string", "gs_last_hip_error", "gs_version", "gs_make_items",
     "gs_workspace_size", "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_pyramid_loss",
-    "gs_render_bwd", "gs_pyramid_downsample",
+    "gs_render_bwd", "gs_pyramid_downsample", "gs_graph_begin", "gs_graph_end", "gs_graph_launch",
+    "gs_graph_destroy",
 )
 
 
@@ -106,8 +107,13 @@ def lib():
                                     c_size_t, c_void_p]
         L.gs_pyramid_downsample.argtypes = [c_void_p, c_int32, c_int64, c_int32, c_int32, c_void_p, c_void_p,
                                             c_void_p]
+        L.gs_graph_begin.argtypes = [c_void_p]
+        L.gs_graph_end.argtypes = [c_void_p, P(c_void_p)]
+        L.gs_graph_launch.argtypes = [c_void_p, c_void_p]
+        L.gs_graph_destroy.argtypes = [c_void_p]
         for name in ("gs_make_items", "gs_workspace_size", "gs_preprocess", "gs_bin_sort", "gs_render_fwd",
-                     "gs_pyramid_loss", "gs_render_bwd", "gs_pyramid_downsample"):
+                     "gs_pyramid_loss", "gs_render_bwd", "gs_pyramid_downsample", "gs_graph_begin", "gs_graph_end",
+                     "gs_graph_launch", "gs_graph_destroy"):
             getattr(L, name).restype = c_int32
         _lib = L
     return _lib

@@ -23,14 +23,38 @@ int launch_preprocess_bwd(const gs_config&, const gs_gaussians&, const gs_view*,
 size_t bin_sort_workspace(int64_t E, int64_t cap);
 int launch_bin_sort(const gs_config&, const gs_projected&, const gs_item*, int, int64_t, int, int64_t, void*, uint64_t*,
                     uint32_t*, uint32_t*, int64_t*, int32_t*, hipStream_t);
-int launch_render_fwd(const gs_config&, const gs_gaussians&, const gs_projected&, const gs_item*, int, int,
-                      const uint32_t*, const uint32_t*, const gs_images&, hipStream_t);
-int launch_render_bwd(const gs_config&, const gs_gaussians&, const gs_projected&, const gs_item*, int, int,
-                      const uint32_t*, const uint32_t*, const gs_images&, const gs_images&, float*, const gs_grads&,
-                      hipStream_t);
+#define GS_RENDER_FWD_ARGS                                                                                 \
+  const gs_config&, const gs_gaussians&, const gs_projected&, const gs_item*, int, int, const uint32_t*, \
+      const uint32_t*, const gs_images&, hipStream_t
+#define GS_RENDER_BWD_ARGS                                                                                 \
+  const gs_config&, const gs_gaussians&, const gs_projected&, const gs_item*, int, int, const uint32_t*, \
+      const uint32_t*, const gs_images&, const gs_images&, float*, const gs_grads&, hipStream_t
+int launch_render_fwd_valu(GS_RENDER_FWD_ARGS);
+int launch_render_bwd_valu(GS_RENDER_BWD_ARGS);
+int launch_render_fwd_mfma(GS_RENDER_FWD_ARGS);
+int launch_render_bwd_mfma(GS_RENDER_BWD_ARGS);
+
+// Render kernel variants: 1 = per-lane FMA accumulation (VALU), 2 = matrix-core channel
+// contraction (MFMA). 0 picks MFMA.
+int launch_render_fwd(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
+                      int n_items, int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& out,
+                      hipStream_t s) {
+  if (n_tiles == 0) return GS_OK;
+  if (cfg.variant == 1) return launch_render_fwd_valu(cfg, g, p, items, n_items, n_tiles, vals, ranges, out, s);
+  return launch_render_fwd_mfma(cfg, g, p, items, n_items, n_tiles, vals, ranges, out, s);
+}
+int launch_render_bwd(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
+                      int n_items, int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& fwd,
+                      const gs_images& gin, float* g2d, const gs_grads& gr, hipStream_t s) {
+  if (n_tiles == 0) return GS_OK;
+  if (cfg.variant == 1)
+    return launch_render_bwd_valu(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
+  return launch_render_bwd_mfma(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
+}
 int launch_loss(const gs_item*, int, int64_t, int, int, const float*, const float*, const gs_targets&, const float*,
                 float*, float*, float*, float*, hipStream_t);
 int launch_downsample(const gs_item*, int, int64_t, int, int, float*, int32_t*, hipStream_t);
+size_t loss_workspace(int n_items);
 int launch_fill_f32(float*, int64_t, float, hipStream_t);
 
 namespace {
@@ -40,7 +64,8 @@ bool cfg_ok(const gs_config* c) {
   if (c->tile_w != kTile || c->tile_h != kTile) return false;
   if (!(c->z_near > 0.0f) || !(c->eps_dilate >= 0.0f) || !(c->alpha_min >= 0.0f)) return false;
   if (!(c->alpha_max > c->alpha_min) || !(c->alpha_max < 1.0f) || !(c->t_min >= 0.0f) || !(c->guard > 0.0f)) return false;
-  if (c->n_sem < 0 || c->n_sem > 64) return false;
+  if (c->n_sem < 0 || c->n_sem > 60) return false;
+  if (c->variant < 0 || c->variant > 2) return false;
   return true;
 }
 
@@ -143,7 +168,7 @@ int gs_workspace_size(int kind, const gs_config* cfg, int32_t n_items, int64_t n
       *bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)n_gauss);
       return GS_OK;
     case GS_WS_LOSS:
-      *bytes = align_up(sizeof(float) * (size_t)std::max(n_items, 1));
+      *bytes = align_up(loss_workspace(n_items));
       return GS_OK;
     default:
       return GS_ERR_INVALID_ARG;
@@ -198,7 +223,7 @@ int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_it
   } else if (n_classes != cfg->n_sem) {
     return GS_ERR_INVALID_ARG;
   }
-  if (!workspace || ws_bytes < align_up(sizeof(float) * (size_t)n_items)) return GS_ERR_WORKSPACE;
+  if (!workspace || ws_bytes < loss_workspace(n_items)) return GS_ERR_WORKSPACE;
   return launch_loss(items_dev, n_items, n_pixels, 4 + cfg->n_sem, n_classes, rendered->color, rendered->logits,
                      *targets, w, loss_dev, grad_out->color, grad_out->logits, (float*)workspace, (hipStream_t)stream);
 }
@@ -231,6 +256,34 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
     if (st) return st;
   }
   return launch_preprocess_bwd(*cfg, *g, views_dev, n_views, items_dev, (const float*)workspace, proj->radius, *grads, s);
+}
+
+int gs_graph_begin(void* stream) {
+  if (!stream) return GS_ERR_INVALID_ARG;  // the legacy null stream cannot be captured
+  return hip_status(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeRelaxed));
+}
+
+int gs_graph_end(void* stream, void** graph_exec) {
+  if (!stream || !graph_exec) return GS_ERR_INVALID_ARG;
+  hipGraph_t graph = nullptr;
+  int st = hip_status(hipStreamEndCapture((hipStream_t)stream, &graph));
+  if (st) return st;
+  hipGraphExec_t exec = nullptr;
+  st = hip_status(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  hipGraphDestroy(graph);
+  if (st) return st;
+  *graph_exec = (void*)exec;
+  return GS_OK;
+}
+
+int gs_graph_launch(void* graph_exec, void* stream) {
+  if (!graph_exec) return GS_ERR_INVALID_ARG;
+  return hip_status(hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream));
+}
+
+int gs_graph_destroy(void* graph_exec) {
+  if (!graph_exec) return GS_OK;
+  return hip_status(hipGraphExecDestroy((hipGraphExec_t)graph_exec));
 }
 
 int gs_pyramid_downsample(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t max_level, int32_t K,

@@ -12,9 +12,15 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
   if (i < n) p[i] = v;
 }
 
-// Number of pixels with a valid (positive) target depth, per item.
+// Partial sums are spread over kSlots addresses per item (slot = block index mod kSlots)
+// so that thousands of blocks do not serialise on one atomic address; a one-block
+// kernel folds the slots afterwards.
+constexpr int kSlots = 64;
+
+// Number of pixels with a valid (positive) target depth, per item: count[item * kSlots + slot].
 __global__ void k_valid_depth(const gs_item* __restrict__ items, int n_items, int64_t P,
-                              const float* __restrict__ tdepth, float* __restrict__ count) {
+                              const float* __restrict__ tdepth, float* __restrict__ count_slots) {
+  float* count = count_slots + (blockIdx.x % kSlots);
   const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = pix < P;
   const int item = live ? item_of_pixel(items, n_items, pix) : -1;
@@ -24,9 +30,19 @@ __global__ void k_valid_depth(const gs_item* __restrict__ items, int n_items, in
   const bool uniform = __ballot(item != first) == 0ull;
   if (uniform) {
     const float s = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && first >= 0 && s != 0.0f) atomicAdd(&count[first], s);
+    if ((threadIdx.x & 63) == 0 && first >= 0 && s != 0.0f) atomicAdd(&count[first * kSlots], s);
   } else if (live && v != 0.0f) {
-    atomicAdd(&count[item], v);
+    atomicAdd(&count[item * kSlots], v);
+  }
+}
+
+// out[i * stride + c] = sum over slots of in[(i * ncomp + c) * kSlots + slot].
+__global__ void k_fold_slots(const float* __restrict__ in, int n_items, int ncomp, float* __restrict__ out) {
+  for (int i = threadIdx.x; i < n_items * ncomp; i += blockDim.x) {
+    const float* src = in + (int64_t)i * kSlots;
+    float s = 0.0f;
+    for (int k = 0; k < kSlots; ++k) s += src[k];
+    out[i] = s;
   }
 }
 
@@ -37,8 +53,9 @@ __global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items,
                                               const float* __restrict__ logits, const float* __restrict__ trgb,
                                               const float* __restrict__ tdepth, const int32_t* __restrict__ tlabel,
                                               float w0, float w1, float w2, const float* __restrict__ nvalid,
-                                              float* __restrict__ loss, float* __restrict__ gcolor,
+                                              float* __restrict__ loss_slots, float* __restrict__ gcolor,
                                               float* __restrict__ glogits) {
+  float* loss = loss_slots + (blockIdx.x % kSlots);
   const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = pix < P;
   float lr = 0.0f, ld = 0.0f, ls = 0.0f;
@@ -88,14 +105,14 @@ __global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items,
   if (uniform) {
     const float a = wave_sum(lr), b = wave_sum(ld), c = wave_sum(ls);
     if ((threadIdx.x & 63) == 0 && first >= 0) {
-      atomicAdd(&loss[3 * first + 0], a);
-      atomicAdd(&loss[3 * first + 1], b);
-      atomicAdd(&loss[3 * first + 2], c);
+      atomicAdd(&loss[(3 * first + 0) * kSlots], a);
+      atomicAdd(&loss[(3 * first + 1) * kSlots], b);
+      atomicAdd(&loss[(3 * first + 2) * kSlots], c);
     }
   } else if (live) {
-    atomicAdd(&loss[3 * item + 0], lr);
-    atomicAdd(&loss[3 * item + 1], ld);
-    atomicAdd(&loss[3 * item + 2], ls);
+    atomicAdd(&loss[(3 * item + 0) * kSlots], lr);
+    atomicAdd(&loss[(3 * item + 1) * kSlots], ld);
+    atomicAdd(&loss[(3 * item + 2) * kSlots], ls);
   }
 }
 
@@ -157,15 +174,21 @@ int launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   return launch_status();
 }
 
+size_t loss_workspace(int n_items) { return sizeof(float) * (size_t)std::max(n_items, 1) * (4 * kSlots + 1); }
+
 int launch_loss(const gs_item* items, int n_items, int64_t P, int K, int n_classes, const float* color,
                 const float* logits, const gs_targets& t, const float* w, float* loss, float* gcolor, float* glogits,
-                float* nvalid, hipStream_t s) {
+                float* ws, hipStream_t s) {
   const unsigned pb = (unsigned)std::max<int64_t>(1, ceil_div(P, 256));
-  launch_fill_f32(loss, (int64_t)3 * n_items, 0.0f, s);
-  launch_fill_f32(nvalid, (int64_t)n_items, 0.0f, s);
-  hipLaunchKernelGGL(k_valid_depth, dim3(pb), dim3(256), 0, s, items, n_items, P, t.depth, nvalid);
+  float* count_slots = ws;                                   // [n_items][kSlots]
+  float* loss_slots = ws + (int64_t)n_items * kSlots;        // [n_items][3][kSlots]
+  float* nvalid = ws + (int64_t)n_items * 4 * kSlots;        // [n_items]
+  launch_fill_f32(ws, (int64_t)n_items * 4 * kSlots, 0.0f, s);
+  hipLaunchKernelGGL(k_valid_depth, dim3(pb), dim3(256), 0, s, items, n_items, P, t.depth, count_slots);
+  hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(256), 0, s, count_slots, n_items, 1, nvalid);
   hipLaunchKernelGGL(k_loss, dim3(pb), dim3(256), 0, s, items, n_items, P, K, n_classes, color, logits, t.rgb, t.depth,
-                     t.label, w[0], w[1], w[2], nvalid, loss, gcolor, glogits);
+                     t.label, w[0], w[1], w[2], nvalid, loss_slots, gcolor, glogits);
+  hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(256), 0, s, loss_slots, n_items, 3, loss);
   return launch_status();
 }
 

@@ -252,7 +252,7 @@ int launch_bwd_t(const gs_config& cfg, const gs_gaussians& g, const gs_projected
 
 }  // namespace
 
-int launch_render_fwd(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
+int launch_render_fwd_valu(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
                       int n_items, int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& out,
                       hipStream_t s) {
   if (n_tiles == 0) return GS_OK;
@@ -266,7 +266,7 @@ int launch_render_fwd(const gs_config& cfg, const gs_gaussians& g, const gs_proj
   return GS_ERR_UNSUPPORTED;
 }
 
-int launch_render_bwd(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
+int launch_render_bwd_valu(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
                       int n_items, int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& fwd,
                       const gs_images& gin, float* g2d, const gs_grads& gr, hipStream_t s) {
   if (n_tiles == 0) return GS_OK;

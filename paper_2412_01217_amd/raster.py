@@ -194,7 +194,8 @@ def loss(cfg, frame: Frame, n_classes: int, rendered: dict, targets: dict, w=(1.
     dev = frame.device
     grad = grad or dict(color=torch.empty_like(rendered["color"]), logits=None)
     loss_out = loss_out if loss_out is not None else torch.empty(3 * frame.n_items, dtype=torch.float32, device=dev)
-    ws = ws if ws is not None else torch.empty(max(256, 4 * frame.n_items), dtype=torch.uint8, device=dev)
+    ws = ws if ws is not None else torch.empty(workspace_bytes(L.GS_WS_LOSS, cfg, frame, 0), dtype=torch.uint8,
+                                               device=dev)
     t = L.Targets(targets["rgb"].data_ptr(), targets["depth"].data_ptr(),
                   None if targets.get("label") is None else targets["label"].data_ptr())
     wv = (ctypes.c_float * 3)(*[float(x) for x in w])
@@ -238,3 +239,35 @@ def downsample(frame: Frame, K: int, img: torch.Tensor, labels: torch.Tensor | N
     L.check(L.lib().gs_pyramid_downsample(_ptr(frame.items_dev), frame.n_items, frame.n_pixels, frame.max_level, K,
                                           _ptr(img), _ptr(labels), _stream(frame.device)), "gs_pyramid_downsample")
     return img, labels
+
+
+class Graph:
+    """A captured sequence of library calls (gs_graph_*), replayed on a stream.
+
+    fn() must only enqueue work (every gs_* hot-path call does) on the current torch
+    stream, and every buffer it touches must outlive the graph."""
+
+    def __init__(self, fn, device="cuda"):
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(self.device)
+        self.exec = ctypes.c_void_p()
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.stream(self.stream):
+            s = ctypes.c_void_p(self.stream.cuda_stream)
+            L.check(L.lib().gs_graph_begin(s), "gs_graph_begin")
+            try:
+                fn()
+            finally:
+                L.check(L.lib().gs_graph_end(s, ctypes.byref(self.exec)), "gs_graph_end")
+        torch.cuda.synchronize(self.device)
+
+    def launch(self, stream=None):
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L.check(L.lib().gs_graph_launch(self.exec, ctypes.c_void_p(st.cuda_stream)), "gs_graph_launch")
+
+    def __del__(self):
+        try:
+            if self.exec:
+                L.lib().gs_graph_destroy(self.exec)
+        except Exception:
+            pass

@@ -251,7 +251,8 @@ def _rot(axis, ang):
 def room_views(scene, n_views, W, H, fx=None, fy=None, cx=None, cy=None, levels=1,
                seed=SEED_VIEWS, level_choices=None):
     """Cameras uniform in the room shrunk by 0.5 m, at least 0.2 m from every box,
-    yaw U[0,2pi), pitch U(-30,30) deg, roll U(-10,10) deg.
+    yaw towards the room centre +- U(-60,60) deg (keyframes look into the room, not
+    into the nearest wall), pitch U(-30,30) deg, roll U(-10,10) deg.
 
     `levels` is a fixed pyramid depth, or `level_choices` a tuple to draw from per view."""
     rng = np.random.default_rng(seed)
@@ -269,7 +270,8 @@ def room_views(scene, n_views, W, H, fx=None, fy=None, cx=None, cy=None, levels=
         for lo, hi in scene.boxes:
             if np.all(c > lo - 0.2) and np.all(c < hi + 0.2):
                 bad = True
-        yaw = rng.uniform(0, 2 * math.pi)
+        # keyframes look into the room: yaw towards the room centre +- 60 degrees
+        yaw = math.atan2(Y / 2 - c[1], X / 2 - c[0]) + math.radians(rng.uniform(-60, 60))
         pitch = math.radians(rng.uniform(-30, 30))
         roll = math.radians(rng.uniform(-10, 10))
         lv = levels if level_choices is None else int(rng.choice(level_choices))

@@ -1,0 +1,62 @@
+"""One mapping iteration of the pyramid rasterizer (paper Sec. III-C/D) with every
+buffer allocated up front, so that it can be replayed eagerly or as a HIP graph.
+
+run(): projection -> binning -> compositing -> per-level loss -> backward, all items
+       of the frame, through the C ABI on the current torch stream.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+from . import raster
+
+
+class MappingStep:
+    def __init__(self, cfg, frame: raster.Frame, g: dict, targets: dict, n_classes: int, w=(1.0, 1.0, 1.0),
+                 capacity_margin=1.15):
+        self.cfg, self.frame, self.g, self.targets = cfg, frame, g, targets
+        self.n_classes = n_classes
+        self.w = tuple(float(x) for x in w)
+        dev = frame.device
+        n = int(g["mean"].shape[0])
+        self.n = n
+        self.proj = raster.preprocess(cfg, g, frame)
+        probe = raster.bin_sort(cfg, self.proj, frame, n)
+        self.n_dup_probe = int(probe.n_dup.item())
+        del probe
+        self.sorter = raster.Sorter(cfg, frame, n, capacity=int(self.n_dup_probe * capacity_margin) + 4096)
+        self.img = raster.alloc_images(cfg, frame)
+        self.grad = dict(color=torch.empty_like(self.img["color"]), logits=None)
+        self.loss = torch.empty(3 * frame.n_items, dtype=torch.float32, device=dev)
+        self.loss_ws = torch.empty(raster.workspace_bytes(L.GS_WS_LOSS, cfg, frame, n), dtype=torch.uint8,
+                                   device=dev)
+        self.grads = raster.alloc_grads(cfg, g, frame)
+        self.bwd_ws = torch.empty(raster.workspace_bytes(L.GS_WS_RENDER_BWD, cfg, frame, n), dtype=torch.uint8,
+                                  device=dev)
+
+    def run(self, ev=None):
+        """Enqueue one step. ev: optional list of 5 torch events recorded between the calls."""
+        cfg, fr, g = self.cfg, self.frame, self.g
+        raster.preprocess_into(cfg, g, fr, self.proj)
+        if ev:
+            ev[0].record()
+        self.sorter.run(self.proj)
+        if ev:
+            ev[1].record()
+        raster.render_fwd(cfg, g, self.proj, fr, self.sorter, out=self.img)
+        if ev:
+            ev[2].record()
+        raster.loss(cfg, fr, self.n_classes, self.img, self.targets, w=self.w, grad=self.grad, loss_out=self.loss,
+                    ws=self.loss_ws)
+        if ev:
+            ev[3].record()
+        raster.render_bwd(cfg, g, self.proj, fr, self.sorter, self.img, self.grad, grads=self.grads, ws=self.bwd_ws)
+        if ev:
+            ev[4].record()
+
+    def capture(self) -> raster.Graph:
+        return raster.Graph(self.run, self.frame.device)
+
+    def overflowed(self) -> bool:
+        return int(self.sorter.status.item()) != L.GS_OK

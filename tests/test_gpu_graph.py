@@ -1,0 +1,74 @@
+"""The whole mapping step captured as one HIP graph replays to the eager result.
+
+Each replay is preceded by eager work on the same buffers (they are overwritten
+with NaN) and followed by a check against the eager step: forward images, binning
+and n_contrib bit-exact (no atomics there), gradients to 1e-5 relative (float
+atomics may add in another order)."""
+import numpy as np
+import pytest
+
+from paper_2412_01217_amd import scenes
+from tests.helpers import rel_check, targets_from_random
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _step(variant=0):
+    from paper_2412_01217_amd import raster
+    from paper_2412_01217_amd.step import MappingStep
+    sc = scenes.room_scene(n=8000, n_classes=10, seed=1200, log_mu=-3.6)
+    views = scenes.room_views(sc, 2, 160, 96, levels=2, seed=2200)
+    cfg = raster.config(10, variant=variant)
+    fr = raster.Frame(cfg, views)
+    g = raster.to_device(sc)
+    t_rgb, t_depth, t_lab = targets_from_random(views, 10, seed=4002)
+    T = dict(rgb=torch.from_numpy(t_rgb).cuda(), depth=torch.from_numpy(t_depth).cuda(),
+             label=torch.from_numpy(t_lab).cuda())
+    return MappingStep(cfg, fr, g, T, 10)
+
+
+def _snapshot(st):
+    D = int(st.sorter.n_dup.item())      # entries past the live count are not part of the result
+    out = {"color": st.img["color"].clone(), "T": st.img["T"].clone(), "nc": st.img["n_contrib"].clone(),
+           "vals": st.sorter.vals[:D].clone(), "ranges": st.sorter.ranges.clone(), "loss": st.loss.clone()}
+    for k, v in st.grads.items():
+        if v is not None:
+            out["g_" + k] = v.clone()
+    return out
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_graph_replays_match_eager(variant):
+    st = _step(variant)
+    st.run()
+    torch.cuda.synchronize()
+    assert not st.overflowed()
+    ref = _snapshot(st)
+    graph = st.capture()
+    for rep in range(3):
+        for t in (st.img["color"], st.img["T"], st.grad["color"], *[v for v in st.grads.values() if v is not None]):
+            t.fill_(float("nan"))
+        st.sorter.vals.fill_(-1)
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        got = _snapshot(st)
+        for k in ("color", "T", "nc", "vals", "ranges"):
+            assert torch.equal(got[k], ref[k]), (rep, k)
+        rel_check(got["loss"].cpu().numpy(), ref["loss"].cpu().numpy(), 1e-5, name=f"loss rep {rep}")
+        for k in ref:
+            if k.startswith("g_"):
+                rel_check(got[k].cpu().numpy(), ref[k].cpu().numpy(), 1e-5, name=f"{k} rep {rep}")
+
+
+def test_eager_steps_are_deterministic_where_no_atomics():
+    st = _step()
+    st.run()
+    torch.cuda.synchronize()
+    a = _snapshot(st)
+    st.run()
+    torch.cuda.synchronize()
+    b = _snapshot(st)
+    for k in ("color", "T", "nc", "vals", "ranges"):
+        assert torch.equal(a[k], b[k]), k

@@ -87,7 +87,7 @@ def test_entry_points_reject_bad_arguments_on_host():
     assert lib.gs_preprocess(ctypes.byref(c), ctypes.byref(g), None, 0, None, 0, ctypes.byref(p), None) == \
         L.GS_ERR_INVALID_ARG
     lib.gs_config_default(ctypes.byref(c))
-    c.n_sem = 65
+    c.n_sem = 61
     b = ctypes.c_size_t()
     assert lib.gs_workspace_size(L.GS_WS_BIN_SORT, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == \
         L.GS_ERR_INVALID_ARG
