@@ -108,6 +108,7 @@ typedef struct gs_images {
   float* T;              /* [P] final transmittance (forward only) */
   uint32_t* n_contrib;   /* [P] 1 + list position of the last blended Gaussian, 0 if none */
   float* logits;         /* [P * n_classes] learned mode decoded logits, else NULL */
+  int64_t n_pixels;      /* P, the total pixel count of all items (read in learned mode) */
 } gs_images;
 
 /* Targets of the loss (the image pyramid of eq. 4-6). */
@@ -139,6 +140,10 @@ typedef struct gs_grads {
   float* sem;        /* [n][n_sem] plain mode */
   float* emb;        /* [n][16] learned mode, float32 */
   float* pose;       /* [n_views][6]: (rho, phi) of T_cw <- Exp(xi) T_cw at xi = 0 */
+  float* head_W1;    /* learned mode: [64][16] */
+  float* head_b1;    /* [64] */
+  float* head_W2;    /* [n_classes][64] */
+  float* head_b2;    /* [n_classes] */
 } gs_grads;
 
 enum gs_workspace_kind { GS_WS_BIN_SORT = 1, GS_WS_RENDER_BWD = 2, GS_WS_LOSS = 3 };
@@ -189,8 +194,11 @@ int gs_bin_sort(const gs_config* cfg, const gs_projected* proj, const gs_item* i
 /* Front-to-back compositing (eq. 7-9) of every pixel of every item: over its tile's
  * list, alpha = min(alpha_max, o exp(-d^T conic d / 2)), skipped below alpha_min;
  * the pixel stops before the Gaussian that would take T below t_min; the colour,
- * depth and semantic channels accumulate f alpha T. head != NULL (learned mode)
- * additionally decodes out->logits from the composited embedding. */
+ * depth and semantic channels accumulate f alpha T. Learned mode (g->emb != NULL,
+ * n_sem = 16, head != NULL): the semantic channels composite the bfloat16 embedding
+ * in single precision, and out->logits [P * head->n_classes] receives the head's
+ * decode W2 relu(W1 E + b1) + b2 of every pixel's embedding E (matrix cores,
+ * bfloat16 weights, single-precision accumulation). */
 int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_item* items_dev,
                   int32_t n_items, int32_t n_tiles, const uint32_t* vals, const uint32_t* ranges,
                   const gs_head* head, gs_images* out, void* stream);
@@ -206,7 +214,11 @@ int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_it
 
 /* Back-propagation (Sec. III-D) of an upstream gradient grad_in->color (and ->logits)
  * through compositing and projection to every Gaussian parameter and every view's
- * pose tangent. fwd must hold T and n_contrib of the matching gs_render_fwd. */
+ * pose tangent. fwd must hold T and n_contrib of the matching gs_render_fwd.
+ * Learned mode (head != NULL): the head is differentiated first; its gradient with
+ * respect to the embedding image overwrites channels 4..19 of grad_in->color (the
+ * caller's buffer), grads->emb receives the per-Gaussian embedding gradient and
+ * grads->head_* the weight gradients. workspace: gs_workspace_size(GS_WS_RENDER_BWD). */
 int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_view* views_dev,
                   int32_t n_views, const gs_item* items_dev, int32_t n_items, int32_t n_tiles,
                   const uint32_t* vals, const uint32_t* ranges, const gs_head* head, const gs_images* fwd,
@@ -218,6 +230,28 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
  * every item, the argmax over channels 4..K-1 (ties to the lowest index). */
 int gs_pyramid_downsample(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t max_level,
                           int32_t K, float* img, int32_t* labels, void* stream);
+
+/* ---- training helpers for the learned head ------------------------------- */
+
+/* One Adam step on n float32 parameters in place (m, v: moment buffers, step >= 1,
+ * bias-corrected). bf16_copy (may be NULL) receives the updated values rounded to
+ * bfloat16 (nearest, ties to even). */
+int gs_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                 float eps, int32_t step, uint16_t* bf16_copy, void* stream);
+
+/* Distillation of decoded logits `student` onto the plain render's logits `teacher`
+ * (both [P * C] planar per item): per item, the mean over pixels of the soft-target
+ * cross-entropy -sum_c softmax(teacher)_c log softmax(student)_c plus mse_w times the
+ * mean over pixels and classes of (student - teacher)^2; *loss_dev = sum over items.
+ * grad receives d loss / d student. workspace: 256 bytes. */
+int gs_distill_loss(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t C, const float* teacher,
+                    const float* student, float mse_w, float* loss_dev, float* grad, void* workspace, size_t ws_bytes,
+                    void* stream);
+
+/* counts_dev[i] (uint64) = number of pixels of item i whose argmax over the C planar
+ * channels of a and b agree (ties to the lowest channel). */
+int gs_argmax_agreement(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t C, const float* a,
+                        const float* b, uint64_t* counts_dev, void* stream);
 
 /* ---- graph capture of a whole step (Sec. III-C/D: one mapping iteration) ----
  * Every hot-path call above only enqueues kernels and never synchronises, so a full

@@ -38,6 +38,9 @@ def _load():
             build(force=True)
         _lib = ctypes.CDLL(_LIB)
         _lib.or_sort_stage.restype = ctypes.c_int64
+        _lib.or_distill.restype = ctypes.c_double
+        _lib.or_distill.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
     return _lib
 
 
@@ -143,10 +146,11 @@ def render(cfg: Config, scene, views, sem=None, brute=False, tile_mask=None):
     Tout = np.zeros(P)
     nc = np.zeros(P, np.int32)
     fl = np.zeros(P, np.int32)
+    nb = np.zeros(P, np.int32)
     mask = None if tile_mask is None else np.ascontiguousarray(tile_mask, dtype=np.uint8)
     lib.or_render(_p(cd), _p(ci), ctypes.c_int64(n), *[_p(a) for a in g], ctypes.c_int(len(views)), _p(vd),
-                  _p(vi), ctypes.c_int(int(brute)), _p(mask), _p(img), _p(Tout), _p(nc), _p(fl))
-    return dict(img=img, T=Tout, n_contrib=nc, flag=fl, K=K)
+                  _p(vi), ctypes.c_int(int(brute)), _p(mask), _p(img), _p(Tout), _p(nc), _p(fl), _p(nb))
+    return dict(img=img, T=Tout, n_contrib=nc, flag=fl, n_blend=nb, K=K)
 
 
 def backward(cfg: Config, scene, views, gimg, sem=None, tile_mask=None):
@@ -218,6 +222,18 @@ def sort_stage(views, n, m2hi, m2lo, radius, depth, tile_w=16, tile_h=16, cap=No
     if D < 0:
         raise ValueError("capacity too small")
     return keys[:D], vals[:D], ranges.reshape(tiles, 2)
+
+
+def distill(views, C, teacher, student, mse_w=0.1, tile_w=16, tile_h=16):
+    """Distillation loss of student logits onto teacher logits ([P*C] planar per item)
+    and its gradient with respect to the student."""
+    lib = _load()
+    _, P, _ = layout(views, tile_w, tile_h)
+    _, ci = Config(tile_w=tile_w, tile_h=tile_h).arrays(0)
+    vi = _views(views)[1]
+    grad = np.zeros(P * C)
+    loss = lib.or_distill(_p(ci), len(views), _p(vi), C, _p(_d(teacher)), _p(_d(student)), float(mse_w), _p(grad))
+    return float(loss), grad
 
 
 def head_forward(E, W1, b1, W2, b2):

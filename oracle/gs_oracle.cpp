@@ -548,19 +548,22 @@ int or_preprocess(const double* cd, const int* ci, int64_t n, const double* mean
 // lists. tile_mask (may be null) restricts the work to the tiles whose byte is set.
 int or_render(const double* cd, const int* ci, int64_t n, const double* mean, const double* lsc, const double* quat,
               const double* opac, const double* rgb, const double* sem, int n_views, const double* vd, const int* vi,
-              int brute, const uint8_t* tile_mask, double* img, double* Tout, int* ncontrib, int* pflag) {
+              int brute, const uint8_t* tile_mask, double* img, double* Tout, int* ncontrib, int* pflag,
+              int* nblend) {
   Scene s;
   setup(s, cd, ci, n, mean, lsc, quat, opac, rgb, sem, n_views, vd, vi);
   build(s, brute != 0);
   int K = s.K();
   for_each_pixel(s, brute != 0, tile_mask,
-                 [&](int k, int u, int v, const std::vector<Contrib>&, int flag, const double* out, double T, int nc) {
+                 [&](int k, int u, int v, const std::vector<Contrib>& cb, int flag, const double* out, double T,
+                     int nc) {
                    const Item& it = s.items[k];
                    int64_t HW = int64_t(it.W) * it.H, pix = int64_t(v) * it.W + u;
                    for (int ch = 0; ch < K; ++ch) img[it.pix0 * K + ch * HW + pix] = out[ch];
                    Tout[it.pix0 + pix] = T;
                    ncontrib[it.pix0 + pix] = nc;
                    pflag[it.pix0 + pix] = flag;
+                   if (nblend) nblend[it.pix0 + pix] = int(cb.size());
                  });
   return 0;
 }
@@ -829,6 +832,50 @@ int or_head_backward(int64_t P, int D, int Hd, int C, const double* E, const dou
     }
   }
   return 0;
+}
+
+// Distillation objective for fitting the learned head to the plain render (a reading;
+// the paper has no learned head): per pixel, the soft-target cross-entropy
+// -sum_c softmax(t)_c log softmax(s)_c plus mse_w * mean_c (s_c - t_c)^2, averaged over
+// each item's pixels and summed over items. t, s: [P*C] planar per item. grad = dL/ds.
+double or_distill(const int* ci, int n_views, const int* vi, int C, const double* t, const double* s, double mse_w,
+                  double* grad) {
+  double cd[8] = {0};
+  Cfg c = read_cfg(cd, ci);
+  std::vector<double> vd(16 * size_t(n_views), 1.0);
+  auto items = make_items(c, n_views, vd.data(), vi);
+  double total = 0;
+  std::vector<double> pt(C), ps(C);
+  for (const Item& it : items) {
+    int64_t HW = int64_t(it.W) * it.H;
+    for (int64_t p = 0; p < HW; ++p) {
+      const double* T = t + it.pix0 * C + p;
+      const double* S = s + it.pix0 * C + p;
+      double mt = -INFINITY, ms = -INFINITY;
+      for (int k = 0; k < C; ++k) {
+        mt = std::max(mt, T[k * HW]);
+        ms = std::max(ms, S[k * HW]);
+      }
+      double zt = 0, zs = 0;
+      for (int k = 0; k < C; ++k) {
+        zt += std::exp(T[k * HW] - mt);
+        zs += std::exp(S[k * HW] - ms);
+      }
+      double lzt = mt + std::log(zt), lzs = ms + std::log(zs);
+      for (int k = 0; k < C; ++k) {
+        pt[k] = std::exp(T[k * HW] - lzt);
+        ps[k] = std::exp(S[k * HW] - lzs);
+      }
+      double l = 0;
+      for (int k = 0; k < C; ++k) {
+        double d = S[k * HW] - T[k * HW];
+        l += -pt[k] * (S[k * HW] - lzs) + mse_w * d * d / C;
+        grad[it.pix0 * C + p + k * HW] = (ps[k] - pt[k] + 2.0 * mse_w * d / C) / double(HW);
+      }
+      total += l / double(HW);
+    }
+  }
+  return total;
 }
 
 }  // extern "C"

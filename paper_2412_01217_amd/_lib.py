@@ -28,7 +28,7 @@ EXPORTS = (
     "gs_config_default", "gs_status_string", "gs_last_hip_error", "gs_version", "gs_make_items",
     "gs_workspace_size", "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_pyramid_loss",
     "gs_render_bwd", "gs_pyramid_downsample", "gs_graph_begin", "gs_graph_end", "gs_graph_launch",
-    "gs_graph_destroy",
+    "gs_graph_destroy", "gs_adam_step", "gs_distill_loss", "gs_argmax_agreement",
 )
 
 
@@ -58,7 +58,8 @@ class Projected(ctypes.Structure):
 
 
 class Images(ctypes.Structure):
-    _fields_ = [("color", c_void_p), ("T", c_void_p), ("n_contrib", c_void_p), ("logits", c_void_p)]
+    _fields_ = [("color", c_void_p), ("T", c_void_p), ("n_contrib", c_void_p), ("logits", c_void_p),
+                ("n_pixels", c_int64)]
 
 
 class Targets(ctypes.Structure):
@@ -72,7 +73,8 @@ class Head(ctypes.Structure):
 
 class Grads(ctypes.Structure):
     _fields_ = [("mean", c_void_p), ("log_scale", c_void_p), ("quat", c_void_p), ("opacity", c_void_p),
-                ("rgb", c_void_p), ("sem", c_void_p), ("emb", c_void_p), ("pose", c_void_p)]
+                ("rgb", c_void_p), ("sem", c_void_p), ("emb", c_void_p), ("pose", c_void_p),
+                ("head_W1", c_void_p), ("head_b1", c_void_p), ("head_W2", c_void_p), ("head_b2", c_void_p)]
 
 
 _lib = None
@@ -107,6 +109,13 @@ def lib():
                                     c_size_t, c_void_p]
         L.gs_pyramid_downsample.argtypes = [c_void_p, c_int32, c_int64, c_int32, c_int32, c_void_p, c_void_p,
                                             c_void_p]
+        L.gs_adam_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_float, c_float, c_float, c_float,
+                                   c_int32, c_void_p, c_void_p]
+        L.gs_distill_loss.argtypes = [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_void_p, c_float, c_void_p,
+                                      c_void_p, c_void_p, c_size_t, c_void_p]
+        L.gs_argmax_agreement.argtypes = [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
+        for name in ("gs_adam_step", "gs_distill_loss", "gs_argmax_agreement"):
+            getattr(L, name).restype = c_int32
         L.gs_graph_begin.argtypes = [c_void_p]
         L.gs_graph_end.argtypes = [c_void_p, P(c_void_p)]
         L.gs_graph_launch.argtypes = [c_void_p, c_void_p]

@@ -55,6 +55,15 @@ int launch_loss(const gs_item*, int, int64_t, int, int, const float*, const floa
                 float*, float*, float*, float*, hipStream_t);
 int launch_downsample(const gs_item*, int, int64_t, int, int, float*, int32_t*, hipStream_t);
 size_t loss_workspace(int n_items);
+size_t head_bwd_workspace();
+int head_shape_ok(const gs_head&);
+int launch_head_fwd(const gs_item*, int, int64_t, int, const gs_head&, const float*, float*, hipStream_t);
+int launch_head_bwd(const gs_item*, int, int64_t, int, const gs_head&, const float*, const float*, float*, float*,
+                    float*, float*, float*, float*, hipStream_t);
+int launch_adam(float*, const float*, float*, float*, int64_t, float, float, float, float, int, uint16_t*, hipStream_t);
+int launch_distill(const gs_item*, int, int64_t, int, const float*, const float*, float, float*, float*, float*,
+                   hipStream_t);
+int launch_agree(const gs_item*, int, int64_t, int, const float*, const float*, unsigned long long*, hipStream_t);
 int launch_fill_f32(float*, int64_t, float, hipStream_t);
 
 namespace {
@@ -165,7 +174,7 @@ int gs_workspace_size(int kind, const gs_config* cfg, int32_t n_items, int64_t n
       *bytes = bin_sort_workspace((int64_t)n_items * n_gauss, dup_capacity);
       return GS_OK;
     case GS_WS_RENDER_BWD:
-      *bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)n_gauss);
+      *bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)n_gauss) + align_up(head_bwd_workspace());
       return GS_OK;
     case GS_WS_LOSS:
       *bytes = align_up(loss_workspace(n_items));
@@ -202,11 +211,17 @@ int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
                   int32_t n_items, int32_t n_tiles, const uint32_t* vals, const uint32_t* ranges,
                   const gs_head* head, gs_images* out, void* stream) {
   if (!cfg_ok(cfg) || !gauss_ok(g, true) || !proj || !out || n_items < 0 || n_tiles < 0) return GS_ERR_INVALID_ARG;
-  if (head) return GS_ERR_UNSUPPORTED;
-  if (cfg->n_sem > 0 && g->n > 0 && !g->sem) return GS_ERR_INVALID_ARG;
+  const bool learned = g->emb != nullptr;
+  if (learned && (cfg->n_sem != 16 || !head || !head_shape_ok(*head) || !out->logits || out->n_pixels < 0))
+    return GS_ERR_INVALID_ARG;
+  if (!learned && head) return GS_ERR_INVALID_ARG;
+  if (!learned && cfg->n_sem > 0 && g->n > 0 && !g->sem) return GS_ERR_INVALID_ARG;
   if (n_tiles == 0) return GS_OK;
   if (!items_dev || !vals || !ranges || !out->color || !out->T || !out->n_contrib) return GS_ERR_INVALID_ARG;
-  return launch_render_fwd(*cfg, *g, *proj, items_dev, n_items, n_tiles, vals, ranges, *out, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  int st = launch_render_fwd(*cfg, *g, *proj, items_dev, n_items, n_tiles, vals, ranges, *out, s);
+  if (st || !learned) return st;
+  return launch_head_fwd(items_dev, n_items, out->n_pixels, 4 + cfg->n_sem, *head, out->color, out->logits, s);
 }
 
 int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_items, int64_t n_pixels,
@@ -235,27 +250,65 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   if (!cfg_ok(cfg) || !gauss_ok(g, true) || !proj || !fwd || !grad_in || !grads || n_views < 0 || n_items < 0 ||
       n_tiles < 0)
     return GS_ERR_INVALID_ARG;
-  if (head) return GS_ERR_UNSUPPORTED;
-  if (cfg->n_sem > 0 && g->n > 0 && (!g->sem || !grads->sem)) return GS_ERR_INVALID_ARG;
+  const bool learned = g->emb != nullptr;
+  if (learned && (cfg->n_sem != 16 || !head || !head_shape_ok(*head) || !grads->emb || !grads->head_W1 ||
+                  !grads->head_b1 || !grads->head_W2 || !grads->head_b2 || !fwd->color || !grad_in->logits ||
+                  fwd->n_pixels < 0))
+    return GS_ERR_INVALID_ARG;
+  if (!learned && head) return GS_ERR_INVALID_ARG;
+  if (!learned && cfg->n_sem > 0 && g->n > 0 && (!g->sem || !grads->sem)) return GS_ERR_INVALID_ARG;
   if (!grads->mean || !grads->log_scale || !grads->quat || !grads->opacity || !grads->rgb || !grads->pose)
     return GS_ERR_INVALID_ARG;
-  const size_t need = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)g->n);
-  if (!workspace || ws_bytes < need) return GS_ERR_WORKSPACE;
+  const size_t rec_bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)g->n);
+  if (!workspace || ws_bytes < rec_bytes + align_up(head_bwd_workspace())) return GS_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = g->n;
+  gs_grads gr = *grads;
+  if (learned) gr.sem = grads->emb;   // the semantic channels' gradient is the embedding's
   int st = launch_fill_f32((float*)workspace, kSortBwdRecord * (int64_t)n_items * n, 0.0f, s);
-  st = st ? st : launch_fill_f32(grads->rgb, 3 * n, 0.0f, s);
-  if (cfg->n_sem > 0) st = st ? st : launch_fill_f32(grads->sem, (int64_t)cfg->n_sem * n, 0.0f, s);
-  st = st ? st : launch_fill_f32(grads->pose, 6ll * n_views, 0.0f, s);
+  st = st ? st : launch_fill_f32(gr.rgb, 3 * n, 0.0f, s);
+  if (cfg->n_sem > 0) st = st ? st : launch_fill_f32(gr.sem, (int64_t)cfg->n_sem * n, 0.0f, s);
+  st = st ? st : launch_fill_f32(gr.pose, 6ll * n_views, 0.0f, s);
   if (st) return st;
+  if (learned) {
+    if (!items_dev) return GS_ERR_INVALID_ARG;
+    st = launch_head_bwd(items_dev, n_items, fwd->n_pixels, 4 + cfg->n_sem, *head, fwd->color, grad_in->logits,
+                         grad_in->color, (float*)((char*)workspace + rec_bytes), gr.head_W1, gr.head_b1, gr.head_W2,
+                         gr.head_b2, s);
+    if (st) return st;
+  }
   if (n == 0) return GS_OK;
   if (n_tiles > 0) {
     if (!items_dev || !vals || !ranges || !fwd->T || !fwd->n_contrib || !grad_in->color) return GS_ERR_INVALID_ARG;
     st = launch_render_bwd(*cfg, *g, *proj, items_dev, n_items, n_tiles, vals, ranges, *fwd, *grad_in, (float*)workspace,
-                           *grads, s);
+                           gr, s);
     if (st) return st;
   }
-  return launch_preprocess_bwd(*cfg, *g, views_dev, n_views, items_dev, (const float*)workspace, proj->radius, *grads, s);
+  return launch_preprocess_bwd(*cfg, *g, views_dev, n_views, items_dev, (const float*)workspace, proj->radius, gr, s);
+}
+
+int gs_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                 float eps, int32_t step, uint16_t* bf16_copy, void* stream) {
+  if (n < 0 || step < 1 || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return GS_ERR_INVALID_ARG;
+  if (n > 0 && (!param || !grad || !m || !v)) return GS_ERR_INVALID_ARG;
+  return launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, bf16_copy, (hipStream_t)stream);
+}
+
+int gs_distill_loss(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t C, const float* teacher,
+                    const float* student, float mse_w, float* loss_dev, float* grad, void* workspace, size_t ws_bytes,
+                    void* stream) {
+  if (n_items <= 0 || n_pixels < 0 || C < 1 || !items_dev || !teacher || !student || !loss_dev || !grad)
+    return GS_ERR_INVALID_ARG;
+  if (!workspace || ws_bytes < 256) return GS_ERR_WORKSPACE;
+  return launch_distill(items_dev, n_items, n_pixels, C, teacher, student, mse_w, loss_dev, grad, (float*)workspace,
+                        (hipStream_t)stream);
+}
+
+int gs_argmax_agreement(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t C, const float* a,
+                        const float* b, uint64_t* counts_dev, void* stream) {
+  if (n_items <= 0 || n_pixels < 0 || C < 1 || !items_dev || !a || !b || !counts_dev) return GS_ERR_INVALID_ARG;
+  return launch_agree(items_dev, n_items, n_pixels, C, a, b, (unsigned long long*)counts_dev, (hipStream_t)stream);
 }
 
 int gs_graph_begin(void* stream) {

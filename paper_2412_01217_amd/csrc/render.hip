@@ -55,7 +55,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const gs_item* items, int n_items, c
 template <int NS>
 __device__ __forceinline__ void stage(float* sm, uint32_t g, int item, int64_t n, const float* __restrict__ rec,
                                       const float* __restrict__ depth, const float* __restrict__ rgb,
-                                      const float* __restrict__ sem, int n_sem) {
+                                      const float* __restrict__ sem, const uint16_t* __restrict__ emb, int n_sem) {
   const int64_t e = (int64_t)item * n + g;
   const float4* r = reinterpret_cast<const float4*>(rec + kRecFloats * e);
   float4* d = reinterpret_cast<float4*>(sm);
@@ -63,13 +63,15 @@ __device__ __forceinline__ void stage(float* sm, uint32_t g, int item, int64_t n
   d[1] = r[1];
   d[2] = make_float4(rgb[3 * (int64_t)g], rgb[3 * (int64_t)g + 1], rgb[3 * (int64_t)g + 2], depth[e]);
   const float* s = sem + (int64_t)n_sem * g;
+  const uint16_t* es = emb + (int64_t)n_sem * g;
 #pragma unroll
-  for (int c = 0; c < NS; ++c) sm[12 + c] = c < n_sem ? s[c] : 0.0f;
+  for (int c = 0; c < NS; ++c)
+    sm[12 + c] = c >= n_sem ? 0.0f : (emb ? __uint_as_float((uint32_t)es[c] << 16) : s[c]);
 }
 
 template <int NS>
 __global__ __launch_bounds__(256) void k_render_fwd(gs_config cfg, const float* __restrict__ rgb, const float* __restrict__ sem,
-                                                    int n_sem, const float* __restrict__ rec,
+                                                    const uint16_t* __restrict__ emb, int n_sem, const float* __restrict__ rec,
                                                     const float* __restrict__ depth, int64_t n,
                                                     const gs_item* __restrict__ items, int n_items,
                                                     const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges,
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(gs_config cfg, const float* 
   for (uint32_t b = c.start; b < c.end; b += BATCH) {
     if (__syncthreads_count(!done) == 0) break;
     const int cnt = (int)min((uint32_t)BATCH, c.end - b);
-    for (int q = threadIdx.x; q < cnt; q += 256) stage<NS>(sm + q * STRIDE, vals[b + q], c.item, n, rec, depth, rgb, sem, n_sem);
+    for (int q = threadIdx.x; q < cnt; q += 256) stage<NS>(sm + q * STRIDE, vals[b + q], c.item, n, rec, depth, rgb, sem, emb, n_sem);
     __syncthreads();
     if (!done) {
       for (int q = 0; q < cnt; ++q) {
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(gs_config cfg, const float* 
 
 template <int NS>
 __global__ __launch_bounds__(256) void k_render_bwd(gs_config cfg, const float* __restrict__ rgb, const float* __restrict__ sem,
-                                                    int n_sem, const float* __restrict__ rec,
+                                                    const uint16_t* __restrict__ emb, int n_sem, const float* __restrict__ rec,
                                                     const float* __restrict__ depth, int64_t n,
                                                     const gs_item* __restrict__ items, int n_items,
                                                     const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges,
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(gs_config cfg, const float* 
     const int cnt = hi - lo;
     __syncthreads();
     for (int q = threadIdx.x; q < cnt; q += 256)
-      stage<NS>(sm + q * STRIDE, vals[c.start + lo + q], c.item, n, rec, depth, rgb, sem, n_sem);
+      stage<NS>(sm + q * STRIDE, vals[c.start + lo + q], c.item, n, rec, depth, rgb, sem, emb, n_sem);
     for (int q = threadIdx.x; q < cnt * NVP; q += 256) red[q] = 0.0f;
     __syncthreads();
     for (int q = cnt - 1; q >= 0; --q) {
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(gs_config cfg, const float* 
 template <int NS>
 int launch_fwd_t(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items, int n_items,
                  int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& out, hipStream_t s) {
-  hipLaunchKernelGGL(k_render_fwd<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, cfg.n_sem, p.rec, p.depth,
+  hipLaunchKernelGGL(k_render_fwd<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb, cfg.n_sem, p.rec, p.depth,
                      g.n, items, n_items, vals, ranges, out.color, out.T, out.n_contrib);
   return launch_status();
 }
@@ -245,7 +247,7 @@ template <int NS>
 int launch_bwd_t(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items, int n_items,
                  int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& fwd,
                  const gs_images& gin, float* g2d, const gs_grads& gr, hipStream_t s) {
-  hipLaunchKernelGGL(k_render_bwd<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, cfg.n_sem, p.rec, p.depth,
+  hipLaunchKernelGGL(k_render_bwd<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb, cfg.n_sem, p.rec, p.depth,
                      g.n, items, n_items, vals, ranges, fwd.T, fwd.n_contrib, gin.color, g2d, gr.rgb, gr.sem);
   return launch_status();
 }

@@ -100,7 +100,8 @@ struct Stage {
 
   __device__ __forceinline__ void fetch(const uint32_t* __restrict__ vals, uint32_t b, int cnt, int item, int64_t n,
                                         const float* __restrict__ rec, const float* __restrict__ depth,
-                                        const float* __restrict__ rgb, const float* __restrict__ sem, int n_sem) {
+                                        const float* __restrict__ rgb, const float* __restrict__ sem,
+                                        const uint16_t* __restrict__ emb, int n_sem) {
     const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
     const bool live = q < cnt;
     const uint32_t g = live ? vals[b + q] : 0u;
@@ -115,6 +116,7 @@ struct Stage {
       if (live && k < Kr) {
         if (k < 3) v = rgb[3 * (int64_t)g + k];
         else if (k == 3) v = depth[e];
+        else if (emb) v = __uint_as_float((uint32_t)emb[(int64_t)n_sem * g + (k - 4)] << 16);
         else v = sem[(int64_t)n_sem * g + (k - 4)];
       }
       f[j] = v;
@@ -131,7 +133,8 @@ struct Stage {
 
 template <int NS>
 __global__ __launch_bounds__(256) void k_render_fwd_mfma(gs_config cfg, const float* __restrict__ rgb,
-                                                         const float* __restrict__ sem, int n_sem,
+                                                         const float* __restrict__ sem,
+                                                         const uint16_t* __restrict__ emb, int n_sem,
                                                          const float* __restrict__ rec, const float* __restrict__ depth,
                                                          int64_t n, const gs_item* __restrict__ items, int n_items,
                                                          const uint32_t* __restrict__ vals,
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(256) void k_render_fwd_mfma(gs_config cfg, const fl
   const float amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
   float* W = s_w[wave];
   Stage<NS> st;
-  if (c.start < c.end) st.fetch(vals, c.start, (int)min((uint32_t)kBatch, c.end - c.start), c.item, n, rec, depth, rgb, sem, n_sem);
+  if (c.start < c.end) st.fetch(vals, c.start, (int)min((uint32_t)kBatch, c.end - c.start), c.item, n, rec, depth, rgb, sem, emb, n_sem);
   for (uint32_t b = c.start; b < c.end; b += kBatch) {
     // every wave is past the previous batch's LDS reads; stop once every pixel has
     if (__syncthreads_count(!done) == 0) break;
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(256) void k_render_fwd_mfma(gs_config cfg, const fl
     __syncthreads();
     const int cnt = (int)min((uint32_t)kBatch, c.end - b);
     if (b + kBatch < c.end)
-      st.fetch(vals, b + kBatch, (int)min((uint32_t)kBatch, c.end - b - kBatch), c.item, n, rec, depth, rgb, sem, n_sem);
+      st.fetch(vals, b + kBatch, (int)min((uint32_t)kBatch, c.end - b - kBatch), c.item, n, rec, depth, rgb, sem, emb, n_sem);
     // front-to-back recurrence, branch-free: the alpha of successive Gaussians is
     // independent, only T carries from one to the next
     uint32_t nz = 0;  // bit q: some lane of this wave blends Gaussian q
@@ -234,7 +237,8 @@ __global__ __launch_bounds__(256) void k_render_fwd_mfma(gs_config cfg, const fl
 
 template <int NS>
 __global__ __launch_bounds__(256) void k_render_bwd_mfma(gs_config cfg, const float* __restrict__ rgb,
-                                                         const float* __restrict__ sem, int n_sem,
+                                                         const float* __restrict__ sem,
+                                                         const uint16_t* __restrict__ emb, int n_sem,
                                                          const float* __restrict__ rec, const float* __restrict__ depth,
                                                          int64_t n, const gs_item* __restrict__ items, int n_items,
                                                          const uint32_t* __restrict__ vals,
@@ -292,7 +296,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_mfma(gs_config cfg, const fl
   Stage<NS> st;
   if (lmax > 0) {
     const int lo0 = max(0, (int)lmax - kBatch);
-    st.fetch(vals, c.start + lo0, (int)lmax - lo0, c.item, n, rec, depth, rgb, sem, n_sem);
+    st.fetch(vals, c.start + lo0, (int)lmax - lo0, c.item, n, rec, depth, rgb, sem, emb, n_sem);
   }
   for (int hi = (int)lmax; hi > 0; hi -= kBatch) {
     const int lo = max(0, hi - kBatch);
@@ -304,7 +308,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_mfma(gs_config cfg, const fl
     __syncthreads();
     if (lo > 0) {
       const int lo2 = max(0, lo - kBatch);
-      st.fetch(vals, c.start + lo2, lo - lo2, c.item, n, rec, depth, rgb, sem, n_sem);
+      st.fetch(vals, c.start + lo2, lo - lo2, c.item, n, rec, depth, rgb, sem, emb, n_sem);
     }
     bool wave_any = false;
 #pragma unroll 2
@@ -394,7 +398,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_mfma(gs_config cfg, const fl
 template <int NS>
 int launch_fwd_m(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items, int n_items,
                  int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& out, hipStream_t s) {
-  hipLaunchKernelGGL(k_render_fwd_mfma<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, cfg.n_sem, p.rec,
+  hipLaunchKernelGGL(k_render_fwd_mfma<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb, cfg.n_sem, p.rec,
                      p.depth, g.n, items, n_items, vals, ranges, out.color, out.T, out.n_contrib);
   return launch_status();
 }
@@ -403,7 +407,7 @@ template <int NS>
 int launch_bwd_m(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items, int n_items,
                  int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& fwd,
                  const gs_images& gin, float* g2d, const gs_grads& gr, hipStream_t s) {
-  hipLaunchKernelGGL(k_render_bwd_mfma<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, cfg.n_sem, p.rec,
+  hipLaunchKernelGGL(k_render_bwd_mfma<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb, cfg.n_sem, p.rec,
                      p.depth, g.n, items, n_items, vals, ranges, fwd.T, fwd.n_contrib, gin.color, g2d, gr.rgb, gr.sem);
   return launch_status();
 }

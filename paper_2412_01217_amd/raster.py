@@ -169,70 +169,121 @@ def alloc_images(cfg, frame: Frame, n_classes=0, learned=False) -> dict:
     P = frame.n_pixels
     out = dict(color=torch.empty(P * K, dtype=torch.float32, device=dev),
                T=torch.empty(P, dtype=torch.float32, device=dev),
-               n_contrib=torch.empty(P, dtype=torch.int32, device=dev), K=K)
+               n_contrib=torch.empty(P, dtype=torch.int32, device=dev), K=K, n_pixels=P)
     out["logits"] = torch.empty(P * n_classes, dtype=torch.float32, device=dev) if learned else None
     return out
 
 
-def _images(d: dict) -> L.Images:
-    return L.Images(*(None if d.get(k) is None else d[k].data_ptr() for k in ("color", "T", "n_contrib", "logits")))
+def _images(d: dict, P: int = 0) -> L.Images:
+    im = L.Images(*(None if d.get(k) is None else d[k].data_ptr() for k in ("color", "T", "n_contrib", "logits")))
+    im.n_pixels = int(d.get("n_pixels", P))
+    return im
 
 
-def render_fwd(cfg, g: dict, proj: dict, frame: Frame, sorter: Sorter, out=None) -> dict:
-    out = out or alloc_images(cfg, frame)
+def head_struct(head: dict | None):
+    """head: W1 [64,16] and W2 [C,64] as int16 tensors of bfloat16 bits, b1 [64], b2 [C] float32."""
+    if head is None:
+        return None
+    h = L.Head()
+    h.d_in, h.d_hidden, h.n_classes = 16, 64, int(head["b2"].shape[0])
+    h.W1, h.b1, h.W2, h.b2 = (head[k].data_ptr() for k in ("W1", "b1", "W2", "b2"))
+    return h
+
+
+def render_fwd(cfg, g: dict, proj: dict, frame: Frame, sorter: Sorter, out=None, head=None) -> dict:
+    learned = g.get("emb") is not None
+    out = out or alloc_images(cfg, frame, int(head["b2"].shape[0]) if learned else 0, learned)
     gs = gaussians_struct(g)
     ps = _projected(proj)
-    im = _images(out)
+    im = _images(out, frame.n_pixels)
+    hs = head_struct(head)
     L.check(L.lib().gs_render_fwd(ctypes.byref(cfg), ctypes.byref(gs), ctypes.byref(ps), _ptr(frame.items_dev),
-                                  frame.n_items, frame.n_tiles, _ptr(sorter.vals), _ptr(sorter.ranges), None,
-                                  ctypes.byref(im), _stream(frame.device)), "gs_render_fwd")
+                                  frame.n_items, frame.n_tiles, _ptr(sorter.vals), _ptr(sorter.ranges),
+                                  ctypes.byref(hs) if hs is not None else None, ctypes.byref(im),
+                                  _stream(frame.device)), "gs_render_fwd")
     return out
 
 
 def loss(cfg, frame: Frame, n_classes: int, rendered: dict, targets: dict, w=(1.0, 1.0, 1.0), grad=None,
          loss_out=None, ws=None):
     dev = frame.device
-    grad = grad or dict(color=torch.empty_like(rendered["color"]), logits=None)
+    if grad is None:
+        grad = dict(color=torch.empty_like(rendered["color"]),
+                    logits=torch.empty_like(rendered["logits"]) if rendered.get("logits") is not None else None)
     loss_out = loss_out if loss_out is not None else torch.empty(3 * frame.n_items, dtype=torch.float32, device=dev)
     ws = ws if ws is not None else torch.empty(workspace_bytes(L.GS_WS_LOSS, cfg, frame, 0), dtype=torch.uint8,
                                                device=dev)
     t = L.Targets(targets["rgb"].data_ptr(), targets["depth"].data_ptr(),
                   None if targets.get("label") is None else targets["label"].data_ptr())
     wv = (ctypes.c_float * 3)(*[float(x) for x in w])
-    ri = _images(rendered)
-    gi = _images(grad)
+    ri = _images(rendered, frame.n_pixels)
+    gi = _images(grad, frame.n_pixels)
     L.check(L.lib().gs_pyramid_loss(ctypes.byref(cfg), _ptr(frame.items_dev), frame.n_items, frame.n_pixels,
                                     n_classes, ctypes.byref(ri), ctypes.byref(t), wv, _ptr(loss_out),
                                     ctypes.byref(gi), _ptr(ws), ws.numel(), _stream(dev)), "gs_pyramid_loss")
     return loss_out.view(frame.n_items, 3), grad
 
 
-def alloc_grads(cfg, g: dict, frame: Frame) -> dict:
+GRAD_FIELDS = ("mean", "log_scale", "quat", "opacity", "rgb", "sem", "emb", "pose", "head_W1", "head_b1", "head_W2",
+               "head_b2")
+
+
+def alloc_grads(cfg, g: dict, frame: Frame, n_classes: int = 0) -> dict:
     n = int(g["mean"].shape[0])
     dev = frame.device
     z = lambda *s: torch.empty(*s, dtype=torch.float32, device=dev)  # noqa: E731
+    learned = g.get("emb") is not None
     out = dict(mean=z(n, 3), log_scale=z(n, 3), quat=z(n, 4), opacity=z(n), rgb=z(n, 3),
-               sem=z(n, cfg.n_sem) if cfg.n_sem else None, emb=None, pose=z(frame.n_views, 6))
+               sem=z(n, cfg.n_sem) if (cfg.n_sem and not learned) else None,
+               emb=z(n, 16) if learned else None, pose=z(frame.n_views, 6))
+    if learned:
+        out.update(head_W1=z(64, 16), head_b1=z(64), head_W2=z(n_classes, 64), head_b2=z(n_classes))
     return out
 
 
 def render_bwd(cfg, g: dict, proj: dict, frame: Frame, sorter: Sorter, fwd: dict, grad_in: dict, grads=None,
-               ws=None) -> dict:
+               ws=None, head=None) -> dict:
     n = int(g["mean"].shape[0])
-    grads = grads or alloc_grads(cfg, g, frame)
+    grads = grads or alloc_grads(cfg, g, frame, int(head["b2"].shape[0]) if head is not None else 0)
     if ws is None:
         ws = torch.empty(workspace_bytes(L.GS_WS_RENDER_BWD, cfg, frame, n), dtype=torch.uint8, device=frame.device)
     gs = gaussians_struct(g)
     ps = _projected(proj)
-    fi = _images(fwd)
-    gi = _images(grad_in)
-    gr = L.Grads(*(None if grads.get(k) is None else grads[k].data_ptr()
-                   for k in ("mean", "log_scale", "quat", "opacity", "rgb", "sem", "emb", "pose")))
+    fi = _images(fwd, frame.n_pixels)
+    gi = _images(grad_in, frame.n_pixels)
+    gr = L.Grads(*(None if grads.get(k) is None else grads[k].data_ptr() for k in GRAD_FIELDS))
+    hs = head_struct(head)
     L.check(L.lib().gs_render_bwd(ctypes.byref(cfg), ctypes.byref(gs), ctypes.byref(ps), _ptr(frame.views_dev),
                                   frame.n_views, _ptr(frame.items_dev), frame.n_items, frame.n_tiles,
-                                  _ptr(sorter.vals), _ptr(sorter.ranges), None, ctypes.byref(fi), ctypes.byref(gi),
-                                  ctypes.byref(gr), _ptr(ws), ws.numel(), _stream(frame.device)), "gs_render_bwd")
+                                  _ptr(sorter.vals), _ptr(sorter.ranges), ctypes.byref(hs) if hs is not None else None,
+                                  ctypes.byref(fi), ctypes.byref(gi), ctypes.byref(gr), _ptr(ws), ws.numel(),
+                                  _stream(frame.device)), "gs_render_bwd")
     return grads
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, lr: float, step: int,
+              bf16_copy: torch.Tensor | None = None, beta1=0.9, beta2=0.999, eps=1e-8):
+    L.check(L.lib().gs_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), lr, beta1, beta2, eps,
+                                 step, _ptr(bf16_copy), _stream(param.device)), "gs_adam_step")
+
+
+def distill_loss(frame: Frame, C: int, teacher: torch.Tensor, student: torch.Tensor, mse_w=0.1, grad=None,
+                 loss_out=None, ws=None):
+    dev = frame.device
+    grad = grad if grad is not None else torch.empty_like(student)
+    loss_out = loss_out if loss_out is not None else torch.empty(1, dtype=torch.float32, device=dev)
+    ws = ws if ws is not None else torch.empty(256, dtype=torch.uint8, device=dev)
+    L.check(L.lib().gs_distill_loss(_ptr(frame.items_dev), frame.n_items, frame.n_pixels, C, _ptr(teacher),
+                                    _ptr(student), mse_w, _ptr(loss_out), _ptr(grad), _ptr(ws), ws.numel(),
+                                    _stream(dev)), "gs_distill_loss")
+    return loss_out, grad
+
+
+def argmax_agreement(frame: Frame, C: int, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    counts = torch.empty(frame.n_items, dtype=torch.int64, device=frame.device)
+    L.check(L.lib().gs_argmax_agreement(_ptr(frame.items_dev), frame.n_items, frame.n_pixels, C, _ptr(a), _ptr(b),
+                                        _ptr(counts), _stream(frame.device)), "gs_argmax_agreement")
+    return counts
 
 
 def downsample(frame: Frame, K: int, img: torch.Tensor, labels: torch.Tensor | None = None):

@@ -224,13 +224,14 @@ def room_scene(n=200_000, n_classes=52, seed=SEED_SCENE + 1, size=(6.0, 5.0, 3.0
     surf = np.concatenate([sid_a, sid_b])
     log_scale, quat, opacity, rgb = _common_params(rng, n, log_mu, log_sd)
     cls = surf % n_classes
-    sem = emb = None
+    emb = None
+    # class logits are drawn in every mode: in learned mode they define the plain
+    # C-class render the head is fitted to
+    sem = rng.normal(size=(n, n_classes))
+    sem[np.arange(n), cls] += 3.0
+    sem = sem.astype(np.float32)
     if embed:
         emb = f32_to_bf16_bits(rng.normal(0.0, 0.1, size=(n, 16)).astype(np.float32))
-    else:
-        sem = rng.normal(size=(n, n_classes))
-        sem[np.arange(n), cls] += 3.0
-        sem = sem.astype(np.float32)
     sc = Scene(mean.astype(np.float32), log_scale.astype(np.float32), quat.astype(np.float32),
                opacity.astype(np.float32), rgb.astype(np.float32), sem, emb, n_classes)
     sc.boxes = boxes
@@ -356,3 +357,21 @@ def random_image(n_pixels, K, seed=5100, scale=1.0):
     """Planar K-channel image of n_pixels pixels, N(0, scale^2)."""
     rng = np.random.default_rng(seed)
     return (rng.normal(size=n_pixels * K) * scale).astype(np.float32)
+
+
+def head_weights(n_classes, seed=6000, d_in=16, d_hidden=64):
+    """Initial learned-head weights: W1 ~ N(0, 1/d_in), W2 ~ N(0, 1/d_hidden) as bfloat16
+    bits, biases zero (float32)."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.normal(0.0, 1.0 / math.sqrt(d_in), size=(d_hidden, d_in)).astype(np.float32)
+    W2 = rng.normal(0.0, 1.0 / math.sqrt(d_hidden), size=(n_classes, d_hidden)).astype(np.float32)
+    return dict(W1=f32_to_bf16_bits(W1), b1=np.zeros(d_hidden, np.float32), W2=f32_to_bf16_bits(W2),
+                b2=np.zeros(n_classes, np.float32))
+
+
+def config_learned(n=500_000, n_classes=52, n_views=8):
+    """The batched room scene with a 16-dim bfloat16 embedding per Gaussian (and the
+    52-class logits that define the plain render), 8 views at 640x480, 1-3 levels."""
+    sc = room_scene(n=n, n_classes=n_classes, seed=SEED_SCENE + 2, embed=True)
+    views = room_views(sc, n_views, 640, 480, seed=SEED_VIEWS + 2, level_choices=(1, 2, 3))
+    return sc, views

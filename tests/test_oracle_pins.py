@@ -512,6 +512,26 @@ def test_head_backward_finite_difference():
             assert g[name][idx] == pytest.approx(fd, rel=1e-6, abs=1e-8), (name, idx)
 
 
+def test_distill_loss_closed_forms_and_gradient():
+    rng = np.random.default_rng(15)
+    v = view(8, 6, 4.0, levels=1)
+    C = 5
+    t = rng.normal(size=48 * C)
+    # student == teacher: the MSE part vanishes and the CE part is the teacher's entropy
+    loss, g = oracle.distill([v], C, t, t, mse_w=0.3)
+    T = t.reshape(C, 48)
+    pt = np.exp(T - T.max(0)) / np.exp(T - T.max(0)).sum(0)
+    assert loss == pytest.approx(float(np.mean(-(pt * np.log(pt)).sum(0))), rel=1e-12)
+    np.testing.assert_allclose(g, 0.0, atol=1e-15)
+    s = rng.normal(size=48 * C)
+    loss, g = oracle.distill([v], C, t, s, mse_w=0.3)
+    h = 1e-6
+    for j in rng.choice(len(s), 20, replace=False):
+        e = np.zeros_like(s); e[j] = h
+        fd = (oracle.distill([v], C, t, s + e, 0.3)[0] - oracle.distill([v], C, t, s - e, 0.3)[0]) / (2 * h)
+        assert g[j] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+
+
 # ---------------------------------------------------------------- P-k
 def test_pyramid_levels_scale_projection_exactly():
     sc, views = scenes.config_room(n=20000, n_classes=4)
