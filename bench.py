@@ -2,11 +2,14 @@
 
 One step = projection -> binning/sort -> compositing -> pyramid loss -> backward to
 every Gaussian parameter and the pose tangent, over every pyramid level of the
-batch, through the C ABI. Inputs are resident in HBM before timing starts; targets
-(2x2 box pyramids of a render of a perturbed copy of the scene) are built once.
+batch, through the C ABI, captured once as a HIP graph and replayed. Inputs are
+resident in HBM before timing; targets (2x2 box pyramids of a render of a perturbed
+copy of the scene) are built once beforehand.
 
-Prints one JSON line. Default workload: 200k Gaussians in a 6x5x3 m room, 52 plain
-semantic classes, one view at 1200x680 with a 3-level pyramid.
+Prints one JSON line. `value` is the default workload's MP/s: 200k Gaussians in a
+6x5x3 m room, 52 plain classes, one view at 1200x680 with a 3-level pyramid. The
+same line carries the batched 8-view workload (autotuned) and the learned-semantic
+head against the plain form (trained first), unless --quick.
 """
 from __future__ import annotations
 
@@ -23,36 +26,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd megapixels/s over all pyramid levels; HBM GB/s; plain vs learned-sem"
 HBM_PEAK_GBS = 8000.0
-# fp32 vector peak from unit counts: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz,
-# doubled by packed-FP32 issue (this library does not emit packed FP32)
+# fp32 vector peak from unit counts: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s,
+# doubled by packed-FP32 issue (157.3); the library is built without packed FP32
 VALU_PEAK_TFLOPS = 157.3
 VALU_PEAK_UNPACKED_TFLOPS = 78.6
 
 
-def build_workload(name, device):
+# ----------------------------------------------------------------------------- workloads
+def make_targets(cfg_plain, fr, sc, device):
+    """rgb, depth, labels: a perturbed copy of the scene rendered at every item, level 0
+    box-downsampled to the coarser levels, labels = argmax of the class channels."""
     import torch
     from paper_2412_01217_amd import raster, scenes
-    if name == "room":
-        sc, views = scenes.config_room()
-        desc = "room 6x5x3 m, 200k Gaussians, 52 plain classes, 1 view 1200x680, 3-level pyramid"
-    elif name == "batch":
-        sc, views = scenes.config_batch()
-        desc = "room 6x5x3 m, 500k Gaussians, 20 plain classes, 8 views 640x480, 1-3 levels each"
-    elif name == "tiny":
-        sc, views = scenes.config_tiny()
-        desc = "tiny 2k Gaussians, 8 classes, 128x96, 1 level"
-    else:
-        raise SystemExit(f"unknown workload {name}")
-    C = sc.n_classes
-    cfg = raster.config(C)
-    fr = raster.Frame(cfg, views, device=device)
-    g = raster.to_device(sc, device)
-    # targets: perturbed copy rendered at every item, then level 0 box-downsampled (labels = argmax)
-    tgt_scene = scenes.perturbed(sc)
-    gt = raster.to_device(tgt_scene, device)
-    pt = raster.preprocess(cfg, gt, fr)
-    st = raster.bin_sort(cfg, pt, fr, sc.n)
-    timg = raster.render_fwd(cfg, gt, pt, fr, st)
+    C = cfg_plain.n_sem
+    tgt = scenes.perturbed(sc)
+    tgt.emb = None
+    gt = raster.to_device(tgt, device)
+    pt = raster.preprocess(cfg_plain, gt, fr)
+    st = raster.bin_sort(cfg_plain, pt, fr, sc.n)
+    timg = raster.render_fwd(cfg_plain, gt, pt, fr, st)
     K = 4 + C
     labels = torch.empty(fr.n_pixels, dtype=torch.int32, device=device)
     raster.downsample(fr, K, timg["color"], labels)
@@ -64,22 +56,208 @@ def build_workload(name, device):
         planes = timg["color"][pb * K: pb * K + K * HW].view(K, HW)
         rgb[pb * 3: pb * 3 + 3 * HW] = planes[:3].reshape(-1)
         depth[pb: pb + HW] = planes[3]
-    targets = dict(rgb=rgb, depth=depth, label=labels)
-    del timg, st, pt, gt
     torch.cuda.synchronize()
-    return dict(scene=sc, views=views, cfg=cfg, frame=fr, g=g, targets=targets, C=C, K=K, desc=desc)
+    return dict(rgb=rgb, depth=depth, label=labels)
 
 
-def cpu_baseline(wl, budget_s=15.0):
+def plain_step(sc, views, device, targets=None, variant=0, tile_order=0):
+    from paper_2412_01217_amd import raster
+    from paper_2412_01217_amd.step import MappingStep
+    C = sc.n_classes
+    cfg = raster.config(C, variant=variant, tile_order=tile_order)
+    fr = raster.Frame(cfg, views, device=device)
+    g = raster.to_device(sc, device)
+    g.pop("emb", None)
+    targets = targets if targets is not None else make_targets(cfg, fr, sc, device)
+    return MappingStep(cfg, fr, g, targets, C), targets
+
+
+def learned_step(sc, views, head, device, targets):
+    from paper_2412_01217_amd import raster
+    from paper_2412_01217_amd.step import MappingStep
+    cfg = raster.config(16)
+    fr = raster.Frame(cfg, views, device=device)
+    g = raster.to_device(sc, device)
+    g.pop("sem", None)
+    return MappingStep(cfg, fr, g, targets, head["b2"].shape[0], head=head)
+
+
+# ----------------------------------------------------------------------------- measurement
+def measure(step, steps, warmup, graph=True):
+    """Per-stage times from an eager pass with events between the calls, then the timed
+    region: `steps` graph replays of the whole step."""
+    import torch
+    from paper_2412_01217_amd import raster
+    for _ in range(warmup):
+        step.run()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for k in range(steps):
+        step.run(evs[k])
+    t1.record()
+    torch.cuda.synchronize()
+    eager_ms = t0.elapsed_time(t1) / steps
+    names = ("bin_sort", "render_fwd", "loss", "render_bwd")
+    stage_ms = {nm: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, nm in enumerate(names)}
+    stage_ms["preprocess_and_gaps"] = eager_ms - sum(stage_ms.values())
+    run = step.run
+    if graph:
+        g = raster.Graph(step.run, step.frame.device)
+        run = g.launch
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        run()
+    t1.record()
+    torch.cuda.synchronize()
+    assert not step.overflowed()
+    return dict(ms=t0.elapsed_time(t1) / steps, eager_ms=eager_ms, stage_ms=stage_ms)
+
+
+def work_counts(step):
+    import torch
+    fr = step.frame
+    nc = int(step.img["n_contrib"].to(torch.int64).sum().item())
+    return dict(pairs=nc, dup=step.n_dup_probe, visible=step.n_visible_probe, pixels=fr.n_pixels, items=fr.n_items,
+                views=fr.n_views, n=step.n, K=4 + step.cfg.n_sem)
+
+
+def algorithmic_bytes(c, n_classes, learned=False):
+    """Bytes the step must move at minimum (model documented with the design notes)."""
+    N, V, E, vis, D, P, K = c["n"], c["views"], c["items"] * c["n"], c["visible"], c["dup"], c["pixels"], c["K"]
+    feat = 4 * (K - 1) if not learned else 12 + 32            # rgb + semantics (float) or embedding (bf16)
+    rec = 32 + 4                                               # render record + depth
+    tile_passes = 2
+    b = 0
+    b += V * N * 44 + E * 4 + vis * 36                          # projection
+    b += E * 4 + vis * 12 * (1 + 2 * 5) + D * 8 * (1 + 2 * tile_passes) + D * 8   # binning and sort
+    b += D * (4 + rec + feat) + P * 4 * (K + 2)                # forward
+    if learned:
+        b += P * 4 * (16 + n_classes)                          # decode: embedding in, logits out
+    b += P * 4 * (K + 5) + P * 4 * K                           # loss
+    b += D * (4 + rec + feat) + P * 4 * (K + 2) + D * 4 * (K + 6)   # backward compositing
+    b += V * N * 44 + vis * 32 + N * (44 + 4 * (K - 1))        # projection backward + gradient writes
+    return b
+
+
+def roofline(step, stage_ms, counts):
+    K = counts["K"]
+    nc = counts["pairs"]
+    kern = {}
+    for name, stage, per_pair in (("k_render_fwd", "render_fwd", 18 + 2 * K), ("k_render_bwd", "render_bwd", 45 + 6 * K)):
+        flops = nc * per_pair
+        t = stage_ms[stage]
+        ach = flops / (t * 1e-3) / 1e12
+        kern[name] = {"bound": "alu", "kernel": name, "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": ach / VALU_PEAK_TFLOPS, "frac_unpacked_peak": ach / VALU_PEAK_UNPACKED_TFLOPS,
+                      "traffic": None, "flops_per_launch": flops, "avg_launch_ms": t, "timed_call": "gs_" + stage}
+    dominant = max(kern, key=lambda k: kern[k]["avg_launch_ms"])
+    return kern[dominant], {k: v for k, v in kern.items() if k != dominant}
+
+
+# ----------------------------------------------------------------------------- sub-benchmarks
+def batch_report(args, device):
+    """The 8-view batch (500k Gaussians, 20 classes, 640x480, 1-3 levels each), with the
+    launch configuration picked by the autotuner."""
+    from paper_2412_01217_amd import autotune, scenes
+    from paper_2412_01217_amd.step import MappingStep
+    sc, views = scenes.config_batch()
+    step, targets = plain_step(sc, views, device)
+
+    def make(cfg):
+        return MappingStep(cfg, step.frame, step.g, targets, sc.n_classes)
+
+    tuned = autotune.tune(make, step.cfg, step.frame, sc.n)
+    step = make(step.cfg)
+    m = measure(step, args.steps, args.warmup)
+    c = work_counts(step)
+    return {"workload": "room 6x5x3 m, 500k Gaussians, 20 plain classes, 8 views 640x480, 1-3 levels each",
+            "value": c["pixels"] / 1e6 / (m["ms"] * 1e-3), "unit": "MP/s", "ms_per_step": m["ms"],
+            "stage_ms": m["stage_ms"], "items": c["items"], "pixels_per_step": c["pixels"], "duplicates": c["dup"],
+            "autotune": tuned,
+            "hbm_gbs_effective": algorithmic_bytes(c, sc.n_classes) / (m["ms"] * 1e-3) / 1e9}
+
+
+def learned_report(args, device):
+    """The learned semantic head on the batched room scene with 52 classes: train the
+    head for 2,000 steps on plain renders of random views, measure argmax agreement and
+    logit error on held-out views, then time learned against plain on the 8-view batch."""
+    import torch
+    from paper_2412_01217_amd import scenes
+    from paper_2412_01217_amd.learned import Trainer
+    sc, views = scenes.config_learned()
+    train_views = scenes.room_views(sc, 24, 640, 480, levels=3, seed=scenes.SEED_VIEWS + 60)
+    test_views = scenes.room_views(sc, 16, 640, 480, levels=3, seed=scenes.SEED_VIEWS + 61)
+    t0 = time.perf_counter()
+    tr = Trainer(sc, train_views, sc.n_classes, device)
+    before = tr.evaluate(test_views[:4])
+    tr.train(args.train_steps)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    quality = tr.evaluate(test_views)
+    head = tr.head.as_dict()
+    trained_sc = sc.copy()
+    trained_sc.emb = tr.g_learned["emb"].cpu().numpy().view(np.uint16).copy()
+    del tr
+    torch.cuda.empty_cache()
+    plain, targets = plain_step(sc, views, device)
+    mp = measure(plain, args.steps, args.warmup)
+    cp = work_counts(plain)
+    del plain
+    lstep = learned_step(trained_sc, views, head, device, targets)
+    ml = measure(lstep, args.steps, args.warmup)
+    cl = work_counts(lstep)
+    mpx = cl["pixels"] / 1e6
+    return {"workload": "room 6x5x3 m, 500k Gaussians, 52 classes via 16-dim bf16 embedding + 16->64->52 MLP, "
+                        "8 views 640x480, 1-3 levels each",
+            "head_training": {"steps": args.train_steps, "seconds": train_s, "train_views": len(train_views),
+                              "agreement_untrained": before["agreement"]},
+            "argmax_agreement": quality["agreement"], "logit_rmse": quality["logit_rmse"],
+            "heldout_views": len(test_views), "heldout_pixels": quality["pixels"],
+            "learned": {"value": mpx / (ml["ms"] * 1e-3), "unit": "MP/s", "ms_per_step": ml["ms"],
+                        "stage_ms": ml["stage_ms"],
+                        "hbm_gbs_effective": algorithmic_bytes(cl, 52, learned=True) / (ml["ms"] * 1e-3) / 1e9},
+            "plain_c52": {"value": mpx / (mp["ms"] * 1e-3), "unit": "MP/s", "ms_per_step": mp["ms"],
+                          "stage_ms": mp["stage_ms"],
+                          "hbm_gbs_effective": algorithmic_bytes(cp, 52) / (mp["ms"] * 1e-3) / 1e9},
+            "speedup_learned_over_plain": mp["ms"] / ml["ms"]}
+
+
+def large_report(args, device):
+    """Two-room scene, 2M Gaussians, 52 classes via the learned head, 16 views at
+    1920x1080 with 4 levels each."""
+    import torch
+    from paper_2412_01217_amd import raster, scenes
+    sc = scenes.room_scene(n=2_000_000, n_classes=52, seed=scenes.SEED_SCENE + 4, size=(12.0, 10.0, 3.0), n_boxes=40,
+                           partition_x=6.0, embed=True)
+    views = scenes.room_views(sc, 16, 1920, 1080, levels=4, seed=scenes.SEED_VIEWS + 4)
+    cfg_p = raster.config(52)
+    fr = raster.Frame(cfg_p, views, device=device)
+    targets = make_targets(cfg_p, fr, sc, device)
+    w = scenes.head_weights(52)
+    head = dict(W1=torch.from_numpy(w["W1"].view(np.int16).copy()).to(device), b1=torch.from_numpy(w["b1"]).to(device),
+                W2=torch.from_numpy(w["W2"].view(np.int16).copy()).to(device), b2=torch.from_numpy(w["b2"]).to(device))
+    step = learned_step(sc, views, head, device, targets)
+    m = measure(step, max(2, args.steps // 4), 1)
+    c = work_counts(step)
+    return {"workload": "two-room 12x10x3 m, 2M Gaussians, 52 classes via learned head, 16 views 1920x1080, 4 levels",
+            "value": c["pixels"] / 1e6 / (m["ms"] * 1e-3), "unit": "MP/s", "ms_per_step": m["ms"],
+            "stage_ms": m["stage_ms"], "pixels_per_step": c["pixels"], "duplicates": c["dup"],
+            "hbm_gbs_effective": algorithmic_bytes(c, 52, learned=True) / (m["ms"] * 1e-3) / 1e9}
+
+
+def cpu_baseline(sc, views, targets, C, budget_s=15.0):
     """The FP64 oracle (single thread) on a bounded sample of the same workload:
     forward + loss + backward restricted to a set of tiles of the first item."""
     import oracle
-    sc, views = wl["scene"], wl["views"]
     its = oracle.items(views)
     n_items, P, tiles = oracle.layout(views)
-    C = wl["C"]
-    tgt = {k: v.cpu().numpy() for k, v in wl["targets"].items()}
-    # grow the tile sample until the oracle's time reaches the budget
+    tgt = {k: v.cpu().numpy() for k, v in targets.items()}
     rng = np.random.default_rng(5050)
     order = rng.permutation(its[0]["ntx"] * its[0]["nty"])
     n_t = 4
@@ -100,92 +278,58 @@ def cpu_baseline(wl, budget_s=15.0):
                        f"binning of all {sc.n} Gaussians at all {n_items} levels included; {dt:.1f} s")
 
 
+# ----------------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="room")
+    ap.add_argument("--workload", default="room", choices=("room", "large"))
+    ap.add_argument("--quick", action="store_true", help="only the default workload (no batch / learned reports)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=0, help="render kernels: 0 auto, 1 VALU, 2 MFMA")
     ap.add_argument("--eager", action="store_true", help="time eager calls instead of graph replays")
+    ap.add_argument("--train-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
+    from paper_2412_01217_amd import scenes
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    wl = build_workload(args.workload, dev)
-    wl["cfg"].variant = args.variant
-    from paper_2412_01217_amd.step import MappingStep
-    step = MappingStep(wl["cfg"], wl["frame"], wl["g"], wl["targets"], wl["C"])
-    fr = wl["frame"]
-    for _ in range(args.warmup):
-        step.run()
-    torch.cuda.synchronize()
-    # eager pass with events between the library calls: per-stage times on the launch stream
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for k in range(args.steps):
-        step.run(evs[k])
-    t1.record()
-    torch.cuda.synchronize()
-    eager_ms = t0.elapsed_time(t1) / args.steps
-    stage = {"bin_sort": [], "render_fwd": [], "loss": [], "render_bwd": []}
-    for e in evs:
-        stage["bin_sort"].append(e[0].elapsed_time(e[1]))
-        stage["render_fwd"].append(e[1].elapsed_time(e[2]))
-        stage["loss"].append(e[2].elapsed_time(e[3]))
-        stage["render_bwd"].append(e[3].elapsed_time(e[4]))
-    stage_ms = {k: float(np.mean(v)) for k, v in stage.items()}
-    stage_ms["preprocess_and_gaps"] = eager_ms - sum(stage_ms.values())
-    # the whole step captured once in a HIP graph and replayed: the timed region
-    from paper_2412_01217_amd import raster
-    graph = raster.Graph(step.run, dev) if not args.eager else None
-    run = (lambda: graph.launch()) if graph else step.run
-    for _ in range(args.warmup):
-        run()
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(args.steps):
-        run()
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / args.steps
-    mp = fr.n_pixels / 1e6
-    # algorithmic work of the compositing kernels, per (pixel, Gaussian) pair iterated up to each
-    # pixel's stop point (E = sum of n_contrib): forward 18 + 2K flop, backward 45 + 6K flop
-    nc = step.img["n_contrib"].to(torch.int64).sum().item()
-    K = wl["K"]
-    kern = {}
-    for name, stage_name, per_pair in (("k_render_fwd", "render_fwd", 18 + 2 * K),
-                                       ("k_render_bwd", "render_bwd", 45 + 6 * K)):
-        flops = nc * per_pair
-        t = stage_ms[stage_name]
-        ach = flops / (t * 1e-3) / 1e12
-        kern[name] = {"bound": "alu", "kernel": name, "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                      "frac": ach / VALU_PEAK_TFLOPS, "frac_unpacked_peak": ach / VALU_PEAK_UNPACKED_TFLOPS,
-                      "traffic": None, "flops_per_launch": flops, "avg_launch_ms": t,
-                      "timed_call": "gs_" + stage_name}
-    dominant = max(kern, key=lambda k: kern[k]["avg_launch_ms"])
+    if args.workload == "large":
+        print(json.dumps({"metric": METRIC, **large_report(args, dev)}), flush=True)
+        return
+    sc, views = scenes.config_room()
+    step, targets = plain_step(sc, views, dev, variant=args.variant)
+    m = measure(step, args.steps, args.warmup, graph=not args.eager)
+    c = work_counts(step)
+    ms = m["ms"]
+    roof, other = roofline(step, m["stage_ms"], c)
     out = {
-        "metric": METRIC, "value": mp / (ms * 1e-3), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": wl["desc"], "gaussians": int(wl["g"]["mean"].shape[0]), "classes": wl["C"],
-                   "pixels_per_step": fr.n_pixels, "items": fr.n_items, "duplicates": step.n_dup_probe,
-                   "pairs_iterated": int(nc), "semantic_mode": "plain", "render_variant": args.variant},
-        "eager_ms_per_step": eager_ms, "timed": "eager calls" if args.eager else "HIP graph replay of the whole step",
-        "stage_ms": stage_ms,
-        "roofline": kern[dominant],
-        "roofline_other": {k: v for k, v in kern.items() if k != dominant},
+        "metric": METRIC, "value": c["pixels"] / 1e6 / (ms * 1e-3), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "room 6x5x3 m, 200k Gaussians, 52 plain classes, 1 view 1200x680, 3-level pyramid",
+                   "gaussians": sc.n, "classes": sc.n_classes, "pixels_per_step": c["pixels"], "items": c["items"],
+                   "duplicates": c["dup"], "visible_item_gaussians": c["visible"], "pairs_iterated": c["pairs"],
+                   "semantic_mode": "plain", "render_variant": args.variant},
+        "timed": "eager calls" if args.eager else "HIP graph replay of the whole step",
+        "eager_ms_per_step": m["eager_ms"], "stage_ms": m["stage_ms"],
+        "hbm_gbs_effective": algorithmic_bytes(c, sc.n_classes) / (ms * 1e-3) / 1e9,
+        "roofline": roof, "roofline_other": other,
     }
+    del step
+    torch.cuda.empty_cache()
+    if not args.quick:
+        out["batch"] = batch_report(args, dev)
+        torch.cuda.empty_cache()
+        out["learned_vs_plain"] = learned_report(args, dev)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline(sc, views, targets, sc.n_classes)
     print(json.dumps(out), flush=True)
 
 

@@ -57,7 +57,7 @@ typedef struct gs_config {
   int32_t full_rect;       /* 0; 1 = every Gaussian covers every tile of its item */
   int32_t n_sem;           /* composited semantic channels, 0..60 (plain: classes; learned: 16) */
   int32_t variant;         /* render kernels: 0 automatic, 1 per-lane FMA (VALU), 2 matrix cores (MFMA) */
-  int32_t reserved;
+  int32_t tile_order;      /* 0: coarse pyramid levels (longest tile lists) launched first; 1: item order */
 } gs_config;
 
 /* One camera view: world -> camera transform x_c = R x_w + t (OpenCV axes,

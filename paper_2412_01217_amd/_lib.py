@@ -35,7 +35,7 @@ EXPORTS = (
 class Config(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("z_near", c_float), ("eps_dilate", c_float),
                 ("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("guard", c_float),
-                ("full_rect", c_int32), ("n_sem", c_int32), ("variant", c_int32), ("reserved", c_int32)]
+                ("full_rect", c_int32), ("n_sem", c_int32), ("variant", c_int32), ("tile_order", c_int32)]
 
 
 class View(ctypes.Structure):

@@ -1,0 +1,93 @@
+"""Autotuner for the batched mapping step.
+
+For one workload signature (Gaussian count, channels, items, pixels, tiles) it times
+each candidate launch configuration -- render kernel variant (per-lane FMA or matrix
+core) and tile launch order (coarse pyramid levels first, or item order) -- as HIP
+graph replays of the whole step, keeps the fastest, and caches the choice in a JSON
+file (GS_AUTOTUNE_CACHE, default ~/.cache/gs_autotune.json) keyed by device and
+signature. Every candidate computes the same result; only the schedule differs.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+CANDIDATES = ({"variant": 2, "tile_order": 0}, {"variant": 2, "tile_order": 1}, {"variant": 1, "tile_order": 1})
+
+
+def cache_path() -> str:
+    return os.environ.get("GS_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "gs_autotune.json"))
+
+
+def signature(cfg, frame, n: int) -> str:
+    dev = torch.cuda.get_device_properties(frame.device)
+    arch = getattr(dev, "gcnArchName", dev.name).split(":")[0]
+    return f"{arch}|n={n}|sem={cfg.n_sem}|items={frame.n_items}|px={frame.n_pixels}|tiles={frame.n_tiles}"
+
+
+def _load():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(db):
+    p = cache_path()
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        tmp = p + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+        os.replace(tmp, p)
+    except OSError:
+        pass   # a read-only home only costs re-tuning next time
+
+
+def time_step(step, reps=5, warmup=2) -> float:
+    """Mean milliseconds of a graph replay of step.run()."""
+    graph = step.capture()
+    for _ in range(warmup):
+        graph.launch()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        graph.launch()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / reps
+
+
+def tune(make_step, cfg, frame, n: int, candidates=CANDIDATES, reps=5, use_cache=True) -> dict:
+    """make_step(cfg) -> an object with run() and capture(). Returns
+    {"choice": {...}, "times_ms": {...}, "cached": bool}; sets the choice on cfg."""
+    key = signature(cfg, frame, n)
+    db = _load() if use_cache else {}
+    if use_cache and key in db:
+        choice = db[key]["choice"]
+        for k, v in choice.items():
+            setattr(cfg, k, v)
+        return {"choice": choice, "times_ms": db[key]["times_ms"], "cached": True}
+    times = {}
+    best, best_t = None, float("inf")
+    for cand in candidates:
+        for k, v in cand.items():
+            setattr(cfg, k, v)
+        step = make_step(cfg)
+        t = time_step(step, reps=reps)
+        name = ",".join(f"{k}={v}" for k, v in cand.items())
+        times[name] = t
+        if t < best_t:
+            best, best_t = cand, t
+        del step
+    for k, v in best.items():
+        setattr(cfg, k, v)
+    db[key] = {"choice": best, "times_ms": times}
+    if use_cache:
+        _store(db)
+    return {"choice": best, "times_ms": times, "cached": False}

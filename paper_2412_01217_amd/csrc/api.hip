@@ -75,6 +75,7 @@ bool cfg_ok(const gs_config* c) {
   if (!(c->alpha_max > c->alpha_min) || !(c->alpha_max < 1.0f) || !(c->t_min >= 0.0f) || !(c->guard > 0.0f)) return false;
   if (c->n_sem < 0 || c->n_sem > 60) return false;
   if (c->variant < 0 || c->variant > 2) return false;
+  if (c->tile_order < 0 || c->tile_order > 1) return false;
   return true;
 }
 
@@ -108,7 +109,7 @@ void gs_config_default(gs_config* c) {
   c->full_rect = 0;
   c->n_sem = 0;
   c->variant = 0;
-  c->reserved = 0;
+  c->tile_order = 0;
 }
 
 const char* gs_status_string(int s) {

@@ -66,9 +66,9 @@ struct Ctx {
 
 // Tiles are launched coarse pyramid levels first: their lists are the longest, and
 // starting them early lets the many short fine-level tiles fill in around them.
-__device__ __forceinline__ Ctx make_ctx(const gs_item* items, int n_items, const uint32_t* ranges) {
+__device__ __forceinline__ Ctx make_ctx(const gs_item* items, int n_items, const uint32_t* ranges, int order) {
   Ctx c;
-  const int tile = (int)gridDim.x - 1 - (int)blockIdx.x;
+  const int tile = order ? (int)blockIdx.x : (int)gridDim.x - 1 - (int)blockIdx.x;
   c.item = item_of_tile(items, n_items, tile);
   const gs_item it = items[c.item];
   const int lt = tile - it.tile_base;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_render_fwd_mfma(gs_config cfg, const fl
   __shared__ float4 s_rec[2 * kBatch];
   __shared__ float s_feat[kBatch * FST];
   __shared__ float s_w[4][64 * kWst];
-  const Ctx c = make_ctx(items, n_items, ranges);
+  const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   int u, v;
   tile_pixel(c, tid, u, v);
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_mfma(gs_config cfg, const fl
   __shared__ float s_df[kBatch * KP];
   __shared__ float s_geo[kBatch * 6 * 16];
   __shared__ uint32_t s_lmax;
-  const Ctx c = make_ctx(items, n_items, ranges);
+  const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int Kr = 4 + n_sem;
   int u, v;

@@ -2,7 +2,8 @@
 buffer allocated up front, so that it can be replayed eagerly or as a HIP graph.
 
 run(): projection -> binning -> compositing -> per-level loss -> backward, all items
-       of the frame, through the C ABI on the current torch stream.
+       of the frame, through the C ABI on the current torch stream. With a head
+       (learned mode) the loss's semantic term acts on the decoded logits.
 """
 from __future__ import annotations
 
@@ -14,9 +15,10 @@ from . import raster
 
 class MappingStep:
     def __init__(self, cfg, frame: raster.Frame, g: dict, targets: dict, n_classes: int, w=(1.0, 1.0, 1.0),
-                 capacity_margin=1.15):
+                 capacity_margin=1.15, head: dict | None = None):
         self.cfg, self.frame, self.g, self.targets = cfg, frame, g, targets
         self.n_classes = n_classes
+        self.head = head
         self.w = tuple(float(x) for x in w)
         dev = frame.device
         n = int(g["mean"].shape[0])
@@ -24,14 +26,17 @@ class MappingStep:
         self.proj = raster.preprocess(cfg, g, frame)
         probe = raster.bin_sort(cfg, self.proj, frame, n)
         self.n_dup_probe = int(probe.n_dup.item())
+        self.n_visible_probe = int((self.proj["radius"] > 0).sum().item())
         del probe
         self.sorter = raster.Sorter(cfg, frame, n, capacity=int(self.n_dup_probe * capacity_margin) + 4096)
-        self.img = raster.alloc_images(cfg, frame)
-        self.grad = dict(color=torch.empty_like(self.img["color"]), logits=None)
+        learned = head is not None
+        self.img = raster.alloc_images(cfg, frame, n_classes if learned else 0, learned)
+        self.grad = dict(color=torch.zeros_like(self.img["color"]),
+                         logits=torch.empty_like(self.img["logits"]) if learned else None)
         self.loss = torch.empty(3 * frame.n_items, dtype=torch.float32, device=dev)
         self.loss_ws = torch.empty(raster.workspace_bytes(L.GS_WS_LOSS, cfg, frame, n), dtype=torch.uint8,
                                    device=dev)
-        self.grads = raster.alloc_grads(cfg, g, frame)
+        self.grads = raster.alloc_grads(cfg, g, frame, n_classes)
         self.bwd_ws = torch.empty(raster.workspace_bytes(L.GS_WS_RENDER_BWD, cfg, frame, n), dtype=torch.uint8,
                                   device=dev)
 
@@ -44,14 +49,15 @@ class MappingStep:
         self.sorter.run(self.proj)
         if ev:
             ev[1].record()
-        raster.render_fwd(cfg, g, self.proj, fr, self.sorter, out=self.img)
+        raster.render_fwd(cfg, g, self.proj, fr, self.sorter, out=self.img, head=self.head)
         if ev:
             ev[2].record()
         raster.loss(cfg, fr, self.n_classes, self.img, self.targets, w=self.w, grad=self.grad, loss_out=self.loss,
                     ws=self.loss_ws)
         if ev:
             ev[3].record()
-        raster.render_bwd(cfg, g, self.proj, fr, self.sorter, self.img, self.grad, grads=self.grads, ws=self.bwd_ws)
+        raster.render_bwd(cfg, g, self.proj, fr, self.sorter, self.img, self.grad, grads=self.grads, ws=self.bwd_ws,
+                          head=self.head)
         if ev:
             ev[4].record()
 
