@@ -284,7 +284,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="room", choices=("room", "large"))
+    ap.add_argument("--workload", default="room", choices=("room", "batch", "learned", "large"))
     ap.add_argument("--quick", action="store_true", help="only the default workload (no batch / learned reports)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=0, help="render kernels: 0 auto, 1 VALU, 2 MFMA")
@@ -299,8 +299,9 @@ def main():
     from paper_2412_01217_amd import scenes
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    if args.workload == "large":
-        print(json.dumps({"metric": METRIC, **large_report(args, dev)}), flush=True)
+    sub = {"batch": batch_report, "learned": learned_report, "large": large_report}.get(args.workload)
+    if sub is not None:
+        print(json.dumps({"metric": METRIC, **sub(args, dev)}), flush=True)
         return
     sc, views = scenes.config_room()
     step, targets = plain_step(sc, views, dev, variant=args.variant)
