@@ -22,12 +22,13 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 
 constexpr int kDin = 16;
 constexpr int kHid = 64;
-constexpr int kHeadBlocksMax = 1024;
+constexpr int kHeadBlocksMax = 512;
 // per-block partial of the weight gradients: dW2 [64][64], dW1 [64][32] (column 16 = db1), db2 [64]
 constexpr int kPartW2 = 64 * 64;
 constexpr int kPartW1 = 64 * 32;
 constexpr int kPartB2 = 64;
 constexpr int kPart = kPartW2 + kPartW1 + kPartB2;
+constexpr int kWtStride = kHid + 8;   // bfloat16 row stride of the transposed weights in LDS (16-byte rows)
 
 __device__ __forceinline__ int drow(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
@@ -38,13 +39,14 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// Splits four floats into hi and lo bfloat16 operands.
+// Splits four floats into hi and lo bfloat16 operands (hardware round-to-nearest-even).
 __device__ __forceinline__ void split4(const float* x, v4s& hi, v4s& lo) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const uint16_t h = bf16_rne(x[j]);
-    hi[j] = (short)h;
-    lo[j] = (short)bf16_rne(x[j] - bf16_f(h));
+    const __bf16 h = (__bf16)x[j];
+    const __bf16 l = (__bf16)(x[j] - (float)h);
+    hi[j] = __builtin_bit_cast(short, h);
+    lo[j] = __builtin_bit_cast(short, l);
   }
 }
 
@@ -171,179 +173,261 @@ __global__ __launch_bounds__(256) void k_head_fwd(const gs_item* __restrict__ it
   }
 }
 
-// Writes the wave's 64 x 64 H^T-layout registers to LDS as [row][pixel] (row-major, 64 pixels).
-__device__ __forceinline__ void store_T(float* sh, const v16f (&X)[2][2]) {
-  const int lane = threadIdx.x & 63;
+// Walks the 64-pixel chunks of the concatenated items in increasing order. Chunks
+// never straddle two items, so every pixel of a chunk shares one item's plane layout.
+struct ChunkCursor {
+  int item;
+  int64_t first, end;   // chunks [first, end) belong to `item`
+};
+
+__device__ __forceinline__ int64_t item_chunks(const gs_item& it) { return ((int64_t)it.W * it.H + 63) / 64; }
+
+// Moves the cursor forward to the item holding `chunk`; false once past the last item.
+__device__ __forceinline__ bool seek_chunk(const gs_item* __restrict__ items, int n_items, int64_t chunk,
+                                           ChunkCursor& cur) {
+  while (chunk >= cur.end && cur.item + 1 < n_items) {
+    ++cur.item;
+    cur.first = cur.end;
+    cur.end += item_chunks(items[cur.item]);
+  }
+  return chunk < cur.end;
+}
+
+// Backward of the head. Each wave takes 64-pixel chunks in a grid-stride loop. It
+// stages the chunk's logit gradients in LDS ([class][pixel], classes >= C stay zero),
+// then, per 32-pixel half,
+//  (1) recomputes the hidden pre-activations for the ReLU mask,
+//  (2) forms dH^T = W2^T dlogits^T (hidden in registers, pixels across lanes),
+//  (3) writes dE^T = W1^T dH^T into the colour-gradient planes 4..19,
+//  (4) recomputes H and dH with pixels in registers and hidden units across lanes --
+//      the layout in which a matrix-core product contracts over pixels -- and
+//  (5) accumulates dW2 = dlogits^T relu(H), db2 and dW1 = dH^T [E, 1] (column 16 is
+//      db1) in registers that live across the whole loop.
+// The accumulators are summed over the block's waves in LDS once at the end and written
+// as one partial per block; k_head_reduce adds the partials.
+constexpr int kGst = 65;   // LDS row stride of the staged logit gradients
+__global__ __launch_bounds__(256, 2) void k_head_bwd(const gs_item* __restrict__ items, int n_items, int K, int C,
+                                                     const float* __restrict__ color,
+                                                     const float* __restrict__ glogits,
+                                                     const uint16_t* __restrict__ W1, const float* __restrict__ b1,
+                                                     const uint16_t* __restrict__ W2, float* __restrict__ gcolor,
+                                                     float* __restrict__ partial) {
+  __shared__ float s_buf[4 * kHid * kGst];        // per wave [class][pixel]; the block's partial at the end
+  __shared__ uint16_t s_w2t[kHid * kWtStride];   // W2^T [hidden][class], classes >= C zero
+  __shared__ uint16_t s_w1t[kDin * kWtStride];   // W1^T [d][hidden]
+  __shared__ float s_b1[kHid];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, l32 = lane & 31;
+  for (int i = threadIdx.x; i < kHid * kHid; i += 256) {
+    const int c = i / kHid, h = i % kHid;
+    s_w2t[h * kWtStride + c] = c < C ? W2[c * kHid + h] : (uint16_t)0;
+  }
+  for (int i = threadIdx.x; i < kHid * kDin; i += 256) {
+    const int h = i / kDin, d = i % kDin;
+    s_w1t[d * kWtStride + h] = W1[h * kDin + d];
+  }
+  if (threadIdx.x < kHid) s_b1[threadIdx.x] = b1[threadIdx.x];
+  float* sg = s_buf + wave * kHid * kGst;
+  for (int i = C * kGst + lane; i < kHid * kGst; i += 64) sg[i] = 0.0f;   // rows of absent classes
+  __syncthreads();
+  v16f aW2[2][2], aW1[2];   // aW2[cb][hb]: D[c][h]; aW1[hb]: D[h][d]
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    aW1[i] = zero16();
+    aW2[i][0] = zero16();
+    aW2[i][1] = zero16();
+  }
+  float aB2[2] = {0.0f, 0.0f};   // class l32 + 32 cb, this lane's pixels
+  // W1 as A (i = hidden l32 + 32 hb, k = d 8 ks + 4 half + j), which is also W1^T as B (k = d, j = hidden)
+  v4s w1a[2][2];
 #pragma unroll
   for (int hb = 0; hb < 2; ++hb)
 #pragma unroll
-    for (int pb = 0; pb < 2; ++pb)
+    for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) sh[(drow(r, lane) + 32 * hb) * 65 + (lane & 31) + 32 * pb] = X[hb][pb][r];
-}
+      for (int j = 0; j < 4; ++j) w1a[hb][ks][j] = (short)W1[(l32 + 32 * hb) * kDin + 8 * ks + 4 * half + j];
+  const float b1l[2] = {s_b1[l32], s_b1[l32 + 32]};
 
-// Backward of the head for one wave of 64 pixels. dE goes to the colour-gradient planes
-// 4..19; the weight gradients accumulate into the block's LDS partial `acc`.
-__global__ __launch_bounds__(256) void k_head_bwd(const gs_item* __restrict__ items, int n_items, int64_t P, int K,
-                                                  int C, const float* __restrict__ color,
-                                                  const float* __restrict__ glogits, const uint16_t* __restrict__ W1,
-                                                  const float* __restrict__ b1, const uint16_t* __restrict__ W2,
-                                                  float* __restrict__ gcolor, float* __restrict__ partial) {
-  __shared__ float s_acc[kPart];
-  __shared__ float s_t[4][64 * 65];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < kPart; i += 256) s_acc[i] = 0.0f;
-  __syncthreads();
-  float* sh = s_t[wave];
-  const int64_t n_chunks = (P + 255) / 256;
-  for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
-    const int64_t wave_pix = chunk * 256 + wave * 64;
-    if (wave_pix >= P) continue;
-    v16f H[2][2];
-    layer1(items, n_items, P, wave_pix, K, color, W1, b1, H);
-    // dH^T = W2^T dlogits^T: A = W2^T (i = hidden l%32 + 32 hb, k = class 8 ks + 4 (l/32) + 0..3)
-    v16f dH[2][2];
+  ChunkCursor cur;
+  cur.item = 0;
+  cur.first = 0;
+  cur.end = item_chunks(items[0]);
+  for (int64_t chunk = (int64_t)blockIdx.x * 4 + wave;; chunk += (int64_t)gridDim.x * 4) {
+    if (!seek_chunk(items, n_items, chunk, cur)) break;
+    const gs_item it = items[cur.item];
+    const int64_t HW = (int64_t)it.W * it.H;
+    const int64_t local0 = (chunk - cur.first) * 64;
+    const int nlive = (int)min((int64_t)64, HW - local0);
+    const float* Eb = color + it.pixel_base * K + 4 * HW + local0;    // plane d at Eb + d HW
+    float* dEb = gcolor + it.pixel_base * K + 4 * HW + local0;
+    {
+      // stage: lane = pixel, one coalesced row per class; dead pixels are zero
+      const bool live = lane < nlive;
+      const float* g = glogits + it.pixel_base * C + local0 + min(lane, nlive - 1);
+      for (int c = 0; c < C; ++c) {
+        const float v = g[(int64_t)c * HW];
+        sg[c * kGst + lane] = live ? v : 0.0f;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+#pragma unroll 1
+    for (int pb = 0; pb < 2; ++pb) {
+      const int q = l32 + 32 * pb;
+      const bool qlive = q < nlive;
+      const float* Eq = Eb + 4 * half * HW + min(q, nlive - 1);   // plane 8 ks + 4 half + j at Eq + (8 ks + j) HW
+      const float* Gq = sg + 4 * half * kGst + q;                 // class 8 ks + 4 half + j at Gq + (8 ks + j) kGst
+      // (1) E with d in registers, pixels across lanes; the sign of the hidden pre-activations
+      v4s ehi[2], elo[2];
 #pragma unroll
-    for (int hb = 0; hb < 2; ++hb)
-#pragma unroll
-      for (int pb = 0; pb < 2; ++pb) dH[hb][pb] = zero16();
-    PixelRef prc[2];
-#pragma unroll
-    for (int pb = 0; pb < 2; ++pb) prc[pb] = pixel_ref(items, n_items, P, wave_pix + (lane & 31) + 32 * pb, C);
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-      v4s a[2];
-#pragma unroll
-      for (int hb = 0; hb < 2; ++hb)
+      for (int ks = 0; ks < 2; ++ks) {
+        float e[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int cls = 8 * ks + 4 * (lane >> 5) + j;
-          a[hb][j] = cls < C ? (short)W2[(int64_t)cls * kHid + (lane & 31) + 32 * hb] : (short)0;
+          const float v = Eq[(8 * ks + j) * HW];
+          e[j] = qlive ? v : 0.0f;
         }
+        split4(e, ehi[ks], elo[ks]);
+      }
+      uint32_t on[2];   // bit r: hidden unit drow(r) + 32 hb is active at this pixel
 #pragma unroll
-      for (int pb = 0; pb < 2; ++pb) {
+      for (int hb = 0; hb < 2; ++hb) {
+        v16f h;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) h[r] = s_b1[drow(r, lane) + 32 * hb];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          h = mfma(w1a[hb][ks], ehi[ks], h);
+          h = mfma(w1a[hb][ks], elo[ks], h);
+        }
+        uint32_t bits = 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) bits |= (h[r] > 0.0f ? 1u : 0u) << r;
+        on[hb] = bits;
+      }
+
+      // (2) dH^T = W2^T dlogits^T: A = W2^T (i = hidden l32 + 32 hb, k = class 8 ks + 4 half + j)
+      v16f dHT[2] = {zero16(), zero16()};
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
         float x[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int cls = 8 * ks + 4 * (lane >> 5) + j;
-          x[j] = (prc[pb].live && cls < C) ? glogits[prc[pb].base + cls * prc[pb].HW] : 0.0f;
-        }
+        for (int j = 0; j < 4; ++j) x[j] = Gq[(8 * ks + j) * kGst];
         v4s hi, lo;
         split4(x, hi, lo);
 #pragma unroll
         for (int hb = 0; hb < 2; ++hb) {
-          dH[hb][pb] = mfma(a[hb], hi, dH[hb][pb]);
-          dH[hb][pb] = mfma(a[hb], lo, dH[hb][pb]);
+          const v4s a = *reinterpret_cast<const v4s*>(s_w2t + (l32 + 32 * hb) * kWtStride + 8 * ks + 4 * half);
+          dHT[hb] = mfma(a, hi, dHT[hb]);
+          dHT[hb] = mfma(a, lo, dHT[hb]);
         }
       }
-    }
-    // ReLU' (0 at 0) and the activations h
 #pragma unroll
-    for (int hb = 0; hb < 2; ++hb)
+      for (int hb = 0; hb < 2; ++hb)
 #pragma unroll
-      for (int pb = 0; pb < 2; ++pb)
+        for (int r = 0; r < 16; ++r) dHT[hb][r] = ((on[hb] >> r) & 1u) ? dHT[hb][r] : 0.0f;
+
+      // (3) dE^T = W1^T dH^T: A = W1^T (i = d l32, k = hidden 8 ks + 4 half + j); B from the
+      // dH^T registers 4 (ks % 4) .. +3 of block ks / 4
+      {
+        v16f dE = zero16();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const bool on = H[hb][pb][r] > 0.0f;
-          dH[hb][pb][r] = on ? dH[hb][pb][r] : 0.0f;
-          H[hb][pb][r] = on ? H[hb][pb][r] : 0.0f;
-        }
-    // dE^T = W1^T dH^T: A = W1^T (i = d l%32, k = hidden 8 ks + 4 (l/32) + 0..3)
-    {
-      v16f dE[2] = {zero16(), zero16()};
-      const int d = lane & 31;
+        for (int ks = 0; ks < 8; ++ks) {
+          v4s a = {0, 0, 0, 0};
+          if (l32 < kDin) a = *reinterpret_cast<const v4s*>(s_w1t + l32 * kWtStride + 8 * ks + 4 * half);
+          float x[4];
 #pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        v4s a;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          a[j] = d < kDin ? (short)W1[(8 * ks + 4 * (lane >> 5) + j) * kDin + d] : (short)0;
-#pragma unroll
-        for (int pb = 0; pb < 2; ++pb) {
+          for (int j = 0; j < 4; ++j) x[j] = dHT[ks >> 2][4 * (ks & 3) + j];
           v4s hi, lo;
-          hidden_operand(dH, pb, ks, hi, lo);
-          dE[pb] = mfma(a, hi, dE[pb]);
-          dE[pb] = mfma(a, lo, dE[pb]);
+          split4(x, hi, lo);
+          dE = mfma(a, hi, dE);
+          dE = mfma(a, lo, dE);
+        }
+        if (qlive)
+#pragma unroll
+          for (int r = 0; r < 8; ++r) dEb[(int64_t)drow(r, lane) * HW + q] = dE[r];   // rows 0..15 = d
+      }
+
+      // Reloading from LDS below is cheaper than keeping (2)'s operands alive through (3).
+      asm volatile("" ::: "memory");
+      // (4) H with pixels in registers: A = E (i = pixel), B = W1^T (k = d, j = hidden l32 + 32 hb)
+      v16f H[2];
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb) {
+        H[hb] = zero16();
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          H[hb] = mfma(ehi[ks], w1a[hb][ks], H[hb]);
+          H[hb] = mfma(elo[ks], w1a[hb][ks], H[hb]);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) H[hb][r] = fmaxf(H[hb][r] + b1l[hb], 0.0f);
+      }
+      // (5a) dW2[c][h] += sum_p dlogits[c][p] relu(H)[p][h] over the half's pixels
+      // p = 32 pb + 8 kk + 4 half + j (registers 4 kk + j): A = dlogits (i = class l32 + 32 cb, k = p)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int p0 = 32 * pb + 8 * kk + 4 * half;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          float x[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) x[j] = sg[(l32 + 32 * cb) * kGst + p0 + j];
+          aB2[cb] += (x[0] + x[1]) + (x[2] + x[3]);
+          v4s ahi, alo;
+          split4(x, ahi, alo);
+#pragma unroll
+          for (int hb = 0; hb < 2; ++hb) {
+            float y[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) y[j] = H[hb][4 * kk + j];
+            v4s bhi, blo;
+            split4(y, bhi, blo);
+            aW2[cb][hb] = mfma(ahi, bhi, aW2[cb][hb]);
+            aW2[cb][hb] = mfma(ahi, blo, aW2[cb][hb]);
+            aW2[cb][hb] = mfma(alo, bhi, aW2[cb][hb]);
+          }
         }
       }
+      uint32_t onH[2];   // bit r: hidden unit l32 + 32 hb is active at pixel drow(r) of the half
 #pragma unroll
-      for (int pb = 0; pb < 2; ++pb) {
-        const PixelRef pr = pixel_ref(items, n_items, P, wave_pix + (lane & 31) + 32 * pb, K);
-        if (!pr.live) continue;
+      for (int hb = 0; hb < 2; ++hb) {
+        uint32_t bits = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int dd = drow(r, lane);
-          if (dd < kDin) gcolor[pr.base + (4 + dd) * pr.HW] = dE[pb][r];
-        }
+        for (int r = 0; r < 16; ++r) bits |= (H[hb][r] > 0.0f ? 1u : 0u) << r;
+        onH[hb] = bits;
       }
-    }
-    // Weight gradients, contractions over the wave's pixels (k = pixel 8 ks + 4 (l/32) + 0..3).
-    // dW2[c][h] = sum_p dlogits[c][p] h[h][p]; db2[c] = sum_p dlogits[c][p]
-    store_T(sh, H);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const int cls = (lane & 31) + 32 * cb;
-      v16f dW[2] = {zero16(), zero16()};
-      v16f dB = zero16();
-      v4s ones;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) ones[j] = (short)0x3F80;   // bfloat16 1.0
+      // (4b) dH with pixels in registers: A = dlogits (i = pixel, k = class), B = W2 (j = hidden)
+      v16f dH[2] = {zero16(), zero16()};
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
         float x[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const PixelRef pr = pixel_ref(items, n_items, P, wave_pix + 8 * ks + 4 * (lane >> 5) + j, C);
-          x[j] = (pr.live && cls < C) ? glogits[pr.base + cls * pr.HW] : 0.0f;
-        }
-        v4s ahi, alo;
-        split4(x, ahi, alo);
+        for (int j = 0; j < 4; ++j) x[j] = Gq[(8 * ks + j) * kGst];
+        v4s hi, lo;
+        split4(x, hi, lo);
 #pragma unroll
         for (int hb = 0; hb < 2; ++hb) {
-          float y[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) y[j] = sh[((lane & 31) + 32 * hb) * 65 + 8 * ks + 4 * (lane >> 5) + j];
-          v4s bhi, blo;
-          split4(y, bhi, blo);
-          dW[hb] = mfma(ahi, bhi, dW[hb]);
-          dW[hb] = mfma(ahi, blo, dW[hb]);
-          dW[hb] = mfma(alo, bhi, dW[hb]);
+          const v4s b = *reinterpret_cast<const v4s*>(s_w2t + (l32 + 32 * hb) * kWtStride + 8 * ks + 4 * half);
+          dH[hb] = mfma(hi, b, dH[hb]);
+          dH[hb] = mfma(lo, b, dH[hb]);
         }
-        dB = mfma(ahi, ones, dB);
-        dB = mfma(alo, ones, dB);
       }
-      // D[c][h]: lane holds h = l%32 + 32 hb, c = drow(r, l) + 32 cb
 #pragma unroll
       for (int hb = 0; hb < 2; ++hb)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int c = drow(r, lane) + 32 * cb;
-          atomicAdd(&s_acc[c * 64 + (lane & 31) + 32 * hb], dW[hb][r]);
-        }
-      if ((lane & 31) == 0)
+        for (int r = 0; r < 16; ++r) dH[hb][r] = ((onH[hb] >> r) & 1u) ? dH[hb][r] : 0.0f;
+      // (5b) dW1[h][d] += sum_p dH[p][h] [E, 1][p][d]: A = dH (i = hidden l32 + 32 hb, k = p), B = [E, 1] (j = d l32)
+      const float* Ed = Eb + (int64_t)min(l32, kDin - 1) * HW;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) atomicAdd(&s_acc[kPartW2 + kPartW1 + drow(r, lane) + 32 * cb], dB[r]);
-    }
-    // dW1[h][d] = sum_p dH[h][p] E[p][d]; column d = 16 carries db1 (E extended by a one)
-    __builtin_amdgcn_wave_barrier();
-    store_T(sh, dH);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    {
-      v16f dW[2] = {zero16(), zero16()};
-      const int d = lane & 31;
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
+      for (int kk = 0; kk < 4; ++kk) {
+        const int p0 = 32 * pb + 8 * kk + 4 * half;
         float e[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int64_t pix = wave_pix + 8 * ks + 4 * (lane >> 5) + j;
-          const PixelRef pr = pixel_ref(items, n_items, P, pix, K);
-          e[j] = !pr.live ? 0.0f : (d < kDin ? color[pr.base + (4 + d) * pr.HW] : (d == kDin ? 1.0f : 0.0f));
+          const float v = Ed[min(p0 + j, nlive - 1)];
+          e[j] = p0 + j >= nlive ? 0.0f : (l32 < kDin ? v : (l32 == kDin ? 1.0f : 0.0f));
         }
         v4s bhi, blo;
         split4(e, bhi, blo);
@@ -351,34 +435,60 @@ __global__ __launch_bounds__(256) void k_head_bwd(const gs_item* __restrict__ it
         for (int hb = 0; hb < 2; ++hb) {
           float y[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) y[j] = sh[((lane & 31) + 32 * hb) * 65 + 8 * ks + 4 * (lane >> 5) + j];
+          for (int j = 0; j < 4; ++j) y[j] = dH[hb][4 * kk + j];
           v4s ahi, alo;
           split4(y, ahi, alo);
-          dW[hb] = mfma(ahi, bhi, dW[hb]);
-          dW[hb] = mfma(ahi, blo, dW[hb]);
-          dW[hb] = mfma(alo, bhi, dW[hb]);
+          aW1[hb] = mfma(ahi, bhi, aW1[hb]);
+          aW1[hb] = mfma(ahi, blo, aW1[hb]);
+          aW1[hb] = mfma(alo, bhi, aW1[hb]);
         }
       }
-      // D[h][d]: lane holds d = l%32, h = drow(r, l) + 32 hb
-#pragma unroll
-      for (int hb = 0; hb < 2; ++hb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) atomicAdd(&s_acc[kPartW2 + (drow(r, lane) + 32 * hb) * 32 + d], dW[hb][r]);
     }
+    // every lane is past this chunk's reads of the staged rows before the next chunk writes them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  // sum the four waves' accumulators and write the block's partial
+  float* s_acc = s_buf;
+  __syncthreads();
+  for (int i = threadIdx.x; i < kPart; i += 256) s_acc[i] = 0.0f;
+  __syncthreads();
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int c = drow(r, lane) + 32 * cb;   // D[c][h]: h = l32 + 32 hb
+        atomicAdd(&s_acc[c * 64 + l32 + 32 * hb], aW2[cb][hb][r]);
+      }
+    atomicAdd(&s_acc[kPartW2 + kPartW1 + l32 + 32 * cb], aB2[cb]);
+  }
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) atomicAdd(&s_acc[kPartW2 + (drow(r, lane) + 32 * hb) * 32 + l32], aW1[hb][r]);
   __syncthreads();
   float* out = partial + (int64_t)blockIdx.x * kPart;
   for (int i = threadIdx.x; i < kPart; i += 256) out[i] = s_acc[i];
 }
 
-// Sums the per-block partials into the head's weight gradients.
-__global__ void k_head_reduce(const float* __restrict__ partial, int n_blocks, int C, float* __restrict__ gW1,
-                              float* __restrict__ gb1, float* __restrict__ gW2, float* __restrict__ gb2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kPart) return;
+// Sums the per-block partials into the head's weight gradients: block = 64 columns,
+// four thread groups over interleaved partials, combined in LDS.
+__global__ __launch_bounds__(256) void k_head_reduce(const float* __restrict__ partial, int n_blocks, int C,
+                                                     float* __restrict__ gW1, float* __restrict__ gb1,
+                                                     float* __restrict__ gW2, float* __restrict__ gb2) {
+  __shared__ float s_sum[4][64];
+  const int col = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + col;
   float s = 0.0f;
-  for (int b = 0; b < n_blocks; ++b) s += partial[(int64_t)b * kPart + i];
+  if (i < kPart)
+    for (int b = grp; b < n_blocks; b += 4) s += partial[(int64_t)b * kPart + i];
+  s_sum[grp][col] = s;
+  __syncthreads();
+  if (grp != 0 || i >= kPart) return;
+  s = (s_sum[0][col] + s_sum[1][col]) + (s_sum[2][col] + s_sum[3][col]);
   if (i < kPartW2) {
     const int c = i / 64, h = i % 64;
     if (c < C) gW2[c * kHid + h] = s;
@@ -411,10 +521,11 @@ int launch_head_bwd(const gs_item* items, int n_items, int64_t P, int K, const g
                     const float* glogits, float* gcolor, float* partial, float* gW1, float* gb1, float* gW2, float* gb2,
                     hipStream_t s) {
   if (P == 0) return GS_OK;
-  const int blocks = (int)std::min<int64_t>(kHeadBlocksMax, ceil_div(P, 256));
-  hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(256), 0, s, items, n_items, P, K, h.n_classes, color, glogits, h.W1,
+  // at most one 64-pixel chunk per item is partial, so P / 64 + n_items bounds the chunk count
+  const int blocks = (int)std::min<int64_t>(kHeadBlocksMax, ceil_div(ceil_div(P, 64) + n_items, 4));
+  hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(256), 0, s, items, n_items, K, h.n_classes, color, glogits, h.W1,
                      h.b1, h.W2, gcolor, partial);
-  hipLaunchKernelGGL(k_head_reduce, dim3((unsigned)ceil_div(kPart, 256)), dim3(256), 0, s, partial, blocks, h.n_classes,
+  hipLaunchKernelGGL(k_head_reduce, dim3((unsigned)ceil_div(kPart, 64)), dim3(256), 0, s, partial, blocks, h.n_classes,
                      gW1, gb1, gW2, gb2);
   return launch_status();
 }

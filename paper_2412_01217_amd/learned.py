@@ -6,9 +6,10 @@ semantic features directly, eq. 9; the learned form replaces the C-wide feature 
 Training objective (a reading, the paper has no learned head): soft-target
 cross-entropy of the decoded logits against the plain render plus 0.1 times their
 mean squared difference; Adam, lr 1e-3 for the MLP and 1e-2 for the embeddings; one
-random view (with its pyramid) per step. Forward, backward, loss and optimizer all run
-in the library's kernels; geometry is held fixed, so each view's projection and
-binning are computed once.
+random view (with its pyramid) per step, either drawn from a fixed pool or generated
+fresh for every step so that every Gaussian is eventually seen. Forward, backward,
+loss and optimizer all run in the library's kernels; geometry is held fixed, so a
+pooled view's projection and binning are computed once.
 """
 from __future__ import annotations
 
@@ -74,6 +75,9 @@ class ViewState:
 
 
 class Trainer:
+    """views: a list (a pool, one drawn at random per step) or a callable step -> View
+    (a fresh view per step)."""
+
     def __init__(self, scene, views, n_classes: int, device="cuda", seed=6000):
         self.device = torch.device(device)
         self.C = n_classes
@@ -87,10 +91,14 @@ class Trainer:
         self.g_learned = {k: v for k, v in g.items() if k != "sem"}
         self.head = Head(n_classes, device, seed)
         self.n = scene.n
-        self.views = [ViewState(self.cfg_plain, self.cfg_learned, v, self.g_plain, self.g_learned, self.n, n_classes,
-                                self.head, self.device) for v in views]
+        self.view_fn = views if callable(views) else None
+        self.views = [] if callable(views) else [self._state(v) for v in views]
         self.rng = np.random.default_rng(seed)
         self.t = 0
+
+    def _state(self, view) -> ViewState:
+        return ViewState(self.cfg_plain, self.cfg_learned, view, self.g_plain, self.g_learned, self.n, self.C,
+                         self.head, self.device)
 
     def forward(self, vs: ViewState):
         raster.render_fwd(self.cfg_learned, self.g_learned, vs.proj, vs.fr, vs.sorter, out=vs.img,
@@ -99,7 +107,10 @@ class Trainer:
     def train(self, steps: int, lr_mlp=1e-3, lr_emb=1e-2, mse_w=0.1):
         losses = []
         for _ in range(steps):
-            vs = self.views[int(self.rng.integers(len(self.views)))]
+            if self.view_fn is not None:
+                vs = self._state(self.view_fn(self.t))
+            else:
+                vs = self.views[int(self.rng.integers(len(self.views)))]
             self.forward(vs)
             raster.distill_loss(vs.fr, self.C, vs.teacher, vs.img["logits"], mse_w, grad=vs.grad["logits"],
                                 loss_out=vs.loss, ws=vs.dws)
@@ -117,8 +128,7 @@ class Trainer:
         agree = total = 0
         se = n = 0.0
         for v in views:
-            vs = ViewState(self.cfg_plain, self.cfg_learned, v, self.g_plain, self.g_learned, self.n, self.C,
-                           self.head, self.device)
+            vs = self._state(v)
             self.forward(vs)
             counts = raster.argmax_agreement(vs.fr, self.C, vs.teacher, vs.img["logits"])
             agree += int(counts.sum().item())
