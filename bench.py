@@ -289,7 +289,7 @@ def main():
     ap.add_argument("--workload", default="room", choices=("room", "batch", "learned", "large"))
     ap.add_argument("--quick", action="store_true", help="only the default workload (no batch / learned reports)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variant", type=int, default=0, help="render kernels: 0 auto, 1 VALU, 2 MFMA")
+    ap.add_argument("--variant", type=int, default=0, help="render kernels: 0 auto (3), 1 VALU, 2 FP32 matrix cores, 3 split-bf16 matrix cores")
     ap.add_argument("--eager", action="store_true", help="time eager calls instead of graph replays")
     ap.add_argument("--train-steps", type=int, default=2000)
     args = ap.parse_args()

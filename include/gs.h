@@ -56,7 +56,9 @@ typedef struct gs_config {
   float guard;             /* 1.3: x/z, y/z clamped to +-guard*(W/2)/fx inside J */
   int32_t full_rect;       /* 0; 1 = every Gaussian covers every tile of its item */
   int32_t n_sem;           /* composited semantic channels, 0..60 (plain: classes; learned: 16) */
-  int32_t variant;         /* render kernels: 0 automatic, 1 per-lane FMA (VALU), 2 matrix cores (MFMA) */
+  int32_t variant;         /* render kernels: 0 automatic (= 3), 1 per-lane FMA (VALU), 2 single-precision
+                              matrix cores, 3 bfloat16 matrix cores with hi/lo split operands
+                              (single-precision accurate to about 2^-16 relative) */
   int32_t tile_order;      /* 0: coarse pyramid levels (longest tile lists) launched first; 1: item order */
 } gs_config;
 

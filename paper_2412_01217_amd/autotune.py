@@ -1,8 +1,8 @@
 """Autotuner for the batched mapping step.
 
 For one workload signature (Gaussian count, channels, items, pixels, tiles) it times
-each candidate launch configuration -- render kernel variant (per-lane FMA or matrix
-core) and tile launch order (coarse pyramid levels first, or item order) -- as HIP
+each candidate launch configuration -- render kernel variant (per-lane FMA, single-precision
+or split-bfloat16 matrix cores) and tile launch order (coarse pyramid levels first, or item order) -- as HIP
 graph replays of the whole step, keeps the fastest, and caches the choice in a JSON
 file (GS_AUTOTUNE_CACHE, default ~/.cache/gs_autotune.json) keyed by device and
 signature. Every candidate computes the same result; only the schedule differs.
@@ -14,7 +14,8 @@ import os
 
 import torch
 
-CANDIDATES = ({"variant": 2, "tile_order": 0}, {"variant": 2, "tile_order": 1}, {"variant": 1, "tile_order": 1})
+CANDIDATES = ({"variant": 3, "tile_order": 0}, {"variant": 3, "tile_order": 1}, {"variant": 2, "tile_order": 0},
+              {"variant": 1, "tile_order": 1})
 
 
 def cache_path() -> str:

@@ -33,15 +33,19 @@ int launch_render_fwd_valu(GS_RENDER_FWD_ARGS);
 int launch_render_bwd_valu(GS_RENDER_BWD_ARGS);
 int launch_render_fwd_mfma(GS_RENDER_FWD_ARGS);
 int launch_render_bwd_mfma(GS_RENDER_BWD_ARGS);
+int launch_render_fwd_split(GS_RENDER_FWD_ARGS);
+int launch_render_bwd_split(GS_RENDER_BWD_ARGS);
 
-// Render kernel variants: 1 = per-lane FMA accumulation (VALU), 2 = matrix-core channel
-// contraction (MFMA). 0 picks MFMA.
+// Render kernel variants: 1 = per-lane FMA accumulation (VALU), 2 = single-precision
+// matrix-core channel contraction, 3 = every contraction on the bfloat16 matrix cores with
+// hi/lo split operands. 0 picks 3.
 int launch_render_fwd(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
                       int n_items, int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& out,
                       hipStream_t s) {
   if (n_tiles == 0) return GS_OK;
   if (cfg.variant == 1) return launch_render_fwd_valu(cfg, g, p, items, n_items, n_tiles, vals, ranges, out, s);
-  return launch_render_fwd_mfma(cfg, g, p, items, n_items, n_tiles, vals, ranges, out, s);
+  if (cfg.variant == 2) return launch_render_fwd_mfma(cfg, g, p, items, n_items, n_tiles, vals, ranges, out, s);
+  return launch_render_fwd_split(cfg, g, p, items, n_items, n_tiles, vals, ranges, out, s);
 }
 int launch_render_bwd(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
                       int n_items, int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& fwd,
@@ -49,7 +53,9 @@ int launch_render_bwd(const gs_config& cfg, const gs_gaussians& g, const gs_proj
   if (n_tiles == 0) return GS_OK;
   if (cfg.variant == 1)
     return launch_render_bwd_valu(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
-  return launch_render_bwd_mfma(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
+  if (cfg.variant == 2)
+    return launch_render_bwd_mfma(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
+  return launch_render_bwd_split(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
 }
 int launch_loss(const gs_item*, int, int64_t, int, int, const float*, const float*, const gs_targets&, const float*,
                 float*, float*, float*, float*, hipStream_t);
@@ -74,7 +80,7 @@ bool cfg_ok(const gs_config* c) {
   if (!(c->z_near > 0.0f) || !(c->eps_dilate >= 0.0f) || !(c->alpha_min >= 0.0f)) return false;
   if (!(c->alpha_max > c->alpha_min) || !(c->alpha_max < 1.0f) || !(c->t_min >= 0.0f) || !(c->guard > 0.0f)) return false;
   if (c->n_sem < 0 || c->n_sem > 60) return false;
-  if (c->variant < 0 || c->variant > 2) return false;
+  if (c->variant < 0 || c->variant > 3) return false;
   if (c->tile_order < 0 || c->tile_order > 1) return false;
   return true;
 }

@@ -53,6 +53,61 @@ __device__ __forceinline__ float footprint_power(float px, float py, float mhx, 
   return fminf(p, 0.0f);
 }
 
+// DPP lane moves within a row of 16 lanes.
+__device__ __forceinline__ float dpp_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_xor2(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_half_mirror(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_mirror(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));
+}
+// Sum over the 16 lanes of each DPP row; every lane of the row receives the sum.
+__device__ __forceinline__ float row_sum16(float v) {
+  v += dpp_xor1(v);
+  v += dpp_xor2(v);
+  v += dpp_half_mirror(v);
+  v += dpp_mirror(v);
+  return v;
+}
+
+// One 16x16 tile of one item, as a render block sees it.
+struct Ctx {
+  int item, tx, ty;
+  int W, H;
+  int64_t HW, pixel_base;
+  uint32_t start, end;
+};
+
+// Tiles are launched coarse pyramid levels first: their lists are the longest, and
+// starting them early lets the many short fine-level tiles fill in around them.
+__device__ __forceinline__ Ctx make_ctx(const gs_item* items, int n_items, const uint32_t* ranges, int order) {
+  Ctx c;
+  const int tile = order ? (int)blockIdx.x : (int)gridDim.x - 1 - (int)blockIdx.x;
+  c.item = item_of_tile(items, n_items, tile);
+  const gs_item it = items[c.item];
+  const int lt = tile - it.tile_base;
+  c.tx = lt % it.tiles_x;
+  c.ty = lt / it.tiles_x;
+  c.W = it.W;
+  c.H = it.H;
+  c.HW = (int64_t)it.W * it.H;
+  c.pixel_base = it.pixel_base;
+  c.start = ranges[2 * (int64_t)tile];
+  c.end = ranges[2 * (int64_t)tile + 1];
+  return c;
+}
+
+// Tile-local pixel index t (0..255, row-major in the 16x16 tile) -> image coordinates.
+__device__ __forceinline__ void tile_pixel(const Ctx& c, int t, int& u, int& v) {
+  u = c.tx * kTile + (t & 15);
+  v = c.ty * kTile + (t >> 4);
+}
+
 __device__ __forceinline__ float fast_exp(float x) { return __expf(x); }
 
 // Wave64 helpers.

@@ -36,59 +36,6 @@ struct MShape {
 
 __device__ __forceinline__ int mfma_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-__device__ __forceinline__ float dpp_xor1(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float dpp_xor2(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float dpp_half_mirror(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float dpp_mirror(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));
-}
-// Sum over the 16 lanes of each DPP row; every lane of the row receives the sum.
-__device__ __forceinline__ float row_sum16(float v) {
-  v += dpp_xor1(v);
-  v += dpp_xor2(v);
-  v += dpp_half_mirror(v);
-  v += dpp_mirror(v);
-  return v;
-}
-
-struct Ctx {
-  int item, tx, ty;
-  int W, H;
-  int64_t HW, pixel_base;
-  uint32_t start, end;
-};
-
-// Tiles are launched coarse pyramid levels first: their lists are the longest, and
-// starting them early lets the many short fine-level tiles fill in around them.
-__device__ __forceinline__ Ctx make_ctx(const gs_item* items, int n_items, const uint32_t* ranges, int order) {
-  Ctx c;
-  const int tile = order ? (int)blockIdx.x : (int)gridDim.x - 1 - (int)blockIdx.x;
-  c.item = item_of_tile(items, n_items, tile);
-  const gs_item it = items[c.item];
-  const int lt = tile - it.tile_base;
-  c.tx = lt % it.tiles_x;
-  c.ty = lt / it.tiles_x;
-  c.W = it.W;
-  c.H = it.H;
-  c.HW = (int64_t)it.W * it.H;
-  c.pixel_base = it.pixel_base;
-  c.start = ranges[2 * (int64_t)tile];
-  c.end = ranges[2 * (int64_t)tile + 1];
-  return c;
-}
-
-// Tile-local pixel index t (0..255, row-major in the 16x16 tile) -> image coordinates.
-__device__ __forceinline__ void tile_pixel(const Ctx& c, int t, int& u, int& v) {
-  u = c.tx * kTile + (t & 15);
-  v = c.ty * kTile + (t >> 4);
-}
-
 // Batch staging, double-buffered through registers: thread t stages Gaussian q = t / 8
 // of the batch, channels [(t % 8) * CPT, +CPT) of its features and, for t % 8 < 2,
 // half of its 8-float record. fetch() issues the global loads; commit() writes LDS.

@@ -1,0 +1,514 @@
+// Tile compositing (eq. 7-9) and its reverse pass, with every dense contraction on the
+// bfloat16 matrix cores of gfx950 (v_mfma_f32_16x16x32_bf16, 2.5 PFLOP/s) and single
+// precision kept by splitting each operand x = hi + lo, hi = bf16(x), lo = bf16(x - hi):
+//   a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi      (relative error about 2^-16)
+//
+// Forward, per batch of 32 depth-ordered Gaussians and per wave of 64 pixels:
+//   each lane runs its pixel's transmittance recurrence and writes w[p][i] = alpha_i T_i
+//   to LDS, then out^T[c][p] += sum_i F^T[c][i] W^T[i][p] on the matrix cores.
+// Backward, per batch (back to front):
+//   GF^T[i][p] = sum_c F[i][c] G^T[c][p]  (g . f of every pixel-Gaussian pair) on the
+//     single-precision matrix cores (v_mfma_f32_16x16x4f32: it decides dL/dalpha, in
+//     which terms cancel); a 4x4 block transpose across lane rows (permlane swaps) hands every
+//     lane its own pixel's 32 values;
+//   each lane runs the reverse recurrence (T recovered with the reciprocal of 1 - alpha)
+//     and writes w[i][p] to LDS, Gaussian-major;
+//   dF[i][c] = sum_p W^T[i][p] G[p][c]                       (feature gradients)
+//   the 2D mean, conic and opacity gradients are summed per pair in single precision
+//   (row sums over 16 lanes, then over rows and waves in LDS): expanding them into
+//   moments about a fixed centre would lose accuracy for compact Gaussians.
+//
+// 16x16x32 bf16 operand layout (lane l, verified on the device):
+//   A[i][k]: i = l % 16, k = 8 (l / 16) + 0..7     B[k][j]: k = 8 (l / 16) + 0..7, j = l % 16
+//   D[i][j]: j = l % 16, i = 4 (l / 16) + r, r = 0..3
+#include "common.h"
+
+namespace gs {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+constexpr int kB = 32;          // Gaussians per batch
+constexpr int kWs = kB + 4;     // dword stride of a pixel-major row of 32 Gaussians
+constexpr int kPs = 64 + 4;     // dword stride of a Gaussian-major row of a wave's 64 pixels
+
+template <int NS>
+struct SShape {
+  static constexpr int K = 4 + NS;
+  static constexpr int KP = (K + 31) / 32 * 32;   // channels padded to whole 32-wide k-steps
+  static constexpr int KS = KP / 32;
+  static constexpr int CB = KP / 16;              // 16-channel blocks
+  static constexpr int CPT = KP / 8;              // channels staged per thread
+  static constexpr int FST = KP + 4;              // dword stride of a Gaussian-major feature row
+};
+
+// x -> (bf16(x) << 16) | bf16(x - bf16(x))
+__device__ __forceinline__ uint32_t pack_hl(float x) {
+  const float h = (float)(__bf16)x;
+  const bf2 v = __builtin_convertvector((f2){x - h, x}, bf2);
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// Eight packed values -> the hi and lo bfloat16 operands.
+__device__ __forceinline__ void unpack8(const uint4 a, const uint4 b, v8bf& hi, v8bf& lo) {
+  const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  uint4 h, l;
+  h.x = __builtin_amdgcn_perm(d[1], d[0], 0x07060302u);
+  h.y = __builtin_amdgcn_perm(d[3], d[2], 0x07060302u);
+  h.z = __builtin_amdgcn_perm(d[5], d[4], 0x07060302u);
+  h.w = __builtin_amdgcn_perm(d[7], d[6], 0x07060302u);
+  l.x = __builtin_amdgcn_perm(d[1], d[0], 0x05040100u);
+  l.y = __builtin_amdgcn_perm(d[3], d[2], 0x05040100u);
+  l.z = __builtin_amdgcn_perm(d[5], d[4], 0x05040100u);
+  l.w = __builtin_amdgcn_perm(d[7], d[6], 0x05040100u);
+  hi = __builtin_bit_cast(v8bf, h);
+  lo = __builtin_bit_cast(v8bf, l);
+}
+
+__device__ __forceinline__ void load_op(const uint32_t* p, v8bf& hi, v8bf& lo) {
+  const uint4 a = *reinterpret_cast<const uint4*>(p);
+  const uint4 b = *reinterpret_cast<const uint4*>(p + 4);
+  unpack8(a, b, hi, lo);
+}
+
+// Splits eight floats into hi and lo operands.
+__device__ __forceinline__ void split8(const float* x, v8bf& hi, v8bf& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    hi[e] = h;
+    lo[e] = (__bf16)(x[e] - (float)h);
+  }
+}
+
+__device__ __forceinline__ v4f mma(v8bf a, v8bf b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ v4f mma3(v8bf ah, v8bf al, v8bf bh, v8bf bl, v4f c) {
+  c = mma(ah, bh, c);
+  c = mma(ah, bl, c);
+  c = mma(al, bh, c);
+  return c;
+}
+__device__ __forceinline__ v4f zero4() { return (v4f){0.0f, 0.0f, 0.0f, 0.0f}; }
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Batch staging, double-buffered through registers: thread t stages Gaussian q = t / 8
+// of the batch, channels [(t % 8) CPT, +CPT) of its features and, for t % 8 < 2, half of
+// its 8-float record.
+template <int NS>
+struct SStage {
+  static constexpr int CPT = SShape<NS>::CPT;
+  float4 r;
+  float f[CPT];
+
+  __device__ __forceinline__ void fetch(const uint32_t* __restrict__ vals, uint32_t b, int cnt, int item, int64_t n,
+                                        const float* __restrict__ rec, const float* __restrict__ depth,
+                                        const float* __restrict__ rgb, const float* __restrict__ sem,
+                                        const uint16_t* __restrict__ emb, int n_sem) {
+    const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
+    const bool live = q < cnt;
+    const uint32_t g = live ? vals[b + q] : 0u;
+    const int64_t e = (int64_t)item * n + g;
+    r = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (live && part < 2) r = reinterpret_cast<const float4*>(rec + kRecFloats * e)[part];
+    const int Kr = 4 + n_sem;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int k = part * CPT + j;
+      float v = 0.0f;
+      if (live && k < Kr) {
+        if (k < 3) v = rgb[3 * (int64_t)g + k];
+        else if (k == 3) v = depth[e];
+        else if (emb) v = __uint_as_float((uint32_t)emb[(int64_t)n_sem * g + (k - 4)] << 16);
+        else v = sem[(int64_t)n_sem * g + (k - 4)];
+      }
+      f[j] = v;
+    }
+  }
+  // features Gaussian-major, single precision: s_f[q][c]
+  __device__ __forceinline__ void commit_rows(float4* s_rec, float* s_f) const {
+    const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
+    if (part < 2) s_rec[2 * q + part] = r;
+    float* dst = s_f + q * SShape<NS>::FST + part * CPT;
+#pragma unroll
+    for (int j = 0; j < CPT; j += 4) *reinterpret_cast<float4*>(dst + j) = make_float4(f[j], f[j + 1], f[j + 2], f[j + 3]);
+  }
+  // features channel-major: s_f[c][q]
+  __device__ __forceinline__ void commit_cols(float4* s_rec, uint32_t* s_f) const {
+    const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
+    if (part < 2) s_rec[2 * q + part] = r;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) s_f[(part * CPT + j) * kWs + q] = pack_hl(f[j]);
+  }
+};
+
+// ------------------------------------------------------------------------- forward
+template <int NS>
+__global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, const float* __restrict__ rgb,
+                                                          const float* __restrict__ sem,
+                                                          const uint16_t* __restrict__ emb, int n_sem,
+                                                          const float* __restrict__ rec,
+                                                          const float* __restrict__ depth, int64_t n,
+                                                          const gs_item* __restrict__ items, int n_items,
+                                                          const uint32_t* __restrict__ vals,
+                                                          const uint32_t* __restrict__ ranges, float* __restrict__ color,
+                                                          float* __restrict__ Tout, uint32_t* __restrict__ ncout) {
+  using S = SShape<NS>;
+  constexpr int CB = S::CB, KP = S::KP;
+  __shared__ float4 s_rec[2 * kB];
+  __shared__ uint32_t s_f[KP * kWs];          // F^T, packed hi|lo, [channel][Gaussian]
+  __shared__ uint32_t s_w[4][64 * kWs];       // per wave W, packed hi|lo, [pixel][Gaussian]
+  const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  int u, v;
+  tile_pixel(c, tid, u, v);
+  const bool inside = u < c.W && v < c.H;
+  const float px = u + 0.5f, py = v + 0.5f;
+  v4f acc[CB][4];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) acc[cb][pb] = zero4();
+  float T = 1.0f;
+  bool done = !inside;
+  uint32_t last = 0;
+  const float amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
+  uint32_t* W = s_w[wave];
+  SStage<NS> st;
+  if (c.start < c.end)
+    st.fetch(vals, c.start, (int)min((uint32_t)kB, c.end - c.start), c.item, n, rec, depth, rgb, sem, emb, n_sem);
+  for (uint32_t b = c.start; b < c.end; b += kB) {
+    // every wave is past the previous batch's LDS reads; stop once every pixel has
+    if (__syncthreads_count(!done) == 0) break;
+    st.commit_cols(s_rec, s_f);
+    __syncthreads();
+    const int cnt = (int)min((uint32_t)kB, c.end - b);
+    if (b + kB < c.end)
+      st.fetch(vals, b + kB, (int)min((uint32_t)kB, c.end - b - kB), c.item, n, rec, depth, rgb, sem, emb, n_sem);
+    // front-to-back recurrence, branch-free; only T carries from one Gaussian to the next
+    bool took = false;
+    const uint32_t base = b - c.start;
+#pragma unroll
+    for (int q4 = 0; q4 < kB; q4 += 4) {
+      uint32_t pk[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int q = q4 + e;
+        const float4 r0 = s_rec[2 * q], r1 = s_rec[2 * q + 1];
+        float dx, dy;
+        const float pw = footprint_power(px, py, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, dx, dy);
+        const float araw = r1.w * fast_exp(pw);
+        const bool ok = (q < cnt) & !done & (araw >= amin);
+        const float a = fminf(amax, araw);
+        const float Tn = T * (1.0f - a);
+        const bool stop = ok & (Tn < tmin);
+        const bool take = ok & !stop;
+        pk[e] = take ? pack_hl(a * T) : 0u;
+        T = take ? Tn : T;
+        done = done | stop;
+        last = take ? base + q + 1 : last;
+        took |= take;
+      }
+      *reinterpret_cast<uint4*>(W + lane * kWs + q4) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    }
+    wave_sync();
+    if (__ballot(took) == 0ull) continue;
+    // out^T[c][p] += F^T[c][i] W^T[i][p]: A = F^T (i = channel 16 cb + l16, k = Gaussian 8 g4 + e),
+    // B = W^T (k = Gaussian, j = pixel 16 pb + l16)
+    v8bf ah[CB], al[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) load_op(s_f + (16 * cb + l16) * kWs + 8 * g4, ah[cb], al[cb]);
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) {
+      v8bf bh, bl;
+      load_op(W + (16 * pb + l16) * kWs + 8 * g4, bh, bl);
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc[cb][pb] = mma3(ah[cb], al[cb], bh, bl, acc[cb][pb]);
+    }
+  }
+  // D[c][p]: lane holds pixel 16 pb + l16 of this wave, channels 16 cb + 4 g4 + r
+  const int Kr = 4 + n_sem;
+#pragma unroll
+  for (int pb = 0; pb < 4; ++pb) {
+    int pu, pv;
+    tile_pixel(c, wave * 64 + 16 * pb + l16, pu, pv);
+    if (pu >= c.W || pv >= c.H) continue;
+    const int64_t pbase = c.pixel_base * Kr + (int64_t)pv * c.W + pu;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ch = 16 * cb + 4 * g4 + r;
+        if (ch < Kr) color[pbase + ch * c.HW] = acc[cb][pb][r];
+      }
+  }
+  if (!inside) return;
+  const int64_t pix = c.pixel_base + (int64_t)v * c.W + u;
+  Tout[pix] = T;
+  ncout[pix] = last;
+}
+
+// ------------------------------------------------------------------------- backward
+// Swaps the 4x4 blocks (lane row R, register group X[pb]) -> (lane row pb, group R):
+// permlane32 exchanges rows 0,1 with 2,3, permlane16 rows 0 with 1 and 2 with 3.
+__device__ __forceinline__ void block_transpose(uint32_t (&X)[4][8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    auto s02 = __builtin_amdgcn_permlane32_swap(X[0][k], X[2][k], false, false);
+    auto s13 = __builtin_amdgcn_permlane32_swap(X[1][k], X[3][k], false, false);
+    X[0][k] = s02[0];
+    X[2][k] = s02[1];
+    X[1][k] = s13[0];
+    X[3][k] = s13[1];
+    auto s01 = __builtin_amdgcn_permlane16_swap(X[0][k], X[1][k], false, false);
+    auto s23 = __builtin_amdgcn_permlane16_swap(X[2][k], X[3][k], false, false);
+    X[0][k] = s01[0];
+    X[1][k] = s01[1];
+    X[2][k] = s23[0];
+    X[3][k] = s23[1];
+  }
+}
+
+template <int NS>
+__global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, const float* __restrict__ rgb,
+                                                          const float* __restrict__ sem,
+                                                          const uint16_t* __restrict__ emb, int n_sem,
+                                                          const float* __restrict__ rec,
+                                                          const float* __restrict__ depth, int64_t n,
+                                                          const gs_item* __restrict__ items, int n_items,
+                                                          const uint32_t* __restrict__ vals,
+                                                          const uint32_t* __restrict__ ranges,
+                                                          const float* __restrict__ Tfin,
+                                                          const uint32_t* __restrict__ ncin,
+                                                          const float* __restrict__ gcolor, float* __restrict__ g2d,
+                                                          float* __restrict__ grgb, float* __restrict__ gsem) {
+  using S = SShape<NS>;
+  constexpr int KP = S::KP, CB = S::CB, FST = S::FST;
+  __shared__ float4 s_rec[2 * kB];
+  __shared__ float s_f[kB * FST];             // F, [Gaussian][channel]
+  __shared__ uint32_t s_w[4][16 * kPs];       // per wave, 16 Gaussians: W packed hi|lo, [Gaussian][pixel]
+  __shared__ float s_df[kB * KP];
+  __shared__ float s_geo[kB * 6 * 16];        // [Gaussian][component][row slot]
+  __shared__ uint32_t s_lmax;
+  const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int Kr = 4 + n_sem;
+  int u, v;
+  tile_pixel(c, tid, u, v);
+  const bool inside = u < c.W && v < c.H;
+  const float px = u + 0.5f, py = v + 0.5f;
+
+  // upstream gradient of a wave pixel (0..63) and channel, zero outside the image
+  auto gval = [&](int wp, int ch) -> float {
+    int pu, pv;
+    tile_pixel(c, wave * 64 + wp, pu, pv);
+    if (pu >= c.W || pv >= c.H || ch >= Kr) return 0.0f;
+    return gcolor[c.pixel_base * Kr + (int64_t)pv * c.W + pu + ch * c.HW];
+  };
+  // G^T as B of GF (k = channel 32 ks + 8 g4 + e, j = pixel 16 pb + l16)
+  float g1[4][KP / 4];
+#pragma unroll
+  for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+    for (int ks = 0; ks < KP / 4; ++ks) g1[pb][ks] = gval(16 * pb + l16, 4 * ks + g4);
+  // G as B of dF (k = pixel 32 ks + 8 g4 + e, j = channel 16 cb + l16)
+  v8bf g2h[2][CB], g2l[2][CB];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = gval(32 * ks + 8 * g4 + e, 16 * cb + l16);
+      split8(x, g2h[ks][cb], g2l[ks][cb]);
+    }
+  float T = inside ? Tfin[c.pixel_base + (int64_t)v * c.W + u] : 1.0f;
+  // n_contrib comes from the matching forward; clamp so that a mismatched call stays in range
+  const uint32_t len = c.end - c.start;
+  const uint32_t last = inside ? min(ncin[c.pixel_base + (int64_t)v * c.W + u], len) : 0u;
+  if (tid == 0) s_lmax = 0;
+  __syncthreads();
+  atomicMax(&s_lmax, last);
+  __syncthreads();
+  const uint32_t lmax = s_lmax;
+  float suffix = 0.0f;   // sum over later Gaussians of (g . f) alpha T
+  const float amin = cfg.alpha_min, amax = cfg.alpha_max;
+  SStage<NS> st;
+  if (lmax > 0) {
+    const int lo0 = max(0, (int)lmax - kB);
+    st.fetch(vals, c.start + lo0, (int)lmax - lo0, c.item, n, rec, depth, rgb, sem, emb, n_sem);
+  }
+  for (int hi = (int)lmax; hi > 0; hi -= kB) {
+    const int lo = max(0, hi - kB);
+    const int cnt = hi - lo;
+    __syncthreads();
+    st.commit_rows(s_rec, s_f);
+    for (int i = tid; i < kB * KP; i += 256) s_df[i] = 0.0f;
+    for (int i = tid; i < kB * 6 * 16; i += 256) s_geo[i] = 0.0f;
+    __syncthreads();
+    if (lo > 0) {
+      const int lo2 = max(0, lo - kB);
+      st.fetch(vals, c.start + lo2, lo - lo2, c.item, n, rec, depth, rgb, sem, emb, n_sem);
+    }
+    if (__ballot((uint32_t)lo < last) != 0ull) {
+      // GF^T[i][p] in single precision (it decides dL/dalpha, where terms cancel):
+      // v_mfma_f32_16x16x4f32, A = F (i = Gaussian 16 bq + l16, k = channel 4 ks + g4), B = G^T
+      uint32_t X[4][8];
+      {
+        v4f gfa[4][2];
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) gfa[pb][0] = gfa[pb][1] = zero4();
+#pragma unroll
+        for (int bq = 0; bq < 2; ++bq)
+#pragma unroll
+          for (int ks = 0; ks < KP / 4; ++ks) {
+            const float a = s_f[(16 * bq + l16) * FST + 4 * ks + g4];
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb)
+              gfa[pb][bq] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g1[pb][ks], gfa[pb][bq], 0, 0, 0);
+          }
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            X[pb][r] = __float_as_uint(gfa[pb][0][r]);
+            X[pb][4 + r] = __float_as_uint(gfa[pb][1][r]);
+          }
+      }
+      // lane row g4 held Gaussians {4 g4 + r, 16 + 4 g4 + r} of all four pixel rows; now
+      // every lane holds its own pixel's values: X[g][4 bq + r] = gf of Gaussian 16 bq + 4 g + r
+      block_transpose(X);
+      // reverse recurrence, one 16-Gaussian block at a time (back to front)
+#pragma unroll
+      for (int bq = 1; bq >= 0; --bq) {
+        uint32_t* Wp = s_w[wave];
+        bool any = false;
+#pragma unroll
+        for (int gq = 3; gq >= 0; --gq)
+#pragma unroll
+          for (int r = 3; r >= 0; --r) {
+            const int q = 16 * bq + 4 * gq + r;
+            const float4 r0 = s_rec[2 * q], r1 = s_rec[2 * q + 1];
+            float dx, dy;
+            const float pw = footprint_power(px, py, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, dx, dy);
+            const float G = fast_exp(pw);
+            const float araw = r1.w * G;
+            const bool act = (q < cnt) & ((uint32_t)(lo + q) < last) & (araw >= amin);
+            const float a = fminf(amax, araw);
+            const float rom = __builtin_amdgcn_rcpf(1.0f - a);
+            const float Tq = act ? T * rom : T;   // transmittance in front of this Gaussian
+            const float w = act ? a * Tq : 0.0f;
+            const float gf = __uint_as_float(X[gq][4 * bq + r]);
+            const float dalpha = Tq * gf - suffix * rom;
+            suffix = act ? __builtin_fmaf(gf, w, suffix) : suffix;
+            T = Tq;
+            const bool unclamped = act & (araw < amax);
+            const float dpow = unclamped ? dalpha * araw : 0.0f;
+            const float dop = unclamped ? dalpha * G : 0.0f;
+            Wp[(4 * gq + r) * kPs + lane] = act ? pack_hl(w) : 0u;
+            if (__ballot(act) != 0ull) {
+              any = true;
+              const float s0 = row_sum16(dpow * (r1.x * dx + r1.y * dy));   // d/d mean2d.x
+              const float s1 = row_sum16(dpow * (r1.z * dy + r1.y * dx));   // d/d mean2d.y
+              const float s2 = row_sum16(-0.5f * dpow * dx * dx);           // d/dA
+              const float s3 = row_sum16(-dpow * dx * dy);                  // d/dB
+              const float s4 = row_sum16(-0.5f * dpow * dy * dy);           // d/dC
+              const float s5 = row_sum16(dop);                              // d/d opacity
+              if (l16 == 0) {
+                float* dst = s_geo + q * 96 + wave * 4 + g4;
+                dst[0] = s0; dst[16] = s1; dst[32] = s2; dst[48] = s3; dst[64] = s4; dst[80] = s5;
+              }
+            }
+          }
+        wave_sync();
+        if (__ballot(any) != 0ull) {
+          // A = W^T (i = Gaussian l16 of the block, k = pixel 32 ks + 8 g4 + e)
+          v8bf wh[2], wl[2];
+#pragma unroll
+          for (int ks = 0; ks < 2; ++ks) load_op(Wp + l16 * kPs + 32 * ks + 8 * g4, wh[ks], wl[ks]);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            v4f d = zero4();
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) d = mma3(wh[ks], wl[ks], g2h[ks][cb], g2l[ks][cb], d);
+            // D[i][c]: Gaussian 16 bq + 4 g4 + r, channel 16 cb + l16
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (d[r] != 0.0f) atomicAdd(&s_df[(16 * bq + 4 * g4 + r) * KP + 16 * cb + l16], d[r]);
+          }
+        }
+        wave_sync();   // the block's W is consumed before the next block overwrites it
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < cnt * KP; idx += 256) {
+      const int q = idx / KP, k = idx - q * KP;
+      const float val = s_df[idx];
+      if (val == 0.0f || k >= Kr) continue;
+      const uint32_t g = vals[c.start + lo + q];
+      if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
+      else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
+      else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
+    }
+    for (int idx = tid; idx < cnt * 6; idx += 256) {
+      const int q = idx / 6, comp = idx - q * 6;
+      const float* src = s_geo + q * 96 + comp * 16;
+      float sum = 0.0f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) sum += src[r];
+      if (sum != 0.0f) {
+        const uint32_t g = vals[c.start + lo + q];
+        atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + comp], sum);
+      }
+    }
+  }
+}
+
+template <int NS>
+int launch_fwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items, int n_items,
+                 int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& out, hipStream_t s) {
+  hipLaunchKernelGGL(k_render_fwd_split<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb, cfg.n_sem,
+                     p.rec, p.depth, g.n, items, n_items, vals, ranges, out.color, out.T, out.n_contrib);
+  return launch_status();
+}
+
+template <int NS>
+int launch_bwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items, int n_items,
+                 int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& fwd,
+                 const gs_images& gin, float* g2d, const gs_grads& gr, hipStream_t s) {
+  hipLaunchKernelGGL(k_render_bwd_split<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb, cfg.n_sem,
+                     p.rec, p.depth, g.n, items, n_items, vals, ranges, fwd.T, fwd.n_contrib, gin.color, g2d, gr.rgb,
+                     gr.sem);
+  return launch_status();
+}
+
+}  // namespace
+
+int launch_render_fwd_split(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
+                            int n_items, int n_tiles, const uint32_t* vals, const uint32_t* ranges,
+                            const gs_images& out, hipStream_t s) {
+  const int ns = cfg.n_sem;
+  if (ns <= 28) return launch_fwd_s<28>(cfg, g, p, items, n_items, n_tiles, vals, ranges, out, s);
+  if (ns <= 60) return launch_fwd_s<60>(cfg, g, p, items, n_items, n_tiles, vals, ranges, out, s);
+  return GS_ERR_UNSUPPORTED;
+}
+
+int launch_render_bwd_split(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
+                            int n_items, int n_tiles, const uint32_t* vals, const uint32_t* ranges,
+                            const gs_images& fwd, const gs_images& gin, float* g2d, const gs_grads& gr, hipStream_t s) {
+  const int ns = cfg.n_sem;
+  if (ns <= 28) return launch_bwd_s<28>(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
+  if (ns <= 60) return launch_bwd_s<60>(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
+  return GS_ERR_UNSUPPORTED;
+}
+
+}  // namespace gs

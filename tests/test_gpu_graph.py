@@ -38,7 +38,7 @@ def _snapshot(st):
     return out
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_graph_replays_match_eager(variant):
     st = _step(variant)
     st.run()

@@ -151,7 +151,7 @@ def test_bin_sort_capacity_overflow_reports_status():
     assert int(s2.status.item()) == _lib.GS_OK and int(s2.n_dup.item()) == int(s.n_dup.item())
 
 
-VARIANTS = {"valu": 1, "mfma": 2}
+VARIANTS = {"valu": 1, "mfma": 2, "split": 3}
 
 
 @pytest.mark.parametrize("variant", list(VARIANTS))
