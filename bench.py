@@ -292,7 +292,19 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="render kernels: 0 auto (3), 1 VALU, 2 FP32 matrix cores, 3 split-bf16 matrix cores")
     ap.add_argument("--eager", action="store_true", help="time eager calls instead of graph replays")
     ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times): the reference for HBM byte counters")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))

@@ -17,25 +17,6 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
 // kernel folds the slots afterwards.
 constexpr int kSlots = 64;
 
-// Number of pixels with a valid (positive) target depth, per item: count[item * kSlots + slot].
-__global__ void k_valid_depth(const gs_item* __restrict__ items, int n_items, int64_t P,
-                              const float* __restrict__ tdepth, float* __restrict__ count_slots) {
-  float* count = count_slots + (blockIdx.x % kSlots);
-  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = pix < P;
-  const int item = live ? item_of_pixel(items, n_items, pix) : -1;
-  const float v = (live && tdepth[pix] > 0.0f) ? 1.0f : 0.0f;
-  // wave-uniform item: one atomic per wave, else one per lane
-  const int first = __shfl(item, 0, 64);
-  const bool uniform = __ballot(item != first) == 0ull;
-  if (uniform) {
-    const float s = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && first >= 0 && s != 0.0f) atomicAdd(&count[first * kSlots], s);
-  } else if (live && v != 0.0f) {
-    atomicAdd(&count[item * kSlots], v);
-  }
-}
-
 // out[i * stride + c] = sum over slots of in[(i * ncomp + c) * kSlots + slot].
 __global__ void k_fold_slots(const float* __restrict__ in, int n_items, int ncomp, float* __restrict__ out) {
   for (int i = threadIdx.x; i < n_items * ncomp; i += blockDim.x) {
@@ -48,72 +29,149 @@ __global__ void k_fold_slots(const float* __restrict__ in, int n_items, int ncom
 
 __device__ __forceinline__ float sgn(float d) { return (float)((d > 0.0f) - (d < 0.0f)); }
 
+// Item of each lane's pixel: one scalar lookup for the wave's first pixel, a per-lane
+// search only where a wave straddles two items.
+__device__ __forceinline__ int lane_item(const gs_item* __restrict__ items, int n_items, int64_t wave_pix0,
+                                         int64_t pix) {
+  const int first = item_of_pixel(items, n_items, wave_pix0);
+  const gs_item it = items[first];
+  const int64_t end = it.pixel_base + (int64_t)it.W * it.H;
+  return pix < end ? first : item_of_pixel(items, n_items, pix);
+}
+
+// Per-item L1 colour, L1 depth over valid target depths, cross-entropy on the class
+// logits, and their image gradients, in one pass over each pixel's channels. The depth
+// gradient is written as sign(d) (or 0) and scaled by w1 / n_valid afterwards, once the
+// valid counts are known; the logits of a pixel are held in registers (CM >= classes).
+template <int CM>
 __global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items, int n_items, int64_t P, int K,
                                               int n_classes, const float* __restrict__ color,
                                               const float* __restrict__ logits, const float* __restrict__ trgb,
                                               const float* __restrict__ tdepth, const int32_t* __restrict__ tlabel,
-                                              float w0, float w1, float w2, const float* __restrict__ nvalid,
-                                              float* __restrict__ loss_slots, float* __restrict__ gcolor,
+                                              float w0, float w2, float* __restrict__ loss_slots,
+                                              float* __restrict__ count_slots, float* __restrict__ gcolor,
                                               float* __restrict__ glogits) {
-  float* loss = loss_slots + (blockIdx.x % kSlots);
-  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = blockIdx.x % kSlots;
+  const int64_t wave_pix0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+  if (wave_pix0 >= P) return;
+  const int64_t pix = wave_pix0 + (threadIdx.x & 63);
   const bool live = pix < P;
-  float lr = 0.0f, ld = 0.0f, ls = 0.0f;
-  int item = -1;
+  const int item = lane_item(items, n_items, wave_pix0, live ? pix : wave_pix0);
+  float lr = 0.0f, ld = 0.0f, ls = 0.0f, nv = 0.0f;
   if (live) {
-    item = item_of_pixel(items, n_items, pix);
     const gs_item it = items[item];
     const int64_t HW = (int64_t)it.W * it.H;
     const int64_t p = pix - it.pixel_base;
     const int64_t cb = it.pixel_base * K + p;
     const float inv3 = 1.0f / (3.0f * (float)HW);
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       const float d = color[cb + ch * HW] - trgb[it.pixel_base * 3 + ch * HW + p];
       lr += fabsf(d) * inv3;
       gcolor[cb + ch * HW] = w0 * sgn(d) * inv3;
     }
     const float td = tdepth[pix];
+    float gd = 0.0f;
     if (td > 0.0f) {
-      const float inv = 1.0f / nvalid[item];
       const float d = color[cb + 3 * HW] - td;
-      ld = fabsf(d) * inv;
-      gcolor[cb + 3 * HW] = w1 * sgn(d) * inv;
-    } else {
-      gcolor[cb + 3 * HW] = 0.0f;
+      ld = fabsf(d);
+      nv = 1.0f;
+      gd = sgn(d);
     }
-    if (n_classes > 0) {
+    gcolor[cb + 3 * HW] = gd;
+    if (CM > 0 && n_classes > 0) {
       // plain mode: logits are colour channels 4..; learned mode: a separate C-plane image
       const float* L = logits ? logits + it.pixel_base * n_classes + p : color + cb + 4 * HW;
       float* G = logits ? glogits + it.pixel_base * n_classes + p : gcolor + cb + 4 * HW;
+      float x[CM > 0 ? CM : 1];
       float m = -INFINITY;
-      for (int c = 0; c < n_classes; ++c) m = fmaxf(m, L[c * HW]);
-      float z = 0.0f;
-      for (int c = 0; c < n_classes; ++c) z += __expf(L[c * HW] - m);
-      const float lse = m + __logf(z);
+      const float* Lc = L;
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        x[c] = c < n_classes ? *Lc : -INFINITY;
+        Lc += HW;
+        m = fmaxf(m, x[c]);
+      }
       const int y = tlabel[pix];
+      float xy = 0.0f, z = 0.0f;
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        xy = c == y ? x[c] : xy;
+        x[c] = c < n_classes ? __expf(x[c] - m) : 0.0f;
+        z += x[c];
+      }
       const float invp = 1.0f / (float)HW;
-      if (y >= 0 && y < n_classes) {
-        ls = (lse - L[(int64_t)y * HW]) * invp;
-        for (int c = 0; c < n_classes; ++c) G[c * HW] = w2 * (__expf(L[c * HW] - lse) - (c == y ? 1.0f : 0.0f)) * invp;
-      } else {  // a label outside [0, C) marks an unlabelled pixel: no semantic term
-        for (int c = 0; c < n_classes; ++c) G[c * HW] = 0.0f;
+      const bool labelled = y >= 0 && y < n_classes;   // outside [0, C): unlabelled, no semantic term
+      if (labelled) ls = (m + __logf(z) - xy) * invp;
+      const float sc = labelled ? w2 * invp / z : 0.0f;
+      const float oh = labelled ? w2 * invp : 0.0f;
+      float* Gc = G;
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        if (c < n_classes) *Gc = x[c] * sc - (c == y ? oh : 0.0f);
+        Gc += HW;
       }
     }
   }
+  // wave-uniform item: one atomic per wave and quantity, else one per lane
   const int first = __shfl(item, 0, 64);
   const bool uniform = __ballot(item != first) == 0ull;
+  float* loss = loss_slots + slot;
+  float* count = count_slots + slot;
   if (uniform) {
-    const float a = wave_sum(lr), b = wave_sum(ld), c = wave_sum(ls);
-    if ((threadIdx.x & 63) == 0 && first >= 0) {
+    const float a = wave_sum(lr), b = wave_sum(ld), c = wave_sum(ls), v = wave_sum(nv);
+    if ((threadIdx.x & 63) == 0) {
       atomicAdd(&loss[(3 * first + 0) * kSlots], a);
-      atomicAdd(&loss[(3 * first + 1) * kSlots], b);
+      if (v != 0.0f) {
+        atomicAdd(&loss[(3 * first + 1) * kSlots], b);
+        atomicAdd(&count[first * kSlots], v);
+      }
       atomicAdd(&loss[(3 * first + 2) * kSlots], c);
     }
   } else if (live) {
     atomicAdd(&loss[(3 * item + 0) * kSlots], lr);
-    atomicAdd(&loss[(3 * item + 1) * kSlots], ld);
+    if (nv != 0.0f) {
+      atomicAdd(&loss[(3 * item + 1) * kSlots], ld);
+      atomicAdd(&count[item * kSlots], nv);
+    }
     atomicAdd(&loss[(3 * item + 2) * kSlots], ls);
   }
+}
+
+// Folds the slots: loss[i] = (L1 colour, L1 depth / n_valid, cross-entropy); n_valid[i].
+__global__ void k_fold_loss(const float* __restrict__ loss_slots, const float* __restrict__ count_slots, int n_items,
+                            float* __restrict__ loss, float* __restrict__ nvalid) {
+  for (int i = threadIdx.x; i < n_items * 4; i += blockDim.x) {
+    const int item = i >> 2, comp = i & 3;
+    const float* src = comp < 3 ? loss_slots + (int64_t)(3 * item + comp) * kSlots : count_slots + (int64_t)item * kSlots;
+    float s = 0.0f;
+    for (int k = 0; k < kSlots; ++k) s += src[k];
+    if (comp == 3) nvalid[item] = s;
+    else if (comp != 1) loss[3 * item + comp] = s;
+  }
+  __syncthreads();
+  for (int item = threadIdx.x; item < n_items; item += blockDim.x) {
+    const float* src = loss_slots + (int64_t)(3 * item + 1) * kSlots;
+    float s = 0.0f;
+    for (int k = 0; k < kSlots; ++k) s += src[k];
+    loss[3 * item + 1] = nvalid[item] > 0.0f ? s / nvalid[item] : 0.0f;
+  }
+}
+
+// Depth-gradient plane *= w1 / n_valid of the pixel's item.
+__global__ __launch_bounds__(256) void k_scale_depth(const gs_item* __restrict__ items, int n_items, int64_t P, int K,
+                                                     float w1, const float* __restrict__ nvalid,
+                                                     float* __restrict__ gcolor) {
+  const int64_t wave_pix0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+  if (wave_pix0 >= P) return;
+  const int64_t pix = wave_pix0 + (threadIdx.x & 63);
+  if (pix >= P) return;
+  const int item = lane_item(items, n_items, wave_pix0, pix);
+  const gs_item it = items[item];
+  const int64_t HW = (int64_t)it.W * it.H;
+  float* g = gcolor + it.pixel_base * K + 3 * HW + (pix - it.pixel_base);
+  const float nv = nvalid[item];
+  *g = nv > 0.0f ? *g * (w1 / nv) : 0.0f;
 }
 
 // Level `level` of every view from the level above (item - 1 of the same view).
@@ -184,11 +242,16 @@ int launch_loss(const gs_item* items, int n_items, int64_t P, int K, int n_class
   float* loss_slots = ws + (int64_t)n_items * kSlots;        // [n_items][3][kSlots]
   float* nvalid = ws + (int64_t)n_items * 4 * kSlots;        // [n_items]
   launch_fill_f32(ws, (int64_t)n_items * 4 * kSlots, 0.0f, s);
-  hipLaunchKernelGGL(k_valid_depth, dim3(pb), dim3(256), 0, s, items, n_items, P, t.depth, count_slots);
-  hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(256), 0, s, count_slots, n_items, 1, nvalid);
-  hipLaunchKernelGGL(k_loss, dim3(pb), dim3(256), 0, s, items, n_items, P, K, n_classes, color, logits, t.rgb, t.depth,
-                     t.label, w[0], w[1], w[2], nvalid, loss_slots, gcolor, glogits);
-  hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(256), 0, s, loss_slots, n_items, 3, loss);
+#define GS_LOSS_ARGS items, n_items, P, K, n_classes, color, logits, t.rgb, t.depth, t.label, w[0], w[2], loss_slots, \
+                     count_slots, gcolor, glogits
+  if (n_classes == 0) hipLaunchKernelGGL(k_loss<0>, dim3(pb), dim3(256), 0, s, GS_LOSS_ARGS);
+  else if (n_classes <= 16) hipLaunchKernelGGL(k_loss<16>, dim3(pb), dim3(256), 0, s, GS_LOSS_ARGS);
+  else if (n_classes <= 32) hipLaunchKernelGGL(k_loss<32>, dim3(pb), dim3(256), 0, s, GS_LOSS_ARGS);
+  else if (n_classes <= 64) hipLaunchKernelGGL(k_loss<64>, dim3(pb), dim3(256), 0, s, GS_LOSS_ARGS);
+  else return GS_ERR_UNSUPPORTED;
+#undef GS_LOSS_ARGS
+  hipLaunchKernelGGL(k_fold_loss, dim3(1), dim3(256), 0, s, loss_slots, count_slots, n_items, loss, nvalid);
+  hipLaunchKernelGGL(k_scale_depth, dim3(pb), dim3(256), 0, s, items, n_items, P, K, w[1], nvalid, gcolor);
   return launch_status();
 }
 

@@ -57,9 +57,11 @@ def test_graph_replays_match_eager(variant):
         for k in ("color", "T", "nc", "vals", "ranges"):
             assert torch.equal(got[k], ref[k]), (rep, k)
         rel_check(got["loss"].cpu().numpy(), ref["loss"].cpu().numpy(), 1e-5, name=f"loss rep {rep}")
+        # gradients are summed with float atomics, whose order differs between runs; a stale
+        # or un-cleared buffer in the graph would show as an O(1) error
         for k in ref:
             if k.startswith("g_"):
-                rel_check(got[k].cpu().numpy(), ref[k].cpu().numpy(), 1e-5, name=f"{k} rep {rep}")
+                rel_check(got[k].cpu().numpy(), ref[k].cpu().numpy(), 1e-4, name=f"{k} rep {rep}")
 
 
 def test_eager_steps_are_deterministic_where_no_atomics():
