@@ -53,18 +53,19 @@ __device__ __forceinline__ float footprint_power(float px, float py, float mhx, 
   return fminf(p, 0.0f);
 }
 
-// DPP lane moves within a row of 16 lanes.
+// DPP lane moves within a row of 16 lanes (every source lane exists, so bound_ctrl only
+// lets the compiler fold the move into the consuming add as one v_add_f32_dpp).
 __device__ __forceinline__ float dpp_xor1(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float dpp_xor2(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float dpp_half_mirror(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float dpp_mirror(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));
 }
 // Sum over the 16 lanes of each DPP row; every lane of the row receives the sum.
 __device__ __forceinline__ float row_sum16(float v) {
