@@ -34,7 +34,11 @@ int launch_render_bwd_valu(GS_RENDER_BWD_ARGS);
 int launch_render_fwd_mfma(GS_RENDER_FWD_ARGS);
 int launch_render_bwd_mfma(GS_RENDER_BWD_ARGS);
 int launch_render_fwd_split(GS_RENDER_FWD_ARGS);
-int launch_render_bwd_split(GS_RENDER_BWD_ARGS);
+int launch_render_bwd_split(const gs_config&, const gs_gaussians&, const gs_projected&, const gs_item*, int, int,
+                            const uint32_t*, const uint32_t*, const gs_images&, const gs_images&, float*,
+                            const gs_grads&, void*, int64_t, hipStream_t);
+size_t render_seg_workspace(int n_tiles, int64_t dup_capacity);
+int64_t render_seg_capacity(int n_tiles, size_t bytes);
 
 // Render kernel variants: 1 = per-lane FMA accumulation (VALU), 2 = single-precision
 // matrix-core channel contraction, 3 = every contraction on the bfloat16 matrix cores with
@@ -49,13 +53,14 @@ int launch_render_fwd(const gs_config& cfg, const gs_gaussians& g, const gs_proj
 }
 int launch_render_bwd(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
                       int n_items, int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& fwd,
-                      const gs_images& gin, float* g2d, const gs_grads& gr, hipStream_t s) {
+                      const gs_images& gin, float* g2d, const gs_grads& gr, void* seg_ws, int64_t cap,
+                      hipStream_t s) {
   if (n_tiles == 0) return GS_OK;
   if (cfg.variant == 1)
     return launch_render_bwd_valu(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
   if (cfg.variant == 2)
     return launch_render_bwd_mfma(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
-  return launch_render_bwd_split(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
+  return launch_render_bwd_split(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, seg_ws, cap, s);
 }
 int launch_loss(const gs_item*, int, int64_t, int, int, const float*, const float*, const gs_targets&, const float*,
                 float*, float*, float*, float*, hipStream_t);
@@ -181,7 +186,8 @@ int gs_workspace_size(int kind, const gs_config* cfg, int32_t n_items, int64_t n
       *bytes = bin_sort_workspace((int64_t)n_items * n_gauss, dup_capacity);
       return GS_OK;
     case GS_WS_RENDER_BWD:
-      *bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)n_gauss) + align_up(head_bwd_workspace());
+      *bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)n_gauss) + align_up(head_bwd_workspace()) +
+               render_seg_workspace(n_tiles, dup_capacity);
       return GS_OK;
     case GS_WS_LOSS:
       *bytes = align_up(loss_workspace(n_items));
@@ -267,7 +273,13 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   if (!grads->mean || !grads->log_scale || !grads->quat || !grads->opacity || !grads->rgb || !grads->pose)
     return GS_ERR_INVALID_ARG;
   const size_t rec_bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)g->n);
-  if (!workspace || ws_bytes < rec_bytes + align_up(head_bwd_workspace())) return GS_ERR_WORKSPACE;
+  const size_t head_bytes = align_up(head_bwd_workspace());
+  if (!workspace || ws_bytes < rec_bytes + head_bytes) return GS_ERR_WORKSPACE;
+  // the rest holds the segment work list of the reverse pass, sized for a duplicate
+  // capacity (0 still works: every tile is then one work item)
+  const int64_t cap = render_seg_capacity(n_tiles, ws_bytes - rec_bytes - head_bytes);
+  if (cap < 0) return GS_ERR_WORKSPACE;
+  void* seg_ws = (char*)workspace + rec_bytes + head_bytes;
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = g->n;
   gs_grads gr = *grads;
@@ -288,7 +300,7 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   if (n_tiles > 0) {
     if (!items_dev || !vals || !ranges || !fwd->T || !fwd->n_contrib || !grad_in->color) return GS_ERR_INVALID_ARG;
     st = launch_render_bwd(*cfg, *g, *proj, items_dev, n_items, n_tiles, vals, ranges, *fwd, *grad_in, (float*)workspace,
-                           gr, s);
+                           gr, seg_ws, cap, s);
     if (st) return st;
   }
   return launch_preprocess_bwd(*cfg, *g, views_dev, n_views, items_dev, (const float*)workspace, proj->radius, gr, s);

@@ -218,25 +218,6 @@ __global__ void k_compact(const int32_t* __restrict__ radius, const float* __res
   vals[p] = (uint32_t)e;
 }
 
-struct Rect {
-  int x0, y0, x1, y1;
-};
-
-__device__ __forceinline__ Rect tile_rect(const gs_config& cfg, const gs_item& it, const float* rec, int r) {
-  const float4 m = *reinterpret_cast<const float4*>(rec);
-  const double mx = (double)m.x + (double)m.z, my = (double)m.y + (double)m.w;
-  Rect R;
-  if (cfg.full_rect) {
-    R.x0 = 0; R.y0 = 0; R.x1 = it.tiles_x; R.y1 = it.tiles_y;
-    return R;
-  }
-  R.x0 = min(it.tiles_x, max(0, (int)floor((mx - r) / cfg.tile_w)));
-  R.y0 = min(it.tiles_y, max(0, (int)floor((my - r) / cfg.tile_h)));
-  R.x1 = min(it.tiles_x, max(0, (int)floor((mx + r) / cfg.tile_w) + 1));
-  R.y1 = min(it.tiles_y, max(0, (int)floor((my + r) / cfg.tile_h) + 1));
-  return R;
-}
-
 __global__ void k_touched(gs_config cfg, const uint32_t* __restrict__ svals, const uint64_t* count_dev,
                           const float* __restrict__ rec, const int32_t* __restrict__ radius,
                           const gs_item* __restrict__ items, int64_t n, uint32_t* __restrict__ touched) {
@@ -244,7 +225,7 @@ __global__ void k_touched(gs_config cfg, const uint32_t* __restrict__ svals, con
   if (j >= (int64_t)*count_dev) return;
   const uint32_t e = svals[j];
   const gs_item it = items[e / n];
-  const Rect R = tile_rect(cfg, it, rec + (int64_t)kRecFloats * e, radius[e]);
+  const Rect R = tile_rect(cfg, it.tiles_x, it.tiles_y, *reinterpret_cast<const float4*>(rec + (int64_t)kRecFloats * e), radius[e]);
   touched[j] = (uint32_t)((R.x1 - R.x0) * (R.y1 - R.y0));
 }
 
@@ -258,7 +239,7 @@ __global__ void k_duplicate(gs_config cfg, const uint32_t* __restrict__ svals, c
   const int64_t item = e / n;
   const uint32_t g = (uint32_t)(e - item * n);
   const gs_item it = items[item];
-  const Rect R = tile_rect(cfg, it, rec + (int64_t)kRecFloats * e, radius[e]);
+  const Rect R = tile_rect(cfg, it.tiles_x, it.tiles_y, *reinterpret_cast<const float4*>(rec + (int64_t)kRecFloats * e), radius[e]);
   int64_t p = offs[j];
   for (int ty = R.y0; ty < R.y1; ++ty)
     for (int tx = R.x0; tx < R.x1; ++tx, ++p) {
@@ -388,6 +369,12 @@ int radix_sort(Key* k0, Key* k1, uint32_t* v0, uint32_t* v1, const uint64_t* cou
 }  // namespace
 
 size_t bin_sort_workspace(int64_t E, int64_t cap) { return plan_sort(E, cap, nullptr).bytes; }
+
+int64_t scan_partials_needed(int64_t n) { return ceil_div(std::max<int64_t>(n, 1), kScanTile) + 2; }
+
+int scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, uint64_t* total, hipStream_t s) {
+  return device_scan(in, out, nullptr, n, n, partial, total, s);
+}
 
 int launch_bin_sort(const gs_config& cfg, const gs_projected& proj, const gs_item* items, int n_items, int64_t n,
                     int n_tiles, int64_t cap, void* ws, uint64_t* keys, uint32_t* vals, uint32_t* ranges,

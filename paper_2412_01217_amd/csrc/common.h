@@ -53,6 +53,27 @@ __device__ __forceinline__ float footprint_power(float px, float py, float mhx, 
   return fminf(p, 0.0f);
 }
 
+struct Rect {
+  int x0, y0, x1, y1;
+};
+
+// Tiles of an item met by the footprint square [mean2d - r, mean2d + r]^2 (half-open
+// tile ranges); m = (mean2d hi, mean2d lo) as the render record stores it. Binning and
+// the reverse pass both use this one definition.
+__device__ __forceinline__ Rect tile_rect(const gs_config& cfg, int tiles_x, int tiles_y, float4 m, int r) {
+  const double mx = (double)m.x + (double)m.z, my = (double)m.y + (double)m.w;
+  Rect R;
+  if (cfg.full_rect) {
+    R.x0 = 0; R.y0 = 0; R.x1 = tiles_x; R.y1 = tiles_y;
+    return R;
+  }
+  R.x0 = min(tiles_x, max(0, (int)floor((mx - r) / cfg.tile_w)));
+  R.y0 = min(tiles_y, max(0, (int)floor((my - r) / cfg.tile_h)));
+  R.x1 = min(tiles_x, max(0, (int)floor((mx + r) / cfg.tile_w) + 1));
+  R.y1 = min(tiles_y, max(0, (int)floor((my + r) / cfg.tile_h) + 1));
+  return R;
+}
+
 // DPP lane moves within a row of 16 lanes (every source lane exists, so bound_ctrl only
 // lets the compiler fold the move into the consuming add as one v_add_f32_dpp).
 __device__ __forceinline__ float dpp_xor1(float v) {
@@ -76,9 +97,17 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;
 }
 
+// Workgroup barrier that orders LDS only: global stores and atomics issued before it stay
+// in flight (nothing in the block reads them back), so their latency overlaps later work.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // One 16x16 tile of one item, as a render block sees it.
 struct Ctx {
-  int item, tx, ty;
+  int item, tx, ty, tiles_x, tiles_y;
   int W, H;
   int64_t HW, pixel_base;
   uint32_t start, end;
@@ -86,14 +115,15 @@ struct Ctx {
 
 // Tiles are launched coarse pyramid levels first: their lists are the longest, and
 // starting them early lets the many short fine-level tiles fill in around them.
-__device__ __forceinline__ Ctx make_ctx(const gs_item* items, int n_items, const uint32_t* ranges, int order) {
+__device__ __forceinline__ Ctx make_ctx_of(const gs_item* items, int n_items, const uint32_t* ranges, int tile) {
   Ctx c;
-  const int tile = order ? (int)blockIdx.x : (int)gridDim.x - 1 - (int)blockIdx.x;
   c.item = item_of_tile(items, n_items, tile);
   const gs_item it = items[c.item];
   const int lt = tile - it.tile_base;
   c.tx = lt % it.tiles_x;
   c.ty = lt / it.tiles_x;
+  c.tiles_x = it.tiles_x;
+  c.tiles_y = it.tiles_y;
   c.W = it.W;
   c.H = it.H;
   c.HW = (int64_t)it.W * it.H;
@@ -101,6 +131,10 @@ __device__ __forceinline__ Ctx make_ctx(const gs_item* items, int n_items, const
   c.start = ranges[2 * (int64_t)tile];
   c.end = ranges[2 * (int64_t)tile + 1];
   return c;
+}
+
+__device__ __forceinline__ Ctx make_ctx(const gs_item* items, int n_items, const uint32_t* ranges, int order) {
+  return make_ctx_of(items, n_items, ranges, order ? (int)blockIdx.x : (int)gridDim.x - 1 - (int)blockIdx.x);
 }
 
 // Tile-local pixel index t (0..255, row-major in the 16x16 tile) -> image coordinates.

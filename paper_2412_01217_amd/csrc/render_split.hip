@@ -24,6 +24,10 @@
 #include "common.h"
 
 namespace gs {
+
+int64_t scan_partials_needed(int64_t n);
+int scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, uint64_t* total, hipStream_t s);
+
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -106,6 +110,7 @@ template <int NS>
 struct SStage {
   static constexpr int CPT = SShape<NS>::CPT;
   float4 r;
+  uint32_t gid;
   float f[CPT];
 
   __device__ __forceinline__ void fetch(const uint32_t* __restrict__ vals, uint32_t b, int cnt, int item, int64_t n,
@@ -115,6 +120,7 @@ struct SStage {
     const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
     const bool live = q < cnt;
     const uint32_t g = live ? vals[b + q] : 0u;
+    gid = g;
     const int64_t e = (int64_t)item * n + g;
     r = make_float4(0.f, 0.f, 0.f, 0.f);
     if (live && part < 2) r = reinterpret_cast<const float4*>(rec + kRecFloats * e)[part];
@@ -132,10 +138,11 @@ struct SStage {
       f[j] = v;
     }
   }
-  // features Gaussian-major, single precision: s_f[q][c]
-  __device__ __forceinline__ void commit_rows(float4* s_rec, float* s_f) const {
+  // features Gaussian-major, single precision: s_f[q][c]; Gaussian ids to s_gid[q]
+  __device__ __forceinline__ void commit_rows(float4* s_rec, float* s_f, uint32_t* s_gid) const {
     const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
     if (part < 2) s_rec[2 * q + part] = r;
+    if (part == 0) s_gid[q] = gid;
     float* dst = s_f + q * SShape<NS>::FST + part * CPT;
 #pragma unroll
     for (int j = 0; j < CPT; j += 4) *reinterpret_cast<float4*>(dst + j) = make_float4(f[j], f[j + 1], f[j + 2], f[j + 3]);
@@ -277,7 +284,68 @@ __device__ __forceinline__ void block_transpose(uint32_t (&X)[4][8]) {
   }
 }
 
-template <int NS>
+// Long tile lists are cut into segments of kSeg list positions, each a work item of its
+// own, so that the longest list no longer sets the length of the launch. Walking a
+// segment backwards needs, per pixel, the transmittance after it and the suffix
+// sum over every later Gaussian of w (g . f). A summary pass gives every segment s of a
+// long list, per pixel,
+//   P_s  = prod over its blended Gaussians of (1 - alpha)            (front to back)
+//   GC_s = sum over its blended Gaussians of alpha T_loc (g . f),     T_loc from 1
+// and then T_after(s) = prod_{s' <= s} P_s' and suffix(s) = sum_{s' > s} T_before(s') GC_s'.
+constexpr int kSeg = 256;
+
+// One block per tile: the tile's list length in use (largest n_contrib) and its segment
+// count, stored in work order (coarse pyramid levels first unless tile_order = 1).
+__global__ __launch_bounds__(256) void k_seg_count(const gs_item* __restrict__ items, int n_items,
+                                                   const uint32_t* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ ncin, int n_tiles, int order,
+                                                   uint32_t* __restrict__ tile_lmax, uint32_t* __restrict__ cnt_ord) {
+  __shared__ uint32_t s_m;
+  const int tile = blockIdx.x;
+  const int item = item_of_tile(items, n_items, tile);
+  const gs_item it = items[item];
+  const int lt = tile - it.tile_base;
+  const int u = (lt % it.tiles_x) * kTile + (threadIdx.x & 15), v = (lt / it.tiles_x) * kTile + (threadIdx.x >> 4);
+  const uint32_t len = ranges[2 * (int64_t)tile + 1] - ranges[2 * (int64_t)tile];
+  const uint32_t last = (u < it.W && v < it.H) ? min(ncin[it.pixel_base + (int64_t)v * it.W + u], len) : 0u;
+  if (threadIdx.x == 0) s_m = 0;
+  __syncthreads();
+  atomicMax(&s_m, last);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t m = s_m;
+    tile_lmax[tile] = m;
+    cnt_ord[order ? tile : n_tiles - 1 - tile] = m == 0 ? 0u : (m <= (uint32_t)kSeg ? 1u : (m + kSeg - 1) / kSeg);
+  }
+}
+
+// Work list: (tile, segment | segment count << 16). If the segments do not fit the
+// workspace, every tile becomes a single item. Also resets the two work counters.
+__global__ void k_seg_list(const uint32_t* __restrict__ cnt_ord, const uint32_t* __restrict__ base_ord,
+                           const uint64_t* __restrict__ total, int n_tiles, int order, int64_t max_segs,
+                           uint2* __restrict__ work, uint32_t* __restrict__ ctl) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t tot = *total;
+  const bool fits = tot <= (uint64_t)max_segs;
+  if (o == 0) {
+    ctl[0] = fits ? (uint32_t)tot : (uint32_t)n_tiles;
+    ctl[1] = 0;
+    ctl[2] = 0;
+  }
+  if (o >= n_tiles) return;
+  const uint32_t tile = order ? o : n_tiles - 1 - o;
+  if (fits) {
+    const uint32_t c = cnt_ord[o], b = base_ord[o];
+    for (uint32_t k = 0; k < c; ++k) work[b + k] = make_uint2(tile, k | (c << 16));
+  } else {
+    work[o] = make_uint2(tile, 1u << 16);
+  }
+}
+
+// SUMMARY = false: the reverse pass proper over one work item (a whole tile list, or one
+// segment of it). SUMMARY = true: the per-segment P and GC of the segments of long lists.
+// Persistent blocks take work items from a counter until the list is exhausted.
+template <int NS, bool SUMMARY>
 __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, const float* __restrict__ rgb,
                                                           const float* __restrict__ sem,
                                                           const uint16_t* __restrict__ emb, int n_sem,
@@ -289,186 +357,247 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
                                                           const float* __restrict__ Tfin,
                                                           const uint32_t* __restrict__ ncin,
                                                           const float* __restrict__ gcolor, float* __restrict__ g2d,
-                                                          float* __restrict__ grgb, float* __restrict__ gsem) {
+                                                          float* __restrict__ grgb, float* __restrict__ gsem,
+                                                          const uint2* __restrict__ work, uint32_t* __restrict__ ctl,
+                                                          const uint32_t* __restrict__ tile_lmax,
+                                                          float* __restrict__ segP, float* __restrict__ segGC) {
   using S = SShape<NS>;
   constexpr int KP = S::KP, CB = S::CB, FST = S::FST;
   __shared__ float4 s_rec[2 * kB];
   __shared__ float s_f[kB * FST];             // F, [Gaussian][channel]
-  __shared__ uint32_t s_w[4][16 * kPs];       // per wave, 16 Gaussians: W packed hi|lo, [Gaussian][pixel]
-  __shared__ float s_df[kB * KP];
-  __shared__ float s_geo[kB * 6 * 16];        // [Gaussian][component][row slot]
-  __shared__ uint32_t s_lmax;
-  const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order);
+  __shared__ uint32_t s_w[SUMMARY ? 1 : 4][16 * kPs];   // per wave, 16 Gaussians: W packed hi|lo, [Gaussian][pixel]
+  __shared__ float s_df[SUMMARY ? 1 : kB * KP];
+  __shared__ float s_geo[SUMMARY ? 1 : kB * 6 * 16];     // [Gaussian][component][row slot]
+  __shared__ uint32_t s_wi;
+  __shared__ uint32_t s_gid[kB];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, g4 = lane >> 4;
   const int Kr = 4 + n_sem;
-  int u, v;
-  tile_pixel(c, tid, u, v);
-  const bool inside = u < c.W && v < c.H;
-  const float px = u + 0.5f, py = v + 0.5f;
-
-  // upstream gradient of a wave pixel (0..63) and channel, zero outside the image
-  auto gval = [&](int wp, int ch) -> float {
-    int pu, pv;
-    tile_pixel(c, wave * 64 + wp, pu, pv);
-    if (pu >= c.W || pv >= c.H || ch >= Kr) return 0.0f;
-    return gcolor[c.pixel_base * Kr + (int64_t)pv * c.W + pu + ch * c.HW];
-  };
-  // G^T as B of GF (k = channel 32 ks + 8 g4 + e, j = pixel 16 pb + l16)
-  float g1[4][KP / 4];
-#pragma unroll
-  for (int pb = 0; pb < 4; ++pb)
-#pragma unroll
-    for (int ks = 0; ks < KP / 4; ++ks) g1[pb][ks] = gval(16 * pb + l16, 4 * ks + g4);
-  // G as B of dF (k = pixel 32 ks + 8 g4 + e, j = channel 16 cb + l16)
-  v8bf g2h[2][CB], g2l[2][CB];
-#pragma unroll
-  for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      float x[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) x[e] = gval(32 * ks + 8 * g4 + e, 16 * cb + l16);
-      split8(x, g2h[ks][cb], g2l[ks][cb]);
-    }
-  float T = inside ? Tfin[c.pixel_base + (int64_t)v * c.W + u] : 1.0f;
-  // n_contrib comes from the matching forward; clamp so that a mismatched call stays in range
-  const uint32_t len = c.end - c.start;
-  const uint32_t last = inside ? min(ncin[c.pixel_base + (int64_t)v * c.W + u], len) : 0u;
-  if (tid == 0) s_lmax = 0;
-  __syncthreads();
-  atomicMax(&s_lmax, last);
-  __syncthreads();
-  const uint32_t lmax = s_lmax;
-  float suffix = 0.0f;   // sum over later Gaussians of (g . f) alpha T
   const float amin = cfg.alpha_min, amax = cfg.alpha_max;
-  SStage<NS> st;
-  if (lmax > 0) {
-    const int lo0 = max(0, (int)lmax - kB);
-    st.fetch(vals, c.start + lo0, (int)lmax - lo0, c.item, n, rec, depth, rgb, sem, emb, n_sem);
-  }
-  for (int hi = (int)lmax; hi > 0; hi -= kB) {
-    const int lo = max(0, hi - kB);
-    const int cnt = hi - lo;
-    __syncthreads();
-    st.commit_rows(s_rec, s_f);
-    for (int i = tid; i < kB * KP; i += 256) s_df[i] = 0.0f;
-    for (int i = tid; i < kB * 6 * 16; i += 256) s_geo[i] = 0.0f;
-    __syncthreads();
-    if (lo > 0) {
-      const int lo2 = max(0, lo - kB);
-      st.fetch(vals, c.start + lo2, lo - lo2, c.item, n, rec, depth, rgb, sem, emb, n_sem);
+  const uint32_t n_work = ctl[0];
+  for (;;) {
+    if (tid == 0) s_wi = atomicAdd(&ctl[SUMMARY ? 1 : 2], 1u);
+    lds_barrier();
+    const uint32_t wi = s_wi;
+    lds_barrier();
+    if (wi >= n_work) break;
+    const uint2 wk = work[wi];
+    const int tile = (int)wk.x;
+    const int seg = (int)(wk.y & 0xffffu), nseg = (int)(wk.y >> 16);
+    if (SUMMARY && nseg < 2) continue;
+    const Ctx c = make_ctx_of(items, n_items, ranges, tile);
+    int u, v;
+    tile_pixel(c, tid, u, v);
+    const bool inside = u < c.W && v < c.H;
+    const float px = u + 0.5f, py = v + 0.5f;
+    const int64_t pix = c.pixel_base + (int64_t)v * c.W + u;
+    // n_contrib comes from the matching forward; clamp so that a mismatched call stays in range
+    const uint32_t len = c.end - c.start;
+    const uint32_t last = inside ? min(ncin[pix], len) : 0u;
+    const int lmax = (int)tile_lmax[tile];
+    const int a0 = nseg == 1 ? 0 : seg * kSeg;
+    const int b0 = nseg == 1 ? lmax : min(lmax, a0 + kSeg);
+
+    // upstream gradient of a wave pixel (0..63) and channel, zero outside the image
+    auto gval = [&](int wp, int ch) -> float {
+      int pu, pv;
+      tile_pixel(c, wave * 64 + wp, pu, pv);
+      if (pu >= c.W || pv >= c.H || ch >= Kr) return 0.0f;
+      return gcolor[c.pixel_base * Kr + (int64_t)pv * c.W + pu + ch * c.HW];
+    };
+    // G^T as B of GF (k = channel 4 ks + g4, j = pixel 16 pb + l16)
+    float g1[4][KP / 4];
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+      for (int ks = 0; ks < KP / 4; ++ks) g1[pb][ks] = gval(16 * pb + l16, 4 * ks + g4);
+    // G as B of dF (k = pixel 32 ks + 8 g4 + e, j = channel 16 cb + l16)
+    v8bf g2h[2][SUMMARY ? 1 : CB], g2l[2][SUMMARY ? 1 : CB];
+    if constexpr (!SUMMARY) {
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          float x[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) x[e] = gval(32 * ks + 8 * g4 + e, 16 * cb + l16);
+          split8(x, g2h[ks][cb], g2l[ks][cb]);
+        }
     }
-    if (__ballot((uint32_t)lo < last) != 0ull) {
-      // GF^T[i][p] in single precision (it decides dL/dalpha, where terms cancel):
-      // v_mfma_f32_16x16x4f32, A = F (i = Gaussian 16 bq + l16, k = channel 4 ks + g4), B = G^T
-      uint32_t X[4][8];
-      {
-        v4f gfa[4][2];
-#pragma unroll
-        for (int pb = 0; pb < 4; ++pb) gfa[pb][0] = gfa[pb][1] = zero4();
-#pragma unroll
-        for (int bq = 0; bq < 2; ++bq)
-#pragma unroll
-          for (int ks = 0; ks < KP / 4; ++ks) {
-            const float a = s_f[(16 * bq + l16) * FST + 4 * ks + g4];
-#pragma unroll
-            for (int pb = 0; pb < 4; ++pb)
-              gfa[pb][bq] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g1[pb][ks], gfa[pb][bq], 0, 0, 0);
-          }
-#pragma unroll
-        for (int pb = 0; pb < 4; ++pb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            X[pb][r] = __float_as_uint(gfa[pb][0][r]);
-            X[pb][4 + r] = __float_as_uint(gfa[pb][1][r]);
-          }
+
+    // per-pixel state at the segment's back end (main pass) or front end (summary pass)
+    float T = 1.0f, acc = 0.0f;   // acc: suffix (main) or GC (summary)
+    if constexpr (!SUMMARY) {
+      const float tf = inside ? Tfin[pix] : 1.0f;
+      if (nseg == 1 || seg == nseg - 1) T = tf;
+      if (nseg > 1) {
+        const int64_t w0 = (int64_t)wi - seg;
+        float tb = 1.0f;   // transmittance in front of segment s
+        for (int s = 0; s < nseg; ++s) {
+          const float P = segP[(w0 + s) * kTilePx + tid], GC = segGC[(w0 + s) * kTilePx + tid];
+          if (s > seg) acc = __builtin_fmaf(tb, GC, acc);
+          tb *= P;
+          if (s == seg && seg < nseg - 1) T = tb;
+        }
       }
-      // lane row g4 held Gaussians {4 g4 + r, 16 + 4 g4 + r} of all four pixel rows; now
-      // every lane holds its own pixel's values: X[g][4 bq + r] = gf of Gaussian 16 bq + 4 g + r
-      block_transpose(X);
-      // reverse recurrence, one 16-Gaussian block at a time (back to front)
+    }
+
+    SStage<NS> st;
+    if (b0 > a0) {
+      const int f0 = SUMMARY ? a0 : max(a0, b0 - kB);
+      const int f1 = SUMMARY ? min(b0, a0 + kB) : b0;
+      st.fetch(vals, c.start + f0, f1 - f0, c.item, n, rec, depth, rgb, sem, emb, n_sem);
+    }
+    const int n_batches = (b0 - a0 + kB - 1) / kB;
+    for (int bi = 0; bi < n_batches; ++bi) {
+      // main pass: batches from the back; summary pass: from the front
+      const int lo = SUMMARY ? a0 + bi * kB : max(a0, b0 - (bi + 1) * kB);
+      const int hi = SUMMARY ? min(b0, lo + kB) : b0 - bi * kB;
+      const int cnt = hi - lo;
+      lds_barrier();
+      st.commit_rows(s_rec, s_f, s_gid);
+      if constexpr (!SUMMARY) {
+        for (int i = tid; i < kB * KP; i += 256) s_df[i] = 0.0f;
+        for (int i = tid; i < kB * 6 * 16; i += 256) s_geo[i] = 0.0f;
+      }
+      lds_barrier();
+      if (bi + 1 < n_batches) {
+        const int nlo = SUMMARY ? hi : max(a0, lo - kB);
+        const int nhi = SUMMARY ? min(b0, hi + kB) : lo;
+        st.fetch(vals, c.start + nlo, nhi - nlo, c.item, n, rec, depth, rgb, sem, emb, n_sem);
+      }
+      if (__ballot((uint32_t)lo < last) != 0ull) {
+        // GF^T[i][p] in single precision (it decides dL/dalpha, where terms cancel):
+        // v_mfma_f32_16x16x4f32, A = F (i = Gaussian 16 bq + l16, k = channel 4 ks + g4), B = G^T
+        uint32_t X[4][8];
+        {
+          v4f gfa[4][2];
 #pragma unroll
-      for (int bq = 1; bq >= 0; --bq) {
-        uint32_t* Wp = s_w[wave];
-        bool any = false;
+          for (int pb = 0; pb < 4; ++pb) gfa[pb][0] = gfa[pb][1] = zero4();
 #pragma unroll
-        for (int gq = 3; gq >= 0; --gq)
+          for (int bq = 0; bq < 2; ++bq)
 #pragma unroll
-          for (int r = 3; r >= 0; --r) {
-            const int q = 16 * bq + 4 * gq + r;
+            for (int ks = 0; ks < KP / 4; ++ks) {
+              const float a = s_f[(16 * bq + l16) * FST + 4 * ks + g4];
+#pragma unroll
+              for (int pb = 0; pb < 4; ++pb)
+                gfa[pb][bq] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g1[pb][ks], gfa[pb][bq], 0, 0, 0);
+            }
+#pragma unroll
+          for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              X[pb][r] = __float_as_uint(gfa[pb][0][r]);
+              X[pb][4 + r] = __float_as_uint(gfa[pb][1][r]);
+            }
+        }
+        // lane row g4 held Gaussians {4 g4 + r, 16 + 4 g4 + r} of all four pixel rows; now
+        // every lane holds its own pixel's values: X[g][4 bq + r] = gf of Gaussian 16 bq + 4 g + r
+        block_transpose(X);
+        if constexpr (SUMMARY) {
+#pragma unroll
+          for (int q = 0; q < kB; ++q) {
             const float4 r0 = s_rec[2 * q], r1 = s_rec[2 * q + 1];
             float dx, dy;
             const float pw = footprint_power(px, py, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, dx, dy);
-            const float G = fast_exp(pw);
-            const float araw = r1.w * G;
+            const float araw = r1.w * fast_exp(pw);
             const bool act = (q < cnt) & ((uint32_t)(lo + q) < last) & (araw >= amin);
             const float a = fminf(amax, araw);
-            const float rom = __builtin_amdgcn_rcpf(1.0f - a);
-            const float Tq = act ? T * rom : T;   // transmittance in front of this Gaussian
-            const float w = act ? a * Tq : 0.0f;
-            const float gf = __uint_as_float(X[gq][4 * bq + r]);
-            const float dalpha = Tq * gf - suffix * rom;
-            suffix = act ? __builtin_fmaf(gf, w, suffix) : suffix;
-            T = Tq;
-            const bool unclamped = act & (araw < amax);
-            const float dpow = unclamped ? dalpha * araw : 0.0f;
-            const float dop = unclamped ? dalpha * G : 0.0f;
-            Wp[(4 * gq + r) * kPs + lane] = act ? pack_hl(w) : 0u;
-            if (__ballot(act) != 0ull) {
-              any = true;
-              const float s0 = row_sum16(dpow * (r1.x * dx + r1.y * dy));   // d/d mean2d.x
-              const float s1 = row_sum16(dpow * (r1.z * dy + r1.y * dx));   // d/d mean2d.y
-              const float s2 = row_sum16(-0.5f * dpow * dx * dx);           // d/dA
-              const float s3 = row_sum16(-dpow * dx * dy);                  // d/dB
-              const float s4 = row_sum16(-0.5f * dpow * dy * dy);           // d/dC
-              const float s5 = row_sum16(dop);                              // d/d opacity
-              if (l16 == 0) {
-                float* dst = s_geo + q * 96 + wave * 4 + g4;
-                dst[0] = s0; dst[16] = s1; dst[32] = s2; dst[48] = s3; dst[64] = s4; dst[80] = s5;
+            const float gf = __uint_as_float(X[(q >> 2) & 3][4 * (q >> 4) + (q & 3)]);
+            acc = act ? __builtin_fmaf(a * T, gf, acc) : acc;
+            T = act ? T * (1.0f - a) : T;
+          }
+        } else {
+          // reverse recurrence, one 16-Gaussian block at a time (back to front)
+#pragma unroll
+          for (int bq = 1; bq >= 0; --bq) {
+            uint32_t* Wp = s_w[wave];
+            bool any = false;
+#pragma unroll
+            for (int gq = 3; gq >= 0; --gq)
+#pragma unroll
+              for (int r = 3; r >= 0; --r) {
+                const int q = 16 * bq + 4 * gq + r;
+                const float4 r0 = s_rec[2 * q], r1 = s_rec[2 * q + 1];
+                float dx, dy;
+                const float pw = footprint_power(px, py, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, dx, dy);
+                const float G = fast_exp(pw);
+                const float araw = r1.w * G;
+                const bool act = (q < cnt) & ((uint32_t)(lo + q) < last) & (araw >= amin);
+                const float a = fminf(amax, araw);
+                const float rom = __builtin_amdgcn_rcpf(1.0f - a);
+                const float Tq = act ? T * rom : T;   // transmittance in front of this Gaussian
+                const float w = act ? a * Tq : 0.0f;
+                const float gf = __uint_as_float(X[gq][4 * bq + r]);
+                const float dalpha = Tq * gf - acc * rom;
+                acc = act ? __builtin_fmaf(gf, w, acc) : acc;
+                T = Tq;
+                const bool unclamped = act & (araw < amax);
+                const float dpow = unclamped ? dalpha * araw : 0.0f;
+                const float dop = unclamped ? dalpha * G : 0.0f;
+                Wp[(4 * gq + r) * kPs + lane] = act ? pack_hl(w) : 0u;
+                if (__ballot(act) != 0ull) {
+                  any = true;
+                  const float s0 = row_sum16(dpow * (r1.x * dx + r1.y * dy));   // d/d mean2d.x
+                  const float s1 = row_sum16(dpow * (r1.z * dy + r1.y * dx));   // d/d mean2d.y
+                  const float s2 = row_sum16(-0.5f * dpow * dx * dx);           // d/dA
+                  const float s3 = row_sum16(-dpow * dx * dy);                  // d/dB
+                  const float s4 = row_sum16(-0.5f * dpow * dy * dy);           // d/dC
+                  const float s5 = row_sum16(dop);                              // d/d opacity
+                  if (l16 == 0) {
+                    float* dst = s_geo + q * 96 + wave * 4 + g4;
+                    dst[0] = s0; dst[16] = s1; dst[32] = s2; dst[48] = s3; dst[64] = s4; dst[80] = s5;
+                  }
+                }
+              }
+            wave_sync();
+            if (__ballot(any) != 0ull) {
+              // A = W^T (i = Gaussian l16 of the block, k = pixel 32 ks + 8 g4 + e)
+              v8bf wh[2], wl[2];
+#pragma unroll
+              for (int ks = 0; ks < 2; ++ks) load_op(Wp + l16 * kPs + 32 * ks + 8 * g4, wh[ks], wl[ks]);
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb) {
+                v4f d = zero4();
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) d = mma3(wh[ks], wl[ks], g2h[ks][cb], g2l[ks][cb], d);
+                // D[i][c]: Gaussian 16 bq + 4 g4 + r, channel 16 cb + l16
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                  if (d[r] != 0.0f) atomicAdd(&s_df[(16 * bq + 4 * g4 + r) * KP + 16 * cb + l16], d[r]);
               }
             }
-          }
-        wave_sync();
-        if (__ballot(any) != 0ull) {
-          // A = W^T (i = Gaussian l16 of the block, k = pixel 32 ks + 8 g4 + e)
-          v8bf wh[2], wl[2];
-#pragma unroll
-          for (int ks = 0; ks < 2; ++ks) load_op(Wp + l16 * kPs + 32 * ks + 8 * g4, wh[ks], wl[ks]);
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            v4f d = zero4();
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) d = mma3(wh[ks], wl[ks], g2h[ks][cb], g2l[ks][cb], d);
-            // D[i][c]: Gaussian 16 bq + 4 g4 + r, channel 16 cb + l16
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (d[r] != 0.0f) atomicAdd(&s_df[(16 * bq + 4 * g4 + r) * KP + 16 * cb + l16], d[r]);
+            wave_sync();   // the block's W is consumed before the next block overwrites it
           }
         }
-        wave_sync();   // the block's W is consumed before the next block overwrites it
       }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < cnt * KP; idx += 256) {
-      const int q = idx / KP, k = idx - q * KP;
-      const float val = s_df[idx];
-      if (val == 0.0f || k >= Kr) continue;
-      const uint32_t g = vals[c.start + lo + q];
-      if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
-      else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
-      else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
-    }
-    for (int idx = tid; idx < cnt * 6; idx += 256) {
-      const int q = idx / 6, comp = idx - q * 6;
-      const float* src = s_geo + q * 96 + comp * 16;
-      float sum = 0.0f;
+      if constexpr (!SUMMARY) {
+        lds_barrier();
+        for (int idx = tid; idx < cnt * KP; idx += 256) {
+          const int q = idx / KP, k = idx - q * KP;
+          const float val = s_df[idx];
+          if (val == 0.0f || k >= Kr) continue;
+          const uint32_t g = s_gid[q];
+          if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
+          else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
+          else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
+        }
+        for (int idx = tid; idx < cnt * 6; idx += 256) {
+          const int q = idx / 6, comp = idx - q * 6;
+          const float* src = s_geo + q * 96 + comp * 16;
+          float sum = 0.0f;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) sum += src[r];
-      if (sum != 0.0f) {
-        const uint32_t g = vals[c.start + lo + q];
-        atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + comp], sum);
+          for (int r = 0; r < 16; ++r) sum += src[r];
+          if (sum != 0.0f) {
+            const uint32_t g = s_gid[q];
+            atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + comp], sum);
+          }
+        }
       }
+    }
+    if constexpr (SUMMARY) {
+      segP[(int64_t)wi * kTilePx + tid] = T;
+      segGC[(int64_t)wi * kTilePx + tid] = acc;
     }
   }
 }
@@ -481,17 +610,100 @@ int launch_fwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected
   return launch_status();
 }
 
+// Caller workspace of the reverse pass: the segment work list, sized for `cap` duplicates.
+struct SegWs {
+  uint32_t *lmax, *cnt, *base, *partial, *ctl;
+  uint64_t* total;
+  uint2* work;
+  float *P, *GC;
+  int64_t max_segs;
+};
+
+size_t seg_layout(int n_tiles, int64_t cap, char* base, SegWs* w) {
+  const int64_t max_segs = (int64_t)n_tiles + ceil_div(cap, kSeg) + 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return base ? base + o : nullptr;
+  };
+  char* p_lmax = take(4 * (size_t)n_tiles);
+  char* p_cnt = take(4 * (size_t)n_tiles);
+  char* p_base = take(4 * (size_t)n_tiles);
+  char* p_part = take(4 * (size_t)scan_partials_needed(n_tiles));
+  char* p_tot = take(8);
+  char* p_ctl = take(16);
+  char* p_work = take(8 * (size_t)max_segs);
+  char* p_P = take(4 * (size_t)kTilePx * max_segs);
+  char* p_GC = take(4 * (size_t)kTilePx * max_segs);
+  if (w) {
+    w->lmax = (uint32_t*)p_lmax;
+    w->cnt = (uint32_t*)p_cnt;
+    w->base = (uint32_t*)p_base;
+    w->partial = (uint32_t*)p_part;
+    w->total = (uint64_t*)p_tot;
+    w->ctl = (uint32_t*)p_ctl;
+    w->work = (uint2*)p_work;
+    w->P = (float*)p_P;
+    w->GC = (float*)p_GC;
+    w->max_segs = max_segs;
+  }
+  return off;
+}
+
+// Blocks of a persistent launch: resident blocks per CU times CUs, per device and kernel.
+template <class F>
+int persistent_grid(F kernel) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess) return 0;
+  return std::max(1, cus * std::max(1, per));
+}
+
 template <int NS>
 int launch_bwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items, int n_items,
                  int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& fwd,
-                 const gs_images& gin, float* g2d, const gs_grads& gr, hipStream_t s) {
-  hipLaunchKernelGGL(k_render_bwd_split<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb, cfg.n_sem,
+                 const gs_images& gin, float* g2d, const gs_grads& gr, void* seg_ws, int64_t cap, hipStream_t s) {
+  SegWs w;
+  seg_layout(n_tiles, cap, (char*)seg_ws, &w);
+  hipLaunchKernelGGL(k_seg_count, dim3(n_tiles), dim3(256), 0, s, items, n_items, ranges, fwd.n_contrib, n_tiles,
+                     cfg.tile_order, w.lmax, w.cnt);
+  int st = launch_status();
+  st = st ? st : scan_u32(w.cnt, w.base, n_tiles, w.partial, w.total, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_seg_list, dim3((unsigned)ceil_div(n_tiles, 256)), dim3(256), 0, s, w.cnt, w.base, w.total,
+                     n_tiles, cfg.tile_order, w.max_segs, w.work, w.ctl);
+  static int grid_sum = 0, grid_main = 0;
+  if (!grid_sum) grid_sum = persistent_grid(k_render_bwd_split<NS, true>);
+  if (!grid_main) grid_main = persistent_grid(k_render_bwd_split<NS, false>);
+  if (!grid_sum || !grid_main) return GS_ERR_HIP;
+  hipLaunchKernelGGL((k_render_bwd_split<NS, true>), dim3(grid_sum), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb, cfg.n_sem,
                      p.rec, p.depth, g.n, items, n_items, vals, ranges, fwd.T, fwd.n_contrib, gin.color, g2d, gr.rgb,
-                     gr.sem);
+                     gr.sem, w.work, w.ctl, w.lmax, w.P, w.GC);
+  hipLaunchKernelGGL((k_render_bwd_split<NS, false>), dim3(grid_main), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb,
+                     cfg.n_sem, p.rec, p.depth, g.n, items, n_items, vals, ranges, fwd.T, fwd.n_contrib, gin.color, g2d,
+                     gr.rgb, gr.sem, w.work, w.ctl, w.lmax, w.P, w.GC);
   return launch_status();
 }
 
 }  // namespace
+
+size_t render_seg_workspace(int n_tiles, int64_t dup_capacity) {
+  return seg_layout(n_tiles, std::max<int64_t>(dup_capacity, 0), nullptr, nullptr);
+}
+
+// Largest duplicate capacity whose segment workspace fits in `bytes` (-1 if none does).
+int64_t render_seg_capacity(int n_tiles, size_t bytes) {
+  if (render_seg_workspace(n_tiles, 0) > bytes) return -1;
+  int64_t lo = 0, hi = 1;
+  while (hi < ((int64_t)1 << 40) && render_seg_workspace(n_tiles, hi) <= bytes) hi *= 2;
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (render_seg_workspace(n_tiles, mid) <= bytes) lo = mid; else hi = mid;
+  }
+  return lo;
+}
 
 int launch_render_fwd_split(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
                             int n_items, int n_tiles, const uint32_t* vals, const uint32_t* ranges,
@@ -504,10 +716,14 @@ int launch_render_fwd_split(const gs_config& cfg, const gs_gaussians& g, const g
 
 int launch_render_bwd_split(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items,
                             int n_items, int n_tiles, const uint32_t* vals, const uint32_t* ranges,
-                            const gs_images& fwd, const gs_images& gin, float* g2d, const gs_grads& gr, hipStream_t s) {
+                            const gs_images& fwd, const gs_images& gin, float* g2d, const gs_grads& gr, void* seg_ws,
+                            int64_t cap, hipStream_t s) {
   const int ns = cfg.n_sem;
-  if (ns <= 28) return launch_bwd_s<28>(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
-  if (ns <= 60) return launch_bwd_s<60>(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
+  if (cap < 0) return GS_ERR_WORKSPACE;
+  if (ns <= 28)
+    return launch_bwd_s<28>(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, seg_ws, cap, s);
+  if (ns <= 60)
+    return launch_bwd_s<60>(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, seg_ws, cap, s);
   return GS_ERR_UNSUPPORTED;
 }
 

@@ -68,7 +68,8 @@ class ViewState:
         self.img = raster.alloc_images(cfg_learned, self.fr, C, learned=True)
         self.grad = dict(color=torch.zeros_like(self.img["color"]), logits=torch.empty_like(self.img["logits"]))
         self.grads = raster.alloc_grads(cfg_learned, g_learned, self.fr, C)
-        self.ws = torch.empty(raster.workspace_bytes(raster.L.GS_WS_RENDER_BWD, cfg_learned, self.fr, n),
+        self.ws = torch.empty(raster.workspace_bytes(raster.L.GS_WS_RENDER_BWD, cfg_learned, self.fr, n,
+                                                     self.sorter.capacity),
                               dtype=torch.uint8, device=device)
         self.loss = torch.empty(1, dtype=torch.float32, device=device)
         self.dws = torch.empty(256, dtype=torch.uint8, device=device)

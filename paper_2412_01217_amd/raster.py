@@ -246,7 +246,8 @@ def render_bwd(cfg, g: dict, proj: dict, frame: Frame, sorter: Sorter, fwd: dict
     n = int(g["mean"].shape[0])
     grads = grads or alloc_grads(cfg, g, frame, int(head["b2"].shape[0]) if head is not None else 0)
     if ws is None:
-        ws = torch.empty(workspace_bytes(L.GS_WS_RENDER_BWD, cfg, frame, n), dtype=torch.uint8, device=frame.device)
+        ws = torch.empty(workspace_bytes(L.GS_WS_RENDER_BWD, cfg, frame, n, sorter.capacity), dtype=torch.uint8,
+                         device=frame.device)
     gs = gaussians_struct(g)
     ps = _projected(proj)
     fi = _images(fwd, frame.n_pixels)

@@ -37,7 +37,8 @@ class MappingStep:
         self.loss_ws = torch.empty(raster.workspace_bytes(L.GS_WS_LOSS, cfg, frame, n), dtype=torch.uint8,
                                    device=dev)
         self.grads = raster.alloc_grads(cfg, g, frame, n_classes)
-        self.bwd_ws = torch.empty(raster.workspace_bytes(L.GS_WS_RENDER_BWD, cfg, frame, n), dtype=torch.uint8,
+        self.bwd_ws = torch.empty(raster.workspace_bytes(L.GS_WS_RENDER_BWD, cfg, frame, n, self.sorter.capacity),
+                                  dtype=torch.uint8,
                                   device=dev)
 
     def run(self, ev=None):

@@ -35,6 +35,11 @@ CASES = {
     "room_ragged_3lv": lambda: small_room(),
     "room_two_views": lambda: (lambda sc: (sc, scenes.room_views(sc, 2, 96, 80, levels=2, seed=77)))(
         scenes.room_scene(n=4000, n_classes=5, seed=1077, log_mu=-3.3)),
+    # coarse tiles with lists of up to ~3000 blended Gaussians: the reverse pass cuts them
+    # into several segments
+    "room_long_lists": lambda: (lambda sc: (sc, scenes.room_views(sc, 1, 128, 96, fx=64, levels=3,
+                                                                 seed=scenes.SEED_VIEWS + 30)))(
+        scenes.room_scene(n=12000, n_classes=6, seed=scenes.SEED_SCENE + 30, log_mu=-3.2)),
 }
 
 
@@ -207,16 +212,31 @@ def _shared_grad_image(fr, K, seed):
 @pytest.mark.parametrize("variant", list(VARIANTS))
 @pytest.mark.parametrize("case", list(CASES))
 def test_render_bwd_parity(case, variant):
+    _check_render_bwd(case, VARIANTS[variant])
+
+
+def test_render_bwd_single_item_fallback():
+    """A workspace sized without the duplicate capacity cannot hold every segment of the
+    long lists; the reverse pass then takes each tile as one work item."""
+    _check_render_bwd("room_long_lists", 3, small_workspace=True)
+
+
+def _check_render_bwd(case, variant, small_workspace=False):
     sc, views = CASES[case]()
-    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, VARIANTS[variant])
+    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant)
     raster = _raster()
+    ws = None
+    if small_workspace:
+        nb = raster.workspace_bytes(raster.L.GS_WS_RENDER_BWD, cfg, fr, sc.n, 0)
+        assert nb < raster.workspace_bytes(raster.L.GS_WS_RENDER_BWD, cfg, fr, sc.n, srt.capacity)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     K = 4 + sc.n_classes
     gimg = _shared_grad_image(fr, K, seed=5200)
     # pixels whose forward decisions sit within rounding of a threshold get no upstream
     # gradient, so they cannot contribute to any parameter's gradient on either side
     r = oracle.render(oracle.Config(), sc, views)
     gimg[pixel_mask_to_channels(r["flag"] != 0, oracle.items(views), K)] = 0.0
-    grads = raster.render_bwd(cfg, g, proj, fr, srt, img, dict(color=torch.from_numpy(gimg).cuda()))
+    grads = raster.render_bwd(cfg, g, proj, fr, srt, img, dict(color=torch.from_numpy(gimg).cuda()), ws=ws)
     torch.cuda.synchronize()
     ref = oracle.backward(oracle.Config(), sc, views, gimg)
     # features enter linearly: sum_p w |g_p| bounds their gradients' terms
