@@ -78,14 +78,40 @@ __device__ __forceinline__ void load_op(const uint32_t* p, v8bf& hi, v8bf& lo) {
   unpack8(a, b, hi, lo);
 }
 
-// Splits eight floats into hi and lo operands.
+// Splits eight floats into hi and lo operands, two values per conversion.
 __device__ __forceinline__ void split8(const float* x, v8bf& hi, v8bf& lo) {
+  uint32_t h[4], l[4];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const __bf16 h = (__bf16)x[e];
-    hi[e] = h;
-    lo[e] = (__bf16)(x[e] - (float)h);
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t hb = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){x[2 * k], x[2 * k + 1]}, bf2));
+    const float h0 = __uint_as_float(hb << 16), h1 = __uint_as_float(hb & 0xffff0000u);
+    h[k] = hb;
+    l[k] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){x[2 * k] - h0, x[2 * k + 1] - h1}, bf2));
   }
+  hi = __builtin_bit_cast(v8bf, make_uint4(h[0], h[1], h[2], h[3]));
+  lo = __builtin_bit_cast(v8bf, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
+// The render record as the compositing loops read it from LDS, per Gaussian two float4:
+//   (mx, my, -, -)  mean2d relative to the centre of the tile's first pixel, so that a
+//                   pixel's offset is its integer position in the tile minus (mx, my);
+//   (a, b, c, o)    the conic scaled so that a dx^2 + b dx dy + c dy^2 is the exponent of
+//                   eq. 4 in base 2: a = -A log2(e) / 2, b = -B log2(e), c = -C log2(e) / 2.
+// The mean's hi + lo sum is rounded once, after the exact subtraction of the tile origin.
+constexpr float kLog2e = 1.4426950408889634f;
+__device__ __forceinline__ float4 local_rec(const float4 r, int part, float ox, float oy) {
+  if (part == 0) return make_float4((r.x - ox) + r.z, (r.y - oy) + r.w, 0.0f, 0.0f);
+  return make_float4(-0.5f * kLog2e * r.x, -kLog2e * r.y, -0.5f * kLog2e * r.z, r.w);
+}
+
+// Base-2 footprint exponent at tile-local pixel (lx, ly), clamped at zero; dx, dy are the
+// pixel's offsets from the mean and t = a dx + b dy.
+__device__ __forceinline__ float local_power2(float lx, float ly, const float4 r0, const float4 r1, float& dx,
+                                              float& dy, float& t) {
+  dx = lx - r0.x;
+  dy = ly - r0.y;
+  t = __builtin_fmaf(r1.x, dx, r1.y * dy);
+  return fminf(__builtin_fmaf(t, dx, (r1.z * dy) * dy), 0.0f);
 }
 
 __device__ __forceinline__ v4f mma(v8bf a, v8bf b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
@@ -139,18 +165,18 @@ struct SStage {
     }
   }
   // features Gaussian-major, single precision: s_f[q][c]; Gaussian ids to s_gid[q]
-  __device__ __forceinline__ void commit_rows(float4* s_rec, float* s_f, uint32_t* s_gid) const {
+  __device__ __forceinline__ void commit_rows(float4* s_rec, float* s_f, uint32_t* s_gid, float ox, float oy) const {
     const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
-    if (part < 2) s_rec[2 * q + part] = r;
+    if (part < 2) s_rec[2 * q + part] = local_rec(r, part, ox, oy);
     if (part == 0) s_gid[q] = gid;
     float* dst = s_f + q * SShape<NS>::FST + part * CPT;
 #pragma unroll
     for (int j = 0; j < CPT; j += 4) *reinterpret_cast<float4*>(dst + j) = make_float4(f[j], f[j + 1], f[j + 2], f[j + 3]);
   }
   // features channel-major: s_f[c][q]
-  __device__ __forceinline__ void commit_cols(float4* s_rec, uint32_t* s_f) const {
+  __device__ __forceinline__ void commit_cols(float4* s_rec, uint32_t* s_f, float ox, float oy) const {
     const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
-    if (part < 2) s_rec[2 * q + part] = r;
+    if (part < 2) s_rec[2 * q + part] = local_rec(r, part, ox, oy);
 #pragma unroll
     for (int j = 0; j < CPT; ++j) s_f[(part * CPT + j) * kWs + q] = pack_hl(f[j]);
   }
@@ -171,14 +197,15 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
   constexpr int CB = S::CB, KP = S::KP;
   __shared__ float4 s_rec[2 * kB];
   __shared__ uint32_t s_f[KP * kWs];          // F^T, packed hi|lo, [channel][Gaussian]
-  __shared__ uint32_t s_w[4][64 * kWs];       // per wave W, packed hi|lo, [pixel][Gaussian]
+  __shared__ float s_w[4][64 * kWs];          // per wave W, [pixel][Gaussian]
   const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, g4 = lane >> 4;
   int u, v;
   tile_pixel(c, tid, u, v);
   const bool inside = u < c.W && v < c.H;
-  const float px = u + 0.5f, py = v + 0.5f;
+  const float lx = (float)(tid & 15), ly = (float)(tid >> 4);
+  const float ox = (float)(c.tx * kTile) + 0.5f, oy = (float)(c.ty * kTile) + 0.5f;
   v4f acc[CB][4];
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb)
@@ -188,14 +215,14 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
   bool done = !inside;
   uint32_t last = 0;
   const float amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
-  uint32_t* W = s_w[wave];
+  float* W = s_w[wave];
   SStage<NS> st;
   if (c.start < c.end)
     st.fetch(vals, c.start, (int)min((uint32_t)kB, c.end - c.start), c.item, n, rec, depth, rgb, sem, emb, n_sem);
   for (uint32_t b = c.start; b < c.end; b += kB) {
     // every wave is past the previous batch's LDS reads; stop once every pixel has
     if (__syncthreads_count(!done) == 0) break;
-    st.commit_cols(s_rec, s_f);
+    st.commit_cols(s_rec, s_f, ox, oy);
     __syncthreads();
     const int cnt = (int)min((uint32_t)kB, c.end - b);
     if (b + kB < c.end)
@@ -205,26 +232,25 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
     const uint32_t base = b - c.start;
 #pragma unroll
     for (int q4 = 0; q4 < kB; q4 += 4) {
-      uint32_t pk[4];
+      float wq[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int q = q4 + e;
         const float4 r0 = s_rec[2 * q], r1 = s_rec[2 * q + 1];
-        float dx, dy;
-        const float pw = footprint_power(px, py, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, dx, dy);
-        const float araw = r1.w * fast_exp(pw);
+        float dx, dy, t;
+        const float araw = r1.w * __builtin_amdgcn_exp2f(local_power2(lx, ly, r0, r1, dx, dy, t));
         const bool ok = (q < cnt) & !done & (araw >= amin);
-        const float a = fminf(amax, araw);
-        const float Tn = T * (1.0f - a);
+        const float w = fminf(amax, araw) * T;
+        const float Tn = T - w;
         const bool stop = ok & (Tn < tmin);
         const bool take = ok & !stop;
-        pk[e] = take ? pack_hl(a * T) : 0u;
+        wq[e] = take ? w : 0.0f;
         T = take ? Tn : T;
         done = done | stop;
         last = take ? base + q + 1 : last;
         took |= take;
       }
-      *reinterpret_cast<uint4*>(W + lane * kWs + q4) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+      *reinterpret_cast<float4*>(W + lane * kWs + q4) = make_float4(wq[0], wq[1], wq[2], wq[3]);
     }
     wave_sync();
     if (__ballot(took) == 0ull) continue;
@@ -235,8 +261,11 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
     for (int cb = 0; cb < CB; ++cb) load_op(s_f + (16 * cb + l16) * kWs + 8 * g4, ah[cb], al[cb]);
 #pragma unroll
     for (int pb = 0; pb < 4; ++pb) {
+      const float* src = W + (16 * pb + l16) * kWs + 8 * g4;
+      const float4 w0 = *reinterpret_cast<const float4*>(src), w1 = *reinterpret_cast<const float4*>(src + 4);
+      const float x[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
       v8bf bh, bl;
-      load_op(W + (16 * pb + l16) * kWs + 8 * g4, bh, bl);
+      split8(x, bh, bl);
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc[cb][pb] = mma3(ah[cb], al[cb], bh, bl, acc[cb][pb]);
     }
@@ -293,6 +322,12 @@ __device__ __forceinline__ void block_transpose(uint32_t (&X)[4][8]) {
 //   GC_s = sum over its blended Gaussians of alpha T_loc (g . f),     T_loc from 1
 // and then T_after(s) = prod_{s' <= s} P_s' and suffix(s) = sum_{s' > s} T_before(s') GC_s'.
 constexpr int kSeg = 256;
+
+// With the exponent E = a dx^2 + b dx dy + c dy^2 of the local record (E = log2(e) power),
+// d power/d mean2d = -(dE/d dx, dE/d dy) / log2(e) and d power/d(A, B, C) =
+// -(dx^2 / 2, dx dy, dy^2 / 2); the reverse pass sums dE/d dx, dE/d dy, dx^2, dx dy, dy^2
+// (times dL/d power) and applies these factors once per Gaussian.
+__constant__ float kGeoScale[6] = {-1.0f / kLog2e, -1.0f / kLog2e, -0.5f, -1.0f, -0.5f, 1.0f};
 
 // One block per tile: the tile's list length in use (largest n_contrib) and its segment
 // count, stored in work order (coarse pyramid levels first unless tile_order = 1).
@@ -365,7 +400,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
   constexpr int KP = S::KP, CB = S::CB, FST = S::FST;
   __shared__ float4 s_rec[2 * kB];
   __shared__ float s_f[kB * FST];             // F, [Gaussian][channel]
-  __shared__ uint32_t s_w[SUMMARY ? 1 : 4][16 * kPs];   // per wave, 16 Gaussians: W packed hi|lo, [Gaussian][pixel]
+  __shared__ float s_w[SUMMARY ? 1 : 4][16 * kPs];      // per wave, 16 Gaussians: W, [Gaussian][pixel]
   __shared__ float s_df[SUMMARY ? 1 : kB * KP];
   __shared__ float s_geo[SUMMARY ? 1 : kB * 6 * 16];     // [Gaussian][component][row slot]
   __shared__ uint32_t s_wi;
@@ -389,7 +424,8 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
     int u, v;
     tile_pixel(c, tid, u, v);
     const bool inside = u < c.W && v < c.H;
-    const float px = u + 0.5f, py = v + 0.5f;
+    const float lx = (float)(tid & 15), ly = (float)(tid >> 4);
+    const float ox = (float)(c.tx * kTile) + 0.5f, oy = (float)(c.ty * kTile) + 0.5f;
     const int64_t pix = c.pixel_base + (int64_t)v * c.W + u;
     // n_contrib comes from the matching forward; clamp so that a mismatched call stays in range
     const uint32_t len = c.end - c.start;
@@ -455,7 +491,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
       const int hi = SUMMARY ? min(b0, lo + kB) : b0 - bi * kB;
       const int cnt = hi - lo;
       lds_barrier();
-      st.commit_rows(s_rec, s_f, s_gid);
+      st.commit_rows(s_rec, s_f, s_gid, ox, oy);
       if constexpr (!SUMMARY) {
         for (int i = tid; i < kB * KP; i += 256) s_df[i] = 0.0f;
         for (int i = tid; i < kB * 6 * 16; i += 256) s_geo[i] = 0.0f;
@@ -498,20 +534,19 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
 #pragma unroll
           for (int q = 0; q < kB; ++q) {
             const float4 r0 = s_rec[2 * q], r1 = s_rec[2 * q + 1];
-            float dx, dy;
-            const float pw = footprint_power(px, py, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, dx, dy);
-            const float araw = r1.w * fast_exp(pw);
+            float dx, dy, t;
+            const float araw = r1.w * __builtin_amdgcn_exp2f(local_power2(lx, ly, r0, r1, dx, dy, t));
             const bool act = (q < cnt) & ((uint32_t)(lo + q) < last) & (araw >= amin);
-            const float a = fminf(amax, araw);
+            const float w = fminf(amax, araw) * T;
             const float gf = __uint_as_float(X[(q >> 2) & 3][4 * (q >> 4) + (q & 3)]);
-            acc = act ? __builtin_fmaf(a * T, gf, acc) : acc;
-            T = act ? T * (1.0f - a) : T;
+            acc = act ? __builtin_fmaf(w, gf, acc) : acc;
+            T = act ? T - w : T;
           }
         } else {
           // reverse recurrence, one 16-Gaussian block at a time (back to front)
 #pragma unroll
           for (int bq = 1; bq >= 0; --bq) {
-            uint32_t* Wp = s_w[wave];
+            float* Wp = s_w[wave];
             bool any = false;
 #pragma unroll
             for (int gq = 3; gq >= 0; --gq)
@@ -519,9 +554,8 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
               for (int r = 3; r >= 0; --r) {
                 const int q = 16 * bq + 4 * gq + r;
                 const float4 r0 = s_rec[2 * q], r1 = s_rec[2 * q + 1];
-                float dx, dy;
-                const float pw = footprint_power(px, py, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, dx, dy);
-                const float G = fast_exp(pw);
+                float dx, dy, t;
+                const float G = __builtin_amdgcn_exp2f(local_power2(lx, ly, r0, r1, dx, dy, t));
                 const float araw = r1.w * G;
                 const bool act = (q < cnt) & ((uint32_t)(lo + q) < last) & (araw >= amin);
                 const float a = fminf(amax, araw);
@@ -535,15 +569,17 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
                 const bool unclamped = act & (araw < amax);
                 const float dpow = unclamped ? dalpha * araw : 0.0f;
                 const float dop = unclamped ? dalpha * G : 0.0f;
-                Wp[(4 * gq + r) * kPs + lane] = act ? pack_hl(w) : 0u;
+                Wp[(4 * gq + r) * kPs + lane] = w;
                 if (__ballot(act) != 0ull) {
                   any = true;
-                  const float s0 = row_sum16(dpow * (r1.x * dx + r1.y * dy));   // d/d mean2d.x
-                  const float s1 = row_sum16(dpow * (r1.z * dy + r1.y * dx));   // d/d mean2d.y
-                  const float s2 = row_sum16(-0.5f * dpow * dx * dx);           // d/dA
-                  const float s3 = row_sum16(-dpow * dx * dy);                  // d/dB
-                  const float s4 = row_sum16(-0.5f * dpow * dy * dy);           // d/dC
-                  const float s5 = row_sum16(dop);                              // d/d opacity
+                  // d power / d (mean2d, A, B, C) up to the per-component factors of kGeoScale
+                  const float pdx = dpow * dx, pdy = dpow * dy;
+                  const float s0 = row_sum16(dpow * __builtin_fmaf(r1.x, dx, t));   // 2a dx + b dy
+                  const float s1 = row_sum16(dpow * __builtin_fmaf(r1.y, dx, 2.0f * (r1.z * dy)));
+                  const float s2 = row_sum16(pdx * dx);
+                  const float s3 = row_sum16(pdx * dy);
+                  const float s4 = row_sum16(pdy * dy);
+                  const float s5 = row_sum16(dop);                                  // d/d opacity
                   if (l16 == 0) {
                     float* dst = s_geo + q * 96 + wave * 4 + g4;
                     dst[0] = s0; dst[16] = s1; dst[32] = s2; dst[48] = s3; dst[64] = s4; dst[80] = s5;
@@ -555,7 +591,12 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
               // A = W^T (i = Gaussian l16 of the block, k = pixel 32 ks + 8 g4 + e)
               v8bf wh[2], wl[2];
 #pragma unroll
-              for (int ks = 0; ks < 2; ++ks) load_op(Wp + l16 * kPs + 32 * ks + 8 * g4, wh[ks], wl[ks]);
+              for (int ks = 0; ks < 2; ++ks) {
+                const float* src = Wp + l16 * kPs + 32 * ks + 8 * g4;
+                const float4 w0 = *reinterpret_cast<const float4*>(src), w1 = *reinterpret_cast<const float4*>(src + 4);
+                const float x[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+                split8(x, wh[ks], wl[ks]);
+              }
 #pragma unroll
               for (int cb = 0; cb < CB; ++cb) {
                 v4f d = zero4();
@@ -590,7 +631,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
           for (int r = 0; r < 16; ++r) sum += src[r];
           if (sum != 0.0f) {
             const uint32_t g = s_gid[q];
-            atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + comp], sum);
+            atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + comp], sum * kGeoScale[comp]);
           }
         }
       }
