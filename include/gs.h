@@ -60,6 +60,9 @@ typedef struct gs_config {
                               matrix cores, 3 bfloat16 matrix cores with hi/lo split operands
                               (single-precision accurate to about 2^-16 relative) */
   int32_t tile_order;      /* 0: coarse pyramid levels (longest tile lists) launched first; 1: item order */
+  int32_t fwd_chunk;       /* 1: forward with a state (gs_images.state), variant 3: 256-entry segments
+                              walked per work item, 1..65535 (a transmittance pre-pass gives every
+                              chunk but a list's first its starting T), or 0 = whole lists */
 } gs_config;
 
 /* One camera view: world -> camera transform x_c = R x_w + t (OpenCV axes,
@@ -111,6 +114,15 @@ typedef struct gs_images {
   uint32_t* n_contrib;   /* [P] 1 + list position of the last blended Gaussian, 0 if none */
   float* logits;         /* [P * n_classes] learned mode decoded logits, else NULL */
   int64_t n_pixels;      /* P, the total pixel count of all items (read in learned mode) */
+  /* Forward output, optional (NULL: none; ignored by render variants 1 and 2): a caller
+   * buffer of state_bytes >= gs_workspace_size(GS_WS_RENDER_STATE) bytes. With it, the
+   * forward cuts tile lists longer than 256 entries into 256-entry segments composited
+   * in parallel (a transmittance pre-pass gives each its starting T) and keeps, per
+   * segment and pixel, what the reverse pass needs to start a segment: gs_render_bwd
+   * given these images then skips its summary pass. Overwritten by every forward; read
+   * by the backward, which must get the same images. */
+  void* state;
+  size_t state_bytes;
 } gs_images;
 
 /* Targets of the loss (the image pyramid of eq. 4-6). */
@@ -148,7 +160,7 @@ typedef struct gs_grads {
   float* head_b2;    /* [n_classes] */
 } gs_grads;
 
-enum gs_workspace_kind { GS_WS_BIN_SORT = 1, GS_WS_RENDER_BWD = 2, GS_WS_LOSS = 3 };
+enum gs_workspace_kind { GS_WS_BIN_SORT = 1, GS_WS_RENDER_BWD = 2, GS_WS_LOSS = 3, GS_WS_RENDER_STATE = 4 };
 
 /* ---- helpers --------------------------------------------------------------- */
 void gs_config_default(gs_config* cfg);
@@ -164,7 +176,10 @@ int gs_version(void);
 int gs_make_items(const gs_config* cfg, int32_t n_views, gs_view* views, const int32_t* W, const int32_t* H,
                   const float* K, const int32_t* levels, gs_item* items, int64_t* n_pixels, int32_t* n_tiles);
 
-/* Bytes of caller workspace a call needs (kind = gs_workspace_kind). */
+/* Bytes of caller workspace a call needs (kind = gs_workspace_kind). GS_WS_RENDER_STATE
+ * (the optional gs_images.state of a forward) depends on n_tiles, dup_capacity (the
+ * bin_sort capacity the lists come from) and cfg->n_sem; a smaller buffer still works
+ * when the lists' segments fit it, and makes every tile one item when they do not. */
 int gs_workspace_size(int kind, const gs_config* cfg, int32_t n_items, int64_t n_gauss, int32_t n_tiles,
                       int64_t dup_capacity, int64_t n_pixels, size_t* bytes);
 

@@ -22,6 +22,7 @@ GS_ERR_UNSUPPORTED = -5
 GS_WS_BIN_SORT = 1
 GS_WS_RENDER_BWD = 2
 GS_WS_LOSS = 3
+GS_WS_RENDER_STATE = 4
 
 # Every symbol include/gs.h declares.
 EXPORTS = (
@@ -35,7 +36,8 @@ EXPORTS = (
 class Config(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("z_near", c_float), ("eps_dilate", c_float),
                 ("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("guard", c_float),
-                ("full_rect", c_int32), ("n_sem", c_int32), ("variant", c_int32), ("tile_order", c_int32)]
+                ("full_rect", c_int32), ("n_sem", c_int32), ("variant", c_int32), ("tile_order", c_int32),
+                ("fwd_chunk", c_int32)]
 
 
 class View(ctypes.Structure):
@@ -59,7 +61,7 @@ class Projected(ctypes.Structure):
 
 class Images(ctypes.Structure):
     _fields_ = [("color", c_void_p), ("T", c_void_p), ("n_contrib", c_void_p), ("logits", c_void_p),
-                ("n_pixels", c_int64)]
+                ("n_pixels", c_int64), ("state", c_void_p), ("state_bytes", ctypes.c_size_t)]
 
 
 class Targets(ctypes.Structure):

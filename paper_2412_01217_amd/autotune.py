@@ -2,7 +2,8 @@
 
 For one workload signature (Gaussian count, channels, items, pixels, tiles) it times
 each candidate launch configuration -- render kernel variant (per-lane FMA, single-precision
-or split-bfloat16 matrix cores) and tile launch order (coarse pyramid levels first, or item order) -- as HIP
+or split-bfloat16 matrix cores), tile launch order (coarse pyramid levels first, or item order)
+and the forward's work item (256-entry segments of long lists, or whole lists) -- as HIP
 graph replays of the whole step, keeps the fastest, and caches the choice in a JSON
 file (GS_AUTOTUNE_CACHE, default ~/.cache/gs_autotune.json) keyed by device and
 signature. Every candidate computes the same result; only the schedule differs.
@@ -14,8 +15,10 @@ import os
 
 import torch
 
-CANDIDATES = ({"variant": 3, "tile_order": 0}, {"variant": 3, "tile_order": 1}, {"variant": 2, "tile_order": 0},
-              {"variant": 1, "tile_order": 1})
+# every candidate sets every key, so that none inherits a value from the previous one
+CANDIDATES = ({"variant": 3, "tile_order": 0, "fwd_chunk": 1}, {"variant": 3, "tile_order": 0, "fwd_chunk": 0},
+              {"variant": 3, "tile_order": 1, "fwd_chunk": 1}, {"variant": 2, "tile_order": 0, "fwd_chunk": 1},
+              {"variant": 1, "tile_order": 1, "fwd_chunk": 1})
 
 
 def cache_path() -> str:

@@ -39,6 +39,8 @@ int launch_render_bwd_split(const gs_config&, const gs_gaussians&, const gs_proj
                             const gs_grads&, void*, int64_t, hipStream_t);
 size_t render_seg_workspace(int n_tiles, int64_t dup_capacity);
 int64_t render_seg_capacity(int n_tiles, size_t bytes);
+size_t render_state_bytes(int n_tiles, int64_t dup_capacity, int K);
+int64_t render_state_capacity(int n_tiles, int K, size_t bytes);
 
 // Render kernel variants: 1 = per-lane FMA accumulation (VALU), 2 = single-precision
 // matrix-core channel contraction, 3 = every contraction on the bfloat16 matrix cores with
@@ -87,6 +89,7 @@ bool cfg_ok(const gs_config* c) {
   if (c->n_sem < 0 || c->n_sem > 60) return false;
   if (c->variant < 0 || c->variant > 3) return false;
   if (c->tile_order < 0 || c->tile_order > 1) return false;
+  if (c->fwd_chunk < 0 || c->fwd_chunk > 65535) return false;
   return true;
 }
 
@@ -121,6 +124,7 @@ void gs_config_default(gs_config* c) {
   c->n_sem = 0;
   c->variant = 0;
   c->tile_order = 0;
+  c->fwd_chunk = 1;
 }
 
 const char* gs_status_string(int s) {
@@ -192,6 +196,9 @@ int gs_workspace_size(int kind, const gs_config* cfg, int32_t n_items, int64_t n
     case GS_WS_LOSS:
       *bytes = align_up(loss_workspace(n_items));
       return GS_OK;
+    case GS_WS_RENDER_STATE:
+      *bytes = render_state_bytes(n_tiles, dup_capacity, 4 + cfg->n_sem);
+      return GS_OK;
     default:
       return GS_ERR_INVALID_ARG;
   }
@@ -231,6 +238,7 @@ int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   if (!learned && cfg->n_sem > 0 && g->n > 0 && !g->sem) return GS_ERR_INVALID_ARG;
   if (n_tiles == 0) return GS_OK;
   if (!items_dev || !vals || !ranges || !out->color || !out->T || !out->n_contrib) return GS_ERR_INVALID_ARG;
+  if (out->state && render_state_capacity(n_tiles, 4 + cfg->n_sem, out->state_bytes) < 0) return GS_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   int st = launch_render_fwd(*cfg, *g, *proj, items_dev, n_items, n_tiles, vals, ranges, *out, s);
   if (st || !learned) return st;
@@ -299,6 +307,7 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   if (n == 0) return GS_OK;
   if (n_tiles > 0) {
     if (!items_dev || !vals || !ranges || !fwd->T || !fwd->n_contrib || !grad_in->color) return GS_ERR_INVALID_ARG;
+    if (fwd->state && render_state_capacity(n_tiles, 4 + cfg->n_sem, fwd->state_bytes) < 0) return GS_ERR_WORKSPACE;
     st = launch_render_bwd(*cfg, *g, *proj, items_dev, n_items, n_tiles, vals, ranges, *fwd, *grad_in, (float*)workspace,
                            gr, seg_ws, cap, s);
     if (st) return st;

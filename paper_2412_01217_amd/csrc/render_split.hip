@@ -92,26 +92,42 @@ __device__ __forceinline__ void split8(const float* x, v8bf& hi, v8bf& lo) {
   lo = __builtin_bit_cast(v8bf, make_uint4(l[0], l[1], l[2], l[3]));
 }
 
-// The render record as the compositing loops read it from LDS, per Gaussian two float4:
-//   (mx, my, -, -)  mean2d relative to the centre of the tile's first pixel, so that a
-//                   pixel's offset is its integer position in the tile minus (mx, my);
-//   (a, b, c, o)    the conic scaled so that a dx^2 + b dx dy + c dy^2 is the exponent of
-//                   eq. 4 in base 2: a = -A log2(e) / 2, b = -B log2(e), c = -C log2(e) / 2.
+// The render record as the compositing loops read it from LDS, 8 floats per Gaussian:
+//   mx, my   mean2d relative to the centre of the tile's first pixel, so that a pixel's
+//            offset is its integer position in the tile minus (mx, my);
+//   a, b, c  the conic scaled so that a dx^2 + b dx dy + c dy^2 is the exponent of eq. 4
+//            in base 2: a = -A log2(e) / 2, b = -B log2(e), c = -C log2(e) / 2;
+//   o        opacity (two floats of padding).
 // The mean's hi + lo sum is rounded once, after the exact subtraction of the tile origin.
 constexpr float kLog2e = 1.4426950408889634f;
-__device__ __forceinline__ float4 local_rec(const float4 r, int part, float ox, float oy) {
-  if (part == 0) return make_float4((r.x - ox) + r.z, (r.y - oy) + r.w, 0.0f, 0.0f);
-  return make_float4(-0.5f * kLog2e * r.x, -kLog2e * r.y, -0.5f * kLog2e * r.z, r.w);
+struct LRec {
+  float4 m;   // mx, my, a, b
+  float2 c;   // c, o
+};
+// Stages half of a render record (part 0: mean hi, lo; part 1: conic, opacity).
+__device__ __forceinline__ void stage_rec(float* s_rec, int q, const float4 r, int part, float ox, float oy) {
+  float* d = s_rec + 8 * q;
+  if (part == 0) {
+    *reinterpret_cast<float2*>(d) = make_float2((r.x - ox) + r.z, (r.y - oy) + r.w);
+  } else {
+    *reinterpret_cast<float2*>(d + 2) = make_float2(-0.5f * kLog2e * r.x, -kLog2e * r.y);
+    *reinterpret_cast<float2*>(d + 4) = make_float2(-0.5f * kLog2e * r.z, r.w);
+  }
+}
+__device__ __forceinline__ LRec load_rec(const float* s_rec, int q) {
+  LRec r;
+  r.m = *reinterpret_cast<const float4*>(s_rec + 8 * q);
+  r.c = *reinterpret_cast<const float2*>(s_rec + 8 * q + 4);
+  return r;
 }
 
 // Base-2 footprint exponent at tile-local pixel (lx, ly), clamped at zero; dx, dy are the
 // pixel's offsets from the mean and t = a dx + b dy.
-__device__ __forceinline__ float local_power2(float lx, float ly, const float4 r0, const float4 r1, float& dx,
-                                              float& dy, float& t) {
-  dx = lx - r0.x;
-  dy = ly - r0.y;
-  t = __builtin_fmaf(r1.x, dx, r1.y * dy);
-  return fminf(__builtin_fmaf(t, dx, (r1.z * dy) * dy), 0.0f);
+__device__ __forceinline__ float local_power2(float lx, float ly, const LRec& r, float& dx, float& dy, float& t) {
+  dx = lx - r.m.x;
+  dy = ly - r.m.y;
+  t = __builtin_fmaf(r.m.z, dx, r.m.w * dy);
+  return fminf(__builtin_fmaf(t, dx, (r.c.x * dy) * dy), 0.0f);
 }
 
 __device__ __forceinline__ v4f mma(v8bf a, v8bf b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
@@ -165,25 +181,142 @@ struct SStage {
     }
   }
   // features Gaussian-major, single precision: s_f[q][c]; Gaussian ids to s_gid[q]
-  __device__ __forceinline__ void commit_rows(float4* s_rec, float* s_f, uint32_t* s_gid, float ox, float oy) const {
+  __device__ __forceinline__ void commit_rows(float* s_rec, float* s_f, uint32_t* s_gid, float ox, float oy) const {
     const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
-    if (part < 2) s_rec[2 * q + part] = local_rec(r, part, ox, oy);
+    if (part < 2) stage_rec(s_rec, q, r, part, ox, oy);
     if (part == 0) s_gid[q] = gid;
     float* dst = s_f + q * SShape<NS>::FST + part * CPT;
 #pragma unroll
     for (int j = 0; j < CPT; j += 4) *reinterpret_cast<float4*>(dst + j) = make_float4(f[j], f[j + 1], f[j + 2], f[j + 3]);
   }
   // features channel-major: s_f[c][q]
-  __device__ __forceinline__ void commit_cols(float4* s_rec, uint32_t* s_f, float ox, float oy) const {
+  __device__ __forceinline__ void commit_cols(float* s_rec, uint32_t* s_f, float ox, float oy) const {
     const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
-    if (part < 2) s_rec[2 * q + part] = local_rec(r, part, ox, oy);
+    if (part < 2) stage_rec(s_rec, q, r, part, ox, oy);
 #pragma unroll
     for (int j = 0; j < CPT; ++j) s_f[(part * CPT + j) * kWs + q] = pack_hl(f[j]);
   }
 };
 
 // ------------------------------------------------------------------------- forward
-template <int NS>
+// Long tile lists are cut into segments of kSeg list positions. The reverse pass takes
+// every segment as a work item of its own; the forward walks up to `chunk` consecutive
+// segments of a list in one work item (one sequential transmittance chain), so that
+// only lists longer than a chunk need a starting transmittance from a pre-pass.
+constexpr int kSeg = 256;
+
+// Segments per forward work item (cfg.fwd_chunk; 0 = the whole list).
+__host__ __device__ inline int fwd_chunk(const gs_config& cfg) { return cfg.fwd_chunk > 0 ? cfg.fwd_chunk : 1 << 16; }
+
+// Saved state of a forward that split its long lists, one slot per segment (a tile's
+// slots are consecutive from tbase[tile]; the work list has an entry per slot):
+//   P[slot][px]     at the first slot of a chunk: product of (1 - alpha) over the chunk's
+//                   Gaussians with alpha >= alpha_min, the stop rule ignored
+//                   (transmittance pre-pass; not for a list's last chunk);
+//   Te[slot][px]    T at the segment's end, for pixels active in it;
+//   info[slot][px]  1 + list position of the last blend in it (0 if none) | active at its
+//                   start << 30 | stopped inside it << 31;
+//   CS[slot][k][px] the segment's colour, then the sum of the colours of all later
+//                   segments of the list, which the reverse pass turns into its starting
+//                   sum of w (g . f) with one dot product.
+struct FState {
+  uint32_t* tcnt;    // [n_tiles] segments of the tile: 1 = whole list, no slot data
+  uint32_t* tbase;   // [n_tiles] first slot of the tile
+  float* P;
+  float* Te;
+  uint32_t* info;
+  float* CS;
+};
+constexpr uint32_t kInfoActive = 1u << 30, kInfoStopped = 1u << 31, kInfoLast = kInfoActive - 1;
+
+// Segments per tile: every tile is at least one item (it writes the tile's output).
+__global__ __launch_bounds__(256) void k_fseg_count(const uint32_t* __restrict__ ranges, int n_tiles, int order,
+                                                    uint32_t* __restrict__ cnt_ord) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const uint32_t len = ranges[2 * (int64_t)t + 1] - ranges[2 * (int64_t)t];
+  cnt_ord[order ? t : n_tiles - 1 - t] = len <= (uint32_t)kSeg ? 1u : (len + kSeg - 1) / kSeg;
+}
+
+// Transmittance pre-pass: P of every chunk of a list but the last. Persistent blocks
+// take work items from ctl[2].
+__global__ __launch_bounds__(256) void k_fwd_trans(gs_config cfg, const float* __restrict__ rec, int64_t n,
+                                                   const gs_item* __restrict__ items, int n_items,
+                                                   const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ ranges, const uint2* __restrict__ work,
+                                                   uint32_t* __restrict__ ctl, float* __restrict__ P) {
+  __shared__ float s_rec[8 * kB];
+  __shared__ uint32_t s_wi;
+  const int tid = threadIdx.x;
+  const float lx = (float)(tid & 15), ly = (float)(tid >> 4);
+  const float amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
+  const uint32_t n_work = ctl[0];
+  for (;;) {
+    if (tid == 0) s_wi = atomicAdd(&ctl[2], 1u);
+    lds_barrier();
+    const uint32_t wi = s_wi;
+    lds_barrier();
+    if (wi >= n_work) break;
+    const uint2 wk = work[wi];
+    const int seg = (int)(wk.y & 0xffffu), nseg = (int)(wk.y >> 16);
+    const int chunk = fwd_chunk(cfg);
+    if (seg % chunk != 0 || seg + chunk >= nseg) continue;
+    const Ctx c = make_ctx_of(items, n_items, ranges, (int)wk.x);
+    int u, v;
+    tile_pixel(c, tid, u, v);
+    const bool inside = u < c.W && v < c.H;
+    const float ox = (float)(c.tx * kTile) + 0.5f, oy = (float)(c.ty * kTile) + 0.5f;
+    const uint32_t a0 = c.start + seg * kSeg;
+    const uint32_t b0 = (uint32_t)min((int64_t)c.end, (int64_t)a0 + (int64_t)chunk * kSeg);
+    // thread t < 64 stages half (t % 2) of the record of Gaussian t / 2
+    const int q = tid >> 1, part = tid & 1;
+    auto fetch = [&](uint32_t b) -> float4 {
+      if (tid >= 2 * kB || b + q >= b0) return make_float4(0.f, 0.f, 0.f, 0.f);
+      const int64_t e = (int64_t)c.item * n + vals[b + q];
+      return reinterpret_cast<const float4*>(rec + kRecFloats * e)[part];
+    };
+    float p = 1.0f;
+    float4 r = fetch(a0);
+    for (uint32_t b = a0; b < b0; b += kB) {
+      // below t_min the product's exact value no longer matters
+      if (__syncthreads_count(inside & (p >= tmin)) == 0) break;
+      if (tid < 2 * kB) stage_rec(s_rec, q, r, part, ox, oy);
+      lds_barrier();
+      const int cnt = (int)min((uint32_t)kB, b0 - b);
+      r = fetch(b + kB);
+      // records of the next four Gaussians are read while the current four are used
+      LRec R[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) R[e] = load_rec(s_rec, e);
+#pragma unroll
+      for (int k4 = 0; k4 < kB; k4 += 4) {
+        LRec N[4];
+        if (k4 + 4 < kB)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) N[e] = load_rec(s_rec, k4 + 4 + e);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float dx, dy, t;
+          const float araw = R[e].c.y * __builtin_amdgcn_exp2f(local_power2(lx, ly, R[e], dx, dy, t));
+          const bool ok = (k4 + e < cnt) & (araw >= amin);
+          p = ok ? p - fminf(amax, araw) * p : p;
+        }
+        if (k4 + 4 < kB)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) R[e] = N[e];
+      }
+    }
+    P[(int64_t)wi * kTilePx + tid] = p;
+  }
+}
+
+// Compositing of one work item per block: a whole tile list (SEG = false, one block per
+// tile) or, SEG = true, a chunk of up to cfg.fwd_chunk segments of a list taken by persistent
+// blocks from ctl[1], starting from the product of the earlier chunks' P. A split list
+// leaves each segment's colour, end T and blend record in its slot; when the list is one
+// chunk, the block also joins its segments (image, T, n_contrib, suffix colours).
+template <int NS, bool SEG>
 __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, const float* __restrict__ rgb,
                                                           const float* __restrict__ sem,
                                                           const uint16_t* __restrict__ emb, int n_sem,
@@ -192,104 +325,252 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
                                                           const gs_item* __restrict__ items, int n_items,
                                                           const uint32_t* __restrict__ vals,
                                                           const uint32_t* __restrict__ ranges, float* __restrict__ color,
-                                                          float* __restrict__ Tout, uint32_t* __restrict__ ncout) {
+                                                          float* __restrict__ Tout, uint32_t* __restrict__ ncout,
+                                                          const uint2* __restrict__ work, uint32_t* __restrict__ ctl,
+                                                          FState fs) {
   using S = SShape<NS>;
   constexpr int CB = S::CB, KP = S::KP;
-  __shared__ float4 s_rec[2 * kB];
+  __shared__ float s_rec[8 * kB];
   __shared__ uint32_t s_f[KP * kWs];          // F^T, packed hi|lo, [channel][Gaussian]
   __shared__ float s_w[4][64 * kWs];          // per wave W, [pixel][Gaussian]
-  const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order);
+  __shared__ uint32_t s_wi;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, g4 = lane >> 4;
-  int u, v;
-  tile_pixel(c, tid, u, v);
-  const bool inside = u < c.W && v < c.H;
-  const float lx = (float)(tid & 15), ly = (float)(tid >> 4);
-  const float ox = (float)(c.tx * kTile) + 0.5f, oy = (float)(c.ty * kTile) + 0.5f;
-  v4f acc[CB][4];
-#pragma unroll
-  for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-    for (int pb = 0; pb < 4; ++pb) acc[cb][pb] = zero4();
-  float T = 1.0f;
-  bool done = !inside;
-  uint32_t last = 0;
-  const float amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
-  float* W = s_w[wave];
-  SStage<NS> st;
-  if (c.start < c.end)
-    st.fetch(vals, c.start, (int)min((uint32_t)kB, c.end - c.start), c.item, n, rec, depth, rgb, sem, emb, n_sem);
-  for (uint32_t b = c.start; b < c.end; b += kB) {
-    // every wave is past the previous batch's LDS reads; stop once every pixel has
-    if (__syncthreads_count(!done) == 0) break;
-    st.commit_cols(s_rec, s_f, ox, oy);
-    __syncthreads();
-    const int cnt = (int)min((uint32_t)kB, c.end - b);
-    if (b + kB < c.end)
-      st.fetch(vals, b + kB, (int)min((uint32_t)kB, c.end - b - kB), c.item, n, rec, depth, rgb, sem, emb, n_sem);
-    // front-to-back recurrence, branch-free; only T carries from one Gaussian to the next
-    bool took = false;
-    const uint32_t base = b - c.start;
-#pragma unroll
-    for (int q4 = 0; q4 < kB; q4 += 4) {
-      float wq[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int q = q4 + e;
-        const float4 r0 = s_rec[2 * q], r1 = s_rec[2 * q + 1];
-        float dx, dy, t;
-        const float araw = r1.w * __builtin_amdgcn_exp2f(local_power2(lx, ly, r0, r1, dx, dy, t));
-        const bool ok = (q < cnt) & !done & (araw >= amin);
-        const float w = fminf(amax, araw) * T;
-        const float Tn = T - w;
-        const bool stop = ok & (Tn < tmin);
-        const bool take = ok & !stop;
-        wq[e] = take ? w : 0.0f;
-        T = take ? Tn : T;
-        done = done | stop;
-        last = take ? base + q + 1 : last;
-        took |= take;
-      }
-      *reinterpret_cast<float4*>(W + lane * kWs + q4) = make_float4(wq[0], wq[1], wq[2], wq[3]);
-    }
-    wave_sync();
-    if (__ballot(took) == 0ull) continue;
-    // out^T[c][p] += F^T[c][i] W^T[i][p]: A = F^T (i = channel 16 cb + l16, k = Gaussian 8 g4 + e),
-    // B = W^T (k = Gaussian, j = pixel 16 pb + l16)
-    v8bf ah[CB], al[CB];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) load_op(s_f + (16 * cb + l16) * kWs + 8 * g4, ah[cb], al[cb]);
-#pragma unroll
-    for (int pb = 0; pb < 4; ++pb) {
-      const float* src = W + (16 * pb + l16) * kWs + 8 * g4;
-      const float4 w0 = *reinterpret_cast<const float4*>(src), w1 = *reinterpret_cast<const float4*>(src + 4);
-      const float x[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-      v8bf bh, bl;
-      split8(x, bh, bl);
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) acc[cb][pb] = mma3(ah[cb], al[cb], bh, bl, acc[cb][pb]);
-    }
-  }
-  // D[c][p]: lane holds pixel 16 pb + l16 of this wave, channels 16 cb + 4 g4 + r
   const int Kr = 4 + n_sem;
-#pragma unroll
-  for (int pb = 0; pb < 4; ++pb) {
-    int pu, pv;
-    tile_pixel(c, wave * 64 + 16 * pb + l16, pu, pv);
-    if (pu >= c.W || pv >= c.H) continue;
-    const int64_t pbase = c.pixel_base * Kr + (int64_t)pv * c.W + pu;
+  const float lx = (float)(tid & 15), ly = (float)(tid >> 4);
+  const float amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
+  const uint32_t n_work = SEG ? ctl[0] : 1u;
+  float* W = s_w[wave];
+  for (uint32_t round = 0;; ++round) {
+    uint32_t wi = 0;
+    int tile, seg = 0, nseg = 1;
+    if constexpr (SEG) {
+      if (tid == 0) s_wi = atomicAdd(&ctl[1], 1u);
+      lds_barrier();
+      wi = s_wi;
+      lds_barrier();
+      if (wi >= n_work) break;
+      const uint2 wk = work[wi];
+      tile = (int)wk.x;
+      seg = (int)(wk.y & 0xffffu);
+      nseg = (int)(wk.y >> 16);
+      if (seg % fwd_chunk(cfg) != 0) continue;   // inside a chunk walked by another item
+    } else {
+      if (round > 0) break;
+      tile = cfg.tile_order ? (int)blockIdx.x : (int)gridDim.x - 1 - (int)blockIdx.x;
+    }
+    const Ctx c = make_ctx_of(items, n_items, ranges, tile);
+    int u, v;
+    tile_pixel(c, tid, u, v);
+    const bool inside = u < c.W && v < c.H;
+    const float ox = (float)(c.tx * kTile) + 0.5f, oy = (float)(c.ty * kTile) + 0.5f;
+    const bool split = SEG && nseg > 1;
+    const int chunk = fwd_chunk(cfg);
+    const int s_hi = split ? min(nseg, seg + chunk) : 1;   // segments [seg, s_hi) of this item
+    const int64_t slot0 = (int64_t)wi - seg;                  // the tile's first slot
+    v4f acc[CB][4];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ch = 16 * cb + 4 * g4 + r;
-        if (ch < Kr) color[pbase + ch * c.HW] = acc[cb][pb][r];
+      for (int pb = 0; pb < 4; ++pb) acc[cb][pb] = zero4();
+    float T = 1.0f;
+    if (split)
+      for (int s2 = 0; s2 < seg; s2 += chunk) T *= fs.P[(slot0 + s2) * kTilePx + tid];
+    // a pixel whose transmittance in front of the chunk is below t_min stopped earlier
+    bool done = !(inside & (T >= tmin));
+    uint32_t last = 0;
+    SStage<NS> st;
+    for (int sg = seg; sg < s_hi; ++sg) {
+      const uint32_t a0 = split ? c.start + sg * kSeg : c.start;
+      const uint32_t b0 = split ? min(c.end, a0 + kSeg) : c.end;
+      const bool active = !done;
+      if (a0 < b0) st.fetch(vals, a0, (int)min((uint32_t)kB, b0 - a0), c.item, n, rec, depth, rgb, sem, emb, n_sem);
+      for (uint32_t b = a0; b < b0; b += kB) {
+        // every wave is past the previous batch's LDS reads; stop once every pixel has
+        if (__syncthreads_count(!done) == 0) break;
+        st.commit_cols(s_rec, s_f, ox, oy);
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)kB, b0 - b);
+        if (b + kB < b0)
+          st.fetch(vals, b + kB, (int)min((uint32_t)kB, b0 - b - kB), c.item, n, rec, depth, rgb, sem, emb, n_sem);
+        // front-to-back recurrence, branch-free; only T carries from one Gaussian to the next
+        bool took = false;
+        const uint32_t base = b - c.start;
+        // records of the next four Gaussians are read while the current four are used
+        LRec R[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) R[e] = load_rec(s_rec, e);
+#pragma unroll
+        for (int q4 = 0; q4 < kB; q4 += 4) {
+          LRec N[4];
+          if (q4 + 4 < kB)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) N[e] = load_rec(s_rec, q4 + 4 + e);
+          __builtin_amdgcn_sched_barrier(0);
+          float wq[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int q = q4 + e;
+            float dx, dy, t;
+            const float araw = R[e].c.y * __builtin_amdgcn_exp2f(local_power2(lx, ly, R[e], dx, dy, t));
+            const bool ok = (q < cnt) & !done & (araw >= amin);
+            const float w = fminf(amax, araw) * T;
+            const float Tn = T - w;
+            const bool stop = ok & (Tn < tmin);
+            const bool take = ok & !stop;
+            wq[e] = take ? w : 0.0f;
+            T = take ? Tn : T;
+            done = done | stop;
+            last = take ? base + q + 1 : last;
+            took |= take;
+          }
+          *reinterpret_cast<float4*>(W + lane * kWs + q4) = make_float4(wq[0], wq[1], wq[2], wq[3]);
+          if (q4 + 4 < kB)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) R[e] = N[e];
+        }
+        wave_sync();
+        if (__ballot(took) == 0ull) continue;
+        // out^T[c][p] += F^T[c][i] W^T[i][p]: A = F^T (i = channel 16 cb + l16, k = Gaussian 8 g4 + e),
+        // B = W^T (k = Gaussian, j = pixel 16 pb + l16)
+        v8bf ah[CB], al[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) load_op(s_f + (16 * cb + l16) * kWs + 8 * g4, ah[cb], al[cb]);
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+          const float* src = W + (16 * pb + l16) * kWs + 8 * g4;
+          const float4 w0 = *reinterpret_cast<const float4*>(src), w1 = *reinterpret_cast<const float4*>(src + 4);
+          const float x[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+          v8bf bh, bl;
+          split8(x, bh, bl);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) acc[cb][pb] = mma3(ah[cb], al[cb], bh, bl, acc[cb][pb]);
+        }
       }
+      if (split) {
+        // the segment's slot; D[c][p]: lane holds pixel 16 pb + l16 of this wave, channels
+        // 16 cb + 4 g4 + r
+        const int64_t sl = slot0 + sg;
+        float* dst = fs.CS + sl * Kr * kTilePx + wave * 64 + l16;
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int ch = 16 * cb + 4 * g4 + r;
+              if (ch < Kr) dst[ch * kTilePx + 16 * pb] = acc[cb][pb][r];
+              acc[cb][pb][r] = 0.0f;
+            }
+        const int64_t o = sl * kTilePx + tid;
+        fs.Te[o] = T;
+        const uint32_t lseg = last > (uint32_t)(sg * kSeg) ? last : 0u;
+        fs.info[o] = lseg | (active ? kInfoActive : 0u) | (active & done ? kInfoStopped : 0u);
+      }
+    }
+    if (split && nseg > chunk) continue;   // joined by k_fwd_combine
+    const int64_t pix = c.pixel_base + (int64_t)v * c.W + u;
+    if (inside) {
+      Tout[pix] = T;
+      ncout[pix] = last;
+    }
+    // D[c][p] (the image), or for a split list the sum of its segments' colours taken back
+    // to front, each slot left holding the sum of the ones after it (acc, zero after the
+    // last flush, carries the running sum; every value read here was written by this lane)
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) {
+      if (split) {
+        float* p = fs.CS + slot0 * Kr * kTilePx + wave * 64 + 16 * pb + l16;
+        for (int s2 = nseg - 1; s2 >= 0; --s2) {
+          float* ps = p + (int64_t)s2 * Kr * kTilePx;
+          float cs[CB][4];
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int ch = 16 * cb + 4 * g4 + r;
+              cs[cb][r] = ch < Kr ? ps[ch * kTilePx] : 0.0f;
+            }
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int ch = 16 * cb + 4 * g4 + r;
+              if (ch < Kr) ps[ch * kTilePx] = acc[cb][pb][r];
+              acc[cb][pb][r] += cs[cb][r];
+            }
+        }
+      }
+      int pu, pv;
+      tile_pixel(c, wave * 64 + 16 * pb + l16, pu, pv);
+      if (pu >= c.W || pv >= c.H) continue;
+      const int64_t pbase = c.pixel_base * Kr + (int64_t)pv * c.W + pu;
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ch = 16 * cb + 4 * g4 + r;
+          if (ch < Kr) color[pbase + ch * c.HW] = acc[cb][pb][r];
+        }
+    }
   }
-  if (!inside) return;
+}
+
+// Joins the segments of every list longer than one chunk: a pixel takes its segments in
+// order up to the one in which it stopped (a later chunk that still found it active, its
+// starting product being rounded differently from the stopping chain, is dropped); the
+// image gets their colour sum, T and n_contrib, and each segment's colour is replaced by
+// the sum of the colours of the kept segments after it. Segments are walked back to
+// front with all channels of a segment loaded at once.
+template <int NS>
+__global__ __launch_bounds__(256) void k_fwd_combine(const gs_item* __restrict__ items, int n_items,
+                                                     const uint32_t* __restrict__ ranges, int Kr, int chunk,
+                                                     FState fs, float* __restrict__ color, float* __restrict__ Tout,
+                                                     uint32_t* __restrict__ ncout) {
+  constexpr int KP = SShape<NS>::KP;
+  const int tile = blockIdx.x, tid = threadIdx.x;
+  const int nseg = (int)fs.tcnt[tile];
+  if (nseg <= chunk) return;
+  const Ctx c = make_ctx_of(items, n_items, ranges, tile);
+  int u, v;
+  tile_pixel(c, tid, u, v);
+  if (u >= c.W || v >= c.H) return;
+  const int64_t b = fs.tbase[tile];
+  float T = 1.0f;
+  uint32_t last = 0;
+  int s_end = nseg;
+  for (int s = 0; s < nseg; ++s) {
+    const int64_t o = (b + s) * kTilePx + tid;
+    const uint32_t inf = fs.info[o];
+    if (!(inf & kInfoActive)) break;
+    T = fs.Te[o];
+    if (inf & kInfoLast) last = inf & kInfoLast;
+    if (inf & kInfoStopped) {
+      s_end = s + 1;
+      break;
+    }
+  }
   const int64_t pix = c.pixel_base + (int64_t)v * c.W + u;
   Tout[pix] = T;
   ncout[pix] = last;
+  float sum[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) sum[k] = 0.0f;
+  for (int s = nseg - 1; s >= 0; --s) {
+    float* p = fs.CS + (b + s) * Kr * kTilePx + tid;
+    float cs[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) cs[k] = (k < Kr && s < s_end) ? p[k * kTilePx] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      if (k < Kr) p[k * kTilePx] = sum[k];
+      sum[k] += cs[k];
+    }
+  }
+  float* out = color + c.pixel_base * Kr + (int64_t)v * c.W + u;
+#pragma unroll
+  for (int k = 0; k < KP; ++k)
+    if (k < Kr) out[k * c.HW] = sum[k];
 }
 
 // ------------------------------------------------------------------------- backward
@@ -313,27 +594,61 @@ __device__ __forceinline__ void block_transpose(uint32_t (&X)[4][8]) {
   }
 }
 
-// Long tile lists are cut into segments of kSeg list positions, each a work item of its
-// own, so that the longest list no longer sets the length of the launch. Walking a
-// segment backwards needs, per pixel, the transmittance after it and the suffix
-// sum over every later Gaussian of w (g . f). A summary pass gives every segment s of a
-// long list, per pixel,
+// Walking a segment of a split list backwards needs, per pixel, the transmittance after
+// it and the suffix sum over every later Gaussian of w (g . f). Without the forward's
+// saved state, a summary pass gives every segment s of a long list, per pixel,
 //   P_s  = prod over its blended Gaussians of (1 - alpha)            (front to back)
 //   GC_s = sum over its blended Gaussians of alpha T_loc (g . f),     T_loc from 1
 // and then T_after(s) = prod_{s' <= s} P_s' and suffix(s) = sum_{s' > s} T_before(s') GC_s'.
-constexpr int kSeg = 256;
-
 // With the exponent E = a dx^2 + b dx dy + c dy^2 of the local record (E = log2(e) power),
 // d power/d mean2d = -(dE/d dx, dE/d dy) / log2(e) and d power/d(A, B, C) =
 // -(dx^2 / 2, dx dy, dy^2 / 2); the reverse pass sums dE/d dx, dE/d dy, dx^2, dx dy, dy^2
 // (times dL/d power) and applies these factors once per Gaussian.
+// Partial sums per (Gaussian, component) left in LDS by a batch: 8 per wave.
+constexpr int kGeoSlots = 32;
+
+// Sums the geometric terms of GG Gaussians (6 GG values per lane) over the wave's four
+// lane rows and over the lane pairs (l16, l16 ^ 8) of a row, halving the values held at each
+// step instead of reducing each value separately: a permlane32 swap pairs rows (0, 2) and
+// (1, 3), a permlane16 swap rows (0, 1) and (2, 3), a row rotation by 8 the halves of a row.
+// Lane (row R, l16) returns Y[j] = sum of V[f + j] over the 8 lanes (l16 % 8 + {0, 8}) x rows,
+// f = 6 R + 3 (l16 / 8) for GG = 4 and f = 3 R for GG = 2.
+template <int GG>
+__device__ __forceinline__ void geo_reduce(const float (&V)[6 * GG], float (&Y)[3]) {
+  constexpr int H1 = 3 * GG, H2 = 3 * GG / 2;
+  float W[H1], X[H2];
+#pragma unroll
+  for (int j = 0; j < H1; ++j) {
+    const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(V[j]), __float_as_uint(V[j + H1]), false, false);
+    W[j] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+  }
+#pragma unroll
+  for (int j = 0; j < H2; ++j) {
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(W[j]), __float_as_uint(W[j + H2]), false, false);
+    X[j] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+  }
+  if constexpr (GG == 4) {
+    const bool upper = (threadIdx.x & 8) != 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const float keep = upper ? X[j + 3] : X[j], send = upper ? X[j] : X[j + 3];
+      Y[j] = keep + dpp_ror8(send);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Y[j] = X[j] + dpp_ror8(X[j]);
+  }
+}
+
 __constant__ float kGeoScale[6] = {-1.0f / kLog2e, -1.0f / kLog2e, -0.5f, -1.0f, -0.5f, 1.0f};
 
 // One block per tile: the tile's list length in use (largest n_contrib) and its segment
 // count, stored in work order (coarse pyramid levels first unless tile_order = 1).
+// With a forward state, a tile that the forward did not split stays one item.
 __global__ __launch_bounds__(256) void k_seg_count(const gs_item* __restrict__ items, int n_items,
                                                    const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ ncin, int n_tiles, int order,
+                                                   const uint32_t* __restrict__ ftcnt,
                                                    uint32_t* __restrict__ tile_lmax, uint32_t* __restrict__ cnt_ord) {
   __shared__ uint32_t s_m;
   const int tile = blockIdx.x;
@@ -350,15 +665,18 @@ __global__ __launch_bounds__(256) void k_seg_count(const gs_item* __restrict__ i
   if (threadIdx.x == 0) {
     const uint32_t m = s_m;
     tile_lmax[tile] = m;
-    cnt_ord[order ? tile : n_tiles - 1 - tile] = m == 0 ? 0u : (m <= (uint32_t)kSeg ? 1u : (m + kSeg - 1) / kSeg);
+    const bool one = m <= (uint32_t)kSeg || (ftcnt && ftcnt[tile] < 2);
+    cnt_ord[order ? tile : n_tiles - 1 - tile] = m == 0 ? 0u : (one ? 1u : (m + kSeg - 1) / kSeg);
   }
 }
 
 // Work list: (tile, segment | segment count << 16). If the segments do not fit the
-// workspace, every tile becomes a single item. Also resets the two work counters.
+// workspace, every tile becomes a single item. Also resets the two work counters and,
+// if tcnt is given, records per tile its item count and first item.
 __global__ void k_seg_list(const uint32_t* __restrict__ cnt_ord, const uint32_t* __restrict__ base_ord,
                            const uint64_t* __restrict__ total, int n_tiles, int order, int64_t max_segs,
-                           uint2* __restrict__ work, uint32_t* __restrict__ ctl) {
+                           uint2* __restrict__ work, uint32_t* __restrict__ ctl, uint32_t* __restrict__ tcnt,
+                           uint32_t* __restrict__ tbase) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t tot = *total;
   const bool fits = tot <= (uint64_t)max_segs;
@@ -372,8 +690,16 @@ __global__ void k_seg_list(const uint32_t* __restrict__ cnt_ord, const uint32_t*
   if (fits) {
     const uint32_t c = cnt_ord[o], b = base_ord[o];
     for (uint32_t k = 0; k < c; ++k) work[b + k] = make_uint2(tile, k | (c << 16));
+    if (tcnt) {
+      tcnt[tile] = c;
+      tbase[tile] = b;
+    }
   } else {
     work[o] = make_uint2(tile, 1u << 16);
+    if (tcnt) {
+      tcnt[tile] = 1;
+      tbase[tile] = o;
+    }
   }
 }
 
@@ -395,14 +721,16 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
                                                           float* __restrict__ grgb, float* __restrict__ gsem,
                                                           const uint2* __restrict__ work, uint32_t* __restrict__ ctl,
                                                           const uint32_t* __restrict__ tile_lmax,
-                                                          float* __restrict__ segP, float* __restrict__ segGC) {
+                                                          float* __restrict__ segP, float* __restrict__ segGC,
+                                                          FState fs) {
   using S = SShape<NS>;
   constexpr int KP = S::KP, CB = S::CB, FST = S::FST;
-  __shared__ float4 s_rec[2 * kB];
+  constexpr int GG = NS > 28 ? 2 : 4;         // Gaussians per geometric-term reduction (register budget)
+  __shared__ float s_rec[8 * kB];
   __shared__ float s_f[kB * FST];             // F, [Gaussian][channel]
   __shared__ float s_w[SUMMARY ? 1 : 4][16 * kPs];      // per wave, 16 Gaussians: W, [Gaussian][pixel]
   __shared__ float s_df[SUMMARY ? 1 : kB * KP];
-  __shared__ float s_geo[SUMMARY ? 1 : kB * 6 * 16];     // [Gaussian][component][row slot]
+  __shared__ float s_geo[SUMMARY ? 1 : kB * 6 * kGeoSlots];   // [Gaussian][component][partial sum]
   __shared__ uint32_t s_wi;
   __shared__ uint32_t s_gid[kB];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -466,7 +794,16 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
     if constexpr (!SUMMARY) {
       const float tf = inside ? Tfin[pix] : 1.0f;
       if (nseg == 1 || seg == nseg - 1) T = tf;
-      if (nseg > 1) {
+      if (nseg > 1 && fs.tcnt) {
+        // the forward's state: T at the segment's end and the suffix colour sum
+        const int64_t slot = (int64_t)fs.tbase[tile] + seg, o = slot * kTilePx + tid;
+        if (fs.info[o] & kInfoActive) T = fs.Te[o];
+        if (inside) {
+          const float* sc = fs.CS + slot * Kr * kTilePx + tid;
+          const float* gp = gcolor + c.pixel_base * Kr + (int64_t)v * c.W + u;
+          for (int k = 0; k < Kr; ++k) acc = __builtin_fmaf(gp[k * c.HW], sc[k * kTilePx], acc);
+        }
+      } else if (nseg > 1) {
         const int64_t w0 = (int64_t)wi - seg;
         float tb = 1.0f;   // transmittance in front of segment s
         for (int s = 0; s < nseg; ++s) {
@@ -494,7 +831,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
       st.commit_rows(s_rec, s_f, s_gid, ox, oy);
       if constexpr (!SUMMARY) {
         for (int i = tid; i < kB * KP; i += 256) s_df[i] = 0.0f;
-        for (int i = tid; i < kB * 6 * 16; i += 256) s_geo[i] = 0.0f;
+        for (int i = tid; i < kB * 6 * kGeoSlots / 4; i += 256) reinterpret_cast<float4*>(s_geo)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
       lds_barrier();
       if (bi + 1 < n_batches) {
@@ -533,9 +870,9 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
         if constexpr (SUMMARY) {
 #pragma unroll
           for (int q = 0; q < kB; ++q) {
-            const float4 r0 = s_rec[2 * q], r1 = s_rec[2 * q + 1];
+            const LRec rq = load_rec(s_rec, q);
             float dx, dy, t;
-            const float araw = r1.w * __builtin_amdgcn_exp2f(local_power2(lx, ly, r0, r1, dx, dy, t));
+            const float araw = rq.c.y * __builtin_amdgcn_exp2f(local_power2(lx, ly, rq, dx, dy, t));
             const bool act = (q < cnt) & ((uint32_t)(lo + q) < last) & (araw >= amin);
             const float w = fminf(amax, araw) * T;
             const float gf = __uint_as_float(X[(q >> 2) & 3][4 * (q >> 4) + (q & 3)]);
@@ -549,43 +886,51 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
             float* Wp = s_w[wave];
             bool any = false;
 #pragma unroll
-            for (int gq = 3; gq >= 0; --gq)
+            for (int gb = 16 / GG - 1; gb >= 0; --gb) {
+              float V[6 * GG];   // V[6 r + k]: component k of the geometric terms of Gaussian GG gb + r
+              bool gact = false;
 #pragma unroll
-              for (int r = 3; r >= 0; --r) {
-                const int q = 16 * bq + 4 * gq + r;
-                const float4 r0 = s_rec[2 * q], r1 = s_rec[2 * q + 1];
+              for (int r = GG - 1; r >= 0; --r) {
+                const int qq = GG * gb + r, q = 16 * bq + qq;
+                const LRec rq = load_rec(s_rec, q);
                 float dx, dy, t;
-                const float G = __builtin_amdgcn_exp2f(local_power2(lx, ly, r0, r1, dx, dy, t));
-                const float araw = r1.w * G;
+                const float G = __builtin_amdgcn_exp2f(local_power2(lx, ly, rq, dx, dy, t));
+                const float araw = rq.c.y * G;
                 const bool act = (q < cnt) & ((uint32_t)(lo + q) < last) & (araw >= amin);
                 const float a = fminf(amax, araw);
                 const float rom = __builtin_amdgcn_rcpf(1.0f - a);
                 const float Tq = act ? T * rom : T;   // transmittance in front of this Gaussian
                 const float w = act ? a * Tq : 0.0f;
-                const float gf = __uint_as_float(X[gq][4 * bq + r]);
+                const float gf = __uint_as_float(X[qq >> 2][4 * bq + (qq & 3)]);
                 const float dalpha = Tq * gf - acc * rom;
                 acc = act ? __builtin_fmaf(gf, w, acc) : acc;
                 T = Tq;
                 const bool unclamped = act & (araw < amax);
                 const float dpow = unclamped ? dalpha * araw : 0.0f;
                 const float dop = unclamped ? dalpha * G : 0.0f;
-                Wp[(4 * gq + r) * kPs + lane] = w;
-                if (__ballot(act) != 0ull) {
-                  any = true;
-                  // d power / d (mean2d, A, B, C) up to the per-component factors of kGeoScale
-                  const float pdx = dpow * dx, pdy = dpow * dy;
-                  const float s0 = row_sum16(dpow * __builtin_fmaf(r1.x, dx, t));   // 2a dx + b dy
-                  const float s1 = row_sum16(dpow * __builtin_fmaf(r1.y, dx, 2.0f * (r1.z * dy)));
-                  const float s2 = row_sum16(pdx * dx);
-                  const float s3 = row_sum16(pdx * dy);
-                  const float s4 = row_sum16(pdy * dy);
-                  const float s5 = row_sum16(dop);                                  // d/d opacity
-                  if (l16 == 0) {
-                    float* dst = s_geo + q * 96 + wave * 4 + g4;
-                    dst[0] = s0; dst[16] = s1; dst[32] = s2; dst[48] = s3; dst[64] = s4; dst[80] = s5;
-                  }
-                }
+                Wp[qq * kPs + lane] = w;
+                gact |= act;
+                // d power / d (mean2d, A, B, C) up to the per-component factors of kGeoScale
+                const float pdx = dpow * dx, pdy = dpow * dy;
+                V[6 * r + 0] = dpow * __builtin_fmaf(rq.m.z, dx, t);   // 2a dx + b dy
+                V[6 * r + 1] = dpow * __builtin_fmaf(rq.m.w, dx, 2.0f * (rq.c.x * dy));
+                V[6 * r + 2] = pdx * dx;
+                V[6 * r + 3] = pdx * dy;
+                V[6 * r + 4] = pdy * dy;
+                V[6 * r + 5] = dop;                                  // d/d opacity
               }
+              if (__ballot(gact) != 0ull) {
+                any = true;
+                float Y[3];
+                geo_reduce<GG>(V, Y);
+                // Gaussian and first component of this lane's three sums
+                const int qd = 16 * bq + GG * gb + (GG == 4 ? g4 : g4 >> 1);
+                const int k0 = GG == 4 ? 3 * (l16 >> 3) : 3 * (g4 & 1);
+                float* dst = s_geo + (qd * 6 + k0) * kGeoSlots + wave * 8 + (l16 & 7);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dst[j * kGeoSlots] = Y[j];
+              }
+            }
             wave_sync();
             if (__ballot(any) != 0ull) {
               // A = W^T (i = Gaussian l16 of the block, k = pixel 32 ks + 8 g4 + e)
@@ -625,10 +970,10 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
         }
         for (int idx = tid; idx < cnt * 6; idx += 256) {
           const int q = idx / 6, comp = idx - q * 6;
-          const float* src = s_geo + q * 96 + comp * 16;
+          const float* src = s_geo + idx * kGeoSlots;
           float sum = 0.0f;
 #pragma unroll
-          for (int r = 0; r < 16; ++r) sum += src[r];
+          for (int r = 0; r < kGeoSlots; ++r) sum += src[r];
           if (sum != 0.0f) {
             const uint32_t g = s_gid[q];
             atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + comp], sum * kGeoScale[comp]);
@@ -641,14 +986,6 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
       segGC[(int64_t)wi * kTilePx + tid] = acc;
     }
   }
-}
-
-template <int NS>
-int launch_fwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items, int n_items,
-                 int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& out, hipStream_t s) {
-  hipLaunchKernelGGL(k_render_fwd_split<NS>, dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb, cfg.n_sem,
-                     p.rec, p.depth, g.n, items, n_items, vals, ranges, out.color, out.T, out.n_contrib);
-  return launch_status();
 }
 
 // Caller workspace of the reverse pass: the segment work list, sized for `cap` duplicates.
@@ -702,29 +1039,142 @@ int persistent_grid(F kernel) {
   return std::max(1, cus * std::max(1, per));
 }
 
+// Caller buffer of a splitting forward (its saved state), sized for `cap` duplicates and
+// K channels.
+struct FLayout {
+  FState fs;
+  uint32_t *cnt, *base, *partial, *ctl;
+  uint64_t* total;
+  uint2* work;
+  int64_t max_segs;
+};
+
+size_t fstate_layout(int n_tiles, int64_t cap, int K, char* base, FLayout* w) {
+  const int64_t max_segs = (int64_t)n_tiles + ceil_div(cap, kSeg) + 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return base ? base + o : nullptr;
+  };
+  char* p_tcnt = take(4 * (size_t)n_tiles);
+  char* p_tbase = take(4 * (size_t)n_tiles);
+  char* p_cnt = take(4 * (size_t)n_tiles);
+  char* p_base = take(4 * (size_t)n_tiles);
+  char* p_part = take(4 * (size_t)scan_partials_needed(n_tiles));
+  char* p_tot = take(8);
+  char* p_ctl = take(16);
+  char* p_work = take(8 * (size_t)max_segs);
+  char* p_P = take(4 * (size_t)kTilePx * max_segs);
+  char* p_Te = take(4 * (size_t)kTilePx * max_segs);
+  char* p_info = take(4 * (size_t)kTilePx * max_segs);
+  char* p_CS = take(4 * (size_t)kTilePx * max_segs * (size_t)K);
+  if (w) {
+    w->fs.tcnt = (uint32_t*)p_tcnt;
+    w->fs.tbase = (uint32_t*)p_tbase;
+    w->fs.P = (float*)p_P;
+    w->fs.Te = (float*)p_Te;
+    w->fs.info = (uint32_t*)p_info;
+    w->fs.CS = (float*)p_CS;
+    w->cnt = (uint32_t*)p_cnt;
+    w->base = (uint32_t*)p_base;
+    w->partial = (uint32_t*)p_part;
+    w->total = (uint64_t*)p_tot;
+    w->ctl = (uint32_t*)p_ctl;
+    w->work = (uint2*)p_work;
+    w->max_segs = max_segs;
+  }
+  return off;
+}
+
+}  // namespace
+
+size_t render_state_bytes(int n_tiles, int64_t dup_capacity, int K) {
+  return fstate_layout(n_tiles, std::max<int64_t>(dup_capacity, 0), K, nullptr, nullptr);
+}
+
+// Largest duplicate capacity whose forward state fits in `bytes` (-1 if none does).
+int64_t render_state_capacity(int n_tiles, int K, size_t bytes) {
+  if (render_state_bytes(n_tiles, 0, K) > bytes) return -1;
+  int64_t lo = 0, hi = 1;
+  while (hi < ((int64_t)1 << 40) && render_state_bytes(n_tiles, hi, K) <= bytes) hi *= 2;
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (render_state_bytes(n_tiles, mid, K) <= bytes) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+namespace {
+
+// Forward state of images `im` (fs.tcnt == nullptr if there is none).
+FLayout state_of(const gs_images& im, int n_tiles, int K) {
+  FLayout w{};
+  if (!im.state) return w;
+  const int64_t cap = render_state_capacity(n_tiles, K, im.state_bytes);
+  if (cap >= 0) fstate_layout(n_tiles, cap, K, (char*)im.state, &w);
+  return w;
+}
+
+template <int NS>
+int launch_fwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items, int n_items,
+                 int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& out, hipStream_t s) {
+  const FLayout w = state_of(out, n_tiles, 4 + cfg.n_sem);
+  if (!w.fs.tcnt) {
+    hipLaunchKernelGGL((k_render_fwd_split<NS, false>), dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb,
+                       cfg.n_sem, p.rec, p.depth, g.n, items, n_items, vals, ranges, out.color, out.T, out.n_contrib,
+                       nullptr, nullptr, w.fs);
+    return launch_status();
+  }
+  const unsigned tb = (unsigned)ceil_div(n_tiles, 256);
+  hipLaunchKernelGGL(k_fseg_count, dim3(tb), dim3(256), 0, s, ranges, n_tiles, cfg.tile_order, w.cnt);
+  int st = launch_status();
+  st = st ? st : scan_u32(w.cnt, w.base, n_tiles, w.partial, w.total, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_seg_list, dim3(tb), dim3(256), 0, s, w.cnt, w.base, w.total, n_tiles, cfg.tile_order,
+                     w.max_segs, w.work, w.ctl, w.fs.tcnt, w.fs.tbase);
+  static int grid_t = 0, grid_f = 0;
+  if (!grid_t) grid_t = persistent_grid(k_fwd_trans);
+  if (!grid_f) grid_f = persistent_grid(k_render_fwd_split<NS, true>);
+  if (!grid_t || !grid_f) return GS_ERR_HIP;
+  if (cfg.fwd_chunk > 0)
+    hipLaunchKernelGGL(k_fwd_trans, dim3(grid_t), dim3(256), 0, s, cfg, p.rec, g.n, items, n_items, vals, ranges,
+                       w.work, w.ctl, w.fs.P);
+  hipLaunchKernelGGL((k_render_fwd_split<NS, true>), dim3(grid_f), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb, cfg.n_sem,
+                     p.rec, p.depth, g.n, items, n_items, vals, ranges, out.color, out.T, out.n_contrib, w.work, w.ctl,
+                     w.fs);
+  if (cfg.fwd_chunk > 0)
+    hipLaunchKernelGGL(k_fwd_combine<NS>, dim3(n_tiles), dim3(256), 0, s, items, n_items, ranges, 4 + cfg.n_sem,
+                       cfg.fwd_chunk, w.fs, out.color, out.T, out.n_contrib);
+  return launch_status();
+}
+
 template <int NS>
 int launch_bwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items, int n_items,
                  int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& fwd,
                  const gs_images& gin, float* g2d, const gs_grads& gr, void* seg_ws, int64_t cap, hipStream_t s) {
   SegWs w;
   seg_layout(n_tiles, cap, (char*)seg_ws, &w);
+  // with the forward's saved state the segments start from it: no summary pass
+  const FState fs = state_of(fwd, n_tiles, 4 + cfg.n_sem).fs;
   hipLaunchKernelGGL(k_seg_count, dim3(n_tiles), dim3(256), 0, s, items, n_items, ranges, fwd.n_contrib, n_tiles,
-                     cfg.tile_order, w.lmax, w.cnt);
+                     cfg.tile_order, fs.tcnt, w.lmax, w.cnt);
   int st = launch_status();
   st = st ? st : scan_u32(w.cnt, w.base, n_tiles, w.partial, w.total, s);
   if (st) return st;
   hipLaunchKernelGGL(k_seg_list, dim3((unsigned)ceil_div(n_tiles, 256)), dim3(256), 0, s, w.cnt, w.base, w.total,
-                     n_tiles, cfg.tile_order, w.max_segs, w.work, w.ctl);
+                     n_tiles, cfg.tile_order, w.max_segs, w.work, w.ctl, nullptr, nullptr);
   static int grid_sum = 0, grid_main = 0;
   if (!grid_sum) grid_sum = persistent_grid(k_render_bwd_split<NS, true>);
   if (!grid_main) grid_main = persistent_grid(k_render_bwd_split<NS, false>);
   if (!grid_sum || !grid_main) return GS_ERR_HIP;
-  hipLaunchKernelGGL((k_render_bwd_split<NS, true>), dim3(grid_sum), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb, cfg.n_sem,
-                     p.rec, p.depth, g.n, items, n_items, vals, ranges, fwd.T, fwd.n_contrib, gin.color, g2d, gr.rgb,
-                     gr.sem, w.work, w.ctl, w.lmax, w.P, w.GC);
+  if (!fs.tcnt)
+    hipLaunchKernelGGL((k_render_bwd_split<NS, true>), dim3(grid_sum), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb,
+                       cfg.n_sem, p.rec, p.depth, g.n, items, n_items, vals, ranges, fwd.T, fwd.n_contrib, gin.color,
+                       g2d, gr.rgb, gr.sem, w.work, w.ctl, w.lmax, w.P, w.GC, fs);
   hipLaunchKernelGGL((k_render_bwd_split<NS, false>), dim3(grid_main), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb,
                      cfg.n_sem, p.rec, p.depth, g.n, items, n_items, vals, ranges, fwd.T, fwd.n_contrib, gin.color, g2d,
-                     gr.rgb, gr.sem, w.work, w.ctl, w.lmax, w.P, w.GC);
+                     gr.rgb, gr.sem, w.work, w.ctl, w.lmax, w.P, w.GC, fs);
   return launch_status();
 }
 

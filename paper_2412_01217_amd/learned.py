@@ -65,7 +65,7 @@ class ViewState:
             pb = it["pixel_base"]
             self.teacher[pb * C: pb * C + C * HW] = plain["color"][pb * K + 4 * HW: pb * K + K * HW]
         del plain
-        self.img = raster.alloc_images(cfg_learned, self.fr, C, learned=True)
+        self.img = raster.alloc_images(cfg_learned, self.fr, C, learned=True, state_capacity=self.sorter.capacity)
         self.grad = dict(color=torch.zeros_like(self.img["color"]), logits=torch.empty_like(self.img["logits"]))
         self.grads = raster.alloc_grads(cfg_learned, g_learned, self.fr, C)
         self.ws = torch.empty(raster.workspace_bytes(raster.L.GS_WS_RENDER_BWD, cfg_learned, self.fr, n,

@@ -163,7 +163,9 @@ def bin_sort(cfg, proj: dict, frame: Frame, n: int, capacity=None, want_keys=Fal
         cap = int(int(s.n_dup.item()) * 1.1) + 1024
 
 
-def alloc_images(cfg, frame: Frame, n_classes=0, learned=False) -> dict:
+def alloc_images(cfg, frame: Frame, n_classes=0, learned=False, state_capacity=None) -> dict:
+    """Forward images; with state_capacity (the bin_sort capacity of the lists), also the
+    forward state that lets long lists be split and the backward skip its summary pass."""
     K = 4 + cfg.n_sem
     dev = frame.device
     P = frame.n_pixels
@@ -171,12 +173,19 @@ def alloc_images(cfg, frame: Frame, n_classes=0, learned=False) -> dict:
                T=torch.empty(P, dtype=torch.float32, device=dev),
                n_contrib=torch.empty(P, dtype=torch.int32, device=dev), K=K, n_pixels=P)
     out["logits"] = torch.empty(P * n_classes, dtype=torch.float32, device=dev) if learned else None
+    out["state"] = None
+    if state_capacity is not None:
+        nb = workspace_bytes(L.GS_WS_RENDER_STATE, cfg, frame, 0, int(state_capacity))
+        out["state"] = torch.empty(nb, dtype=torch.uint8, device=dev)
     return out
 
 
 def _images(d: dict, P: int = 0) -> L.Images:
     im = L.Images(*(None if d.get(k) is None else d[k].data_ptr() for k in ("color", "T", "n_contrib", "logits")))
     im.n_pixels = int(d.get("n_pixels", P))
+    st = d.get("state")
+    if st is not None:
+        im.state, im.state_bytes = st.data_ptr(), st.numel()
     return im
 
 
@@ -190,9 +199,12 @@ def head_struct(head: dict | None):
     return h
 
 
-def render_fwd(cfg, g: dict, proj: dict, frame: Frame, sorter: Sorter, out=None, head=None) -> dict:
+def render_fwd(cfg, g: dict, proj: dict, frame: Frame, sorter: Sorter, out=None, head=None, split=True) -> dict:
+    """split: allocate the forward state (long lists composited in segments) when out is
+    not given; a given out carries its own (or no) state."""
     learned = g.get("emb") is not None
-    out = out or alloc_images(cfg, frame, int(head["b2"].shape[0]) if learned else 0, learned)
+    out = out or alloc_images(cfg, frame, int(head["b2"].shape[0]) if learned else 0, learned,
+                              state_capacity=sorter.capacity if split else None)
     gs = gaussians_struct(g)
     ps = _projected(proj)
     im = _images(out, frame.n_pixels)

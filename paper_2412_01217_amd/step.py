@@ -15,7 +15,7 @@ from . import raster
 
 class MappingStep:
     def __init__(self, cfg, frame: raster.Frame, g: dict, targets: dict, n_classes: int, w=(1.0, 1.0, 1.0),
-                 capacity_margin=1.15, head: dict | None = None):
+                 capacity_margin=1.15, head: dict | None = None, split=True):
         self.cfg, self.frame, self.g, self.targets = cfg, frame, g, targets
         self.n_classes = n_classes
         self.head = head
@@ -30,7 +30,8 @@ class MappingStep:
         del probe
         self.sorter = raster.Sorter(cfg, frame, n, capacity=int(self.n_dup_probe * capacity_margin) + 4096)
         learned = head is not None
-        self.img = raster.alloc_images(cfg, frame, n_classes if learned else 0, learned)
+        self.img = raster.alloc_images(cfg, frame, n_classes if learned else 0, learned,
+                                       state_capacity=self.sorter.capacity if split else None)
         self.grad = dict(color=torch.zeros_like(self.img["color"]),
                          logits=torch.empty_like(self.img["logits"]) if learned else None)
         self.loss = torch.empty(3 * frame.n_items, dtype=torch.float32, device=dev)

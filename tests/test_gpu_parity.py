@@ -43,14 +43,19 @@ CASES = {
 }
 
 
-def _pipeline(sc, views, n_sem, variant=0):
+def _pipeline(sc, views, n_sem, variant=0, split=True, state_capacity=None, fwd_chunk=1):
+    """split: forward with its state (long lists in segments of fwd_chunk 256-entry pieces,
+    0 = whole lists); state_capacity overrides the capacity the state is sized for."""
     raster = _raster()
-    cfg = raster.config(n_sem, variant=variant)
+    cfg = raster.config(n_sem, variant=variant, fwd_chunk=fwd_chunk)
     fr = raster.Frame(cfg, views)
     g = raster.to_device(sc)
     proj = raster.preprocess(cfg, g, fr)
     srt = raster.bin_sort(cfg, proj, fr, sc.n, want_keys=True)
-    img = raster.render_fwd(cfg, g, proj, fr, srt)
+    out = None
+    if split and state_capacity is not None:
+        out = raster.alloc_images(cfg, fr, state_capacity=state_capacity)
+    img = raster.render_fwd(cfg, g, proj, fr, srt, out=out, split=split)
     torch.cuda.synchronize()
     return cfg, fr, g, proj, srt, img
 
@@ -156,14 +161,32 @@ def test_bin_sort_capacity_overflow_reports_status():
     assert int(s2.status.item()) == _lib.GS_OK and int(s2.n_dup.item()) == int(s.n_dup.item())
 
 
-VARIANTS = {"valu": 1, "mfma": 2, "split": 3}
+# (render variant, forward with its state, forward chunk): "split_nostate" is the bfloat16
+# matrix-core path with every tile list composited whole and the reverse pass's own
+# summary pass; with the state, a forward work item walks 1 or 2 segments of 256 entries
+# (longer lists start from the transmittance pre-pass) or the whole list (chunk 0)
+VARIANTS = {"valu": (1, False, 1), "mfma": (2, False, 1), "split": (3, True, 1), "split_chunk2": (3, True, 2),
+            "split_wholewalk": (3, True, 0), "split_nostate": (3, False, 1)}
 
 
 @pytest.mark.parametrize("variant", list(VARIANTS))
 @pytest.mark.parametrize("case", list(CASES))
 def test_render_fwd_parity(case, variant):
     sc, views = CASES[case]()
-    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, VARIANTS[variant])
+    _check_render_fwd(sc, views, *VARIANTS[variant])
+
+
+def test_render_fwd_state_too_small():
+    """A forward state sized for no duplicates cannot hold the long lists' segments; every
+    tile is then one item, in the forward and in the reverse pass."""
+    sc, views = CASES["room_long_lists"]()
+    _check_render_fwd(sc, views, 3, True, state_capacity=0)
+    _check_render_bwd("room_long_lists", 3, True, state_capacity=0)
+    _check_render_bwd("room_long_lists", 3, True, fwd_chunk=0, state_capacity=0)
+
+
+def _check_render_fwd(sc, views, variant, split, fwd_chunk=1, state_capacity=None):
+    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant, split, state_capacity, fwd_chunk)
     ref = oracle.render(oracle.Config(), sc, views)
     # sum_i w_i |f_i|: the magnitude a composited sum with mixed signs is measured against
     mag = oracle.render(oracle.Config(), sc, views, sem=np.abs(sc.sem))["img"]
@@ -212,18 +235,19 @@ def _shared_grad_image(fr, K, seed):
 @pytest.mark.parametrize("variant", list(VARIANTS))
 @pytest.mark.parametrize("case", list(CASES))
 def test_render_bwd_parity(case, variant):
-    _check_render_bwd(case, VARIANTS[variant])
+    _check_render_bwd(case, *VARIANTS[variant])
 
 
-def test_render_bwd_single_item_fallback():
+@pytest.mark.parametrize("split", [True, False])
+def test_render_bwd_single_item_fallback(split):
     """A workspace sized without the duplicate capacity cannot hold every segment of the
     long lists; the reverse pass then takes each tile as one work item."""
-    _check_render_bwd("room_long_lists", 3, small_workspace=True)
+    _check_render_bwd("room_long_lists", 3, split, small_workspace=True)
 
 
-def _check_render_bwd(case, variant, small_workspace=False):
+def _check_render_bwd(case, variant, split, fwd_chunk=1, small_workspace=False, state_capacity=None):
     sc, views = CASES[case]()
-    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant)
+    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant, split, state_capacity, fwd_chunk)
     raster = _raster()
     ws = None
     if small_workspace:

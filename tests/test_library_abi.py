@@ -27,7 +27,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(L.Config) == 48
+    assert ctypes.sizeof(L.Config) == 52
+    assert ctypes.sizeof(L.Images) == 56
     assert ctypes.sizeof(L.View) == 56
     assert ctypes.sizeof(L.Item) == 56
     assert ctypes.sizeof(L.Gaussians) == 64
@@ -40,6 +41,7 @@ def test_defaults_and_status_strings():
     assert (c.tile_w, c.tile_h) == (16, 16)
     assert c.alpha_min == pytest.approx(1 / 255) and c.alpha_max == pytest.approx(0.99)
     assert c.t_min == pytest.approx(1e-4) and c.z_near == pytest.approx(0.2)
+    assert (c.variant, c.tile_order, c.fwd_chunk) == (0, 0, 1)
     assert lib.gs_status_string(L.GS_ERR_CAPACITY) == b"duplicate capacity exceeded"
     assert lib.gs_version() > 0
 
@@ -99,3 +101,28 @@ def test_entry_points_reject_bad_arguments_on_host():
     assert lib.gs_bin_sort(ctypes.byref(c), ctypes.byref(p), ctypes.c_void_p(16), 1, 10, 4, 100,
                            ctypes.c_void_p(16), 1, None, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None,
                            None) in (L.GS_ERR_INVALID_ARG, L.GS_ERR_WORKSPACE)
+
+
+def test_forward_state_size_and_host_check():
+    """The forward state grows with the duplicate capacity and the channel count; a state
+    buffer too small for even one item per tile is refused before any launch."""
+    lib = L.lib()
+    c = L.Config()
+    lib.gs_config_default(ctypes.byref(c))
+    c.n_sem = 12
+    b0, b1, b2 = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.gs_workspace_size(L.GS_WS_RENDER_STATE, ctypes.byref(c), 3, 100, 40, 0, 0, ctypes.byref(b0)) == 0
+    assert lib.gs_workspace_size(L.GS_WS_RENDER_STATE, ctypes.byref(c), 3, 100, 40, 10000, 0, ctypes.byref(b1)) == 0
+    c.n_sem = 20
+    assert lib.gs_workspace_size(L.GS_WS_RENDER_STATE, ctypes.byref(c), 3, 100, 40, 10000, 0, ctypes.byref(b2)) == 0
+    # one slot per tile (and one spare) at capacity 0, 40 more segments at 10000 duplicates
+    assert b0.value >= 41 * 256 * 4 * (4 + 12 + 3)
+    assert b1.value - b0.value >= 40 * 256 * 4 * (4 + 12 + 3)
+    assert b2.value > b1.value
+    c.n_sem = 12
+    fake = ctypes.c_void_p(256)
+    g = L.Gaussians(10, fake, fake, fake, fake, fake, fake, None)
+    p = L.Projected(fake, fake, fake)
+    im = L.Images(fake, fake, fake, None, 0, fake, b0.value - 1)
+    assert lib.gs_render_fwd(ctypes.byref(c), ctypes.byref(g), ctypes.byref(p), fake, 1, 40, fake, fake, None,
+                             ctypes.byref(im), None) == L.GS_ERR_WORKSPACE
