@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_fwd_trans(gs_config cfg, const float* _
                                                    const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges, const uint2* __restrict__ work,
                                                    uint32_t* __restrict__ ctl, float* __restrict__ P) {
-  __shared__ float s_rec[8 * kB];
+  __shared__ __align__(16) float s_rec[8 * kB];
   __shared__ uint32_t s_wi;
   const int tid = threadIdx.x;
   const float lx = (float)(tid & 15), ly = (float)(tid >> 4);
@@ -330,9 +330,9 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
                                                           FState fs) {
   using S = SShape<NS>;
   constexpr int CB = S::CB, KP = S::KP;
-  __shared__ float s_rec[8 * kB];
-  __shared__ uint32_t s_f[KP * kWs];          // F^T, packed hi|lo, [channel][Gaussian]
-  __shared__ float s_w[4][64 * kWs];          // per wave W, [pixel][Gaussian]
+  __shared__ __align__(16) float s_rec[8 * kB];
+  __shared__ __align__(16) uint32_t s_f[KP * kWs];          // F^T, packed hi|lo, [channel][Gaussian]
+  __shared__ __align__(16) float s_w[4][64 * kWs];          // per wave W, [pixel][Gaussian]
   __shared__ uint32_t s_wi;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, g4 = lane >> 4;
@@ -726,11 +726,12 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
   using S = SShape<NS>;
   constexpr int KP = S::KP, CB = S::CB, FST = S::FST;
   constexpr int GG = NS > 28 ? 2 : 4;         // Gaussians per geometric-term reduction (register budget)
-  __shared__ float s_rec[8 * kB];
-  __shared__ float s_f[kB * FST];             // F, [Gaussian][channel]
-  __shared__ float s_w[SUMMARY ? 1 : 4][16 * kPs];      // per wave, 16 Gaussians: W, [Gaussian][pixel]
-  __shared__ float s_df[SUMMARY ? 1 : kB * KP];
-  __shared__ float s_geo[SUMMARY ? 1 : kB * 6 * kGeoSlots];   // [Gaussian][component][partial sum]
+  __shared__ __align__(16) float s_rec[8 * kB];
+  __shared__ __align__(16) float s_f[kB * FST];             // F, [Gaussian][channel]
+  __shared__ __align__(16) float s_w[SUMMARY ? 1 : 4][16 * kPs];      // per wave, 16 Gaussians: W, [Gaussian][pixel]
+  constexpr int DFS = KP + 4;                 // row stride of s_df: lane rows land on other banks
+  __shared__ __align__(16) float s_df[SUMMARY ? 1 : kB * DFS];
+  __shared__ __align__(16) float s_geo[SUMMARY ? 1 : kB * 6 * kGeoSlots];   // [Gaussian][component][partial sum]
   __shared__ uint32_t s_wi;
   __shared__ uint32_t s_gid[kB];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -775,9 +776,23 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
     for (int pb = 0; pb < 4; ++pb)
 #pragma unroll
       for (int ks = 0; ks < KP / 4; ++ks) g1[pb][ks] = gval(16 * pb + l16, 4 * ks + g4);
-    // G as B of dF (k = pixel 32 ks + 8 g4 + e, j = channel 16 cb + l16)
+    // G as B of dF (k = pixel 32 ks + 8 g4 + e, j = channel 16 cb + l16); with registers to
+    // spare (up to 32 channels) every load is issued before the first split waits for one
     v8bf g2h[2][SUMMARY ? 1 : CB], g2l[2][SUMMARY ? 1 : CB];
-    if constexpr (!SUMMARY) {
+    if constexpr (!SUMMARY && KP <= 32) {
+      float x[2][CB][8];
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) x[ks][cb][e] = gval(32 * ks + 8 * g4 + e, 16 * cb + l16);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) split8(x[ks][cb], g2h[ks][cb], g2l[ks][cb]);
+    } else if constexpr (!SUMMARY) {
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
@@ -801,7 +816,19 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
         if (inside) {
           const float* sc = fs.CS + slot * Kr * kTilePx + tid;
           const float* gp = gcolor + c.pixel_base * Kr + (int64_t)v * c.W + u;
-          for (int k = 0; k < Kr; ++k) acc = __builtin_fmaf(gp[k * c.HW], sc[k * kTilePx], acc);
+          // eight channels' loads in flight at a time
+#pragma unroll 1
+          for (int k0 = 0; k0 < Kr; k0 += 8) {
+            float gv[8], sv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const bool ok = k0 + j < Kr;
+              gv[j] = ok ? gp[(k0 + j) * c.HW] : 0.0f;
+              sv[j] = ok ? sc[(k0 + j) * kTilePx] : 0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc = __builtin_fmaf(gv[j], sv[j], acc);
+          }
         }
       } else if (nseg > 1) {
         const int64_t w0 = (int64_t)wi - seg;
@@ -830,7 +857,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
       lds_barrier();
       st.commit_rows(s_rec, s_f, s_gid, ox, oy);
       if constexpr (!SUMMARY) {
-        for (int i = tid; i < kB * KP; i += 256) s_df[i] = 0.0f;
+        for (int i = tid; i < kB * DFS; i += 256) s_df[i] = 0.0f;
         for (int i = tid; i < kB * 6 * kGeoSlots / 4; i += 256) reinterpret_cast<float4*>(s_geo)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
       lds_barrier();
@@ -950,7 +977,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
                 // D[i][c]: Gaussian 16 bq + 4 g4 + r, channel 16 cb + l16
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                  if (d[r] != 0.0f) atomicAdd(&s_df[(16 * bq + 4 * g4 + r) * KP + 16 * cb + l16], d[r]);
+                  if (d[r] != 0.0f) atomicAdd(&s_df[(16 * bq + 4 * g4 + r) * DFS + 16 * cb + l16], d[r]);
               }
             }
             wave_sync();   // the block's W is consumed before the next block overwrites it
@@ -959,14 +986,38 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
       }
       if constexpr (!SUMMARY) {
         lds_barrier();
-        for (int idx = tid; idx < cnt * KP; idx += 256) {
-          const int q = idx / KP, k = idx - q * KP;
-          const float val = s_df[idx];
-          if (val == 0.0f || k >= Kr) continue;
-          const uint32_t g = s_gid[q];
-          if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
-          else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
-          else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
+        if constexpr (KP <= 32) {
+          // feature gradients: Gaussian q = idx / KP, channel k = idx % KP, all LDS reads first
+          constexpr int kFl = kB * KP / 256;
+          float fv[kFl];
+          uint32_t fg[kFl];
+#pragma unroll
+          for (int j = 0; j < kFl; ++j) {
+            const int idx = tid + 256 * j, q = idx / KP;
+            fv[j] = s_df[q * DFS + (idx - q * KP)];
+            fg[j] = s_gid[q];
+          }
+#pragma unroll
+          for (int j = 0; j < kFl; ++j) {
+            const int idx = tid + 256 * j, q = idx / KP, k = idx - q * KP;
+            const float val = fv[j];
+            if (q >= cnt || val == 0.0f || k >= Kr) continue;
+            const uint32_t g = fg[j];
+            if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
+            else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
+            else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
+          }
+        } else {
+          // (a register budget without room for the unrolled form)
+          for (int idx = tid; idx < cnt * KP; idx += 256) {
+            const int q = idx / KP, k = idx - q * KP;
+            const float val = s_df[q * DFS + k];
+            if (val == 0.0f || k >= Kr) continue;
+            const uint32_t g = s_gid[q];
+            if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
+            else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
+            else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
+          }
         }
         for (int idx = tid; idx < cnt * 6; idx += 256) {
           const int q = idx / 6, comp = idx - q * 6;
