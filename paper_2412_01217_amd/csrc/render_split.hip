@@ -576,9 +576,10 @@ __global__ __launch_bounds__(256) void k_fwd_combine(const gs_item* __restrict__
 // ------------------------------------------------------------------------- backward
 // Swaps the 4x4 blocks (lane row R, register group X[pb]) -> (lane row pb, group R):
 // permlane32 exchanges rows 0,1 with 2,3, permlane16 rows 0 with 1 and 2 with 3.
-__device__ __forceinline__ void block_transpose(uint32_t (&X)[4][8]) {
+template <int NK>
+__device__ __forceinline__ void block_transpose(uint32_t (&X)[4][NK]) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < NK; ++k) {
     auto s02 = __builtin_amdgcn_permlane32_swap(X[0][k], X[2][k], false, false);
     auto s13 = __builtin_amdgcn_permlane32_swap(X[1][k], X[3][k], false, false);
     X[0][k] = s02[0];
@@ -861,16 +862,23 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
         for (int i = tid; i < kB * 6 * kGeoSlots / 4; i += 256) reinterpret_cast<float4*>(s_geo)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
       lds_barrier();
-      if (bi + 1 < n_batches) {
-        const int nlo = SUMMARY ? hi : max(a0, lo - kB);
-        const int nhi = SUMMARY ? min(b0, hi + kB) : lo;
-        st.fetch(vals, c.start + nlo, nhi - nlo, c.item, n, rec, depth, rgb, sem, emb, n_sem);
-      }
-      if (__ballot((uint32_t)lo < last) != 0ull) {
+      // the next batch's gather: the summary pass issues it here; the main pass after its
+      // recurrence, whose register peak it would otherwise add to
+      auto fetch_next = [&]() {
+        if (bi + 1 < n_batches) {
+          const int nlo = SUMMARY ? hi : max(a0, lo - kB);
+          const int nhi = SUMMARY ? min(b0, hi + kB) : lo;
+          st.fetch(vals, c.start + nlo, nhi - nlo, c.item, n, rec, depth, rgb, sem, emb, n_sem);
+        }
+      };
+      if constexpr (SUMMARY) fetch_next();
+      const bool wave_live = __ballot((uint32_t)lo < last) != 0ull;
+      if (!SUMMARY && !wave_live) fetch_next();
+      if (wave_live) {
         // GF^T[i][p] in single precision (it decides dL/dalpha, where terms cancel):
         // v_mfma_f32_16x16x4f32, A = F (i = Gaussian 16 bq + l16, k = channel 4 ks + g4), B = G^T
         uint32_t X[4][8];
-        {
+        if constexpr (SUMMARY) {
           v4f gfa[4][2];
 #pragma unroll
           for (int pb = 0; pb < 4; ++pb) gfa[pb][0] = gfa[pb][1] = zero4();
@@ -893,7 +901,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
         }
         // lane row g4 held Gaussians {4 g4 + r, 16 + 4 g4 + r} of all four pixel rows; now
         // every lane holds its own pixel's values: X[g][4 bq + r] = gf of Gaussian 16 bq + 4 g + r
-        block_transpose(X);
+        if constexpr (SUMMARY) block_transpose(X);
         if constexpr (SUMMARY) {
 #pragma unroll
           for (int q = 0; q < kB; ++q) {
@@ -907,9 +915,28 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
             T = act ? T - w : T;
           }
         } else {
-          // reverse recurrence, one 16-Gaussian block at a time (back to front)
+          // reverse recurrence, one 16-Gaussian block at a time (back to front), each with
+          // its own GF^T block: Y[g][r] = gf of Gaussian 16 bq + 4 g + r after the transpose
 #pragma unroll
           for (int bq = 1; bq >= 0; --bq) {
+            uint32_t Y4[4][4];
+            {
+              v4f gfa[4];
+#pragma unroll
+              for (int pb = 0; pb < 4; ++pb) gfa[pb] = zero4();
+#pragma unroll
+              for (int ks = 0; ks < KP / 4; ++ks) {
+                const float a = s_f[(16 * bq + l16) * FST + 4 * ks + g4];
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb)
+                  gfa[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g1[pb][ks], gfa[pb], 0, 0, 0);
+              }
+#pragma unroll
+              for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Y4[pb][r] = __float_as_uint(gfa[pb][r]);
+            }
+            block_transpose(Y4);
             float* Wp = s_w[wave];
             bool any = false;
 #pragma unroll
@@ -928,7 +955,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
                 const float rom = __builtin_amdgcn_rcpf(1.0f - a);
                 const float Tq = act ? T * rom : T;   // transmittance in front of this Gaussian
                 const float w = act ? a * Tq : 0.0f;
-                const float gf = __uint_as_float(X[qq >> 2][4 * bq + (qq & 3)]);
+                const float gf = __uint_as_float(Y4[qq >> 2][qq & 3]);
                 const float dalpha = Tq * gf - acc * rom;
                 acc = act ? __builtin_fmaf(gf, w, acc) : acc;
                 T = Tq;
@@ -958,6 +985,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
                 for (int j = 0; j < 3; ++j) dst[j * kGeoSlots] = Y[j];
               }
             }
+            if (bq == 0) fetch_next();
             wave_sync();
             if (__ballot(any) != 0ull) {
               // A = W^T (i = Gaussian l16 of the block, k = pixel 32 ks + 8 g4 + e)
