@@ -729,10 +729,16 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
   constexpr int GG = NS > 28 ? 2 : 4;         // Gaussians per geometric-term reduction (register budget)
   __shared__ __align__(16) float s_rec[8 * kB];
   __shared__ __align__(16) float s_f[kB * FST];             // F, [Gaussian][channel]
-  __shared__ __align__(16) float s_w[SUMMARY ? 1 : 4][16 * kPs];      // per wave, 16 Gaussians: W, [Gaussian][pixel]
   constexpr int DFS = KP + 4;                 // row stride of s_df: lane rows land on other banks
-  __shared__ __align__(16) float s_df[SUMMARY ? 1 : kB * DFS];
-  __shared__ __align__(16) float s_geo[SUMMARY ? 1 : kB * 6 * kGeoSlots];   // [Gaussian][component][partial sum]
+  // One pool for the batch loop's W (per wave, 16 Gaussians, [Gaussian][pixel]), dF
+  // ([Gaussian][channel]) and geometric partial sums ([Gaussian][component][slot]); at the
+  // start of a work item each wave stages its pixels' upstream gradient in it instead
+  // (32 channels at a time, [channel][pixel], rows of kGst floats).
+  constexpr int kWsz = 4 * 16 * kPs, kDsz = kB * DFS, kGsz = kB * 6 * kGeoSlots, kGst = 64 + 4;
+  static_assert(4 * 32 * kGst <= kWsz + kDsz + kGsz, "staging fits the pool");
+  __shared__ __align__(16) float s_pool[SUMMARY ? 1 : kWsz + kDsz + kGsz];
+  float* const s_df = s_pool + kWsz;
+  float* const s_geo = s_pool + kWsz + kDsz;
   __shared__ uint32_t s_wi;
   __shared__ uint32_t s_gid[kB];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -773,36 +779,58 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
     };
     // G^T as B of GF (k = channel 4 ks + g4, j = pixel 16 pb + l16)
     float g1[4][KP / 4];
+    if constexpr (SUMMARY) {
 #pragma unroll
-    for (int pb = 0; pb < 4; ++pb)
+      for (int pb = 0; pb < 4; ++pb)
 #pragma unroll
-      for (int ks = 0; ks < KP / 4; ++ks) g1[pb][ks] = gval(16 * pb + l16, 4 * ks + g4);
-    // G as B of dF (k = pixel 32 ks + 8 g4 + e, j = channel 16 cb + l16); with registers to
-    // spare (up to 32 channels) every load is issued before the first split waits for one
+        for (int ks = 0; ks < KP / 4; ++ks) g1[pb][ks] = gval(16 * pb + l16, 4 * ks + g4);
+    }
+    // G as B of dF (k = pixel 32 ks + 8 g4 + e, j = channel 16 cb + l16). Main pass: each
+    // wave stages its 64 pixels' upstream gradient, 32 channels at a time, with one
+    // coalesced load per channel and lane, and builds both operand layouts from LDS; the
+    // lane's own pixel's values also give the state's dot product.
     v8bf g2h[2][SUMMARY ? 1 : CB], g2l[2][SUMMARY ? 1 : CB];
-    if constexpr (!SUMMARY && KP <= 32) {
-      float x[2][CB][8];
+    float gdot = 0.0f;          // sum_k g_k S_k of the lane's pixel (forward state)
+    if constexpr (!SUMMARY) {
+      const bool use_state = nseg > 1 && fs.tcnt != nullptr && inside;
+      const float* sc = use_state ? fs.CS + ((int64_t)fs.tbase[tile] + seg) * Kr * kTilePx + tid : nullptr;
+      const float* gp = gcolor + c.pixel_base * Kr + (int64_t)v * c.W + u;   // this lane's pixel (tid)
+      float* stg = s_pool + wave * 32 * kGst;
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
+      for (int h = 0; h < KP / 32; ++h) {
+        float gl[32];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
+        for (int j = 0; j < 32; ++j) gl[j] = (inside && 32 * h + j < Kr) ? gp[(int64_t)(32 * h + j) * c.HW] : 0.0f;
+        if (use_state) {
+          // all 32 loads in flight where the registers allow it, else 8 at a time
+          constexpr int kSv = KP <= 32 ? 32 : 8;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) x[ks][cb][e] = gval(32 * ks + 8 * g4 + e, 16 * cb + l16);
-      __builtin_amdgcn_sched_barrier(0);
+          for (int j0 = 0; j0 < 32; j0 += kSv) {
+            float sv[kSv];
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
+            for (int j = 0; j < kSv; ++j) sv[j] = 32 * h + j0 + j < Kr ? sc[(32 * h + j0 + j) * kTilePx] : 0.0f;
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) split8(x[ks][cb], g2h[ks][cb], g2l[ks][cb]);
-    } else if constexpr (!SUMMARY) {
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          float x[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) x[e] = gval(32 * ks + 8 * g4 + e, 16 * cb + l16);
-          split8(x, g2h[ks][cb], g2l[ks][cb]);
+            for (int j = 0; j < kSv; ++j) gdot = __builtin_fmaf(gl[j0 + j], sv[j], gdot);
+          }
         }
+#pragma unroll
+        for (int j = 0; j < 32; ++j) stg[j * kGst + lane] = gl[j];
+        wave_sync();
+#pragma unroll
+        for (int ks = 8 * h; ks < 8 * h + 8; ++ks)
+#pragma unroll
+          for (int pb = 0; pb < 4; ++pb) g1[pb][ks] = stg[(4 * ks + g4 - 32 * h) * kGst + 16 * pb + l16];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+          for (int cb = 2 * h; cb < 2 * h + 2; ++cb) {
+            const float* src = stg + (16 * cb + l16 - 32 * h) * kGst + 32 * ks + 8 * g4;
+            const float4 x0 = *reinterpret_cast<const float4*>(src), x1 = *reinterpret_cast<const float4*>(src + 4);
+            const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+            split8(x, g2h[ks][cb], g2l[ks][cb]);
+          }
+        wave_sync();   // every lane has read the stage before the next half overwrites it
+      }
     }
 
     // per-pixel state at the segment's back end (main pass) or front end (summary pass)
@@ -814,23 +842,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
         // the forward's state: T at the segment's end and the suffix colour sum
         const int64_t slot = (int64_t)fs.tbase[tile] + seg, o = slot * kTilePx + tid;
         if (fs.info[o] & kInfoActive) T = fs.Te[o];
-        if (inside) {
-          const float* sc = fs.CS + slot * Kr * kTilePx + tid;
-          const float* gp = gcolor + c.pixel_base * Kr + (int64_t)v * c.W + u;
-          // eight channels' loads in flight at a time
-#pragma unroll 1
-          for (int k0 = 0; k0 < Kr; k0 += 8) {
-            float gv[8], sv[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const bool ok = k0 + j < Kr;
-              gv[j] = ok ? gp[(k0 + j) * c.HW] : 0.0f;
-              sv[j] = ok ? sc[(k0 + j) * kTilePx] : 0.0f;
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) acc = __builtin_fmaf(gv[j], sv[j], acc);
-          }
-        }
+        acc = gdot;
       } else if (nseg > 1) {
         const int64_t w0 = (int64_t)wi - seg;
         float tb = 1.0f;   // transmittance in front of segment s
@@ -937,7 +949,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
                 for (int r = 0; r < 4; ++r) Y4[pb][r] = __float_as_uint(gfa[pb][r]);
             }
             block_transpose(Y4);
-            float* Wp = s_w[wave];
+            float* Wp = s_pool + wave * 16 * kPs;
             bool any = false;
 #pragma unroll
             for (int gb = 16 / GG - 1; gb >= 0; --gb) {
