@@ -121,6 +121,71 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* __r
   }
 }
 
+// One workgroup scans inputs up to kOneMax elements in tiles of 16K (16 consecutive per
+// thread), carrying the running total and loading the next tile while scanning this one:
+// one launch instead of three, where launch latency rather than bandwidth sets the time
+// (radix histograms, per-tile counts).
+constexpr int kOneThreads = 1024;
+constexpr int kOneItems = 16;
+constexpr int kOneTile = kOneItems * kOneThreads;
+constexpr int64_t kOneMax = (int64_t)1 << 15;
+
+__device__ __forceinline__ void one_load(const uint32_t* in, int64_t i0, int64_t count, uint32_t (&v)[kOneItems]) {
+  if (i0 + kOneItems <= count && ((reinterpret_cast<uintptr_t>(in + i0) & 15) == 0)) {
+#pragma unroll
+    for (int k = 0; k < kOneItems; k += 4) {
+      const uint4 q = *reinterpret_cast<const uint4*>(in + i0 + k);
+      v[k] = q.x; v[k + 1] = q.y; v[k + 2] = q.z; v[k + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kOneItems; ++k) v[k] = i0 + k < count ? in[i0 + k] : 0u;
+  }
+}
+
+__global__ __launch_bounds__(kOneThreads) void k_scan_one(const uint32_t* in, const uint64_t* count_dev,
+                                                          int64_t count_host, uint32_t* out, uint64_t* total_out) {
+  __shared__ uint32_t sh[kOneThreads / 64];
+  const int64_t count = count_dev ? (int64_t)*count_dev : count_host;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  uint64_t carry = 0;
+  uint32_t cur[kOneItems], nxt[kOneItems];
+  if (count > 0) one_load(in, (int64_t)kOneItems * t, count, cur);
+  for (int64_t base = 0; base < count; base += kOneTile) {
+    const int64_t i0 = base + (int64_t)kOneItems * t;
+    if (base + kOneTile < count) one_load(in, i0 + kOneTile, count, nxt);
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kOneItems; ++k) s += cur[k];
+    uint32_t inc = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t x = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += x;
+    }
+    if (lane == 63) sh[wid] = inc;
+    __syncthreads();
+    uint32_t wbase = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kOneThreads / 64; ++w) {
+      const uint32_t x = sh[w];
+      wbase += w < wid ? x : 0u;
+      tot += x;
+    }
+    __syncthreads();   // sh is rewritten for the next tile
+    uint32_t run = (uint32_t)carry + wbase + (inc - s);
+#pragma unroll
+    for (int k = 0; k < kOneItems; ++k) {
+      if (i0 + k < count) out[i0 + k] = run;
+      run += cur[k];
+    }
+    carry += tot;
+#pragma unroll
+    for (int k = 0; k < kOneItems; ++k) cur[k] = nxt[k];
+  }
+  if (t == 0 && total_out) *total_out = carry;
+}
+
 // ---------------------------------------------------------------------------
 // Stable LSD radix sort pass (8-bit digit) of (key, value) pairs.
 // ---------------------------------------------------------------------------
@@ -340,6 +405,10 @@ SortWs plan_sort(int64_t E, int64_t cap, void* base) {
 // Exclusive scan of in[0..count) into out; total (if non-null) to *total.
 int device_scan(const uint32_t* in, uint32_t* out, const uint64_t* count_dev, int64_t count_host, int64_t cap_count,
                 uint32_t* partial, uint64_t* total, hipStream_t s) {
+  if (cap_count <= kOneMax) {
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kOneThreads), 0, s, in, count_dev, count_host, out, total);
+    return launch_status();
+  }
   const int64_t nb = std::max<int64_t>(1, ceil_div(cap_count, kScanTile));
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, count_dev, count_host, partial);
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partial, nb, count_dev, count_host, total);
