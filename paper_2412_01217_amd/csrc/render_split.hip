@@ -605,15 +605,17 @@ __device__ __forceinline__ void block_transpose(uint32_t (&X)[4][NK]) {
 // d power/d mean2d = -(dE/d dx, dE/d dy) / log2(e) and d power/d(A, B, C) =
 // -(dx^2 / 2, dx dy, dy^2 / 2); the reverse pass sums dE/d dx, dE/d dy, dx^2, dx dy, dy^2
 // (times dL/d power) and applies these factors once per Gaussian.
-// Partial sums per (Gaussian, component) left in LDS by a batch: 8 per wave.
-constexpr int kGeoSlots = 32;
+// Partial sums per (Gaussian, component) left in LDS by a batch: 4 per wave.
+constexpr int kGeoSlots = 16;
 
 // Sums the geometric terms of GG Gaussians (6 GG values per lane) over the wave's four
 // lane rows and over the lane pairs (l16, l16 ^ 8) of a row, halving the values held at each
 // step instead of reducing each value separately: a permlane32 swap pairs rows (0, 2) and
 // (1, 3), a permlane16 swap rows (0, 1) and (2, 3), a row rotation by 8 the halves of a row.
-// Lane (row R, l16) returns Y[j] = sum of V[f + j] over the 8 lanes (l16 % 8 + {0, 8}) x rows,
-// f = 6 R + 3 (l16 / 8) for GG = 4 and f = 3 R for GG = 2.
+// A last mirror within each half row pairs lanes i and 7 - i. Lane (row R, l16) returns
+// Y[j] = sum of V[f + j] over the 16 lanes (l16 % 4, 7 - l16 % 4) + {0, 8}, times the four
+// rows, with f = 6 R + 3 (l16 / 8) for GG = 4 and f = 3 R for GG = 2. Lanes with l16 % 8 < 4
+// hold the distinct sums (for GG = 2 the two half rows hold the same ones).
 template <int GG>
 __device__ __forceinline__ void geo_reduce(const float (&V)[6 * GG], float (&Y)[3]) {
   constexpr int H1 = 3 * GG, H2 = 3 * GG / 2;
@@ -639,6 +641,8 @@ __device__ __forceinline__ void geo_reduce(const float (&V)[6 * GG], float (&Y)[
 #pragma unroll
     for (int j = 0; j < 3; ++j) Y[j] = X[j] + dpp_ror8(X[j]);
   }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Y[j] += dpp_half_mirror(Y[j]);
 }
 
 __constant__ float kGeoScale[6] = {-1.0f / kLog2e, -1.0f / kLog2e, -0.5f, -1.0f, -0.5f, 1.0f};
@@ -730,17 +734,16 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
   __shared__ __align__(16) float s_rec[8 * kB];
   __shared__ __align__(16) float s_f[kB * FST];             // F, [Gaussian][channel]
   constexpr int DFS = KP + 4;                 // row stride of s_df: lane rows land on other banks
-  // One pool for the batch loop's W (per wave, 16 Gaussians, [Gaussian][pixel]), dF
-  // ([Gaussian][channel]) and geometric partial sums ([Gaussian][component][slot]); at the
-  // start of a work item each wave stages its pixels' upstream gradient in it instead
-  // (32 channels at a time, [channel][pixel], rows of kGst floats).
+  // One pool for the batch loop's W (per wave, 16 Gaussians, [Gaussian][pixel]) and two
+  // buffers each of dF ([Gaussian][channel]) and geometric partial sums
+  // ([Gaussian][component][slot]): a batch's sums are flushed to global memory during the
+  // next batch. At the start of a work item each wave stages its pixels' upstream gradient
+  // in the pool instead (32 channels at a time, [channel][pixel], rows of kGst floats).
   constexpr int kWsz = 4 * 16 * kPs, kDsz = kB * DFS, kGsz = kB * 6 * kGeoSlots, kGst = 64 + 4;
-  static_assert(4 * 32 * kGst <= kWsz + kDsz + kGsz, "staging fits the pool");
-  __shared__ __align__(16) float s_pool[SUMMARY ? 1 : kWsz + kDsz + kGsz];
-  float* const s_df = s_pool + kWsz;
-  float* const s_geo = s_pool + kWsz + kDsz;
+  static_assert(4 * 32 * kGst <= kWsz + 2 * kDsz + 2 * kGsz, "staging fits the pool");
+  __shared__ __align__(16) float s_pool[SUMMARY ? 1 : kWsz + 2 * kDsz + 2 * kGsz];
   __shared__ uint32_t s_wi;
-  __shared__ uint32_t s_gid[kB];
+  __shared__ uint32_t s_gid[2][kB];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, g4 = lane >> 4;
   const int Kr = 4 + n_sem;
@@ -862,18 +865,79 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
       st.fetch(vals, c.start + f0, f1 - f0, c.item, n, rec, depth, rgb, sem, emb, n_sem);
     }
     const int n_batches = (b0 - a0 + kB - 1) / kB;
+    // one FP32 atomic per (Gaussian, channel) and (Gaussian, component) of a finished batch
+    auto flush = [&](int fb, int fcnt) {
+      const float* fdf = s_pool + kWsz + fb * kDsz;
+      const float* fgeo = s_pool + kWsz + 2 * kDsz + fb * kGsz;
+      const uint32_t* fgid = s_gid[fb];
+      if constexpr (KP <= 32) {
+        // feature gradients: Gaussian q = idx / KP, channel k = idx % KP, all LDS reads first
+        constexpr int kFl = kB * KP / 256;
+        float fv[kFl];
+        uint32_t fg[kFl];
+#pragma unroll
+        for (int j = 0; j < kFl; ++j) {
+          const int idx = tid + 256 * j, q = idx / KP;
+          fv[j] = fdf[q * DFS + (idx - q * KP)];
+          fg[j] = fgid[q];
+        }
+#pragma unroll
+        for (int j = 0; j < kFl; ++j) {
+          const int idx = tid + 256 * j, q = idx / KP, k = idx - q * KP;
+          const float val = fv[j];
+          if (q >= fcnt || val == 0.0f || k >= Kr) continue;
+          const uint32_t g = fg[j];
+          if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
+          else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
+          else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
+        }
+      } else {
+        // (a register budget without room for the unrolled form)
+        for (int idx = tid; idx < fcnt * KP; idx += 256) {
+          const int q = idx / KP, k = idx - q * KP;
+          const float val = fdf[q * DFS + k];
+          if (val == 0.0f || k >= Kr) continue;
+          const uint32_t g = fgid[q];
+          if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
+          else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
+          else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
+        }
+      }
+      for (int idx = tid; idx < fcnt * 6; idx += 256) {
+        const int q = idx / 6, comp = idx - q * 6;
+        const float4* src = reinterpret_cast<const float4*>(fgeo + idx * kGeoSlots);
+        float sum = 0.0f;
+#pragma unroll
+        for (int r = 0; r < kGeoSlots / 4; ++r) {
+          const float4 x = src[r];
+          sum += (x.x + x.y) + (x.z + x.w);
+        }
+        if (sum != 0.0f) {
+          const uint32_t g = fgid[q];
+          atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + comp], sum * kGeoScale[comp]);
+        }
+      }
+    };
+    int prev_cnt = 0;
     for (int bi = 0; bi < n_batches; ++bi) {
       // main pass: batches from the back; summary pass: from the front
       const int lo = SUMMARY ? a0 + bi * kB : max(a0, b0 - (bi + 1) * kB);
       const int hi = SUMMARY ? min(b0, lo + kB) : b0 - bi * kB;
       const int cnt = hi - lo;
+      const int buf = bi & 1;
+      float* const s_df = s_pool + kWsz + buf * kDsz;
+      float* const s_geo = s_pool + kWsz + 2 * kDsz + buf * kGsz;
       lds_barrier();
-      st.commit_rows(s_rec, s_f, s_gid, ox, oy);
+      st.commit_rows(s_rec, s_f, s_gid[buf], ox, oy);
       if constexpr (!SUMMARY) {
         for (int i = tid; i < kB * DFS; i += 256) s_df[i] = 0.0f;
         for (int i = tid; i < kB * 6 * kGeoSlots / 4; i += 256) reinterpret_cast<float4*>(s_geo)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
       lds_barrier();
+      // every wave is done with the previous batch: its sums go out while this one runs
+      if constexpr (!SUMMARY)
+        if (bi > 0) flush(buf ^ 1, prev_cnt);
+      prev_cnt = cnt;
       // the next batch's gather: the summary pass issues it here; the main pass after its
       // recurrence, whose register peak it would otherwise add to
       auto fetch_next = [&]() {
@@ -992,9 +1056,10 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
                 // Gaussian and first component of this lane's three sums
                 const int qd = 16 * bq + GG * gb + (GG == 4 ? g4 : g4 >> 1);
                 const int k0 = GG == 4 ? 3 * (l16 >> 3) : 3 * (g4 & 1);
-                float* dst = s_geo + (qd * 6 + k0) * kGeoSlots + wave * 8 + (l16 & 7);
+                float* dst = s_geo + (qd * 6 + k0) * kGeoSlots + wave * 4 + (l16 & 3);
+                if ((l16 & 4) == 0 && (GG == 4 || l16 < 8))
 #pragma unroll
-                for (int j = 0; j < 3; ++j) dst[j * kGeoSlots] = Y[j];
+                  for (int j = 0; j < 3; ++j) dst[j * kGeoSlots] = Y[j];
               }
             }
             if (bq == 0) fetch_next();
@@ -1024,52 +1089,12 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
           }
         }
       }
-      if constexpr (!SUMMARY) {
+    }
+    // the work item's last batch
+    if constexpr (!SUMMARY) {
+      if (n_batches > 0) {
         lds_barrier();
-        if constexpr (KP <= 32) {
-          // feature gradients: Gaussian q = idx / KP, channel k = idx % KP, all LDS reads first
-          constexpr int kFl = kB * KP / 256;
-          float fv[kFl];
-          uint32_t fg[kFl];
-#pragma unroll
-          for (int j = 0; j < kFl; ++j) {
-            const int idx = tid + 256 * j, q = idx / KP;
-            fv[j] = s_df[q * DFS + (idx - q * KP)];
-            fg[j] = s_gid[q];
-          }
-#pragma unroll
-          for (int j = 0; j < kFl; ++j) {
-            const int idx = tid + 256 * j, q = idx / KP, k = idx - q * KP;
-            const float val = fv[j];
-            if (q >= cnt || val == 0.0f || k >= Kr) continue;
-            const uint32_t g = fg[j];
-            if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
-            else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
-            else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
-          }
-        } else {
-          // (a register budget without room for the unrolled form)
-          for (int idx = tid; idx < cnt * KP; idx += 256) {
-            const int q = idx / KP, k = idx - q * KP;
-            const float val = s_df[q * DFS + k];
-            if (val == 0.0f || k >= Kr) continue;
-            const uint32_t g = s_gid[q];
-            if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
-            else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
-            else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
-          }
-        }
-        for (int idx = tid; idx < cnt * 6; idx += 256) {
-          const int q = idx / 6, comp = idx - q * 6;
-          const float* src = s_geo + idx * kGeoSlots;
-          float sum = 0.0f;
-#pragma unroll
-          for (int r = 0; r < kGeoSlots; ++r) sum += src[r];
-          if (sum != 0.0f) {
-            const uint32_t g = s_gid[q];
-            atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + comp], sum * kGeoScale[comp]);
-          }
-        }
+        flush((n_batches - 1) & 1, prev_cnt);
       }
     }
     if constexpr (SUMMARY) {
