@@ -200,6 +200,7 @@ int gs_preprocess(const gs_config* cfg, const gs_gaussians* g, const gs_view* vi
  * tile << 32 | bits(depth), ties by index -- and ranges[2t], ranges[2t+1] receive
  * the first and one-past-last position of tile t ((0, 0) if empty).
  * vals[j] = Gaussian index of entry j; keys (may be NULL) = the 64-bit keys.
+ * Every entry with radius > 0 must have depth > 0 (gs_preprocess gives depth > z_near).
  * n_dup_dev (device int64) receives the duplicate count. If it exceeds dup_capacity,
  * status_dev (device int32) is set to GS_ERR_CAPACITY and nothing past the capacity
  * is written; otherwise status_dev is set to GS_OK. */

@@ -78,6 +78,7 @@ int launch_distill(const gs_item*, int, int64_t, int, const float*, const float*
                    hipStream_t);
 int launch_agree(const gs_item*, int, int64_t, int, const float*, const float*, unsigned long long*, hipStream_t);
 int launch_fill_f32(float*, int64_t, float, hipStream_t);
+int launch_zero_f32(float* const* p, const int64_t* n, int count, hipStream_t s);
 
 namespace {
 
@@ -292,10 +293,9 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   const int64_t n = g->n;
   gs_grads gr = *grads;
   if (learned) gr.sem = grads->emb;   // the semantic channels' gradient is the embedding's
-  int st = launch_fill_f32((float*)workspace, kSortBwdRecord * (int64_t)n_items * n, 0.0f, s);
-  st = st ? st : launch_fill_f32(gr.rgb, 3 * n, 0.0f, s);
-  if (cfg->n_sem > 0) st = st ? st : launch_fill_f32(gr.sem, (int64_t)cfg->n_sem * n, 0.0f, s);
-  st = st ? st : launch_fill_f32(gr.pose, 6ll * n_views, 0.0f, s);
+  float* const zp[4] = {(float*)workspace, gr.rgb, cfg->n_sem > 0 ? gr.sem : nullptr, gr.pose};
+  const int64_t zn[4] = {kSortBwdRecord * (int64_t)n_items * n, 3 * n, (int64_t)cfg->n_sem * n, 6ll * n_views};
+  int st = launch_zero_f32(zp, zn, 4, s);
   if (st) return st;
   if (learned) {
     if (!items_dev) return GS_ERR_INVALID_ARG;

@@ -25,6 +25,10 @@ constexpr int kRadixThreads = 256;
 constexpr int kRadixItems = 8;
 constexpr int kRadixTile = kRadixThreads * kRadixItems;  // 2048
 constexpr int kRadixWaveSpan = kRadixTile / 4;            // keys per wave
+// Digit widths: the (item, depth) keys of the visible entries take 31 + log2(items) bits,
+// three 11-bit passes for up to four items; the duplicates' tile ids take 8-bit passes.
+constexpr int kDigitVis = 11;
+constexpr int kDigitTile = 8;
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = threadIdx.x & 63;
@@ -187,32 +191,35 @@ __global__ __launch_bounds__(kOneThreads) void k_scan_one(const uint32_t* in, co
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort pass (8-bit digit) of (key, value) pairs.
+// Stable LSD radix sort pass (B-bit digit) of (key, value) pairs. Each wave ranks its
+// keys with B ballots per key; per-wave digit counters live in LDS (4 << B words).
 // ---------------------------------------------------------------------------
-template <class Key>
+template <class Key, int B>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const Key* __restrict__ keys, const uint64_t* count_dev,
                                                               int shift, int nblk, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  constexpr int ND = 1 << B;
+  __shared__ uint32_t h[ND];
+  for (int d = threadIdx.x; d < ND; d += kRadixThreads) h[d] = 0;
   __syncthreads();
   const int64_t count = (int64_t)*count_dev;
   const int64_t base = (int64_t)blockIdx.x * kRadixTile;
   for (int k = 0; k < kRadixItems; ++k) {
     const int64_t idx = base + (int64_t)k * kRadixThreads + threadIdx.x;
-    if (idx < count) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+    if (idx < count) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & (uint32_t)(ND - 1)], 1u);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < ND; d += kRadixThreads) hist[(int64_t)d * nblk + blockIdx.x] = h[d];
 }
 
-template <class Key>
+template <class Key, int B>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const Key* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                                  Key* __restrict__ kout, uint32_t* __restrict__ vout,
                                                                  const uint64_t* count_dev, int shift, int nblk,
                                                                  const uint32_t* __restrict__ offs) {
-  __shared__ uint32_t cnt[4][256];
+  constexpr int ND = 1 << B;
+  __shared__ uint32_t cnt[4][ND];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int d = lane; d < 256; d += 64) cnt[wid][d] = 0;
+  for (int d = lane; d < ND; d += 64) cnt[wid][d] = 0;
   __syncthreads();
   const int64_t count = (int64_t)*count_dev;
   const int64_t base = (int64_t)blockIdx.x * kRadixTile + (int64_t)wid * kRadixWaveSpan;
@@ -225,11 +232,11 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const Key* __re
     ok[r] = idx < count;
     k[r] = ok[r] ? kin[idx] : Key(0);
     v[r] = ok[r] ? vin[idx] : 0u;
-    const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+    const uint32_t d = (uint32_t)(k[r] >> shift) & (uint32_t)(ND - 1);
     dig[r] = d;
     uint64_t peers = __ballot(ok[r]);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < B; ++b) {
       const uint64_t m = __ballot((d >> b) & 1u);
       peers &= ((d >> b) & 1u) ? m : ~m;
     }
@@ -245,8 +252,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const Key* __re
   }
   __syncthreads();
   // per digit: exclusive prefix over the four waves
-  {
-    const int d = threadIdx.x;
+  for (int d = threadIdx.x; d < ND; d += kRadixThreads) {
     const uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d];
     const uint32_t g = offs[(int64_t)d * nblk + blockIdx.x];
     cnt[0][d] = g;
@@ -263,9 +269,6 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const Key* __re
   }
 }
 
-// ---------------------------------------------------------------------------
-// Compaction, footprint rectangles, duplication, ranges.
-// ---------------------------------------------------------------------------
 __global__ void k_visible_flags(const int32_t* __restrict__ radius, int64_t E, uint32_t* __restrict__ flags) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < E) flags[e] = radius[e] > 0 ? 1u : 0u;
@@ -279,7 +282,9 @@ __global__ void k_compact(const int32_t* __restrict__ radius, const float* __res
   if (e >= E || radius[e] <= 0) return;
   const uint32_t p = pos[e];
   const uint64_t item = (uint64_t)(e / n);
-  keys[p] = (item << 32) | (uint64_t)__float_as_uint(depth[e]);
+  // a visible entry's depth is above z_near > 0, so its sign bit is 0 (the mask only keeps
+  // an invalid negative depth from reaching the item bits)
+  keys[p] = (item << 31) | (uint64_t)(__float_as_uint(depth[e]) & 0x7fffffffu);
   vals[p] = (uint32_t)e;
 }
 
@@ -294,24 +299,62 @@ __global__ void k_touched(gs_config cfg, const uint32_t* __restrict__ svals, con
   touched[j] = (uint32_t)((R.x1 - R.x0) * (R.y1 - R.y0));
 }
 
-__global__ void k_duplicate(gs_config cfg, const uint32_t* __restrict__ svals, const uint64_t* count_dev,
-                            const uint32_t* __restrict__ offs, const float* __restrict__ rec,
-                            const int32_t* __restrict__ radius, const gs_item* __restrict__ items, int64_t n,
-                            int64_t cap, uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= (int64_t)*count_dev) return;
-  const uint32_t e = svals[j];
-  const int64_t item = e / n;
-  const uint32_t g = (uint32_t)(e - item * n);
-  const gs_item it = items[item];
-  const Rect R = tile_rect(cfg, it.tiles_x, it.tiles_y, *reinterpret_cast<const float4*>(rec + (int64_t)kRecFloats * e), radius[e]);
-  int64_t p = offs[j];
-  for (int ty = R.y0; ty < R.y1; ++ty)
-    for (int tx = R.x0; tx < R.x1; ++tx, ++p) {
-      if (p >= cap) return;
-      tkeys[p] = (uint32_t)(it.tile_base + ty * it.tiles_x + tx);
-      tvals[p] = g;
+// Each wave takes 64 consecutive depth-ordered entries and writes their duplicates as one
+// run (their offsets are consecutive): lane l of round k writes output k * 64 + l of the
+// run, finding its entry by a binary search over the wave's inclusive count prefix. A
+// footprint with many tiles is spread over the wave instead of one lane, and the stores
+// are coalesced.
+__global__ __launch_bounds__(256) void k_duplicate(gs_config cfg, const uint32_t* __restrict__ svals,
+                                                   const uint64_t* count_dev, const uint32_t* __restrict__ offs,
+                                                   const float* __restrict__ rec, const int32_t* __restrict__ radius,
+                                                   const gs_item* __restrict__ items, int64_t n, int64_t cap,
+                                                   uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
+  __shared__ uint32_t s_pre[4][64];   // inclusive prefix of the wave's tile counts
+  __shared__ int4 s_rect[4][64];      // x0, width, tiles_x, id of tile (0, y0) of the item
+  __shared__ uint32_t s_g[4][64];     // Gaussian index
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t count = (int64_t)*count_dev;
+  const int64_t j0 = ((int64_t)blockIdx.x * 4 + wid) * 64;
+  if (j0 >= count) return;
+  const int64_t j = j0 + lane;
+  uint32_t c = 0;
+  if (j < count) {
+    const uint32_t e = svals[j];
+    const int64_t item = e / n;
+    const gs_item it = items[item];
+    const Rect R = tile_rect(cfg, it.tiles_x, it.tiles_y, *reinterpret_cast<const float4*>(rec + (int64_t)kRecFloats * e),
+                             radius[e]);
+    const int w = R.x1 - R.x0;
+    c = (uint32_t)(w * (R.y1 - R.y0));
+    s_rect[wid][lane] = make_int4(R.x0, w, it.tiles_x, it.tile_base + R.y0 * it.tiles_x);
+    s_g[wid][lane] = (uint32_t)(e - item * n);
+  }
+  uint32_t inc = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  s_pre[wid][lane] = inc;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint32_t total = __shfl(inc, 63, 64);
+  const int64_t base = offs[j0];
+  for (uint32_t k = lane; k < total; k += 64) {
+    const int64_t pos = base + k;
+    if (pos >= cap) break;
+    int lo = 0, hi = 63;   // first entry whose inclusive prefix exceeds k
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s_pre[wid][mid] > k) hi = mid; else lo = mid + 1;
     }
+    const uint32_t m = k - (lo > 0 ? s_pre[wid][lo - 1] : 0u);   // index within the entry's rect
+    const int4 r = s_rect[wid][lo];
+    const int row = (int)(m / (uint32_t)r.y), col = (int)m - row * r.y;
+    tkeys[pos] = (uint32_t)(r.w + row * r.z + r.x + col);
+    tvals[pos] = s_g[wid][lo];
+  }
 }
 
 // Clamp the duplicate count to the capacity and report the status.
@@ -372,7 +415,7 @@ SortWs plan_sort(int64_t E, int64_t cap, void* base) {
   SortWs w{};
   const int64_t nmax = std::max<int64_t>(E, cap);
   const int64_t nblk = ceil_div(std::max<int64_t>(nmax, 1), kRadixTile);
-  const int64_t hist_n = 256 * nblk;
+  const int64_t hist_n = ((int64_t)1 << kDigitVis) * nblk;
   const int64_t np = ceil_div(std::max<int64_t>(std::max(nmax, hist_n), 1), kScanTile) + 2;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -416,18 +459,20 @@ int device_scan(const uint32_t* in, uint32_t* out, const uint64_t* count_dev, in
   return launch_status();
 }
 
-template <class Key>
+template <class Key, int B>
 int radix_sort(Key* k0, Key* k1, uint32_t* v0, uint32_t* v1, const uint64_t* count_dev, int64_t cap_count, int bits,
                SortWs& w, hipStream_t s, int* final_buf) {
   const int nblk = (int)std::max<int64_t>(1, ceil_div(cap_count, kRadixTile));
+  const int64_t nh = ((int64_t)1 << B) * nblk;
   Key* kb[2] = {k0, k1};
   uint32_t* vb[2] = {v0, v1};
   int cur = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(k_radix_hist<Key>, dim3(nblk), dim3(kRadixThreads), 0, s, kb[cur], count_dev, shift, nblk, w.hist);
-    int st = device_scan(w.hist, w.hist, nullptr, 256ll * nblk, 256ll * nblk, w.partial, nullptr, s);
+  for (int shift = 0; shift < bits; shift += B) {
+    hipLaunchKernelGGL((k_radix_hist<Key, B>), dim3(nblk), dim3(kRadixThreads), 0, s, kb[cur], count_dev, shift, nblk,
+                       w.hist);
+    int st = device_scan(w.hist, w.hist, nullptr, nh, nh, w.partial, nullptr, s);
     if (st) return st;
-    hipLaunchKernelGGL(k_radix_scatter<Key>, dim3(nblk), dim3(kRadixThreads), 0, s, kb[cur], vb[cur], kb[cur ^ 1],
+    hipLaunchKernelGGL((k_radix_scatter<Key, B>), dim3(nblk), dim3(kRadixThreads), 0, s, kb[cur], vb[cur], kb[cur ^ 1],
                        vb[cur ^ 1], count_dev, shift, nblk, w.hist);
     cur ^= 1;
   }
@@ -462,8 +507,8 @@ int launch_bin_sort(const gs_config& cfg, const gs_projected& proj, const gs_ite
                      w.vvals[0]);
   // 2. stable sort of the visible entries by (item, depth)
   int fin = 0;
-  st = radix_sort<uint64_t>(w.vkeys[0], w.vkeys[1], w.vvals[0], w.vvals[1], n_vis, E, 32 + bits_for((uint64_t)n_items), w,
-                            s, &fin);
+  st = radix_sort<uint64_t, kDigitVis>(w.vkeys[0], w.vkeys[1], w.vvals[0], w.vvals[1], n_vis, E,
+                                       31 + bits_for((uint64_t)n_items), w, s, &fin);
   if (st) return st;
   const uint32_t* svals = w.vvals[fin];
   // 3. duplicates in depth order
@@ -474,13 +519,13 @@ int launch_bin_sort(const gs_config& cfg, const gs_projected& proj, const gs_ite
   hipLaunchKernelGGL(k_dup_count, dim3(1), dim3(1), 0, s, d_total, cap, d_live, n_dup_dev, status_dev);
   // the tile sort must end in the caller's vals: start there after an even pass count
   const int tbits = std::max(1, bits_for((uint64_t)n_tiles));
-  const int passes = (tbits + 7) / 8;
+  const int passes = (tbits + kDigitTile - 1) / kDigitTile;
   uint32_t* v_first = (passes % 2 == 0) ? vals : w.tvals;
   uint32_t* v_other = (passes % 2 == 0) ? w.tvals : vals;
-  hipLaunchKernelGGL(k_duplicate, dim3(eb), dim3(256), 0, s, cfg, svals, n_vis, w.touched, proj.rec, proj.radius,
-                     items, n, cap, w.tkeys[0], v_first);
+  hipLaunchKernelGGL(k_duplicate, dim3((unsigned)std::max<int64_t>(1, ceil_div(E, 256))), dim3(256), 0, s, cfg, svals,
+                     n_vis, w.touched, proj.rec, proj.radius, items, n, cap, w.tkeys[0], v_first);
   // 4. stable sort of the duplicates by tile
-  st = radix_sort<uint32_t>(w.tkeys[0], w.tkeys[1], v_first, v_other, d_live, cap, tbits, w, s, &fin);
+  st = radix_sort<uint32_t, kDigitTile>(w.tkeys[0], w.tkeys[1], v_first, v_other, d_live, cap, tbits, w, s, &fin);
   if (st) return st;
   const uint32_t* tk = w.tkeys[fin];
   // 5. tile ranges

@@ -226,6 +226,34 @@ __global__ void k_argmax_labels(const gs_item* __restrict__ items, int n_items, 
 
 }  // namespace
 
+// Zeroes up to four arrays in one launch (grid-stride over their concatenation).
+struct ZeroList {
+  float* p[4];
+  int64_t end[4];   // running totals of the lengths
+};
+__global__ __launch_bounds__(256) void k_zero_multi(ZeroList z) {
+  const int64_t tot = z.end[3];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (i >= z.end[0]) + (i >= z.end[1]) + (i >= z.end[2]);
+    z.p[k][i - (k > 0 ? z.end[k - 1] : 0)] = 0.0f;
+  }
+}
+
+int launch_zero_f32(float* const* p, const int64_t* n, int count, hipStream_t s) {
+  ZeroList z{};
+  int64_t run = 0;
+  for (int k = 0; k < 4; ++k) {
+    const bool use = k < count && p[k] && n[k] > 0;
+    z.p[k] = use ? p[k] : nullptr;
+    run += use ? n[k] : 0;
+    z.end[k] = run;
+  }
+  if (run == 0) return GS_OK;
+  const int64_t blocks = std::min<int64_t>(ceil_div(run, 256), 4096);
+  hipLaunchKernelGGL(k_zero_multi, dim3((unsigned)blocks), dim3(256), 0, s, z);
+  return launch_status();
+}
+
 int launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   if (n <= 0) return GS_OK;
   hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, p, n, v);

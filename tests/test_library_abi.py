@@ -126,3 +126,17 @@ def test_forward_state_size_and_host_check():
     im = L.Images(fake, fake, fake, None, 0, fake, b0.value - 1)
     assert lib.gs_render_fwd(ctypes.byref(c), ctypes.byref(g), ctypes.byref(p), fake, 1, 40, fake, fake, None,
                              ctypes.byref(im), None) == L.GS_ERR_WORKSPACE
+
+
+def test_config_rejects_out_of_range_forward_chunk():
+    lib = L.lib()
+    c = L.Config()
+    lib.gs_config_default(ctypes.byref(c))
+    b = ctypes.c_size_t()
+    for bad in (-1, 65536):
+        c.fwd_chunk = bad
+        assert lib.gs_workspace_size(L.GS_WS_LOSS, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == \
+            L.GS_ERR_INVALID_ARG
+    for good in (0, 1, 65535):
+        c.fwd_chunk = good
+        assert lib.gs_workspace_size(L.GS_WS_LOSS, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == 0
