@@ -174,9 +174,10 @@ def backward(cfg: Config, scene, views, gimg, sem=None, tile_mask=None):
     return out
 
 
-def loss(views, S, img, t_rgb, t_depth, t_label, w=(1.0, 1.0, 1.0), tile_w=16, tile_h=16):
-    """Per-item [L1 rgb, L1 depth (valid), CE] means and the image-layout gradient of
-    w . sum over items."""
+def loss(views, S, img, t_rgb, t_depth, t_label, w=(1.0, 1.0, 1.0), tile_w=16, tile_h=16, ssim_lambda=0.0):
+    """Per-item [L_rgb, L1 depth (valid), CE] and the image-layout gradient of
+    w . sum over items. L_rgb = (1 - lambda) mean L1 + lambda (1 - mean SSIM); lambda = 0
+    gives the plain L1 mean."""
     lib = _load()
     n_items, P, _ = layout(views, tile_w, tile_h)
     K = 4 + S
@@ -185,8 +186,9 @@ def loss(views, S, img, t_rgb, t_depth, t_label, w=(1.0, 1.0, 1.0), tile_w=16, t
     ls = np.zeros((n_items, 3))
     gimg = np.zeros(P * K)
     lab = np.ascontiguousarray(t_label, dtype=np.int32)
+    w4 = np.array([w[0], w[1], w[2], ssim_lambda], np.float64)
     lib.or_loss(_p(ci), ctypes.c_int(len(views)), _p(vi), _p(_d(img)), _p(_d(t_rgb)), _p(_d(t_depth)),
-                _p(lab), _p(_d(w)), _p(ls), _p(gimg))
+                _p(lab), _p(w4), _p(ls), _p(gimg))
     return ls, gimg
 
 

@@ -629,9 +629,83 @@ int or_backward(const double* cd, const int* ci, int64_t n, const double* mean, 
   return 0;
 }
 
-// Pyramid loss, summed over items: w0 * mean|R-Rgt| over 3HW + w1 * mean|D-Dgt| over valid
-// (Dgt > 0) pixels + w2 * mean cross-entropy of softmax(S) against the label, per item.
-// loss: [n_items][3] unweighted means. gimg: dLoss/dimg in the image layout.
+// SSIM of Wang et al. 2004 as used by the RGB term of eq. 10: an 11 x 11 Gaussian window of
+// standard deviation 1.5 (normalised to sum 1), applied at every pixel with the image
+// taken as zero outside (a same-size map), C1 = 0.01^2, C2 = 0.03^2. Window sums here are
+// the plain 2D sums of the definition.
+static void ssim_window(double g[11]) {
+  double t = 0;
+  for (int i = 0; i < 11; ++i) {
+    g[i] = std::exp(-double((i - 5) * (i - 5)) / (2.0 * 1.5 * 1.5));
+    t += g[i];
+  }
+  for (int i = 0; i < 11; ++i) g[i] /= t;
+}
+
+// out(q) = sum over the window of g(u) g(v) in(q + (u - 5, v - 5)), zero outside.
+static void ssim_filter(const double* in, int W, int H, double* out) {
+  double g[11];
+  ssim_window(g);
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      double a = 0;
+      for (int v = 0; v < 11; ++v) {
+        const int yy = y + v - 5;
+        if (yy < 0 || yy >= H) continue;
+        for (int u = 0; u < 11; ++u) {
+          const int xx = x + u - 5;
+          if (xx < 0 || xx >= W) continue;
+          a += g[u] * g[v] * in[int64_t(yy) * W + xx];
+        }
+      }
+      out[int64_t(y) * W + x] = a;
+    }
+}
+
+// Mean SSIM of one channel x against y; grad (may be null) receives d(mean SSIM)/dx.
+static double ssim_channel(const double* x, const double* y, int W, int H, double* grad) {
+  const int64_t HW = int64_t(W) * H;
+  const double C1 = 0.01 * 0.01, C2 = 0.03 * 0.03;
+  std::vector<double> xx(HW), yy(HW), xy(HW), m1(HW), m2(HW), e11(HW), e22(HW), e12(HW);
+  for (int64_t p = 0; p < HW; ++p) {
+    xx[p] = x[p] * x[p];
+    yy[p] = y[p] * y[p];
+    xy[p] = x[p] * y[p];
+  }
+  ssim_filter(x, W, H, m1.data());
+  ssim_filter(y, W, H, m2.data());
+  ssim_filter(xx.data(), W, H, e11.data());
+  ssim_filter(yy.data(), W, H, e22.data());
+  ssim_filter(xy.data(), W, H, e12.data());
+  double sum = 0;
+  std::vector<double> A(HW), B(HW), Cc(HW);
+  for (int64_t q = 0; q < HW; ++q) {
+    const double mu1 = m1[q], mu2 = m2[q];
+    const double s11 = e11[q] - mu1 * mu1, s22 = e22[q] - mu2 * mu2, s12 = e12[q] - mu1 * mu2;
+    const double a = 2 * mu1 * mu2 + C1, b = 2 * s12 + C2, c = mu1 * mu1 + mu2 * mu2 + C1, d = s11 + s22 + C2;
+    const double S = a * b / (c * d);
+    sum += S;
+    // partial derivatives of S with respect to the window sums of x, x^2 and x y
+    A[q] = S * (2 * mu2 / a - 2 * mu2 / b - 2 * mu1 / c + 2 * mu1 / d);
+    B[q] = -S / d;
+    Cc[q] = 2 * S / b;
+  }
+  if (grad) {
+    // d S(q) / d x(p) reaches p through the window of q: the same (symmetric) window sums
+    std::vector<double> fA(HW), fB(HW), fC(HW);
+    ssim_filter(A.data(), W, H, fA.data());
+    ssim_filter(B.data(), W, H, fB.data());
+    ssim_filter(Cc.data(), W, H, fC.data());
+    for (int64_t p = 0; p < HW; ++p) grad[p] = (fA[p] + 2 * x[p] * fB[p] + y[p] * fC[p]) / double(HW);
+  }
+  return sum / double(HW);
+}
+
+// Pyramid loss, summed over items: w0 * L_rgb + w1 * mean|D-Dgt| over valid (Dgt > 0)
+// pixels + w2 * mean cross-entropy of softmax(S) against the label, per item, with
+// L_rgb = (1 - lambda) mean|R-Rgt| over 3HW + lambda (1 - mean SSIM over the 3 channels)
+// (eq. 10 with the SSIM term read as 1 - SSIM), lambda = w[3].
+// loss: [n_items][3] unweighted terms. gimg: dLoss/dimg in the image layout.
 int or_loss(const int* ci, int n_views, const int* vi, const double* img, const double* trgb, const double* tdepth,
             const int* tlabel, const double* w, double* loss, double* gimg) {
   double cd[8] = {0};
@@ -677,7 +751,19 @@ int or_loss(const int* ci, int n_views, const int* vi, const double* img, const 
         }
       }
     }
-    loss[3 * k] = lr / (3.0 * HW);
+    const double lam = w[3];
+    double ssim = 1.0;
+    if (lam != 0.0) {
+      double sm3 = 0;
+      std::vector<double> gs(HW);
+      for (int ch = 0; ch < 3; ++ch) {
+        sm3 += ssim_channel(I + ch * HW, TR + ch * HW, it.W, it.H, gs.data());
+        for (int64_t p = 0; p < HW; ++p)
+          GI[ch * HW + p] = (1.0 - lam) * GI[ch * HW + p] - w[0] * lam * gs[p] / 3.0;
+      }
+      ssim = sm3 / 3.0;
+    }
+    loss[3 * k] = (1.0 - lam) * lr / (3.0 * HW) + lam * (1.0 - ssim);
     loss[3 * k + 1] = nvalid ? ld / double(nvalid) : 0.0;
     loss[3 * k + 2] = S > 0 ? ls / double(HW) : 0.0;
   }

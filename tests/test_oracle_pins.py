@@ -320,6 +320,102 @@ def test_loss_gradient_finite_difference():
         assert fd == pytest.approx(g[j], rel=1e-6, abs=1e-9)
 
 
+# SSIM term of the RGB loss (eq. 10): 11 x 11 Gaussian window, sigma 1.5, zero outside.
+def _ssim_scipy(x, y):
+    """Mean SSIM from scipy's separable Gaussian filter (radius 5, normalised window,
+    zero padding): an implementation of the definition independent of the oracle's loops."""
+    from scipy import ndimage
+    f = lambda a: ndimage.gaussian_filter(a, 1.5, mode="constant", cval=0.0, truncate=5 / 1.5)  # noqa: E731
+    m1, m2 = f(x), f(y)
+    s11, s22, s12 = f(x * x) - m1 * m1, f(y * y) - m2 * m2, f(x * y) - m1 * m2
+    C1, C2 = 0.01 ** 2, 0.03 ** 2
+    return float(np.mean((2 * m1 * m2 + C1) * (2 * s12 + C2) / ((m1 * m1 + m2 * m2 + C1) * (s11 + s22 + C2))))
+
+
+def _rgb_only(W, H, S, rgb, rng):
+    """Image-layout buffer whose RGB planes are rgb and whose other planes are noise."""
+    img = np.zeros((4 + S, H, W))
+    img[:3] = rgb
+    img[3:] = rng.normal(size=(1 + S, H, W))
+    return img.reshape(-1)
+
+
+def test_ssim_matches_scipy_gaussian_filter():
+    rng = np.random.default_rng(21)
+    W, H, S = 23, 17, 2
+    v = view(W, H, 4.0)
+    x, y = rng.uniform(size=(3, H, W)), rng.uniform(size=(3, H, W))
+    y[1] = 0.6 * x[1] + 0.2                                       # a correlated channel
+    lam = 0.35
+    ls, _ = oracle.loss([v], S, _rgb_only(W, H, S, x, rng), y.reshape(-1), np.ones(W * H),
+                        np.zeros(W * H, np.int32), ssim_lambda=lam)
+    ssim = np.mean([_ssim_scipy(x[c], y[c]) for c in range(3)])
+    l1 = np.abs(x - y).mean()
+    assert ls[0, 0] == pytest.approx((1 - lam) * l1 + lam * (1 - ssim), rel=1e-12, abs=1e-14)
+
+
+def test_ssim_constant_images_closed_form():
+    # constant planes a and b: inside, sigma = 0 and S = (2ab + C1) / (a^2 + b^2 + C1); near the
+    # border the window covers a fraction k(q) of itself, giving means k a, k b, variances
+    # k (1 - k) a^2, k (1 - k) b^2 and covariance k (1 - k) a b.
+    W, H, S = 14, 13, 1                                           # the centre sees the whole window
+    a, b = 0.8, 0.3
+    rng = np.random.default_rng(22)
+    v = view(W, H, 4.0)
+    x = np.full((3, H, W), a)
+    y = np.full((3, H, W), b)
+    ls, _ = oracle.loss([v], S, _rgb_only(W, H, S, x, rng), y.reshape(-1), np.ones(W * H),
+                        np.zeros(W * H, np.int32), ssim_lambda=1.0)
+    g = np.exp(-((np.arange(11) - 5) ** 2) / (2 * 1.5 ** 2))
+    g /= g.sum()
+    cover = lambda n: np.array([g[max(0, 5 - i): min(11, n + 5 - i)].sum() for i in range(n)])  # noqa: E731
+    k = np.outer(cover(H), cover(W))
+    C1, C2 = 0.01 ** 2, 0.03 ** 2
+    m1, m2, v12 = k * a, k * b, k * (1 - k)
+    smap = ((2 * m1 * m2 + C1) * (2 * v12 * a * b + C2)
+            / ((m1 ** 2 + m2 ** 2 + C1) * (v12 * (a * a + b * b) + C2)))
+    assert ls[0, 0] == pytest.approx(1 - smap.mean(), rel=1e-12)
+    assert smap[H // 2, W // 2] == pytest.approx((2 * a * b + C1) / (a * a + b * b + C1), rel=1e-12)
+
+
+def test_ssim_of_identical_images_is_one_and_stationary():
+    rng = np.random.default_rng(23)
+    W, H, S = 19, 13, 2
+    v = view(W, H, 4.0)
+    x = rng.uniform(size=(3, H, W))
+    ls, g = oracle.loss([v], S, _rgb_only(W, H, S, x, rng), x.reshape(-1), np.zeros(W * H),
+                        np.zeros(W * H, np.int32), w=(1, 0, 0), ssim_lambda=1.0)
+    assert abs(ls[0, 0]) < 1e-14
+    assert np.abs(g.reshape(4 + S, H, W)[:3]).max() < 1e-13
+
+
+def test_ssim_symmetric_in_its_arguments():
+    rng = np.random.default_rng(24)
+    W, H, S = 16, 12, 1
+    v = view(W, H, 4.0)
+    x, y = rng.uniform(size=(3, H, W)), rng.uniform(size=(3, H, W))
+    args = (np.ones(W * H), np.zeros(W * H, np.int32))
+    l_xy = oracle.loss([v], S, _rgb_only(W, H, S, x, rng), y.reshape(-1), *args, ssim_lambda=1.0)[0][0, 0]
+    l_yx = oracle.loss([v], S, _rgb_only(W, H, S, y, rng), x.reshape(-1), *args, ssim_lambda=1.0)[0][0, 0]
+    assert l_xy == pytest.approx(l_yx, rel=1e-13)
+
+
+def test_ssim_loss_gradient_finite_difference():
+    rng = np.random.default_rng(25)
+    v = view(13, 11, 4.0)
+    S, HW = 3, 143
+    img = rng.uniform(size=(4 + S) * HW)
+    t_rgb, t_depth, t_lab = rng.uniform(size=3 * HW), rng.uniform(0, 2, HW), rng.integers(0, S, HW)
+    w, lam = (0.7, 1.3, 0.9), 0.2
+    ls, g = oracle.loss([v], S, img, t_rgb, t_depth, t_lab, w=w, ssim_lambda=lam)
+    L = lambda x: float(np.dot(w, oracle.loss([v], S, x, t_rgb, t_depth, t_lab, ssim_lambda=lam)[0][0]))  # noqa: E731
+    h = 1e-6
+    for j in list(rng.choice(3 * HW, 40, replace=False)) + [0, HW - 1, 2 * HW + 5]:
+        e = np.zeros_like(img); e[j] = h
+        fd = (L(img + e) - L(img - e)) / (2 * h)
+        assert fd == pytest.approx(g[j], rel=1e-6, abs=1e-9)
+
+
 def test_box_pyramid_of_constant_is_constant():
     v = view(32, 16, 10.0, levels=3)
     S = 2
