@@ -60,11 +60,11 @@ def make_targets(cfg_plain, fr, sc, device):
     return dict(rgb=rgb, depth=depth, label=labels)
 
 
-def plain_step(sc, views, device, targets=None, variant=0, tile_order=0):
+def plain_step(sc, views, device, targets=None, variant=0, tile_order=0, ssim_lambda=0.0):
     from paper_2412_01217_amd import raster
     from paper_2412_01217_amd.step import MappingStep
     C = sc.n_classes
-    cfg = raster.config(C, variant=variant, tile_order=tile_order)
+    cfg = raster.config(C, variant=variant, tile_order=tile_order, ssim_lambda=float(ssim_lambda))
     fr = raster.Frame(cfg, views, device=device)
     g = raster.to_device(sc, device)
     g.pop("emb", None)
@@ -302,6 +302,22 @@ def cpu_baseline(sc, views, targets, C, budget_s=15.0):
                        f"binning of all {sc.n} Gaussians at all {n_items} levels included; {dt:.1f} s")
 
 
+def ssim_report(args, dev, sc, views, targets, ms_ref, loss_ms_ref, lam=0.2):
+    """The same room step with the colour loss of eq. 10 at the paper's lambda = 0.2
+    (L1 and SSIM) in place of the plain L1 term."""
+    import torch
+    lam = lam if args.ssim_lambda == 0.0 else 0.0
+    step, _ = plain_step(sc, views, dev, targets=targets, variant=args.variant, ssim_lambda=lam)
+    m = measure(step, args.steps, args.warmup, graph=not args.eager)
+    px = step.frame.n_pixels
+    del step
+    torch.cuda.empty_cache()
+    return {"ssim_lambda": lam, "value": px / 1e6 / (m["ms"] * 1e-3), "unit": "MP/s", "ms_per_step": m["ms"],
+            "loss_stage_ms": m["stage_ms"]["loss"], "compared_to": {"ssim_lambda": args.ssim_lambda,
+                                                                      "ms_per_step": ms_ref,
+                                                                      "loss_stage_ms": loss_ms_ref}}
+
+
 # ----------------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
@@ -313,6 +329,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=0, help="render kernels: 0 auto (3), 1 VALU, 2 FP32 matrix cores, 3 split-bf16 matrix cores")
     ap.add_argument("--eager", action="store_true", help="time eager calls instead of graph replays")
+    ap.add_argument("--ssim-lambda", type=float, default=0.0,
+                    help="SSIM weight of the colour loss in the timed step (0: the L1 loss of the workloads)")
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times): the reference for HBM byte counters")
@@ -340,7 +358,7 @@ def main():
         print(json.dumps({"metric": METRIC, **sub(args, dev)}), flush=True)
         return
     sc, views = scenes.config_room()
-    step, targets = plain_step(sc, views, dev, variant=args.variant)
+    step, targets = plain_step(sc, views, dev, variant=args.variant, ssim_lambda=args.ssim_lambda)
     m = measure(step, args.steps, args.warmup, graph=not args.eager)
     c = work_counts(step)
     ms = m["ms"]
@@ -354,7 +372,7 @@ def main():
         "config": {"workload": "room 6x5x3 m, 200k Gaussians, 52 plain classes, 1 view 1200x680, 3-level pyramid",
                    "gaussians": sc.n, "classes": sc.n_classes, "pixels_per_step": c["pixels"], "items": c["items"],
                    "duplicates": c["dup"], "visible_item_gaussians": c["visible"], "pairs_iterated": c["pairs"],
-                   "semantic_mode": "plain", "render_variant": args.variant},
+                   "semantic_mode": "plain", "render_variant": args.variant, "ssim_lambda": args.ssim_lambda},
         "timed": "eager calls" if args.eager else "HIP graph replay of the whole step",
         "eager_ms_per_step": m["eager_ms"], "stage_ms": m["stage_ms"],
         "hbm_gbs_effective": algorithmic_bytes(c, sc.n_classes) / (ms * 1e-3) / 1e9,
@@ -363,6 +381,8 @@ def main():
     del step
     torch.cuda.empty_cache()
     if not args.quick:
+        out["with_ssim"] = ssim_report(args, dev, sc, views, targets, ms, m["stage_ms"]["loss"])
+        torch.cuda.empty_cache()
         out["batch"] = batch_report(args, dev)
         torch.cuda.empty_cache()
         out["learned_vs_plain"] = learned_report(args, dev)

@@ -63,6 +63,8 @@ typedef struct gs_config {
   int32_t fwd_chunk;       /* 1: forward with a state (gs_images.state), variant 3: 256-entry segments
                               walked per work item, 1..65535 (a transmittance pre-pass gives every
                               chunk but a list's first its starting T), or 0 = whole lists */
+  float ssim_lambda;       /* 0: weight lambda of the SSIM term of the colour loss (eq. 10, read as
+                              (1 - lambda) L1 + lambda (1 - SSIM)), 0..1; the paper trains with 0.2 */
 } gs_config;
 
 /* One camera view: world -> camera transform x_c = R x_w + t (OpenCV axes,
@@ -221,11 +223,15 @@ int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
                   int32_t n_items, int32_t n_tiles, const uint32_t* vals, const uint32_t* ranges,
                   const gs_head* head, gs_images* out, void* stream);
 
-/* Per-level loss (eq. 10-13, L1 parts; semantics as cross-entropy on the class
- * logits): for each item, loss_dev[3i..3i+2] = mean |R - R_gt| over 3HW,
- * mean |D - D_gt| over pixels with D_gt > 0, mean -log softmax(S)[label].
- * grad_out->color (and ->logits in learned mode) receives the gradient of
- * sum_i (w[0] L_rgb + w[1] L_depth + w[2] L_sem). w is a host array. */
+/* Per-level loss (eq. 10-13; semantics as cross-entropy on the class logits): for each
+ * item, loss_dev[3i..3i+2] = L_rgb, mean |D - D_gt| over pixels with D_gt > 0, and
+ * mean -log softmax(S)[label], where L_rgb = (1 - l) mean |R - R_gt| over 3HW + l (1 - SSIM),
+ * l = cfg->ssim_lambda, and SSIM is the mean over the 3 colour channels and all pixels of
+ * the structural similarity of Wang et al. (2004) with an 11 x 11 Gaussian window of
+ * standard deviation 1.5 (weights summing to 1; both images taken as zero outside),
+ * C1 = 0.01^2, C2 = 0.03^2. grad_out->color (and ->logits in learned mode) receives the
+ * gradient of sum_i (w[0] L_rgb + w[1] L_depth + w[2] L_sem). w is a host array of 3.
+ * workspace: gs_workspace_size(GS_WS_LOSS); its contents are scratch between calls. */
 int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_items, int64_t n_pixels,
                     int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const float* w,
                     float* loss_dev, gs_images* grad_out, void* workspace, size_t ws_bytes, void* stream);

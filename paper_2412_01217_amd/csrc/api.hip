@@ -65,7 +65,7 @@ int launch_render_bwd(const gs_config& cfg, const gs_gaussians& g, const gs_proj
   return launch_render_bwd_split(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, seg_ws, cap, s);
 }
 int launch_loss(const gs_item*, int, int64_t, int, int, const float*, const float*, const gs_targets&, const float*,
-                float*, float*, float*, float*, hipStream_t);
+                float, float*, float*, float*, float*, hipStream_t);
 int launch_downsample(const gs_item*, int, int64_t, int, int, float*, int32_t*, hipStream_t);
 size_t loss_workspace(int n_items);
 size_t head_bwd_workspace();
@@ -91,6 +91,7 @@ bool cfg_ok(const gs_config* c) {
   if (c->variant < 0 || c->variant > 3) return false;
   if (c->tile_order < 0 || c->tile_order > 1) return false;
   if (c->fwd_chunk < 0 || c->fwd_chunk > 65535) return false;
+  if (!(c->ssim_lambda >= 0.0f && c->ssim_lambda <= 1.0f)) return false;
   return true;
 }
 
@@ -126,6 +127,7 @@ void gs_config_default(gs_config* c) {
   c->variant = 0;
   c->tile_order = 0;
   c->fwd_chunk = 1;
+  c->ssim_lambda = 0.0f;
 }
 
 const char* gs_status_string(int s) {
@@ -262,7 +264,8 @@ int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_it
   }
   if (!workspace || ws_bytes < loss_workspace(n_items)) return GS_ERR_WORKSPACE;
   return launch_loss(items_dev, n_items, n_pixels, 4 + cfg->n_sem, n_classes, rendered->color, rendered->logits,
-                     *targets, w, loss_dev, grad_out->color, grad_out->logits, (float*)workspace, (hipStream_t)stream);
+                     *targets, w, cfg->ssim_lambda, loss_dev, grad_out->color, grad_out->logits, (float*)workspace,
+                     (hipStream_t)stream);
 }
 
 int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_view* views_dev,

@@ -228,6 +228,43 @@ def test_loss_parity_on_shared_images():
     rel_check(grad["color"].cpu().numpy(), g_ref, 1e-5, mask=near_kink, name="dloss/dimg")
 
 
+SSIM_VIEWS = {
+    # 200 x 136 with 3 levels: several 32 x 32 SSIM tiles per level with ragged tails, and a
+    # 50 x 34 level barely wider than one tile
+    "room": lambda: small_room(n_classes=9)[1],
+    # images smaller than the 11 x 11 window next to a larger one
+    "tiny_items": lambda: [scenes.identity_view(8, 6, levels=1), scenes.identity_view(72, 40, levels=2),
+                           scenes.identity_view(4, 4, levels=2)],
+}
+
+
+@pytest.mark.parametrize("lam", [0.2, 1.0])
+@pytest.mark.parametrize("case", list(SSIM_VIEWS))
+def test_loss_parity_with_ssim(case, lam):
+    raster = _raster()
+    views = SSIM_VIEWS[case]()
+    cfg = raster.config(9)
+    cfg.ssim_lambda = lam
+    fr = raster.Frame(cfg, views)
+    K = 13
+    img = scenes.random_image(fr.n_pixels, K, seed=5102)
+    t_rgb, t_depth, t_lab = targets_from_random(views, 9, seed=4002)
+    w = (0.8, 1.1, 0.6)
+    ls_ref, g_ref = oracle.loss(views, 9, img, t_rgb, t_depth, t_lab, w=w, ssim_lambda=lam)
+    T = dict(rgb=torch.from_numpy(t_rgb).cuda(), depth=torch.from_numpy(t_depth).cuda(),
+             label=torch.from_numpy(t_lab).cuda())
+    rendered = dict(color=torch.from_numpy(img).cuda())
+    ls, grad = raster.loss(cfg, fr, 9, rendered, T, w=w)
+    torch.cuda.synchronize()
+    rel_check(ls.cpu().numpy(), ls_ref, FWD_TOL, name="loss")
+    rel_check(grad["color"].cpu().numpy(), g_ref, BWD_TOL, name="dloss/dimg")
+    # the same call again: the workspace's slots are cleared by every call (the slot sums
+    # are float atomics, so only their order, not their content, may differ)
+    ls2, _ = raster.loss(cfg, fr, 9, rendered, T, w=w)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(ls2.cpu().numpy(), ls.cpu().numpy(), rtol=1e-6)
+
+
 def _shared_grad_image(fr, K, seed):
     return scenes.random_image(fr.n_pixels, K, seed=seed, scale=1e-3)
 
@@ -272,9 +309,11 @@ def _check_render_bwd(case, variant, split, fwd_chunk=1, small_workspace=False, 
     rel_check(grads["pose"].cpu().numpy(), ref["pose"], BWD_TOL, name="pose")
 
 
-def test_end_to_end_tiny_loss_and_gradients():
+@pytest.mark.parametrize("lam", [0.0, 0.2])
+def test_end_to_end_tiny_loss_and_gradients(lam):
     sc, views = scenes.config_tiny()
     cfg, fr, g, proj, srt, img = _pipeline(sc, views, 8)
+    cfg.ssim_lambda = lam
     raster = _raster()
     t_rgb, t_depth, t_lab = targets_from_random(views, 8, seed=4000, invalid_frac=0.0)
     T = dict(rgb=torch.from_numpy(t_rgb).cuda(), depth=torch.from_numpy(t_depth).cuda(),
@@ -283,7 +322,7 @@ def test_end_to_end_tiny_loss_and_gradients():
     grads = raster.render_bwd(cfg, g, proj, fr, srt, img, grad)
     torch.cuda.synchronize()
     r = oracle.render(oracle.Config(), sc, views)
-    ls_ref, gimg = oracle.loss(views, 8, r["img"], t_rgb, t_depth, t_lab)
+    ls_ref, gimg = oracle.loss(views, 8, r["img"], t_rgb, t_depth, t_lab, ssim_lambda=lam)
     rel_check(ls.cpu().numpy(), ls_ref, 1e-4, name="loss")
     ref = oracle.backward(oracle.Config(), sc, views, gimg)
     # features enter linearly: sum_p w |g_p| bounds their gradients' terms

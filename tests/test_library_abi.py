@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(L.Config) == 52
+    assert ctypes.sizeof(L.Config) == 56
     assert ctypes.sizeof(L.Images) == 56
     assert ctypes.sizeof(L.View) == 56
     assert ctypes.sizeof(L.Item) == 56
@@ -41,7 +41,7 @@ def test_defaults_and_status_strings():
     assert (c.tile_w, c.tile_h) == (16, 16)
     assert c.alpha_min == pytest.approx(1 / 255) and c.alpha_max == pytest.approx(0.99)
     assert c.t_min == pytest.approx(1e-4) and c.z_near == pytest.approx(0.2)
-    assert (c.variant, c.tile_order, c.fwd_chunk) == (0, 0, 1)
+    assert (c.variant, c.tile_order, c.fwd_chunk, c.ssim_lambda) == (0, 0, 1, 0.0)
     assert lib.gs_status_string(L.GS_ERR_CAPACITY) == b"duplicate capacity exceeded"
     assert lib.gs_version() > 0
 
@@ -139,4 +139,18 @@ def test_config_rejects_out_of_range_forward_chunk():
             L.GS_ERR_INVALID_ARG
     for good in (0, 1, 65535):
         c.fwd_chunk = good
+        assert lib.gs_workspace_size(L.GS_WS_LOSS, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == 0
+
+
+def test_config_rejects_ssim_weight_outside_unit_interval():
+    lib = L.lib()
+    c = L.Config()
+    lib.gs_config_default(ctypes.byref(c))
+    b = ctypes.c_size_t()
+    for bad in (-0.1, 1.5, float("nan")):
+        c.ssim_lambda = bad
+        assert lib.gs_workspace_size(L.GS_WS_LOSS, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == \
+            L.GS_ERR_INVALID_ARG
+    for good in (0.0, 0.2, 1.0):
+        c.ssim_lambda = good
         assert lib.gs_workspace_size(L.GS_WS_LOSS, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == 0
