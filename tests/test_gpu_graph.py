@@ -14,12 +14,12 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def _step(variant=0, fwd_chunk=1):
+def _step(variant=0, fwd_chunk=1, ssim_lambda=0.0):
     from paper_2412_01217_amd import raster
     from paper_2412_01217_amd.step import MappingStep
     sc = scenes.room_scene(n=8000, n_classes=10, seed=1200, log_mu=-3.6)
     views = scenes.room_views(sc, 2, 160, 96, levels=2, seed=2200)
-    cfg = raster.config(10, variant=variant, fwd_chunk=fwd_chunk)
+    cfg = raster.config(10, variant=variant, fwd_chunk=fwd_chunk, ssim_lambda=ssim_lambda)
     fr = raster.Frame(cfg, views)
     g = raster.to_device(sc)
     t_rgb, t_depth, t_lab = targets_from_random(views, 10, seed=4002)
@@ -38,9 +38,10 @@ def _snapshot(st):
     return out
 
 
-@pytest.mark.parametrize("variant,fwd_chunk", [(1, 1), (2, 1), (3, 1), (3, 0)])
-def test_graph_replays_match_eager(variant, fwd_chunk):
-    st = _step(variant, fwd_chunk)
+@pytest.mark.parametrize("variant,fwd_chunk,ssim_lambda", [(1, 1, 0.0), (2, 1, 0.0), (3, 1, 0.0), (3, 0, 0.0),
+                                                            (3, 1, 0.2)])
+def test_graph_replays_match_eager(variant, fwd_chunk, ssim_lambda):
+    st = _step(variant, fwd_chunk, ssim_lambda)
     st.run()
     torch.cuda.synchronize()
     assert not st.overflowed()
