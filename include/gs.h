@@ -255,6 +255,45 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
 int gs_pyramid_downsample(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t max_level,
                           int32_t K, float* img, int32_t* labels, void* stream);
 
+/* ---- mapping update (Sec. III-D) -------------------------------------------- */
+
+/* Writable float32 arrays in the layouts of the gs_gaussians fields of the same name. */
+typedef struct gs_param_arrays {
+  float* mean;       /* [n][3] */
+  float* log_scale;  /* [n][3] */
+  float* quat;       /* [n][4] */
+  float* opacity;    /* [n] logit */
+  float* rgb;        /* [n][3] */
+  float* sem;        /* [n][n_sem] (plain mode; NULL when n_sem = 0) */
+} gs_param_arrays;
+
+/* Adam hyper-parameters of a mapping step: one learning rate per parameter group and
+ * for the translation (rho) and rotation (phi) parts of the pose tangent. A group whose
+ * rate is 0 is left untouched (parameters and moments). */
+typedef struct gs_adam_config {
+  float lr_mean, lr_log_scale, lr_quat, lr_opacity, lr_rgb, lr_sem;
+  float lr_rho, lr_phi;
+  float beta1, beta2, eps;   /* 0 <= beta < 1, eps > 0 */
+} gs_adam_config;
+
+/* One Adam step (Kingma and Ba 2015, Algorithm 1, bias-corrected; step >= 1) on every
+ * parameter group of n Gaussians at once: p <- p - lr m_hat / (sqrt(v_hat) + eps) with the
+ * gradients of gs_render_bwd (grads->mean .. grads->sem; the other fields are not read).
+ * m and v (device, same layouts, zero before the first step) hold the moments. In place on
+ * `params`; one launch on `stream`. */
+int gs_gaussians_adam(int64_t n, int32_t n_sem, const gs_param_arrays* params, const gs_grads* grads,
+                      const gs_param_arrays* m, const gs_param_arrays* v, const gs_adam_config* hp, int32_t step,
+                      void* stream);
+
+/* Pose update of n_views views (device gs_view array, R and t rewritten in place): Adam on
+ * each view's tangent gradient grad_pose [n_views][6] = (rho, phi) (as gs_grads.pose), with
+ * moments m, v [n_views][6] (device, zero before the first step), gives the step delta;
+ * then T_cw <- Exp(delta) T_cw, the left-multiplied SE(3) exponential, composed in double
+ * precision and its rotation re-orthonormalised before it is stored. item_first and
+ * item_count are not touched. */
+int gs_pose_adam(gs_view* views_dev, int32_t n_views, const float* grad_pose, float* m, float* v,
+                 const gs_adam_config* hp, int32_t step, void* stream);
+
 /* ---- training helpers for the learned head ------------------------------- */
 
 /* One Adam step on n float32 parameters in place (m, v: moment buffers, step >= 1,

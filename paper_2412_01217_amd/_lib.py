@@ -29,7 +29,8 @@ EXPORTS = (
     "gs_config_default", "gs_status_string", "gs_last_hip_error", "gs_version", "gs_make_items",
     "gs_workspace_size", "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_pyramid_loss",
     "gs_render_bwd", "gs_pyramid_downsample", "gs_graph_begin", "gs_graph_end", "gs_graph_launch",
-    "gs_graph_destroy", "gs_adam_step", "gs_distill_loss", "gs_argmax_agreement",
+    "gs_graph_destroy", "gs_adam_step", "gs_distill_loss", "gs_argmax_agreement", "gs_gaussians_adam",
+    "gs_pose_adam",
 )
 
 
@@ -66,6 +67,16 @@ class Images(ctypes.Structure):
 
 class Targets(ctypes.Structure):
     _fields_ = [("rgb", c_void_p), ("depth", c_void_p), ("label", c_void_p)]
+
+
+class ParamArrays(ctypes.Structure):
+    _fields_ = [("mean", c_void_p), ("log_scale", c_void_p), ("quat", c_void_p), ("opacity", c_void_p),
+                ("rgb", c_void_p), ("sem", c_void_p)]
+
+
+class AdamConfig(ctypes.Structure):
+    _fields_ = [(k, c_float) for k in ("lr_mean", "lr_log_scale", "lr_quat", "lr_opacity", "lr_rgb", "lr_sem",
+                                       "lr_rho", "lr_phi", "beta1", "beta2", "eps")]
 
 
 class Head(ctypes.Structure):
@@ -116,7 +127,10 @@ def lib():
         L.gs_distill_loss.argtypes = [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_void_p, c_float, c_void_p,
                                       c_void_p, c_void_p, c_size_t, c_void_p]
         L.gs_argmax_agreement.argtypes = [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
-        for name in ("gs_adam_step", "gs_distill_loss", "gs_argmax_agreement"):
+        L.gs_gaussians_adam.argtypes = [c_int64, c_int32, P(ParamArrays), P(Grads), P(ParamArrays), P(ParamArrays),
+                                        P(AdamConfig), c_int32, c_void_p]
+        L.gs_pose_adam.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, P(AdamConfig), c_int32, c_void_p]
+        for name in ("gs_adam_step", "gs_distill_loss", "gs_argmax_agreement", "gs_gaussians_adam", "gs_pose_adam"):
             getattr(L, name).restype = c_int32
         L.gs_graph_begin.argtypes = [c_void_p]
         L.gs_graph_end.argtypes = [c_void_p, P(c_void_p)]

@@ -74,6 +74,9 @@ int launch_head_fwd(const gs_item*, int, int64_t, int, const gs_head&, const flo
 int launch_head_bwd(const gs_item*, int, int64_t, int, const gs_head&, const float*, const float*, float*, float*,
                     float*, float*, float*, float*, hipStream_t);
 int launch_adam(float*, const float*, float*, float*, int64_t, float, float, float, float, int, uint16_t*, hipStream_t);
+int launch_gaussians_adam(int64_t, int, const gs_param_arrays&, const gs_grads&, const gs_param_arrays&,
+                          const gs_param_arrays&, const gs_adam_config&, int, hipStream_t);
+int launch_pose_adam(gs_view*, int, const float*, float*, float*, const gs_adam_config&, int, hipStream_t);
 int launch_distill(const gs_item*, int, int64_t, int, const float*, const float*, float, float*, float*, float*,
                    hipStream_t);
 int launch_agree(const gs_item*, int, int64_t, int, const float*, const float*, unsigned long long*, hipStream_t);
@@ -324,6 +327,42 @@ int gs_adam_step(float* param, const float* grad, float* m, float* v, int64_t n,
     return GS_ERR_INVALID_ARG;
   if (n > 0 && (!param || !grad || !m || !v)) return GS_ERR_INVALID_ARG;
   return launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, bf16_copy, (hipStream_t)stream);
+}
+
+static bool adam_ok(const gs_adam_config* hp, int32_t step) {
+  if (!hp || step < 1) return false;
+  if (!(hp->beta1 >= 0.0f && hp->beta1 < 1.0f) || !(hp->beta2 >= 0.0f && hp->beta2 < 1.0f) || !(hp->eps > 0.0f))
+    return false;
+  const float lr[8] = {hp->lr_mean, hp->lr_log_scale, hp->lr_quat, hp->lr_opacity, hp->lr_rgb, hp->lr_sem,
+                       hp->lr_rho, hp->lr_phi};
+  for (float x : lr)
+    if (!(x >= 0.0f) || !std::isfinite(x)) return false;
+  return true;
+}
+
+int gs_gaussians_adam(int64_t n, int32_t n_sem, const gs_param_arrays* params, const gs_grads* grads,
+                      const gs_param_arrays* m, const gs_param_arrays* v, const gs_adam_config* hp, int32_t step,
+                      void* stream) {
+  if (n < 0 || n_sem < 0 || n_sem > 60 || !params || !grads || !m || !v || !adam_ok(hp, step)) return GS_ERR_INVALID_ARG;
+  if (n == 0) return GS_OK;
+  const float lr[6] = {hp->lr_mean, hp->lr_log_scale, hp->lr_quat, hp->lr_opacity, hp->lr_rgb, hp->lr_sem};
+  const float* P[6] = {params->mean, params->log_scale, params->quat, params->opacity, params->rgb, params->sem};
+  const float* G[6] = {grads->mean, grads->log_scale, grads->quat, grads->opacity, grads->rgb, grads->sem};
+  const float* M[6] = {m->mean, m->log_scale, m->quat, m->opacity, m->rgb, m->sem};
+  const float* V[6] = {v->mean, v->log_scale, v->quat, v->opacity, v->rgb, v->sem};
+  for (int k = 0; k < 6; ++k) {
+    if (lr[k] == 0.0f || (k == 5 && n_sem == 0)) continue;
+    if (!P[k] || !G[k] || !M[k] || !V[k]) return GS_ERR_INVALID_ARG;
+  }
+  return launch_gaussians_adam(n, n_sem, *params, *grads, *m, *v, *hp, step, (hipStream_t)stream);
+}
+
+int gs_pose_adam(gs_view* views_dev, int32_t n_views, const float* grad_pose, float* m, float* v,
+                 const gs_adam_config* hp, int32_t step, void* stream) {
+  if (n_views < 0 || !adam_ok(hp, step)) return GS_ERR_INVALID_ARG;
+  if (n_views == 0) return GS_OK;
+  if (!views_dev || !grad_pose || !m || !v) return GS_ERR_INVALID_ARG;
+  return launch_pose_adam(views_dev, n_views, grad_pose, m, v, *hp, step, (hipStream_t)stream);
 }
 
 int gs_distill_loss(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t C, const float* teacher,

@@ -280,6 +280,35 @@ def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch
                                  step, _ptr(bf16_copy), _stream(param.device)), "gs_adam_step")
 
 
+PARAM_FIELDS = ("mean", "log_scale", "quat", "opacity", "rgb", "sem")
+
+
+def _param_arrays(d: dict) -> L.ParamArrays:
+    return L.ParamArrays(*(None if d.get(k) is None else d[k].data_ptr() for k in PARAM_FIELDS))
+
+
+def adam_config(lr: dict, beta1=0.9, beta2=0.999, eps=1e-8) -> L.AdamConfig:
+    """Learning rates by name (mean, log_scale, quat, opacity, rgb, sem, rho, phi); missing = 0."""
+    return L.AdamConfig(*[float(lr.get(k, 0.0)) for k in PARAM_FIELDS + ("rho", "phi")], beta1, beta2, eps)
+
+
+def gaussians_adam(g: dict, grads: dict, m: dict, v: dict, hp: L.AdamConfig, step: int):
+    """One Adam step on every Gaussian parameter group of g (in place), one launch."""
+    n = int(g["mean"].shape[0])
+    n_sem = int(g["sem"].shape[1]) if g.get("sem") is not None else 0
+    gr = L.Grads(*(None if grads.get(k) is None else grads[k].data_ptr() for k in GRAD_FIELDS))
+    L.check(L.lib().gs_gaussians_adam(n, n_sem, ctypes.byref(_param_arrays(g)), ctypes.byref(gr),
+                                      ctypes.byref(_param_arrays(m)), ctypes.byref(_param_arrays(v)),
+                                      ctypes.byref(hp), int(step), _stream(g["mean"].device)), "gs_gaussians_adam")
+
+
+def pose_adam(views_dev: torch.Tensor, n_views: int, grad_pose: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+              hp: L.AdamConfig, step: int):
+    """Adam on the pose tangents, then T_cw <- Exp(delta) T_cw of every view in views_dev."""
+    L.check(L.lib().gs_pose_adam(_ptr(views_dev), int(n_views), _ptr(grad_pose), _ptr(m), _ptr(v), ctypes.byref(hp),
+                                 int(step), _stream(views_dev.device)), "gs_pose_adam")
+
+
 def distill_loss(frame: Frame, C: int, teacher: torch.Tensor, student: torch.Tensor, mse_w=0.1, grad=None,
                  loss_out=None, ws=None):
     dev = frame.device

@@ -154,3 +154,30 @@ def test_config_rejects_ssim_weight_outside_unit_interval():
     for good in (0.0, 0.2, 1.0):
         c.ssim_lambda = good
         assert lib.gs_workspace_size(L.GS_WS_LOSS, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == 0
+
+
+def test_mapping_update_structs_and_argument_checks():
+    lib = L.lib()
+    assert ctypes.sizeof(L.ParamArrays) == 48 and ctypes.sizeof(L.AdamConfig) == 44
+    fake = ctypes.c_void_p(256)
+    p = L.ParamArrays(fake, fake, fake, fake, fake, None)
+    g = L.Grads(*([fake] * 12))
+
+    def hp(**kw):
+        h = L.AdamConfig(1e-3, 1e-3, 1e-3, 1e-2, 1e-2, 0.0, 1e-3, 1e-3, 0.9, 0.999, 1e-8)
+        for k, val in kw.items():
+            setattr(h, k, val)
+        return h
+    call = lambda n, n_sem, h, step, sem=None: lib.gs_gaussians_adam(  # noqa: E731
+        n, n_sem, ctypes.byref(p if sem is None else sem), ctypes.byref(g), ctypes.byref(p), ctypes.byref(p),
+        ctypes.byref(h), step, None)
+    assert call(0, 0, hp(), 1) == L.GS_OK                              # nothing to update: no launch
+    for bad in (dict(beta1=1.0), dict(beta2=-0.1), dict(eps=0.0), dict(lr_mean=-1.0), dict(lr_phi=float("inf"))):
+        assert call(0, 0, hp(**bad), 1) == L.GS_ERR_INVALID_ARG, bad
+    assert call(0, 0, hp(), 0) == L.GS_ERR_INVALID_ARG                 # steps count from 1
+    assert call(-1, 0, hp(), 1) == L.GS_ERR_INVALID_ARG
+    # a semantic group with a nonzero rate needs its arrays
+    assert call(5, 3, hp(lr_sem=1e-2), 1) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_pose_adam(None, 0, None, None, None, ctypes.byref(hp()), 1, None) == L.GS_OK
+    assert lib.gs_pose_adam(None, 2, fake, fake, fake, ctypes.byref(hp()), 1, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_pose_adam(fake, 2, fake, fake, fake, ctypes.byref(hp()), 0, None) == L.GS_ERR_INVALID_ARG
