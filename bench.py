@@ -302,6 +302,39 @@ def cpu_baseline(sc, views, targets, C, budget_s=15.0):
                        f"binning of all {sc.n} Gaussians at all {n_items} levels included; {dt:.1f} s")
 
 
+def adam_report(step, steps):
+    """The mapping update after the step's backward: one Adam launch over every Gaussian
+    parameter group (HBM-bound: 4 float reads and 3 writes per element), timed on the
+    step's own gradients."""
+    import torch
+    from paper_2412_01217_amd import raster
+    g = step.g
+    m = {k: torch.zeros_like(t) for k, t in g.items() if k in raster.PARAM_FIELDS and t is not None}
+    v = {k: torch.zeros_like(t) for k, t in g.items() if k in raster.PARAM_FIELDS and t is not None}
+    saved = {k: t.clone() for k, t in m.items()}
+    saved_g = {k: g[k].clone() for k in m}
+    hp = raster.adam_config(dict(mean=1e-6, log_scale=1e-6, quat=1e-6, opacity=1e-6, rgb=1e-6, sem=1e-6))
+    for i in range(3):
+        raster.gaussians_adam(g, step.grads, m, v, hp, i + 1)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for i in range(steps):
+        raster.gaussians_adam(g, step.grads, m, v, hp, i + 4)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    for k in m:                                    # leave the scene as it was
+        g[k].copy_(saved_g[k])
+    del saved
+    elems = sum(t.numel() for t in m.values())
+    gbs = 28.0 * elems / (ms * 1e-3) / 1e9
+    return {"kernel": "k_adam_groups", "elements": elems, "avg_launch_ms": ms, "algorithmic_bytes": 28 * elems,
+            "achieved_gbs": gbs, "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                              "frac": gbs / HBM_PEAK_GBS}}
+
+
 def ssim_report(args, dev, sc, views, targets, ms_ref, loss_ms_ref, lam=0.2):
     """The same room step with the colour loss of eq. 10 at the paper's lambda = 0.2
     (L1 and SSIM) in place of the plain L1 term."""
@@ -378,6 +411,7 @@ def main():
         "hbm_gbs_effective": algorithmic_bytes(c, sc.n_classes) / (ms * 1e-3) / 1e9,
         "roofline": roof, "roofline_other": other,
     }
+    out["mapping_update"] = adam_report(step, args.steps)
     del step
     torch.cuda.empty_cache()
     if not args.quick:
