@@ -57,6 +57,7 @@ class Config:
     full_rect: bool = False
     margin: float = 2e-5        # per-pixel decisions (alpha_min, alpha_max, t_min, depth ties)
     margin_pre: float = 1e-9    # projection decisions (z_near, guard, radius and rect rounding)
+    isotropic: bool = False     # the primitive of eq. 1-3: one scale (log_scale[:, 0]), no rotation
 
     def exact(self) -> "Config":
         """Cut-offs removed: every Gaussian covers every tile, no alpha_min / t_min."""
@@ -65,7 +66,7 @@ class Config:
     def arrays(self, S: int):
         cd = np.array([self.z_near, self.eps, self.alpha_min, self.alpha_max, self.t_min,
                        self.guard, self.margin, self.margin_pre], np.float64)
-        ci = np.array([self.tile_w, self.tile_h, int(self.full_rect), S], np.int32)
+        ci = np.array([self.tile_w, self.tile_h, int(self.full_rect), S, int(self.isotropic)], np.int32)
         return cd, ci
 
 

@@ -38,6 +38,7 @@ namespace {
 
 struct Cfg {
   int tw, th, full_rect, S;
+  int isotropic;      // 1: the primitive of eq. 1-3 (one scale, no rotation, r2D = f r / d)
   double z_near, eps, a_min, a_max, t_min, guard;
   double margin;      // relative closeness that flags a per-pixel decision
   double margin_pre;  // the same for the projection's decisions
@@ -57,6 +58,7 @@ Cfg read_cfg(const double* cd, const int* ci) {
   c.th = ci[1];
   c.full_rect = ci[2];
   c.S = ci[3];
+  c.isotropic = ci[4];
   return c;
 }
 
@@ -167,6 +169,15 @@ Proj project(const Cfg& c, const Gauss& g, int64_t i, const double* Rv, const do
   p.z = p.mc[2];
   if (near_rel(p.z, c.z_near, c.margin_pre)) p.flag |= 1;
   if (!(p.z > c.z_near)) return p;
+  if (c.isotropic) {
+    // eq. 1-3: g3D = o exp(-|x - mu|^2 / (2 r^2)) with r = exp(first log-scale) projects to a
+    // 2D Gaussian of standard deviation r2D = f r / d about mu2D, f taken per image axis
+    p.s[0] = std::exp(g.lsc[3 * i]);
+    const double rx = it.fx * p.s[0] / p.z, ry = it.fy * p.s[0] / p.z;
+    p.cov[0] = rx * rx + c.eps;
+    p.cov[1] = 0.0;
+    p.cov[2] = ry * ry + c.eps;
+  } else {
   const double* q = g.quat + 4 * i;
   p.qlen = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
   if (!(p.qlen > 0) || !std::isfinite(p.qlen)) return p;
@@ -207,6 +218,7 @@ Proj project(const Cfg& c, const Gauss& g, int64_t i, const double* Rv, const do
   p.cov[0] = C2[0] + c.eps;
   p.cov[1] = C2[1];
   p.cov[2] = C2[3] + c.eps;
+  }
   double det = p.cov[0] * p.cov[2] - p.cov[1] * p.cov[1];
   if (!(det > 0)) return p;
   p.conic[0] = p.cov[2] / det;
@@ -414,6 +426,23 @@ void project_backward(const Scene& s, int k, int64_t i, const G2& g2, double* gm
     for (int c = 0; c < 2; ++c) QG[2 * r + c] = Q[2 * r] * G[c] + Q[2 * r + 1] * G[2 + c];
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) GC[2 * r + c] = -(QG[2 * r] * Q[c] + QG[2 * r + 1] * Q[2 + c]);
+  if (s.c.isotropic) {
+    // cov = diag((fx r/z)^2, (fy r/z)^2) + eps I, r = exp(l): d/dz = -2/z, d/dl = 2 per diagonal entry
+    const double vx = std::pow(it.fx * p.s[0] / z, 2), vy = std::pow(it.fy * p.s[0] / z, 2);
+    double dmc[3] = {0, 0, -2.0 * (GC[0] * vx + GC[3] * vy) / z};
+    glsc[3 * i] += 2.0 * (GC[0] * vx + GC[3] * vy);
+    dmc[0] += g2.m2[0] * it.fx / z;
+    dmc[1] += g2.m2[1] * it.fy / z;
+    dmc[2] += -g2.m2[0] * it.fx * x / (z * z) - g2.m2[1] * it.fy * y / (z * z);
+    dmc[2] += g2.zf;
+    for (int a = 0; a < 3; ++a) gmean[3 * i + a] += Rv[a] * dmc[0] + Rv[3 + a] * dmc[1] + Rv[6 + a] * dmc[2];
+    double* gp = gpose + 6 * it.view;
+    for (int a = 0; a < 3; ++a) gp[a] += dmc[a];
+    gp[3] += p.mc[1] * dmc[2] - p.mc[2] * dmc[1];
+    gp[4] += p.mc[2] * dmc[0] - p.mc[0] * dmc[2];
+    gp[5] += p.mc[0] * dmc[1] - p.mc[1] * dmc[0];
+    return;
+  }
   // cov = J Sc J^T + eps I:  dSc = J^T GC J,  dJ = 2 GC J Sc
   double dSc[9];
   for (int a = 0; a < 3; ++a)

@@ -67,6 +67,46 @@ def test_single_gaussian_on_axis_closed_form():
     np.testing.assert_allclose(out["T"].reshape(H, W), 1 - g2d, rtol=1e-12)
 
 
+# Literal primitive of eq. 1-3: one scale, no rotation, r2D = f r / d.
+def test_isotropic_primitive_off_axis_follows_eq_2_and_3():
+    # off the optical axis the EWA footprint is an ellipse; eq. 2-3 keep a circle of
+    # radius f r / d about the projected mean, whatever the quaternion and other scales
+    x, y, z, r, a = 0.6, -0.35, 2.5, 0.04, -0.4
+    W, H, f = 64, 48, 50.0
+    sc = make_scene([[x, y, z]], [[math.log(r), 0.7, -2.0]], [[0.3, 0.5, -0.2, 0.7]], [a],
+                    [[0.2, 0.7, 0.9]], [[1.5, -0.5, 0.25]])
+    v = view(W, H, f)
+    cfg = oracle.Config(eps=0.0, isotropic=True).exact()
+    out = oracle.render(cfg, sc, [v])
+    I = planes(out["img"], 7, W, H)
+    u, vv = pixel_grid(W, H)
+    mu2 = (f * x / z + W / 2, f * y / z + H / 2)            # eq. 2
+    r2d = f * r / z
+    o = 1 / (1 + math.exp(-a))
+    g2d = o * np.exp(-((u - mu2[0]) ** 2 + (vv - mu2[1]) ** 2) / (2 * r2d ** 2))   # eq. 3
+    for c, val in enumerate([0.2, 0.7, 0.9]):
+        np.testing.assert_allclose(I[c], val * g2d, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(I[3], z * g2d, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(out["T"].reshape(H, W), 1 - g2d, rtol=1e-12)
+    # the EWA footprint of the same Gaussian differs (it is an ellipse here)
+    ewa = oracle.render(oracle.Config(eps=0.0).exact(), sc, [v])
+    assert np.abs(ewa["img"] - out["img"]).max() > 1e-3
+
+
+def test_isotropic_primitive_ignores_rotation_and_other_scales():
+    sc, rng = _fd_scene(12)
+    v = view(40, 32, 30.0)
+    cfg = oracle.Config(isotropic=True)
+    base = oracle.render(cfg, sc, [v])["img"]
+    other = sc.copy()
+    other.quat = rng.normal(size=other.quat.shape)
+    other.log_scale[:, 1:] += rng.normal(size=(other.n, 2))
+    np.testing.assert_array_equal(oracle.render(cfg, other, [v])["img"], base)
+    g = oracle.backward(cfg, sc, [v], rng.normal(size=base.shape))
+    assert not g["quat"].any() and not g["log_scale"][:, 1:].any()
+    assert np.abs(g["log_scale"][:, 0]).max() > 0
+
+
 # ---------------------------------------------------------------- P-b
 def test_off_axis_isotropic_ewa_closed_form():
     rng = np.random.default_rng(5)
@@ -471,12 +511,13 @@ def _exp_se3(xi):
     return R, V @ rho
 
 
+@pytest.mark.parametrize("isotropic", [False, True])
 @pytest.mark.parametrize("clamp_one", [False, True])
-def test_backward_matches_central_differences(clamp_one):
+def test_backward_matches_central_differences(clamp_one, isotropic):
     sc, rng = _fd_scene(11, clamp_one=clamp_one)
     Rv = _rodrigues(np.array([0.05, -0.1, 0.08]))
     v = view(40, 32, 30.0, R=Rv, t=[0.05, -0.02, 0.1])
-    cfg = oracle.Config().exact()
+    cfg = oracle.Config(isotropic=isotropic).exact()
     K = 7
     out = oracle.render(cfg, sc, [v])
     gimg = rng.normal(size=out["img"].shape)
