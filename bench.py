@@ -60,11 +60,12 @@ def make_targets(cfg_plain, fr, sc, device):
     return dict(rgb=rgb, depth=depth, label=labels)
 
 
-def plain_step(sc, views, device, targets=None, variant=0, tile_order=0, ssim_lambda=0.0):
+def plain_step(sc, views, device, targets=None, variant=0, tile_order=0, ssim_lambda=0.0, isotropic=0):
     from paper_2412_01217_amd import raster
     from paper_2412_01217_amd.step import MappingStep
     C = sc.n_classes
-    cfg = raster.config(C, variant=variant, tile_order=tile_order, ssim_lambda=float(ssim_lambda))
+    cfg = raster.config(C, variant=variant, tile_order=tile_order, ssim_lambda=float(ssim_lambda),
+                        isotropic=int(isotropic))
     fr = raster.Frame(cfg, views, device=device)
     g = raster.to_device(sc, device)
     g.pop("emb", None)
@@ -335,6 +336,19 @@ def adam_report(step, steps):
                                               "frac": gbs / HBM_PEAK_GBS}}
 
 
+def isotropic_report(args, dev, sc, views, targets):
+    """The room step with the literal primitive of eq. 1-3 (one scale per Gaussian, the
+    first of the scene's three, no rotation) in place of the EWA footprint."""
+    import torch
+    step, _ = plain_step(sc, views, dev, targets=targets, variant=args.variant, isotropic=1)
+    m = measure(step, args.steps, args.warmup, graph=not args.eager)
+    c = work_counts(step)
+    del step
+    torch.cuda.empty_cache()
+    return {"primitive": "isotropic (eq. 1-3)", "value": c["pixels"] / 1e6 / (m["ms"] * 1e-3), "unit": "MP/s",
+            "ms_per_step": m["ms"], "stage_ms": m["stage_ms"], "duplicates": c["dup"], "pairs_iterated": c["pairs"]}
+
+
 def ssim_report(args, dev, sc, views, targets, ms_ref, loss_ms_ref, lam=0.2):
     """The same room step with the colour loss of eq. 10 at the paper's lambda = 0.2
     (L1 and SSIM) in place of the plain L1 term."""
@@ -416,6 +430,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.quick:
         out["with_ssim"] = ssim_report(args, dev, sc, views, targets, ms, m["stage_ms"]["loss"])
+        torch.cuda.empty_cache()
+        out["isotropic_primitive"] = isotropic_report(args, dev, sc, views, targets)
         torch.cuda.empty_cache()
         out["batch"] = batch_report(args, dev)
         torch.cuda.empty_cache()

@@ -65,6 +65,10 @@ typedef struct gs_config {
                               chunk but a list's first its starting T), or 0 = whole lists */
   float ssim_lambda;       /* 0: weight lambda of the SSIM term of the colour loss (eq. 10, read as
                               (1 - lambda) L1 + lambda (1 - SSIM)), 0..1; the paper trains with 0.2 */
+  int32_t isotropic;       /* 0: EWA footprint of scale x rotation; 1: the literal primitive of eq. 1-3,
+                              one scale r = exp(log_scale[0]) projected to standard deviation f r / d
+                              along each image axis (plus eps_dilate); quat and log_scale[1..2] are
+                              then unused and get zero gradient */
 } gs_config;
 
 /* One camera view: world -> camera transform x_c = R x_w + t (OpenCV axes,

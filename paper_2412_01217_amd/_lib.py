@@ -38,7 +38,7 @@ class Config(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("z_near", c_float), ("eps_dilate", c_float),
                 ("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("guard", c_float),
                 ("full_rect", c_int32), ("n_sem", c_int32), ("variant", c_int32), ("tile_order", c_int32),
-                ("fwd_chunk", c_int32), ("ssim_lambda", c_float)]
+                ("fwd_chunk", c_int32), ("ssim_lambda", c_float), ("isotropic", c_int32)]
 
 
 class View(ctypes.Structure):

@@ -95,6 +95,7 @@ bool cfg_ok(const gs_config* c) {
   if (c->tile_order < 0 || c->tile_order > 1) return false;
   if (c->fwd_chunk < 0 || c->fwd_chunk > 65535) return false;
   if (!(c->ssim_lambda >= 0.0f && c->ssim_lambda <= 1.0f)) return false;
+  if (c->isotropic < 0 || c->isotropic > 1) return false;
   return true;
 }
 
@@ -131,6 +132,7 @@ void gs_config_default(gs_config* c) {
   c->tile_order = 0;
   c->fwd_chunk = 1;
   c->ssim_lambda = 0.0f;
+  c->isotropic = 0;
 }
 
 const char* gs_status_string(int s) {

@@ -1,5 +1,6 @@
 // Projection of 3D Gaussians to 2D footprints (paper Sec. III-B, eq. 2-3, in the EWA
-// form) and its backward pass, including the pose tangent.
+// form, or literally with cfg.isotropic: one scale, no rotation, r2D = f r / d per image
+// axis) and its backward pass, including the pose tangent.
 //
 // One thread per Gaussian walks every view and, per view, every pyramid level. The
 // arithmetic is double precision (these kernels are bound by HBM traffic, and the
@@ -27,10 +28,21 @@ __device__ inline void quat_rot(const double* q, double* R) {
   R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-__device__ inline Geo load_geo(const gs_gaussians& g, int64_t i) {
+__device__ inline Geo load_geo(const gs_gaussians& g, int64_t i, bool iso) {
   Geo G;
   const float* m = g.mean + 3 * i;
   G.mu[0] = m[0]; G.mu[1] = m[1]; G.mu[2] = m[2];
+  if (iso) {   // eq. 1: one scale; the rotation and covariance are not used
+    G.s[0] = exp((double)g.log_scale[3 * i]);
+    G.s[1] = G.s[2] = G.s[0];
+    for (int k = 0; k < 4; ++k) G.qn[k] = 0.0;
+    G.qlen = 1.0;
+    for (int k = 0; k < 9; ++k) G.Rq[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    for (int k = 0; k < 6; ++k) G.Sig[k] = 0.0;
+    G.o = 1.0 / (1.0 + exp(-(double)g.opacity[i]));
+    G.ok = true;
+    return G;
+  }
   const float4 q = *reinterpret_cast<const float4*>(g.quat + 4 * i);
   double qv[4] = {q.x, q.y, q.z, q.w};
   G.qlen = sqrt(qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3]);
@@ -88,11 +100,22 @@ struct Lvl {           // one level's 2D footprint
   bool vis;
 };
 
-__device__ inline Lvl footprint(const gs_config& cfg, const gs_item& it, const Cam& c) {
+__device__ inline Lvl footprint(const gs_config& cfg, const gs_item& it, const Cam& c, double s0) {
   Lvl L;
   L.vis = false;
   const double z = c.mc[2], x = c.mc[0], y = c.mc[1];
   const double fx = it.fx, fy = it.fy;
+  if (cfg.isotropic) {
+    // eq. 2-3: standard deviation f r / d along each image axis
+    const double rx = fx * s0 / z, ry = fy * s0 / z;
+    L.clx = L.cly = false;
+    L.ux = x / z;
+    L.uy = y / z;
+    L.J[0] = L.J[1] = L.J[2] = L.J[3] = 0.0;
+    L.cov[0] = rx * rx + cfg.eps_dilate;
+    L.cov[1] = 0.0;
+    L.cov[2] = ry * ry + cfg.eps_dilate;
+  } else {
   const double limx = (double)cfg.guard * (0.5 * it.W) / fx;
   const double limy = (double)cfg.guard * (0.5 * it.H) / fy;
   const double tx = x / z, ty = y / z;
@@ -114,6 +137,7 @@ __device__ inline Lvl footprint(const gs_config& cfg, const gs_item& it, const C
   L.cov[0] = r0S0 * L.J[0] + r0S2 * L.J[1] + cfg.eps_dilate;
   L.cov[1] = r0S1 * L.J[2] + r0S2 * L.J[3];
   L.cov[2] = r1S1 * L.J[2] + r1S2 * L.J[3] + cfg.eps_dilate;
+  }
   const double det = L.cov[0] * L.cov[2] - L.cov[1] * L.cov[1];
   if (!(det > 0.0)) return L;
   const double id = 1.0 / det;
@@ -145,7 +169,7 @@ __global__ __launch_bounds__(256) void k_preprocess(gs_config cfg, gs_gaussians 
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n) return;
   const int64_t n = g.n;
-  const Geo G = load_geo(g, i);
+  const Geo G = load_geo(g, i, cfg.isotropic != 0);
   for (int v = 0; v < n_views; ++v) {
     const gs_view V = views[v];
     const Cam c = to_camera(V, G);
@@ -153,7 +177,7 @@ __global__ __launch_bounds__(256) void k_preprocess(gs_config cfg, gs_gaussians 
     for (int k = V.item_first; k < V.item_first + V.item_count; ++k) {
       const int64_t e = (int64_t)k * n + i;
       if (!front) { out.radius[e] = 0; continue; }
-      const Lvl L = footprint(cfg, items[k], c);
+      const Lvl L = footprint(cfg, items[k], c, G.s[0]);
       if (!L.vis) { out.radius[e] = 0; continue; }
       float4 a, b;
       a.x = (float)L.m2[0];
@@ -184,8 +208,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(gs_config cfg, gs_gaussi
   const bool live = i < g.n;
   const int64_t n = g.n;
   const int64_t ii = live ? i : 0;
-  const Geo G = load_geo(g, ii);
-  double gmu[3] = {0, 0, 0}, gsig[6] = {0, 0, 0, 0, 0, 0}, gop = 0;
+  const bool iso = cfg.isotropic != 0;
+  const Geo G = load_geo(g, ii, iso);
+  double gmu[3] = {0, 0, 0}, gsig[6] = {0, 0, 0, 0, 0, 0}, gop = 0, gls0 = 0;
   __shared__ double red[4][6];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int v = 0; v < n_views; ++v) {
@@ -203,7 +228,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(gs_config cfg, gs_gaussi
         const int64_t e = (int64_t)k * n + i;
         if (radius[e] <= 0) continue;
         const gs_item it = items[k];
-        const Lvl L = footprint(cfg, it, c);
+        const Lvl L = footprint(cfg, it, c, G.s[0]);
         const float4 ga = *reinterpret_cast<const float4*>(g2d + 8 * e);
         const float4 gb = *reinterpret_cast<const float4*>(g2d + 8 * e + 4);
         const double dmx = ga.x, dmy = ga.y, dA = ga.z, dB = ga.w, dC = gb.x, dO = gb.y, dZ = gb.z;
@@ -216,6 +241,20 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(gs_config cfg, gs_gaussi
         const double C00 = -(T00 * Q00 + T01 * Q01);
         const double C01 = -(T00 * Q01 + T01 * Q11);
         const double C11 = -(T10 * Q01 + T11 * Q11);
+        if (iso) {
+          // cov = diag((fx r/z)^2, (fy r/z)^2) + eps: each diagonal entry v has dv/dz = -2v/z and
+          // dv/d(log r) = 2v
+          const double z = c.mc[2], x = c.mc[0], y = c.mc[1];
+          const double rx = it.fx * G.s[0] / z, ry = it.fy * G.s[0] / z;
+          const double dv = C00 * rx * rx + C11 * ry * ry;
+          gls0 += 2.0 * dv;
+          gmc[2] += -2.0 * dv / z;
+          gmc[0] += dmx * it.fx / z;
+          gmc[1] += dmy * it.fy / z;
+          gmc[2] += -(dmx * it.fx * x + dmy * it.fy * y) / (z * z);
+          gmc[2] += dZ;
+          continue;
+        }
         // cov = J Sc J^T: dSc = J^T C J (symmetric), dJ = 2 C J Sc
         const double j00 = L.J[0], j02 = L.J[1], j11 = L.J[2], j12 = L.J[3];
         // J^T C J, J rows r0 = (j00, 0, j02), r1 = (0, j11, j12)
@@ -306,6 +345,15 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(gs_config cfg, gs_gaussi
     }
   }
   if (!live) return;
+  if (iso) {   // no covariance: only the first log-scale has a gradient
+    for (int a = 0; a < 3; ++a) out.mean[3 * i + a] = (float)gmu[a];
+    out.log_scale[3 * i] = (float)gls0;
+    out.log_scale[3 * i + 1] = 0.0f;
+    out.log_scale[3 * i + 2] = 0.0f;
+    for (int a = 0; a < 4; ++a) out.quat[4 * i + a] = 0.0f;
+    out.opacity[i] = (float)gop;
+    return;
+  }
   // Sigma = M M^T, M = Rq diag(s): dM = 2 dSigma M, with dSigma the full symmetric gradient
   double D[9];
   for (int a = 0; a < 3; ++a)

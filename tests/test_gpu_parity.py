@@ -43,11 +43,12 @@ CASES = {
 }
 
 
-def _pipeline(sc, views, n_sem, variant=0, split=True, state_capacity=None, fwd_chunk=1):
+def _pipeline(sc, views, n_sem, variant=0, split=True, state_capacity=None, fwd_chunk=1, isotropic=False):
     """split: forward with its state (long lists in segments of fwd_chunk 256-entry pieces,
-    0 = whole lists); state_capacity overrides the capacity the state is sized for."""
+    0 = whole lists); state_capacity overrides the capacity the state is sized for;
+    isotropic: the primitive of eq. 1-3."""
     raster = _raster()
-    cfg = raster.config(n_sem, variant=variant, fwd_chunk=fwd_chunk)
+    cfg = raster.config(n_sem, variant=variant, fwd_chunk=fwd_chunk, isotropic=int(isotropic))
     fr = raster.Frame(cfg, views)
     g = raster.to_device(sc)
     proj = raster.preprocess(cfg, g, fr)
@@ -73,15 +74,16 @@ def test_item_layout_matches_oracle():
                (b["W"], b["H"], b["view"], b["level"], b["tile0"], b["pix0"])
 
 
+@pytest.mark.parametrize("isotropic", [False, True])
 @pytest.mark.parametrize("case", list(CASES))
-def test_preprocess_parity(case):
+def test_preprocess_parity(case, isotropic):
     sc, views = CASES[case]()
     raster = _raster()
-    cfg = raster.config(sc.n_classes)
+    cfg = raster.config(sc.n_classes, isotropic=int(isotropic))
     fr = raster.Frame(cfg, views)
     proj = raster.preprocess(cfg, raster.to_device(sc), fr)
     torch.cuda.synchronize()
-    ref = oracle.preprocess(oracle.Config(), sc, views)
+    ref = oracle.preprocess(oracle.Config(isotropic=isotropic), sc, views)
     rad = proj["radius"].cpu().numpy()
     rec = proj["rec"].cpu().numpy().reshape(-1, 8).astype(np.float64)
     depth = proj["depth"].cpu().numpy()
@@ -176,6 +178,12 @@ def test_render_fwd_parity(case, variant):
     _check_render_fwd(sc, views, *VARIANTS[variant])
 
 
+@pytest.mark.parametrize("case", ["room_ragged_3lv", "room_two_views", "room_long_lists"])
+def test_render_fwd_parity_isotropic_primitive(case):
+    sc, views = CASES[case]()
+    _check_render_fwd(sc, views, *VARIANTS["split"], isotropic=True)
+
+
 def test_render_fwd_state_too_small():
     """A forward state sized for no duplicates cannot hold the long lists' segments; every
     tile is then one item, in the forward and in the reverse pass."""
@@ -185,11 +193,13 @@ def test_render_fwd_state_too_small():
     _check_render_bwd("room_long_lists", 3, True, fwd_chunk=0, state_capacity=0)
 
 
-def _check_render_fwd(sc, views, variant, split, fwd_chunk=1, state_capacity=None):
-    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant, split, state_capacity, fwd_chunk)
-    ref = oracle.render(oracle.Config(), sc, views)
+def _check_render_fwd(sc, views, variant, split, fwd_chunk=1, state_capacity=None, isotropic=False):
+    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant, split, state_capacity, fwd_chunk,
+                                           isotropic)
+    ocfg = oracle.Config(isotropic=isotropic)
+    ref = oracle.render(ocfg, sc, views)
     # sum_i w_i |f_i|: the magnitude a composited sum with mixed signs is measured against
-    mag = oracle.render(oracle.Config(), sc, views, sem=np.abs(sc.sem))["img"]
+    mag = oracle.render(ocfg, sc, views, sem=np.abs(sc.sem))["img"]
     its = oracle.items(views)
     K = ref["K"]
     flag = ref["flag"] != 0
@@ -275,6 +285,11 @@ def test_render_bwd_parity(case, variant):
     _check_render_bwd(case, *VARIANTS[variant])
 
 
+@pytest.mark.parametrize("case", ["room_ragged_3lv", "room_two_views", "room_long_lists"])
+def test_render_bwd_parity_isotropic_primitive(case):
+    _check_render_bwd(case, *VARIANTS["split"], isotropic=True)
+
+
 @pytest.mark.parametrize("split", [True, False])
 def test_render_bwd_single_item_fallback(split):
     """A workspace sized without the duplicate capacity cannot hold every segment of the
@@ -282,9 +297,12 @@ def test_render_bwd_single_item_fallback(split):
     _check_render_bwd("room_long_lists", 3, split, small_workspace=True)
 
 
-def _check_render_bwd(case, variant, split, fwd_chunk=1, small_workspace=False, state_capacity=None):
+def _check_render_bwd(case, variant, split, fwd_chunk=1, small_workspace=False, state_capacity=None,
+                      isotropic=False):
     sc, views = CASES[case]()
-    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant, split, state_capacity, fwd_chunk)
+    cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant, split, state_capacity, fwd_chunk,
+                                           isotropic)
+    ocfg = oracle.Config(isotropic=isotropic)
     raster = _raster()
     ws = None
     if small_workspace:
@@ -295,17 +313,19 @@ def _check_render_bwd(case, variant, split, fwd_chunk=1, small_workspace=False, 
     gimg = _shared_grad_image(fr, K, seed=5200)
     # pixels whose forward decisions sit within rounding of a threshold get no upstream
     # gradient, so they cannot contribute to any parameter's gradient on either side
-    r = oracle.render(oracle.Config(), sc, views)
+    r = oracle.render(ocfg, sc, views)
     gimg[pixel_mask_to_channels(r["flag"] != 0, oracle.items(views), K)] = 0.0
     grads = raster.render_bwd(cfg, g, proj, fr, srt, img, dict(color=torch.from_numpy(gimg).cuda()), ws=ws)
     torch.cuda.synchronize()
-    ref = oracle.backward(oracle.Config(), sc, views, gimg)
+    ref = oracle.backward(ocfg, sc, views, gimg)
     # features enter linearly: sum_p w |g_p| bounds their gradients' terms
-    mag = oracle.backward(oracle.Config(), sc, views, np.abs(gimg))
+    mag = oracle.backward(ocfg, sc, views, np.abs(gimg))
     for name in ("mean", "log_scale", "quat", "opacity", "rgb", "sem"):
         got = grads[name].cpu().numpy()
         sc_ = mag[name] if name in ("rgb", "sem") else None
         rel_check(got, ref[name], BWD_TOL, name=name, scale=sc_)
+    if isotropic:           # eq. 1-3 use one scale and no rotation
+        assert not grads["quat"].any() and not grads["log_scale"][:, 1:].any()
     rel_check(grads["pose"].cpu().numpy(), ref["pose"], BWD_TOL, name="pose")
 
 

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(L.Config) == 56
+    assert ctypes.sizeof(L.Config) == 60
     assert ctypes.sizeof(L.Images) == 56
     assert ctypes.sizeof(L.View) == 56
     assert ctypes.sizeof(L.Item) == 56
@@ -41,7 +41,7 @@ def test_defaults_and_status_strings():
     assert (c.tile_w, c.tile_h) == (16, 16)
     assert c.alpha_min == pytest.approx(1 / 255) and c.alpha_max == pytest.approx(0.99)
     assert c.t_min == pytest.approx(1e-4) and c.z_near == pytest.approx(0.2)
-    assert (c.variant, c.tile_order, c.fwd_chunk, c.ssim_lambda) == (0, 0, 1, 0.0)
+    assert (c.variant, c.tile_order, c.fwd_chunk, c.ssim_lambda, c.isotropic) == (0, 0, 1, 0.0, 0)
     assert lib.gs_status_string(L.GS_ERR_CAPACITY) == b"duplicate capacity exceeded"
     assert lib.gs_version() > 0
 
