@@ -69,6 +69,11 @@ typedef struct gs_config {
                               one scale r = exp(log_scale[0]) projected to standard deviation f r / d
                               along each image axis (plus eps_dilate); quat and log_scale[1..2] are
                               then unused and get zero gradient */
+  int32_t view_features;   /* 0: g->rgb [n][3] and g->sem [n][n_sem] are shared by all views;
+                              1: one block per view, [n_views][n][3] and [n_views][n][n_sem] (e.g.
+                              view-dependent colours from gs_sh_features), and gs_render_bwd's
+                              grads->rgb / grads->sem have the same per-view layout. Plain
+                              semantics only (not with an embedding) */
 } gs_config;
 
 /* One camera view: world -> camera transform x_c = R x_w + t (OpenCV axes,
@@ -258,6 +263,38 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
  * every item, the argmax over channels 4..K-1 (ties to the lowest index). */
 int gs_pyramid_downsample(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t max_level,
                           int32_t K, float* img, int32_t* labels, void* stream);
+
+/* ---- view-dependent features (Sec. III-B, spherical harmonics) -------------- */
+
+/* Higher SH bands of the colour and semantic features. The constant band is the plain
+ * feature (gs_gaussians.rgb / .sem), so degree 0 needs no array here. Coefficients are
+ * [n][(degree+1)^2 - 1][channels], band index j = l^2 + l + m (l >= 1), real harmonics in
+ * the sign convention of the 3DGS renderer. */
+typedef struct gs_sh {
+  int32_t rgb_degree, sem_degree;   /* 0..3 */
+  const float* rgb_rest;            /* [n][(rgb_degree+1)^2 - 1][3], NULL for degree 0 */
+  const float* sem_rest;            /* [n][(sem_degree+1)^2 - 1][n_sem], NULL for degree 0 */
+} gs_sh;
+
+/* Per view v and Gaussian i: f_vic = dc_ic + sum_j Y_j(d_vi) k_ijc with d_vi the unit
+ * direction from the camera centre -R_v^T t_v to the mean. Writes rgb_out [n_views][n][3]
+ * and sem_out [n_views][n][n_sem] (device), the per-view feature blocks that gs_render_fwd
+ * and gs_render_bwd read with cfg->view_features = 1. g supplies mean, rgb and sem (the
+ * constant band); n_sem may be 0 (sem_out unused). One launch on `stream`. */
+int gs_sh_features(int32_t n_sem, const gs_gaussians* g, const gs_sh* sh, const gs_view* views_dev, int32_t n_views,
+                   float* rgb_out, float* sem_out, void* stream);
+
+/* Backward of gs_sh_features for the per-view feature gradients grad_rgb [n_views][n][3]
+ * and grad_sem [n_views][n][n_sem] (gs_render_bwd's grads->rgb / ->sem under
+ * view_features): WRITES the constant-band gradients grad_rgb_dc [n][3], grad_sem_dc
+ * [n][n_sem] and the band gradients grad_rgb_rest / grad_sem_rest (the layouts of gs_sh;
+ * any may be NULL to skip it), and ADDS the direction's share to grad_mean [n][3] and to the
+ * translation part of grad_pose [n_views][6] (the camera centre moves by -R^T rho under
+ * T_cw <- Exp(xi) T_cw, and not with phi), so that it runs after gs_render_bwd. */
+int gs_sh_features_bwd(int32_t n_sem, const gs_gaussians* g, const gs_sh* sh, const gs_view* views_dev,
+                       int32_t n_views, const float* grad_rgb, const float* grad_sem, float* grad_rgb_dc,
+                       float* grad_rgb_rest, float* grad_sem_dc, float* grad_sem_rest, float* grad_mean,
+                       float* grad_pose, void* stream);
 
 /* ---- mapping update (Sec. III-D) -------------------------------------------- */
 

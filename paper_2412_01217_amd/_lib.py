@@ -30,7 +30,7 @@ EXPORTS = (
     "gs_workspace_size", "gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_pyramid_loss",
     "gs_render_bwd", "gs_pyramid_downsample", "gs_graph_begin", "gs_graph_end", "gs_graph_launch",
     "gs_graph_destroy", "gs_adam_step", "gs_distill_loss", "gs_argmax_agreement", "gs_gaussians_adam",
-    "gs_pose_adam",
+    "gs_pose_adam", "gs_sh_features", "gs_sh_features_bwd",
 )
 
 
@@ -38,7 +38,8 @@ class Config(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("z_near", c_float), ("eps_dilate", c_float),
                 ("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("guard", c_float),
                 ("full_rect", c_int32), ("n_sem", c_int32), ("variant", c_int32), ("tile_order", c_int32),
-                ("fwd_chunk", c_int32), ("ssim_lambda", c_float), ("isotropic", c_int32)]
+                ("fwd_chunk", c_int32), ("ssim_lambda", c_float), ("isotropic", c_int32),
+                ("view_features", c_int32)]
 
 
 class View(ctypes.Structure):
@@ -72,6 +73,10 @@ class Targets(ctypes.Structure):
 class ParamArrays(ctypes.Structure):
     _fields_ = [("mean", c_void_p), ("log_scale", c_void_p), ("quat", c_void_p), ("opacity", c_void_p),
                 ("rgb", c_void_p), ("sem", c_void_p)]
+
+
+class SH(ctypes.Structure):
+    _fields_ = [("rgb_degree", c_int32), ("sem_degree", c_int32), ("rgb_rest", c_void_p), ("sem_rest", c_void_p)]
 
 
 class AdamConfig(ctypes.Structure):
@@ -130,7 +135,10 @@ def lib():
         L.gs_gaussians_adam.argtypes = [c_int64, c_int32, P(ParamArrays), P(Grads), P(ParamArrays), P(ParamArrays),
                                         P(AdamConfig), c_int32, c_void_p]
         L.gs_pose_adam.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, P(AdamConfig), c_int32, c_void_p]
-        for name in ("gs_adam_step", "gs_distill_loss", "gs_argmax_agreement", "gs_gaussians_adam", "gs_pose_adam"):
+        L.gs_sh_features.argtypes = [c_int32, P(Gaussians), P(SH), c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
+        L.gs_sh_features_bwd.argtypes = [c_int32, P(Gaussians), P(SH), c_void_p, c_int32] + [c_void_p] * 9
+        for name in ("gs_adam_step", "gs_distill_loss", "gs_argmax_agreement", "gs_gaussians_adam", "gs_pose_adam",
+                     "gs_sh_features", "gs_sh_features_bwd"):
             getattr(L, name).restype = c_int32
         L.gs_graph_begin.argtypes = [c_void_p]
         L.gs_graph_end.argtypes = [c_void_p, P(c_void_p)]

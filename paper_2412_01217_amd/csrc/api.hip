@@ -77,6 +77,9 @@ int launch_adam(float*, const float*, float*, float*, int64_t, float, float, flo
 int launch_gaussians_adam(int64_t, int, const gs_param_arrays&, const gs_grads&, const gs_param_arrays&,
                           const gs_param_arrays&, const gs_adam_config&, int, hipStream_t);
 int launch_pose_adam(gs_view*, int, const float*, float*, float*, const gs_adam_config&, int, hipStream_t);
+int launch_sh_fwd(const gs_gaussians&, const gs_sh&, int, const gs_view*, int, float*, float*, hipStream_t);
+int launch_sh_bwd(const gs_gaussians&, const gs_sh&, int, const gs_view*, int, const float*, const float*, float*,
+                  float*, float*, float*, float*, float*, hipStream_t);
 int launch_distill(const gs_item*, int, int64_t, int, const float*, const float*, float, float*, float*, float*,
                    hipStream_t);
 int launch_agree(const gs_item*, int, int64_t, int, const float*, const float*, unsigned long long*, hipStream_t);
@@ -96,6 +99,7 @@ bool cfg_ok(const gs_config* c) {
   if (c->fwd_chunk < 0 || c->fwd_chunk > 65535) return false;
   if (!(c->ssim_lambda >= 0.0f && c->ssim_lambda <= 1.0f)) return false;
   if (c->isotropic < 0 || c->isotropic > 1) return false;
+  if (c->view_features < 0 || c->view_features > 1) return false;
   return true;
 }
 
@@ -133,6 +137,7 @@ void gs_config_default(gs_config* c) {
   c->fwd_chunk = 1;
   c->ssim_lambda = 0.0f;
   c->isotropic = 0;
+  c->view_features = 0;
 }
 
 const char* gs_status_string(int s) {
@@ -243,6 +248,7 @@ int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   if (learned && (cfg->n_sem != 16 || !head || !head_shape_ok(*head) || !out->logits || out->n_pixels < 0))
     return GS_ERR_INVALID_ARG;
   if (!learned && head) return GS_ERR_INVALID_ARG;
+  if (learned && cfg->view_features) return GS_ERR_INVALID_ARG;
   if (!learned && cfg->n_sem > 0 && g->n > 0 && !g->sem) return GS_ERR_INVALID_ARG;
   if (n_tiles == 0) return GS_OK;
   if (!items_dev || !vals || !ranges || !out->color || !out->T || !out->n_contrib) return GS_ERR_INVALID_ARG;
@@ -286,6 +292,7 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
                   fwd->n_pixels < 0))
     return GS_ERR_INVALID_ARG;
   if (!learned && head) return GS_ERR_INVALID_ARG;
+  if (learned && cfg->view_features) return GS_ERR_INVALID_ARG;
   if (!learned && cfg->n_sem > 0 && g->n > 0 && (!g->sem || !grads->sem)) return GS_ERR_INVALID_ARG;
   if (!grads->mean || !grads->log_scale || !grads->quat || !grads->opacity || !grads->rgb || !grads->pose)
     return GS_ERR_INVALID_ARG;
@@ -302,7 +309,8 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   gs_grads gr = *grads;
   if (learned) gr.sem = grads->emb;   // the semantic channels' gradient is the embedding's
   float* const zp[4] = {(float*)workspace, gr.rgb, cfg->n_sem > 0 ? gr.sem : nullptr, gr.pose};
-  const int64_t zn[4] = {kSortBwdRecord * (int64_t)n_items * n, 3 * n, (int64_t)cfg->n_sem * n, 6ll * n_views};
+  const int64_t fv = cfg->view_features ? n_views : 1;   // feature blocks (one per view, or shared)
+  const int64_t zn[4] = {kSortBwdRecord * (int64_t)n_items * n, 3 * n * fv, (int64_t)cfg->n_sem * n * fv, 6ll * n_views};
   int st = launch_zero_f32(zp, zn, 4, s);
   if (st) return st;
   if (learned) {
@@ -329,6 +337,41 @@ int gs_adam_step(float* param, const float* grad, float* m, float* v, int64_t n,
     return GS_ERR_INVALID_ARG;
   if (n > 0 && (!param || !grad || !m || !v)) return GS_ERR_INVALID_ARG;
   return launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, bf16_copy, (hipStream_t)stream);
+}
+
+static bool sh_ok(int32_t n_sem, const gs_gaussians* g, const gs_sh* sh) {
+  if (!sh || !g || g->n < 0 || n_sem < 0 || n_sem > 60) return false;
+  if (sh->rgb_degree < 0 || sh->rgb_degree > 3 || sh->sem_degree < 0 || sh->sem_degree > 3) return false;
+  if (g->emb) return false;   // plain semantics only
+  if (g->n == 0) return true;
+  if (!g->mean || !g->rgb || (n_sem > 0 && !g->sem)) return false;
+  if (sh->rgb_degree > 0 && !sh->rgb_rest) return false;
+  if (n_sem > 0 && sh->sem_degree > 0 && !sh->sem_rest) return false;
+  return true;
+}
+
+int gs_sh_features(int32_t n_sem, const gs_gaussians* g, const gs_sh* sh, const gs_view* views_dev, int32_t n_views,
+                   float* rgb_out, float* sem_out, void* stream) {
+  if (!sh_ok(n_sem, g, sh) || n_views < 0) return GS_ERR_INVALID_ARG;
+  if (g->n == 0 || n_views == 0) return GS_OK;
+  if (!views_dev || !rgb_out || (n_sem > 0 && !sem_out)) return GS_ERR_INVALID_ARG;
+  return launch_sh_fwd(*g, *sh, n_sem, views_dev, n_views, rgb_out, sem_out, (hipStream_t)stream);
+}
+
+int gs_sh_features_bwd(int32_t n_sem, const gs_gaussians* g, const gs_sh* sh, const gs_view* views_dev,
+                       int32_t n_views, const float* grad_rgb, const float* grad_sem, float* grad_rgb_dc,
+                       float* grad_rgb_rest, float* grad_sem_dc, float* grad_sem_rest, float* grad_mean,
+                       float* grad_pose, void* stream) {
+  if (!sh_ok(n_sem, g, sh) || n_views < 0) return GS_ERR_INVALID_ARG;
+  if (g->n == 0) return GS_OK;
+  if (n_views > 0 && (!views_dev || !grad_rgb || (n_sem > 0 && !grad_sem))) return GS_ERR_INVALID_ARG;
+  const bool dir = (sh->rgb_degree > 0 || (n_sem > 0 && sh->sem_degree > 0)) && n_views > 0;
+  if (dir && (!grad_mean || !grad_pose)) return GS_ERR_INVALID_ARG;
+  if (n_views == 0) return GS_ERR_INVALID_ARG;   // the constant-band gradient is a sum over views
+  gs_sh s = *sh;
+  if (n_sem == 0) s.sem_degree = 0;
+  return launch_sh_bwd(*g, s, n_sem, views_dev, n_views, grad_rgb, grad_sem, grad_rgb_dc, grad_rgb_rest, grad_sem_dc,
+                       grad_sem_rest, grad_mean, grad_pose, (hipStream_t)stream);
 }
 
 static bool adam_ok(const gs_adam_config* hp, int32_t step) {

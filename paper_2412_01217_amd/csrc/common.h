@@ -110,7 +110,7 @@ __device__ __forceinline__ void lds_barrier() {
 
 // One 16x16 tile of one item, as a render block sees it.
 struct Ctx {
-  int item, tx, ty, tiles_x, tiles_y;
+  int item, view, tx, ty, tiles_x, tiles_y;
   int W, H;
   int64_t HW, pixel_base;
   uint32_t start, end;
@@ -122,6 +122,7 @@ __device__ __forceinline__ Ctx make_ctx_of(const gs_item* items, int n_items, co
   Ctx c;
   c.item = item_of_tile(items, n_items, tile);
   const gs_item it = items[c.item];
+  c.view = it.view;
   const int lt = tile - it.tile_base;
   c.tx = lt % it.tiles_x;
   c.ty = lt / it.tiles_x;
@@ -138,6 +139,12 @@ __device__ __forceinline__ Ctx make_ctx_of(const gs_item* items, int n_items, co
 
 __device__ __forceinline__ Ctx make_ctx(const gs_item* items, int n_items, const uint32_t* ranges, int order) {
   return make_ctx_of(items, n_items, ranges, order ? (int)blockIdx.x : (int)gridDim.x - 1 - (int)blockIdx.x);
+}
+
+// First feature entry of a tile's Gaussians: with per-view features (cfg.view_features) the
+// rgb / sem arrays (and their gradients) hold one [n][channels] block per view.
+__device__ __forceinline__ int64_t feature_offset(const gs_config& cfg, int view, int64_t n) {
+  return cfg.view_features ? (int64_t)view * n : 0;
 }
 
 // Tile-local pixel index t (0..255, row-major in the 16x16 tile) -> image coordinates.

@@ -20,7 +20,7 @@ struct Shape {
 };
 
 struct TileCtx {
-  int item, tx, ty, u, v;
+  int item, view, tx, ty, u, v;
   bool inside;
   float px, py;
   int64_t pix;      // global pixel index
@@ -34,6 +34,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const gs_item* items, int n_items, c
   const int tile = blockIdx.x;
   c.item = item_of_tile(items, n_items, tile);
   const gs_item it = items[c.item];
+  c.view = it.view;
   const int lt = tile - it.tile_base;
   c.tx = lt % it.tiles_x;
   c.ty = lt / it.tiles_x;
@@ -55,15 +56,16 @@ __device__ __forceinline__ TileCtx tile_ctx(const gs_item* items, int n_items, c
 template <int NS>
 __device__ __forceinline__ void stage(float* sm, uint32_t g, int item, int64_t n, const float* __restrict__ rec,
                                       const float* __restrict__ depth, const float* __restrict__ rgb,
-                                      const float* __restrict__ sem, const uint16_t* __restrict__ emb, int n_sem) {
+                                      const float* __restrict__ sem, const uint16_t* __restrict__ emb, int n_sem,
+                                      int64_t foff) {
   const int64_t e = (int64_t)item * n + g;
   const float4* r = reinterpret_cast<const float4*>(rec + kRecFloats * e);
   float4* d = reinterpret_cast<float4*>(sm);
   d[0] = r[0];
   d[1] = r[1];
-  d[2] = make_float4(rgb[3 * (int64_t)g], rgb[3 * (int64_t)g + 1], rgb[3 * (int64_t)g + 2], depth[e]);
-  const float* s = sem + (int64_t)n_sem * g;
-  const uint16_t* es = emb + (int64_t)n_sem * g;
+  d[2] = make_float4(rgb[3 * ((int64_t)g + foff)], rgb[3 * ((int64_t)g + foff) + 1], rgb[3 * ((int64_t)g + foff) + 2], depth[e]);
+  const float* s = sem + (int64_t)n_sem * ((int64_t)g + foff);
+  const uint16_t* es = emb + (int64_t)n_sem * ((int64_t)g + foff);
 #pragma unroll
   for (int c = 0; c < NS; ++c)
     sm[12 + c] = c >= n_sem ? 0.0f : (emb ? __uint_as_float((uint32_t)es[c] << 16) : s[c]);
@@ -83,6 +85,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(gs_config cfg, const float* 
   float* sm = reinterpret_cast<float*>(smem);
   const int Kr = 4 + n_sem;
   const TileCtx c = tile_ctx(items, n_items, ranges, Kr);
+  const int64_t foff = feature_offset(cfg, c.view, n);
   float acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0f;
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(gs_config cfg, const float* 
   for (uint32_t b = c.start; b < c.end; b += BATCH) {
     if (__syncthreads_count(!done) == 0) break;
     const int cnt = (int)min((uint32_t)BATCH, c.end - b);
-    for (int q = threadIdx.x; q < cnt; q += 256) stage<NS>(sm + q * STRIDE, vals[b + q], c.item, n, rec, depth, rgb, sem, emb, n_sem);
+    for (int q = threadIdx.x; q < cnt; q += 256) stage<NS>(sm + q * STRIDE, vals[b + q], c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
     __syncthreads();
     if (!done) {
       for (int q = 0; q < cnt; ++q) {
@@ -148,6 +151,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(gs_config cfg, const float* 
   float* sm = reinterpret_cast<float*>(smem);
   const int Kr = 4 + n_sem;
   const TileCtx c = tile_ctx(items, n_items, ranges, Kr);
+  const int64_t foff = feature_offset(cfg, c.view, n);
   const int lane = threadIdx.x & 63;
   float gp[K];
 #pragma unroll
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(gs_config cfg, const float* 
     const int cnt = hi - lo;
     __syncthreads();
     for (int q = threadIdx.x; q < cnt; q += 256)
-      stage<NS>(sm + q * STRIDE, vals[c.start + lo + q], c.item, n, rec, depth, rgb, sem, emb, n_sem);
+      stage<NS>(sm + q * STRIDE, vals[c.start + lo + q], c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
     for (int q = threadIdx.x; q < cnt * NVP; q += 256) red[q] = 0.0f;
     __syncthreads();
     for (int q = cnt - 1; q >= 0; --q) {
@@ -228,9 +232,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(gs_config cfg, const float* 
       const uint32_t g = vals[c.start + lo + q];
       const int64_t e = (int64_t)c.item * n + g;
       if (v < 6) atomicAdd(&g2d[8 * e + v], s);
-      else if (v < 9) atomicAdd(&grgb[3 * (int64_t)g + (v - 6)], s);
+      else if (v < 9) atomicAdd(&grgb[3 * ((int64_t)g + foff) + (v - 6)], s);
       else if (v == 9) atomicAdd(&g2d[8 * e + 6], s);
-      else if (v - 10 < n_sem) atomicAdd(&gsem[(int64_t)n_sem * g + (v - 10)], s);
+      else if (v - 10 < n_sem) atomicAdd(&gsem[(int64_t)n_sem * ((int64_t)g + foff) + (v - 10)], s);
     }
   }
 }

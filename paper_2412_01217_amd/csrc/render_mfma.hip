@@ -48,7 +48,7 @@ struct Stage {
   __device__ __forceinline__ void fetch(const uint32_t* __restrict__ vals, uint32_t b, int cnt, int item, int64_t n,
                                         const float* __restrict__ rec, const float* __restrict__ depth,
                                         const float* __restrict__ rgb, const float* __restrict__ sem,
-                                        const uint16_t* __restrict__ emb, int n_sem) {
+                                        const uint16_t* __restrict__ emb, int n_sem, int64_t foff) {
     const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
     const bool live = q < cnt;
     const uint32_t g = live ? vals[b + q] : 0u;
@@ -61,10 +61,10 @@ struct Stage {
       const int k = part * CPT + j;
       float v = 0.0f;
       if (live && k < Kr) {
-        if (k < 3) v = rgb[3 * (int64_t)g + k];
+        if (k < 3) v = rgb[3 * ((int64_t)g + foff) + k];
         else if (k == 3) v = depth[e];
-        else if (emb) v = __uint_as_float((uint32_t)emb[(int64_t)n_sem * g + (k - 4)] << 16);
-        else v = sem[(int64_t)n_sem * g + (k - 4)];
+        else if (emb) v = __uint_as_float((uint32_t)emb[(int64_t)n_sem * ((int64_t)g + foff) + (k - 4)] << 16);
+        else v = sem[(int64_t)n_sem * ((int64_t)g + foff) + (k - 4)];
       }
       f[j] = v;
     }
@@ -93,6 +93,7 @@ __global__ __launch_bounds__(256) void k_render_fwd_mfma(gs_config cfg, const fl
   __shared__ float s_feat[kBatch * FST];
   __shared__ float s_w[4][64 * kWst];
   const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order);
+  const int64_t foff = feature_offset(cfg, c.view, n);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   int u, v;
   tile_pixel(c, tid, u, v);
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(256) void k_render_fwd_mfma(gs_config cfg, const fl
   const float amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
   float* W = s_w[wave];
   Stage<NS> st;
-  if (c.start < c.end) st.fetch(vals, c.start, (int)min((uint32_t)kBatch, c.end - c.start), c.item, n, rec, depth, rgb, sem, emb, n_sem);
+  if (c.start < c.end) st.fetch(vals, c.start, (int)min((uint32_t)kBatch, c.end - c.start), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
   for (uint32_t b = c.start; b < c.end; b += kBatch) {
     // every wave is past the previous batch's LDS reads; stop once every pixel has
     if (__syncthreads_count(!done) == 0) break;
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(256) void k_render_fwd_mfma(gs_config cfg, const fl
     __syncthreads();
     const int cnt = (int)min((uint32_t)kBatch, c.end - b);
     if (b + kBatch < c.end)
-      st.fetch(vals, b + kBatch, (int)min((uint32_t)kBatch, c.end - b - kBatch), c.item, n, rec, depth, rgb, sem, emb, n_sem);
+      st.fetch(vals, b + kBatch, (int)min((uint32_t)kBatch, c.end - b - kBatch), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
     // front-to-back recurrence, branch-free: the alpha of successive Gaussians is
     // independent, only T carries from one to the next
     uint32_t nz = 0;  // bit q: some lane of this wave blends Gaussian q
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_mfma(gs_config cfg, const fl
   __shared__ float s_geo[kBatch * 6 * 16];
   __shared__ uint32_t s_lmax;
   const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order);
+  const int64_t foff = feature_offset(cfg, c.view, n);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int Kr = 4 + n_sem;
   int u, v;
@@ -243,7 +245,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_mfma(gs_config cfg, const fl
   Stage<NS> st;
   if (lmax > 0) {
     const int lo0 = max(0, (int)lmax - kBatch);
-    st.fetch(vals, c.start + lo0, (int)lmax - lo0, c.item, n, rec, depth, rgb, sem, emb, n_sem);
+    st.fetch(vals, c.start + lo0, (int)lmax - lo0, c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
   }
   for (int hi = (int)lmax; hi > 0; hi -= kBatch) {
     const int lo = max(0, hi - kBatch);
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_mfma(gs_config cfg, const fl
     __syncthreads();
     if (lo > 0) {
       const int lo2 = max(0, lo - kBatch);
-      st.fetch(vals, c.start + lo2, lo - lo2, c.item, n, rec, depth, rgb, sem, emb, n_sem);
+      st.fetch(vals, c.start + lo2, lo - lo2, c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
     }
     bool wave_any = false;
 #pragma unroll 2
@@ -324,9 +326,9 @@ __global__ __launch_bounds__(256) void k_render_bwd_mfma(gs_config cfg, const fl
       const float val = s_df[idx];
       if (val == 0.0f || k >= Kr) continue;
       const uint32_t g = vals[c.start + lo + q];
-      if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
+      if (k < 3) atomicAdd(&grgb[3 * ((int64_t)g + foff) + k], val);
       else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
-      else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
+      else atomicAdd(&gsem[(int64_t)n_sem * ((int64_t)g + foff) + (k - 4)], val);
     }
     for (int idx = tid; idx < cnt * 6; idx += 256) {
       const int q = idx / 6, comp = idx - q * 6;

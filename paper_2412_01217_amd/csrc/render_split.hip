@@ -158,7 +158,7 @@ struct SStage {
   __device__ __forceinline__ void fetch(const uint32_t* __restrict__ vals, uint32_t b, int cnt, int item, int64_t n,
                                         const float* __restrict__ rec, const float* __restrict__ depth,
                                         const float* __restrict__ rgb, const float* __restrict__ sem,
-                                        const uint16_t* __restrict__ emb, int n_sem) {
+                                        const uint16_t* __restrict__ emb, int n_sem, int64_t foff) {
     const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
     const bool live = q < cnt;
     const uint32_t g = live ? vals[b + q] : 0u;
@@ -172,10 +172,10 @@ struct SStage {
       const int k = part * CPT + j;
       float v = 0.0f;
       if (live && k < Kr) {
-        if (k < 3) v = rgb[3 * (int64_t)g + k];
+        if (k < 3) v = rgb[3 * ((int64_t)g + foff) + k];
         else if (k == 3) v = depth[e];
-        else if (emb) v = __uint_as_float((uint32_t)emb[(int64_t)n_sem * g + (k - 4)] << 16);
-        else v = sem[(int64_t)n_sem * g + (k - 4)];
+        else if (emb) v = __uint_as_float((uint32_t)emb[(int64_t)n_sem * ((int64_t)g + foff) + (k - 4)] << 16);
+        else v = sem[(int64_t)n_sem * ((int64_t)g + foff) + (k - 4)];
       }
       f[j] = v;
     }
@@ -360,6 +360,7 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
       tile = cfg.tile_order ? (int)blockIdx.x : (int)gridDim.x - 1 - (int)blockIdx.x;
     }
     const Ctx c = make_ctx_of(items, n_items, ranges, tile);
+    const int64_t foff = feature_offset(cfg, c.view, n);
     int u, v;
     tile_pixel(c, tid, u, v);
     const bool inside = u < c.W && v < c.H;
@@ -384,7 +385,7 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
       const uint32_t a0 = split ? c.start + sg * kSeg : c.start;
       const uint32_t b0 = split ? min(c.end, a0 + kSeg) : c.end;
       const bool active = !done;
-      if (a0 < b0) st.fetch(vals, a0, (int)min((uint32_t)kB, b0 - a0), c.item, n, rec, depth, rgb, sem, emb, n_sem);
+      if (a0 < b0) st.fetch(vals, a0, (int)min((uint32_t)kB, b0 - a0), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
       for (uint32_t b = a0; b < b0; b += kB) {
         // every wave is past the previous batch's LDS reads; stop once every pixel has
         if (__syncthreads_count(!done) == 0) break;
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
         __syncthreads();
         const int cnt = (int)min((uint32_t)kB, b0 - b);
         if (b + kB < b0)
-          st.fetch(vals, b + kB, (int)min((uint32_t)kB, b0 - b - kB), c.item, n, rec, depth, rgb, sem, emb, n_sem);
+          st.fetch(vals, b + kB, (int)min((uint32_t)kB, b0 - b - kB), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
         // front-to-back recurrence, branch-free; only T carries from one Gaussian to the next
         bool took = false;
         const uint32_t base = b - c.start;
@@ -760,6 +761,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
     const int seg = (int)(wk.y & 0xffffu), nseg = (int)(wk.y >> 16);
     if (SUMMARY && nseg < 2) continue;
     const Ctx c = make_ctx_of(items, n_items, ranges, tile);
+    const int64_t foff = feature_offset(cfg, c.view, n);
     int u, v;
     tile_pixel(c, tid, u, v);
     const bool inside = u < c.W && v < c.H;
@@ -862,7 +864,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
     if (b0 > a0) {
       const int f0 = SUMMARY ? a0 : max(a0, b0 - kB);
       const int f1 = SUMMARY ? min(b0, a0 + kB) : b0;
-      st.fetch(vals, c.start + f0, f1 - f0, c.item, n, rec, depth, rgb, sem, emb, n_sem);
+      st.fetch(vals, c.start + f0, f1 - f0, c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
     }
     const int n_batches = (b0 - a0 + kB - 1) / kB;
     // one FP32 atomic per (Gaussian, channel) and (Gaussian, component) of a finished batch
@@ -887,9 +889,9 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
           const float val = fv[j];
           if (q >= fcnt || val == 0.0f || k >= Kr) continue;
           const uint32_t g = fg[j];
-          if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
+          if (k < 3) atomicAdd(&grgb[3 * ((int64_t)g + foff) + k], val);
           else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
-          else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
+          else atomicAdd(&gsem[(int64_t)n_sem * ((int64_t)g + foff) + (k - 4)], val);
         }
       } else {
         // (a register budget without room for the unrolled form)
@@ -898,9 +900,9 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
           const float val = fdf[q * DFS + k];
           if (val == 0.0f || k >= Kr) continue;
           const uint32_t g = fgid[q];
-          if (k < 3) atomicAdd(&grgb[3 * (int64_t)g + k], val);
+          if (k < 3) atomicAdd(&grgb[3 * ((int64_t)g + foff) + k], val);
           else if (k == 3) atomicAdd(&g2d[8 * ((int64_t)c.item * n + g) + 6], val);
-          else atomicAdd(&gsem[(int64_t)n_sem * g + (k - 4)], val);
+          else atomicAdd(&gsem[(int64_t)n_sem * ((int64_t)g + foff) + (k - 4)], val);
         }
       }
       for (int idx = tid; idx < fcnt * 6; idx += 256) {
@@ -944,7 +946,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
         if (bi + 1 < n_batches) {
           const int nlo = SUMMARY ? hi : max(a0, lo - kB);
           const int nhi = SUMMARY ? min(b0, hi + kB) : lo;
-          st.fetch(vals, c.start + nlo, nhi - nlo, c.item, n, rec, depth, rgb, sem, emb, n_sem);
+          st.fetch(vals, c.start + nlo, nhi - nlo, c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
         }
       };
       if constexpr (SUMMARY) fetch_next();

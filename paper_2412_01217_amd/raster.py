@@ -245,8 +245,9 @@ def alloc_grads(cfg, g: dict, frame: Frame, n_classes: int = 0) -> dict:
     dev = frame.device
     z = lambda *s: torch.empty(*s, dtype=torch.float32, device=dev)  # noqa: E731
     learned = g.get("emb") is not None
-    out = dict(mean=z(n, 3), log_scale=z(n, 3), quat=z(n, 4), opacity=z(n), rgb=z(n, 3),
-               sem=z(n, cfg.n_sem) if (cfg.n_sem and not learned) else None,
+    fv = frame.n_views if cfg.view_features else 1        # per-view feature blocks
+    out = dict(mean=z(n, 3), log_scale=z(n, 3), quat=z(n, 4), opacity=z(n), rgb=z(fv * n, 3),
+               sem=z(fv * n, cfg.n_sem) if (cfg.n_sem and not learned) else None,
                emb=z(n, 16) if learned else None, pose=z(frame.n_views, 6))
     if learned:
         out.update(head_W1=z(64, 16), head_b1=z(64), head_W2=z(n_classes, 64), head_b2=z(n_classes))
@@ -278,6 +279,43 @@ def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch
               bf16_copy: torch.Tensor | None = None, beta1=0.9, beta2=0.999, eps=1e-8):
     L.check(L.lib().gs_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), lr, beta1, beta2, eps,
                                  step, _ptr(bf16_copy), _stream(param.device)), "gs_adam_step")
+
+
+def sh_struct(sh: dict) -> L.SH:
+    """sh: rgb_degree, sem_degree and the band arrays rgb_rest / sem_rest (device)."""
+    return L.SH(int(sh.get("rgb_degree", 0)), int(sh.get("sem_degree", 0)), _ptr(sh.get("rgb_rest")),
+                _ptr(sh.get("sem_rest")))
+
+
+def sh_features(g: dict, sh: dict, frame: Frame, out: dict | None = None) -> dict:
+    """Per-view features [n_views * n, 3] and [n_views * n, n_sem] of every view of frame,
+    for a render with cfg.view_features = 1."""
+    n = int(g["mean"].shape[0])
+    S = int(g["sem"].shape[1]) if g.get("sem") is not None else 0
+    V = frame.n_views
+    if out is None:
+        out = dict(rgb=torch.empty(V * n, 3, device=frame.device),
+                   sem=torch.empty(V * n, S, device=frame.device) if S else None)
+    L.check(L.lib().gs_sh_features(S, ctypes.byref(gaussians_struct(g)), ctypes.byref(sh_struct(sh)), _ptr(frame.views_dev), V,
+                                   _ptr(out["rgb"]), _ptr(out.get("sem")), _stream(frame.device)), "gs_sh_features")
+    return out
+
+
+def sh_features_bwd(g: dict, sh: dict, frame: Frame, grads: dict, out: dict | None = None) -> dict:
+    """Takes gs_render_bwd's per-view feature gradients (grads rgb / sem) to the constant
+    bands and SH bands (returned), and adds the direction's share to grads mean and pose."""
+    n = int(g["mean"].shape[0])
+    S = int(g["sem"].shape[1]) if g.get("sem") is not None else 0
+    dev = frame.device
+    if out is None:
+        z = lambda t: None if t is None else torch.empty_like(t)  # noqa: E731
+        out = dict(rgb_dc=torch.empty(n, 3, device=dev), sem_dc=torch.empty(n, S, device=dev) if S else None,
+                   rgb_rest=z(sh.get("rgb_rest")), sem_rest=z(sh.get("sem_rest")))
+    L.check(L.lib().gs_sh_features_bwd(S, ctypes.byref(gaussians_struct(g)), ctypes.byref(sh_struct(sh)), _ptr(frame.views_dev),
+                                       frame.n_views, _ptr(grads["rgb"]), _ptr(grads.get("sem")), _ptr(out["rgb_dc"]),
+                                       _ptr(out.get("rgb_rest")), _ptr(out.get("sem_dc")), _ptr(out.get("sem_rest")),
+                                       _ptr(grads["mean"]), _ptr(grads["pose"]), _stream(dev)), "gs_sh_features_bwd")
+    return out
 
 
 PARAM_FIELDS = ("mean", "log_scale", "quat", "opacity", "rgb", "sem")

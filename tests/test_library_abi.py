@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(L.Config) == 60
+    assert ctypes.sizeof(L.Config) == 64
     assert ctypes.sizeof(L.Images) == 56
     assert ctypes.sizeof(L.View) == 56
     assert ctypes.sizeof(L.Item) == 56
@@ -41,7 +41,7 @@ def test_defaults_and_status_strings():
     assert (c.tile_w, c.tile_h) == (16, 16)
     assert c.alpha_min == pytest.approx(1 / 255) and c.alpha_max == pytest.approx(0.99)
     assert c.t_min == pytest.approx(1e-4) and c.z_near == pytest.approx(0.2)
-    assert (c.variant, c.tile_order, c.fwd_chunk, c.ssim_lambda, c.isotropic) == (0, 0, 1, 0.0, 0)
+    assert (c.variant, c.tile_order, c.fwd_chunk, c.ssim_lambda, c.isotropic, c.view_features) == (0, 0, 1, 0.0, 0, 0)
     assert lib.gs_status_string(L.GS_ERR_CAPACITY) == b"duplicate capacity exceeded"
     assert lib.gs_version() > 0
 
@@ -181,3 +181,20 @@ def test_mapping_update_structs_and_argument_checks():
     assert lib.gs_pose_adam(None, 0, None, None, None, ctypes.byref(hp()), 1, None) == L.GS_OK
     assert lib.gs_pose_adam(None, 2, fake, fake, fake, ctypes.byref(hp()), 1, None) == L.GS_ERR_INVALID_ARG
     assert lib.gs_pose_adam(fake, 2, fake, fake, fake, ctypes.byref(hp()), 0, None) == L.GS_ERR_INVALID_ARG
+
+
+def test_sh_struct_and_argument_checks():
+    lib = L.lib()
+    assert ctypes.sizeof(L.SH) == 24
+    fake = ctypes.c_void_p(256)
+    g = L.Gaussians(10, fake, fake, fake, fake, fake, fake, None)
+    ok = L.SH(3, 1, fake, fake)
+    assert lib.gs_sh_features(4, ctypes.byref(g), ctypes.byref(ok), fake, 0, fake, fake, None) == L.GS_OK
+    for bad in (L.SH(4, 0, fake, None), L.SH(2, 0, None, None), L.SH(0, 2, None, None), L.SH(-1, 0, None, None)):
+        assert lib.gs_sh_features(4, ctypes.byref(g), ctypes.byref(bad), fake, 1, fake, fake, None) == \
+            L.GS_ERR_INVALID_ARG
+    # the constant-band gradient is a sum over views: no views is an error, missing outputs too
+    assert lib.gs_sh_features_bwd(4, ctypes.byref(g), ctypes.byref(ok), fake, 0, *([fake] * 8), None) == \
+        L.GS_ERR_INVALID_ARG
+    assert lib.gs_sh_features_bwd(4, ctypes.byref(g), ctypes.byref(ok), fake, 2, fake, fake, fake, fake, fake, fake,
+                                  None, fake, None) == L.GS_ERR_INVALID_ARG
