@@ -60,17 +60,26 @@ def make_targets(cfg_plain, fr, sc, device):
     return dict(rgb=rgb, depth=depth, label=labels)
 
 
-def plain_step(sc, views, device, targets=None, variant=0, tile_order=0, ssim_lambda=0.0, isotropic=0):
+def plain_step(sc, views, device, targets=None, variant=0, tile_order=0, ssim_lambda=0.0, isotropic=0, sh=None):
+    """sh: (rgb degree, semantic degree) of seeded SH bands N(0, 0.1), or None."""
+    import torch
     from paper_2412_01217_amd import raster
     from paper_2412_01217_amd.step import MappingStep
     C = sc.n_classes
     cfg = raster.config(C, variant=variant, tile_order=tile_order, ssim_lambda=float(ssim_lambda),
-                        isotropic=int(isotropic))
+                        isotropic=int(isotropic), view_features=int(sh is not None))
     fr = raster.Frame(cfg, views, device=device)
     g = raster.to_device(sc, device)
     g.pop("emb", None)
     targets = targets if targets is not None else make_targets(cfg, fr, sc, device)
-    return MappingStep(cfg, fr, g, targets, C), targets
+    shd = None
+    if sh is not None:
+        rng = np.random.default_rng(7000)
+        dr, ds = sh
+        band = lambda d, ch: (torch.tensor(rng.normal(size=(sc.n, (d + 1) ** 2 - 1, ch)) * 0.1,  # noqa: E731
+                                           dtype=torch.float32, device=device) if d else None)
+        shd = dict(rgb_degree=dr, sem_degree=ds, rgb_rest=band(dr, 3), sem_rest=band(ds, C))
+    return MappingStep(cfg, fr, g, targets, C, sh=shd), targets
 
 
 def learned_step(sc, views, head, device, targets):
@@ -349,6 +358,20 @@ def isotropic_report(args, dev, sc, views, targets):
             "ms_per_step": m["ms"], "stage_ms": m["stage_ms"], "duplicates": c["dup"], "pairs_iterated": c["pairs"]}
 
 
+def sh_report(args, dev, sc, views, targets, degrees=(3, 1)):
+    """The room step with view-dependent features: SH of degree 3 for colour and 1 for the
+    52 class logits, evaluated per view before the render and differentiated after it."""
+    import torch
+    step, _ = plain_step(sc, views, dev, targets=targets, variant=args.variant, sh=degrees)
+    m = measure(step, args.steps, args.warmup, graph=not args.eager)
+    c = work_counts(step)
+    del step
+    torch.cuda.empty_cache()
+    return {"sh_degrees": {"rgb": degrees[0], "semantics": degrees[1]},
+            "value": c["pixels"] / 1e6 / (m["ms"] * 1e-3), "unit": "MP/s", "ms_per_step": m["ms"],
+            "stage_ms": m["stage_ms"]}
+
+
 def ssim_report(args, dev, sc, views, targets, ms_ref, loss_ms_ref, lam=0.2):
     """The same room step with the colour loss of eq. 10 at the paper's lambda = 0.2
     (L1 and SSIM) in place of the plain L1 term."""
@@ -376,6 +399,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=0, help="render kernels: 0 auto (3), 1 VALU, 2 FP32 matrix cores, 3 split-bf16 matrix cores")
     ap.add_argument("--eager", action="store_true", help="time eager calls instead of graph replays")
+    ap.add_argument("--sh", default="", metavar="R,S",
+                    help="SH degrees (colour, semantics) of view-dependent features in the timed step (default: none)")
     ap.add_argument("--ssim-lambda", type=float, default=0.0,
                     help="SSIM weight of the colour loss in the timed step (0: the L1 loss of the workloads)")
     ap.add_argument("--train-steps", type=int, default=2000)
@@ -405,7 +430,8 @@ def main():
         print(json.dumps({"metric": METRIC, **sub(args, dev)}), flush=True)
         return
     sc, views = scenes.config_room()
-    step, targets = plain_step(sc, views, dev, variant=args.variant, ssim_lambda=args.ssim_lambda)
+    sh = tuple(int(x) for x in args.sh.split(",")) if args.sh else None
+    step, targets = plain_step(sc, views, dev, variant=args.variant, ssim_lambda=args.ssim_lambda, sh=sh)
     m = measure(step, args.steps, args.warmup, graph=not args.eager)
     c = work_counts(step)
     ms = m["ms"]
@@ -419,7 +445,8 @@ def main():
         "config": {"workload": "room 6x5x3 m, 200k Gaussians, 52 plain classes, 1 view 1200x680, 3-level pyramid",
                    "gaussians": sc.n, "classes": sc.n_classes, "pixels_per_step": c["pixels"], "items": c["items"],
                    "duplicates": c["dup"], "visible_item_gaussians": c["visible"], "pairs_iterated": c["pairs"],
-                   "semantic_mode": "plain", "render_variant": args.variant, "ssim_lambda": args.ssim_lambda},
+                   "semantic_mode": "plain", "render_variant": args.variant, "ssim_lambda": args.ssim_lambda,
+                   "sh_degrees": list(sh) if sh else None},
         "timed": "eager calls" if args.eager else "HIP graph replay of the whole step",
         "eager_ms_per_step": m["eager_ms"], "stage_ms": m["stage_ms"],
         "hbm_gbs_effective": algorithmic_bytes(c, sc.n_classes) / (ms * 1e-3) / 1e9,
@@ -432,6 +459,8 @@ def main():
         out["with_ssim"] = ssim_report(args, dev, sc, views, targets, ms, m["stage_ms"]["loss"])
         torch.cuda.empty_cache()
         out["isotropic_primitive"] = isotropic_report(args, dev, sc, views, targets)
+        torch.cuda.empty_cache()
+        out["sh_features"] = sh_report(args, dev, sc, views, targets)
         torch.cuda.empty_cache()
         out["batch"] = batch_report(args, dev)
         torch.cuda.empty_cache()

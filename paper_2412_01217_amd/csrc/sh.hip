@@ -98,6 +98,16 @@ __device__ __forceinline__ void sh_grad_dot(float x, float y, float z, int deg, 
   gy += -kC3a * (-6.0f * x * y) * a[15];
 }
 
+// Lane mapping of both kernels: each Gaussian takes an aligned group of `gsz` lanes (the
+// channel count 3 + n_sem <= 63 rounded up to a power of two), its channels on consecutive
+// lanes, so loads and stores of a Gaussian's channels are contiguous and a reduction over
+// them is a butterfly within the group.
+__device__ __forceinline__ int group_size(int ct) {
+  int g = 1;
+  while (g < ct) g <<= 1;
+  return g;
+}
+
 constexpr int kViewChunk = 256;   // camera centres staged in LDS per pass over the views
 
 __device__ __forceinline__ void stage_centres(const gs_view* __restrict__ views, int v0, int nv, float* s_c) {
@@ -133,11 +143,12 @@ __device__ __forceinline__ ShChan sh_chan(const gs_gaussians& g, const gs_sh& sh
 __global__ __launch_bounds__(256) void k_sh_fwd(gs_gaussians g, gs_sh sh, int n_sem, const gs_view* __restrict__ views,
                                                 int n_views, float* __restrict__ rgb_out, float* __restrict__ sem_out) {
   __shared__ float s_c[3 * kViewChunk];
-  const int Ct = 3 + n_sem;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = t < g.n * Ct;
-  const int64_t i = live ? t / Ct : 0;
-  const int c = live ? (int)(t - i * Ct) : 0;
+  const int Ct = 3 + n_sem, gsz = group_size(Ct);
+  const int64_t i0 = (int64_t)blockIdx.x * (256 / gsz) + threadIdx.x / gsz;
+  const int c0 = (int)(threadIdx.x % gsz);
+  const bool live = i0 < g.n && c0 < Ct;
+  const int64_t i = live ? i0 : 0;
+  const int c = live ? c0 : 0;
   ShChan h{};
   float coef[16];
   float mx = 0.0f, my = 0.0f, mz = 0.0f;
@@ -175,128 +186,175 @@ __global__ __launch_bounds__(256) void k_sh_fwd(gs_gaussians g, gs_sh sh, int n_
   }
 }
 
-// Constant band and coefficients: sums over views of the feature gradient (times Y_j).
-__global__ __launch_bounds__(256) void k_sh_bwd_coef(gs_gaussians g, gs_sh sh, int n_sem,
-                                                     const gs_view* __restrict__ views, int n_views,
-                                                     const float* __restrict__ grgb, const float* __restrict__ gsem,
-                                                     float* __restrict__ gdc_rgb, float* __restrict__ grest_rgb,
-                                                     float* __restrict__ gdc_sem, float* __restrict__ grest_sem) {
-  __shared__ float s_c[3 * kViewChunk];
-  const int Ct = 3 + n_sem;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = t < g.n * Ct;
-  const int64_t i = live ? t / Ct : 0;
-  const int c = live ? (int)(t - i * Ct) : 0;
+// The backward, one lane per (Gaussian, channel), persistent blocks of 256 lanes walking the
+// Gaussians: the constant band and the bands sum the feature gradient (times Y_j) over views;
+// the channel's share of d L/d d, g_c sum_j k_jc dY_j/dd, goes through the normalisation
+// (linear, so channels can be summed in any order) to the mean, summed over the Gaussian's
+// lane group by a butterfly, and to the pose's rho (gpose[v][0..2] += R_v sum). Views are
+// taken kPoseViews at a time: each lane keeps that many rho sums in registers over all its
+// Gaussians, so a block adds to each pose once per chunk (a grid of few blocks keeps those
+// same-address atomics few). The bands of a later chunk are added to the first chunk's.
+constexpr int kPoseViews = 4;
+constexpr int kShBwdThreads = 256;
+
+// What one lane reads for one Gaussian: its channel's bands, the mean, the feature gradient
+// of each view of the chunk.
+struct ShIn {
+  float coef[16];
+  float m[3];
+  float gm0[3];   // the mean gradient so far (read by the lane that adds to it, the only writer)
+  float gf[kPoseViews];
+};
+
+__device__ __forceinline__ void sh_load(const gs_gaussians& g, const gs_sh& sh, int n_sem, int64_t i, int c, bool live,
+                                        int v0, int nv, const float* __restrict__ grgb,
+                                        const float* __restrict__ gsem, const float* gmean, ShIn& in) {
   const bool rgb = c < 3;
-  const int deg = rgb ? sh.rgb_degree : sh.sem_degree;
-  const int nk = (deg + 1) * (deg + 1);
-  float acc[16];
-  for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
-  const float mx = live ? g.mean[3 * i] : 0.0f, my = live ? g.mean[3 * i + 1] : 0.0f;
-  const float mz = live ? g.mean[3 * i + 2] : 0.0f;
-  for (int v0 = 0; v0 < n_views; v0 += kViewChunk) {
-    const int nv = min(kViewChunk, n_views - v0);
-    __syncthreads();
-    stage_centres(views, v0, nv, s_c);
-    __syncthreads();
-    if (!live) continue;
-    for (int k = 0; k < nv; ++k) {
-      const int64_t v = v0 + k;
-      const float gf = rgb ? grgb[(v * g.n + i) * 3 + c] : gsem[(v * g.n + i) * n_sem + (c - 3)];
-      acc[0] += gf;
-      if (deg > 0) {
-        const float ux = mx - s_c[3 * k], uy = my - s_c[3 * k + 1], uz = mz - s_c[3 * k + 2];
-        const float ir = rsqrtf(ux * ux + uy * uy + uz * uz);
-        float Y[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) Y[j] = 0.0f;
-        sh_basis(ux * ir, uy * ir, uz * ir, deg, Y);
-#pragma unroll
-        for (int j = 1; j < 16; ++j) acc[j] = fmaf(Y[j], gf, acc[j]);
-      }
-    }
-  }
-  if (!live) return;
   const int ch = rgb ? 3 : n_sem, kc = rgb ? c : c - 3;
-  float* gdc = rgb ? gdc_rgb : gdc_sem;
-  float* grest = rgb ? grest_rgb : grest_sem;
-  if (gdc) gdc[(int64_t)ch * i + kc] = acc[0];
-  if (deg > 0 && grest) {
+  const int deg = rgb ? sh.rgb_degree : sh.sem_degree;
+  const int K = (deg + 1) * (deg + 1);
+  const float* rest = rgb ? sh.rgb_rest : sh.sem_rest;
+  const float* r = (live && deg > 0) ? rest + (int64_t)i * (K - 1) * ch + kc : nullptr;
 #pragma unroll
-    for (int j = 1; j < 16; ++j)
-      if (j < nk) grest[((int64_t)i * (nk - 1) + (j - 1)) * ch + kc] = acc[j];
+  for (int j = 0; j < 16; ++j) in.coef[j] = (r && j >= 1 && j < K) ? r[(int64_t)(j - 1) * ch] : 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) in.m[a] = live ? g.mean[3 * i + a] : 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) in.gm0[a] = (live && c == 0 && gmean) ? gmean[3 * i + a] : 0.0f;
+#pragma unroll
+  for (int k = 0; k < kPoseViews; ++k) {
+    const int64_t v = v0 + k;
+    in.gf[k] = (live && k < nv) ? (rgb ? grgb[(v * g.n + i) * 3 + c] : gsem[(v * g.n + i) * n_sem + kc]) : 0.0f;
   }
 }
 
-// Direction: d L/d d = sum_c g_c sum_j k_jc dY_j/dd, through the normalisation to the mean
-// (added to gmean) and, summed over the block, to the pose's rho (gpose[v][0..2] += R_v sum).
-__global__ __launch_bounds__(256) void k_sh_bwd_dir(gs_gaussians g, gs_sh sh, int n_sem,
-                                                    const gs_view* __restrict__ views, int n_views,
-                                                    const float* __restrict__ grgb, const float* __restrict__ gsem,
-                                                    float* __restrict__ gmean, float* __restrict__ gpose) {
-  __shared__ double red[4][3];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = i < g.n;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const float mx = live ? g.mean[3 * i] : 0.0f, my = live ? g.mean[3 * i + 1] : 0.0f;
-  const float mz = live ? g.mean[3 * i + 2] : 0.0f;
-  double am[3] = {0, 0, 0};
-  const int nkr = (sh.rgb_degree + 1) * (sh.rgb_degree + 1) - 1, nks = (sh.sem_degree + 1) * (sh.sem_degree + 1) - 1;
-  for (int v = 0; v < n_views; ++v) {
-    const gs_view V = views[v];
-    double gu[3] = {0, 0, 0};
-    if (live) {
-      float cc[3];
-      for (int a = 0; a < 3; ++a) cc[a] = -(V.R[a] * V.t[0] + V.R[3 + a] * V.t[1] + V.R[6 + a] * V.t[2]);
-      const float ux = mx - cc[0], uy = my - cc[1], uz = mz - cc[2];
-      const float ir = rsqrtf(ux * ux + uy * uy + uz * uz);
-      const float dx = ux * ir, dy = uy * ir, dz = uz * ir;
-      float gd[3] = {0.0f, 0.0f, 0.0f};
-      for (int part = 0; part < 2; ++part) {
-        const int deg = part == 0 ? sh.rgb_degree : sh.sem_degree;
-        if (deg == 0) continue;
-        const int ch = part == 0 ? 3 : n_sem, nk = part == 0 ? nkr : nks;
-        const float* rest = (part == 0 ? sh.rgb_rest : sh.sem_rest) + (int64_t)i * nk * ch;
-        const float* gf = part == 0 ? grgb + ((int64_t)v * g.n + i) * 3 : gsem + ((int64_t)v * g.n + i) * n_sem;
-        float a[16];
+__global__ __launch_bounds__(kShBwdThreads) void k_sh_bwd(gs_gaussians g, gs_sh sh, int n_sem,
+                                                          const gs_view* __restrict__ views, int n_views,
+                                                          const float* __restrict__ grgb,
+                                                          const float* __restrict__ gsem, float* __restrict__ gdc_rgb,
+                                                          float* __restrict__ grest_rgb, float* __restrict__ gdc_sem,
+                                                          float* __restrict__ grest_sem, float* __restrict__ gmean,
+                                                          float* __restrict__ gpose) {
+  __shared__ double red[kShBwdThreads / 64][3 * kPoseViews];
+  const int Ct = 3 + n_sem, gsz = group_size(Ct);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int per_block = kShBwdThreads / gsz;          // Gaussians per block and pass
+  const int64_t step = (int64_t)gridDim.x * per_block;
+  const int c0 = tid % gsz;
+  const int c = c0 < Ct ? c0 : 0;
+  const bool rgb = c < 3;
+  const int ch = rgb ? 3 : n_sem, kc = rgb ? c : c - 3;
+  const int deg = rgb ? sh.rgb_degree : sh.sem_degree;
+  const int nk = (deg + 1) * (deg + 1);
+  const bool any_dir = sh.rgb_degree > 0 || sh.sem_degree > 0;
+  for (int v0 = 0; v0 < n_views; v0 += kPoseViews) {
+    const int nv = min(kPoseViews, n_views - v0);
+    float pr[kPoseViews][3];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) a[j] = 0.0f;
-        for (int k = 0; k < ch; ++k) {
-          const float gk = gf[k];
-          if (gk == 0.0f) continue;
+    for (int k = 0; k < kPoseViews; ++k) pr[k][0] = pr[k][1] = pr[k][2] = 0.0f;
+    float Rv[kPoseViews][9], cv[kPoseViews][3];   // the chunk's rotations and camera centres
 #pragma unroll
-          for (int j = 1; j < 16; ++j)
-            if (j <= nk) a[j] = fmaf(gk, rest[(j - 1) * ch + k], a[j]);
-        }
-        float gx, gy, gz;
-        sh_grad_dot(dx, dy, dz, deg, a, gx, gy, gz);
-        gd[0] += gx;
-        gd[1] += gy;
-        gd[2] += gz;
+    for (int k = 0; k < kPoseViews; ++k) {
+      const gs_view V = views[v0 + min(k, nv - 1)];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) Rv[k][e] = V.R[e];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) cv[k][a] = -(V.R[a] * V.t[0] + V.R[3 + a] * V.t[1] + V.R[6 + a] * V.t[2]);
+    }
+    int64_t gb = (int64_t)blockIdx.x * per_block;
+    ShIn cur;
+    {
+      const int64_t i0 = gb + tid / gsz;
+      const bool live = i0 < g.n && c0 < Ct;
+      sh_load(g, sh, n_sem, live ? i0 : 0, c, live && c0 < Ct, v0, nv, grgb, gsem, any_dir ? gmean : nullptr, cur);
+    }
+    for (; gb < g.n; gb += step) {
+      const int64_t i0 = gb + tid / gsz;
+      const bool live = i0 < g.n && c0 < Ct;
+      const int64_t i = live ? i0 : 0;
+      ShIn nxt;                               // the next Gaussian's inputs, in flight meanwhile
+      {
+        const int64_t j0 = gb + step + tid / gsz;
+        const bool nlive = j0 < g.n && c0 < Ct;
+        sh_load(g, sh, n_sem, nlive ? j0 : 0, c, nlive, v0, nv, grgb, gsem, any_dir ? gmean : nullptr, nxt);
       }
-      const float dd = dx * gd[0] + dy * gd[1] + dz * gd[2];
-      gu[0] = (double)((gd[0] - dx * dd) * ir);
-      gu[1] = (double)((gd[1] - dy * dd) * ir);
-      gu[2] = (double)((gd[2] - dz * dd) * ir);
-      for (int a = 0; a < 3; ++a) am[a] += gu[a];
+      float acc[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+      float gm[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int k = 0; k < kPoseViews; ++k) {
+        const float gf = cur.gf[k];
+        acc[0] += gf;
+        if (deg == 0 || gf == 0.0f) continue;
+        const float ux = cur.m[0] - cv[k][0], uy = cur.m[1] - cv[k][1], uz = cur.m[2] - cv[k][2];
+        const float ir = rsqrtf(ux * ux + uy * uy + uz * uz);
+        const float dx = ux * ir, dy = uy * ir, dz = uz * ir;
+        float Y[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) Y[j] = 0.0f;
+        sh_basis(dx, dy, dz, deg, Y);
+#pragma unroll
+        for (int j = 1; j < 16; ++j) acc[j] = fmaf(Y[j], gf, acc[j]);
+        float gx, gy, gz;   // sum_j k_jc dY_j/dd, times g_c below (linear in g_c)
+        sh_grad_dot(dx, dy, dz, deg, cur.coef, gx, gy, gz);
+        const float dd = dx * gx + dy * gy + dz * gz;
+        const float gi = gf * ir;
+        const float u0 = (gx - dx * dd) * gi, u1 = (gy - dy * dd) * gi, u2 = (gz - dz * dd) * gi;
+        gm[0] += u0;
+        gm[1] += u1;
+        gm[2] += u2;
+        // rho: R_v (d L/d mu), the camera centre -R^T t moving by -R^T rho
+        pr[k][0] += Rv[k][0] * u0 + Rv[k][1] * u1 + Rv[k][2] * u2;
+        pr[k][1] += Rv[k][3] * u0 + Rv[k][4] * u1 + Rv[k][5] * u2;
+        pr[k][2] += Rv[k][6] * u0 + Rv[k][7] * u1 + Rv[k][8] * u2;
+      }
+      if (live) {
+        float* gdc = rgb ? gdc_rgb : gdc_sem;
+        float* grest = rgb ? grest_rgb : grest_sem;
+        // the first chunk of views stores, later chunks add (no read before the first store)
+        if (gdc) {
+          float* o = gdc + (int64_t)ch * i + kc;
+          if (v0 == 0) *o = acc[0];
+          else *o += acc[0];
+        }
+        if (deg > 0 && grest) {
+          float* o = grest + (int64_t)i * (nk - 1) * ch + kc;
+          if (v0 == 0) {
+#pragma unroll
+            for (int j = 1; j < 16; ++j)
+              if (j < nk) o[(int64_t)(j - 1) * ch] = acc[j];
+          } else {
+#pragma unroll
+            for (int j = 1; j < 16; ++j)
+              if (j < nk) o[(int64_t)(j - 1) * ch] += acc[j];
+          }
+        }
+      }
+      if (any_dir) {   // the mean's share over the Gaussian's channels, added by the group's first lane
+        for (int o = 1; o < gsz; o <<= 1)
+          for (int k = 0; k < 3; ++k) gm[k] += __shfl_xor(gm[k], o, 64);
+        if (live && c0 == 0)
+          for (int k = 0; k < 3; ++k) gmean[3 * i + k] = cur.gm0[k] + gm[k];
+      }
+      cur = nxt;
     }
-    // pose: c_v = -R^T t moves by -R^T rho, so d L/d rho = R sum_i d L/d mu (direction part)
-    for (int a = 0; a < 3; ++a) {
-      const double s = wave_sum_d(gu[a]);
-      if (lane == 0) red[wid][a] = s;
+    if (any_dir) {   // the chunk's rho sums: one block reduction, one atomic per (view, component)
+#pragma unroll
+      for (int k = 0; k < kPoseViews; ++k)
+        for (int a = 0; a < 3; ++a) {
+          const double sum = wave_sum_d((double)pr[k][a]);
+          if (lane == 0) red[wid][3 * k + a] = sum;
+        }
+      __syncthreads();
+      if (tid < 3 * nv) {
+        double S = 0.0;
+        for (int w = 0; w < kShBwdThreads / 64; ++w) S += red[w][tid];
+        if (S != 0.0) atomicAdd(gpose + 6 * (v0 + tid / 3) + tid % 3, (float)S);
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-      double S[3];
-      for (int a = 0; a < 3; ++a) S[a] = red[0][a] + red[1][a] + red[2][a] + red[3][a];
-      const int r = threadIdx.x;
-      const double p = V.R[3 * r] * S[0] + V.R[3 * r + 1] * S[1] + V.R[3 * r + 2] * S[2];
-      if (p != 0.0) atomicAdd(gpose + 6 * v + r, (float)p);
-    }
-    __syncthreads();
   }
-  if (!live) return;
-  for (int a = 0; a < 3; ++a) gmean[3 * i + a] += (float)am[a];
 }
 
 }  // namespace
@@ -305,21 +363,29 @@ int launch_sh_fwd(const gs_gaussians& g, const gs_sh& sh, int n_sem, const gs_vi
                   float* sem_out, hipStream_t s) {
   const int64_t work = g.n * (3 + n_sem);
   if (work == 0 || n_views == 0) return GS_OK;
-  hipLaunchKernelGGL(k_sh_fwd, dim3((unsigned)ceil_div(work, 256)), dim3(256), 0, s, g, sh, n_sem, views, n_views,
-                     rgb_out, sem_out);
+  int gsz = 1;
+  while (gsz < 3 + n_sem) gsz <<= 1;
+  hipLaunchKernelGGL(k_sh_fwd, dim3((unsigned)ceil_div(g.n, 256 / gsz)), dim3(256), 0, s, g, sh, n_sem, views,
+                     n_views, rgb_out, sem_out);
   return launch_status();
 }
 
 int launch_sh_bwd(const gs_gaussians& g, const gs_sh& sh, int n_sem, const gs_view* views, int n_views,
                   const float* grgb, const float* gsem, float* gdc_rgb, float* grest_rgb, float* gdc_sem,
                   float* grest_sem, float* gmean, float* gpose, hipStream_t s) {
-  const int64_t work = g.n * (3 + n_sem);
-  if (work == 0) return GS_OK;
-  hipLaunchKernelGGL(k_sh_bwd_coef, dim3((unsigned)ceil_div(work, 256)), dim3(256), 0, s, g, sh, n_sem, views, n_views,
-                     grgb, gsem, gdc_rgb, grest_rgb, gdc_sem, grest_sem);
-  if ((sh.rgb_degree > 0 || sh.sem_degree > 0) && n_views > 0)
-    hipLaunchKernelGGL(k_sh_bwd_dir, dim3((unsigned)ceil_div(g.n, 256)), dim3(256), 0, s, g, sh, n_sem, views, n_views,
-                       grgb, gsem, gmean, gpose);
+  if (g.n == 0 || n_views == 0) return GS_OK;
+  int gsz = 1;
+  while (gsz < 3 + n_sem) gsz <<= 1;
+  // a few blocks per CU: enough lanes in flight, few same-address atomics on the poses
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+  }
+  const int64_t blocks = std::min<int64_t>(ceil_div(g.n, kShBwdThreads / gsz), 4 * (int64_t)cus);
+  hipLaunchKernelGGL(k_sh_bwd, dim3((unsigned)blocks), dim3(kShBwdThreads), 0, s, g, sh, n_sem, views, n_views, grgb,
+                     gsem, gdc_rgb, grest_rgb, gdc_sem, grest_sem, gmean, gpose);
   return launch_status();
 }
 

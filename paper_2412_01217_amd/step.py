@@ -3,7 +3,9 @@ buffer allocated up front, so that it can be replayed eagerly or as a HIP graph.
 
 run(): projection -> binning -> compositing -> per-level loss -> backward, all items
        of the frame, through the C ABI on the current torch stream. With a head
-       (learned mode) the loss's semantic term acts on the decoded logits.
+       (learned mode) the loss's semantic term acts on the decoded logits. With SH bands
+       (`sh`), the per-view features are evaluated after the projection and the backward
+       ends with their gradients (to the bands in `sh_grads`, to means and poses in place).
 """
 from __future__ import annotations
 
@@ -15,8 +17,15 @@ from . import raster
 
 class MappingStep:
     def __init__(self, cfg, frame: raster.Frame, g: dict, targets: dict, n_classes: int, w=(1.0, 1.0, 1.0),
-                 capacity_margin=1.15, head: dict | None = None, split=True):
+                 capacity_margin=1.15, head: dict | None = None, split=True, sh: dict | None = None):
+        if sh is not None and not cfg.view_features:
+            raise ValueError("SH features need a config with view_features = 1")
         self.cfg, self.frame, self.g, self.targets = cfg, frame, g, targets
+        self.sh = sh
+        self.feats = raster.sh_features(g, sh, frame) if sh is not None else None
+        self.sh_grads = None
+        # the render reads the per-view feature blocks in place of the constant bands
+        self.g_render = dict(g, rgb=self.feats["rgb"], sem=self.feats["sem"]) if sh is not None else g
         self.n_classes = n_classes
         self.head = head
         self.w = tuple(float(x) for x in w)
@@ -38,6 +47,12 @@ class MappingStep:
         self.loss_ws = torch.empty(raster.workspace_bytes(L.GS_WS_LOSS, cfg, frame, n), dtype=torch.uint8,
                                    device=dev)
         self.grads = raster.alloc_grads(cfg, g, frame, n_classes)
+        if sh is not None:
+            z = lambda t: None if t is None else torch.empty_like(t)  # noqa: E731
+            S = cfg.n_sem
+            self.sh_grads = dict(rgb_dc=torch.empty(n, 3, device=dev),
+                                 sem_dc=torch.empty(n, S, device=dev) if S else None,
+                                 rgb_rest=z(sh.get("rgb_rest")), sem_rest=z(sh.get("sem_rest")))
         self.bwd_ws = torch.empty(raster.workspace_bytes(L.GS_WS_RENDER_BWD, cfg, frame, n, self.sorter.capacity),
                                   dtype=torch.uint8,
                                   device=dev)
@@ -46,20 +61,25 @@ class MappingStep:
         """Enqueue one step. ev: optional list of 5 torch events recorded between the calls."""
         cfg, fr, g = self.cfg, self.frame, self.g
         raster.preprocess_into(cfg, g, fr, self.proj)
+        if self.sh is not None:
+            raster.sh_features(g, self.sh, fr, out=self.feats)
+        gr = self.g_render
         if ev:
             ev[0].record()
         self.sorter.run(self.proj)
         if ev:
             ev[1].record()
-        raster.render_fwd(cfg, g, self.proj, fr, self.sorter, out=self.img, head=self.head)
+        raster.render_fwd(cfg, gr, self.proj, fr, self.sorter, out=self.img, head=self.head)
         if ev:
             ev[2].record()
         raster.loss(cfg, fr, self.n_classes, self.img, self.targets, w=self.w, grad=self.grad, loss_out=self.loss,
                     ws=self.loss_ws)
         if ev:
             ev[3].record()
-        raster.render_bwd(cfg, g, self.proj, fr, self.sorter, self.img, self.grad, grads=self.grads, ws=self.bwd_ws,
+        raster.render_bwd(cfg, gr, self.proj, fr, self.sorter, self.img, self.grad, grads=self.grads, ws=self.bwd_ws,
                           head=self.head)
+        if self.sh is not None:
+            raster.sh_features_bwd(g, self.sh, fr, self.grads, out=self.sh_grads)
         if ev:
             ev[4].record()
 

@@ -14,18 +14,26 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def _step(variant=0, fwd_chunk=1, ssim_lambda=0.0):
+def _step(variant=0, fwd_chunk=1, ssim_lambda=0.0, sh_degree=0):
     from paper_2412_01217_amd import raster
     from paper_2412_01217_amd.step import MappingStep
     sc = scenes.room_scene(n=8000, n_classes=10, seed=1200, log_mu=-3.6)
     views = scenes.room_views(sc, 2, 160, 96, levels=2, seed=2200)
-    cfg = raster.config(10, variant=variant, fwd_chunk=fwd_chunk, ssim_lambda=ssim_lambda)
+    cfg = raster.config(10, variant=variant, fwd_chunk=fwd_chunk, ssim_lambda=ssim_lambda,
+                        view_features=int(sh_degree > 0))
     fr = raster.Frame(cfg, views)
     g = raster.to_device(sc)
     t_rgb, t_depth, t_lab = targets_from_random(views, 10, seed=4002)
     T = dict(rgb=torch.from_numpy(t_rgb).cuda(), depth=torch.from_numpy(t_depth).cuda(),
              label=torch.from_numpy(t_lab).cuda())
-    return MappingStep(cfg, fr, g, T, 10)
+    sh = None
+    if sh_degree:
+        rng = np.random.default_rng(2300)
+        K = (sh_degree + 1) ** 2 - 1
+        sh = dict(rgb_degree=sh_degree, sem_degree=1,
+                  rgb_rest=torch.tensor(rng.normal(size=(sc.n, K, 3)) * 0.2, dtype=torch.float32, device="cuda"),
+                  sem_rest=torch.tensor(rng.normal(size=(sc.n, 3, 10)) * 0.2, dtype=torch.float32, device="cuda"))
+    return MappingStep(cfg, fr, g, T, 10, sh=sh)
 
 
 def _snapshot(st):
@@ -35,20 +43,24 @@ def _snapshot(st):
     for k, v in st.grads.items():
         if v is not None:
             out["g_" + k] = v.clone()
+    for k, v in (st.sh_grads or {}).items():
+        if v is not None:
+            out["g_sh_" + k] = v.clone()
     return out
 
 
-@pytest.mark.parametrize("variant,fwd_chunk,ssim_lambda", [(1, 1, 0.0), (2, 1, 0.0), (3, 1, 0.0), (3, 0, 0.0),
-                                                            (3, 1, 0.2)])
-def test_graph_replays_match_eager(variant, fwd_chunk, ssim_lambda):
-    st = _step(variant, fwd_chunk, ssim_lambda)
+@pytest.mark.parametrize("variant,fwd_chunk,ssim_lambda,sh_degree", [(1, 1, 0.0, 0), (2, 1, 0.0, 0), (3, 1, 0.0, 0),
+                                                                      (3, 0, 0.0, 0), (3, 1, 0.2, 0), (3, 1, 0.0, 3)])
+def test_graph_replays_match_eager(variant, fwd_chunk, ssim_lambda, sh_degree):
+    st = _step(variant, fwd_chunk, ssim_lambda, sh_degree)
     st.run()
     torch.cuda.synchronize()
     assert not st.overflowed()
     ref = _snapshot(st)
     graph = st.capture()
     for rep in range(3):
-        for t in (st.img["color"], st.img["T"], st.grad["color"], *[v for v in st.grads.values() if v is not None]):
+        for t in (st.img["color"], st.img["T"], st.grad["color"], *[v for v in st.grads.values() if v is not None],
+                  *[v for v in (st.sh_grads or {}).values() if v is not None]):
             t.fill_(float("nan"))
         st.sorter.vals.fill_(-1)
         torch.cuda.synchronize()
