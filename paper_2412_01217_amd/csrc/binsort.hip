@@ -125,6 +125,53 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* __r
   }
 }
 
+// Two-kernel form for inputs of up to kDirectTiles tiles: each apply block sums the tile
+// totals before it itself (at most kDirectTiles loads over 256 threads), so the single-block
+// scan of the partials between the two passes, a launch bound by latency, is not needed.
+// Block 0 also sums all of them for the total.
+constexpr int64_t kDirectTiles = 2048;
+
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* sh /*[4]*/) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const uint64_t t = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply_direct(const uint32_t* __restrict__ in,
+                                                                     const uint64_t* count_dev, int64_t count_host,
+                                                                     const uint32_t* __restrict__ partial,
+                                                                     uint32_t* __restrict__ out, uint64_t* total_out) {
+  const int64_t count = count_dev ? (int64_t)*count_dev : count_host;
+  const int64_t np = min((int64_t)gridDim.x, (count + kScanTile - 1) / kScanTile);
+  const int64_t lim = blockIdx.x == 0 ? np : min((int64_t)blockIdx.x, np);
+  uint64_t acc = 0;
+  for (int64_t j = threadIdx.x; j < lim; j += kScanThreads) acc += partial[j];
+  __shared__ uint64_t sh64[4];
+  const uint64_t pre = block_sum_u64(acc, sh64);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = pre;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= count) return;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+  const int64_t tb = base + (int64_t)threadIdx.x * kScanItems;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = tb + k;
+    v[k] = idx < count ? in[idx] : 0;
+    s += v[k];
+  }
+  __shared__ uint32_t sh[4];
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, total, sh) + (blockIdx.x == 0 ? 0u : (uint32_t)pre);
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = tb + k;
+    if (idx < count) out[idx] = run;
+    run += v[k];
+  }
+}
+
 // One workgroup scans inputs up to kOneMax elements in tiles of 16K (16 consecutive per
 // thread), carrying the running total and loading the next tile while scanning this one:
 // one launch instead of three, where launch latency rather than bandwidth sets the time
@@ -454,6 +501,11 @@ int device_scan(const uint32_t* in, uint32_t* out, const uint64_t* count_dev, in
   }
   const int64_t nb = std::max<int64_t>(1, ceil_div(cap_count, kScanTile));
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, count_dev, count_host, partial);
+  if (nb <= kDirectTiles) {
+    hipLaunchKernelGGL(k_scan_apply_direct, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, count_dev, count_host,
+                       partial, out, total);
+    return launch_status();
+  }
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partial, nb, count_dev, count_host, total);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, count_dev, count_host, partial, out);
   return launch_status();
