@@ -206,7 +206,7 @@ __device__ __forceinline__ bool seek_chunk(const gs_item* __restrict__ items, in
 // The accumulators are summed over the block's waves in LDS once at the end and written
 // as one partial per block; k_head_reduce adds the partials.
 constexpr int kGst = 65;   // LDS row stride of the staged logit gradients
-__global__ __launch_bounds__(256, 2) void k_head_bwd(const gs_item* __restrict__ items, int n_items, int K, int C,
+__global__ __launch_bounds__(256, 1) void k_head_bwd(const gs_item* __restrict__ items, int n_items, int K, int C,
                                                      const float* __restrict__ color,
                                                      const float* __restrict__ glogits,
                                                      const uint16_t* __restrict__ W1, const float* __restrict__ b1,
@@ -261,11 +261,16 @@ __global__ __launch_bounds__(256, 2) void k_head_bwd(const gs_item* __restrict__
     float* dEb = gcolor + it.pixel_base * K + 4 * HW + local0;
     {
       // stage: lane = pixel, one coalesced row per class; dead pixels are zero
+      // (16 rows' loads in flight per round trip)
       const bool live = lane < nlive;
       const float* g = glogits + it.pixel_base * C + local0 + min(lane, nlive - 1);
-      for (int c = 0; c < C; ++c) {
-        const float v = g[(int64_t)c * HW];
-        sg[c * kGst + lane] = live ? v : 0.0f;
+      for (int c0 = 0; c0 < C; c0 += 16) {
+        float v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = c0 + k < C ? g[(int64_t)(c0 + k) * HW] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (c0 + k < C) sg[(c0 + k) * kGst + lane] = live ? v[k] : 0.0f;
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -521,8 +526,19 @@ int launch_head_bwd(const gs_item* items, int n_items, int64_t P, int K, const g
                     const float* glogits, float* gcolor, float* partial, float* gW1, float* gb1, float* gW2, float* gb2,
                     hipStream_t s) {
   if (P == 0) return GS_OK;
-  // at most one 64-pixel chunk per item is partial, so P / 64 + n_items bounds the chunk count
-  const int blocks = (int)std::min<int64_t>(kHeadBlocksMax, ceil_div(ceil_div(P, 64) + n_items, 4));
+  // at most one 64-pixel chunk per item is partial, so P / 64 + n_items bounds the chunk count;
+  // the blocks walk the chunks grid-stride, so the grid is the resident count (one wave per
+  // SIMD: the register file holds the weight-gradient accumulators without spilling)
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_head_bwd, 256, 0) == hipSuccess)
+      resident = std::max(1, cus * std::max(1, per));
+    else
+      resident = kHeadBlocksMax;
+  }
+  const int blocks = (int)std::min<int64_t>(std::min(kHeadBlocksMax, resident), ceil_div(ceil_div(P, 64) + n_items, 4));
   hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(256), 0, s, items, n_items, K, h.n_classes, color, glogits, h.W1,
                      h.b1, h.W2, gcolor, partial);
   hipLaunchKernelGGL(k_head_reduce, dim3((unsigned)ceil_div(kPart, 64)), dim3(256), 0, s, partial, blocks, h.n_classes,
