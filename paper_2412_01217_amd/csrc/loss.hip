@@ -65,6 +65,7 @@ __device__ __forceinline__ PixItem lane_item(const gs_item* __restrict__ items, 
 // issued before the arithmetic). The depth gradient is written as sign(d) (or 0) and
 // scaled by w1 / n_valid afterwards, once the valid counts are known; the logits of a
 // pixel are held in registers (CM >= classes).
+// Every input and output element is touched once: loads and stores are non-temporal.
 template <int CM>
 __global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items, int n_items, int64_t P, int K,
                                               int n_classes, const float* __restrict__ color,
@@ -92,14 +93,14 @@ __global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items,
     const float* L = logits ? logits : color;
     float col[4], tr[3];
 #pragma unroll
-    for (int ch = 0; ch < 4; ++ch) col[ch] = color[cb + ch * HW];
+    for (int ch = 0; ch < 4; ++ch) col[ch] = __builtin_nontemporal_load(&color[cb + ch * HW]);
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) tr[ch] = trgb[tb + ch * HW];
-    const float td = tdepth[pix];
-    const int y = sem ? tlabel[pix] : -1;
+    for (int ch = 0; ch < 3; ++ch) tr[ch] = __builtin_nontemporal_load(&trgb[tb + ch * HW]);
+    const float td = __builtin_nontemporal_load(&tdepth[pix]);
+    const int y = sem ? __builtin_nontemporal_load(&tlabel[pix]) : -1;
     float x[CM > 0 ? CM : 1];
 #pragma unroll
-    for (int c = 0; c < CM; ++c) x[c] = c < n_classes ? L[lb + c * HW] : -INFINITY;
+    for (int c = 0; c < CM; ++c) x[c] = c < n_classes ? __builtin_nontemporal_load(&L[lb + c * HW]) : -INFINITY;
 
     const float inv3 = 1.0f / (3.0f * (float)HW);
     float gc[3];
@@ -118,9 +119,9 @@ __global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items,
     }
     if (rgb_grad) {   // else the SSIM pass writes the colour gradient
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) gcolor[cb + ch * HW] = gc[ch];
+      for (int ch = 0; ch < 3; ++ch) __builtin_nontemporal_store(gc[ch], &gcolor[cb + ch * HW]);
     }
-    gcolor[cb + 3 * HW] = gd;
+    __builtin_nontemporal_store(gd, &gcolor[cb + 3 * HW]);
     if (sem) {
       float* G = logits ? glogits + lb : gcolor + lb;
       float m = -INFINITY;
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items,
       const float oh = labelled ? w2 * invp : 0.0f;
 #pragma unroll
       for (int c = 0; c < CM; ++c)
-        if (c < n_classes) G[c * HW] = x[c] * sc - (c == y ? oh : 0.0f);
+        if (c < n_classes) __builtin_nontemporal_store(x[c] * sc - (c == y ? oh : 0.0f), &G[c * HW]);
     }
   }
   // wave-uniform item: one atomic per wave and quantity, else one per lane
