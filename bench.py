@@ -126,7 +126,43 @@ def measure(step, steps, warmup, graph=True):
     t1.record()
     torch.cuda.synchronize()
     assert not step.overflowed()
-    return dict(ms=t0.elapsed_time(t1) / steps, eager_ms=eager_ms, stage_ms=stage_ms)
+    ms = t0.elapsed_time(t1) / steps
+    # the spread of single replays, from a second set of `steps` replays with an event
+    # between every two (outside the timed region above)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    marks[0].record()
+    for k in range(steps):
+        run()
+        marks[k + 1].record()
+    torch.cuda.synchronize()
+    per = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(steps)])
+    spread = {"median": float(np.median(per)), "p90": float(np.percentile(per, 90)), "replays": steps}
+    return dict(ms=ms, eager_ms=eager_ms, stage_ms=stage_ms, step_ms_spread=spread)
+
+
+def gpu_clocks():
+    """The clock lines of `rocm-smi --showclocks` (a read-only query run as a child
+    process), or None."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=30)
+    except (OSError, subprocess.SubprocessError):
+        return None
+    lines = [ln.strip() for ln in r.stdout.splitlines() if "clk" in ln and ":" in ln]
+    return lines or None
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host that runs the CPU baseline."""
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
 
 
 def work_counts(step):
@@ -421,6 +457,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    clocks = gpu_clocks()   # queried before this process initialises the GPU
     import torch
     from paper_2412_01217_amd import scenes
     dev = "cuda:0"
@@ -448,10 +485,11 @@ def main():
                    "semantic_mode": "plain", "render_variant": args.variant, "ssim_lambda": args.ssim_lambda,
                    "sh_degrees": list(sh) if sh else None},
         "timed": "eager calls" if args.eager else "HIP graph replay of the whole step",
-        "eager_ms_per_step": m["eager_ms"], "stage_ms": m["stage_ms"],
+        "eager_ms_per_step": m["eager_ms"], "step_ms_spread": m["step_ms_spread"], "stage_ms": m["stage_ms"],
         "hbm_gbs_effective": algorithmic_bytes(c, sc.n_classes) / (ms * 1e-3) / 1e9,
         "roofline": roof, "roofline_other": other,
     }
+    out["gpu_clocks_at_start"] = clocks
     out["mapping_update"] = adam_report(step, args.steps)
     del step
     torch.cuda.empty_cache()
@@ -468,6 +506,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, views, targets, sc.n_classes)
+        out["cpu_baseline"]["host"] = host_cpu()
     print(json.dumps(out), flush=True)
 
 
