@@ -321,31 +321,24 @@ def large_report(args, device):
             "hbm_gbs_effective": algorithmic_bytes(c, 52, learned=True) / (m["ms"] * 1e-3) / 1e9}
 
 
-def cpu_baseline(sc, views, targets, C, budget_s=15.0):
-    """The FP64 oracle (single thread) on a bounded sample of the same workload:
-    forward + loss + backward restricted to a set of tiles of the first item."""
+def cpu_baseline(sc, views, targets, C, min_s=10.0):
+    """The FP64 oracle (single thread) on the whole room workload: forward + loss + backward
+    over every pixel of every pyramid level (7-15 s of one core per run), repeated until at
+    least min_s seconds have been timed."""
     import oracle
-    its = oracle.items(views)
     n_items, P, tiles = oracle.layout(views)
     tgt = {k: v.cpu().numpy() for k, v in targets.items()}
-    rng = np.random.default_rng(5050)
-    order = rng.permutation(its[0]["ntx"] * its[0]["nty"])
-    n_t = 4
-    while True:
-        mask = np.zeros(tiles, np.uint8)
-        mask[order[:n_t]] = 1
+    total, reps = 0.0, 0
+    while total < min_s:
         t0 = time.perf_counter()
-        r = oracle.render(oracle.Config(), sc, views, tile_mask=mask)
+        r = oracle.render(oracle.Config(), sc, views)
         _, gimg = oracle.loss(views, C, r["img"], tgt["rgb"], tgt["depth"], tgt["label"])
-        oracle.backward(oracle.Config(), sc, views, gimg, tile_mask=mask)
-        dt = time.perf_counter() - t0
-        px = int(min(n_t, len(order)) * 256)
-        if dt > budget_s / 3 or n_t >= len(order):
-            break
-        n_t = min(len(order), int(n_t * max(2.0, budget_s / 3 / max(dt, 1e-3))))
-    return dict(value=px / dt / 1e6, unit="MP/s", cores=1, kind="oracle",
-                sample=f"{min(n_t, len(order))} random 16x16 tiles of level 0 ({px} px); projection and "
-                       f"binning of all {sc.n} Gaussians at all {n_items} levels included; {dt:.1f} s")
+        oracle.backward(oracle.Config(), sc, views, gimg)
+        total += time.perf_counter() - t0
+        reps += 1
+    return dict(value=P * reps / total / 1e6, unit="MP/s", cores=1, kind="oracle",
+                sample=f"the whole workload ({n_items} levels, {tiles} tiles, {P} px), forward + loss + backward "
+                       f"including the projection and binning of all {sc.n} Gaussians; {reps} runs, {total:.1f} s")
 
 
 def adam_report(step, steps):
