@@ -27,6 +27,11 @@
 // Near-threshold decisions (alpha_min / alpha_max / t_min, z_near, the guard band,
 // rect and radius rounding) are flagged per pixel, and per Gaussian, so that a
 // single-precision implementation can be compared away from them.
+//
+// Items (view, level) are independent given the Gaussians, so the render and its backward
+// take one item at a time (project every Gaussian, bin and sort the item's tiles, composite,
+// chain the item's 2D gradients back to the parameters) and hold one item's projections at
+// once; with a tile mask, items without a masked tile are skipped.
 
 #include <algorithm>
 #include <cmath>
@@ -259,44 +264,42 @@ struct Scene {
   int n_views;
   const double* vd;
   std::vector<Item> items;
-  std::vector<std::vector<Proj>> proj;          // [item][gaussian]
-  std::vector<std::vector<uint32_t>> lists;     // [global tile] -> sorted Gaussian ids
+  // The item being processed: the projections of every Gaussian for it and its tiles'
+  // sorted lists. One item is held at a time, so the memory is that of one item.
+  int cur = -1;
+  std::vector<Proj> proj;                       // [gaussian]
+  std::vector<std::vector<uint32_t>> lists;     // [tile of item cur] -> sorted Gaussian ids
   int K() const { return 4 + c.S; }
 };
 
-void build(Scene& s, bool brute) {
-  int tiles = 0;
-  for (auto& it : s.items) tiles += it.ntx * it.nty;
-  s.proj.assign(s.items.size(), {});
-  s.lists.assign(tiles, {});
-  for (size_t k = 0; k < s.items.size(); ++k) {
-    const Item& it = s.items[k];
-    const double* Rv = s.vd + 16 * it.view;
-    s.proj[k].resize(s.g.n);
-    for (int64_t i = 0; i < s.g.n; ++i) {
-      Proj p = project(s.c, s.g, i, Rv, Rv + 9, it);
-      s.proj[k][i] = p;
-      if (!p.vis || brute) continue;
-      for (int ty = p.rect[1]; ty < p.rect[3]; ++ty)
-        for (int tx = p.rect[0]; tx < p.rect[2]; ++tx) s.lists[it.tile0 + ty * it.ntx + tx].push_back(uint32_t(i));
-    }
-    if (brute) continue;
-    for (int t = it.tile0; t < it.tile0 + it.ntx * it.nty; ++t) {
-      auto& L = s.lists[t];
-      const auto& P = s.proj[k];
-      std::sort(L.begin(), L.end(), [&](uint32_t a, uint32_t b) {
-        if (P[a].z32 != P[b].z32) return P[a].z32 < P[b].z32;
-        return a < b;
-      });
-    }
+// Projects every Gaussian for item k and, unless brute, bins and depth-sorts its tiles.
+void build_item(Scene& s, int k, bool brute) {
+  const Item& it = s.items[k];
+  const double* Rv = s.vd + 16 * it.view;
+  s.cur = k;
+  s.proj.assign(size_t(s.g.n), Proj());
+  s.lists.assign(size_t(it.ntx) * it.nty, {});
+  for (int64_t i = 0; i < s.g.n; ++i) {
+    Proj p = project(s.c, s.g, i, Rv, Rv + 9, it);
+    s.proj[i] = p;
+    if (!p.vis || brute) continue;
+    for (int ty = p.rect[1]; ty < p.rect[3]; ++ty)
+      for (int tx = p.rect[0]; tx < p.rect[2]; ++tx) s.lists[ty * it.ntx + tx].push_back(uint32_t(i));
   }
+  if (brute) return;
+  const auto& P = s.proj;
+  for (auto& L : s.lists)
+    std::sort(L.begin(), L.end(), [&](uint32_t a, uint32_t b) {
+      if (P[a].z32 != P[b].z32) return P[a].z32 < P[b].z32;
+      return a < b;
+    });
 }
 
-// The list a pixel iterates in brute-force mode: every Gaussian whose rect holds the
-// pixel's tile, in (float depth, index) order, found without tile lists.
-std::vector<uint32_t> brute_list(const Scene& s, int k, int tx, int ty) {
+// The list a pixel of the current item iterates in brute-force mode: every Gaussian whose
+// rect holds the pixel's tile, in (float depth, index) order, found without tile lists.
+std::vector<uint32_t> brute_list(const Scene& s, int tx, int ty) {
   std::vector<uint32_t> L;
-  const auto& P = s.proj[k];
+  const auto& P = s.proj;
   for (int64_t i = 0; i < s.g.n; ++i) {
     const Proj& p = P[i];
     if (p.vis && tx >= p.rect[0] && tx < p.rect[2] && ty >= p.rect[1] && ty < p.rect[3]) L.push_back(uint32_t(i));
@@ -320,10 +323,10 @@ struct Contrib {
 
 // Composites one pixel front to back; returns the contributions in order.
 // out[K] accumulates; Tfinal, ncontrib returned; flag set for near-threshold cases.
-void composite_pixel(const Scene& s, int k, const std::vector<uint32_t>& L, double px, double py,
+void composite_pixel(const Scene& s, const std::vector<uint32_t>& L, double px, double py,
                      std::vector<Contrib>& contrib, double* out, double& Tfinal, int& ncontrib, int& flag) {
   const Cfg& c = s.c;
-  const auto& P = s.proj[k];
+  const auto& P = s.proj;
   int K = s.K();
   std::vector<double> f(K);
   double T = 1.0;
@@ -371,22 +374,30 @@ void setup(Scene& s, const double* cd, const int* ci, int64_t n, const double* m
 
 
 // Visits every pixel of every item (optionally only the tiles whose mask byte is set),
-// composites it and calls fn(item, u, v, contributions, flag, out).
-template <class Fn>
-void for_each_pixel(const Scene& s, bool brute, const uint8_t* tile_mask, Fn&& fn) {
+// composites it and calls fn(item, u, v, contributions, flag, out). Items are taken one
+// at a time (projected, binned, composited); after an item's pixels, done(item) is called
+// while its projections are still held. An item with no tile in the mask is skipped.
+template <class Fn, class Done>
+void for_each_pixel(Scene& s, bool brute, const uint8_t* tile_mask, Fn&& fn, Done&& done) {
   int K = s.K();
   std::vector<Contrib> contrib;
   std::vector<double> out(K);
   for (size_t k = 0; k < s.items.size(); ++k) {
     const Item& it = s.items[k];
+    if (tile_mask) {
+      bool any = false;
+      for (int t = it.tile0; t < it.tile0 + it.ntx * it.nty && !any; ++t) any = tile_mask[t] != 0;
+      if (!any) continue;
+    }
+    build_item(s, int(k), brute);
     for (int ty = 0; ty < it.nty; ++ty)
       for (int tx = 0; tx < it.ntx; ++tx) {
         int tile = it.tile0 + ty * it.ntx + tx;
         if (tile_mask && !tile_mask[tile]) continue;
         std::vector<uint32_t> bl;
-        const std::vector<uint32_t>* L = &s.lists[tile];
+        const std::vector<uint32_t>* L = &s.lists[ty * it.ntx + tx];
         if (brute) {
-          bl = brute_list(s, int(k), tx, ty);
+          bl = brute_list(s, tx, ty);
           L = &bl;
         }
         for (int v = ty * s.c.th; v < std::min(it.H, (ty + 1) * s.c.th); ++v)
@@ -394,12 +405,13 @@ void for_each_pixel(const Scene& s, bool brute, const uint8_t* tile_mask, Fn&& f
             std::fill(out.begin(), out.end(), 0.0);
             double T;
             int ncontrib, flag = 0;
-            composite_pixel(s, int(k), *L, u + 0.5, v + 0.5, contrib, out.data(), T, ncontrib, flag);
+            composite_pixel(s, *L, u + 0.5, v + 0.5, contrib, out.data(), T, ncontrib, flag);
             for (auto& cb : contrib)
-              if (s.proj[k][cb.id].flag) flag |= 16;
+              if (s.proj[cb.id].flag) flag |= 16;
             fn(int(k), u, v, contrib, flag, out.data(), T, ncontrib);
           }
       }
+    done(int(k));
   }
 }
 
@@ -413,7 +425,7 @@ struct G2 {
 void project_backward(const Scene& s, int k, int64_t i, const G2& g2, double* gmean, double* glsc, double* gquat,
                       double* gopac, double* gpose) {
   const Item& it = s.items[k];
-  const Proj& p = s.proj[k][i];
+  const Proj& p = s.proj[i];     // item k is the one held
   const double* Rv = s.vd + 16 * it.view;
   double z = p.z, x = p.mc[0], y = p.mc[1];
   // opacity = sigmoid(a)
@@ -581,7 +593,6 @@ int or_render(const double* cd, const int* ci, int64_t n, const double* mean, co
               int* nblend) {
   Scene s;
   setup(s, cd, ci, n, mean, lsc, quat, opac, rgb, sem, n_views, vd, vi);
-  build(s, brute != 0);
   int K = s.K();
   for_each_pixel(s, brute != 0, tile_mask,
                  [&](int k, int u, int v, const std::vector<Contrib>& cb, int flag, const double* out, double T,
@@ -593,7 +604,8 @@ int or_render(const double* cd, const int* ci, int64_t n, const double* mean, co
                    ncontrib[it.pix0 + pix] = nc;
                    pflag[it.pix0 + pix] = flag;
                    if (nblend) nblend[it.pix0 + pix] = int(cb.size());
-                 });
+                 },
+                 [](int) {});
   return 0;
 }
 
@@ -608,19 +620,19 @@ int or_backward(const double* cd, const int* ci, int64_t n, const double* mean, 
                 int* gflag) {
   Scene s;
   setup(s, cd, ci, n, mean, lsc, quat, opac, rgb, sem, n_views, vd, vi);
-  build(s, false);
   int K = s.K(), S = s.c.S;
-  std::vector<std::vector<G2>> g2(s.items.size(), std::vector<G2>(size_t(n)));
+  std::vector<G2> g2;                    // [gaussian] of the item being processed
   std::vector<double> f(K), suffix(K), gp(K);
   for_each_pixel(s, false, tile_mask,
                  [&](int k, int u, int v, const std::vector<Contrib>& cb, int flag, const double*, double, int) {
                    const Item& it = s.items[k];
+                   if (g2.empty()) g2.assign(size_t(n), G2());
                    int64_t HW = int64_t(it.W) * it.H, pix = int64_t(v) * it.W + u;
                    for (int ch = 0; ch < K; ++ch) gp[ch] = gimg[it.pix0 * K + ch * HW + pix];
                    std::fill(suffix.begin(), suffix.end(), 0.0);
                    for (int q = int(cb.size()) - 1; q >= 0; --q) {
                      const Contrib& c = cb[q];
-                     const Proj& p = s.proj[k][c.id];
+                     const Proj& p = s.proj[c.id];
                      features(s, p, c.id, f.data());
                      double wgt = c.alpha * c.T;
                      double dalpha = 0;
@@ -629,7 +641,7 @@ int or_backward(const double* cd, const int* ci, int64_t n, const double* mean, 
                      for (int ch = 0; ch < K; ++ch) suffix[ch] += f[ch] * wgt;
                      for (int ch = 0; ch < 3; ++ch) grgb[3 * int64_t(c.id) + ch] += wgt * gp[ch];
                      for (int ch = 0; ch < S; ++ch) gsem[int64_t(S) * c.id + ch] += wgt * gp[4 + ch];
-                     G2& G = g2[k][c.id];
+                     G2& G = g2[c.id];
                      G.zf += wgt * gp[3];
                      if (c.araw < s.c.a_max) {
                        G.o += dalpha * c.G;
@@ -642,19 +654,23 @@ int or_backward(const double* cd, const int* ci, int64_t n, const double* mean, 
                      }
                      if (flag && gflag) gflag[c.id] = 1;
                    }
+                 },
+                 [&](int k) {
+                   // the item's 2D gradients back to the parameters and the pose, while its
+                   // projections are held (an item without pixels in the mask adds nothing)
+                   if (g2.empty()) return;
+                   for (int64_t i = 0; i < n; ++i) {
+                     const G2& G = g2[i];
+                     if (g2d) {
+                       double* o = g2d + 7 * (int64_t(k) * n + i);
+                       o[0] = G.m2[0]; o[1] = G.m2[1]; o[2] = G.conic[0]; o[3] = G.conic[1]; o[4] = G.conic[2];
+                       o[5] = G.o; o[6] = G.zf;
+                     }
+                     if (!s.proj[i].vis) continue;
+                     project_backward(s, k, i, G, gmean, glsc, gquat, gopac, gpose);
+                   }
+                   g2.clear();
                  });
-  for (size_t k = 0; k < s.items.size(); ++k)
-    for (int64_t i = 0; i < n; ++i) {
-      const Proj& p = s.proj[k][i];
-      const G2& G = g2[k][i];
-      if (g2d) {
-        double* o = g2d + 7 * (int64_t(k) * n + i);
-        o[0] = G.m2[0]; o[1] = G.m2[1]; o[2] = G.conic[0]; o[3] = G.conic[1]; o[4] = G.conic[2];
-        o[5] = G.o; o[6] = G.zf;
-      }
-      if (!p.vis) continue;
-      project_backward(s, int(k), i, G, gmean, glsc, gquat, gopac, gpose);
-    }
   return 0;
 }
 

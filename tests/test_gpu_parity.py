@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_2412_01217_amd import scenes
-from tests.helpers import pixel_mask_to_channels, rel_check, targets_from_random
+from tests.helpers import flagged, pixel_mask_to_channels, rel_check, targets_from_random
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -87,7 +87,7 @@ def test_preprocess_parity(case, isotropic):
     rad = proj["radius"].cpu().numpy()
     rec = proj["rec"].cpu().numpy().reshape(-1, 8).astype(np.float64)
     depth = proj["depth"].cpu().numpy()
-    ok = ref["flag"] == 0
+    ok = ~flagged(ref["flag"], "projections")
     np.testing.assert_array_equal(rad[ok], ref["radius"][ok])
     vis = ok & (ref["radius"] > 0)
     assert vis.sum() > 100
@@ -202,8 +202,7 @@ def _check_render_fwd(sc, views, variant, split, fwd_chunk=1, state_capacity=Non
     mag = oracle.render(ocfg, sc, views, sem=np.abs(sc.sem))["img"]
     its = oracle.items(views)
     K = ref["K"]
-    flag = ref["flag"] != 0
-    assert flag.mean() < 0.01, flag.mean()
+    flag = flagged(ref["flag"], "pixels")
     got = img["color"].cpu().numpy()
     mask = pixel_mask_to_channels(flag, its, K)
     for c0, c1, nm in ((0, 3, "rgb"), (3, 4, "depth"), (4, K, "sem")):
@@ -314,7 +313,7 @@ def _check_render_bwd(case, variant, split, fwd_chunk=1, small_workspace=False, 
     # pixels whose forward decisions sit within rounding of a threshold get no upstream
     # gradient, so they cannot contribute to any parameter's gradient on either side
     r = oracle.render(ocfg, sc, views)
-    gimg[pixel_mask_to_channels(r["flag"] != 0, oracle.items(views), K)] = 0.0
+    gimg[pixel_mask_to_channels(flagged(r["flag"], "pixels"), oracle.items(views), K)] = 0.0
     grads = raster.render_bwd(cfg, g, proj, fr, srt, img, dict(color=torch.from_numpy(gimg).cuda()), ws=ws)
     torch.cuda.synchronize()
     ref = oracle.backward(ocfg, sc, views, gimg)
@@ -347,7 +346,9 @@ def test_end_to_end_tiny_loss_and_gradients(lam):
     ref = oracle.backward(oracle.Config(), sc, views, gimg)
     # features enter linearly: sum_p w |g_p| bounds their gradients' terms
     mag = oracle.backward(oracle.Config(), sc, views, np.abs(gimg))
-    bad = ref["gflag"] != 0
+    flagged(r["flag"], "pixels")
+    # every contributor of a flagged pixel (4 pixels here reach about 9 % of the Gaussians)
+    bad = flagged(ref["gflag"], "Gaussians touching a flagged pixel", bound=0.15)
     for name in ("mean", "log_scale", "quat", "opacity", "rgb", "sem"):
         got = grads[name].cpu().numpy()
         m = np.broadcast_to(bad.reshape(-1, *([1] * (got.ndim - 1))), got.shape)
