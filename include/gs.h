@@ -15,7 +15,9 @@
  *    it and returns; results are ready when the stream is.
  *  - Return value: GS_OK (0) or a negative gs_status. Argument errors are
  *    detected on the host before anything is enqueued. No C++ exception crosses
- *    the ABI. The functions keep no state between calls.
+ *    the ABI. The hot-path functions keep no state between calls (launch sizes
+ *    are derived from the calling thread's current device at every call); the
+ *    only state is the last HIP error code, kept per thread for gs_last_hip_error().
  *  - Work item ("item"): one (view, pyramid level) pair. Level l of a view with
  *    base size W x H has size (W >> l) x (H >> l) and intrinsics
  *    fx/2^l, fy/2^l, cx/2^l, cy/2^l (Sec. III-C, eq. 4-6: the pyramid).

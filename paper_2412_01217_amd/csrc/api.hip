@@ -6,7 +6,8 @@
 
 namespace gs {
 
-static int g_last_hip = 0;
+// the last HIP error code seen by this thread's calls (gs_last_hip_error)
+static thread_local int g_last_hip = 0;
 
 int hip_status(hipError_t e) {
   if (e == hipSuccess) return GS_OK;
@@ -283,19 +284,26 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
                   int32_t n_views, const gs_item* items_dev, int32_t n_items, int32_t n_tiles,
                   const uint32_t* vals, const uint32_t* ranges, const gs_head* head, const gs_images* fwd,
                   const gs_images* grad_in, gs_grads* grads, void* workspace, size_t ws_bytes, void* stream) {
+  // every argument is checked before the first launch: an invalid call enqueues nothing
   if (!cfg_ok(cfg) || !gauss_ok(g, true) || !proj || !fwd || !grad_in || !grads || n_views < 0 || n_items < 0 ||
       n_tiles < 0)
     return GS_ERR_INVALID_ARG;
   const bool learned = g->emb != nullptr;
   if (learned && (cfg->n_sem != 16 || !head || !head_shape_ok(*head) || !grads->emb || !grads->head_W1 ||
                   !grads->head_b1 || !grads->head_W2 || !grads->head_b2 || !fwd->color || !grad_in->logits ||
-                  fwd->n_pixels < 0))
+                  !grad_in->color || fwd->n_pixels < 0 || !items_dev))
     return GS_ERR_INVALID_ARG;
   if (!learned && head) return GS_ERR_INVALID_ARG;
   if (learned && cfg->view_features) return GS_ERR_INVALID_ARG;
   if (!learned && cfg->n_sem > 0 && g->n > 0 && (!g->sem || !grads->sem)) return GS_ERR_INVALID_ARG;
   if (!grads->mean || !grads->log_scale || !grads->quat || !grads->opacity || !grads->rgb || !grads->pose)
     return GS_ERR_INVALID_ARG;
+  if (g->n > 0 && n_items > 0 && (!views_dev || !items_dev || !proj->rec || !proj->radius)) return GS_ERR_INVALID_ARG;
+  const bool render = g->n > 0 && n_tiles > 0;
+  if (render) {
+    if (!items_dev || !vals || !ranges || !fwd->T || !fwd->n_contrib || !grad_in->color) return GS_ERR_INVALID_ARG;
+    if (fwd->state && render_state_capacity(n_tiles, 4 + cfg->n_sem, fwd->state_bytes) < 0) return GS_ERR_WORKSPACE;
+  }
   const size_t rec_bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)g->n);
   const size_t head_bytes = align_up(head_bwd_workspace());
   if (!workspace || ws_bytes < rec_bytes + head_bytes) return GS_ERR_WORKSPACE;
@@ -314,16 +322,13 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   int st = launch_zero_f32(zp, zn, 4, s);
   if (st) return st;
   if (learned) {
-    if (!items_dev) return GS_ERR_INVALID_ARG;
     st = launch_head_bwd(items_dev, n_items, fwd->n_pixels, 4 + cfg->n_sem, *head, fwd->color, grad_in->logits,
                          grad_in->color, (float*)((char*)workspace + rec_bytes), gr.head_W1, gr.head_b1, gr.head_W2,
                          gr.head_b2, s);
     if (st) return st;
   }
   if (n == 0) return GS_OK;
-  if (n_tiles > 0) {
-    if (!items_dev || !vals || !ranges || !fwd->T || !fwd->n_contrib || !grad_in->color) return GS_ERR_INVALID_ARG;
-    if (fwd->state && render_state_capacity(n_tiles, 4 + cfg->n_sem, fwd->state_bytes) < 0) return GS_ERR_WORKSPACE;
+  if (render) {
     st = launch_render_bwd(*cfg, *g, *proj, items_dev, n_items, n_tiles, vals, ranges, *fwd, *grad_in, (float*)workspace,
                            gr, seg_ws, cap, s);
     if (st) return st;

@@ -100,9 +100,11 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partial, int64
   if (t == 1023 && total_out) *total_out = sh[1023];
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* __restrict__ in, const uint64_t* count_dev,
+// in and out may be the same array (in-place scans): each thread reads its elements
+// before it writes them, and no other thread touches them.
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* in, const uint64_t* count_dev,
                                                               int64_t count_host, const uint32_t* __restrict__ partial,
-                                                              uint32_t* __restrict__ out) {
+                                                              uint32_t* out) {
   const int64_t count = count_dev ? (int64_t)*count_dev : count_host;
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   if (base >= count) return;
@@ -140,10 +142,11 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* sh /*[4]
   return t;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply_direct(const uint32_t* __restrict__ in,
+// (in and out may be the same array, as for k_scan_apply)
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply_direct(const uint32_t* in,
                                                                      const uint64_t* count_dev, int64_t count_host,
                                                                      const uint32_t* __restrict__ partial,
-                                                                     uint32_t* __restrict__ out, uint64_t* total_out) {
+                                                                     uint32_t* out, uint64_t* total_out) {
   const int64_t count = count_dev ? (int64_t)*count_dev : count_host;
   const int64_t np = min((int64_t)gridDim.x, (count + kScanTile - 1) / kScanTile);
   const int64_t lim = blockIdx.x == 0 ? np : min((int64_t)blockIdx.x, np);

@@ -17,6 +17,19 @@ int hip_status(hipError_t e);
 int launch_status();  // hipGetLastError() folded into a gs_status
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Blocks of a persistent (grid-stride or work-queue) launch that fill the calling thread's
+// current device: resident blocks per CU times CUs. Computed at every call (nothing is
+// cached, so a second device or a changed current device is sized correctly); `fallback`
+// (0: report failure) if the runtime cannot tell.
+template <class F>
+int resident_blocks(F kernel, int threads, int fallback) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess)
+    return fallback;
+  return (cus > 0 ? cus : 1) * (per > 0 ? per : 1);
+}
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // Item owning a global tile index (items are ordered by tile_base).

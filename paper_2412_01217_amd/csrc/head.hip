@@ -529,15 +529,7 @@ int launch_head_bwd(const gs_item* items, int n_items, int64_t P, int K, const g
   // at most one 64-pixel chunk per item is partial, so P / 64 + n_items bounds the chunk count;
   // the blocks walk the chunks grid-stride, so the grid is the resident count (one wave per
   // SIMD: the register file holds the weight-gradient accumulators without spilling)
-  static int resident = 0;
-  if (!resident) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_head_bwd, 256, 0) == hipSuccess)
-      resident = std::max(1, cus * std::max(1, per));
-    else
-      resident = kHeadBlocksMax;
-  }
+  const int resident = resident_blocks(k_head_bwd, 256, kHeadBlocksMax);
   const int blocks = (int)std::min<int64_t>(std::min(kHeadBlocksMax, resident), ceil_div(ceil_div(P, 64) + n_items, 4));
   hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(256), 0, s, items, n_items, K, h.n_classes, color, glogits, h.W1,
                      h.b1, h.W2, gcolor, partial);

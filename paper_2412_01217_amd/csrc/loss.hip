@@ -660,16 +660,7 @@ int launch_loss(const gs_item* items, int n_items, int64_t P, int K, int n_class
   if (ssim) {
     hipLaunchKernelGGL(k_ssim_prefix, dim3(1), dim3(256), 0, s, items, n_items, prefix);
     // a grid-stride loop covers every (tile, channel); the grid only needs to fill the chip
-    static int resident = 0;
-    if (!resident) {
-      int dev = 0, cus = 0, per = 0;
-      if (hipGetDevice(&dev) == hipSuccess &&
-          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_ssim, 256, 0) == hipSuccess)
-        resident = std::max(1, cus * std::max(1, per));
-      else
-        resident = 512;
-    }
+    const int resident = resident_blocks(k_ssim, 256, 512);
     const int64_t est = 3 * (ceil_div(P, kSsT * kSsT) + n_items);
     const unsigned grid = (unsigned)std::min<int64_t>(std::max<int64_t>(est, 1), resident);
     hipLaunchKernelGGL(k_ssim, dim3(grid), dim3(256), 0, s, items, n_items, prefix, K, color, t.rgb, w[0], lambda,

@@ -1147,16 +1147,6 @@ size_t seg_layout(int n_tiles, int64_t cap, char* base, SegWs* w) {
   return off;
 }
 
-// Blocks of a persistent launch: resident blocks per CU times CUs, per device and kernel.
-template <class F>
-int persistent_grid(F kernel) {
-  int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess) return 0;
-  return std::max(1, cus * std::max(1, per));
-}
-
 // Caller buffer of a splitting forward (its saved state), sized for `cap` duplicates and
 // K channels.
 struct FLayout {
@@ -1251,9 +1241,8 @@ int launch_fwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected
   if (st) return st;
   hipLaunchKernelGGL(k_seg_list, dim3(tb), dim3(256), 0, s, w.cnt, w.base, w.total, n_tiles, cfg.tile_order,
                      w.max_segs, w.work, w.ctl, w.fs.tcnt, w.fs.tbase);
-  static int grid_t = 0, grid_f = 0;
-  if (!grid_t) grid_t = persistent_grid(k_fwd_trans);
-  if (!grid_f) grid_f = persistent_grid(k_render_fwd_split<NS, true>);
+  const int grid_t = resident_blocks(k_fwd_trans, 256, 0);
+  const int grid_f = resident_blocks(k_render_fwd_split<NS, true>, 256, 0);
   if (!grid_t || !grid_f) return GS_ERR_HIP;
   if (cfg.fwd_chunk > 0)
     hipLaunchKernelGGL(k_fwd_trans, dim3(grid_t), dim3(256), 0, s, cfg, p.rec, g.n, items, n_items, vals, ranges,
@@ -1282,9 +1271,8 @@ int launch_bwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected
   if (st) return st;
   hipLaunchKernelGGL(k_seg_list, dim3((unsigned)ceil_div(n_tiles, 256)), dim3(256), 0, s, w.cnt, w.base, w.total,
                      n_tiles, cfg.tile_order, w.max_segs, w.work, w.ctl, nullptr, nullptr);
-  static int grid_sum = 0, grid_main = 0;
-  if (!grid_sum) grid_sum = persistent_grid(k_render_bwd_split<NS, true>);
-  if (!grid_main) grid_main = persistent_grid(k_render_bwd_split<NS, false>);
+  const int grid_sum = resident_blocks(k_render_bwd_split<NS, true>, 256, 0);
+  const int grid_main = resident_blocks(k_render_bwd_split<NS, false>, 256, 0);
   if (!grid_sum || !grid_main) return GS_ERR_HIP;
   if (!fs.tcnt)
     hipLaunchKernelGGL((k_render_bwd_split<NS, true>), dim3(grid_sum), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb,

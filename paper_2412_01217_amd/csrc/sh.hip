@@ -377,12 +377,10 @@ int launch_sh_bwd(const gs_gaussians& g, const gs_sh& sh, int n_sem, const gs_vi
   int gsz = 1;
   while (gsz < 3 + n_sem) gsz <<= 1;
   // a few blocks per CU: enough lanes in flight, few same-address atomics on the poses
-  static int cus = 0;
-  if (!cus) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
   const int64_t blocks = std::min<int64_t>(ceil_div(g.n, kShBwdThreads / gsz), 4 * (int64_t)cus);
   hipLaunchKernelGGL(k_sh_bwd, dim3((unsigned)blocks), dim3(kShBwdThreads), 0, s, g, sh, n_sem, views, n_views, grgb,
                      gsem, gdc_rgb, grest_rgb, gdc_sem, grest_sem, gmean, gpose);

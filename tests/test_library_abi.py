@@ -198,3 +198,53 @@ def test_sh_struct_and_argument_checks():
         L.GS_ERR_INVALID_ARG
     assert lib.gs_sh_features_bwd(4, ctypes.byref(g), ctypes.byref(ok), fake, 2, fake, fake, fake, fake, fake, fake,
                                   None, fake, None) == L.GS_ERR_INVALID_ARG
+
+
+def _learned_bwd_call(drop=None):
+    """gs_render_bwd in learned mode with placeholder pointers (never dereferenced on the
+    host); `drop` names one argument to leave out."""
+    lib = L.lib()
+    c = L.Config()
+    lib.gs_config_default(ctypes.byref(c))
+    c.n_sem = 16
+    fake = ctypes.c_void_p(256)
+    g = L.Gaussians(10, fake, fake, fake, fake, fake, None, fake)
+    p = L.Projected(fake, fake, fake)
+    h = L.Head()
+    h.d_in, h.d_hidden, h.n_classes = 16, 64, 52
+    h.W1 = h.b1 = h.W2 = h.b2 = 256
+    fwd = L.Images(fake, fake, fake, None, 100, None, 0)
+    gin = L.Images(fake, None, None, fake, 100, None, 0)
+    gr = L.Grads(*([fake] * 12))
+    ws = 1 << 30
+    items = fake
+    if drop == "emb_grad":
+        gr.emb = None
+    elif drop == "head_W2_grad":
+        gr.head_W2 = None
+    elif drop == "logit_grad":
+        gin.logits = None
+    elif drop == "items":
+        items = None
+    elif drop == "head":
+        h = None
+    elif drop == "n_classes":
+        h.n_classes = 65
+    elif drop == "n_sem":
+        c.n_sem = 20
+    elif drop == "workspace":
+        ws = 16
+    return lib.gs_render_bwd(ctypes.byref(c), ctypes.byref(g), ctypes.byref(p), fake, 1, items, 1, 4, fake, fake,
+                             ctypes.byref(h) if h is not None else None, ctypes.byref(fwd), ctypes.byref(gin),
+                             ctypes.byref(gr), fake, ws, None)
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="host-only check: placeholder pointers must never reach a GPU")
+def test_invalid_learned_backward_enqueues_nothing():
+    """Without a GPU, any launch fails with GS_ERR_HIP. An invalid learned-mode call must come
+    back with its argument error instead: nothing was enqueued before the check (the zeroing
+    of the outputs included). The complete call is the control: it reaches a launch."""
+    for drop in ("emb_grad", "head_W2_grad", "logit_grad", "items", "head", "n_classes", "n_sem"):
+        assert _learned_bwd_call(drop) == L.GS_ERR_INVALID_ARG, drop
+    assert _learned_bwd_call("workspace") == L.GS_ERR_WORKSPACE
+    assert _learned_bwd_call() == L.GS_ERR_HIP
