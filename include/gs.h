@@ -240,8 +240,9 @@ int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
  * l = cfg->ssim_lambda, and SSIM is the mean over the 3 colour channels and all pixels of
  * the structural similarity of Wang et al. (2004) with an 11 x 11 Gaussian window of
  * standard deviation 1.5 (weights summing to 1; both images taken as zero outside),
- * C1 = 0.01^2, C2 = 0.03^2. grad_out->color (and ->logits in learned mode) receives the
- * gradient of sum_i (w[0] L_rgb + w[1] L_depth + w[2] L_sem). w is a host array of 3.
+ * C1 = 0.01^2, C2 = 0.03^2. grad_out->color (every channel; in learned mode the embedding
+ * channels get 0) and ->logits in learned mode receive the gradient of
+ * sum_i (w[0] L_rgb + w[1] L_depth + w[2] L_sem). w is a host array of 3.
  * workspace: gs_workspace_size(GS_WS_LOSS); its contents are scratch between calls. */
 int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_items, int64_t n_pixels,
                     int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const float* w,
@@ -251,8 +252,9 @@ int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_it
  * through compositing and projection to every Gaussian parameter and every view's
  * pose tangent. fwd must hold T and n_contrib of the matching gs_render_fwd.
  * Learned mode (head != NULL): the head is differentiated first; its gradient with
- * respect to the embedding image overwrites channels 4..19 of grad_in->color (the
- * caller's buffer), grads->emb receives the per-Gaussian embedding gradient and
+ * respect to the embedding image is added to channels 4..19 of grad_in->color (the
+ * caller's buffer, which holds any direct gradient of those channels: zero after
+ * gs_pyramid_loss), grads->emb receives the per-Gaussian embedding gradient and
  * grads->head_* the weight gradients. workspace: gs_workspace_size(GS_WS_RENDER_BWD). */
 int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_view* views_dev,
                   int32_t n_views, const gs_item* items_dev, int32_t n_items, int32_t n_tiles,
@@ -336,6 +338,20 @@ int gs_gaussians_adam(int64_t n, int32_t n_sem, const gs_param_arrays* params, c
  * item_count are not touched. */
 int gs_pose_adam(gs_view* views_dev, int32_t n_views, const float* grad_pose, float* m, float* v,
                  const gs_adam_config* hp, int32_t step, void* stream);
+
+/* Left perturbation of view poses at a nonzero tangent (the pose input of an autograd
+ * wrapper; R12 of the readings: T_cw <- Exp(xi) T_cw, xi = (rho, phi), rho first):
+ * views_out[i] = views_in[i] with R, t replaced by those of Exp(xi_i) T_cw, composed in
+ * double precision and rounded once to single precision (not re-orthonormalised);
+ * item_first and item_count are copied. xi [n_views][6] (device). views_out may equal
+ * views_in. One launch on `stream`. */
+int gs_pose_perturb(const gs_view* views_in, int32_t n_views, const float* xi, gs_view* views_out, void* stream);
+
+/* Chain rule of gs_pose_perturb: grad_xi[i] = J_l(xi_i)^T grad_pose[i], where grad_pose is the
+ * gradient with respect to a tangent at the perturbed pose (gs_render_bwd's grads->pose after
+ * rendering with views_out) and J_l the left Jacobian of SE(3), Exp(xi + d) = Exp(J_l d) Exp(xi)
+ * to first order in d. Arrays [n_views][6] (device); grad_xi must not alias grad_pose. */
+int gs_pose_perturb_bwd(const float* xi, int32_t n_views, const float* grad_pose, float* grad_xi, void* stream);
 
 /* ---- training helpers for the learned head ------------------------------- */
 

@@ -78,6 +78,8 @@ int launch_adam(float*, const float*, float*, float*, int64_t, float, float, flo
 int launch_gaussians_adam(int64_t, int, const gs_param_arrays&, const gs_grads&, const gs_param_arrays&,
                           const gs_param_arrays&, const gs_adam_config&, int, hipStream_t);
 int launch_pose_adam(gs_view*, int, const float*, float*, float*, const gs_adam_config&, int, hipStream_t);
+int launch_pose_perturb(const gs_view*, int, const float*, gs_view*, hipStream_t);
+int launch_pose_perturb_bwd(const float*, int, const float*, float*, hipStream_t);
 int launch_sh_fwd(const gs_gaussians&, const gs_sh&, int, const gs_view*, int, float*, float*, hipStream_t);
 int launch_sh_bwd(const gs_gaussians&, const gs_sh&, int, const gs_view*, int, const float*, const float*, float*,
                   float*, float*, float*, float*, float*, hipStream_t);
@@ -413,6 +415,20 @@ int gs_pose_adam(gs_view* views_dev, int32_t n_views, const float* grad_pose, fl
   if (n_views == 0) return GS_OK;
   if (!views_dev || !grad_pose || !m || !v) return GS_ERR_INVALID_ARG;
   return launch_pose_adam(views_dev, n_views, grad_pose, m, v, *hp, step, (hipStream_t)stream);
+}
+
+int gs_pose_perturb(const gs_view* views_in, int32_t n_views, const float* xi, gs_view* views_out, void* stream) {
+  if (n_views < 0) return GS_ERR_INVALID_ARG;
+  if (n_views == 0) return GS_OK;
+  if (!views_in || !xi || !views_out) return GS_ERR_INVALID_ARG;
+  return launch_pose_perturb(views_in, n_views, xi, views_out, (hipStream_t)stream);
+}
+
+int gs_pose_perturb_bwd(const float* xi, int32_t n_views, const float* grad_pose, float* grad_xi, void* stream) {
+  if (n_views < 0) return GS_ERR_INVALID_ARG;
+  if (n_views == 0) return GS_OK;
+  if (!xi || !grad_pose || !grad_xi || grad_pose == grad_xi) return GS_ERR_INVALID_ARG;
+  return launch_pose_perturb_bwd(xi, n_views, grad_pose, grad_xi, (hipStream_t)stream);
 }
 
 int gs_distill_loss(const gs_item* items_dev, int32_t n_items, int64_t n_pixels, int32_t C, const float* teacher,

@@ -198,7 +198,7 @@ __device__ __forceinline__ bool seek_chunk(const gs_item* __restrict__ items, in
 // then, per 32-pixel half,
 //  (1) recomputes the hidden pre-activations for the ReLU mask,
 //  (2) forms dH^T = W2^T dlogits^T (hidden in registers, pixels across lanes),
-//  (3) writes dE^T = W1^T dH^T into the colour-gradient planes 4..19,
+//  (3) adds dE^T = W1^T dH^T to the colour-gradient planes 4..19,
 //  (4) recomputes H and dH with pixels in registers and hidden units across lanes --
 //      the layout in which a matrix-core product contracts over pixels -- and
 //  (5) accumulates dW2 = dlogits^T relu(H), db2 and dW1 = dH^T [E, 1] (column 16 is
@@ -349,9 +349,10 @@ __global__ __launch_bounds__(256, 1) void k_head_bwd(const gs_item* __restrict__
           dE = mfma(a, hi, dE);
           dE = mfma(a, lo, dE);
         }
+        // added to what the caller's gradient holds for the embedding channels (rows 0..15 = d)
         if (qlive)
 #pragma unroll
-          for (int r = 0; r < 8; ++r) dEb[(int64_t)drow(r, lane) * HW + q] = dE[r];   // rows 0..15 = d
+          for (int r = 0; r < 8; ++r) dEb[(int64_t)drow(r, lane) * HW + q] += dE[r];
       }
 
       // Reloading from LDS below is cheaper than keeping (2)'s operands alive through (3).

@@ -122,6 +122,10 @@ __global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items,
       for (int ch = 0; ch < 3; ++ch) __builtin_nontemporal_store(gc[ch], &gcolor[cb + ch * HW]);
     }
     __builtin_nontemporal_store(gd, &gcolor[cb + 3 * HW]);
+    // learned mode: the loss has no direct term on the composited embedding channels
+    // (the head's backward adds its input gradient there)
+    if (logits)
+      for (int ch = 4; ch < K; ++ch) __builtin_nontemporal_store(0.0f, &gcolor[cb + ch * HW]);
     if (sem) {
       float* G = logits ? glogits + lb : gcolor + lb;
       float m = -INFINITY;

@@ -141,6 +141,99 @@ __global__ void k_pose_adam(gs_view* __restrict__ views, int n_views, const floa
   for (int e = 0; e < 3; ++e) vw.t[e] = (float)t[e];
 }
 
+// T_cw <- Exp(xi) T_cw for a pose tangent xi = (rho, phi) at a nonzero point: the product in
+// double precision, rounded once (no re-orthonormalisation, so that the result is the smooth
+// function of xi whose derivative k_pose_perturb_bwd gives).
+__global__ void k_pose_perturb(const gs_view* __restrict__ vin, int n_views, const float* __restrict__ xi_in,
+                               gs_view* vout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_views) return;
+  double xi[6];
+  for (int k = 0; k < 6; ++k) xi[k] = (double)xi_in[6 * i + k];
+  double Rd[9], td[3];
+  exp_se3(xi, Rd, td);
+  const gs_view v0 = vin[i];
+  gs_view v1 = v0;
+  for (int r = 0; r < 3; ++r) {
+    double t = td[r];
+    for (int cc = 0; cc < 3; ++cc) {
+      double a = 0.0;
+      for (int k = 0; k < 3; ++k) a += Rd[3 * r + k] * (double)v0.R[3 * k + cc];
+      v1.R[3 * r + cc] = (float)a;
+      t += Rd[3 * r + cc] * (double)v0.t[cc];
+    }
+    v1.t[r] = (float)t;
+  }
+  vout[i] = v1;
+}
+
+// The left Jacobian of SE(3) at xi = (rho, phi), J_l = [[J, Q], [0, J]], for which
+// Exp(xi + d) = Exp(J_l d + O(d^2)) Exp(xi): J is SO(3)'s left Jacobian (the V of exp_se3,
+// J = I + c K + e3 K^2 with c = (1 - cos a) / a^2, e3 = (a - sin a) / a^3, K = [phi]x), and,
+// matching the translations of both sides, Q = d(J rho)/d phi + [J rho]x J. With
+// J rho = rho + c phi x rho + e3 phi x (phi x rho):
+//   d(J rho)/d phi = -c [rho]x + e3 ((phi . rho) I + phi rho^T - 2 rho phi^T)
+//                    + (phi x rho) c' phi^T + (phi x (phi x rho)) e3' phi^T,
+// c' = (dc/da) / a and e3' = (de3/da) / a (Taylor series below a = 0.1, where they cancel).
+// grad_xi = J_l^T grad at the perturbed pose.
+__global__ void k_pose_perturb_bwd(const float* __restrict__ xi_in, int n_views, const float* __restrict__ g_in,
+                                   float* __restrict__ g_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_views) return;
+  double rho[3], w[3], g_r[3], g_w[3];
+  for (int k = 0; k < 3; ++k) {
+    rho[k] = (double)xi_in[6 * i + k];
+    w[k] = (double)xi_in[6 * i + 3 + k];
+    g_r[k] = (double)g_in[6 * i + k];
+    g_w[k] = (double)g_in[6 * i + 3 + k];
+  }
+  const double a2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], a = sqrt(a2);
+  double c, e3, cp, ep;
+  if (a < 0.1) {
+    c = 0.5 - a2 / 24.0 + a2 * a2 / 720.0 - a2 * a2 * a2 / 40320.0;
+    e3 = 1.0 / 6.0 - a2 / 120.0 + a2 * a2 / 5040.0 - a2 * a2 * a2 / 362880.0;
+    cp = -1.0 / 12.0 + a2 / 180.0 - a2 * a2 / 6720.0 + a2 * a2 * a2 / 453600.0;
+    ep = -1.0 / 60.0 + a2 / 1260.0 - a2 * a2 / 60480.0 + a2 * a2 * a2 / 4989600.0;
+  } else {
+    const double sa = sin(a), ca = cos(a);
+    c = (1.0 - ca) / a2;
+    e3 = (a - sa) / (a2 * a);
+    cp = sa / (a2 * a) - 2.0 * (1.0 - ca) / (a2 * a2);
+    ep = (1.0 - ca) / (a2 * a2) - 3.0 * (a - sa) / (a2 * a2 * a);
+  }
+  const double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+  double J[9];
+  for (int r = 0; r < 3; ++r)
+    for (int cc = 0; cc < 3; ++cc) {
+      const double k2 = K[3 * r] * K[cc] + K[3 * r + 1] * K[3 + cc] + K[3 * r + 2] * K[6 + cc];
+      J[3 * r + cc] = (r == cc ? 1.0 : 0.0) + c * K[3 * r + cc] + e3 * k2;
+    }
+  const double wxr[3] = {w[1] * rho[2] - w[2] * rho[1], w[2] * rho[0] - w[0] * rho[2], w[0] * rho[1] - w[1] * rho[0]};
+  const double wxwxr[3] = {w[1] * wxr[2] - w[2] * wxr[1], w[2] * wxr[0] - w[0] * wxr[2], w[0] * wxr[1] - w[1] * wxr[0]};
+  const double wr = w[0] * rho[0] + w[1] * rho[1] + w[2] * rho[2];
+  double Jr[3];
+  for (int k = 0; k < 3; ++k) Jr[k] = rho[k] + c * wxr[k] + e3 * wxwxr[k];
+  const double Rx[9] = {0.0, -rho[2], rho[1], rho[2], 0.0, -rho[0], -rho[1], rho[0], 0.0};
+  const double JRx[9] = {0.0, -Jr[2], Jr[1], Jr[2], 0.0, -Jr[0], -Jr[1], Jr[0], 0.0};
+  double Q[9];
+  for (int r = 0; r < 3; ++r)
+    for (int cc = 0; cc < 3; ++cc) {
+      double q = -c * Rx[3 * r + cc] + e3 * ((r == cc ? wr : 0.0) + w[r] * rho[cc] - 2.0 * rho[r] * w[cc]) +
+                 cp * wxr[r] * w[cc] + ep * wxwxr[r] * w[cc];
+      for (int k = 0; k < 3; ++k) q += JRx[3 * r + k] * J[3 * k + cc];
+      Q[3 * r + cc] = q;
+    }
+  for (int cc = 0; cc < 3; ++cc) {
+    double dr = 0.0, dw = 0.0;
+    for (int r = 0; r < 3; ++r) {
+      dr += J[3 * r + cc] * g_r[r];
+      dw += Q[3 * r + cc] * g_r[r] + J[3 * r + cc] * g_w[r];
+    }
+    g_out[6 * i + cc] = (float)dr;
+    g_out[6 * i + 3 + cc] = (float)dw;
+  }
+}
+
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 }  // namespace
@@ -183,6 +276,18 @@ int launch_pose_adam(gs_view* views, int n_views, const float* grad, float* m, f
   const double c2 = 1.0 / (1.0 - pow((double)hp.beta2, step));
   hipLaunchKernelGGL(k_pose_adam, dim3((unsigned)ceil_div(n_views, 64)), dim3(64), 0, s, views, n_views, grad, m, v,
                      hp.lr_rho, hp.lr_phi, hp.beta1, hp.beta2, hp.eps, (float)c1, (float)c2);
+  return launch_status();
+}
+
+int launch_pose_perturb(const gs_view* vin, int n_views, const float* xi, gs_view* vout, hipStream_t s) {
+  if (n_views == 0) return GS_OK;
+  hipLaunchKernelGGL(k_pose_perturb, dim3((unsigned)ceil_div(n_views, 64)), dim3(64), 0, s, vin, n_views, xi, vout);
+  return launch_status();
+}
+
+int launch_pose_perturb_bwd(const float* xi, int n_views, const float* g_in, float* g_out, hipStream_t s) {
+  if (n_views == 0) return GS_OK;
+  hipLaunchKernelGGL(k_pose_perturb_bwd, dim3((unsigned)ceil_div(n_views, 64)), dim3(64), 0, s, xi, n_views, g_in, g_out);
   return launch_status();
 }
 

@@ -13,6 +13,8 @@ pooled view's projection and binning are computed once.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import torch
 
@@ -105,22 +107,26 @@ class Trainer:
         raster.render_fwd(self.cfg_learned, self.g_learned, vs.proj, vs.fr, vs.sorter, out=vs.img,
                           head=self.head.as_dict())
 
-    def train(self, steps: int, lr_mlp=1e-3, lr_emb=1e-2, mse_w=0.1):
+    def train(self, steps: int, lr_mlp=1e-3, lr_emb=1e-2, mse_w=0.1, schedule="constant"):
+        """schedule: "constant" rates, or "cosine" (each rate times (1 + cos(pi k / steps)) / 2
+        at step k, decaying to 0 at the end)."""
         losses = []
-        for _ in range(steps):
+        for k in range(steps):
+            f = 1.0 if schedule == "constant" else 0.5 * (1.0 + math.cos(math.pi * k / steps))
             if self.view_fn is not None:
                 vs = self._state(self.view_fn(self.t))
             else:
                 vs = self.views[int(self.rng.integers(len(self.views)))]
             self.forward(vs)
+            vs.grad["color"].zero_()      # the head's backward adds to the embedding channels
             raster.distill_loss(vs.fr, self.C, vs.teacher, vs.img["logits"], mse_w, grad=vs.grad["logits"],
                                 loss_out=vs.loss, ws=vs.dws)
             raster.render_bwd(self.cfg_learned, self.g_learned, vs.proj, vs.fr, vs.sorter, vs.img, vs.grad,
                               grads=vs.grads, ws=vs.ws, head=self.head.as_dict())
             self.t += 1
-            raster.adam_step(self.emb_master, vs.grads["emb"], self.emb_m, self.emb_v, lr_emb, self.t,
+            raster.adam_step(self.emb_master, vs.grads["emb"], self.emb_m, self.emb_v, lr_emb * f, self.t,
                              bf16_copy=self.g_learned["emb"])
-            self.head.step(vs.grads, lr_mlp, self.t)
+            self.head.step(vs.grads, lr_mlp * f, self.t)
             losses.append(vs.loss)
         return torch.stack([x.clone() for x in losses[-10:]]).mean().item() if losses else float("nan")
 

@@ -347,6 +347,23 @@ def pose_adam(views_dev: torch.Tensor, n_views: int, grad_pose: torch.Tensor, m:
                                  int(step), _stream(views_dev.device)), "gs_pose_adam")
 
 
+def pose_perturb(frame: Frame, xi: torch.Tensor, views_out: torch.Tensor | None = None) -> torch.Tensor:
+    """The frame's views with T_cw <- Exp(xi_v) T_cw (xi [n_views, 6], device float32),
+    as a device gs_view array (views_out, or a new one)."""
+    out = views_out if views_out is not None else torch.empty_like(frame.views_dev)
+    L.check(L.lib().gs_pose_perturb(_ptr(frame.views_dev), frame.n_views, _ptr(xi), _ptr(out), _stream(frame.device)),
+            "gs_pose_perturb")
+    return out
+
+
+def pose_perturb_bwd(xi: torch.Tensor, grad_pose: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/dxi from the gradient with respect to a tangent at the perturbed poses."""
+    out = out if out is not None else torch.empty_like(grad_pose)
+    L.check(L.lib().gs_pose_perturb_bwd(_ptr(xi), int(xi.shape[0]), _ptr(grad_pose), _ptr(out), _stream(xi.device)),
+            "gs_pose_perturb_bwd")
+    return out
+
+
 def distill_loss(frame: Frame, C: int, teacher: torch.Tensor, student: torch.Tensor, mse_w=0.1, grad=None,
                  loss_out=None, ws=None):
     dev = frame.device

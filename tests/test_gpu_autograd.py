@@ -144,3 +144,192 @@ def test_autograd_twice_gives_same_gradients():
     # float atomics may add in another order from run to run
     for k in out[0]:
         torch.testing.assert_close(out[0][k], out[1][k], rtol=1e-4, atol=1e-7)
+
+
+def _perturbed_view(v, xi):
+    Rx, tx = _exp_se3(np.asarray(xi, np.float64))
+    return scenes.View(Rx @ np.asarray(v.R, np.float64), Rx @ np.asarray(v.t, np.float64) + tx,
+                       v.fx, v.fy, v.cx, v.cy, v.W, v.H, v.levels)
+
+
+@pytest.mark.parametrize("xi0", [(0.0,) * 6, (0.03, -0.02, 0.025, 0.06, -0.04, 0.05)])
+def test_autograd_pose_gradient_at_a_nonzero_tangent(xi0):
+    """The render at xi is that of Exp(xi) T_cw, and dL/dxi there (through SE(3)'s left
+    Jacobian) matches central differences of the oracle in xi. The cut-offs are removed
+    (alpha_min = t_min = 0, every Gaussian on every tile) so that moving the camera changes
+    no blending decision. Rotations about the image axes also reorder depths; the scene is
+    thinned to 200 Gaussians so that no two Gaussians that overlap on screen swap depth
+    order within +-h (the 2000-Gaussian scene has such swaps, whose jump in the image
+    would dominate a difference quotient)."""
+    from paper_2412_01217_amd import autograd, raster
+    full, views = scenes.config_tiny()
+    keep = np.arange(200)
+    sc32 = scenes.Scene(full.mean[keep], full.log_scale[keep], full.quat[keep], full.opacity[keep], full.rgb[keep],
+                        full.sem[keep], None, full.n_classes)
+    v = views[0]
+    v = scenes.View(_rodrigues(np.array([0.03, -0.02, 0.04])).astype(np.float32),
+                    np.array([0.02, -0.03, 0.05], np.float32), v.fx, v.fy, v.cx, v.cy, v.W, v.H, v.levels)
+    sc = _double(sc32)
+    xi0 = np.array(xi0, np.float32).astype(np.float64)
+    cfg_o = oracle.Config(alpha_min=0.0, t_min=0.0, full_rect=True)
+    base = oracle.render(cfg_o, sc, [_perturbed_view(v, xi0)])
+    K = base["K"]
+    rng = np.random.default_rng(5310)
+    gimg = rng.normal(size=base["img"].shape)
+    gimg[pixel_mask_to_channels(base["flag"] != 0, oracle.items([v]), K)] = 0.0
+
+    cfg = raster.config(sc32.n_classes, alpha_min=0.0, t_min=0.0, full_rect=1)
+    fr = raster.Frame(cfg, [v])
+    t = {k: torch.tensor(np.asarray(getattr(sc32, k)), device="cuda", requires_grad=True)
+         for k in ("mean", "log_scale", "quat", "opacity", "rgb", "sem")}
+    xi = torch.tensor(xi0[None], dtype=torch.float32, device="cuda", requires_grad=True)
+    color, _, _ = autograd.render(t, fr, cfg, pose_xi=xi)
+    # the forward is the oracle's render at the perturbed pose
+    ok = base["flag"] == 0
+    got = color.detach().cpu().numpy().reshape(K, -1)
+    ref = base["img"].reshape(K, -1)
+    assert np.abs(got - ref)[:, ok].max() <= 1e-4 * max(np.abs(ref).max(), 1e-12)
+    (color * torch.from_numpy(gimg).float().cuda()).sum().backward()
+    gxi = xi.grad.cpu().numpy().astype(np.float64)[0]
+    for j in range(6):
+        e = np.zeros(6)
+        e[j] = H
+        vp, vm = _perturbed_view(v, xi0 + e), _perturbed_view(v, xi0 - e)
+        rp = oracle.render(cfg_o, sc, [vp])
+        rm = oracle.render(cfg_o, sc, [vm])
+        assert np.array_equal(rp["n_contrib"], rm["n_contrib"]) and np.array_equal(rp["n_blend"], rm["n_blend"])
+        fd = float(np.dot(gimg, rp["img"] - rm["img"])) / (2 * H)
+        scale = max(abs(fd), 0.01 * float(np.sqrt(np.mean(gxi ** 2))))
+        assert abs(gxi[j] - fd) <= TOL * scale, (j, gxi[j], fd)
+
+
+def _planar(x, its):
+    """[P, C] -> [P * C] planar per item."""
+    C = x.shape[1]
+    out = np.zeros(x.shape[0] * C)
+    for it in its:
+        HW = it["W"] * it["H"]
+        out[it["pix0"] * C: it["pix0"] * C + C * HW] = x[it["pix0"]: it["pix0"] + HW].T.reshape(-1)
+    return out
+
+
+def _pixels(img, its, K):
+    """[P * K] planar -> [P, K]."""
+    return np.concatenate([img[it["pix0"] * K: it["pix0"] * K + K * it["W"] * it["H"]].reshape(K, -1).T
+                           for it in its])
+
+
+def learned_fd_problem():
+    """Tiny scene with a 16-dim embedding and a 16 -> 64 -> 52 head, and the upstream
+    gradients of L = sum(gimg * color) + sum(glog * logits). The hidden biases are +-1.5
+    (even units on, odd units off at every pixel), far from the ReLU kink compared with how
+    far a step of h moves a pre-activation, so that the difference quotients are smooth."""
+    C = 52
+    sc32, views = scenes.config_tiny()
+    rng = np.random.default_rng(5320)
+    n = sc32.n
+    emb = scenes.bf16_bits_to_f32(scenes.f32_to_bf16_bits(rng.normal(0, 0.3, (n, 16)).astype(np.float32)))
+    hw = scenes.head_weights(C, seed=6010)
+    b1 = np.where(np.arange(64) % 2 == 0, 1.5, -1.5) * (1 + 0.1 * rng.normal(size=64))
+    pb = dict(sc32=sc32, sc=_double(sc32), views=views, its=oracle.items(views), C=C,
+              emb=emb.astype(np.float64), W1=scenes.bf16_bits_to_f32(hw["W1"]).astype(np.float64),
+              b1=b1.astype(np.float32).astype(np.float64),
+              W2=scenes.bf16_bits_to_f32(hw["W2"]).astype(np.float64),
+              b2=rng.normal(0, 0.1, C).astype(np.float32).astype(np.float64))
+    base = oracle.render(oracle.Config(), pb["sc"], views, sem=pb["emb"])
+    P = base["T"].size
+    gimg = rng.normal(size=P * 20)
+    gimg[pixel_mask_to_channels(base["flag"] != 0, pb["its"], 20)] = 0.0
+    glog_px = rng.normal(size=(P, C))
+    glog_px[base["flag"] != 0] = 0.0
+    pb.update(base=base, gimg=gimg, glog_px=glog_px, glog=_planar(glog_px, pb["its"]), rng=rng)
+    return pb
+
+
+def learned_fd_check(pb, grads):
+    """64 parameters (embedding, the head's four arrays on its active units, geometry) against
+    central differences of the FP64 oracle: the render of the embedding channels, then the
+    head in double precision on the same bfloat16 values."""
+    sc, views, its, rng = pb["sc"], pb["views"], pb["its"], pb["rng"]
+    cfg_o = oracle.Config()
+    base, gimg, glog = pb["base"], pb["gimg"], pb["glog"]
+    dl_drelu = pb["glog_px"] @ pb["W2"]         # dL / d relu(hidden) per pixel, through the logits
+
+    def evaluate(s, a):
+        r = oracle.render(cfg_o, s, views, sem=a["emb"])
+        E = _pixels(r["img"], its, 20)[:, 4:]
+        lg = oracle.head_forward(E, a["W1"], a["b1"], a["W2"], a["b2"])
+        return float(np.dot(gimg, r["img"]) + np.dot(glog, _planar(lg, its))), r, E @ a["W1"].T + a["b1"][None, :]
+
+    visible = np.flatnonzero(oracle.preprocess(cfg_o, sc, views)["radius"] > 0)
+    arrays = ("emb", "W1", "b1", "W2", "b2")
+    draws = (["emb"] * 16 + ["W1"] * 10 + ["b1"] * 6 + ["W2"] * 10 + ["b2"] * 6 +
+             ["mean", "log_scale", "quat", "opacity", "rgb"] * 3 + ["emb"])
+    checked = redrawn = 0
+    for name in draws:
+        key = "head_" + name if name in ("W1", "b1", "W2", "b2") else name
+        shape = grads[key].shape
+        while True:
+            if name in ("emb", "mean", "log_scale", "quat", "opacity", "rgb"):
+                i = int(rng.choice(visible))
+                idx = (i,) if len(shape) == 1 else (i, int(rng.integers(shape[1])))
+            else:
+                idx = tuple(int(rng.integers(d)) for d in shape)
+                hid = {"W1": 0, "b1": 0, "W2": 1}.get(name)   # the hidden-unit index of the entry
+                if hid is not None:
+                    idx = tuple(2 * (x // 2) if k == hid else x for k, x in enumerate(idx))
+
+            def at(d):
+                a = {k: pb[k] for k in arrays}
+                s2 = sc
+                if name in arrays:
+                    a[name] = pb[name].copy()
+                    a[name][idx] += d
+                else:
+                    s2 = sc.copy()
+                    getattr(s2, name)[idx] += d
+                return evaluate(s2, a)
+            lp, rp, hp_ = at(+H)
+            lm, rm, hm_ = at(-H)
+            same = (np.array_equal(rp["n_contrib"], rm["n_contrib"]) and np.array_equal(rp["n_blend"], rm["n_blend"])
+                    and np.array_equal(rp["n_contrib"], base["n_contrib"]))
+            # a hidden unit whose pre-activation changes sign between -h and +h puts a kink in
+            # the difference quotient; its error is at most |dL/d relu| times the smaller
+            # |pre-activation| over 2h, summed over such units
+            flip = (hp_ > 0) != (hm_ > 0)
+            kink = float((np.abs(dl_drelu) * np.minimum(np.abs(hp_), np.abs(hm_)))[flip].sum()) / (2 * H)
+            scale_lo = max(abs(float(grads[key][idx])), 0.01 * float(np.sqrt(np.mean(grads[key] ** 2))))
+            if same and kink <= 0.1 * TOL * scale_lo:
+                break
+            redrawn += 1
+            assert redrawn < 64, "too many draws cross a decision"
+        fd = (lp - lm) / (2 * H)
+        g = grads[key][idx]
+        scale = max(abs(fd), 0.01 * float(np.sqrt(np.mean(grads[key] ** 2))))
+        assert abs(g - fd) <= TOL * scale, (key, idx, g, fd)
+        checked += 1
+    assert checked == 64
+    return redrawn
+
+
+def test_autograd_learned_head_matches_fp64_finite_differences():
+    """Learned mode through the autograd.Function: the gradients of the embedding, of the
+    head's four weight arrays and of the geometry, for L = sum(gimg * color) +
+    sum(glog * logits), against central differences of the FP64 oracle."""
+    from paper_2412_01217_amd import autograd, raster
+    pb = learned_fd_problem()
+    sc32 = pb["sc32"]
+    cfg = raster.config(16)
+    fr = raster.Frame(cfg, pb["views"])
+    t = {k: torch.tensor(np.asarray(getattr(sc32, k)), device="cuda", requires_grad=True)
+         for k in ("mean", "log_scale", "quat", "opacity", "rgb")}
+    t["emb"] = torch.tensor(pb["emb"].astype(np.float32), device="cuda", requires_grad=True)
+    hd = {k: torch.tensor(pb[k].astype(np.float32), device="cuda", requires_grad=True) for k in ("W1", "b1", "W2", "b2")}
+    color, logits, _, _ = autograd.render_learned(t, hd, fr, cfg)
+    loss = ((color * torch.from_numpy(pb["gimg"]).float().cuda()).sum() +
+            (logits * torch.from_numpy(pb["glog"]).float().cuda()).sum())
+    loss.backward()
+    grads = {k: v.grad.cpu().numpy().astype(np.float64) for k, v in t.items()}
+    grads.update({"head_" + k: v.grad.cpu().numpy().astype(np.float64) for k, v in hd.items()})
+    redrawn = learned_fd_check(pb, grads)
+    print("redrawn", redrawn)
