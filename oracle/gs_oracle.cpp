@@ -747,7 +747,8 @@ static double ssim_channel(const double* x, const double* y, int W, int H, doubl
 }
 
 // Pyramid loss, summed over items: w0 * L_rgb + w1 * mean|D-Dgt| over valid (Dgt > 0)
-// pixels + w2 * mean cross-entropy of softmax(S) against the label, per item, with
+// pixels + w2 * mean cross-entropy of softmax(S) against the label (a label outside [0, S)
+// marks an unlabelled pixel, which adds no term but counts in the mean), per item, with
 // L_rgb = (1 - lambda) mean|R-Rgt| over 3HW + lambda (1 - mean SSIM over the 3 channels)
 // (eq. 10 with the SSIM term read as 1 - SSIM), lambda = w[3].
 // loss: [n_items][3] unweighted terms. gimg: dLoss/dimg in the image layout.
@@ -783,7 +784,10 @@ int or_loss(const int* ci, int n_views, const int* vi, const double* img, const 
       } else {
         GI[3 * HW + p] = 0;
       }
-      if (S > 0) {
+      if (S > 0 && (TL[p] < 0 || TL[p] >= S)) {
+        // a label outside [0, S) marks an unlabelled pixel: no cross-entropy term
+        for (int ch = 0; ch < S; ++ch) GI[(4 + ch) * HW + p] = 0.0;
+      } else if (S > 0) {
         double m = -INFINITY;
         for (int ch = 0; ch < S; ++ch) m = std::max(m, I[(4 + ch) * HW + p]);
         double z = 0;

@@ -343,6 +343,24 @@ def test_loss_hand_values_and_gradient():
     assert G[3, 1] == 0 and G[3, 0] == 0 and G[3, 7] == pytest.approx(-1 / 4)
 
 
+def test_loss_unlabelled_pixels_add_no_cross_entropy():
+    # the same image as above with pixels 1 and 6 unlabelled (labels -1 and S): their
+    # cross-entropy terms vanish while the mean still divides by all 8 pixels, and their
+    # logit gradient is zero
+    v = view(4, 2, 4.0)
+    S = 3
+    img = np.zeros((7, 2, 4))
+    img[4:] = np.arange(3)[:, None, None] * 1.0
+    t_lab = np.array([0, -1, 2, 0, 1, 2, 3, 1])
+    ls, g = oracle.loss([v], S, img.reshape(-1), np.zeros(24), np.zeros(8), t_lab, w=(1, 1, 1))
+    lse = math.log(1 + math.e + math.e ** 2)
+    assert ls[0, 2] == pytest.approx(sum(lse - t for t in (0, 2, 0, 1, 2, 1)) / 8)
+    G = g.reshape(7, 8)
+    assert np.all(G[4:, 1] == 0) and np.all(G[4:, 6] == 0)
+    sm = np.exp(np.arange(3) - lse)
+    np.testing.assert_allclose(G[4:, 0], (sm - np.eye(3)[0]) / 8, rtol=1e-13)
+
+
 def test_loss_gradient_finite_difference():
     rng = np.random.default_rng(10)
     v = view(8, 6, 4.0)
