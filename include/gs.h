@@ -226,9 +226,9 @@ int gs_bin_sort(const gs_config* cfg, const gs_projected* proj, const gs_item* i
  * list, alpha = min(alpha_max, o exp(-d^T conic d / 2)), skipped below alpha_min;
  * the pixel stops before the Gaussian that would take T below t_min; the colour,
  * depth and semantic channels accumulate f alpha T. Learned mode (g->emb != NULL,
- * n_sem = 16, head != NULL): the semantic channels composite the bfloat16 embedding
- * in single precision, and out->logits [P * head->n_classes] receives the head's
- * decode W2 relu(W1 E + b1) + b2 of every pixel's embedding E (matrix cores,
+ * n_sem = 16): the semantic channels composite the bfloat16 embedding in single
+ * precision; with head != NULL, out->logits [P * head->n_classes] also receives the
+ * head's decode W2 relu(W1 E + b1) + b2 of every pixel's embedding E (matrix cores,
  * bfloat16 weights, single-precision accumulation). */
 int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_item* items_dev,
                   int32_t n_items, int32_t n_tiles, const uint32_t* vals, const uint32_t* ranges,
@@ -240,22 +240,33 @@ int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
  * l = cfg->ssim_lambda, and SSIM is the mean over the 3 colour channels and all pixels of
  * the structural similarity of Wang et al. (2004) with an 11 x 11 Gaussian window of
  * standard deviation 1.5 (weights summing to 1; both images taken as zero outside),
- * C1 = 0.01^2, C2 = 0.03^2. grad_out->color (every channel; in learned mode the embedding
- * channels get 0) and ->logits in learned mode receive the gradient of
- * sum_i (w[0] L_rgb + w[1] L_depth + w[2] L_sem). w is a host array of 3.
+ * C1 = 0.01^2, C2 = 0.03^2. grad_out->color receives the gradient of
+ * sum_i (w[0] L_rgb + w[1] L_depth + w[2] L_sem) with respect to every rendered channel.
+ * w is a host array of 3. The class logits S are, in plain mode, channels 4.. of
+ * rendered->color; in learned mode (cfg->n_sem = 16) either
+ *  - head != NULL: the decode S = W2 relu(W1 E + b1) + b2 of the embedding channels E,
+ *    evaluated inside the loss (matrix cores, as gs_render_fwd's) and differentiated there:
+ *    grad_out->color channels 4..19 receive dL/dE and head_grads->head_W1 .. head_b2 the
+ *    weight gradients (overwritten); no logits are read or written (rendered->logits and
+ *    grad_out->logits are ignored); or
+ *  - head == NULL: S = rendered->logits (gs_render_fwd's decode), whose gradient goes to
+ *    grad_out->logits; channels 4..19 of grad_out->color get 0.
  * workspace: gs_workspace_size(GS_WS_LOSS); its contents are scratch between calls. */
 int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_items, int64_t n_pixels,
-                    int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const float* w,
-                    float* loss_dev, gs_images* grad_out, void* workspace, size_t ws_bytes, void* stream);
+                    int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const gs_head* head,
+                    const float* w, float* loss_dev, gs_images* grad_out, gs_grads* head_grads, void* workspace,
+                    size_t ws_bytes, void* stream);
 
 /* Back-propagation (Sec. III-D) of an upstream gradient grad_in->color (and ->logits)
  * through compositing and projection to every Gaussian parameter and every view's
  * pose tangent. fwd must hold T and n_contrib of the matching gs_render_fwd.
- * Learned mode (head != NULL): the head is differentiated first; its gradient with
- * respect to the embedding image is added to channels 4..19 of grad_in->color (the
- * caller's buffer, which holds any direct gradient of those channels: zero after
- * gs_pyramid_loss), grads->emb receives the per-Gaussian embedding gradient and
- * grads->head_* the weight gradients. workspace: gs_workspace_size(GS_WS_RENDER_BWD). */
+ * Learned mode (g->emb != NULL): grads->emb receives the per-Gaussian embedding gradient
+ * of the embedding channels' gradient, channels 4..19 of grad_in->color. With head != NULL
+ * and grad_in->logits (a decode's logit gradient), the head is differentiated first: its
+ * gradient with respect to the embedding image is added to channels 4..19 of
+ * grad_in->color (the caller's buffer) and grads->head_* receive the weight gradients.
+ * With head == NULL (grad_in->logits must be NULL) channels 4..19 are taken as they are,
+ * e.g. from gs_pyramid_loss with its head. workspace: gs_workspace_size(GS_WS_RENDER_BWD). */
 int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_view* views_dev,
                   int32_t n_views, const gs_item* items_dev, int32_t n_items, int32_t n_tiles,
                   const uint32_t* vals, const uint32_t* ranges, const gs_head* head, const gs_images* fwd,

@@ -121,7 +121,7 @@ def lib():
         L.gs_render_fwd.argtypes = [P(Config), P(Gaussians), P(Projected), c_void_p, c_int32, c_int32, c_void_p,
                                     c_void_p, c_void_p, P(Images), c_void_p]
         L.gs_pyramid_loss.argtypes = [P(Config), c_void_p, c_int32, c_int64, c_int32, P(Images), P(Targets),
-                                      P(c_float), c_void_p, P(Images), c_void_p, c_size_t, c_void_p]
+                                      c_void_p, P(c_float), c_void_p, P(Images), c_void_p, c_void_p, c_size_t, c_void_p]
         L.gs_render_bwd.argtypes = [P(Config), P(Gaussians), P(Projected), c_void_p, c_int32, c_void_p, c_int32,
                                     c_int32, c_void_p, c_void_p, c_void_p, P(Images), P(Images), P(Grads), c_void_p,
                                     c_size_t, c_void_p]

@@ -65,8 +65,8 @@ int launch_render_bwd(const gs_config& cfg, const gs_gaussians& g, const gs_proj
     return launch_render_bwd_mfma(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, s);
   return launch_render_bwd_split(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, seg_ws, cap, s);
 }
-int launch_loss(const gs_item*, int, int64_t, int, int, const float*, const float*, const gs_targets&, const float*,
-                float, float*, float*, float*, float*, hipStream_t);
+int launch_loss(const gs_item*, int, int64_t, int, int, const float*, const float*, const gs_targets&, const gs_head*,
+                const float*, float, float*, float*, float*, const gs_grads*, float*, hipStream_t);
 int launch_downsample(const gs_item*, int, int64_t, int, int, float*, int32_t*, hipStream_t);
 size_t loss_workspace(int n_items);
 size_t head_bwd_workspace();
@@ -248,38 +248,45 @@ int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
                   const gs_head* head, gs_images* out, void* stream) {
   if (!cfg_ok(cfg) || !gauss_ok(g, true) || !proj || !out || n_items < 0 || n_tiles < 0) return GS_ERR_INVALID_ARG;
   const bool learned = g->emb != nullptr;
-  if (learned && (cfg->n_sem != 16 || !head || !head_shape_ok(*head) || !out->logits || out->n_pixels < 0))
+  if (learned && cfg->n_sem != 16) return GS_ERR_INVALID_ARG;
+  if (head && (!learned || !head_shape_ok(*head) || !out->logits || out->n_pixels < 0 || !items_dev))
     return GS_ERR_INVALID_ARG;
-  if (!learned && head) return GS_ERR_INVALID_ARG;
   if (learned && cfg->view_features) return GS_ERR_INVALID_ARG;
   if (!learned && cfg->n_sem > 0 && g->n > 0 && !g->sem) return GS_ERR_INVALID_ARG;
-  if (n_tiles == 0) return GS_OK;
-  if (!items_dev || !vals || !ranges || !out->color || !out->T || !out->n_contrib) return GS_ERR_INVALID_ARG;
-  if (out->state && render_state_capacity(n_tiles, 4 + cfg->n_sem, out->state_bytes) < 0) return GS_ERR_WORKSPACE;
+  if (n_tiles > 0) {
+    if (!items_dev || !vals || !ranges || !out->color || !out->T || !out->n_contrib) return GS_ERR_INVALID_ARG;
+    if (out->state && render_state_capacity(n_tiles, 4 + cfg->n_sem, out->state_bytes) < 0) return GS_ERR_WORKSPACE;
+  }
   hipStream_t s = (hipStream_t)stream;
   int st = launch_render_fwd(*cfg, *g, *proj, items_dev, n_items, n_tiles, vals, ranges, *out, s);
-  if (st || !learned) return st;
+  if (st || !head) return st;
   return launch_head_fwd(items_dev, n_items, out->n_pixels, 4 + cfg->n_sem, *head, out->color, out->logits, s);
 }
 
 int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_items, int64_t n_pixels,
-                    int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const float* w,
-                    float* loss_dev, gs_images* grad_out, void* workspace, size_t ws_bytes, void* stream) {
+                    int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const gs_head* head,
+                    const float* w, float* loss_dev, gs_images* grad_out, gs_grads* head_grads, void* workspace,
+                    size_t ws_bytes, void* stream) {
   if (!cfg_ok(cfg) || n_items < 0 || n_pixels < 0 || n_classes < 0 || !rendered || !targets || !w || !grad_out)
     return GS_ERR_INVALID_ARG;
   if (n_items == 0) return GS_OK;
   if (!items_dev || !loss_dev || !rendered->color || !grad_out->color || !targets->rgb || !targets->depth)
     return GS_ERR_INVALID_ARG;
   if (n_classes > 0 && !targets->label) return GS_ERR_INVALID_ARG;
-  if (rendered->logits) {
+  if (head) {
+    // the decode inside the loss: the embedding channels in, the head's gradients out
+    if (cfg->n_sem != 16 || !head_shape_ok(*head) || head->n_classes != n_classes || !head_grads ||
+        !head_grads->head_W1 || !head_grads->head_b1 || !head_grads->head_W2 || !head_grads->head_b2)
+      return GS_ERR_INVALID_ARG;
+  } else if (rendered->logits) {
     if (!grad_out->logits) return GS_ERR_INVALID_ARG;
   } else if (n_classes != cfg->n_sem) {
     return GS_ERR_INVALID_ARG;
   }
   if (!workspace || ws_bytes < loss_workspace(n_items)) return GS_ERR_WORKSPACE;
-  return launch_loss(items_dev, n_items, n_pixels, 4 + cfg->n_sem, n_classes, rendered->color, rendered->logits,
-                     *targets, w, cfg->ssim_lambda, loss_dev, grad_out->color, grad_out->logits, (float*)workspace,
-                     (hipStream_t)stream);
+  return launch_loss(items_dev, n_items, n_pixels, 4 + cfg->n_sem, n_classes, rendered->color,
+                     head ? nullptr : rendered->logits, *targets, head, w, cfg->ssim_lambda, loss_dev, grad_out->color,
+                     head ? nullptr : grad_out->logits, head_grads, (float*)workspace, (hipStream_t)stream);
 }
 
 int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_view* views_dev,
@@ -291,11 +298,14 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
       n_tiles < 0)
     return GS_ERR_INVALID_ARG;
   const bool learned = g->emb != nullptr;
-  if (learned && (cfg->n_sem != 16 || !head || !head_shape_ok(*head) || !grads->emb || !grads->head_W1 ||
-                  !grads->head_b1 || !grads->head_W2 || !grads->head_b2 || !fwd->color || !grad_in->logits ||
-                  !grad_in->color || fwd->n_pixels < 0 || !items_dev))
+  if (learned && (cfg->n_sem != 16 || !grads->emb)) return GS_ERR_INVALID_ARG;
+  // with a head, the decode's logit gradient is taken back through it; without, the
+  // embedding channels' gradient is used as given (and no logit gradient may be passed)
+  if (head && (!learned || !head_shape_ok(*head) || !grads->head_W1 || !grads->head_b1 || !grads->head_W2 ||
+               !grads->head_b2 || !fwd->color || !grad_in->logits || !grad_in->color || fwd->n_pixels < 0 ||
+               !items_dev))
     return GS_ERR_INVALID_ARG;
-  if (!learned && head) return GS_ERR_INVALID_ARG;
+  if (learned && !head && grad_in->logits) return GS_ERR_INVALID_ARG;
   if (learned && cfg->view_features) return GS_ERR_INVALID_ARG;
   if (!learned && cfg->n_sem > 0 && g->n > 0 && (!g->sem || !grads->sem)) return GS_ERR_INVALID_ARG;
   if (!grads->mean || !grads->log_scale || !grads->quat || !grads->opacity || !grads->rgb || !grads->pose)
@@ -323,7 +333,7 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   const int64_t zn[4] = {kSortBwdRecord * (int64_t)n_items * n, 3 * n * fv, (int64_t)cfg->n_sem * n * fv, 6ll * n_views};
   int st = launch_zero_f32(zp, zn, 4, s);
   if (st) return st;
-  if (learned) {
+  if (head) {
     st = launch_head_bwd(items_dev, n_items, fwd->n_pixels, 4 + cfg->n_sem, *head, fwd->color, grad_in->logits,
                          grad_in->color, (float*)((char*)workspace + rec_bytes), gr.head_W1, gr.head_b1, gr.head_W2,
                          gr.head_b2, s);

@@ -198,7 +198,7 @@ __device__ __forceinline__ bool seek_chunk(const gs_item* __restrict__ items, in
 // then, per 32-pixel half,
 //  (1) recomputes the hidden pre-activations for the ReLU mask,
 //  (2) forms dH^T = W2^T dlogits^T (hidden in registers, pixels across lanes),
-//  (3) adds dE^T = W1^T dH^T to the colour-gradient planes 4..19,
+//  (3) adds (or stores) dE^T = W1^T dH^T to the colour-gradient planes 4..19,
 //  (4) recomputes H and dH with pixels in registers and hidden units across lanes --
 //      the layout in which a matrix-core product contracts over pixels -- and
 //  (5) accumulates dW2 = dlogits^T relu(H), db2 and dW1 = dH^T [E, 1] (column 16 is
@@ -206,47 +206,287 @@ __device__ __forceinline__ bool seek_chunk(const gs_item* __restrict__ items, in
 // The accumulators are summed over the block's waves in LDS once at the end and written
 // as one partial per block; k_head_reduce adds the partials.
 constexpr int kGst = 65;   // LDS row stride of the staged logit gradients
-__global__ __launch_bounds__(256, 1) void k_head_bwd(const gs_item* __restrict__ items, int n_items, int K, int C,
-                                                     const float* __restrict__ color,
-                                                     const float* __restrict__ glogits,
-                                                     const uint16_t* __restrict__ W1, const float* __restrict__ b1,
-                                                     const uint16_t* __restrict__ W2, float* __restrict__ gcolor,
-                                                     float* __restrict__ partial) {
-  __shared__ float s_buf[4 * kHid * kGst];        // per wave [class][pixel]; the block's partial at the end
-  __shared__ uint16_t s_w2t[kHid * kWtStride];   // W2^T [hidden][class], classes >= C zero
-  __shared__ uint16_t s_w1t[kDin * kWtStride];   // W1^T [d][hidden]
-  __shared__ float s_b1[kHid];
+
+// The block's shared state of a head backward: transposed weights and the per-wave staging.
+struct HeadLds {
+  float buf[4 * kHid * kGst];        // per wave [class][pixel]; the block's partial at the end
+  uint16_t w2t[kHid * kWtStride];    // W2^T [hidden][class], classes >= C zero
+  uint16_t w1t[kDin * kWtStride];    // W1^T [d][hidden]
+  float b1[kHid];
+};
+
+// Per-lane accumulators of the weight gradients over a block's chunks.
+struct HeadAcc {
+  v16f W2[2][2], W1[2];   // W2[cb][hb]: D[c][h]; W1[hb]: D[h][d]
+  float B2[2];            // class l32 + 32 cb, this lane's pixels
+};
+
+__device__ __forceinline__ void head_setup(HeadLds& L, int C, const uint16_t* __restrict__ W1,
+                                           const float* __restrict__ b1, const uint16_t* __restrict__ W2,
+                                           HeadAcc& acc, v4s (&w1a)[2][2], float (&b1l)[2]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, l32 = lane & 31;
   for (int i = threadIdx.x; i < kHid * kHid; i += 256) {
     const int c = i / kHid, h = i % kHid;
-    s_w2t[h * kWtStride + c] = c < C ? W2[c * kHid + h] : (uint16_t)0;
+    L.w2t[h * kWtStride + c] = c < C ? W2[c * kHid + h] : (uint16_t)0;
   }
   for (int i = threadIdx.x; i < kHid * kDin; i += 256) {
     const int h = i / kDin, d = i % kDin;
-    s_w1t[d * kWtStride + h] = W1[h * kDin + d];
+    L.w1t[d * kWtStride + h] = W1[h * kDin + d];
   }
-  if (threadIdx.x < kHid) s_b1[threadIdx.x] = b1[threadIdx.x];
-  float* sg = s_buf + wave * kHid * kGst;
+  if (threadIdx.x < kHid) L.b1[threadIdx.x] = b1[threadIdx.x];
+  float* sg = L.buf + wave * kHid * kGst;
   for (int i = C * kGst + lane; i < kHid * kGst; i += 64) sg[i] = 0.0f;   // rows of absent classes
   __syncthreads();
-  v16f aW2[2][2], aW1[2];   // aW2[cb][hb]: D[c][h]; aW1[hb]: D[h][d]
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    aW1[i] = zero16();
-    aW2[i][0] = zero16();
-    aW2[i][1] = zero16();
+    acc.W1[i] = zero16();
+    acc.W2[i][0] = zero16();
+    acc.W2[i][1] = zero16();
+    acc.B2[i] = 0.0f;
   }
-  float aB2[2] = {0.0f, 0.0f};   // class l32 + 32 cb, this lane's pixels
   // W1 as A (i = hidden l32 + 32 hb, k = d 8 ks + 4 half + j), which is also W1^T as B (k = d, j = hidden)
-  v4s w1a[2][2];
 #pragma unroll
   for (int hb = 0; hb < 2; ++hb)
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
       for (int j = 0; j < 4; ++j) w1a[hb][ks][j] = (short)W1[(l32 + 32 * hb) * kDin + 8 * ks + 4 * half + j];
-  const float b1l[2] = {s_b1[l32], s_b1[l32 + 32]};
+  b1l[0] = L.b1[l32];
+  b1l[1] = L.b1[l32 + 32];
+}
 
+// Steps (1)-(5) for one 64-pixel chunk whose logit gradients are staged in sg [class][pixel].
+// Eb: plane 0 of the chunk's embedding (plane d at Eb + d HW); dEb the same in the gradient.
+template <bool ADD>
+__device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const float* sg, const float* Eb, float* dEb,
+                                                    int64_t HW, int nlive, const v4s (&w1a)[2][2],
+                                                    const float (&b1l)[2], HeadAcc& acc) {
+  const int lane = threadIdx.x & 63, half = lane >> 5, l32 = lane & 31;
+#pragma unroll 1
+  for (int pb = 0; pb < 2; ++pb) {
+    const int q = l32 + 32 * pb;
+    const bool qlive = q < nlive;
+    const float* Eq = Eb + 4 * half * HW + min(q, nlive - 1);   // plane 8 ks + 4 half + j at Eq + (8 ks + j) HW
+    const float* Gq = sg + 4 * half * kGst + q;                 // class 8 ks + 4 half + j at Gq + (8 ks + j) kGst
+    // (1) E with d in registers, pixels across lanes; the sign of the hidden pre-activations
+    v4s ehi[2], elo[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      float e[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float v = Eq[(8 * ks + j) * HW];
+        e[j] = qlive ? v : 0.0f;
+      }
+      split4(e, ehi[ks], elo[ks]);
+    }
+    uint32_t on[2];   // bit r: hidden unit drow(r) + 32 hb is active at this pixel
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      v16f h;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) h[r] = L.b1[drow(r, lane) + 32 * hb];
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        h = mfma(w1a[hb][ks], ehi[ks], h);
+        h = mfma(w1a[hb][ks], elo[ks], h);
+      }
+      uint32_t bits = 0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) bits |= (h[r] > 0.0f ? 1u : 0u) << r;
+      on[hb] = bits;
+    }
+
+    // (2) dH^T = W2^T dlogits^T: A = W2^T (i = hidden l32 + 32 hb, k = class 8 ks + 4 half + j)
+    v16f dHT[2] = {zero16(), zero16()};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      float x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] = Gq[(8 * ks + j) * kGst];
+      v4s hi, lo;
+      split4(x, hi, lo);
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb) {
+        const v4s a = *reinterpret_cast<const v4s*>(L.w2t + (l32 + 32 * hb) * kWtStride + 8 * ks + 4 * half);
+        dHT[hb] = mfma(a, hi, dHT[hb]);
+        dHT[hb] = mfma(a, lo, dHT[hb]);
+      }
+    }
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) dHT[hb][r] = ((on[hb] >> r) & 1u) ? dHT[hb][r] : 0.0f;
+
+    // (3) dE^T = W1^T dH^T: A = W1^T (i = d l32, k = hidden 8 ks + 4 half + j); B from the
+    // dH^T registers 4 (ks % 4) .. +3 of block ks / 4
+    {
+      v16f dE = zero16();
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        v4s a = {0, 0, 0, 0};
+        if (l32 < kDin) a = *reinterpret_cast<const v4s*>(L.w1t + l32 * kWtStride + 8 * ks + 4 * half);
+        float x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = dHT[ks >> 2][4 * (ks & 3) + j];
+        v4s hi, lo;
+        split4(x, hi, lo);
+        dE = mfma(a, hi, dE);
+        dE = mfma(a, lo, dE);
+      }
+      // rows 0..15 = d: added to what the caller's gradient holds there, or stored
+      if (qlive)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          float* dst = dEb + (int64_t)drow(r, lane) * HW + q;
+          if constexpr (ADD) *dst += dE[r];
+          else *dst = dE[r];
+        }
+    }
+
+    // Reloading from LDS below is cheaper than keeping (2)'s operands alive through (3).
+    asm volatile("" ::: "memory");
+    // (4) H with pixels in registers: A = E (i = pixel), B = W1^T (k = d, j = hidden l32 + 32 hb)
+    v16f H[2];
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      H[hb] = zero16();
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        H[hb] = mfma(ehi[ks], w1a[hb][ks], H[hb]);
+        H[hb] = mfma(elo[ks], w1a[hb][ks], H[hb]);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) H[hb][r] = fmaxf(H[hb][r] + b1l[hb], 0.0f);
+    }
+    // (5a) dW2[c][h] += sum_p dlogits[c][p] relu(H)[p][h] over the half's pixels
+    // p = 32 pb + 8 kk + 4 half + j (registers 4 kk + j): A = dlogits (i = class l32 + 32 cb, k = p)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int p0 = 32 * pb + 8 * kk + 4 * half;
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        float x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = sg[(l32 + 32 * cb) * kGst + p0 + j];
+        acc.B2[cb] += (x[0] + x[1]) + (x[2] + x[3]);
+        v4s ahi, alo;
+        split4(x, ahi, alo);
+#pragma unroll
+        for (int hb = 0; hb < 2; ++hb) {
+          float y[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) y[j] = H[hb][4 * kk + j];
+          v4s bhi, blo;
+          split4(y, bhi, blo);
+          acc.W2[cb][hb] = mfma(ahi, bhi, acc.W2[cb][hb]);
+          acc.W2[cb][hb] = mfma(ahi, blo, acc.W2[cb][hb]);
+          acc.W2[cb][hb] = mfma(alo, bhi, acc.W2[cb][hb]);
+        }
+      }
+    }
+    uint32_t onH[2];   // bit r: hidden unit l32 + 32 hb is active at pixel drow(r) of the half
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      uint32_t bits = 0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) bits |= (H[hb][r] > 0.0f ? 1u : 0u) << r;
+      onH[hb] = bits;
+    }
+    // (4b) dH with pixels in registers: A = dlogits (i = pixel, k = class), B = W2 (j = hidden)
+    v16f dH[2] = {zero16(), zero16()};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      float x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] = Gq[(8 * ks + j) * kGst];
+      v4s hi, lo;
+      split4(x, hi, lo);
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb) {
+        const v4s b = *reinterpret_cast<const v4s*>(L.w2t + (l32 + 32 * hb) * kWtStride + 8 * ks + 4 * half);
+        dH[hb] = mfma(hi, b, dH[hb]);
+        dH[hb] = mfma(lo, b, dH[hb]);
+      }
+    }
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) dH[hb][r] = ((onH[hb] >> r) & 1u) ? dH[hb][r] : 0.0f;
+    // (5b) dW1[h][d] += sum_p dH[p][h] [E, 1][p][d]: A = dH (i = hidden l32 + 32 hb, k = p), B = [E, 1] (j = d l32)
+    const float* Ed = Eb + (int64_t)min(l32, kDin - 1) * HW;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int p0 = 32 * pb + 8 * kk + 4 * half;
+      float e[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float v = Ed[min(p0 + j, nlive - 1)];
+        e[j] = p0 + j >= nlive ? 0.0f : (l32 < kDin ? v : (l32 == kDin ? 1.0f : 0.0f));
+      }
+      v4s bhi, blo;
+      split4(e, bhi, blo);
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb) {
+        float y[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) y[j] = dH[hb][4 * kk + j];
+        v4s ahi, alo;
+        split4(y, ahi, alo);
+        acc.W1[hb] = mfma(ahi, bhi, acc.W1[hb]);
+        acc.W1[hb] = mfma(ahi, blo, acc.W1[hb]);
+        acc.W1[hb] = mfma(alo, bhi, acc.W1[hb]);
+      }
+    }
+  }
+}
+
+// Sums the block's four waves' accumulators in LDS and writes the block's partial.
+__device__ __forceinline__ void head_write_partial(HeadLds& L, const HeadAcc& acc, float* __restrict__ partial) {
+  const int lane = threadIdx.x & 63, l32 = lane & 31;
+  float* s_acc = L.buf;
+  __syncthreads();
+  for (int i = threadIdx.x; i < kPart; i += 256) s_acc[i] = 0.0f;
+  __syncthreads();
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int c = drow(r, lane) + 32 * cb;   // D[c][h]: h = l32 + 32 hb
+        atomicAdd(&s_acc[c * 64 + l32 + 32 * hb], acc.W2[cb][hb][r]);
+      }
+    atomicAdd(&s_acc[kPartW2 + kPartW1 + l32 + 32 * cb], acc.B2[cb]);
+  }
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) atomicAdd(&s_acc[kPartW2 + (drow(r, lane) + 32 * hb) * 32 + l32], acc.W1[hb][r]);
+  __syncthreads();
+  float* out = partial + (int64_t)blockIdx.x * kPart;
+  for (int i = threadIdx.x; i < kPart; i += 256) out[i] = s_acc[i];
+}
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256, 1) void k_head_bwd(const gs_item* __restrict__ items, int n_items, int K, int C,
+                                                     const float* __restrict__ color,
+                                                     const float* __restrict__ glogits,
+                                                     const uint16_t* __restrict__ W1, const float* __restrict__ b1,
+                                                     const uint16_t* __restrict__ W2, float* __restrict__ gcolor,
+                                                     float* __restrict__ partial) {
+  __shared__ HeadLds L;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  HeadAcc acc;
+  v4s w1a[2][2];
+  float b1l[2];
+  head_setup(L, C, W1, b1, W2, acc, w1a, b1l);
+  float* sg = L.buf + wave * kHid * kGst;
   ChunkCursor cur;
   cur.item = 0;
   cur.first = 0;
@@ -257,8 +497,6 @@ __global__ __launch_bounds__(256, 1) void k_head_bwd(const gs_item* __restrict__
     const int64_t HW = (int64_t)it.W * it.H;
     const int64_t local0 = (chunk - cur.first) * 64;
     const int nlive = (int)min((int64_t)64, HW - local0);
-    const float* Eb = color + it.pixel_base * K + 4 * HW + local0;    // plane d at Eb + d HW
-    float* dEb = gcolor + it.pixel_base * K + 4 * HW + local0;
     {
       // stage: lane = pixel, one coalesced row per class; dead pixels are zero
       // (16 rows' loads in flight per round trip)
@@ -273,211 +511,205 @@ __global__ __launch_bounds__(256, 1) void k_head_bwd(const gs_item* __restrict__
           if (c0 + k < C) sg[(c0 + k) * kGst + lane] = live ? v[k] : 0.0f;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_fence();
+    head_chunk_backward<true>(L, sg, color + it.pixel_base * K + 4 * HW + local0,
+                              gcolor + it.pixel_base * K + 4 * HW + local0, HW, nlive, w1a, b1l, acc);
+    // every lane is past this chunk's reads of the staged rows before the next chunk writes them
+    wave_fence();
+  }
+  head_write_partial(L, acc, partial);
+}
 
+// Learned-mode loss with the decode fused in (paper eq. 10-13 with the semantic term a
+// cross-entropy on the head's logits): per 64-pixel chunk of one item, the L1 colour and
+// depth terms (lane = pixel, as in the plain loss), the decode logits = W2 relu(W1 E + b1)
+// + b2 on the matrix cores, the cross-entropy against the label and its logit gradient
+// w2 (softmax - onehot) / HW, staged in LDS, then the head's backward (steps (1)-(5) above)
+// storing dL/dE in the colour-gradient planes 4..19 and accumulating the weight gradients.
+// No logits touch global memory. Loss partial sums go to the same per-item slots as the
+// plain loss's.
+__global__ __launch_bounds__(256, 1) void k_head_loss(const gs_item* __restrict__ items, int n_items, int K, int C,
+                                                      const float* __restrict__ color, const float* __restrict__ trgb,
+                                                      const float* __restrict__ tdepth,
+                                                      const int32_t* __restrict__ tlabel,
+                                                      const uint16_t* __restrict__ W1, const float* __restrict__ b1,
+                                                      const uint16_t* __restrict__ W2, const float* __restrict__ b2,
+                                                      float w0, float w2, bool rgb_grad, int n_slots,
+                                                      float* __restrict__ loss_slots, float* __restrict__ count_slots,
+                                                      float* __restrict__ gcolor, float* __restrict__ partial) {
+  __shared__ HeadLds L;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l32 = lane & 31;
+  HeadAcc acc;
+  v4s w1a[2][2];
+  float b1l[2];
+  head_setup(L, C, W1, b1, W2, acc, w1a, b1l);
+  float* sg = L.buf + wave * kHid * kGst;
+  // b2 of this lane's classes drow(r) + 32 cb
+  float b2r[2][16];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int c = drow(r, lane) + 32 * cb;
+      b2r[cb][r] = c < C ? b2[c] : 0.0f;
+    }
+  ChunkCursor cur;
+  cur.item = 0;
+  cur.first = 0;
+  cur.end = item_chunks(items[0]);
+  for (int64_t chunk = (int64_t)blockIdx.x * 4 + wave;; chunk += (int64_t)gridDim.x * 4) {
+    if (!seek_chunk(items, n_items, chunk, cur)) break;
+    const gs_item it = items[cur.item];
+    const int64_t HW = (int64_t)it.W * it.H;
+    const int64_t local0 = (chunk - cur.first) * 64;
+    const int nlive = (int)min((int64_t)64, HW - local0);
+    const float invp = 1.0f / (float)HW;
+    // L1 colour and depth, lane = pixel
+    const bool live = lane < nlive;
+    const int64_t p = local0 + min(lane, nlive - 1);
+    const int64_t cbase = it.pixel_base * K + p, tbase = it.pixel_base * 3 + p;
+    float col[4], tr[3];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) col[ch] = __builtin_nontemporal_load(&color[cbase + ch * HW]);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) tr[ch] = __builtin_nontemporal_load(&trgb[tbase + ch * HW]);
+    const float td = __builtin_nontemporal_load(&tdepth[it.pixel_base + p]);
+    const int y_own = __builtin_nontemporal_load(&tlabel[it.pixel_base + p]);
+    float lr = 0.0f, ld = 0.0f, nv = 0.0f, ls = 0.0f;
+    {
+      const float inv3 = 1.0f / (3.0f * (float)HW);
+      float gc[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const float d = col[ch] - tr[ch];
+        lr += fabsf(d) * inv3;
+        gc[ch] = w0 * (float)((d > 0.0f) - (d < 0.0f)) * inv3;
+      }
+      float gd = 0.0f;
+      if (td > 0.0f) {
+        const float d = col[3] - td;
+        ld = fabsf(d);
+        nv = 1.0f;
+        gd = (float)((d > 0.0f) - (d < 0.0f));
+      }
+      if (live) {
+        if (rgb_grad)
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) __builtin_nontemporal_store(gc[ch], &gcolor[cbase + ch * HW]);
+        __builtin_nontemporal_store(gd, &gcolor[cbase + 3 * HW]);
+      } else {
+        lr = ld = nv = 0.0f;
+      }
+    }
+    const float* Eb = color + it.pixel_base * K + 4 * HW + local0;
+    // decode and cross-entropy per 32-pixel half: logits^T[cb][.] in D layout, lane l holding
+    // pixel 32 pb + l32, classes drow(r) + 32 cb; each pixel's classes span lanes l32 and l32 + 32
 #pragma unroll 1
     for (int pb = 0; pb < 2; ++pb) {
       const int q = l32 + 32 * pb;
       const bool qlive = q < nlive;
-      const float* Eq = Eb + 4 * half * HW + min(q, nlive - 1);   // plane 8 ks + 4 half + j at Eq + (8 ks + j) HW
-      const float* Gq = sg + 4 * half * kGst + q;                 // class 8 ks + 4 half + j at Gq + (8 ks + j) kGst
-      // (1) E with d in registers, pixels across lanes; the sign of the hidden pre-activations
-      v4s ehi[2], elo[2];
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        float e[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float v = Eq[(8 * ks + j) * HW];
-          e[j] = qlive ? v : 0.0f;
-        }
-        split4(e, ehi[ks], elo[ks]);
-      }
-      uint32_t on[2];   // bit r: hidden unit drow(r) + 32 hb is active at this pixel
-#pragma unroll
-      for (int hb = 0; hb < 2; ++hb) {
-        v16f h;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) h[r] = s_b1[drow(r, lane) + 32 * hb];
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-          h = mfma(w1a[hb][ks], ehi[ks], h);
-          h = mfma(w1a[hb][ks], elo[ks], h);
-        }
-        uint32_t bits = 0;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) bits |= (h[r] > 0.0f ? 1u : 0u) << r;
-        on[hb] = bits;
-      }
-
-      // (2) dH^T = W2^T dlogits^T: A = W2^T (i = hidden l32 + 32 hb, k = class 8 ks + 4 half + j)
-      v16f dHT[2] = {zero16(), zero16()};
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        float x[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = Gq[(8 * ks + j) * kGst];
-        v4s hi, lo;
-        split4(x, hi, lo);
-#pragma unroll
-        for (int hb = 0; hb < 2; ++hb) {
-          const v4s a = *reinterpret_cast<const v4s*>(s_w2t + (l32 + 32 * hb) * kWtStride + 8 * ks + 4 * half);
-          dHT[hb] = mfma(a, hi, dHT[hb]);
-          dHT[hb] = mfma(a, lo, dHT[hb]);
-        }
-      }
-#pragma unroll
-      for (int hb = 0; hb < 2; ++hb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) dHT[hb][r] = ((on[hb] >> r) & 1u) ? dHT[hb][r] : 0.0f;
-
-      // (3) dE^T = W1^T dH^T: A = W1^T (i = d l32, k = hidden 8 ks + 4 half + j); B from the
-      // dH^T registers 4 (ks % 4) .. +3 of block ks / 4
-      {
-        v16f dE = zero16();
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-          v4s a = {0, 0, 0, 0};
-          if (l32 < kDin) a = *reinterpret_cast<const v4s*>(s_w1t + l32 * kWtStride + 8 * ks + 4 * half);
-          float x[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) x[j] = dHT[ks >> 2][4 * (ks & 3) + j];
-          v4s hi, lo;
-          split4(x, hi, lo);
-          dE = mfma(a, hi, dE);
-          dE = mfma(a, lo, dE);
-        }
-        // added to what the caller's gradient holds for the embedding channels (rows 0..15 = d)
-        if (qlive)
-#pragma unroll
-          for (int r = 0; r < 8; ++r) dEb[(int64_t)drow(r, lane) * HW + q] += dE[r];
-      }
-
-      // Reloading from LDS below is cheaper than keeping (2)'s operands alive through (3).
-      asm volatile("" ::: "memory");
-      // (4) H with pixels in registers: A = E (i = pixel), B = W1^T (k = d, j = hidden l32 + 32 hb)
+      const int y = __shfl(y_own, q, 64);
       v16f H[2];
+      {
+        const float* Eq = Eb + min(q, nlive - 1);
 #pragma unroll
-      for (int hb = 0; hb < 2; ++hb) {
-        H[hb] = zero16();
+        for (int hb = 0; hb < 2; ++hb) H[hb] = zero16();
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-          H[hb] = mfma(ehi[ks], w1a[hb][ks], H[hb]);
-          H[hb] = mfma(elo[ks], w1a[hb][ks], H[hb]);
-        }
+          float e[4];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) H[hb][r] = fmaxf(H[hb][r] + b1l[hb], 0.0f);
-      }
-      // (5a) dW2[c][h] += sum_p dlogits[c][p] relu(H)[p][h] over the half's pixels
-      // p = 32 pb + 8 kk + 4 half + j (registers 4 kk + j): A = dlogits (i = class l32 + 32 cb, k = p)
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int p0 = 32 * pb + 8 * kk + 4 * half;
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          float x[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) x[j] = sg[(l32 + 32 * cb) * kGst + p0 + j];
-          aB2[cb] += (x[0] + x[1]) + (x[2] + x[3]);
-          v4s ahi, alo;
-          split4(x, ahi, alo);
+          for (int j = 0; j < 4; ++j) {
+            const float v = Eq[(int64_t)(8 * ks + 4 * (lane >> 5) + j) * HW];
+            e[j] = qlive ? v : 0.0f;
+          }
+          v4s hi, lo;
+          split4(e, hi, lo);
 #pragma unroll
           for (int hb = 0; hb < 2; ++hb) {
-            float y[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) y[j] = H[hb][4 * kk + j];
-            v4s bhi, blo;
-            split4(y, bhi, blo);
-            aW2[cb][hb] = mfma(ahi, bhi, aW2[cb][hb]);
-            aW2[cb][hb] = mfma(ahi, blo, aW2[cb][hb]);
-            aW2[cb][hb] = mfma(alo, bhi, aW2[cb][hb]);
+            H[hb] = mfma(w1a[hb][ks], hi, H[hb]);
+            H[hb] = mfma(w1a[hb][ks], lo, H[hb]);
           }
         }
+#pragma unroll
+        for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) H[hb][r] = fmaxf(H[hb][r] + L.b1[drow(r, lane) + 32 * hb], 0.0f);
       }
-      uint32_t onH[2];   // bit r: hidden unit l32 + 32 hb is active at pixel drow(r) of the half
+      v16f Lg[2];
 #pragma unroll
-      for (int hb = 0; hb < 2; ++hb) {
-        uint32_t bits = 0;
+      for (int cb = 0; cb < 2; ++cb) {
+        Lg[cb] = zero16();
+        const int cls = l32 + 32 * cb;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) bits |= (H[hb][r] > 0.0f ? 1u : 0u) << r;
-        onH[hb] = bits;
-      }
-      // (4b) dH with pixels in registers: A = dlogits (i = pixel, k = class), B = W2 (j = hidden)
-      v16f dH[2] = {zero16(), zero16()};
+        for (int ks = 0; ks < 8; ++ks) {
+          // A = W2 (i = class l32 + 32 cb, k = hidden 8 ks + 4 (l / 32) + j)
+          v4s a;
 #pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        float x[4];
+          for (int j = 0; j < 4; ++j) a[j] = cls < C ? (short)W2[(int64_t)cls * kHid + 8 * ks + 4 * (lane >> 5) + j] : (short)0;
+          float x[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = Gq[(8 * ks + j) * kGst];
-        v4s hi, lo;
-        split4(x, hi, lo);
-#pragma unroll
-        for (int hb = 0; hb < 2; ++hb) {
-          const v4s b = *reinterpret_cast<const v4s*>(s_w2t + (l32 + 32 * hb) * kWtStride + 8 * ks + 4 * half);
-          dH[hb] = mfma(hi, b, dH[hb]);
-          dH[hb] = mfma(lo, b, dH[hb]);
+          for (int j = 0; j < 4; ++j) x[j] = H[ks >> 2][4 * (ks & 3) + j];
+          v4s hi, lo;
+          split4(x, hi, lo);
+          Lg[cb] = mfma(a, hi, Lg[cb]);
+          Lg[cb] = mfma(a, lo, Lg[cb]);
         }
       }
+      // softmax over the pixel's classes: this lane's 32, then the partner lane's
+      float m = -INFINITY;
 #pragma unroll
-      for (int hb = 0; hb < 2; ++hb)
+      for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) dH[hb][r] = ((onH[hb] >> r) & 1u) ? dH[hb][r] : 0.0f;
-      // (5b) dW1[h][d] += sum_p dH[p][h] [E, 1][p][d]: A = dH (i = hidden l32 + 32 hb, k = p), B = [E, 1] (j = d l32)
-      const float* Ed = Eb + (int64_t)min(l32, kDin - 1) * HW;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int p0 = 32 * pb + 8 * kk + 4 * half;
-        float e[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float v = Ed[min(p0 + j, nlive - 1)];
-          e[j] = p0 + j >= nlive ? 0.0f : (l32 < kDin ? v : (l32 == kDin ? 1.0f : 0.0f));
+        for (int r = 0; r < 16; ++r) {
+          const int c = drow(r, lane) + 32 * cb;
+          const float v = c < C ? Lg[cb][r] + b2r[cb][r] : -INFINITY;
+          Lg[cb][r] = v;
+          m = fmaxf(m, v);
         }
-        v4s bhi, blo;
-        split4(e, bhi, blo);
+      m = fmaxf(m, __shfl_xor(m, 32, 64));
+      float z = 0.0f, xy = 0.0f;
 #pragma unroll
-        for (int hb = 0; hb < 2; ++hb) {
-          float y[4];
+      for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) y[j] = dH[hb][4 * kk + j];
-          v4s ahi, alo;
-          split4(y, ahi, alo);
-          aW1[hb] = mfma(ahi, bhi, aW1[hb]);
-          aW1[hb] = mfma(ahi, blo, aW1[hb]);
-          aW1[hb] = mfma(alo, bhi, aW1[hb]);
+        for (int r = 0; r < 16; ++r) {
+          const int c = drow(r, lane) + 32 * cb;
+          xy = c == y ? Lg[cb][r] : xy;
+          const float e = c < C ? __expf(Lg[cb][r] - m) : 0.0f;
+          Lg[cb][r] = e;
+          z += e;
         }
-      }
+      z += __shfl_xor(z, 32, 64);
+      xy += __shfl_xor(xy, 32, 64);
+      const bool labelled = qlive && y >= 0 && y < C;   // outside [0, C): unlabelled, no semantic term
+      if (labelled && lane < 32) ls += (m + __logf(z) - xy) * invp;
+      const float sc = labelled ? w2 * invp / z : 0.0f;
+      const float oh = labelled ? w2 * invp : 0.0f;
+      // dlogits to LDS [class][pixel] (rows of absent classes stay zero)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int c = drow(r, lane) + 32 * cb;
+          if (c < C) sg[c * kGst + q] = Lg[cb][r] * sc - (c == y ? oh : 0.0f);
+        }
     }
-    // every lane is past this chunk's reads of the staged rows before the next chunk writes them
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-  // sum the four waves' accumulators and write the block's partial
-  float* s_acc = s_buf;
-  __syncthreads();
-  for (int i = threadIdx.x; i < kPart; i += 256) s_acc[i] = 0.0f;
-  __syncthreads();
-#pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-#pragma unroll
-    for (int hb = 0; hb < 2; ++hb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int c = drow(r, lane) + 32 * cb;   // D[c][h]: h = l32 + 32 hb
-        atomicAdd(&s_acc[c * 64 + l32 + 32 * hb], aW2[cb][hb][r]);
+    wave_fence();
+    head_chunk_backward<false>(L, sg, Eb, gcolor + it.pixel_base * K + 4 * HW + local0, HW, nlive, w1a, b1l, acc);
+    wave_fence();
+    // loss partial sums: one atomic per wave and quantity (a chunk lies in one item)
+    const float a = wave_sum(lr), bsum = wave_sum(ld), c = wave_sum(ls), v = wave_sum(nv);
+    if (lane == 0) {
+      const int slot = (int)(chunk % n_slots);
+      float* loss = loss_slots + slot;
+      atomicAdd(&loss[(3 * cur.item + 0) * n_slots], a);
+      if (v != 0.0f) {
+        atomicAdd(&loss[(3 * cur.item + 1) * n_slots], bsum);
+        atomicAdd(&count_slots[cur.item * n_slots + slot], v);
       }
-    atomicAdd(&s_acc[kPartW2 + kPartW1 + l32 + 32 * cb], aB2[cb]);
+      atomicAdd(&loss[(3 * cur.item + 2) * n_slots], c);
+    }
   }
-#pragma unroll
-  for (int hb = 0; hb < 2; ++hb)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) atomicAdd(&s_acc[kPartW2 + (drow(r, lane) + 32 * hb) * 32 + l32], aW1[hb][r]);
-  __syncthreads();
-  float* out = partial + (int64_t)blockIdx.x * kPart;
-  for (int i = threadIdx.x; i < kPart; i += 256) out[i] = s_acc[i];
+  head_write_partial(L, acc, partial);
 }
 
 // Sums the per-block partials into the head's weight gradients: block = 64 columns,
@@ -534,6 +766,21 @@ int launch_head_bwd(const gs_item* items, int n_items, int64_t P, int K, const g
   const int blocks = (int)std::min<int64_t>(std::min(kHeadBlocksMax, resident), ceil_div(ceil_div(P, 64) + n_items, 4));
   hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(256), 0, s, items, n_items, K, h.n_classes, color, glogits, h.W1,
                      h.b1, h.W2, gcolor, partial);
+  hipLaunchKernelGGL(k_head_reduce, dim3((unsigned)ceil_div(kPart, 64)), dim3(256), 0, s, partial, blocks, h.n_classes,
+                     gW1, gb1, gW2, gb2);
+  return launch_status();
+}
+
+int launch_head_loss(const gs_item* items, int n_items, int64_t P, int K, const gs_head& h, const float* color,
+                     const gs_targets& t, float w0, float w2, bool rgb_grad, int n_slots, float* loss_slots,
+                     float* count_slots, float* gcolor, float* partial, float* gW1, float* gb1, float* gW2, float* gb2,
+                     hipStream_t s) {
+  if (P == 0) return GS_OK;
+  const int resident = resident_blocks(k_head_loss, 256, kHeadBlocksMax);
+  const int blocks = (int)std::min<int64_t>(std::min(kHeadBlocksMax, resident), ceil_div(ceil_div(P, 64) + n_items, 4));
+  hipLaunchKernelGGL(k_head_loss, dim3(blocks), dim3(256), 0, s, items, n_items, K, h.n_classes, color, t.rgb, t.depth,
+                     t.label, h.W1, h.b1, h.W2, h.b2, w0, w2, rgb_grad, n_slots, loss_slots, count_slots, gcolor,
+                     partial);
   hipLaunchKernelGGL(k_head_reduce, dim3((unsigned)ceil_div(kPart, 64)), dim3(256), 0, s, partial, blocks, h.n_classes,
                      gW1, gb1, gW2, gb2);
   return launch_status();

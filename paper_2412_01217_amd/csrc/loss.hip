@@ -635,16 +635,26 @@ int launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   return launch_status();
 }
 
+size_t head_bwd_workspace();
+int launch_head_loss(const gs_item* items, int n_items, int64_t P, int K, const gs_head& h, const float* color,
+                     const gs_targets& t, float w0, float w2, bool rgb_grad, int n_slots, float* loss_slots,
+                     float* count_slots, float* gcolor, float* partial, float* gW1, float* gb1, float* gW2, float* gb2,
+                     hipStream_t s);
+
 // Workspace: count slots [n][kSlots], loss slots [n][3][kSlots], SSIM slots [n][kSlots],
-// n_valid [n], then the SSIM tile prefix [n + 1] (int64, 8-byte aligned).
+// n_valid [n], then the SSIM tile prefix [n + 1] (int64, 8-byte aligned), then the learned
+// head's per-block weight-gradient partials (256-byte aligned).
 static size_t loss_prefix_offset(int n_items) {
   return (sizeof(float) * (size_t)std::max(n_items, 1) * (5 * kSlots + 1) + 7) / 8 * 8;
 }
-size_t loss_workspace(int n_items) { return loss_prefix_offset(n_items) + sizeof(int64_t) * ((size_t)n_items + 1); }
+static size_t loss_head_offset(int n_items) {
+  return align_up(loss_prefix_offset(n_items) + sizeof(int64_t) * ((size_t)n_items + 1));
+}
+size_t loss_workspace(int n_items) { return loss_head_offset(n_items) + head_bwd_workspace(); }
 
 int launch_loss(const gs_item* items, int n_items, int64_t P, int K, int n_classes, const float* color,
-                const float* logits, const gs_targets& t, const float* w, float lambda, float* loss, float* gcolor,
-                float* glogits, float* ws, hipStream_t s) {
+                const float* logits, const gs_targets& t, const gs_head* head, const float* w, float lambda,
+                float* loss, float* gcolor, float* glogits, const gs_grads* head_grads, float* ws, hipStream_t s) {
   const unsigned pb = (unsigned)std::max<int64_t>(1, ceil_div(P, 256));
   float* count_slots = ws;                                   // [n_items][kSlots]
   float* loss_slots = ws + (int64_t)n_items * kSlots;        // [n_items][3][kSlots]
@@ -655,7 +665,13 @@ int launch_loss(const gs_item* items, int n_items, int64_t P, int K, int n_class
   launch_fill_f32(ws, (int64_t)n_items * 5 * kSlots, 0.0f, s);
 #define GS_LOSS_ARGS items, n_items, P, K, n_classes, color, logits, t.rgb, t.depth, t.label, w[0], w[2], !ssim, \
                      loss_slots, count_slots, gcolor, glogits
-  if (n_classes == 0) hipLaunchKernelGGL(k_loss<0>, dim3(pb), dim3(256), 0, s, GS_LOSS_ARGS);
+  if (head) {
+    float* partial = (float*)((char*)ws + loss_head_offset(n_items));
+    const int st = launch_head_loss(items, n_items, P, K, *head, color, t, w[0], w[2], !ssim, kSlots, loss_slots,
+                                    count_slots, gcolor, partial, head_grads->head_W1, head_grads->head_b1,
+                                    head_grads->head_W2, head_grads->head_b2, s);
+    if (st) return st;
+  } else if (n_classes == 0) hipLaunchKernelGGL(k_loss<0>, dim3(pb), dim3(256), 0, s, GS_LOSS_ARGS);
   else if (n_classes <= 16) hipLaunchKernelGGL(k_loss<16>, dim3(pb), dim3(256), 0, s, GS_LOSS_ARGS);
   else if (n_classes <= 32) hipLaunchKernelGGL(k_loss<32>, dim3(pb), dim3(256), 0, s, GS_LOSS_ARGS);
   else if (n_classes <= 64) hipLaunchKernelGGL(k_loss<64>, dim3(pb), dim3(256), 0, s, GS_LOSS_ARGS);

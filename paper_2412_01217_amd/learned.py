@@ -5,8 +5,8 @@ semantic features directly, eq. 9; the learned form replaces the C-wide feature 
 
 Training objective (a reading, the paper has no learned head): soft-target
 cross-entropy of the decoded logits against the plain render plus 0.1 times their
-mean squared difference; Adam, lr 1e-3 for the MLP and 1e-2 for the embeddings; one
-random view (with its pyramid) per step, either drawn from a fixed pool or generated
+mean squared difference; Adam, lr 3e-3 for the MLP and 3e-2 for the embeddings, both
+decayed to 0 by a half cosine over the steps; one random view (with its pyramid) per step, either drawn from a fixed pool or generated
 fresh for every step so that every Gaussian is eventually seen. Forward, backward,
 loss and optimizer all run in the library's kernels; geometry is held fixed, so a
 pooled view's projection and binning are computed once.
@@ -107,7 +107,7 @@ class Trainer:
         raster.render_fwd(self.cfg_learned, self.g_learned, vs.proj, vs.fr, vs.sorter, out=vs.img,
                           head=self.head.as_dict())
 
-    def train(self, steps: int, lr_mlp=1e-3, lr_emb=1e-2, mse_w=0.1, schedule="constant"):
+    def train(self, steps: int, lr_mlp=3e-3, lr_emb=3e-2, mse_w=0.1, schedule="cosine"):
         """schedule: "constant" rates, or "cosine" (each rate times (1 + cos(pi k / steps)) / 2
         at step k, decaying to 0 at the end)."""
         losses = []

@@ -202,8 +202,8 @@ def head_struct(head: dict | None):
 def render_fwd(cfg, g: dict, proj: dict, frame: Frame, sorter: Sorter, out=None, head=None, split=True) -> dict:
     """split: allocate the forward state (long lists composited in segments) when out is
     not given; a given out carries its own (or no) state."""
-    learned = g.get("emb") is not None
-    out = out or alloc_images(cfg, frame, int(head["b2"].shape[0]) if learned else 0, learned,
+    decode = head is not None
+    out = out or alloc_images(cfg, frame, int(head["b2"].shape[0]) if decode else 0, decode,
                               state_capacity=sorter.capacity if split else None)
     gs = gaussians_struct(g)
     ps = _projected(proj)
@@ -217,11 +217,15 @@ def render_fwd(cfg, g: dict, proj: dict, frame: Frame, sorter: Sorter, out=None,
 
 
 def loss(cfg, frame: Frame, n_classes: int, rendered: dict, targets: dict, w=(1.0, 1.0, 1.0), grad=None,
-         loss_out=None, ws=None):
+         loss_out=None, ws=None, head=None, grads=None):
+    """Per-item loss parts [n_items, 3] and the image gradient. Learned mode with `head`: the
+    decode runs inside the loss, grad["color"] channels 4.. receive dL/dE and grads'
+    head_W1 .. head_b2 the head's weight gradients (grads: a dict with those four tensors)."""
     dev = frame.device
     if grad is None:
         grad = dict(color=torch.empty_like(rendered["color"]),
-                    logits=torch.empty_like(rendered["logits"]) if rendered.get("logits") is not None else None)
+                    logits=(torch.empty_like(rendered["logits"])
+                            if rendered.get("logits") is not None and head is None else None))
     loss_out = loss_out if loss_out is not None else torch.empty(3 * frame.n_items, dtype=torch.float32, device=dev)
     ws = ws if ws is not None else torch.empty(workspace_bytes(L.GS_WS_LOSS, cfg, frame, 0), dtype=torch.uint8,
                                                device=dev)
@@ -230,9 +234,15 @@ def loss(cfg, frame: Frame, n_classes: int, rendered: dict, targets: dict, w=(1.
     wv = (ctypes.c_float * 3)(*[float(x) for x in w])
     ri = _images(rendered, frame.n_pixels)
     gi = _images(grad, frame.n_pixels)
+    hs = head_struct(head)
+    gr = None
+    if head is not None:
+        gr = L.Grads(*(None if grads.get(k) is None else grads[k].data_ptr() for k in GRAD_FIELDS))
     L.check(L.lib().gs_pyramid_loss(ctypes.byref(cfg), _ptr(frame.items_dev), frame.n_items, frame.n_pixels,
-                                    n_classes, ctypes.byref(ri), ctypes.byref(t), wv, _ptr(loss_out),
-                                    ctypes.byref(gi), _ptr(ws), ws.numel(), _stream(dev)), "gs_pyramid_loss")
+                                    n_classes, ctypes.byref(ri), ctypes.byref(t),
+                                    ctypes.byref(hs) if hs is not None else None, wv, _ptr(loss_out),
+                                    ctypes.byref(gi), ctypes.byref(gr) if gr is not None else None, _ptr(ws),
+                                    ws.numel(), _stream(dev)), "gs_pyramid_loss")
     return loss_out.view(frame.n_items, 3), grad
 
 

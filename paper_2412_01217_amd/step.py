@@ -3,7 +3,10 @@ buffer allocated up front, so that it can be replayed eagerly or as a HIP graph.
 
 run(): projection -> binning -> compositing -> per-level loss -> backward, all items
        of the frame, through the C ABI on the current torch stream. With a head
-       (learned mode) the loss's semantic term acts on the decoded logits. With SH bands
+       (learned mode) the loss's semantic term acts on the decoded logits: by default the
+       decode, its cross-entropy and the decode's backward run inside the loss call
+       (fused_head), so no logits are stored; fused_head=False decodes in the forward and
+       differentiates the head in the backward instead. With SH bands
        (`sh`), the per-view features are evaluated after the projection and the backward
        ends with their gradients (to the bands in `sh_grads`, to means and poses in place).
 """
@@ -17,7 +20,8 @@ from . import raster
 
 class MappingStep:
     def __init__(self, cfg, frame: raster.Frame, g: dict, targets: dict, n_classes: int, w=(1.0, 1.0, 1.0),
-                 capacity_margin=1.15, head: dict | None = None, split=True, sh: dict | None = None):
+                 capacity_margin=1.15, head: dict | None = None, split=True, sh: dict | None = None,
+                 fused_head=True):
         if sh is not None and not cfg.view_features:
             raise ValueError("SH features need a config with view_features = 1")
         self.cfg, self.frame, self.g, self.targets = cfg, frame, g, targets
@@ -39,10 +43,12 @@ class MappingStep:
         del probe
         self.sorter = raster.Sorter(cfg, frame, n, capacity=int(self.n_dup_probe * capacity_margin) + 4096)
         learned = head is not None
-        self.img = raster.alloc_images(cfg, frame, n_classes if learned else 0, learned,
+        self.fused_head = learned and fused_head
+        decode = learned and not self.fused_head          # logits stored between the calls
+        self.img = raster.alloc_images(cfg, frame, n_classes if decode else 0, decode,
                                        state_capacity=self.sorter.capacity if split else None)
         self.grad = dict(color=torch.zeros_like(self.img["color"]),
-                         logits=torch.empty_like(self.img["logits"]) if learned else None)
+                         logits=torch.empty_like(self.img["logits"]) if decode else None)
         self.loss = torch.empty(3 * frame.n_items, dtype=torch.float32, device=dev)
         self.loss_ws = torch.empty(raster.workspace_bytes(L.GS_WS_LOSS, cfg, frame, n), dtype=torch.uint8,
                                    device=dev)
@@ -69,15 +75,16 @@ class MappingStep:
         self.sorter.run(self.proj)
         if ev:
             ev[1].record()
-        raster.render_fwd(cfg, gr, self.proj, fr, self.sorter, out=self.img, head=self.head)
+        fused = self.fused_head
+        raster.render_fwd(cfg, gr, self.proj, fr, self.sorter, out=self.img, head=None if fused else self.head)
         if ev:
             ev[2].record()
         raster.loss(cfg, fr, self.n_classes, self.img, self.targets, w=self.w, grad=self.grad, loss_out=self.loss,
-                    ws=self.loss_ws)
+                    ws=self.loss_ws, head=self.head if fused else None, grads=self.grads)
         if ev:
             ev[3].record()
         raster.render_bwd(cfg, gr, self.proj, fr, self.sorter, self.img, self.grad, grads=self.grads, ws=self.bwd_ws,
-                          head=self.head)
+                          head=None if fused else self.head)
         if self.sh is not None:
             raster.sh_features_bwd(g, self.sh, fr, self.grads, out=self.sh_grads)
         if ev:

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2412_01217_amd import scenes
-from tests.helpers import flagged, pixel_mask_to_channels, rel_check
+from tests.helpers import flagged, pixel_mask_to_channels, rel_check, targets_from_random
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -188,3 +188,85 @@ def test_training_improves_argmax_agreement():
     assert after["agreement"] > 0.8
     assert after["agreement"] > before["agreement"] + 0.4
     assert after["logit_rmse"] < before["logit_rmse"]
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.2])
+@pytest.mark.parametrize("C", [20, 52])
+def test_fused_learned_loss_matches_oracle(C, lam):
+    """The loss with the decode inside it (gs_pyramid_loss with a head): loss parts, the
+    colour and depth gradients, dL/dE in the embedding channels and the head's weight
+    gradients, against the oracle's loss on the oracle's decode followed by the oracle's
+    head backward. Pixels near a ReLU kink are left unlabelled (no semantic term)."""
+    from paper_2412_01217_amd import raster
+    views = [scenes.identity_view(72, 40, levels=2), scenes.identity_view(16, 8, levels=1)]
+    cfg = raster.config(16, ssim_lambda=lam)
+    fr = raster.Frame(cfg, views)
+    its = oracle.items(views)
+    P = fr.n_pixels
+    img = scenes.random_image(P, 20, seed=5600).astype(np.float64)
+    hw = _head(C, seed=6003)
+    W1, b1, W2, b2 = _w(hw)
+    E = _pixels_by_channel(img, its, 20)[:, 4:]
+    t_rgb, t_depth, t_lab = targets_from_random(views, C, seed=4003)
+    near = relu_flagged(E, W1, b1)
+    flagged(near, "pixels near a ReLU kink (64 units each)", bound=0.02)
+    t_lab = np.where(near, -1, t_lab).astype(np.int32)
+    w = (0.8, 1.1, 0.6)
+    # oracle: decode, then the loss on [rgb, depth, logits], then the head backward
+    logits = oracle.head_forward(E, W1, b1, W2, b2)
+    img_l = np.zeros(P * (4 + C))
+    for it in its:
+        HW = it["W"] * it["H"]
+        src = img[it["pix0"] * 20: it["pix0"] * 20 + 20 * HW].reshape(20, HW)
+        dst = img_l[it["pix0"] * (4 + C): it["pix0"] * (4 + C) + (4 + C) * HW].reshape(4 + C, HW)
+        dst[:4] = src[:4]
+        dst[4:] = logits[it["pix0"]: it["pix0"] + HW].T
+    ls_ref, g_ref = oracle.loss(views, C, img_l, t_rgb, t_depth, t_lab, w=w, ssim_lambda=lam)
+    glog = _pixels_by_channel(g_ref, its, 4 + C)[:, 4:]
+    hb = oracle.head_backward(E, W1, b1, W2, glog)
+    habs = oracle.head_backward(np.abs(E), np.abs(W1), np.abs(b1), np.abs(W2), np.abs(glog))
+    # GPU
+    T = dict(rgb=torch.from_numpy(t_rgb).cuda(), depth=torch.from_numpy(t_depth).cuda(),
+             label=torch.from_numpy(t_lab).cuda())
+    rendered = dict(color=torch.from_numpy(img.astype(np.float32)).cuda(), logits=None)
+    grads = {k: torch.empty(*s, device="cuda") for k, s in (("head_W1", (64, 16)), ("head_b1", (64,)),
+                                                            ("head_W2", (C, 64)), ("head_b2", (C,)))}
+    ls, grad = raster.loss(cfg, fr, C, rendered, T, w=w, head=_dev_head(hw), grads=grads)
+    torch.cuda.synchronize()
+    rel_check(ls.cpu().numpy(), ls_ref, 1e-4, name="loss")
+    got = _pixels_by_channel(grad["color"].cpu().numpy(), its, 20)
+    ref = _pixels_by_channel(g_ref, its, 4 + C)
+    rel_check(got[:, :4], ref[:, :4], 1e-3, name="rgb/depth gradient")
+    hmag = oracle.head_backward(np.abs(E), np.abs(W1), np.abs(b1), np.abs(W2), np.abs(glog))["E"]
+    rel_check(got[:, 4:], hb["E"], 1e-3, scale=hmag, name="dL/dE")
+    for k, kk in (("head_W1", "W1"), ("head_b1", "b1"), ("head_W2", "W2"), ("head_b2", "b2")):
+        rel_check(grads[k].cpu().numpy(), hb[kk], 1e-3, scale=habs[kk], name=k)
+
+
+def test_fused_and_unfused_learned_steps_agree():
+    """The learned mapping step with the decode inside the loss against the one that
+    decodes in the forward and differentiates the head in the backward: same loss and
+    gradients (to float atomics' order)."""
+    from paper_2412_01217_amd import raster
+    from paper_2412_01217_amd.step import MappingStep
+    C = 52
+    sc, views = _scene(C=C, seed=2)
+    hw = _head(C, seed=6004)
+    cfg = raster.config(16)
+    fr = raster.Frame(cfg, views)
+    g = raster.to_device(sc)
+    g.pop("sem")
+    t_rgb, t_depth, t_lab = targets_from_random(views, C, seed=4004)
+    T = dict(rgb=torch.from_numpy(t_rgb).cuda(), depth=torch.from_numpy(t_depth).cuda(),
+             label=torch.from_numpy(t_lab).cuda())
+    out = []
+    for fused in (True, False):
+        st = MappingStep(cfg, fr, g, T, C, head=_dev_head(hw), fused_head=fused)
+        st.run()
+        torch.cuda.synchronize()
+        out.append((st.loss.cpu().numpy(), {k: v.cpu().numpy() for k, v in st.grads.items() if v is not None}))
+    np.testing.assert_allclose(out[0][0], out[1][0], rtol=2e-5)
+    for k in out[0][1]:
+        a, b = out[0][1][k], out[1][1][k]
+        scale = max(float(np.abs(b).max()), 1e-20)
+        assert float(np.abs(a - b).max()) <= 1e-4 * scale, k
