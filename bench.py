@@ -6,10 +6,12 @@ batch, through the C ABI, captured once as a HIP graph and replayed. Inputs are
 resident in HBM before timing; targets (2x2 box pyramids of a render of a perturbed
 copy of the scene) are built once beforehand.
 
-Prints one JSON line. `value` is the default workload's MP/s: 200k Gaussians in a
-6x5x3 m room, 52 plain classes, one view at 1200x680 with a 3-level pyramid. The
-same line carries the batched 8-view workload (autotuned) and the learned-semantic
-head against the plain form (trained first), unless --quick.
+Prints one JSON line. `value` is the default workload's MP/s: the large two-room scene
+(2M Gaussians, 52 classes through the learned 16 -> 64 -> 52 head, its decode fused into
+the loss), 16 views at 1920x1080 with 4 pyramid levels each, in the launch configuration
+the autotuner picks, with the head first trained on the GPU. The same line carries the
+room (200k, plain 52 classes), the 8-view batch (autotuned), learned against plain on the
+batch scene and on the large scene, and the room step's variants, unless --quick.
 """
 from __future__ import annotations
 
@@ -82,14 +84,46 @@ def plain_step(sc, views, device, targets=None, variant=0, tile_order=0, ssim_la
     return MappingStep(cfg, fr, g, targets, C, sh=shd), targets
 
 
-def learned_step(sc, views, head, device, targets):
+def learned_step(sc, views, head, device, targets, cfg=None):
+    """The learned mapping step (decode, cross-entropy and the decode's backward inside the
+    loss call)."""
     from paper_2412_01217_amd import raster
     from paper_2412_01217_amd.step import MappingStep
-    cfg = raster.config(16)
+    cfg = cfg or raster.config(16)
     fr = raster.Frame(cfg, views, device=device)
     g = raster.to_device(sc, device)
     g.pop("sem", None)
     return MappingStep(cfg, fr, g, targets, head["b2"].shape[0], head=head)
+
+
+def train_head(sc, device, steps, heldout_views, seed_offset):
+    """Fits the embedding and the 16 -> 64 -> C head to the plain C-class render on the GPU
+    (a fresh random 640x480 view with 3 levels per step), then measures argmax agreement
+    and logit error on held-out views. Returns (report, head dict, scene copy with the
+    trained embedding)."""
+    import torch
+    from paper_2412_01217_amd import scenes
+    from paper_2412_01217_amd.learned import Trainer
+
+    def train_views(k):
+        return scenes.room_views(sc, 1, 640, 480, levels=3, seed=scenes.SEED_VIEWS + seed_offset + k)[0]
+    t0 = time.perf_counter()
+    tr = Trainer(sc, train_views, sc.n_classes, device)
+    before = tr.evaluate(heldout_views[:1])
+    tr.train(steps)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    quality = tr.evaluate(heldout_views)
+    head = tr.head.as_dict()
+    trained = sc.copy()
+    trained.emb = tr.g_learned["emb"].cpu().numpy().view(np.uint16).copy()
+    del tr
+    torch.cuda.empty_cache()
+    rep = {"head_training": {"steps": steps, "seconds": train_s, "train_views": "a fresh random 640x480 view "
+                             "(3 levels) per step", "agreement_untrained": before["agreement"]},
+           "argmax_agreement": quality["agreement"], "logit_rmse": quality["logit_rmse"],
+           "heldout_views": len(heldout_views), "heldout_pixels": quality["pixels"]}
+    return rep, head, trained
 
 
 # ----------------------------------------------------------------------------- measurement
@@ -191,19 +225,22 @@ def algorithmic_bytes(c, n_classes, learned=False):
     return b
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "render_room200k_c52_hbm_counters.md")
+# committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries per workload (the render kernels'
+# HBM bytes per launch, with the source hash they were taken on)
+COUNTERS = {"room": os.path.join(ROOT, "profiles", "render_room200k_c52_hbm_counters.md"),
+            "large": os.path.join(ROOT, "profiles", "render_large2m_c52_learned_hbm_counters.md")}
 
 
-def measured_traffic():
-    """HBM bytes per launch of the render kernels on the room workload, from the committed
+def measured_traffic(workload):
+    """HBM bytes per launch of the render kernels on `workload`, from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by the copy calibration there), or {}
     when the render source has changed since the counters were taken."""
     import hashlib
     import re
     try:
-        text = open(COUNTERS).read()
+        text = open(COUNTERS[workload]).read()
         src = open(os.path.join(ROOT, "paper_2412_01217_amd", "csrc", "render_split.hip"), "rb").read()
-    except OSError:
+    except (OSError, KeyError):
         return {}
     m = re.search(r"source sha256: ([0-9a-f]{64})", text)
     if not m or m.group(1) != hashlib.sha256(src).hexdigest():
@@ -253,42 +290,24 @@ def batch_report(args, device):
 
 def learned_report(args, device):
     """The learned semantic head on the batched room scene with 52 classes: train the
-    head for 2,000 steps on plain renders of random views, measure argmax agreement and
-    logit error on held-out views, then time learned against plain on the 8-view batch."""
+    head for --train-steps steps on plain renders of random views, measure argmax agreement
+    and logit error on 16 held-out views, then time learned against plain on the 8-view batch."""
     import torch
     from paper_2412_01217_amd import scenes
-    from paper_2412_01217_amd.learned import Trainer
     sc, views = scenes.config_learned()
-    # a fresh random 640x480 view (3 levels) for every training step; 16 held-out views
-    def train_views(k):
-        return scenes.room_views(sc, 1, 640, 480, levels=3, seed=scenes.SEED_VIEWS + 10000 + k)[0]
     test_views = scenes.room_views(sc, 16, 640, 480, levels=3, seed=scenes.SEED_VIEWS + 61)
-    t0 = time.perf_counter()
-    tr = Trainer(sc, train_views, sc.n_classes, device)
-    before = tr.evaluate(test_views[:4])
-    tr.train(args.train_steps)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    quality = tr.evaluate(test_views)
-    head = tr.head.as_dict()
-    trained_sc = sc.copy()
-    trained_sc.emb = tr.g_learned["emb"].cpu().numpy().view(np.uint16).copy()
-    del tr
-    torch.cuda.empty_cache()
+    rep, head, trained_sc = train_head(sc, device, args.train_steps, test_views, 10000)
     plain, targets = plain_step(sc, views, device)
     mp = measure(plain, args.steps, args.warmup)
     cp = work_counts(plain)
     del plain
+    torch.cuda.empty_cache()
     lstep = learned_step(trained_sc, views, head, device, targets)
     ml = measure(lstep, args.steps, args.warmup)
     cl = work_counts(lstep)
     mpx = cl["pixels"] / 1e6
     return {"workload": "room 6x5x3 m, 500k Gaussians, 52 classes via 16-dim bf16 embedding + 16->64->52 MLP, "
-                        "8 views 640x480, 1-3 levels each",
-            "head_training": {"steps": args.train_steps, "seconds": train_s, "train_views": "a fresh random view per step",
-                              "agreement_untrained": before["agreement"]},
-            "argmax_agreement": quality["agreement"], "logit_rmse": quality["logit_rmse"],
-            "heldout_views": len(test_views), "heldout_pixels": quality["pixels"],
+                        "8 views 640x480, 1-3 levels each", **rep,
             "learned": {"value": mpx / (ml["ms"] * 1e-3), "unit": "MP/s", "ms_per_step": ml["ms"],
                         "stage_ms": ml["stage_ms"],
                         "hbm_gbs_effective": algorithmic_bytes(cl, 52, learned=True) / (ml["ms"] * 1e-3) / 1e9},
@@ -298,27 +317,58 @@ def learned_report(args, device):
             "speedup_learned_over_plain": mp["ms"] / ml["ms"]}
 
 
-def large_report(args, device):
-    """Two-room scene, 2M Gaussians, 52 classes via the learned head, 16 views at
-    1920x1080 with 4 levels each."""
+# candidates timed for the large workload (the per-lane FMA variant, several times slower on
+# every workload measured, is left out to keep the tuning short)
+def large_candidates():
+    from paper_2412_01217_amd import autotune
+    return [c for c in autotune.CANDIDATES if c["variant"] != 1]
+
+
+def large_headline(args, dev):
+    """The large workload: two rooms, 2M Gaussians, 52 classes through the learned head,
+    16 views at 1920x1080 with 4 levels. Trains the head (640x480 views of this scene),
+    autotunes the launch configuration, then times the learned step."""
     import torch
-    from paper_2412_01217_amd import raster, scenes
-    sc = scenes.room_scene(n=2_000_000, n_classes=52, seed=scenes.SEED_SCENE + 4, size=(12.0, 10.0, 3.0), n_boxes=40,
-                           partition_x=6.0, embed=True)
-    views = scenes.room_views(sc, 16, 1920, 1080, levels=4, seed=scenes.SEED_VIEWS + 4)
+    from paper_2412_01217_amd import autotune, raster, scenes
+    sc, views = scenes.config_large()
     cfg_p = raster.config(52)
-    fr = raster.Frame(cfg_p, views, device=device)
-    targets = make_targets(cfg_p, fr, sc, device)
-    w = scenes.head_weights(52)
-    head = dict(W1=torch.from_numpy(w["W1"].view(np.int16).copy()).to(device), b1=torch.from_numpy(w["b1"]).to(device),
-                W2=torch.from_numpy(w["W2"].view(np.int16).copy()).to(device), b2=torch.from_numpy(w["b2"]).to(device))
-    step = learned_step(sc, views, head, device, targets)
-    m = measure(step, max(2, args.steps // 4), 1)
+    fr_p = raster.Frame(cfg_p, views, device=dev)
+    targets = make_targets(cfg_p, fr_p, sc, dev)
+    torch.cuda.empty_cache()
+    heldout = scenes.room_views(sc, 2, 1920, 1080, levels=4, seed=scenes.SEED_VIEWS + 64)
+    rep, head, trained_sc = train_head(sc, dev, args.train_steps, heldout, 40000)
+    cfg = raster.config(16)
+    step = learned_step(trained_sc, views, head, dev, targets, cfg=cfg)
+
+    def make(c):
+        from paper_2412_01217_amd.step import MappingStep
+        return MappingStep(c, step.frame, step.g, targets, 52, head=head)
+    tuned = autotune.tune(make, cfg, step.frame, sc.n, candidates=large_candidates(), reps=3)
+    step = make(cfg)
+    m = measure(step, args.steps, args.warmup, graph=not args.eager)
     c = work_counts(step)
-    return {"workload": "two-room 12x10x3 m, 2M Gaussians, 52 classes via learned head, 16 views 1920x1080, 4 levels",
-            "value": c["pixels"] / 1e6 / (m["ms"] * 1e-3), "unit": "MP/s", "ms_per_step": m["ms"],
-            "stage_ms": m["stage_ms"], "pixels_per_step": c["pixels"], "duplicates": c["dup"],
-            "hbm_gbs_effective": algorithmic_bytes(c, 52, learned=True) / (m["ms"] * 1e-3) / 1e9}
+    return sc, views, targets, head, trained_sc, step, m, c, tuned, rep
+
+
+def large_plain_report(args, dev, sc, views, targets, ms_learned):
+    """The plain 52-class render of the large workload (logits composited per Gaussian) in
+    the autotuner's configuration, beside the learned form."""
+    import torch
+    from paper_2412_01217_amd import autotune
+    from paper_2412_01217_amd.step import MappingStep
+    step, _ = plain_step(sc, views, dev, targets=targets)
+
+    def make(c):
+        return MappingStep(c, step.frame, step.g, targets, 52)
+    tuned = autotune.tune(make, step.cfg, step.frame, sc.n, candidates=large_candidates(), reps=2)
+    step = make(step.cfg)
+    m = measure(step, max(3, args.steps // 4), 2, graph=not args.eager)
+    px = step.frame.n_pixels
+    del step
+    torch.cuda.empty_cache()
+    return {"workload": "the large workload with the plain 52-class render", "value": px / 1e6 / (m["ms"] * 1e-3),
+            "unit": "MP/s", "ms_per_step": m["ms"], "stage_ms": m["stage_ms"], "autotune": tuned,
+            "speedup_learned_over_plain": m["ms"] / ms_learned}
 
 
 def cpu_baseline(sc, views, targets, C, min_s=10.0):
@@ -339,6 +389,66 @@ def cpu_baseline(sc, views, targets, C, min_s=10.0):
     return dict(value=P * reps / total / 1e6, unit="MP/s", cores=1, kind="oracle",
                 sample=f"the whole workload ({n_items} levels, {tiles} tiles, {P} px), forward + loss + backward "
                        f"including the projection and binning of all {sc.n} Gaussians; {reps} runs, {total:.1f} s")
+
+
+def cpu_baseline_large(sc, views, targets, head, stride=4):
+    """The FP64 oracle (single thread) on a sample of the large learned workload: view 0 with
+    its 4 levels, every `stride`-th tile of each level; forward (projection and binning of
+    all Gaussians included), the head's decode, the loss, the head's backward and the render
+    backward, once. MP/s counts the sampled tiles' pixels."""
+    import oracle
+    from paper_2412_01217_amd import scenes
+    v0 = views[:1]
+    its = oracle.items(v0)
+    n_items, P0, tiles = oracle.layout(v0)
+    mask = (np.arange(tiles) % stride == 0).astype(np.uint8)
+    sel = np.zeros(P0, bool)
+    for it in its:
+        vv, uu = np.mgrid[0:it["H"], 0:it["W"]]
+        t = it["tile0"] + (vv // 16) * it["ntx"] + (uu // 16)
+        sel[it["pix0"]: it["pix0"] + it["W"] * it["H"]] = mask[t.reshape(-1)] != 0
+    C = int(head["b2"].shape[0])
+    w = {k: (scenes.bf16_bits_to_f32(head[k].cpu().numpy().view(np.uint16)) if k in ("W1", "W2")
+             else head[k].cpu().numpy()).astype(np.float64) for k in ("W1", "b1", "W2", "b2")}
+    emb = scenes.bf16_bits_to_f32(sc.emb).astype(np.float64)
+    t_rgb = targets["rgb"][:3 * P0].cpu().numpy()
+    t_depth = targets["depth"][:P0].cpu().numpy()
+    t_lab = np.where(sel, targets["label"][:P0].cpu().numpy(), -1).astype(np.int32)
+    cfg = oracle.Config()
+    t0 = time.perf_counter()
+    r = oracle.render(cfg, sc, v0, sem=emb, tile_mask=mask)
+    K = 20
+    E = np.concatenate([r["img"][it["pix0"] * K: it["pix0"] * K + K * it["W"] * it["H"]].reshape(K, -1).T[:, 4:]
+                        for it in its])
+    logits = np.zeros((P0, C))
+    logits[sel] = oracle.head_forward(E[sel], w["W1"], w["b1"], w["W2"], w["b2"])
+    img_l = np.zeros(P0 * (4 + C))
+    for it in its:
+        HW = it["W"] * it["H"]
+        src = r["img"][it["pix0"] * K: it["pix0"] * K + K * HW].reshape(K, HW)
+        dst = img_l[it["pix0"] * (4 + C): it["pix0"] * (4 + C) + (4 + C) * HW].reshape(4 + C, HW)
+        dst[:4] = src[:4]
+        dst[4:] = logits[it["pix0"]: it["pix0"] + HW].T
+    _, g_l = oracle.loss(v0, C, img_l, t_rgb, t_depth, t_lab)
+    glog = np.concatenate([g_l[it["pix0"] * (4 + C): it["pix0"] * (4 + C) + (4 + C) * it["W"] * it["H"]]
+                           .reshape(4 + C, -1).T[:, 4:] for it in its])
+    hb = oracle.head_backward(E[sel], w["W1"], w["b1"], w["W2"], glog[sel])
+    gimg = np.zeros(P0 * K)
+    dE = np.zeros((P0, 16))
+    dE[sel] = hb["E"]
+    for it in its:
+        HW = it["W"] * it["H"]
+        src = g_l[it["pix0"] * (4 + C): it["pix0"] * (4 + C) + (4 + C) * HW].reshape(4 + C, HW)
+        dst = gimg[it["pix0"] * K: it["pix0"] * K + K * HW].reshape(K, HW)
+        dst[:4] = src[:4] * sel[it["pix0"]: it["pix0"] + HW]
+        dst[4:] = dE[it["pix0"]: it["pix0"] + HW].T
+    oracle.backward(cfg, sc, v0, gimg, sem=emb, tile_mask=mask)
+    total = time.perf_counter() - t0
+    n_px = int(sel.sum())
+    return dict(value=n_px / total / 1e6, unit="MP/s", cores=1, kind="oracle",
+                sample=f"view 0 of the large workload (its {n_items} levels), every {stride}th tile: {n_px} of "
+                       f"{P0} px; forward (projection and binning of all {sc.n} Gaussians per level), decode, loss, "
+                       f"head backward and render backward; {total:.1f} s")
 
 
 def adam_report(step, steps):
@@ -418,20 +528,32 @@ def ssim_report(args, dev, sc, views, targets, ms_ref, loss_ms_ref, lam=0.2):
 
 
 # ----------------------------------------------------------------------------- main
+def room_headline(args, dev):
+    """The room workload (200k Gaussians, 52 plain classes, 1200x680 with 3 levels) in the
+    default launch configuration."""
+    from paper_2412_01217_amd import scenes
+    sc, views = scenes.config_room()
+    sh = tuple(int(x) for x in args.sh.split(",")) if args.sh else None
+    step, targets = plain_step(sc, views, dev, variant=args.variant, ssim_lambda=args.ssim_lambda, sh=sh)
+    m = measure(step, args.steps, args.warmup, graph=not args.eager)
+    c = work_counts(step)
+    return sc, views, targets, step, m, c, sh
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="room", choices=("room", "batch", "learned", "large"))
-    ap.add_argument("--quick", action="store_true", help="only the default workload (no batch / learned reports)")
+    ap.add_argument("--workload", default="large", choices=("large", "room", "batch", "learned"))
+    ap.add_argument("--quick", action="store_true", help="only the timed workload (no sub-reports)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variant", type=int, default=0, help="render kernels: 0 auto (3), 1 VALU, 2 FP32 matrix cores, 3 split-bf16 matrix cores")
+    ap.add_argument("--variant", type=int, default=0, help="room: render kernels 0 auto (3), 1 VALU, 2 FP32 matrix cores, 3 split-bf16 matrix cores")
     ap.add_argument("--eager", action="store_true", help="time eager calls instead of graph replays")
     ap.add_argument("--sh", default="", metavar="R,S",
-                    help="SH degrees (colour, semantics) of view-dependent features in the timed step (default: none)")
+                    help="room: SH degrees (colour, semantics) of view-dependent features in the timed step")
     ap.add_argument("--ssim-lambda", type=float, default=0.0,
-                    help="SSIM weight of the colour loss in the timed step (0: the L1 loss of the workloads)")
+                    help="room: SSIM weight of the colour loss in the timed step (0: the L1 loss of the workloads)")
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times): the reference for HBM byte counters")
@@ -452,51 +574,82 @@ def main():
         sys.exit(2)
     clocks = gpu_clocks()   # queried before this process initialises the GPU
     import torch
-    from paper_2412_01217_amd import scenes
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    sub = {"batch": batch_report, "learned": learned_report, "large": large_report}.get(args.workload)
+    sub = {"batch": batch_report, "learned": learned_report}.get(args.workload)
     if sub is not None:
         print(json.dumps({"metric": METRIC, **sub(args, dev)}), flush=True)
         return
-    sc, views = scenes.config_room()
-    sh = tuple(int(x) for x in args.sh.split(",")) if args.sh else None
-    step, targets = plain_step(sc, views, dev, variant=args.variant, ssim_lambda=args.ssim_lambda, sh=sh)
-    m = measure(step, args.steps, args.warmup, graph=not args.eager)
-    c = work_counts(step)
+    common = {"metric": METRIC, "unit": "MP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
+    if args.workload == "large":
+        sc, views, targets, head, trained_sc, step, m, c, tuned, quality = large_headline(args, dev)
+        ms = m["ms"]
+        roof, other = roofline(step, m["stage_ms"], c, measured_traffic("large"))
+        out = {**common, "value": c["pixels"] / 1e6 / (ms * 1e-3), "ms_per_step": ms,
+               # compositing, loss and gradients in single precision; the channel contractions on
+               # bfloat16 matrix cores with hi/lo split operands (about 2^-16 relative), the decode
+               # with bfloat16 weights and hi/lo split activations
+               "dtype": "f32 (contractions as split-bf16 MFMA)",
+               "config": {"workload": "two-room 12x10x3 m, 2M Gaussians, 52 classes via the learned 16->64->52 head "
+                                      "(decode fused into the loss), 16 views 1920x1080, 4-level pyramid",
+                          "gaussians": sc.n, "classes": 52, "pixels_per_step": c["pixels"], "items": c["items"],
+                          "duplicates": c["dup"], "visible_item_gaussians": c["visible"], "pairs_iterated": c["pairs"],
+                          "semantic_mode": "learned", "launch": tuned["choice"]},
+               "timed": "eager calls" if args.eager else "HIP graph replay of the whole step",
+               "eager_ms_per_step": m["eager_ms"], "step_ms_spread": m["step_ms_spread"], "stage_ms": m["stage_ms"],
+               "hbm_gbs_effective": algorithmic_bytes(c, 52, learned=True) / (ms * 1e-3) / 1e9,
+               "roofline": roof, "roofline_other": other, "autotune": tuned, "learned_head": quality,
+               "gpu_clocks_at_start": clocks}
+        del step
+        torch.cuda.empty_cache()
+        if not args.quick:
+            out["large_plain_c52"] = large_plain_report(args, dev, sc, views, targets, ms)
+            torch.cuda.empty_cache()
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_large(trained_sc, views, targets, head)
+            out["cpu_baseline"]["host"] = host_cpu()
+        del targets, head, trained_sc
+        torch.cuda.empty_cache()
+        if not args.quick:
+            rsc, rviews, rtargets, rstep, rm, rc, _ = room_headline(args, dev)
+            rroof, rother = roofline(rstep, rm["stage_ms"], rc, measured_traffic("room") if args.variant == 0 else {})
+            out["room"] = {"workload": "room 6x5x3 m, 200k Gaussians, 52 plain classes, 1 view 1200x680, 3-level "
+                                       "pyramid", "value": rc["pixels"] / 1e6 / (rm["ms"] * 1e-3), "unit": "MP/s",
+                           "ms_per_step": rm["ms"], "step_ms_spread": rm["step_ms_spread"], "stage_ms": rm["stage_ms"],
+                           "duplicates": rc["dup"], "pairs_iterated": rc["pairs"],
+                           "hbm_gbs_effective": algorithmic_bytes(rc, 52) / (rm["ms"] * 1e-3) / 1e9,
+                           "roofline": rroof, "roofline_other": rother}
+            out["mapping_update"] = adam_report(rstep, args.steps)
+            del rstep
+            torch.cuda.empty_cache()
+            out["room"]["with_ssim"] = ssim_report(args, dev, rsc, rviews, rtargets, rm["ms"], rm["stage_ms"]["loss"])
+            torch.cuda.empty_cache()
+            out["room"]["isotropic_primitive"] = isotropic_report(args, dev, rsc, rviews, rtargets)
+            torch.cuda.empty_cache()
+            out["room"]["sh_features"] = sh_report(args, dev, rsc, rviews, rtargets)
+            torch.cuda.empty_cache()
+            out["batch"] = batch_report(args, dev)
+            torch.cuda.empty_cache()
+            out["learned_vs_plain"] = learned_report(args, dev)
+            torch.cuda.empty_cache()
+        print(json.dumps(out), flush=True)
+        return
+    # --workload room
+    sc, views, targets, step, m, c, sh = room_headline(args, dev)
     ms = m["ms"]
-    # the committed counters describe the default configuration only
-    traffic = measured_traffic() if args.variant == 0 else {}
-    roof, other = roofline(step, m["stage_ms"], c, traffic)
-    out = {
-        "metric": METRIC, "value": c["pixels"] / 1e6 / (ms * 1e-3), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "room 6x5x3 m, 200k Gaussians, 52 plain classes, 1 view 1200x680, 3-level pyramid",
-                   "gaussians": sc.n, "classes": sc.n_classes, "pixels_per_step": c["pixels"], "items": c["items"],
-                   "duplicates": c["dup"], "visible_item_gaussians": c["visible"], "pairs_iterated": c["pairs"],
-                   "semantic_mode": "plain", "render_variant": args.variant, "ssim_lambda": args.ssim_lambda,
-                   "sh_degrees": list(sh) if sh else None},
-        "timed": "eager calls" if args.eager else "HIP graph replay of the whole step",
-        "eager_ms_per_step": m["eager_ms"], "step_ms_spread": m["step_ms_spread"], "stage_ms": m["stage_ms"],
-        "hbm_gbs_effective": algorithmic_bytes(c, sc.n_classes) / (ms * 1e-3) / 1e9,
-        "roofline": roof, "roofline_other": other,
-    }
-    out["gpu_clocks_at_start"] = clocks
-    out["mapping_update"] = adam_report(step, args.steps)
-    del step
-    torch.cuda.empty_cache()
-    if not args.quick:
-        out["with_ssim"] = ssim_report(args, dev, sc, views, targets, ms, m["stage_ms"]["loss"])
-        torch.cuda.empty_cache()
-        out["isotropic_primitive"] = isotropic_report(args, dev, sc, views, targets)
-        torch.cuda.empty_cache()
-        out["sh_features"] = sh_report(args, dev, sc, views, targets)
-        torch.cuda.empty_cache()
-        out["batch"] = batch_report(args, dev)
-        torch.cuda.empty_cache()
-        out["learned_vs_plain"] = learned_report(args, dev)
-        torch.cuda.empty_cache()
+    roof, other = roofline(step, m["stage_ms"], c, measured_traffic("room") if args.variant == 0 else {})
+    out = {**common, "value": c["pixels"] / 1e6 / (ms * 1e-3), "ms_per_step": ms,
+           "dtype": "f32 (contractions as split-bf16 MFMA)",
+           "config": {"workload": "room 6x5x3 m, 200k Gaussians, 52 plain classes, 1 view 1200x680, 3-level pyramid",
+                      "gaussians": sc.n, "classes": sc.n_classes, "pixels_per_step": c["pixels"], "items": c["items"],
+                      "duplicates": c["dup"], "visible_item_gaussians": c["visible"], "pairs_iterated": c["pairs"],
+                      "semantic_mode": "plain", "render_variant": args.variant, "ssim_lambda": args.ssim_lambda,
+                      "sh_degrees": list(sh) if sh else None},
+           "timed": "eager calls" if args.eager else "HIP graph replay of the whole step",
+           "eager_ms_per_step": m["eager_ms"], "step_ms_spread": m["step_ms_spread"], "stage_ms": m["stage_ms"],
+           "hbm_gbs_effective": algorithmic_bytes(c, sc.n_classes) / (ms * 1e-3) / 1e9,
+           "roofline": roof, "roofline_other": other, "gpu_clocks_at_start": clocks}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, views, targets, sc.n_classes)
         out["cpu_baseline"]["host"] = host_cpu()

@@ -375,3 +375,13 @@ def config_learned(n=500_000, n_classes=52, n_views=8):
     sc = room_scene(n=n, n_classes=n_classes, seed=SEED_SCENE + 2, embed=True)
     views = room_views(sc, n_views, 640, 480, seed=SEED_VIEWS + 2, level_choices=(1, 2, 3))
     return sc, views
+
+
+def config_large(n=2_000_000, n_classes=52, n_views=16):
+    """Two rooms (12x10x3 m, a partition at x = 6 m with a 1.0 x 2.1 m door), 40 boxes,
+    2M Gaussians, 52 classes with a 16-dim bfloat16 embedding each; 16 views at 1920x1080
+    (fx = fy = 960 at the image centre), 4 pyramid levels each."""
+    sc = room_scene(n=n, n_classes=n_classes, seed=SEED_SCENE + 4, size=(12.0, 10.0, 3.0), n_boxes=40,
+                    partition_x=6.0, embed=True)
+    views = room_views(sc, n_views, 1920, 1080, levels=4, seed=SEED_VIEWS + 4)
+    return sc, views
