@@ -257,6 +257,19 @@ int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_it
                     const float* w, float* loss_dev, gs_images* grad_out, gs_grads* head_grads, void* workspace,
                     size_t ws_bytes, void* stream);
 
+/* gs_pyramid_loss for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same computation
+ * and arguments without the workspace, which is instead a 16 MiB array the library holds
+ * in each GPU's memory (from the library's load until the process ends). The caller still
+ * passes every input and output. At most 2048 items; more returns GS_ERR_WORKSPACE before
+ * anything is enqueued. Nothing is allocated or freed by the call. Every call on one GPU
+ * shares that GPU's array, which keeps the last call's contents (each call clears what it
+ * sums into first), so calls that overlap in time on one GPU, on any streams, race and must
+ * be ordered by the caller. */
+int gs_pyramid_loss_static(const gs_config* cfg, const gs_item* items_dev, int32_t n_items, int64_t n_pixels,
+                           int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const gs_head* head,
+                           const float* w, float* loss_dev, gs_images* grad_out, gs_grads* head_grads, void* stream);
+
 /* Back-propagation (Sec. III-D) of an upstream gradient grad_in->color (and ->logits)
  * through compositing and projection to every Gaussian parameter and every view's
  * pose tangent. fwd must hold T and n_contrib of the matching gs_render_fwd.

@@ -31,6 +31,7 @@ EXPORTS = (
     "gs_render_bwd", "gs_pyramid_downsample", "gs_graph_begin", "gs_graph_end", "gs_graph_launch",
     "gs_graph_destroy", "gs_adam_step", "gs_distill_loss", "gs_argmax_agreement", "gs_gaussians_adam",
     "gs_pose_adam", "gs_sh_features", "gs_sh_features_bwd", "gs_pose_perturb", "gs_pose_perturb_bwd",
+    "gs_pyramid_loss_static",
 )
 
 
@@ -138,9 +139,12 @@ def lib():
         L.gs_sh_features.argtypes = [c_int32, P(Gaussians), P(SH), c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
         L.gs_sh_features_bwd.argtypes = [c_int32, P(Gaussians), P(SH), c_void_p, c_int32] + [c_void_p] * 9
         L.gs_pose_perturb.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
+        L.gs_pyramid_loss_static.argtypes = [P(Config), c_void_p, c_int32, c_int64, c_int32, P(Images), P(Targets),
+                                             c_void_p, P(c_float), c_void_p, P(Images), c_void_p, c_void_p]
         L.gs_pose_perturb_bwd.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
         for name in ("gs_adam_step", "gs_distill_loss", "gs_argmax_agreement", "gs_gaussians_adam", "gs_pose_adam",
-                     "gs_sh_features", "gs_sh_features_bwd", "gs_pose_perturb", "gs_pose_perturb_bwd"):
+                     "gs_sh_features", "gs_sh_features_bwd", "gs_pose_perturb", "gs_pose_perturb_bwd",
+                     "gs_pyramid_loss_static"):
             getattr(L, name).restype = c_int32
         L.gs_graph_begin.argtypes = [c_void_p]
         L.gs_graph_end.argtypes = [c_void_p, P(c_void_p)]

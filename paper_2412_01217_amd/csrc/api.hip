@@ -1,6 +1,7 @@
 // C ABI entry points: argument validation, workspace planning and kernel launches.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 
@@ -263,10 +264,10 @@ int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   return launch_head_fwd(items_dev, n_items, out->n_pixels, 4 + cfg->n_sem, *head, out->color, out->logits, s);
 }
 
-int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_items, int64_t n_pixels,
-                    int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const gs_head* head,
-                    const float* w, float* loss_dev, gs_images* grad_out, gs_grads* head_grads, void* workspace,
-                    size_t ws_bytes, void* stream) {
+// Argument checks of gs_pyramid_loss other than the workspace's.
+static int loss_args(const gs_config* cfg, const gs_item* items_dev, int32_t n_items, int64_t n_pixels,
+                     int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const gs_head* head,
+                     const float* w, const float* loss_dev, const gs_images* grad_out, const gs_grads* head_grads) {
   if (!cfg_ok(cfg) || n_items < 0 || n_pixels < 0 || n_classes < 0 || !rendered || !targets || !w || !grad_out)
     return GS_ERR_INVALID_ARG;
   if (n_items == 0) return GS_OK;
@@ -283,10 +284,64 @@ int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_it
   } else if (n_classes != cfg->n_sem) {
     return GS_ERR_INVALID_ARG;
   }
+  return GS_OK;
+}
+
+int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_items, int64_t n_pixels,
+                    int32_t n_classes, const gs_images* rendered, const gs_targets* targets, const gs_head* head,
+                    const float* w, float* loss_dev, gs_images* grad_out, gs_grads* head_grads, void* workspace,
+                    size_t ws_bytes, void* stream) {
+  const int st = loss_args(cfg, items_dev, n_items, n_pixels, n_classes, rendered, targets, head, w, loss_dev,
+                           grad_out, head_grads);
+  if (st != GS_OK || n_items == 0) return st;
   if (!workspace || ws_bytes < loss_workspace(n_items)) return GS_ERR_WORKSPACE;
   return launch_loss(items_dev, n_items, n_pixels, 4 + cfg->n_sem, n_classes, rendered->color,
                      head ? nullptr : rendered->logits, *targets, head, w, cfg->ssim_lambda, loss_dev, grad_out->color,
                      head ? nullptr : grad_out->logits, head_grads, (float*)workspace, (hipStream_t)stream);
+}
+
+// ---- the loss with library-held scratch ----------------------------------------
+// gs_pyramid_loss_static runs gs_pyramid_loss's kernels with the workspace taken from this
+// file-scope device array instead of a caller buffer, for callers that cannot allocate.
+// Each GPU holds its own copy; its address is looked up once per device (the array's name
+// is a host-side stand-in, never passed to a kernel).
+constexpr size_t kLossScratchBytes = (size_t)16 << 20;
+constexpr int32_t kLossScratchItems = 2048;
+static __device__ __align__(256) unsigned char scratch[kLossScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's device address on the calling thread's current device (nullptr and a
+// recorded HIP error if it cannot be had).
+void* scratch_on_current_device() {
+  int dev = -1;
+  if (hip_status(hipGetDevice(&dev)) != GS_OK || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hip_status(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != GS_OK) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" int gs_pyramid_loss_static(const gs_config* cfg, const gs_item* items_dev, int32_t n_items,
+                                      int64_t n_pixels, int32_t n_classes, const gs_images* rendered,
+                                      const gs_targets* targets, const gs_head* head, const float* w, float* loss_dev,
+                                      gs_images* grad_out, gs_grads* head_grads, void* stream) {
+  const int st = loss_args(cfg, items_dev, n_items, n_pixels, n_classes, rendered, targets, head, w, loss_dev,
+                           grad_out, head_grads);
+  if (st != GS_OK || n_items == 0) return st;
+  // more items than the scratch array holds the per-item sums of: refused before any launch
+  if (n_items > kLossScratchItems || loss_workspace(n_items) > kLossScratchBytes) return GS_ERR_WORKSPACE;
+  void* ws = scratch_on_current_device();
+  if (!ws) return GS_ERR_HIP;
+  return gs_pyramid_loss(cfg, items_dev, n_items, n_pixels, n_classes, rendered, targets, head, w, loss_dev, grad_out,
+                         head_grads, ws, kLossScratchBytes, stream);
 }
 
 int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projected* proj, const gs_view* views_dev,

@@ -217,18 +217,19 @@ def render_fwd(cfg, g: dict, proj: dict, frame: Frame, sorter: Sorter, out=None,
 
 
 def loss(cfg, frame: Frame, n_classes: int, rendered: dict, targets: dict, w=(1.0, 1.0, 1.0), grad=None,
-         loss_out=None, ws=None, head=None, grads=None):
+         loss_out=None, ws=None, head=None, grads=None, static=False):
     """Per-item loss parts [n_items, 3] and the image gradient. Learned mode with `head`: the
     decode runs inside the loss, grad["color"] channels 4.. receive dL/dE and grads'
-    head_W1 .. head_b2 the head's weight gradients (grads: a dict with those four tensors)."""
+    head_W1 .. head_b2 the head's weight gradients (grads: a dict with those four tensors).
+    static: gs_pyramid_loss_static, whose workspace is the library's own device array."""
     dev = frame.device
     if grad is None:
         grad = dict(color=torch.empty_like(rendered["color"]),
                     logits=(torch.empty_like(rendered["logits"])
                             if rendered.get("logits") is not None and head is None else None))
     loss_out = loss_out if loss_out is not None else torch.empty(3 * frame.n_items, dtype=torch.float32, device=dev)
-    ws = ws if ws is not None else torch.empty(workspace_bytes(L.GS_WS_LOSS, cfg, frame, 0), dtype=torch.uint8,
-                                               device=dev)
+    if ws is None and not static:
+        ws = torch.empty(workspace_bytes(L.GS_WS_LOSS, cfg, frame, 0), dtype=torch.uint8, device=dev)
     t = L.Targets(targets["rgb"].data_ptr(), targets["depth"].data_ptr(),
                   None if targets.get("label") is None else targets["label"].data_ptr())
     wv = (ctypes.c_float * 3)(*[float(x) for x in w])
@@ -238,11 +239,17 @@ def loss(cfg, frame: Frame, n_classes: int, rendered: dict, targets: dict, w=(1.
     gr = None
     if head is not None:
         gr = L.Grads(*(None if grads.get(k) is None else grads[k].data_ptr() for k in GRAD_FIELDS))
-    L.check(L.lib().gs_pyramid_loss(ctypes.byref(cfg), _ptr(frame.items_dev), frame.n_items, frame.n_pixels,
-                                    n_classes, ctypes.byref(ri), ctypes.byref(t),
-                                    ctypes.byref(hs) if hs is not None else None, wv, _ptr(loss_out),
-                                    ctypes.byref(gi), ctypes.byref(gr) if gr is not None else None, _ptr(ws),
-                                    ws.numel(), _stream(dev)), "gs_pyramid_loss")
+    hp = ctypes.byref(hs) if hs is not None else None
+    gp = ctypes.byref(gr) if gr is not None else None
+    if static:
+        L.check(L.lib().gs_pyramid_loss_static(ctypes.byref(cfg), _ptr(frame.items_dev), frame.n_items,
+                                               frame.n_pixels, n_classes, ctypes.byref(ri), ctypes.byref(t), hp, wv,
+                                               _ptr(loss_out), ctypes.byref(gi), gp, _stream(dev)),
+                "gs_pyramid_loss_static")
+    else:
+        L.check(L.lib().gs_pyramid_loss(ctypes.byref(cfg), _ptr(frame.items_dev), frame.n_items, frame.n_pixels,
+                                        n_classes, ctypes.byref(ri), ctypes.byref(t), hp, wv, _ptr(loss_out),
+                                        ctypes.byref(gi), gp, _ptr(ws), ws.numel(), _stream(dev)), "gs_pyramid_loss")
     return loss_out.view(frame.n_items, 3), grad
 
 

@@ -248,3 +248,22 @@ def test_invalid_learned_backward_enqueues_nothing():
         assert _learned_bwd_call(drop) == L.GS_ERR_INVALID_ARG, drop
     assert _learned_bwd_call("workspace") == L.GS_ERR_WORKSPACE
     assert _learned_bwd_call() == L.GS_ERR_HIP
+
+
+def test_static_loss_refuses_more_items_than_its_scratch_holds():
+    """gs_pyramid_loss_static returns GS_ERR_WORKSPACE for more than 2048 items before any
+    launch (placeholder pointers, never dereferenced)."""
+    lib = L.lib()
+    c = L.Config()
+    lib.gs_config_default(ctypes.byref(c))
+    c.n_sem = 4
+    fake = ctypes.c_void_p(256)
+    img = L.Images(fake, None, None, None, 100, None, 0)
+    t = L.Targets(fake, fake, fake)
+    w = (ctypes.c_float * 3)(1.0, 1.0, 1.0)
+    call = lambda n_items: lib.gs_pyramid_loss_static(  # noqa: E731
+        ctypes.byref(c), fake, n_items, 100, 4, ctypes.byref(img), ctypes.byref(t), None, w, fake,
+        ctypes.byref(img), None, None)
+    assert call(2049) == L.GS_ERR_WORKSPACE
+    assert call(-1) == L.GS_ERR_INVALID_ARG
+    assert call(0) == L.GS_OK
