@@ -2,16 +2,19 @@
 
 - the whole bin sort, bit-exact, against the oracle's sort stage run on the GPU's own
   single-precision projections;
-- the forward on sampled tiles (the longest lists and random ones; the oracle renders only
-  those tiles) and every gradient from an upstream gradient confined to them (the oracle
-  differentiates only those tiles);
+- the forward on every tile (room) or on sampled tiles (the 8-view batch: the longest lists
+  and random ones; the oracle renders only those tiles), and every gradient from an upstream
+  gradient confined to sampled tiles (the oracle differentiates only those tiles);
+- the learned batch (52 classes through the head, its decode fused into the loss): the
+  forward on sampled tiles, the embedding and geometry gradients from the step's own loss
+  gradient confined to them;
 - the loss with the SSIM term over the full room pyramid.
 """
 import numpy as np
 import pytest
 
 import oracle
-from tests.helpers import pixel_mask_to_channels, rel_check
+from tests.helpers import flagged, pixel_mask_to_channels, rel_check
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -75,13 +78,15 @@ def test_full_size_sort_and_sampled_tiles(name):
     mask = np.zeros(ntiles, np.uint8)
     mask[sorted(pick)] = 1
     ocfg = oracle.Config()
-    ref = oracle.render(ocfg, sc, views, tile_mask=mask)
-    mag = oracle.render(ocfg, sc, views, sem=np.abs(sc.sem), tile_mask=mask)["img"]
+    # the room is compared on every tile (the oracle renders it whole in a few seconds)
+    fmask = None if name == "room" else mask
+    ref = oracle.render(ocfg, sc, views, tile_mask=fmask)
+    mag = oracle.render(ocfg, sc, views, sem=np.abs(sc.sem), tile_mask=fmask)["img"]
     K = ref["K"]
-    sel = _tile_pixels(its, mask)
-    flag = ref["flag"] != 0
-    assert flag[sel].mean() < 0.02
-    keep_px = sel & ~flag
+    sel = np.ones(len(ref["T"]), bool) if fmask is None else _tile_pixels(its, mask)
+    flag = flagged(ref["flag"][sel], "pixels compared")
+    keep_px = sel.copy()
+    keep_px[np.flatnonzero(sel)[flag]] = False
     keep = pixel_mask_to_channels(keep_px, its, K)
     got = st.img["color"].cpu().numpy()
     rel_check(got, ref["img"], FWD_TOL, mask=~keep, name="image", scale=mag)
@@ -90,6 +95,7 @@ def test_full_size_sort_and_sampled_tiles(name):
     np.testing.assert_array_equal(nc[keep_px], ref["n_contrib"][keep_px])
 
     # backward from an upstream gradient on the sampled tiles only
+    keep = pixel_mask_to_channels(keep_px & _tile_pixels(its, mask), its, K)
     gimg = (rng.normal(size=got.shape) * 1e-3).astype(np.float32)
     gimg[~keep] = 0.0
     grads = raster.render_bwd(st.cfg, st.g, st.proj, st.frame, st.sorter, st.img,
@@ -138,3 +144,75 @@ def test_full_size_loss_with_ssim_on_the_room_pyramid():
         HW = it["W"] * it["H"]
         scale[it["pix0"] * K: it["pix0"] * K + 3 * HW] = (1 - 0.2) / (3 * HW)
     rel_check(st.grad["color"].cpu().numpy(), g_ref, BWD_TOL, name="dloss/dimg", scale=scale)
+
+
+def test_full_size_learned_batch_sampled_tiles():
+    """The learned 8-view batch (500k Gaussians, 52 classes through the head) in the launch
+    the benchmark times: its whole step runs (decode fused into the loss); the composited
+    rgb, depth and embedding are compared on sampled tiles, and the gradients of every
+    Gaussian parameter (the embedding's included) from an upstream gradient confined to
+    them."""
+    import bench
+    from paper_2412_01217_amd import raster, scenes
+    sc, views = scenes.config_learned()
+    rng = np.random.default_rng(7710)
+    w = scenes.head_weights(52, seed=6030)
+    head = dict(W1=torch.from_numpy(w["W1"].view(np.int16).copy()).cuda(), b1=torch.from_numpy(w["b1"]).cuda(),
+                W2=torch.from_numpy(w["W2"].view(np.int16).copy()).cuda(), b2=torch.from_numpy(w["b2"]).cuda())
+    cfg_p = raster.config(52)
+    tg = bench.make_targets(cfg_p, raster.Frame(cfg_p, views), sc, "cuda:0")
+    st = bench.learned_step(sc, views, head, "cuda:0", tg)
+    st.run()
+    torch.cuda.synchronize()
+    assert not st.overflowed()
+    assert np.isfinite(st.loss.cpu().numpy()).all()
+    its = oracle.items(views)
+    ranges = st.sorter.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    ntiles = len(ranges)
+    lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    pick = set(np.argsort(-lens)[:4].tolist()) | set(rng.choice(ntiles, 8, replace=False).tolist())
+    mask = np.zeros(ntiles, np.uint8)
+    mask[sorted(pick)] = 1
+    emb = scenes.bf16_bits_to_f32(sc.emb).astype(np.float64)
+    ocfg = oracle.Config()
+    ref = oracle.render(ocfg, sc, views, sem=emb, tile_mask=mask)
+    mag = oracle.render(ocfg, sc, views, sem=np.abs(emb), tile_mask=mask)["img"]
+    K = 20
+    sel = _tile_pixels(its, mask)
+    flag = flagged(ref["flag"][sel], "sampled pixels")
+    keep_px = sel.copy()
+    keep_px[np.flatnonzero(sel)[flag]] = False
+    keep = pixel_mask_to_channels(keep_px, its, K)
+    got = st.img["color"].cpu().numpy()
+    rel_check(got, ref["img"], FWD_TOL, mask=~keep, name="rgb/depth/E", scale=mag)
+    nc = st.img["n_contrib"].cpu().numpy()
+    np.testing.assert_array_equal(nc[keep_px], ref["n_contrib"][keep_px])
+    gimg = (rng.normal(size=got.shape) * 1e-3).astype(np.float32)
+    gimg[~keep] = 0.0
+    grads = raster.render_bwd(st.cfg, st.g, st.proj, st.frame, st.sorter, st.img,
+                              dict(color=torch.from_numpy(gimg).cuda(), logits=None), ws=st.bwd_ws)
+    torch.cuda.synchronize()
+    g64 = gimg.astype(np.float64)
+    ob = oracle.backward(ocfg, sc, views, g64, sem=emb, tile_mask=mask)
+    om = oracle.backward(ocfg, sc, views, np.abs(g64), sem=emb, tile_mask=mask)
+    geo = ("mean", "log_scale", "quat", "opacity")
+    per_tile = {k: np.zeros_like(ob[k]) for k in geo}
+    for t in sorted(pick):
+        m1 = np.zeros_like(mask)
+        m1[t] = 1
+        o1 = oracle.backward(ocfg, sc, views, g64, sem=emb, tile_mask=m1)
+        for k in geo:
+            per_tile[k] += np.abs(o1[k])
+    # as for the plain workloads: Gaussians that also reach a flagged pixel are left out, and
+    # the geometric gradients are held to 1e-3 of max(|ref|, the sum of the per-tile
+    # magnitudes, 5 % of the rms)
+    bad = flagged(ob["gflag"], "Gaussians touching a flagged pixel", bound=0.01)
+    for k, ko in (("mean", "mean"), ("log_scale", "log_scale"), ("quat", "quat"), ("opacity", "opacity"),
+                  ("rgb", "rgb"), ("emb", "sem")):
+        g = grads[k].cpu().numpy()
+        m = np.broadcast_to(bad.reshape(-1, *([1] * (g.ndim - 1))), g.shape)
+        feat = k in ("rgb", "emb")
+        res = rel_check(g, ob[ko], BWD_TOL, mask=m, name=k, scale=om[ko] if feat else per_tile[k],
+                        floor=0.01 if feat else 0.05)
+        assert res["l2"] < 1e-5, (k, res)
+    rel_check(grads["pose"].cpu().numpy(), ob["pose"], BWD_TOL, name="pose")
