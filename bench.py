@@ -572,7 +572,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    clocks = gpu_clocks()   # queried before this process initialises the GPU
+    # queried before this process initialises the GPU; skipped under --quick, whose runs are
+    # the profiled ones (a profiler refuses the query's child process)
+    clocks = None if args.quick else gpu_clocks()
     import torch
     dev = "cuda:0"
     torch.cuda.set_device(0)
