@@ -181,21 +181,28 @@ def backward(cfg: Config, scene, views, gimg, sem=None, tile_mask=None, want_g2d
     return out
 
 
-def loss(views, S, img, t_rgb, t_depth, t_label, w=(1.0, 1.0, 1.0), tile_w=16, tile_h=16, ssim_lambda=0.0):
-    """Per-item [L_rgb, L1 depth (valid), CE] and the image-layout gradient of
+def loss(views, S, img, t_rgb, t_depth, t_label, w=(1.0, 1.0, 1.0), tile_w=16, tile_h=16, ssim_lambda=0.0,
+         t_sem=None, sem_ssim_lambda=0.0):
+    """Per-item [L_rgb, L1 depth (valid), L_sem] and the image-layout gradient of
     w . sum over items. L_rgb = (1 - lambda) mean L1 + lambda (1 - mean SSIM); lambda = 0
-    gives the plain L1 mean."""
+    gives the plain L1 mean. L_sem is the cross-entropy against t_label, or, with t_sem (a
+    3-channel semantic colour image in the t_rgb layout, S = 3), eq. 12: the same form as
+    L_rgb on the semantic channels with lambda = sem_ssim_lambda."""
     lib = _load()
+    if t_sem is not None and S != 3:
+        raise ValueError("the semantic colour loss composites 3 semantic channels")
     n_items, P, _ = layout(views, tile_w, tile_h)
     K = 4 + S
     _, ci = Config(tile_w=tile_w, tile_h=tile_h).arrays(S)
     vi = _views(views)[1]
     ls = np.zeros((n_items, 3))
     gimg = np.zeros(P * K)
-    lab = np.ascontiguousarray(t_label, dtype=np.int32)
-    w4 = np.array([w[0], w[1], w[2], ssim_lambda], np.float64)
-    lib.or_loss(_p(ci), ctypes.c_int(len(views)), _p(vi), _p(_d(img)), _p(_d(t_rgb)), _p(_d(t_depth)),
-                _p(lab), _p(w4), _p(ls), _p(gimg))
+    lab = np.ascontiguousarray(np.zeros(P, np.int32) if t_label is None else t_label, dtype=np.int32)
+    w5 = np.array([w[0], w[1], w[2], ssim_lambda, sem_ssim_lambda], np.float64)
+    ts = None if t_sem is None else _d(t_sem)
+    rc = lib.or_loss(_p(ci), ctypes.c_int(len(views)), _p(vi), _p(_d(img)), _p(_d(t_rgb)), _p(_d(t_depth)),
+                     _p(lab), _p(ts), _p(w5), _p(ls), _p(gimg))
+    assert rc == 0, rc
     return ls, gimg
 
 

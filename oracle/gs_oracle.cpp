@@ -747,15 +747,20 @@ static double ssim_channel(const double* x, const double* y, int W, int H, doubl
 }
 
 // Pyramid loss, summed over items: w0 * L_rgb + w1 * mean|D-Dgt| over valid (Dgt > 0)
-// pixels + w2 * mean cross-entropy of softmax(S) against the label (a label outside [0, S)
-// marks an unlabelled pixel, which adds no term but counts in the mean), per item, with
-// L_rgb = (1 - lambda) mean|R-Rgt| over 3HW + lambda (1 - mean SSIM over the 3 channels)
-// (eq. 10 with the SSIM term read as 1 - SSIM), lambda = w[3].
+// pixels + w2 * L_sem, per item, with
+//   L_rgb = (1 - lambda_r) mean|R-Rgt| over 3HW + lambda_r (1 - mean SSIM over the 3 channels)
+// (eq. 10 with the SSIM term read as 1 - SSIM), lambda_r = w[3], and L_sem either
+//   - (tsem == null) the mean cross-entropy of softmax(S) against the label (a label outside
+//     [0, S) marks an unlabelled pixel, which adds no term but counts in the mean), or
+//   - (tsem != null, S = 3: the semantic feature is a colour) eq. 12, the same form as L_rgb
+//     on the semantic colour image against tsem: (1 - lambda_s) mean|S-Sgt| over 3HW +
+//     lambda_s (1 - mean SSIM over its 3 channels), lambda_s = w[4].
 // loss: [n_items][3] unweighted terms. gimg: dLoss/dimg in the image layout.
 int or_loss(const int* ci, int n_views, const int* vi, const double* img, const double* trgb, const double* tdepth,
-            const int* tlabel, const double* w, double* loss, double* gimg) {
+            const int* tlabel, const double* tsem, const double* w, double* loss, double* gimg) {
   double cd[8] = {0};
   Cfg c = read_cfg(cd, ci);
+  if (tsem && c.S != 3) return -1;
   std::vector<double> vd(16 * size_t(n_views), 1.0);
   auto items = make_items(c, n_views, vd.data(), vi);
   int S = c.S, K = 4 + S;
@@ -767,7 +772,8 @@ int or_loss(const int* ci, int n_views, const int* vi, const double* img, const 
     double* GI = gimg + it.pix0 * K;
     const double* TR = trgb + it.pix0 * 3;
     const double* TD = tdepth + it.pix0;
-    const int* TL = tlabel + it.pix0;
+    const int* TL = tsem ? nullptr : tlabel + it.pix0;
+    const double* TS = tsem ? tsem + it.pix0 * 3 : nullptr;
     int64_t nvalid = 0;
     for (int64_t p = 0; p < HW; ++p) nvalid += TD[p] > 0;
     double lr = 0, ld = 0, ls = 0;
@@ -784,7 +790,14 @@ int or_loss(const int* ci, int n_views, const int* vi, const double* img, const 
       } else {
         GI[3 * HW + p] = 0;
       }
-      if (S > 0 && (TL[p] < 0 || TL[p] >= S)) {
+      if (TS) {
+        // eq. 12's L1 part: the semantic colour channels against their targets
+        for (int ch = 0; ch < 3; ++ch) {
+          double d = I[(4 + ch) * HW + p] - TS[ch * HW + p];
+          ls += std::fabs(d);
+          GI[(4 + ch) * HW + p] = w[2] * ((d > 0) - (d < 0)) / (3.0 * HW);
+        }
+      } else if (S > 0 && (TL[p] < 0 || TL[p] >= S)) {
         // a label outside [0, S) marks an unlabelled pixel: no cross-entropy term
         for (int ch = 0; ch < S; ++ch) GI[(4 + ch) * HW + p] = 0.0;
       } else if (S > 0) {
@@ -814,7 +827,24 @@ int or_loss(const int* ci, int n_views, const int* vi, const double* img, const 
     }
     loss[3 * k] = (1.0 - lam) * lr / (3.0 * HW) + lam * (1.0 - ssim);
     loss[3 * k + 1] = nvalid ? ld / double(nvalid) : 0.0;
-    loss[3 * k + 2] = S > 0 ? ls / double(HW) : 0.0;
+    if (TS) {
+      // eq. 12: L1 and SSIM of the semantic colour image, with its own lambda_s
+      const double lam_s = w[4];
+      double ssim_s = 1.0;
+      if (lam_s != 0.0) {
+        double sm3 = 0;
+        std::vector<double> gs(HW);
+        for (int ch = 0; ch < 3; ++ch) {
+          sm3 += ssim_channel(I + (4 + ch) * HW, TS + ch * HW, it.W, it.H, gs.data());
+          for (int64_t p = 0; p < HW; ++p)
+            GI[(4 + ch) * HW + p] = (1.0 - lam_s) * GI[(4 + ch) * HW + p] - w[2] * lam_s * gs[p] / 3.0;
+        }
+        ssim_s = sm3 / 3.0;
+      }
+      loss[3 * k + 2] = (1.0 - lam_s) * ls / (3.0 * HW) + lam_s * (1.0 - ssim_s);
+    } else {
+      loss[3 * k + 2] = S > 0 ? ls / double(HW) : 0.0;
+    }
   }
   return 0;
 }
