@@ -35,9 +35,11 @@ VALU_PEAK_UNPACKED_TFLOPS = 78.6
 
 
 # ----------------------------------------------------------------------------- workloads
-def make_targets(cfg_plain, fr, sc, device):
+def make_targets(cfg_plain, fr, sc, device, sem_color=False):
     """rgb, depth, labels: a perturbed copy of the scene rendered at every item, level 0
-    box-downsampled to the coarser levels, labels = argmax of the class channels."""
+    box-downsampled to the coarser levels, labels = argmax of the class channels; with
+    sem_color (a scene whose semantic feature is a 3-channel colour) the semantic colour
+    image instead of labels."""
     import torch
     from paper_2412_01217_amd import raster, scenes
     C = cfg_plain.n_sem
@@ -58,22 +60,37 @@ def make_targets(cfg_plain, fr, sc, device):
         planes = timg["color"][pb * K: pb * K + K * HW].view(K, HW)
         rgb[pb * 3: pb * 3 + 3 * HW] = planes[:3].reshape(-1)
         depth[pb: pb + HW] = planes[3]
+    if sem_color:
+        semc = torch.empty(3 * fr.n_pixels, dtype=torch.float32, device=device)
+        for it in fr.item_list():
+            HW = it["W"] * it["H"]
+            pb = it["pixel_base"]
+            semc[pb * 3: pb * 3 + 3 * HW] = timg["color"][pb * K: pb * K + K * HW].view(K, HW)[4:7].reshape(-1)
+        torch.cuda.synchronize()
+        return dict(rgb=rgb, depth=depth, sem_color=semc)
     torch.cuda.synchronize()
     return dict(rgb=rgb, depth=depth, label=labels)
 
 
-def plain_step(sc, views, device, targets=None, variant=0, tile_order=0, ssim_lambda=0.0, isotropic=0, sh=None):
-    """sh: (rgb degree, semantic degree) of seeded SH bands N(0, 0.1), or None."""
+def plain_step(sc, views, device, targets=None, variant=0, tile_order=0, ssim_lambda=0.0, isotropic=0, sh=None,
+               sem_ssim_lambda=None):
+    """sh: (rgb degree, semantic degree) of seeded SH bands N(0, 0.1), or None.
+    sem_ssim_lambda: not None for a scene whose semantic feature is a 3-channel colour,
+    trained with eq. 12's loss at that lambda_s against a semantic colour target."""
     import torch
     from paper_2412_01217_amd import raster
     from paper_2412_01217_amd.step import MappingStep
     C = sc.n_classes
     cfg = raster.config(C, variant=variant, tile_order=tile_order, ssim_lambda=float(ssim_lambda),
-                        isotropic=int(isotropic), view_features=int(sh is not None))
+                        isotropic=int(isotropic), view_features=int(sh is not None),
+                        sem_ssim_lambda=float(sem_ssim_lambda or 0.0))
     fr = raster.Frame(cfg, views, device=device)
     g = raster.to_device(sc, device)
     g.pop("emb", None)
-    targets = targets if targets is not None else make_targets(cfg, fr, sc, device)
+    semc = sem_ssim_lambda is not None
+    targets = targets if targets is not None else make_targets(cfg, fr, sc, device, sem_color=semc)
+    if semc:
+        return MappingStep(cfg, fr, g, targets, 0), targets
     shd = None
     if sh is not None:
         rng = np.random.default_rng(7000)
@@ -511,6 +528,21 @@ def sh_report(args, dev, sc, views, targets, degrees=(3, 1)):
             "stage_ms": m["stage_ms"]}
 
 
+def semantic_colour_report(args, dev, sc, views, lam=0.2):
+    """The room step with the paper's semantic colour feature (3 channels per Gaussian, its
+    class's colour) and its full loss: eq. 10 and eq. 12 with lambda_r = lambda_s = 0.2."""
+    import torch
+    from paper_2412_01217_amd import scenes
+    sc3 = scenes.semantic_colour_scene(sc)
+    step, _ = plain_step(sc3, views, dev, variant=args.variant, ssim_lambda=lam, sem_ssim_lambda=lam)
+    m = measure(step, args.steps, args.warmup, graph=not args.eager)
+    px = step.frame.n_pixels
+    del step
+    torch.cuda.empty_cache()
+    return {"semantic_feature": "3-channel semantic colour", "ssim_lambda": lam, "sem_ssim_lambda": lam,
+            "value": px / 1e6 / (m["ms"] * 1e-3), "unit": "MP/s", "ms_per_step": m["ms"], "stage_ms": m["stage_ms"]}
+
+
 def ssim_report(args, dev, sc, views, targets, ms_ref, loss_ms_ref, lam=0.2):
     """The same room step with the colour loss of eq. 10 at the paper's lambda = 0.2
     (L1 and SSIM) in place of the plain L1 term."""
@@ -630,6 +662,8 @@ def main():
             out["room"]["isotropic_primitive"] = isotropic_report(args, dev, rsc, rviews, rtargets)
             torch.cuda.empty_cache()
             out["room"]["sh_features"] = sh_report(args, dev, rsc, rviews, rtargets)
+            torch.cuda.empty_cache()
+            out["room"]["semantic_colour_eq12"] = semantic_colour_report(args, dev, rsc, rviews)
             torch.cuda.empty_cache()
             out["batch"] = batch_report(args, dev)
             torch.cuda.empty_cache()

@@ -76,6 +76,9 @@ typedef struct gs_config {
                               view-dependent colours from gs_sh_features), and gs_render_bwd's
                               grads->rgb / grads->sem have the same per-view layout. Plain
                               semantics only (not with an embedding) */
+  float sem_ssim_lambda;   /* 0: weight lambda_s of the SSIM term of the semantic colour loss (eq. 12,
+                              read as (1 - lambda_s) L1 + lambda_s (1 - SSIM)), 0..1, used when the
+                              targets carry a semantic colour image; the paper trains with 0.2 */
 } gs_config;
 
 /* One camera view: world -> camera transform x_c = R x_w + t (OpenCV axes,
@@ -143,6 +146,8 @@ typedef struct gs_targets {
   const float* rgb;      /* [P * 3] planar per item */
   const float* depth;    /* [P]; <= 0 marks a missing depth */
   const int32_t* label;  /* [P] class index in [0, n_classes); any other value = unlabelled */
+  const float* sem_color; /* [P * 3] planar per item: a semantic colour image (eq. 12), or NULL for
+                             the cross-entropy on labels */
 } gs_targets;
 
 /* Learned semantic head: logits = W2 relu(W1 E + b1) + b2 (bfloat16 weights). */
@@ -234,16 +239,21 @@ int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
                   int32_t n_items, int32_t n_tiles, const uint32_t* vals, const uint32_t* ranges,
                   const gs_head* head, gs_images* out, void* stream);
 
-/* Per-level loss (eq. 10-13; semantics as cross-entropy on the class logits): for each
- * item, loss_dev[3i..3i+2] = L_rgb, mean |D - D_gt| over pixels with D_gt > 0, and
- * mean -log softmax(S)[label], where L_rgb = (1 - l) mean |R - R_gt| over 3HW + l (1 - SSIM),
- * l = cfg->ssim_lambda, and SSIM is the mean over the 3 colour channels and all pixels of
- * the structural similarity of Wang et al. (2004) with an 11 x 11 Gaussian window of
- * standard deviation 1.5 (weights summing to 1; both images taken as zero outside),
+/* Per-level loss (eq. 10-13): for each item, loss_dev[3i..3i+2] = L_rgb, mean |D - D_gt|
+ * over pixels with D_gt > 0, and L_sem, where L_rgb = (1 - l) mean |R - R_gt| over 3HW +
+ * l (1 - SSIM), l = cfg->ssim_lambda, and SSIM is the mean over the 3 colour channels and all
+ * pixels of the structural similarity of Wang et al. (2004) with an 11 x 11 Gaussian window
+ * of standard deviation 1.5 (weights summing to 1; both images taken as zero outside),
  * C1 = 0.01^2, C2 = 0.03^2. grad_out->color receives the gradient of
  * sum_i (w[0] L_rgb + w[1] L_depth + w[2] L_sem) with respect to every rendered channel.
- * w is a host array of 3. The class logits S are, in plain mode, channels 4.. of
- * rendered->color; in learned mode (cfg->n_sem = 16) either
+ * w is a host array of 3. L_sem is one of:
+ *  - targets->sem_color != NULL (eq. 12, the semantic feature a colour): plain mode with
+ *    cfg->n_sem = 3 and n_classes = 0; channels 4..6 of rendered->color are the semantic
+ *    colour image S and L_sem = (1 - l_s) mean |S - S_gt| over 3HW + l_s (1 - SSIM(S, S_gt)),
+ *    l_s = cfg->sem_ssim_lambda, SSIM as above;
+ *  - otherwise the mean over pixels of -log softmax(S)[label] (a label outside
+ *    [0, n_classes) adds no term), with the class logits S, in plain mode, channels 4.. of
+ *    rendered->color; in learned mode (cfg->n_sem = 16) either
  *  - head != NULL: the decode S = W2 relu(W1 E + b1) + b2 of the embedding channels E,
  *    evaluated inside the loss (matrix cores, as gs_render_fwd's) and differentiated there:
  *    grad_out->color channels 4..19 receive dL/dE and head_grads->head_W1 .. head_b2 the

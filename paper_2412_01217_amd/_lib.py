@@ -40,7 +40,7 @@ class Config(ctypes.Structure):
                 ("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("guard", c_float),
                 ("full_rect", c_int32), ("n_sem", c_int32), ("variant", c_int32), ("tile_order", c_int32),
                 ("fwd_chunk", c_int32), ("ssim_lambda", c_float), ("isotropic", c_int32),
-                ("view_features", c_int32)]
+                ("view_features", c_int32), ("sem_ssim_lambda", c_float)]
 
 
 class View(ctypes.Structure):
@@ -68,7 +68,7 @@ class Images(ctypes.Structure):
 
 
 class Targets(ctypes.Structure):
-    _fields_ = [("rgb", c_void_p), ("depth", c_void_p), ("label", c_void_p)]
+    _fields_ = [("rgb", c_void_p), ("depth", c_void_p), ("label", c_void_p), ("sem_color", c_void_p)]
 
 
 class ParamArrays(ctypes.Structure):

@@ -67,7 +67,7 @@ int launch_render_bwd(const gs_config& cfg, const gs_gaussians& g, const gs_proj
   return launch_render_bwd_split(cfg, g, p, items, n_items, n_tiles, vals, ranges, fwd, gin, g2d, gr, seg_ws, cap, s);
 }
 int launch_loss(const gs_item*, int, int64_t, int, int, const float*, const float*, const gs_targets&, const gs_head*,
-                const float*, float, float*, float*, float*, const gs_grads*, float*, hipStream_t);
+                const float*, float, float, float*, float*, float*, const gs_grads*, float*, hipStream_t);
 int launch_downsample(const gs_item*, int, int64_t, int, int, float*, int32_t*, hipStream_t);
 size_t loss_workspace(int n_items);
 size_t head_bwd_workspace();
@@ -102,6 +102,7 @@ bool cfg_ok(const gs_config* c) {
   if (c->tile_order < 0 || c->tile_order > 1) return false;
   if (c->fwd_chunk < 0 || c->fwd_chunk > 65535) return false;
   if (!(c->ssim_lambda >= 0.0f && c->ssim_lambda <= 1.0f)) return false;
+  if (!(c->sem_ssim_lambda >= 0.0f && c->sem_ssim_lambda <= 1.0f)) return false;
   if (c->isotropic < 0 || c->isotropic > 1) return false;
   if (c->view_features < 0 || c->view_features > 1) return false;
   return true;
@@ -142,6 +143,7 @@ void gs_config_default(gs_config* c) {
   c->ssim_lambda = 0.0f;
   c->isotropic = 0;
   c->view_features = 0;
+  c->sem_ssim_lambda = 0.0f;
 }
 
 const char* gs_status_string(int s) {
@@ -273,6 +275,11 @@ static int loss_args(const gs_config* cfg, const gs_item* items_dev, int32_t n_i
   if (n_items == 0) return GS_OK;
   if (!items_dev || !loss_dev || !rendered->color || !grad_out->color || !targets->rgb || !targets->depth)
     return GS_ERR_INVALID_ARG;
+  if (targets->sem_color) {
+    // eq. 12: the semantic feature is a 3-channel colour, composited as channels 4..6
+    if (cfg->n_sem != 3 || n_classes != 0 || head || rendered->logits) return GS_ERR_INVALID_ARG;
+    return GS_OK;
+  }
   if (n_classes > 0 && !targets->label) return GS_ERR_INVALID_ARG;
   if (head) {
     // the decode inside the loss: the embedding channels in, the head's gradients out
@@ -296,7 +303,8 @@ int gs_pyramid_loss(const gs_config* cfg, const gs_item* items_dev, int32_t n_it
   if (st != GS_OK || n_items == 0) return st;
   if (!workspace || ws_bytes < loss_workspace(n_items)) return GS_ERR_WORKSPACE;
   return launch_loss(items_dev, n_items, n_pixels, 4 + cfg->n_sem, n_classes, rendered->color,
-                     head ? nullptr : rendered->logits, *targets, head, w, cfg->ssim_lambda, loss_dev, grad_out->color,
+                     head ? nullptr : rendered->logits, *targets, head, w, cfg->ssim_lambda,
+                     targets->sem_color ? cfg->sem_ssim_lambda : 0.0f, loss_dev, grad_out->color,
                      head ? nullptr : grad_out->logits, head_grads, (float*)workspace, (hipStream_t)stream);
 }
 

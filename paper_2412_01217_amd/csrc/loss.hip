@@ -1,5 +1,6 @@
 // Per-level reconstruction loss (paper eq. 10-13: L1 terms, the SSIM term of the colour
-// loss, semantics as a per-pixel cross-entropy on the composited class logits) and the
+// loss, semantics as a per-pixel cross-entropy on the composited class logits or, when the
+// semantic feature is a colour, eq. 12's L1 and SSIM on the semantic colour image) and the
 // image pyramid of the targets (eq. 4-6, 2x2 box means). The L1 / cross-entropy pass and
 // the pyramid are elementwise over pixels and bound by HBM traffic: one thread per pixel,
 // planar channel reads coalesced along x. SSIM is a windowed filter: LDS-tiled, one
@@ -64,14 +65,17 @@ __device__ __forceinline__ PixItem lane_item(const gs_item* __restrict__ items, 
 // logits, and their image gradients, in one pass over each pixel's channels (every load
 // issued before the arithmetic). The depth gradient is written as sign(d) (or 0) and
 // scaled by w1 / n_valid afterwards, once the valid counts are known; the logits of a
-// pixel are held in registers (CM >= classes).
+// pixel are held in registers (CM >= classes). With a semantic colour target (tsem, eq. 12;
+// then CM = 0 and K = 7) the semantic term is instead the L1 mean of channels 4..6 against
+// it, with its gradient written here unless the SSIM pass writes it (sem_grad false).
 // Every input and output element is touched once: loads and stores are non-temporal.
 template <int CM>
 __global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items, int n_items, int64_t P, int K,
                                               int n_classes, const float* __restrict__ color,
                                               const float* __restrict__ logits, const float* __restrict__ trgb,
                                               const float* __restrict__ tdepth, const int32_t* __restrict__ tlabel,
-                                              float w0, float w2, bool rgb_grad, float* __restrict__ loss_slots,
+                                              const float* __restrict__ tsem, float w0, float w2, bool rgb_grad,
+                                              bool sem_grad, float* __restrict__ loss_slots,
                                               float* __restrict__ count_slots, float* __restrict__ gcolor,
                                               float* __restrict__ glogits) {
   const int slot = blockIdx.x % kSlots;
@@ -126,6 +130,16 @@ __global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items,
     // (the head's backward adds its input gradient there)
     if (logits)
       for (int ch = 4; ch < K; ++ch) __builtin_nontemporal_store(0.0f, &gcolor[cb + ch * HW]);
+    if (CM == 0 && tsem) {
+      // eq. 12's L1 part on the semantic colour channels 4..6
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const float d = __builtin_nontemporal_load(&color[cb + (4 + ch) * HW]) -
+                        __builtin_nontemporal_load(&tsem[tb + ch * HW]);
+        ls += fabsf(d) * inv3;
+        if (sem_grad) __builtin_nontemporal_store(w2 * sgn(d) * inv3, &gcolor[cb + (4 + ch) * HW]);
+      }
+    }
     if (sem) {
       float* G = logits ? glogits + lb : gcolor + lb;
       float m = -INFINITY;
@@ -173,11 +187,13 @@ __global__ __launch_bounds__(256) void k_loss(const gs_item* __restrict__ items,
   }
 }
 
-// Folds the slots: loss[i] = (colour term, L1 depth / n_valid, cross-entropy); n_valid[i].
-// The colour term is (1 - lambda) L1 + lambda (1 - mean SSIM) (lambda = 0: the L1 mean).
+// Folds the slots: loss[i] = (colour term, L1 depth / n_valid, semantic term); n_valid[i].
+// The colour term is (1 - lambda) L1 + lambda (1 - mean SSIM) (lambda = 0: the L1 mean); the
+// semantic term is the cross-entropy, or the same form as the colour term with lambda_s on
+// the semantic colour image (its SSIM sums in the second block of n_items slot rows).
 __global__ void k_fold_loss(const float* __restrict__ loss_slots, const float* __restrict__ count_slots,
-                            const float* __restrict__ ssim_slots, float lambda, int n_items, float* __restrict__ loss,
-                            float* __restrict__ nvalid) {
+                            const float* __restrict__ ssim_slots, float lambda, float lambda_s, int n_items,
+                            float* __restrict__ loss, float* __restrict__ nvalid) {
   for (int i = threadIdx.x; i < n_items * 4; i += blockDim.x) {
     const int item = i >> 2, comp = i & 3;
     const float* src = comp < 3 ? loss_slots + (int64_t)(3 * item + comp) * kSlots : count_slots + (int64_t)item * kSlots;
@@ -190,6 +206,11 @@ __global__ void k_fold_loss(const float* __restrict__ loss_slots, const float* _
       float m = 0.0f;
       for (int k = 0; k < kSlots; ++k) m += ss[k];
       loss[3 * item] = (1.0f - lambda) * s + lambda * (1.0f - m);
+    } else if (comp == 2 && lambda_s != 0.0f) {
+      const float* ss = ssim_slots + (int64_t)(n_items + item) * kSlots;
+      float m = 0.0f;
+      for (int k = 0; k < kSlots; ++k) m += ss[k];
+      loss[3 * item + 2] = (1.0f - lambda_s) * s + lambda_s * (1.0f - m);
     } else if (comp != 1) {
       loss[3 * item + comp] = s;
     }
@@ -288,17 +309,19 @@ __global__ void k_ssim_prefix(const gs_item* __restrict__ items, int n_items, in
   }
 }
 
-// Where one (tile, channel) unit of the SSIM pass sits.
+// Where one (tile, channel) unit of the SSIM pass sits. Channels 0..2 are the colour image
+// (planes 0..2, targets trgb), 3..5 the semantic colour image of eq. 12 (planes 4..6,
+// targets tsem); a launch covers the nch channels from c0.
 struct SsUnit {
   int64_t tile, pixel_base;
   int item, ch, W, H, tx0, ty0;
 };
 
 __device__ __forceinline__ SsUnit ss_locate(const gs_item* __restrict__ items, int n_items,
-                                            const int64_t* __restrict__ prefix, int64_t w) {
+                                            const int64_t* __restrict__ prefix, int64_t w, int nch, int c0) {
   SsUnit u;
-  u.tile = w / 3;
-  u.ch = (int)(w - 3 * u.tile);
+  u.tile = w / nch;
+  u.ch = c0 + (int)(w - nch * u.tile);
   int lo = 0, hi = n_items - 1;                   // last item with prefix <= tile
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -321,11 +344,12 @@ constexpr int kSsLoads = (kSsN1 * kSsN1 + 255) / 256;   // input values per thre
 // Inputs of a unit over [ty0 - 10, ty0 + 42) x [tx0 - 10, tx0 + 42), zero outside the image,
 // all loads issued before any is used.
 __device__ __forceinline__ void ss_fetch(const SsUnit& u, int K, const float* __restrict__ color,
-                                         const float* __restrict__ trgb, float (&px)[kSsLoads],
-                                         float (&py)[kSsLoads]) {
+                                         const float* __restrict__ trgb, const float* __restrict__ tsem,
+                                         float (&px)[kSsLoads], float (&py)[kSsLoads]) {
   const int64_t HW = (int64_t)u.W * u.H;
-  const float* X = color + u.pixel_base * K + u.ch * HW;
-  const float* Y = trgb + u.pixel_base * 3 + u.ch * HW;
+  const bool semc = u.ch >= 3;
+  const float* X = color + u.pixel_base * K + (semc ? u.ch + 1 : u.ch) * HW;
+  const float* Y = (semc ? tsem : trgb) + u.pixel_base * 3 + (semc ? u.ch - 3 : u.ch) * HW;
 #pragma unroll
   for (int k = 0; k < kSsLoads; ++k) {
     const int e = (int)threadIdx.x + 256 * k;
@@ -384,14 +408,16 @@ __device__ __forceinline__ void ss_vpass(const float* __restrict__ sH, int r0, i
   }
 }
 
-// Persistent loop over the 3 x tile-count (tile, channel) units; the next unit's inputs
-// are loaded into registers while the current one is filtered. Writes the colour gradient
-// w0 ((1 - lambda) sign(x - y) / (3HW) - lambda / 3 d mean(S) / dx) of the tile's pixels and
-// adds S / (3HW) over them to the item's SSIM slots.
+// Persistent loop over the nch x tile-count (tile, channel) units; the next unit's inputs
+// are loaded into registers while the current one is filtered. Writes the gradient
+// w ((1 - lambda) sign(x - y) / (3HW) - lambda / 3 d mean(S) / dx) of the tile's pixels (w0 and
+// lambda for the colour channels, w2 and lambda_s for the semantic colour ones) and adds
+// S / (3HW) over them to the item's SSIM slots (semantic colour: rows n_items + item).
 __global__ __launch_bounds__(256) void k_ssim(const gs_item* __restrict__ items, int n_items,
-                                              const int64_t* __restrict__ prefix, int K,
+                                              const int64_t* __restrict__ prefix, int K, int nch, int c0,
                                               const float* __restrict__ color, const float* __restrict__ trgb,
-                                              float w0, float lambda, float* __restrict__ ssim_slots,
+                                              const float* __restrict__ tsem, float w0, float lambda, float w2,
+                                              float lambda_s, float* __restrict__ ssim_slots,
                                               float* __restrict__ gcolor) {
   __shared__ float sXY[2 * kSsN1 * kSsN1];       // inputs; later the second horizontal pass
   __shared__ float sH[5 * kSsN1 * kSsN2];        // first horizontal pass; later A, B, C
@@ -402,13 +428,13 @@ __global__ __launch_bounds__(256) void k_ssim(const gs_item* __restrict__ items,
   static_assert(3 * kSsN2 * kSsN2 <= 5 * kSsN1 * kSsN2 && 3 * kSsN2 * kSsHA <= 2 * kSsN1 * kSsN1,
                 "ssim LDS aliasing");
   const int tid = threadIdx.x;
-  const int64_t total = 3 * prefix[n_items];
+  const int64_t total = nch * prefix[n_items];
   const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
   int64_t w = blockIdx.x;
   if (w >= total) return;
   float px[kSsLoads], py[kSsLoads];
-  SsUnit cur = ss_locate(items, n_items, prefix, w);
-  ss_fetch(cur, K, color, trgb, px, py);
+  SsUnit cur = ss_locate(items, n_items, prefix, w, nch, c0);
+  ss_fetch(cur, K, color, trgb, tsem, px, py);
   const bool vunit = tid < kSsN2 * (kSsN2 / kSsV);
   const int vj = tid % kSsN2, vr0 = (tid / kSsN2) * kSsV;   // first vertical pass
   const int oj = tid % kSsT, or0 = (tid / kSsT) * kSsV2;    // second vertical pass and output
@@ -425,8 +451,8 @@ __global__ __launch_bounds__(256) void k_ssim(const gs_item* __restrict__ items,
     const int64_t wn = w + gridDim.x;
     SsUnit nxt = cur;
     if (wn < total) {
-      nxt = ss_locate(items, n_items, prefix, wn);
-      ss_fetch(nxt, K, color, trgb, px, py);
+      nxt = ss_locate(items, n_items, prefix, wn, nch, c0);
+      ss_fetch(nxt, K, color, trgb, tsem, px, py);
     }
     const int W = cur.W, H = cur.H;
     const int64_t HW = (int64_t)W * H;
@@ -526,9 +552,11 @@ __global__ __launch_bounds__(256) void k_ssim(const gs_item* __restrict__ items,
       }
       const int gx = tx0 + oj;
       const float inv = 1.0f / (float)HW;
-      const float l1 = w0 * (1.0f - lambda) * inv * (1.0f / 3.0f);
-      const float ls = -w0 * lambda * inv * (1.0f / 3.0f);
-      float* G = gcolor + cur.pixel_base * K + cur.ch * HW;
+      const bool semc = cur.ch >= 3;
+      const float wq = semc ? w2 : w0, lq = semc ? lambda_s : lambda;
+      const float l1 = wq * (1.0f - lq) * inv * (1.0f / 3.0f);
+      const float ls = -wq * lq * inv * (1.0f / 3.0f);
+      float* G = gcolor + cur.pixel_base * K + (semc ? cur.ch + 1 : cur.ch) * HW;
 #pragma unroll
       for (int i = 0; i < kSsV2; ++i) {
         const int gy = ty0 + or0 + i;
@@ -542,7 +570,7 @@ __global__ __launch_bounds__(256) void k_ssim(const gs_item* __restrict__ items,
     // the tile's S / (3HW), one atomic per wave
     const float part = wave_sum(ssum);
     if ((tid & 63) == 0 && part != 0.0f)
-      atomicAdd(&ssim_slots[(int64_t)cur.item * kSlots + (int)(cur.tile % kSlots)],
+      atomicAdd(&ssim_slots[(int64_t)(cur.ch >= 3 ? n_items + cur.item : cur.item) * kSlots + (int)(cur.tile % kSlots)],
                 part * (1.0f / (3.0f * (float)HW)));
     __syncthreads();                                // LDS is rewritten by the next unit
     cur = nxt;
@@ -641,30 +669,35 @@ int launch_head_loss(const gs_item* items, int n_items, int64_t P, int K, const 
                      float* count_slots, float* gcolor, float* partial, float* gW1, float* gb1, float* gW2, float* gb2,
                      hipStream_t s);
 
-// Workspace: count slots [n][kSlots], loss slots [n][3][kSlots], SSIM slots [n][kSlots],
-// n_valid [n], then the SSIM tile prefix [n + 1] (int64, 8-byte aligned), then the learned
-// head's per-block weight-gradient partials (256-byte aligned).
+// Workspace: count slots [n][kSlots], loss slots [n][3][kSlots], SSIM slots [2n][kSlots]
+// (colour, then semantic colour), n_valid [n], then the SSIM tile prefix [n + 1] (int64,
+// 8-byte aligned), then the learned head's per-block weight-gradient partials (256-byte
+// aligned).
 static size_t loss_prefix_offset(int n_items) {
-  return (sizeof(float) * (size_t)std::max(n_items, 1) * (5 * kSlots + 1) + 7) / 8 * 8;
+  return (sizeof(float) * (size_t)std::max(n_items, 1) * (6 * kSlots + 1) + 7) / 8 * 8;
 }
 static size_t loss_head_offset(int n_items) {
   return align_up(loss_prefix_offset(n_items) + sizeof(int64_t) * ((size_t)n_items + 1));
 }
 size_t loss_workspace(int n_items) { return loss_head_offset(n_items) + head_bwd_workspace(); }
 
+// lambda_s is used only with a semantic colour target (t.sem_color, eq. 12).
 int launch_loss(const gs_item* items, int n_items, int64_t P, int K, int n_classes, const float* color,
                 const float* logits, const gs_targets& t, const gs_head* head, const float* w, float lambda,
-                float* loss, float* gcolor, float* glogits, const gs_grads* head_grads, float* ws, hipStream_t s) {
+                float lambda_s, float* loss, float* gcolor, float* glogits, const gs_grads* head_grads, float* ws,
+                hipStream_t s) {
   const unsigned pb = (unsigned)std::max<int64_t>(1, ceil_div(P, 256));
   float* count_slots = ws;                                   // [n_items][kSlots]
   float* loss_slots = ws + (int64_t)n_items * kSlots;        // [n_items][3][kSlots]
-  float* ssim_slots = ws + (int64_t)n_items * 4 * kSlots;    // [n_items][kSlots]
-  float* nvalid = ws + (int64_t)n_items * 5 * kSlots;        // [n_items]
+  float* ssim_slots = ws + (int64_t)n_items * 4 * kSlots;    // [2 n_items][kSlots]
+  float* nvalid = ws + (int64_t)n_items * 6 * kSlots;        // [n_items]
   int64_t* prefix = (int64_t*)((char*)ws + loss_prefix_offset(n_items));
-  const bool ssim = lambda != 0.0f;
-  launch_fill_f32(ws, (int64_t)n_items * 5 * kSlots, 0.0f, s);
-#define GS_LOSS_ARGS items, n_items, P, K, n_classes, color, logits, t.rgb, t.depth, t.label, w[0], w[2], !ssim, \
-                     loss_slots, count_slots, gcolor, glogits
+  const float* tsem = t.sem_color;
+  if (!tsem) lambda_s = 0.0f;
+  const bool ssim = lambda != 0.0f, ssim_s = lambda_s != 0.0f;
+  launch_fill_f32(ws, (int64_t)n_items * 6 * kSlots, 0.0f, s);
+#define GS_LOSS_ARGS items, n_items, P, K, n_classes, color, logits, t.rgb, t.depth, t.label, tsem, w[0], w[2], \
+                     !ssim, !ssim_s, loss_slots, count_slots, gcolor, glogits
   if (head) {
     float* partial = (float*)((char*)ws + loss_head_offset(n_items));
     const int st = launch_head_loss(items, n_items, P, K, *head, color, t, w[0], w[2], !ssim, kSlots, loss_slots,
@@ -677,17 +710,19 @@ int launch_loss(const gs_item* items, int n_items, int64_t P, int K, int n_class
   else if (n_classes <= 64) hipLaunchKernelGGL(k_loss<64>, dim3(pb), dim3(256), 0, s, GS_LOSS_ARGS);
   else return GS_ERR_UNSUPPORTED;
 #undef GS_LOSS_ARGS
-  if (ssim) {
+  if (ssim || ssim_s) {
+    // one launch over the colour channels (0..2), the semantic colour ones (3..5) or both
+    const int c0 = ssim ? 0 : 3, nch = (ssim && ssim_s) ? 6 : 3;
     hipLaunchKernelGGL(k_ssim_prefix, dim3(1), dim3(256), 0, s, items, n_items, prefix);
     // a grid-stride loop covers every (tile, channel); the grid only needs to fill the chip
     const int resident = resident_blocks(k_ssim, 256, 512);
-    const int64_t est = 3 * (ceil_div(P, kSsT * kSsT) + n_items);
+    const int64_t est = nch * (ceil_div(P, kSsT * kSsT) + n_items);
     const unsigned grid = (unsigned)std::min<int64_t>(std::max<int64_t>(est, 1), resident);
-    hipLaunchKernelGGL(k_ssim, dim3(grid), dim3(256), 0, s, items, n_items, prefix, K, color, t.rgb, w[0], lambda,
-                       ssim_slots, gcolor);
+    hipLaunchKernelGGL(k_ssim, dim3(grid), dim3(256), 0, s, items, n_items, prefix, K, nch, c0, color, t.rgb, tsem,
+                       w[0], lambda, w[2], lambda_s, ssim_slots, gcolor);
   }
-  hipLaunchKernelGGL(k_fold_loss, dim3(1), dim3(256), 0, s, loss_slots, count_slots, ssim_slots, lambda, n_items, loss,
-                     nvalid);
+  hipLaunchKernelGGL(k_fold_loss, dim3(1), dim3(256), 0, s, loss_slots, count_slots, ssim_slots, lambda, lambda_s,
+                     n_items, loss, nvalid);
   hipLaunchKernelGGL(k_scale_depth, dim3(pb), dim3(256), 0, s, items, n_items, P, K, w[1], nvalid, gcolor);
   return launch_status();
 }

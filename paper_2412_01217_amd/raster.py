@@ -221,6 +221,9 @@ def loss(cfg, frame: Frame, n_classes: int, rendered: dict, targets: dict, w=(1.
     """Per-item loss parts [n_items, 3] and the image gradient. Learned mode with `head`: the
     decode runs inside the loss, grad["color"] channels 4.. receive dL/dE and grads'
     head_W1 .. head_b2 the head's weight gradients (grads: a dict with those four tensors).
+    targets["sem_color"] (a 3-channel semantic colour image in the rgb target's layout, with
+    cfg.n_sem = 3 and n_classes = 0) selects eq. 12's semantic loss, weighted by
+    cfg.sem_ssim_lambda, instead of the cross-entropy on targets["label"].
     static: gs_pyramid_loss_static, whose workspace is the library's own device array."""
     dev = frame.device
     if grad is None:
@@ -231,7 +234,8 @@ def loss(cfg, frame: Frame, n_classes: int, rendered: dict, targets: dict, w=(1.
     if ws is None and not static:
         ws = torch.empty(workspace_bytes(L.GS_WS_LOSS, cfg, frame, 0), dtype=torch.uint8, device=dev)
     t = L.Targets(targets["rgb"].data_ptr(), targets["depth"].data_ptr(),
-                  None if targets.get("label") is None else targets["label"].data_ptr())
+                  None if targets.get("label") is None else targets["label"].data_ptr(),
+                  None if targets.get("sem_color") is None else targets["sem_color"].data_ptr())
     wv = (ctypes.c_float * 3)(*[float(x) for x in w])
     ri = _images(rendered, frame.n_pixels)
     gi = _images(grad, frame.n_pixels)

@@ -353,6 +353,21 @@ def synthetic_projection(item_sizes, n, seed=5000, tie_depths=True, cull_frac=0.
     return hi, lo, radius, depth
 
 
+def semantic_colour_scene(sc: Scene, seed=SEED_SCENE + 50, noise=0.05) -> Scene:
+    """A copy of sc whose semantic feature is a colour (3 channels, Sec. III-B's semantic
+    colour): each Gaussian takes its class's colour, the class being the argmax of its
+    logits, from a seeded palette of uniform colours, plus N(0, noise^2), clipped to [0, 1]."""
+    rng = np.random.default_rng(seed)
+    palette = rng.uniform(0.0, 1.0, size=(max(sc.n_classes, 1), 3))
+    cls = np.argmax(sc.sem, axis=1) if sc.sem is not None and sc.n_classes > 0 else np.zeros(sc.n, np.int64)
+    col = np.clip(palette[cls] + rng.normal(0.0, noise, size=(sc.n, 3)), 0.0, 1.0)
+    out = sc.copy()
+    out.sem = col.astype(np.float32)
+    out.emb = None
+    out.n_classes = 3
+    return out
+
+
 def random_image(n_pixels, K, seed=5100, scale=1.0):
     """Planar K-channel image of n_pixels pixels, N(0, scale^2)."""
     rng = np.random.default_rng(seed)

@@ -14,18 +14,26 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def _step(variant=0, fwd_chunk=1, ssim_lambda=0.0, sh_degree=0):
+def _step(variant=0, fwd_chunk=1, ssim_lambda=0.0, sh_degree=0, sem_colour=False):
+    """sem_colour: 3-channel semantic colours under eq. 12's loss at lambda_s = 0.2."""
     from paper_2412_01217_amd import raster
     from paper_2412_01217_amd.step import MappingStep
     sc = scenes.room_scene(n=8000, n_classes=10, seed=1200, log_mu=-3.6)
     views = scenes.room_views(sc, 2, 160, 96, levels=2, seed=2200)
-    cfg = raster.config(10, variant=variant, fwd_chunk=fwd_chunk, ssim_lambda=ssim_lambda,
-                        view_features=int(sh_degree > 0))
+    if sem_colour:
+        sc = scenes.semantic_colour_scene(sc)
+    C = sc.n_classes
+    cfg = raster.config(C, variant=variant, fwd_chunk=fwd_chunk, ssim_lambda=ssim_lambda,
+                        view_features=int(sh_degree > 0), sem_ssim_lambda=0.2 if sem_colour else 0.0)
     fr = raster.Frame(cfg, views)
     g = raster.to_device(sc)
-    t_rgb, t_depth, t_lab = targets_from_random(views, 10, seed=4002)
+    t_rgb, t_depth, t_lab = targets_from_random(views, C, seed=4002)
     T = dict(rgb=torch.from_numpy(t_rgb).cuda(), depth=torch.from_numpy(t_depth).cuda(),
              label=torch.from_numpy(t_lab).cuda())
+    if sem_colour:
+        t_sem = np.random.default_rng(4003).uniform(size=t_rgb.shape).astype(np.float32)
+        T = dict(rgb=T["rgb"], depth=T["depth"], sem_color=torch.from_numpy(t_sem).cuda())
+        return MappingStep(cfg, fr, g, T, 0)
     sh = None
     if sh_degree:
         rng = np.random.default_rng(2300)
@@ -49,10 +57,11 @@ def _snapshot(st):
     return out
 
 
-@pytest.mark.parametrize("variant,fwd_chunk,ssim_lambda,sh_degree", [(1, 1, 0.0, 0), (2, 1, 0.0, 0), (3, 1, 0.0, 0),
-                                                                      (3, 0, 0.0, 0), (3, 1, 0.2, 0), (3, 1, 0.0, 3)])
-def test_graph_replays_match_eager(variant, fwd_chunk, ssim_lambda, sh_degree):
-    st = _step(variant, fwd_chunk, ssim_lambda, sh_degree)
+@pytest.mark.parametrize("variant,fwd_chunk,ssim_lambda,sh_degree,sem_colour",
+                         [(1, 1, 0.0, 0, False), (2, 1, 0.0, 0, False), (3, 1, 0.0, 0, False), (3, 0, 0.0, 0, False),
+                          (3, 1, 0.2, 0, False), (3, 1, 0.0, 3, False), (3, 1, 0.2, 0, True)])
+def test_graph_replays_match_eager(variant, fwd_chunk, ssim_lambda, sh_degree, sem_colour):
+    st = _step(variant, fwd_chunk, ssim_lambda, sh_degree, sem_colour)
     st.run()
     torch.cuda.synchronize()
     assert not st.overflowed()

@@ -27,7 +27,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(L.Config) == 64
+    assert ctypes.sizeof(L.Config) == 68
+    assert ctypes.sizeof(L.Targets) == 32
     assert ctypes.sizeof(L.Images) == 56
     assert ctypes.sizeof(L.View) == 56
     assert ctypes.sizeof(L.Item) == 56
@@ -42,6 +43,7 @@ def test_defaults_and_status_strings():
     assert c.alpha_min == pytest.approx(1 / 255) and c.alpha_max == pytest.approx(0.99)
     assert c.t_min == pytest.approx(1e-4) and c.z_near == pytest.approx(0.2)
     assert (c.variant, c.tile_order, c.fwd_chunk, c.ssim_lambda, c.isotropic, c.view_features) == (0, 0, 1, 0.0, 0, 0)
+    assert c.sem_ssim_lambda == 0.0
     assert lib.gs_status_string(L.GS_ERR_CAPACITY) == b"duplicate capacity exceeded"
     assert lib.gs_version() > 0
 
@@ -267,3 +269,30 @@ def test_static_loss_refuses_more_items_than_its_scratch_holds():
     assert call(2049) == L.GS_ERR_WORKSPACE
     assert call(-1) == L.GS_ERR_INVALID_ARG
     assert call(0) == L.GS_OK
+
+
+def test_semantic_colour_loss_arguments_are_checked_on_the_host():
+    """The semantic colour loss (eq. 12) needs plain mode with 3 composited semantic channels
+    and no class count; a weight outside [0, 1] is refused. Every refusal comes before any
+    launch (placeholder pointers; the static entry point refuses on the host before it looks
+    up its array)."""
+    lib = L.lib()
+    fake = ctypes.c_void_p(256)
+    w = (ctypes.c_float * 3)(1.0, 1.0, 1.0)
+
+    def call(n_sem=3, n_classes=0, lam_s=0.2, logits=None):
+        c = L.Config()
+        lib.gs_config_default(ctypes.byref(c))
+        c.n_sem = n_sem
+        c.sem_ssim_lambda = lam_s
+        img = L.Images(fake, None, None, logits, 100, None, 0)
+        t = L.Targets(fake, fake, None, fake)
+        return lib.gs_pyramid_loss_static(ctypes.byref(c), fake, 3000, 100, n_classes, ctypes.byref(img),
+                                          ctypes.byref(t), None, w, fake, ctypes.byref(img), None, None)
+
+    assert call(n_sem=4) == L.GS_ERR_INVALID_ARG
+    assert call(n_classes=3) == L.GS_ERR_INVALID_ARG
+    assert call(logits=fake) == L.GS_ERR_INVALID_ARG
+    assert call(lam_s=1.5) == L.GS_ERR_INVALID_ARG
+    assert call(lam_s=-0.1) == L.GS_ERR_INVALID_ARG
+    assert call() == L.GS_ERR_WORKSPACE          # valid arguments: refused only for its 3000 items
