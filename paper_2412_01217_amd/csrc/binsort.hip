@@ -25,10 +25,10 @@ constexpr int kRadixThreads = 256;
 constexpr int kRadixItems = 8;
 constexpr int kRadixTile = kRadixThreads * kRadixItems;  // 2048
 constexpr int kRadixWaveSpan = kRadixTile / 4;            // keys per wave
-// Digit widths: the (item, depth) keys of the visible entries take 31 + log2(items) bits,
-// three 11-bit passes for up to four items; the duplicates' tile ids take 8-bit passes.
-constexpr int kDigitVis = 11;
-constexpr int kDigitTile = 8;
+// Digits of 8 to 11 bits: a sort of b-bit keys takes ceil(b / 11) passes of equal width
+// (the (item, depth) keys of the visible entries have 31 + log2(items) bits, the
+// duplicates' tile ids log2(tiles)).
+constexpr int kDigitMax = 11;
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = threadIdx.x & 63;
@@ -241,21 +241,37 @@ __global__ __launch_bounds__(kOneThreads) void k_scan_one(const uint32_t* in, co
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort pass (B-bit digit) of (key, value) pairs. Each wave ranks its
-// keys with B ballots per key; per-wave digit counters live in LDS (4 << B words).
+// Stable LSD radix sort pass (B-bit digit) of (key, value) pairs. A block owns `sub`
+// consecutive sub-tiles of kRadixTile keys, so that the per-block digit histogram (and its
+// scan) is small against the keys: the histogram kernel counts the block's keys, the scan
+// turns the counts into each block's first output slot per digit, and the scatter walks the
+// sub-tiles in order, carrying a running slot per digit in LDS. Within a sub-tile each wave
+// ranks its keys with B ballots per key against per-wave digit counters.
 // ---------------------------------------------------------------------------
 template <class Key, int B>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const Key* __restrict__ keys, const uint64_t* count_dev,
-                                                              int shift, int nblk, uint32_t* __restrict__ hist) {
+                                                              int shift, int nblk, int sub, uint32_t* __restrict__ hist) {
   constexpr int ND = 1 << B;
   __shared__ uint32_t h[ND];
   for (int d = threadIdx.x; d < ND; d += kRadixThreads) h[d] = 0;
   __syncthreads();
   const int64_t count = (int64_t)*count_dev;
-  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
-  for (int k = 0; k < kRadixItems; ++k) {
-    const int64_t idx = base + (int64_t)k * kRadixThreads + threadIdx.x;
-    if (idx < count) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & (uint32_t)(ND - 1)], 1u);
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile * sub;
+  const int64_t end = min(count, base + (int64_t)kRadixTile * sub);
+  const uint64_t lt = lanemask_lt();
+  // every block writes its counts (zeros past the live keys): the scan reads them all
+  for (int64_t i0 = base + (threadIdx.x & ~63); i0 < end; i0 += kRadixThreads) {
+    const int64_t idx = i0 + (threadIdx.x & 63);
+    const bool ok = idx < end;
+    const uint32_t d = ok ? (uint32_t)(keys[idx] >> shift) & (uint32_t)(ND - 1) : 0u;
+    // one LDS atomic per distinct digit of the wave: keys of one pass share few digits
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const uint64_t m = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    if (ok && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
   }
   __syncthreads();
   for (int d = threadIdx.x; d < ND; d += kRadixThreads) hist[(int64_t)d * nblk + blockIdx.x] = h[d];
@@ -264,58 +280,70 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const Key* __restr
 template <class Key, int B>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const Key* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                                  Key* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                                 const uint64_t* count_dev, int shift, int nblk,
+                                                                 const uint64_t* count_dev, int shift, int nblk, int sub,
                                                                  const uint32_t* __restrict__ offs) {
   constexpr int ND = 1 << B;
   __shared__ uint32_t cnt[4][ND];
+  __shared__ uint32_t run[ND];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int d = lane; d < ND; d += 64) cnt[wid][d] = 0;
-  __syncthreads();
   const int64_t count = (int64_t)*count_dev;
-  const int64_t base = (int64_t)blockIdx.x * kRadixTile + (int64_t)wid * kRadixWaveSpan;
-  Key k[kRadixItems];
-  uint32_t v[kRadixItems], pos[kRadixItems], dig[kRadixItems];
-  bool ok[kRadixItems];
+  const int64_t block0 = (int64_t)blockIdx.x * kRadixTile * sub;
+  if (block0 >= count) return;
+  for (int d = threadIdx.x; d < ND; d += kRadixThreads) run[d] = offs[(int64_t)d * nblk + blockIdx.x];
   const uint64_t lt = lanemask_lt();
-  for (int r = 0; r < kRadixItems; ++r) {
-    const int64_t idx = base + (int64_t)r * 64 + lane;
-    ok[r] = idx < count;
-    k[r] = ok[r] ? kin[idx] : Key(0);
-    v[r] = ok[r] ? vin[idx] : 0u;
-    const uint32_t d = (uint32_t)(k[r] >> shift) & (uint32_t)(ND - 1);
-    dig[r] = d;
-    uint64_t peers = __ballot(ok[r]);
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const uint64_t m = __ballot((d >> b) & 1u);
-      peers &= ((d >> b) & 1u) ? m : ~m;
+  for (int st = 0; st < sub; ++st) {
+    const int64_t tile0 = block0 + (int64_t)st * kRadixTile;
+    if (tile0 >= count) break;                      // uniform over the block
+    for (int d = lane; d < ND; d += 64) cnt[wid][d] = 0;
+    __syncthreads();
+    const int64_t base = tile0 + (int64_t)wid * kRadixWaveSpan;
+    Key k[kRadixItems];
+    uint32_t v[kRadixItems], pos[kRadixItems], dig[kRadixItems];
+    bool ok[kRadixItems];
+    for (int r = 0; r < kRadixItems; ++r) {
+      const int64_t idx = base + (int64_t)r * 64 + lane;
+      ok[r] = idx < count;
+      k[r] = ok[r] ? kin[idx] : Key(0);
+      v[r] = ok[r] ? vin[idx] : 0u;
     }
-    const uint32_t rank = __popcll(peers & lt);
-    uint32_t old = 0;
-    if (ok[r]) old = cnt[wid][d];
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    if (ok[r] && rank == 0) cnt[wid][d] = old + (uint32_t)__popcll(peers);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    pos[r] = old + rank;
-  }
-  __syncthreads();
-  // per digit: exclusive prefix over the four waves
-  for (int d = threadIdx.x; d < ND; d += kRadixThreads) {
-    const uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d];
-    const uint32_t g = offs[(int64_t)d * nblk + blockIdx.x];
-    cnt[0][d] = g;
-    cnt[1][d] = g + c0;
-    cnt[2][d] = g + c0 + c1;
-    cnt[3][d] = g + c0 + c1 + c2;
-  }
-  __syncthreads();
-  for (int r = 0; r < kRadixItems; ++r) {
-    if (!ok[r]) continue;
-    const uint32_t dst = cnt[wid][dig[r]] + pos[r];
-    kout[dst] = k[r];
-    vout[dst] = v[r];
+    for (int r = 0; r < kRadixItems; ++r) {
+      const uint32_t d = (uint32_t)(k[r] >> shift) & (uint32_t)(ND - 1);
+      dig[r] = d;
+      uint64_t peers = __ballot(ok[r]);
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const uint64_t m = __ballot((d >> b) & 1u);
+        peers &= ((d >> b) & 1u) ? m : ~m;
+      }
+      const uint32_t rank = __popcll(peers & lt);
+      uint32_t old = 0;
+      if (ok[r]) old = cnt[wid][d];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      if (ok[r] && rank == 0) cnt[wid][d] = old + (uint32_t)__popcll(peers);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      pos[r] = old + rank;
+    }
+    __syncthreads();
+    // per digit: the sub-tile's first slot, then an exclusive prefix over the four waves
+    for (int d = threadIdx.x; d < ND; d += kRadixThreads) {
+      const uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d], c3 = cnt[3][d];
+      const uint32_t g = run[d];
+      cnt[0][d] = g;
+      cnt[1][d] = g + c0;
+      cnt[2][d] = g + c0 + c1;
+      cnt[3][d] = g + c0 + c1 + c2;
+      run[d] = g + c0 + c1 + c2 + c3;
+    }
+    __syncthreads();
+    for (int r = 0; r < kRadixItems; ++r) {
+      if (!ok[r]) continue;
+      const uint32_t dst = cnt[wid][dig[r]] + pos[r];
+      kout[dst] = k[r];
+      vout[dst] = v[r];
+    }
+    __syncthreads();                                  // cnt is cleared for the next sub-tile
   }
 }
 
@@ -465,7 +493,7 @@ SortWs plan_sort(int64_t E, int64_t cap, void* base) {
   SortWs w{};
   const int64_t nmax = std::max<int64_t>(E, cap);
   const int64_t nblk = ceil_div(std::max<int64_t>(nmax, 1), kRadixTile);
-  const int64_t hist_n = ((int64_t)1 << kDigitVis) * nblk;
+  const int64_t hist_n = ((int64_t)1 << kDigitMax) * nblk;   // the largest digit with one sub-tile per block
   const int64_t np = ceil_div(std::max<int64_t>(std::max(nmax, hist_n), 1), kScanTile) + 2;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -514,26 +542,54 @@ int device_scan(const uint32_t* in, uint32_t* out, const uint64_t* count_dev, in
   return launch_status();
 }
 
+// Sub-tiles per radix block for cap_count keys: about 8K blocks at most, so that the
+// per-block histograms stay a small fraction of the keys.
+int radix_sub(int64_t cap_count) {
+  return (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(cap_count, (int64_t)kRadixTile * 8192)));
+}
+
 template <class Key, int B>
+int radix_pass(Key* kin, Key* kout, uint32_t* vin, uint32_t* vout, const uint64_t* count_dev, int64_t cap_count,
+               int shift, SortWs& w, hipStream_t s) {
+  const int sub = radix_sub(cap_count);
+  const int nblk = (int)std::max<int64_t>(1, ceil_div(cap_count, (int64_t)kRadixTile * sub));
+  const int64_t nh = ((int64_t)1 << B) * nblk;
+  hipLaunchKernelGGL((k_radix_hist<Key, B>), dim3(nblk), dim3(kRadixThreads), 0, s, kin, count_dev, shift, nblk, sub,
+                     w.hist);
+  const int st = device_scan(w.hist, w.hist, nullptr, nh, nh, w.partial, nullptr, s);
+  if (st) return st;
+  hipLaunchKernelGGL((k_radix_scatter<Key, B>), dim3(nblk), dim3(kRadixThreads), 0, s, kin, vin, kout, vout, count_dev,
+                     shift, nblk, sub, w.hist);
+  return launch_status();
+}
+
+// Stable sort of `bits`-bit keys in ceil(bits / 11) passes of equal digits (8 to 11 bits).
+template <class Key>
 int radix_sort(Key* k0, Key* k1, uint32_t* v0, uint32_t* v1, const uint64_t* count_dev, int64_t cap_count, int bits,
                SortWs& w, hipStream_t s, int* final_buf) {
-  const int nblk = (int)std::max<int64_t>(1, ceil_div(cap_count, kRadixTile));
-  const int64_t nh = ((int64_t)1 << B) * nblk;
+  const int passes = std::max(1, (bits + kDigitMax - 1) / kDigitMax);
+  const int B = std::max(8, (bits + passes - 1) / passes);
   Key* kb[2] = {k0, k1};
   uint32_t* vb[2] = {v0, v1};
   int cur = 0;
-  for (int shift = 0; shift < bits; shift += B) {
-    hipLaunchKernelGGL((k_radix_hist<Key, B>), dim3(nblk), dim3(kRadixThreads), 0, s, kb[cur], count_dev, shift, nblk,
-                       w.hist);
-    int st = device_scan(w.hist, w.hist, nullptr, nh, nh, w.partial, nullptr, s);
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * B;
+    int st = GS_OK;
+    switch (B) {
+      case 8: st = radix_pass<Key, 8>(kb[cur], kb[cur ^ 1], vb[cur], vb[cur ^ 1], count_dev, cap_count, shift, w, s); break;
+      case 9: st = radix_pass<Key, 9>(kb[cur], kb[cur ^ 1], vb[cur], vb[cur ^ 1], count_dev, cap_count, shift, w, s); break;
+      case 10: st = radix_pass<Key, 10>(kb[cur], kb[cur ^ 1], vb[cur], vb[cur ^ 1], count_dev, cap_count, shift, w, s); break;
+      default: st = radix_pass<Key, 11>(kb[cur], kb[cur ^ 1], vb[cur], vb[cur ^ 1], count_dev, cap_count, shift, w, s); break;
+    }
     if (st) return st;
-    hipLaunchKernelGGL((k_radix_scatter<Key, B>), dim3(nblk), dim3(kRadixThreads), 0, s, kb[cur], vb[cur], kb[cur ^ 1],
-                       vb[cur ^ 1], count_dev, shift, nblk, w.hist);
     cur ^= 1;
   }
   *final_buf = cur;
-  return launch_status();
+  return GS_OK;
 }
+
+// Number of passes radix_sort takes for `bits`-bit keys.
+int radix_passes(int bits) { return std::max(1, (bits + kDigitMax - 1) / kDigitMax); }
 
 }  // namespace
 
@@ -562,8 +618,8 @@ int launch_bin_sort(const gs_config& cfg, const gs_projected& proj, const gs_ite
                      w.vvals[0]);
   // 2. stable sort of the visible entries by (item, depth)
   int fin = 0;
-  st = radix_sort<uint64_t, kDigitVis>(w.vkeys[0], w.vkeys[1], w.vvals[0], w.vvals[1], n_vis, E,
-                                       31 + bits_for((uint64_t)n_items), w, s, &fin);
+  st = radix_sort<uint64_t>(w.vkeys[0], w.vkeys[1], w.vvals[0], w.vvals[1], n_vis, E,
+                            31 + bits_for((uint64_t)n_items), w, s, &fin);
   if (st) return st;
   const uint32_t* svals = w.vvals[fin];
   // 3. duplicates in depth order
@@ -574,13 +630,13 @@ int launch_bin_sort(const gs_config& cfg, const gs_projected& proj, const gs_ite
   hipLaunchKernelGGL(k_dup_count, dim3(1), dim3(1), 0, s, d_total, cap, d_live, n_dup_dev, status_dev);
   // the tile sort must end in the caller's vals: start there after an even pass count
   const int tbits = std::max(1, bits_for((uint64_t)n_tiles));
-  const int passes = (tbits + kDigitTile - 1) / kDigitTile;
+  const int passes = radix_passes(tbits);
   uint32_t* v_first = (passes % 2 == 0) ? vals : w.tvals;
   uint32_t* v_other = (passes % 2 == 0) ? w.tvals : vals;
   hipLaunchKernelGGL(k_duplicate, dim3((unsigned)std::max<int64_t>(1, ceil_div(E, 256))), dim3(256), 0, s, cfg, svals,
                      n_vis, w.touched, proj.rec, proj.radius, items, n, cap, w.tkeys[0], v_first);
   // 4. stable sort of the duplicates by tile
-  st = radix_sort<uint32_t, kDigitTile>(w.tkeys[0], w.tkeys[1], v_first, v_other, d_live, cap, tbits, w, s, &fin);
+  st = radix_sort<uint32_t>(w.tkeys[0], w.tkeys[1], v_first, v_other, d_live, cap, tbits, w, s, &fin);
   if (st) return st;
   const uint32_t* tk = w.tkeys[fin];
   // 5. tile ranges
