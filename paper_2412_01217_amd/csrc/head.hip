@@ -256,17 +256,19 @@ __device__ __forceinline__ void head_setup(HeadLds& L, int C, const uint16_t* __
 }
 
 // Steps (1)-(5) for one 64-pixel chunk whose logit gradients are staged in sg [class][pixel].
-// Eb: plane 0 of the chunk's embedding (plane d at Eb + d HW); dEb the same in the gradient.
-template <bool ADD>
-__device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const float* sg, const float* Eb, float* dEb,
-                                                    int64_t HW, int nlive, const v4s (&w1a)[2][2],
+// Eb: pixel 0 of plane 0 of the chunk's embedding, plane d at Eb + d es (es = HW in global
+// memory; the row stride when staged in LDS, whose 64 entries per row are all readable);
+// dEb: the chunk's gradient planes (plane d at dEb + d HW).
+template <bool ADD, bool LDS_E>
+__device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const float* sg, const float* Eb, int64_t es,
+                                                    float* dEb, int64_t HW, int nlive, const v4s (&w1a)[2][2],
                                                     const float (&b1l)[2], HeadAcc& acc) {
   const int lane = threadIdx.x & 63, half = lane >> 5, l32 = lane & 31;
 #pragma unroll 1
   for (int pb = 0; pb < 2; ++pb) {
     const int q = l32 + 32 * pb;
     const bool qlive = q < nlive;
-    const float* Eq = Eb + 4 * half * HW + min(q, nlive - 1);   // plane 8 ks + 4 half + j at Eq + (8 ks + j) HW
+    const float* Eq = Eb + 4 * half * es + min(q, nlive - 1);   // plane 8 ks + 4 half + j at Eq + (8 ks + j) es
     const float* Gq = sg + 4 * half * kGst + q;                 // class 8 ks + 4 half + j at Gq + (8 ks + j) kGst
     // (1) E with d in registers, pixels across lanes; the sign of the hidden pre-activations
     v4s ehi[2], elo[2];
@@ -275,7 +277,7 @@ __device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const floa
       float e[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const float v = Eq[(8 * ks + j) * HW];
+        const float v = Eq[(8 * ks + j) * es];
         e[j] = qlive ? v : 0.0f;
       }
       split4(e, ehi[ks], elo[ks]);
@@ -414,14 +416,14 @@ __device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const floa
 #pragma unroll
       for (int r = 0; r < 16; ++r) dH[hb][r] = ((onH[hb] >> r) & 1u) ? dH[hb][r] : 0.0f;
     // (5b) dW1[h][d] += sum_p dH[p][h] [E, 1][p][d]: A = dH (i = hidden l32 + 32 hb, k = p), B = [E, 1] (j = d l32)
-    const float* Ed = Eb + (int64_t)min(l32, kDin - 1) * HW;
+    const float* Ed = Eb + (int64_t)min(l32, kDin - 1) * es;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int p0 = 32 * pb + 8 * kk + 4 * half;
       float e[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const float v = Ed[min(p0 + j, nlive - 1)];
+        const float v = Ed[LDS_E ? p0 + j : min(p0 + j, nlive - 1)];
         e[j] = p0 + j >= nlive ? 0.0f : (l32 < kDin ? v : (l32 == kDin ? 1.0f : 0.0f));
       }
       v4s bhi, blo;
@@ -512,8 +514,8 @@ __global__ __launch_bounds__(256, 1) void k_head_bwd(const gs_item* __restrict__
       }
     }
     wave_fence();
-    head_chunk_backward<true>(L, sg, color + it.pixel_base * K + 4 * HW + local0,
-                              gcolor + it.pixel_base * K + 4 * HW + local0, HW, nlive, w1a, b1l, acc);
+    head_chunk_backward<true, false>(L, sg, color + it.pixel_base * K + 4 * HW + local0, HW,
+                                     gcolor + it.pixel_base * K + 4 * HW + local0, HW, nlive, w1a, b1l, acc);
     // every lane is past this chunk's reads of the staged rows before the next chunk writes them
     wave_fence();
   }
@@ -528,6 +530,243 @@ __global__ __launch_bounds__(256, 1) void k_head_bwd(const gs_item* __restrict__
 // storing dL/dE in the colour-gradient planes 4..19 and accumulating the weight gradients.
 // No logits touch global memory. Loss partial sums go to the same per-item slots as the
 // plain loss's.
+//
+// At one wave per SIMD nothing hides a load's latency, so every input a chunk reads (the
+// 16 embedding planes, colour and depth, the targets) comes from LDS: while a wave works
+// on one chunk, direct global-to-LDS loads fill the other of its two staging buffers with
+// its next chunk. The buffers are two separate LDS arrays and the loop handles two chunks
+// per iteration, one from each, so that the compiler's wait for a buffer's loads never
+// waits for the other's.
+constexpr int kEst = 68;   // row stride (floats) of a staged embedding plane
+
+struct ChunkStage {        // one wave's staged chunk: 64 pixels of every input plane
+  float E[kDin][kEst];
+  float col[4][64];
+  float tr[3][64];
+  float td[64];
+  int32_t lab[64];
+};
+
+struct ChunkInfo {
+  int64_t chunk, pixel_base, HW, local0;
+  int item, nlive;
+};
+
+// The item table read through the constant address space: the chunk walk is wave-uniform,
+// and its reads become scalar loads, which do not wait behind the vector memory queue
+// (where the staging loads are in flight).
+typedef const __attribute__((address_space(4))) gs_item* ConstItems;
+
+__device__ __forceinline__ bool seek_chunk_c(ConstItems items, int n_items, int64_t chunk, ChunkCursor& cur) {
+  while (chunk >= cur.end && cur.item + 1 < n_items) {
+    ++cur.item;
+    cur.first = cur.end;
+    cur.end += ((int64_t)items[cur.item].W * items[cur.item].H + 63) / 64;
+  }
+  return chunk < cur.end;
+}
+
+// The chunk's place in the item table (false once past the last item).
+__device__ __forceinline__ bool chunk_info(ConstItems items, int n_items, int64_t chunk, ChunkCursor& cur,
+                                           ChunkInfo& ci) {
+  if (!seek_chunk_c(items, n_items, chunk, cur)) return false;
+  ci.chunk = chunk;
+  ci.item = cur.item;
+  ci.pixel_base = items[cur.item].pixel_base;
+  ci.HW = (int64_t)items[cur.item].W * items[cur.item].H;
+  ci.local0 = (chunk - cur.first) * 64;
+  ci.nlive = (int)min((int64_t)64, ci.HW - ci.local0);
+  return true;
+}
+
+constexpr int kStageLoads = kDin + 4 + 3 + 1 + 1;   // direct-to-LDS loads per staged chunk
+
+// Waits until at most kStageLoads vector memory operations are in flight: those are the
+// other buffer's loads, issued last, so everything before them -- this buffer's loads and
+// the previous chunk's stores -- is complete. Vector memory operations complete in issue
+// order. (s_waitcnt encoding: vmcnt 25 in bits 3:0 and 15:14, expcnt and lgkmcnt not
+// waited for.)
+__device__ __forceinline__ void wait_own_stage() {
+  static_assert(kStageLoads == 25, "the wait below encodes vmcnt(25)");
+  __builtin_amdgcn_s_waitcnt((1 << 14) | (0xF << 8) | (0x7 << 4) | 9);
+}
+
+// Issues the direct-to-LDS loads of chunk ci into S (lane l fills entry l of every row;
+// lanes past the item's last pixel load that pixel again).
+__device__ __forceinline__ void stage_chunk(ChunkStage& S, const ChunkInfo& ci, int K, const float* color,
+                                            const float* trgb, const float* tdepth, const int32_t* tlabel) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = ci.local0 + min(lane, ci.nlive - 1);
+  const float* cb = color + ci.pixel_base * K + p;
+  // the previous chunk's reads of S are complete before the loads overwrite it
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int d = 0; d < kDin; ++d)
+    __builtin_amdgcn_global_load_lds(cb + (int64_t)(4 + d) * ci.HW, &S.E[d][0], 4, 0, 0);
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) __builtin_amdgcn_global_load_lds(cb + (int64_t)ch * ci.HW, &S.col[ch][0], 4, 0, 0);
+  const float* tb = trgb + ci.pixel_base * 3 + p;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) __builtin_amdgcn_global_load_lds(tb + (int64_t)ch * ci.HW, &S.tr[ch][0], 4, 0, 0);
+  __builtin_amdgcn_global_load_lds(tdepth + ci.pixel_base + p, &S.td[0], 4, 0, 0);
+  __builtin_amdgcn_global_load_lds(tlabel + ci.pixel_base + p, &S.lab[0], 4, 0, 0);
+}
+
+// Everything k_head_loss does for one staged chunk.
+__device__ __forceinline__ void head_loss_chunk(const HeadLds& L, const uint16_t* w2r, const ChunkStage& S,
+                                                const ChunkInfo& ci, float* sg, int K, int C, float w0, float w2,
+                                                bool rgb_grad, int n_slots, const float (&b2r)[2][16],
+                                                const v4s (&w1a)[2][2], const float (&b1l)[2], HeadAcc& acc,
+                                                float* __restrict__ loss_slots, float* __restrict__ count_slots,
+                                                float* __restrict__ gcolor) {
+  const int lane = threadIdx.x & 63, l32 = lane & 31;
+  const int64_t HW = ci.HW;
+  const int nlive = ci.nlive;
+  const float invp = 1.0f / (float)HW;
+  wait_own_stage();
+  // L1 colour and depth, lane = pixel
+  const bool live = lane < nlive;
+  const int64_t cbase = ci.pixel_base * K + ci.local0 + min(lane, nlive - 1);
+  float col[4], tr[3];
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) col[ch] = S.col[ch][lane];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) tr[ch] = S.tr[ch][lane];
+  const float td = S.td[lane];
+  const int y_own = S.lab[lane];
+  float lr = 0.0f, ld = 0.0f, nv = 0.0f, ls = 0.0f;
+  {
+    const float inv3 = 1.0f / (3.0f * (float)HW);
+    float gc[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float d = col[ch] - tr[ch];
+      lr += fabsf(d) * inv3;
+      gc[ch] = w0 * (float)((d > 0.0f) - (d < 0.0f)) * inv3;
+    }
+    float gd = 0.0f;
+    if (td > 0.0f) {
+      const float d = col[3] - td;
+      ld = fabsf(d);
+      nv = 1.0f;
+      gd = (float)((d > 0.0f) - (d < 0.0f));
+    }
+    if (live) {
+      if (rgb_grad)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) __builtin_nontemporal_store(gc[ch], &gcolor[cbase + ch * HW]);
+      __builtin_nontemporal_store(gd, &gcolor[cbase + 3 * HW]);
+    } else {
+      lr = ld = nv = 0.0f;
+    }
+  }
+  // decode and cross-entropy per 32-pixel half: logits^T[cb][.] in D layout, lane l holding
+  // pixel 32 pb + l32, classes drow(r) + 32 cb; each pixel's classes span lanes l32 and l32 + 32
+#pragma unroll 1
+  for (int pb = 0; pb < 2; ++pb) {
+    const int q = l32 + 32 * pb;
+    const bool qlive = q < nlive;
+    const int y = __shfl(y_own, q, 64);
+    v16f H[2];
+    {
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb) H[hb] = zero16();
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        float e[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float v = S.E[8 * ks + 4 * (lane >> 5) + j][q];
+          e[j] = qlive ? v : 0.0f;
+        }
+        v4s hi, lo;
+        split4(e, hi, lo);
+#pragma unroll
+        for (int hb = 0; hb < 2; ++hb) {
+          H[hb] = mfma(w1a[hb][ks], hi, H[hb]);
+          H[hb] = mfma(w1a[hb][ks], lo, H[hb]);
+        }
+      }
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) H[hb][r] = fmaxf(H[hb][r] + L.b1[drow(r, lane) + 32 * hb], 0.0f);
+    }
+    v16f Lg[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      Lg[cb] = zero16();
+      const uint16_t* wrow = w2r + (l32 + 32 * cb) * kWtStride + 4 * (lane >> 5);
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        // A = W2 (i = class l32 + 32 cb, k = hidden 8 ks + 4 (l / 32) + j); rows >= C are zero
+        const v4s a = *reinterpret_cast<const v4s*>(wrow + 8 * ks);
+        float x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = H[ks >> 2][4 * (ks & 3) + j];
+        v4s hi, lo;
+        split4(x, hi, lo);
+        Lg[cb] = mfma(a, hi, Lg[cb]);
+        Lg[cb] = mfma(a, lo, Lg[cb]);
+      }
+    }
+    // softmax over the pixel's classes: this lane's 32, then the partner lane's
+    float m = -INFINITY;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int c = drow(r, lane) + 32 * cb;
+        const float v = c < C ? Lg[cb][r] + b2r[cb][r] : -INFINITY;
+        Lg[cb][r] = v;
+        m = fmaxf(m, v);
+      }
+    m = fmaxf(m, __shfl_xor(m, 32, 64));
+    float z = 0.0f, xy = 0.0f;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int c = drow(r, lane) + 32 * cb;
+        xy = c == y ? Lg[cb][r] : xy;
+        const float e = c < C ? __expf(Lg[cb][r] - m) : 0.0f;
+        Lg[cb][r] = e;
+        z += e;
+      }
+    z += __shfl_xor(z, 32, 64);
+    xy += __shfl_xor(xy, 32, 64);
+    const bool labelled = qlive && y >= 0 && y < C;   // outside [0, C): unlabelled, no semantic term
+    if (labelled && lane < 32) ls += (m + __logf(z) - xy) * invp;
+    const float sc = labelled ? w2 * invp / z : 0.0f;
+    const float oh = labelled ? w2 * invp : 0.0f;
+    // dlogits to LDS [class][pixel] (rows of absent classes stay zero)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int c = drow(r, lane) + 32 * cb;
+        if (c < C) sg[c * kGst + q] = Lg[cb][r] * sc - (c == y ? oh : 0.0f);
+      }
+  }
+  wave_fence();
+  head_chunk_backward<false, true>(L, sg, &S.E[0][0], kEst, gcolor + ci.pixel_base * K + 4 * HW + ci.local0, HW,
+                                   nlive, w1a, b1l, acc);
+  wave_fence();
+  // loss partial sums: one atomic per wave and quantity (a chunk lies in one item)
+  const float a = wave_sum(lr), bsum = wave_sum(ld), c = wave_sum(ls), v = wave_sum(nv);
+  if (lane == 0) {
+    const int slot = (int)(ci.chunk % n_slots);
+    float* loss = loss_slots + slot;
+    atomicAdd(&loss[(3 * ci.item + 0) * n_slots], a);
+    if (v != 0.0f) {
+      atomicAdd(&loss[(3 * ci.item + 1) * n_slots], bsum);
+      atomicAdd(&count_slots[ci.item * n_slots + slot], v);
+    }
+    atomicAdd(&loss[(3 * ci.item + 2) * n_slots], c);
+  }
+}
+
 __global__ __launch_bounds__(256, 1) void k_head_loss(const gs_item* __restrict__ items, int n_items, int K, int C,
                                                       const float* __restrict__ color, const float* __restrict__ trgb,
                                                       const float* __restrict__ tdepth,
@@ -538,11 +777,20 @@ __global__ __launch_bounds__(256, 1) void k_head_loss(const gs_item* __restrict_
                                                       float* __restrict__ loss_slots, float* __restrict__ count_slots,
                                                       float* __restrict__ gcolor, float* __restrict__ partial) {
   __shared__ HeadLds L;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l32 = lane & 31;
+  __shared__ uint16_t w2r[kHid * kWtStride];   // W2 [class][hidden], rows >= C zero
+  __shared__ ChunkStage SA[4];
+  __shared__ ChunkStage SB[4];
+  const int lane = threadIdx.x & 63;
+  // wave-uniform: the chunk walk and the item table reads stay in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int i = threadIdx.x; i < kHid * kHid; i += 256) {
+    const int c = i / kHid, h = i % kHid;
+    w2r[c * kWtStride + h] = c < C ? W2[c * kHid + h] : (uint16_t)0;
+  }
   HeadAcc acc;
   v4s w1a[2][2];
   float b1l[2];
-  head_setup(L, C, W1, b1, W2, acc, w1a, b1l);
+  head_setup(L, C, W1, b1, W2, acc, w1a, b1l);   // ends in a block barrier: w2r is complete
   float* sg = L.buf + wave * kHid * kGst;
   // b2 of this lane's classes drow(r) + 32 cb
   float b2r[2][16];
@@ -553,162 +801,39 @@ __global__ __launch_bounds__(256, 1) void k_head_loss(const gs_item* __restrict_
       const int c = drow(r, lane) + 32 * cb;
       b2r[cb][r] = c < C ? b2[c] : 0.0f;
     }
+  ConstItems citems = (ConstItems)items;
   ChunkCursor cur;
   cur.item = 0;
   cur.first = 0;
-  cur.end = item_chunks(items[0]);
-  for (int64_t chunk = (int64_t)blockIdx.x * 4 + wave;; chunk += (int64_t)gridDim.x * 4) {
-    if (!seek_chunk(items, n_items, chunk, cur)) break;
-    const gs_item it = items[cur.item];
-    const int64_t HW = (int64_t)it.W * it.H;
-    const int64_t local0 = (chunk - cur.first) * 64;
-    const int nlive = (int)min((int64_t)64, HW - local0);
-    const float invp = 1.0f / (float)HW;
-    // L1 colour and depth, lane = pixel
-    const bool live = lane < nlive;
-    const int64_t p = local0 + min(lane, nlive - 1);
-    const int64_t cbase = it.pixel_base * K + p, tbase = it.pixel_base * 3 + p;
-    float col[4], tr[3];
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) col[ch] = __builtin_nontemporal_load(&color[cbase + ch * HW]);
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) tr[ch] = __builtin_nontemporal_load(&trgb[tbase + ch * HW]);
-    const float td = __builtin_nontemporal_load(&tdepth[it.pixel_base + p]);
-    const int y_own = __builtin_nontemporal_load(&tlabel[it.pixel_base + p]);
-    float lr = 0.0f, ld = 0.0f, nv = 0.0f, ls = 0.0f;
-    {
-      const float inv3 = 1.0f / (3.0f * (float)HW);
-      float gc[3];
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        const float d = col[ch] - tr[ch];
-        lr += fabsf(d) * inv3;
-        gc[ch] = w0 * (float)((d > 0.0f) - (d < 0.0f)) * inv3;
-      }
-      float gd = 0.0f;
-      if (td > 0.0f) {
-        const float d = col[3] - td;
-        ld = fabsf(d);
-        nv = 1.0f;
-        gd = (float)((d > 0.0f) - (d < 0.0f));
-      }
-      if (live) {
-        if (rgb_grad)
-#pragma unroll
-          for (int ch = 0; ch < 3; ++ch) __builtin_nontemporal_store(gc[ch], &gcolor[cbase + ch * HW]);
-        __builtin_nontemporal_store(gd, &gcolor[cbase + 3 * HW]);
-      } else {
-        lr = ld = nv = 0.0f;
-      }
-    }
-    const float* Eb = color + it.pixel_base * K + 4 * HW + local0;
-    // decode and cross-entropy per 32-pixel half: logits^T[cb][.] in D layout, lane l holding
-    // pixel 32 pb + l32, classes drow(r) + 32 cb; each pixel's classes span lanes l32 and l32 + 32
-#pragma unroll 1
-    for (int pb = 0; pb < 2; ++pb) {
-      const int q = l32 + 32 * pb;
-      const bool qlive = q < nlive;
-      const int y = __shfl(y_own, q, 64);
-      v16f H[2];
-      {
-        const float* Eq = Eb + min(q, nlive - 1);
-#pragma unroll
-        for (int hb = 0; hb < 2; ++hb) H[hb] = zero16();
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-          float e[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const float v = Eq[(int64_t)(8 * ks + 4 * (lane >> 5) + j) * HW];
-            e[j] = qlive ? v : 0.0f;
-          }
-          v4s hi, lo;
-          split4(e, hi, lo);
-#pragma unroll
-          for (int hb = 0; hb < 2; ++hb) {
-            H[hb] = mfma(w1a[hb][ks], hi, H[hb]);
-            H[hb] = mfma(w1a[hb][ks], lo, H[hb]);
-          }
-        }
-#pragma unroll
-        for (int hb = 0; hb < 2; ++hb)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) H[hb][r] = fmaxf(H[hb][r] + L.b1[drow(r, lane) + 32 * hb], 0.0f);
-      }
-      v16f Lg[2];
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        Lg[cb] = zero16();
-        const int cls = l32 + 32 * cb;
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-          // A = W2 (i = class l32 + 32 cb, k = hidden 8 ks + 4 (l / 32) + j)
-          v4s a;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) a[j] = cls < C ? (short)W2[(int64_t)cls * kHid + 8 * ks + 4 * (lane >> 5) + j] : (short)0;
-          float x[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) x[j] = H[ks >> 2][4 * (ks & 3) + j];
-          v4s hi, lo;
-          split4(x, hi, lo);
-          Lg[cb] = mfma(a, hi, Lg[cb]);
-          Lg[cb] = mfma(a, lo, Lg[cb]);
-        }
-      }
-      // softmax over the pixel's classes: this lane's 32, then the partner lane's
-      float m = -INFINITY;
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int c = drow(r, lane) + 32 * cb;
-          const float v = c < C ? Lg[cb][r] + b2r[cb][r] : -INFINITY;
-          Lg[cb][r] = v;
-          m = fmaxf(m, v);
-        }
-      m = fmaxf(m, __shfl_xor(m, 32, 64));
-      float z = 0.0f, xy = 0.0f;
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int c = drow(r, lane) + 32 * cb;
-          xy = c == y ? Lg[cb][r] : xy;
-          const float e = c < C ? __expf(Lg[cb][r] - m) : 0.0f;
-          Lg[cb][r] = e;
-          z += e;
-        }
-      z += __shfl_xor(z, 32, 64);
-      xy += __shfl_xor(xy, 32, 64);
-      const bool labelled = qlive && y >= 0 && y < C;   // outside [0, C): unlabelled, no semantic term
-      if (labelled && lane < 32) ls += (m + __logf(z) - xy) * invp;
-      const float sc = labelled ? w2 * invp / z : 0.0f;
-      const float oh = labelled ? w2 * invp : 0.0f;
-      // dlogits to LDS [class][pixel] (rows of absent classes stay zero)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int c = drow(r, lane) + 32 * cb;
-          if (c < C) sg[c * kGst + q] = Lg[cb][r] * sc - (c == y ? oh : 0.0f);
-        }
-    }
-    wave_fence();
-    head_chunk_backward<false>(L, sg, Eb, gcolor + it.pixel_base * K + 4 * HW + local0, HW, nlive, w1a, b1l, acc);
-    wave_fence();
-    // loss partial sums: one atomic per wave and quantity (a chunk lies in one item)
-    const float a = wave_sum(lr), bsum = wave_sum(ld), c = wave_sum(ls), v = wave_sum(nv);
-    if (lane == 0) {
-      const int slot = (int)(chunk % n_slots);
-      float* loss = loss_slots + slot;
-      atomicAdd(&loss[(3 * cur.item + 0) * n_slots], a);
-      if (v != 0.0f) {
-        atomicAdd(&loss[(3 * cur.item + 1) * n_slots], bsum);
-        atomicAdd(&count_slots[cur.item * n_slots + slot], v);
-      }
-      atomicAdd(&loss[(3 * cur.item + 2) * n_slots], c);
-    }
+  cur.end = ((int64_t)citems[0].W * citems[0].H + 63) / 64;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  // Every iteration issues the same loads whether or not a next chunk exists (past the end
+  // the current chunk is loaded again and not used), so the number of loads in flight is
+  // the same on every path and each buffer's wait covers exactly its own loads.
+  ChunkInfo ca, cb;
+  bool have = chunk_info(citems, n_items, (int64_t)blockIdx.x * 4 + wave, cur, ca);
+  if (!have) {
+    head_write_partial(L, acc, partial);
+    return;
   }
+  stage_chunk(SA[wave], ca, K, color, trgb, tdepth, tlabel);
+  for (;;) {
+    const bool hb = chunk_info(citems, n_items, ca.chunk + stride, cur, cb);
+    if (!hb) cb = ca;
+    stage_chunk(SB[wave], cb, K, color, trgb, tdepth, tlabel);
+    head_loss_chunk(L, w2r, SA[wave], ca, sg, K, C, w0, w2, rgb_grad, n_slots, b2r, w1a, b1l, acc, loss_slots,
+                    count_slots, gcolor);
+    if (!hb) break;
+    const bool ha = chunk_info(citems, n_items, cb.chunk + stride, cur, ca);
+    if (!ha) ca = cb;
+    stage_chunk(SA[wave], ca, K, color, trgb, tdepth, tlabel);
+    head_loss_chunk(L, w2r, SB[wave], cb, sg, K, C, w0, w2, rgb_grad, n_slots, b2r, w1a, b1l, acc, loss_slots,
+                    count_slots, gcolor);
+    if (!ha) break;
+  }
+  // the last iteration's loads into the unused buffer are complete before the block's LDS
+  // is reused below
+  __builtin_amdgcn_s_waitcnt(0);
   head_write_partial(L, acc, partial);
 }
 
