@@ -49,7 +49,7 @@ typedef enum gs_status {
 
 /* Rasterizer configuration. gs_config_default() fills the values listed. */
 typedef struct gs_config {
-  int32_t tile_w, tile_h;  /* 16, 16: screen tile (the only shape built) */
+  int32_t tile_w, tile_h;  /* 16, 16: screen tile of 256 pixels: 8x32, 16x16, 32x8 or 64x4 */
   float z_near;            /* 0.2: cull Gaussians whose camera depth <= z_near */
   float eps_dilate;        /* 0.3: added to the 2D covariance diagonal (px^2) */
   float alpha_min;         /* 1/255: a Gaussian is skipped where alpha < alpha_min */

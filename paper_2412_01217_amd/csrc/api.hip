@@ -94,7 +94,9 @@ namespace {
 
 bool cfg_ok(const gs_config* c) {
   if (!c) return false;
-  if (c->tile_w != kTile || c->tile_h != kTile) return false;
+  // 256-pixel tiles: 8x32, 16x16, 32x8 or 64x4
+  if (!((c->tile_w == 8 || c->tile_w == 16 || c->tile_w == 32 || c->tile_w == 64) && c->tile_w * c->tile_h == kTilePx))
+    return false;
   if (!(c->z_near > 0.0f) || !(c->eps_dilate >= 0.0f) || !(c->alpha_min >= 0.0f)) return false;
   if (!(c->alpha_max > c->alpha_min) || !(c->alpha_max < 1.0f) || !(c->t_min >= 0.0f) || !(c->guard > 0.0f)) return false;
   if (c->n_sem < 0 || c->n_sem > 60) return false;

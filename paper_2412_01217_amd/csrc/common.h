@@ -8,8 +8,14 @@
 
 namespace gs {
 
-constexpr int kTile = 16;          // screen tile edge (pixels)
-constexpr int kTilePx = kTile * kTile;
+constexpr int kTile = 16;          // default screen tile edge (pixels)
+constexpr int kTilePx = 256;       // pixels per tile: every shape is tile_w x (256 / tile_w)
+
+// Tile width as a shift: tiles are 8x32, 16x16, 32x8 or 64x4 pixels (one pixel per
+// thread of a 256-thread block; tile-local pixel t sits at (t % tile_w, t / tile_w)).
+__host__ __device__ inline int tile_shift(const gs_config& cfg) {
+  return cfg.tile_w == 8 ? 3 : cfg.tile_w == 32 ? 5 : cfg.tile_w == 64 ? 6 : 4;
+}
 constexpr int kRecFloats = 8;      // per (item, Gaussian) render record
 
 // Records the last HIP error for gs_last_hip_error(); returns GS_ERR_HIP if e != success.
@@ -121,9 +127,9 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// One 16x16 tile of one item, as a render block sees it.
+// One tile of one item, as a render block sees it (tile width 1 << tws, height 256 >> tws).
 struct Ctx {
-  int item, view, tx, ty, tiles_x, tiles_y;
+  int item, view, tx, ty, tiles_x, tiles_y, tws;
   int W, H;
   int64_t HW, pixel_base;
   uint32_t start, end;
@@ -131,8 +137,10 @@ struct Ctx {
 
 // Tiles are launched coarse pyramid levels first: their lists are the longest, and
 // starting them early lets the many short fine-level tiles fill in around them.
-__device__ __forceinline__ Ctx make_ctx_of(const gs_item* items, int n_items, const uint32_t* ranges, int tile) {
+__device__ __forceinline__ Ctx make_ctx_of(const gs_item* items, int n_items, const uint32_t* ranges, int tile,
+                                           int tws) {
   Ctx c;
+  c.tws = tws;
   c.item = item_of_tile(items, n_items, tile);
   const gs_item it = items[c.item];
   c.view = it.view;
@@ -150,8 +158,8 @@ __device__ __forceinline__ Ctx make_ctx_of(const gs_item* items, int n_items, co
   return c;
 }
 
-__device__ __forceinline__ Ctx make_ctx(const gs_item* items, int n_items, const uint32_t* ranges, int order) {
-  return make_ctx_of(items, n_items, ranges, order ? (int)blockIdx.x : (int)gridDim.x - 1 - (int)blockIdx.x);
+__device__ __forceinline__ Ctx make_ctx(const gs_item* items, int n_items, const uint32_t* ranges, int order, int tws) {
+  return make_ctx_of(items, n_items, ranges, order ? (int)blockIdx.x : (int)gridDim.x - 1 - (int)blockIdx.x, tws);
 }
 
 // First feature entry of a tile's Gaussians: with per-view features (cfg.view_features) the
@@ -160,11 +168,14 @@ __device__ __forceinline__ int64_t feature_offset(const gs_config& cfg, int view
   return cfg.view_features ? (int64_t)view * n : 0;
 }
 
-// Tile-local pixel index t (0..255, row-major in the 16x16 tile) -> image coordinates.
+// Tile-local pixel index t (0..255, row-major in the tile) -> image coordinates.
 __device__ __forceinline__ void tile_pixel(const Ctx& c, int t, int& u, int& v) {
-  u = c.tx * kTile + (t & 15);
-  v = c.ty * kTile + (t >> 4);
+  u = (c.tx << c.tws) + (t & ((1 << c.tws) - 1));
+  v = c.ty * (kTilePx >> c.tws) + (t >> c.tws);
 }
+// The image coordinates of the tile's middle pixel (tile_w / 2, tile_h / 2).
+__device__ __forceinline__ int tile_mid_x(const Ctx& c) { return (c.tx << c.tws) + (1 << (c.tws - 1)); }
+__device__ __forceinline__ int tile_mid_y(const Ctx& c) { return c.ty * (kTilePx >> c.tws) + (128 >> c.tws); }
 
 __device__ __forceinline__ float fast_exp(float x) { return __expf(x); }
 

@@ -29,7 +29,7 @@ struct TileCtx {
   uint32_t start, end;
 };
 
-__device__ __forceinline__ TileCtx tile_ctx(const gs_item* items, int n_items, const uint32_t* ranges, int K) {
+__device__ __forceinline__ TileCtx tile_ctx(const gs_item* items, int n_items, const uint32_t* ranges, int K, int tws) {
   TileCtx c;
   const int tile = blockIdx.x;
   c.item = item_of_tile(items, n_items, tile);
@@ -38,8 +38,8 @@ __device__ __forceinline__ TileCtx tile_ctx(const gs_item* items, int n_items, c
   const int lt = tile - it.tile_base;
   c.tx = lt % it.tiles_x;
   c.ty = lt / it.tiles_x;
-  c.u = c.tx * kTile + (threadIdx.x & 15);
-  c.v = c.ty * kTile + (threadIdx.x >> 4);
+  c.u = (c.tx << tws) + (threadIdx.x & ((1 << tws) - 1));
+  c.v = c.ty * (kTilePx >> tws) + (threadIdx.x >> tws);
   c.inside = c.u < it.W && c.v < it.H;
   c.px = c.u + 0.5f;
   c.py = c.v + 0.5f;
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(gs_config cfg, const float* 
   __shared__ float4 smem[BATCH * STRIDE / 4];
   float* sm = reinterpret_cast<float*>(smem);
   const int Kr = 4 + n_sem;
-  const TileCtx c = tile_ctx(items, n_items, ranges, Kr);
+  const TileCtx c = tile_ctx(items, n_items, ranges, Kr, tile_shift(cfg));
   const int64_t foff = feature_offset(cfg, c.view, n);
   float acc[K];
 #pragma unroll
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(gs_config cfg, const float* 
   __shared__ uint32_t s_lmax;
   float* sm = reinterpret_cast<float*>(smem);
   const int Kr = 4 + n_sem;
-  const TileCtx c = tile_ctx(items, n_items, ranges, Kr);
+  const TileCtx c = tile_ctx(items, n_items, ranges, Kr, tile_shift(cfg));
   const int64_t foff = feature_offset(cfg, c.view, n);
   const int lane = threadIdx.x & 63;
   float gp[K];

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_render_fwd_mfma(gs_config cfg, const fl
   __shared__ float4 s_rec[2 * kBatch];
   __shared__ float s_feat[kBatch * FST];
   __shared__ float s_w[4][64 * kWst];
-  const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order);
+  const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order, tile_shift(cfg));
   const int64_t foff = feature_offset(cfg, c.view, n);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   int u, v;
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_mfma(gs_config cfg, const fl
   __shared__ float s_df[kBatch * KP];
   __shared__ float s_geo[kBatch * 6 * 16];
   __shared__ uint32_t s_lmax;
-  const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order);
+  const Ctx c = make_ctx(items, n_items, ranges, cfg.tile_order, tile_shift(cfg));
   const int64_t foff = feature_offset(cfg, c.view, n);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int Kr = 4 + n_sem;

@@ -93,8 +93,10 @@ __device__ __forceinline__ void split8(const float* x, v8bf& hi, v8bf& lo) {
 }
 
 // The render record as the compositing loops read it from LDS, 8 floats per Gaussian:
-//   mx, my   mean2d relative to the centre of the tile's first pixel, so that a pixel's
-//            offset is its integer position in the tile minus (mx, my);
+//   mx, my   mean2d relative to the tile's middle (the centre of its pixel (tw / 2, th / 2)),
+//            so that a pixel's offset is its integer position relative to that pixel minus
+//            (mx, my); a middle origin keeps |mx|, |my| (and their rounding) small for every
+//            tile shape;
 //   a, b, c  the conic scaled so that a dx^2 + b dx dy + c dy^2 is the exponent of eq. 4
 //            in base 2: a = -A log2(e) / 2, b = -B log2(e), c = -C log2(e) / 2;
 //   o        opacity (two floats of padding).
@@ -248,7 +250,8 @@ __global__ __launch_bounds__(256) void k_fwd_trans(gs_config cfg, const float* _
   __shared__ __align__(16) float s_rec[8 * kB];
   __shared__ uint32_t s_wi;
   const int tid = threadIdx.x;
-  const float lx = (float)(tid & 15), ly = (float)(tid >> 4);
+  const int tws = tile_shift(cfg);
+  const float lx = (float)((tid & ((1 << tws) - 1)) - (1 << (tws - 1))), ly = (float)((tid >> tws) - (128 >> tws));
   const float amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
   const uint32_t n_work = ctl[0];
   for (;;) {
@@ -261,11 +264,11 @@ __global__ __launch_bounds__(256) void k_fwd_trans(gs_config cfg, const float* _
     const int seg = (int)(wk.y & 0xffffu), nseg = (int)(wk.y >> 16);
     const int chunk = fwd_chunk(cfg);
     if (seg % chunk != 0 || seg + chunk >= nseg) continue;
-    const Ctx c = make_ctx_of(items, n_items, ranges, (int)wk.x);
+    const Ctx c = make_ctx_of(items, n_items, ranges, (int)wk.x, tws);
     int u, v;
     tile_pixel(c, tid, u, v);
     const bool inside = u < c.W && v < c.H;
-    const float ox = (float)(c.tx * kTile) + 0.5f, oy = (float)(c.ty * kTile) + 0.5f;
+    const float ox = (float)tile_mid_x(c) + 0.5f, oy = (float)tile_mid_y(c) + 0.5f;
     const uint32_t a0 = c.start + seg * kSeg;
     const uint32_t b0 = (uint32_t)min((int64_t)c.end, (int64_t)a0 + (int64_t)chunk * kSeg);
     // thread t < 64 stages half (t % 2) of the record of Gaussian t / 2
@@ -337,7 +340,8 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, g4 = lane >> 4;
   const int Kr = 4 + n_sem;
-  const float lx = (float)(tid & 15), ly = (float)(tid >> 4);
+  const int tws = tile_shift(cfg);
+  const float lx = (float)((tid & ((1 << tws) - 1)) - (1 << (tws - 1))), ly = (float)((tid >> tws) - (128 >> tws));
   const float amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
   const uint32_t n_work = SEG ? ctl[0] : 1u;
   float* W = s_w[wave];
@@ -359,12 +363,12 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
       if (round > 0) break;
       tile = cfg.tile_order ? (int)blockIdx.x : (int)gridDim.x - 1 - (int)blockIdx.x;
     }
-    const Ctx c = make_ctx_of(items, n_items, ranges, tile);
+    const Ctx c = make_ctx_of(items, n_items, ranges, tile, tws);
     const int64_t foff = feature_offset(cfg, c.view, n);
     int u, v;
     tile_pixel(c, tid, u, v);
     const bool inside = u < c.W && v < c.H;
-    const float ox = (float)(c.tx * kTile) + 0.5f, oy = (float)(c.ty * kTile) + 0.5f;
+    const float ox = (float)tile_mid_x(c) + 0.5f, oy = (float)tile_mid_y(c) + 0.5f;
     const bool split = SEG && nseg > 1;
     const int chunk = fwd_chunk(cfg);
     const int s_hi = split ? min(nseg, seg + chunk) : 1;   // segments [seg, s_hi) of this item
@@ -525,14 +529,14 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
 // front with all channels of a segment loaded at once.
 template <int NS>
 __global__ __launch_bounds__(256) void k_fwd_combine(const gs_item* __restrict__ items, int n_items,
-                                                     const uint32_t* __restrict__ ranges, int Kr, int chunk,
+                                                     const uint32_t* __restrict__ ranges, int Kr, int chunk, int tws,
                                                      FState fs, float* __restrict__ color, float* __restrict__ Tout,
                                                      uint32_t* __restrict__ ncout) {
   constexpr int KP = SShape<NS>::KP;
   const int tile = blockIdx.x, tid = threadIdx.x;
   const int nseg = (int)fs.tcnt[tile];
   if (nseg <= chunk) return;
-  const Ctx c = make_ctx_of(items, n_items, ranges, tile);
+  const Ctx c = make_ctx_of(items, n_items, ranges, tile, tws);
   int u, v;
   tile_pixel(c, tid, u, v);
   if (u >= c.W || v >= c.H) return;
@@ -653,7 +657,7 @@ __constant__ float kGeoScale[6] = {-1.0f / kLog2e, -1.0f / kLog2e, -0.5f, -1.0f,
 // With a forward state, a tile that the forward did not split stays one item.
 __global__ __launch_bounds__(256) void k_seg_count(const gs_item* __restrict__ items, int n_items,
                                                    const uint32_t* __restrict__ ranges,
-                                                   const uint32_t* __restrict__ ncin, int n_tiles, int order,
+                                                   const uint32_t* __restrict__ ncin, int n_tiles, int order, int tws,
                                                    const uint32_t* __restrict__ ftcnt,
                                                    uint32_t* __restrict__ tile_lmax, uint32_t* __restrict__ cnt_ord) {
   __shared__ uint32_t s_m;
@@ -661,7 +665,8 @@ __global__ __launch_bounds__(256) void k_seg_count(const gs_item* __restrict__ i
   const int item = item_of_tile(items, n_items, tile);
   const gs_item it = items[item];
   const int lt = tile - it.tile_base;
-  const int u = (lt % it.tiles_x) * kTile + (threadIdx.x & 15), v = (lt / it.tiles_x) * kTile + (threadIdx.x >> 4);
+  const int u = ((lt % it.tiles_x) << tws) + (threadIdx.x & ((1 << tws) - 1));
+  const int v = (lt / it.tiles_x) * (kTilePx >> tws) + (threadIdx.x >> tws);
   const uint32_t len = ranges[2 * (int64_t)tile + 1] - ranges[2 * (int64_t)tile];
   const uint32_t last = (u < it.W && v < it.H) ? min(ncin[it.pixel_base + (int64_t)v * it.W + u], len) : 0u;
   if (threadIdx.x == 0) s_m = 0;
@@ -760,13 +765,13 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
     const int tile = (int)wk.x;
     const int seg = (int)(wk.y & 0xffffu), nseg = (int)(wk.y >> 16);
     if (SUMMARY && nseg < 2) continue;
-    const Ctx c = make_ctx_of(items, n_items, ranges, tile);
+    const Ctx c = make_ctx_of(items, n_items, ranges, tile, tile_shift(cfg));
     const int64_t foff = feature_offset(cfg, c.view, n);
     int u, v;
     tile_pixel(c, tid, u, v);
     const bool inside = u < c.W && v < c.H;
-    const float lx = (float)(tid & 15), ly = (float)(tid >> 4);
-    const float ox = (float)(c.tx * kTile) + 0.5f, oy = (float)(c.ty * kTile) + 0.5f;
+    const float lx = (float)((tid & ((1 << c.tws) - 1)) - (1 << (c.tws - 1))), ly = (float)((tid >> c.tws) - (128 >> c.tws));
+    const float ox = (float)tile_mid_x(c) + 0.5f, oy = (float)tile_mid_y(c) + 0.5f;
     const int64_t pix = c.pixel_base + (int64_t)v * c.W + u;
     // n_contrib comes from the matching forward; clamp so that a mismatched call stays in range
     const uint32_t len = c.end - c.start;
@@ -1252,7 +1257,7 @@ int launch_fwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected
                      w.fs);
   if (cfg.fwd_chunk > 0)
     hipLaunchKernelGGL(k_fwd_combine<NS>, dim3(n_tiles), dim3(256), 0, s, items, n_items, ranges, 4 + cfg.n_sem,
-                       cfg.fwd_chunk, w.fs, out.color, out.T, out.n_contrib);
+                       cfg.fwd_chunk, tile_shift(cfg), w.fs, out.color, out.T, out.n_contrib);
   return launch_status();
 }
 
@@ -1265,7 +1270,7 @@ int launch_bwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected
   // with the forward's saved state the segments start from it: no summary pass
   const FState fs = state_of(fwd, n_tiles, 4 + cfg.n_sem).fs;
   hipLaunchKernelGGL(k_seg_count, dim3(n_tiles), dim3(256), 0, s, items, n_items, ranges, fwd.n_contrib, n_tiles,
-                     cfg.tile_order, fs.tcnt, w.lmax, w.cnt);
+                     cfg.tile_order, tile_shift(cfg), fs.tcnt, w.lmax, w.cnt);
   int st = launch_status();
   st = st ? st : scan_u32(w.cnt, w.base, n_tiles, w.partial, w.total, s);
   if (st) return st;

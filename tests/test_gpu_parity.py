@@ -43,12 +43,14 @@ CASES = {
 }
 
 
-def _pipeline(sc, views, n_sem, variant=0, split=True, state_capacity=None, fwd_chunk=1, isotropic=False):
+def _pipeline(sc, views, n_sem, variant=0, split=True, state_capacity=None, fwd_chunk=1, isotropic=False,
+              tile=(16, 16)):
     """split: forward with its state (long lists in segments of fwd_chunk 256-entry pieces,
     0 = whole lists); state_capacity overrides the capacity the state is sized for;
-    isotropic: the primitive of eq. 1-3."""
+    isotropic: the primitive of eq. 1-3; tile: the screen tile (width, height)."""
     raster = _raster()
-    cfg = raster.config(n_sem, variant=variant, fwd_chunk=fwd_chunk, isotropic=int(isotropic))
+    cfg = raster.config(n_sem, variant=variant, fwd_chunk=fwd_chunk, isotropic=int(isotropic), tile_w=tile[0],
+                        tile_h=tile[1])
     fr = raster.Frame(cfg, views)
     g = raster.to_device(sc)
     proj = raster.preprocess(cfg, g, fr)
@@ -100,9 +102,9 @@ def test_preprocess_parity(case, isotropic):
     np.testing.assert_array_equal(depth[vis], ref["depth"][vis].astype(np.float32))
 
 
-def _check_sort(views, n, hi, lo, radius, depth):
+def _check_sort(views, n, hi, lo, radius, depth, tile=(16, 16)):
     raster = _raster()
-    cfg = raster.config(0)
+    cfg = raster.config(0, tile_w=tile[0], tile_h=tile[1])
     fr = raster.Frame(cfg, views)
     E = fr.n_items * n
     rec = np.zeros((E, 8), np.float32)
@@ -114,7 +116,7 @@ def _check_sort(views, n, hi, lo, radius, depth):
                 radius=torch.from_numpy(radius).cuda())
     srt = raster.bin_sort(cfg, proj, fr, n, want_keys=True)
     torch.cuda.synchronize()
-    keys, vals, ranges = oracle.sort_stage(views, n, hi, lo, radius, depth)
+    keys, vals, ranges = oracle.sort_stage(views, n, hi, lo, radius, depth, tile_w=tile[0], tile_h=tile[1])
     D = int(srt.n_dup.item())
     assert D == len(keys)
     np.testing.assert_array_equal(srt.keys[:D].cpu().numpy().view(np.uint64), keys)
@@ -140,6 +142,47 @@ def test_bin_sort_bit_exact_on_oracle_projection():
     hi = ref["m2"].astype(np.float32)
     lo = (ref["m2"] - hi.astype(np.float64)).astype(np.float32)
     _check_sort(views, sc.n, hi, lo, ref["radius"].astype(np.int32), ref["depth"].astype(np.float32))
+
+
+# 256-pixel tiles other than 16 x 16 (the autotuner's tile shapes)
+TILE_SHAPES = [(32, 8), (8, 32), (64, 4)]
+
+
+@pytest.mark.parametrize("tile", TILE_SHAPES)
+def test_bin_sort_bit_exact_tile_shapes(tile):
+    views = [scenes.identity_view(200, 120, levels=2), scenes.identity_view(100, 70, levels=1)]
+    sizes = [(it["W"], it["H"]) for it in oracle.items(views)]
+    hi, lo, radius, depth = scenes.synthetic_projection(sizes, 3000, seed=5020, tie_depths=True)
+    assert _check_sort(views, 3000, hi, lo, radius, depth, tile) > 10000
+    sc, views = small_room(n=20000)
+    ref = oracle.preprocess(oracle.Config(tile_w=tile[0], tile_h=tile[1]), sc, views)
+    hi = ref["m2"].astype(np.float32)
+    lo = (ref["m2"] - hi.astype(np.float64)).astype(np.float32)
+    _check_sort(views, sc.n, hi, lo, ref["radius"].astype(np.int32), ref["depth"].astype(np.float32), tile)
+
+
+@pytest.mark.parametrize("tile", TILE_SHAPES)
+def test_preprocess_parity_tile_shapes(tile):
+    """A footprint whose rect misses every tile of its item is culled (radius 0): that
+    decision depends on the tile shape."""
+    sc, views = CASES["room_ragged_3lv"]()
+    raster = _raster()
+    cfg = raster.config(sc.n_classes, tile_w=tile[0], tile_h=tile[1])
+    fr = raster.Frame(cfg, views)
+    proj = raster.preprocess(cfg, raster.to_device(sc), fr)
+    torch.cuda.synchronize()
+    ref = oracle.preprocess(oracle.Config(tile_w=tile[0], tile_h=tile[1]), sc, views)
+    ok = ~flagged(ref["flag"], "projections")
+    np.testing.assert_array_equal(proj["radius"].cpu().numpy()[ok], ref["radius"][ok])
+
+
+@pytest.mark.parametrize("variant", ["split", "split_wholewalk", "mfma", "valu"])
+@pytest.mark.parametrize("tile", TILE_SHAPES)
+@pytest.mark.parametrize("case", ["room_ragged_3lv", "room_long_lists"])
+def test_render_parity_tile_shapes(case, tile, variant):
+    sc, views = CASES[case]()
+    _check_render_fwd(sc, views, *VARIANTS[variant], tile=tile)
+    _check_render_bwd(case, *VARIANTS[variant], tile=tile)
 
 
 def test_bin_sort_capacity_overflow_reports_status():
@@ -193,10 +236,10 @@ def test_render_fwd_state_too_small():
     _check_render_bwd("room_long_lists", 3, True, fwd_chunk=0, state_capacity=0)
 
 
-def _check_render_fwd(sc, views, variant, split, fwd_chunk=1, state_capacity=None, isotropic=False):
+def _check_render_fwd(sc, views, variant, split, fwd_chunk=1, state_capacity=None, isotropic=False, tile=(16, 16)):
     cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant, split, state_capacity, fwd_chunk,
-                                           isotropic)
-    ocfg = oracle.Config(isotropic=isotropic)
+                                           isotropic, tile)
+    ocfg = oracle.Config(isotropic=isotropic, tile_w=tile[0], tile_h=tile[1])
     ref = oracle.render(ocfg, sc, views)
     # sum_i w_i |f_i|: the magnitude a composited sum with mixed signs is measured against
     mag = oracle.render(ocfg, sc, views, sem=np.abs(sc.sem))["img"]
@@ -297,11 +340,11 @@ def test_render_bwd_single_item_fallback(split):
 
 
 def _check_render_bwd(case, variant, split, fwd_chunk=1, small_workspace=False, state_capacity=None,
-                      isotropic=False):
+                      isotropic=False, tile=(16, 16)):
     sc, views = CASES[case]()
     cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant, split, state_capacity, fwd_chunk,
-                                           isotropic)
-    ocfg = oracle.Config(isotropic=isotropic)
+                                           isotropic, tile)
+    ocfg = oracle.Config(isotropic=isotropic, tile_w=tile[0], tile_h=tile[1])
     raster = _raster()
     ws = None
     if small_workspace:

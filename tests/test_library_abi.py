@@ -296,3 +296,24 @@ def test_semantic_colour_loss_arguments_are_checked_on_the_host():
     assert call(lam_s=1.5) == L.GS_ERR_INVALID_ARG
     assert call(lam_s=-0.1) == L.GS_ERR_INVALID_ARG
     assert call() == L.GS_ERR_WORKSPACE          # valid arguments: refused only for its 3000 items
+
+
+def test_tile_shapes_accepted_and_refused_on_the_host():
+    """256-pixel tiles of width 8, 16, 32 or 64 are accepted; other shapes are refused."""
+    lib = L.lib()
+    V = (L.View * 1)()
+    W = (ctypes.c_int32 * 1)(100)
+    H = (ctypes.c_int32 * 1)(60)
+    K = (ctypes.c_float * 4)(50.0, 50.0, 50.0, 30.0)
+    lv = (ctypes.c_int32 * 1)(1)
+    for (tw, th), ok in (((16, 16), True), ((32, 8), True), ((8, 32), True), ((64, 4), True), ((32, 16), False),
+                         ((4, 64), False), ((12, 12), False)):
+        c = L.Config()
+        lib.gs_config_default(ctypes.byref(c))
+        c.tile_w, c.tile_h = tw, th
+        items = (L.Item * 1)()
+        npix, ntile = ctypes.c_int64(), ctypes.c_int32()
+        r = lib.gs_make_items(ctypes.byref(c), 1, V, W, H, K, lv, items, ctypes.byref(npix), ctypes.byref(ntile))
+        assert (r >= 0) == ok, (tw, th, r)   # the item count, or a negative status
+        if ok:
+            assert ntile.value == -(-100 // tw) * -(-60 // th)
