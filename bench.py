@@ -292,7 +292,7 @@ def batch_report(args, device):
     step, targets = plain_step(sc, views, device)
 
     def make(cfg):
-        return MappingStep(cfg, step.frame, step.g, targets, sc.n_classes)
+        return MappingStep(cfg, autotune.frame_for(cfg, step.frame), step.g, targets, sc.n_classes)
 
     tuned = autotune.tune(make, step.cfg, step.frame, sc.n)
     step = make(step.cfg)
@@ -359,7 +359,7 @@ def large_headline(args, dev):
 
     def make(c):
         from paper_2412_01217_amd.step import MappingStep
-        return MappingStep(c, step.frame, step.g, targets, 52, head=head)
+        return MappingStep(c, autotune.frame_for(c, step.frame), step.g, targets, 52, head=head)
     tuned = autotune.tune(make, cfg, step.frame, sc.n, candidates=large_candidates(), reps=3)
     step = make(cfg)
     m = measure(step, args.steps, args.warmup, graph=not args.eager)
@@ -376,7 +376,7 @@ def large_plain_report(args, dev, sc, views, targets, ms_learned):
     step, _ = plain_step(sc, views, dev, targets=targets)
 
     def make(c):
-        return MappingStep(c, step.frame, step.g, targets, 52)
+        return MappingStep(c, autotune.frame_for(c, step.frame), step.g, targets, 52)
     tuned = autotune.tune(make, step.cfg, step.frame, sc.n, candidates=large_candidates(), reps=2)
     step = make(step.cfg)
     m = measure(step, max(3, args.steps // 4), 2, graph=not args.eager)

@@ -2,11 +2,14 @@
 
 For one workload signature (Gaussian count, channels, items, pixels, tiles) it times
 each candidate launch configuration -- render kernel variant (per-lane FMA, single-precision
-or split-bfloat16 matrix cores), tile launch order (coarse pyramid levels first, or item order)
-and the forward's work item (256-entry segments of long lists, or whole lists) -- as HIP
-graph replays of the whole step, keeps the fastest, and caches the choice in a JSON
-file (GS_AUTOTUNE_CACHE, default ~/.cache/gs_autotune.json) keyed by device and
-signature. Every candidate computes the same result; only the schedule differs.
+or split-bfloat16 matrix cores), tile launch order (coarse pyramid levels first, or item order),
+the forward's work item (256-entry segments of long lists, or whole lists) and the screen
+tile's shape (256 pixels as 16x16, 32x8, 8x32 or 64x4) -- as HIP graph replays of the whole
+step, keeps the fastest, and caches the choice in a JSON file (GS_AUTOTUNE_CACHE, default
+~/.cache/gs_autotune.json) keyed by device and signature. Every candidate computes the same
+result; only the schedule (and, with the tile shape, the binning) differs. A candidate with
+another tile shape needs the item table of that shape: make_step builds its step on
+frame_for(cfg, frame).
 """
 from __future__ import annotations
 
@@ -15,10 +18,26 @@ import os
 
 import torch
 
+def _c(variant, tile_order, fwd_chunk, tile_w=16, tile_h=16):
+    return {"variant": variant, "tile_order": tile_order, "fwd_chunk": fwd_chunk, "tile_w": tile_w, "tile_h": tile_h}
+
+
 # every candidate sets every key, so that none inherits a value from the previous one
-CANDIDATES = ({"variant": 3, "tile_order": 0, "fwd_chunk": 1}, {"variant": 3, "tile_order": 0, "fwd_chunk": 0},
-              {"variant": 3, "tile_order": 1, "fwd_chunk": 1}, {"variant": 2, "tile_order": 0, "fwd_chunk": 1},
-              {"variant": 1, "tile_order": 1, "fwd_chunk": 1})
+CANDIDATES = (_c(3, 0, 1), _c(3, 0, 0), _c(3, 1, 1), _c(2, 0, 1), _c(1, 1, 1),
+              _c(3, 0, 1, 32, 8), _c(3, 0, 0, 32, 8), _c(3, 0, 0, 8, 32), _c(3, 0, 0, 64, 4))
+
+
+def frame_for(cfg, frame):
+    """The item table of `frame`'s views for cfg's tile shape (frame itself when the shape
+    is the same; built once per shape and kept on frame)."""
+    tile = (int(cfg.tile_w), int(cfg.tile_h))
+    if tile == frame.tile:
+        return frame
+    cache = frame.__dict__.setdefault("_tile_frames", {})
+    if tile not in cache:
+        from . import raster
+        cache[tile] = raster.Frame(cfg, frame.views, device=frame.device)
+    return cache[tile]
 
 
 def cache_path() -> str:

@@ -39,6 +39,8 @@ class Frame:
 
     def __init__(self, cfg: L.Config, views, device="cuda"):
         self.device = torch.device(device)
+        self.views = list(views)
+        self.tile = (int(cfg.tile_w), int(cfg.tile_h))
         nv = len(views)
         V = (L.View * max(nv, 1))()
         W = (ctypes.c_int32 * max(nv, 1))()

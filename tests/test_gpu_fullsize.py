@@ -35,18 +35,18 @@ def _workload(name, ssim_lambda=0.0):
         st, tg = bench.plain_step(sc, views, "cuda:0")
 
         def make(cfg):
-            return MappingStep(cfg, st.frame, st.g, tg, sc.n_classes)
+            return MappingStep(cfg, autotune.frame_for(cfg, st.frame), st.g, tg, sc.n_classes)
         autotune.tune(make, st.cfg, st.frame, sc.n)
         st = make(st.cfg)
     return sc, views, st, tg
 
 
-def _tile_pixels(its, mask):
+def _tile_pixels(its, mask, tile=(16, 16)):
     """Per pixel of the concatenated items: does its tile belong to the sample."""
     sel = []
     for it in its:
         v, u = np.mgrid[0:it["H"], 0:it["W"]]
-        t = it["tile0"] + (v // 16) * it["ntx"] + (u // 16)
+        t = it["tile0"] + (v // tile[1]) * it["ntx"] + (u // tile[0])
         sel.append(mask[t.reshape(-1)] != 0)
     return np.concatenate(sel)
 
@@ -62,14 +62,17 @@ def test_full_size_sort_and_sampled_tiles(name):
     rec = st.proj["rec"].cpu().numpy().reshape(-1, 8)
     radius = st.proj["radius"].cpu().numpy()
     depth = st.proj["depth"].cpu().numpy()
-    keys, vals, ranges = oracle.sort_stage(views, sc.n, rec[:, 0:2], rec[:, 2:4], radius, depth)
+    tile = st.frame.tile                   # the launch's tile shape (the autotuner may pick another)
+    print(f"[full size] {name}: tile {tile}, variant {st.cfg.variant}, fwd_chunk {st.cfg.fwd_chunk}", flush=True)
+    keys, vals, ranges = oracle.sort_stage(views, sc.n, rec[:, 0:2], rec[:, 2:4], radius, depth, tile_w=tile[0],
+                                           tile_h=tile[1])
     D = int(st.sorter.n_dup.item())
     assert D == len(vals) and D > 100_000
     np.testing.assert_array_equal(st.sorter.vals[:D].cpu().numpy().view(np.uint32), vals)
     np.testing.assert_array_equal(st.sorter.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), ranges)
 
     # sampled tiles: the longest lists and random ones
-    its = oracle.items(views)
+    its = oracle.items(views, *tile)
     ntiles = len(ranges)
     lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
     rng = np.random.default_rng(7700)
@@ -77,13 +80,13 @@ def test_full_size_sort_and_sampled_tiles(name):
     pick = set(np.argsort(-lens)[:4].tolist()) | set(rng.choice(ntiles, n_rand, replace=False).tolist())
     mask = np.zeros(ntiles, np.uint8)
     mask[sorted(pick)] = 1
-    ocfg = oracle.Config()
+    ocfg = oracle.Config(tile_w=tile[0], tile_h=tile[1])
     # the room is compared on every tile (the oracle renders it whole in a few seconds)
     fmask = None if name == "room" else mask
     ref = oracle.render(ocfg, sc, views, tile_mask=fmask)
     mag = oracle.render(ocfg, sc, views, sem=np.abs(sc.sem), tile_mask=fmask)["img"]
     K = ref["K"]
-    sel = np.ones(len(ref["T"]), bool) if fmask is None else _tile_pixels(its, mask)
+    sel = np.ones(len(ref["T"]), bool) if fmask is None else _tile_pixels(its, mask, tile)
     flag = flagged(ref["flag"][sel], "pixels compared")
     keep_px = sel.copy()
     keep_px[np.flatnonzero(sel)[flag]] = False
@@ -95,7 +98,7 @@ def test_full_size_sort_and_sampled_tiles(name):
     np.testing.assert_array_equal(nc[keep_px], ref["n_contrib"][keep_px])
 
     # backward from an upstream gradient on the sampled tiles only
-    keep = pixel_mask_to_channels(keep_px & _tile_pixels(its, mask), its, K)
+    keep = pixel_mask_to_channels(keep_px & _tile_pixels(its, mask, tile), its, K)
     gimg = (rng.normal(size=got.shape) * 1e-3).astype(np.float32)
     gimg[~keep] = 0.0
     grads = raster.render_bwd(st.cfg, st.g, st.proj, st.frame, st.sorter, st.img,
