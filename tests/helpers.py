@@ -76,3 +76,63 @@ def flagged(flag, name="", bound=FLAG_BOUND):
     print(f"[flagged] {name}: {int(f.sum())} of {f.size} ({share:.2e}, bound {bound:.0e})")
     assert share <= bound, (name, share, bound)
     return f
+
+
+def over_limit(got, ref, tol, mask=None, floor=0.01, scale=None):
+    """Flat indices where |got - ref| > tol * max(|ref|, floor * rms(ref), scale) outside mask
+    (the measure of rel_check), with their errors."""
+    got = np.asarray(got, np.float64).reshape(-1)
+    ref = np.asarray(ref, np.float64).reshape(-1)
+    keep = np.ones(ref.shape, bool) if mask is None else ~np.asarray(mask, bool).reshape(-1)
+    r = ref[keep]
+    rms = float(np.sqrt(np.mean(r * r))) if r.size else 0.0
+    mag = np.maximum(np.abs(ref), floor * rms)
+    if scale is not None:
+        mag = np.maximum(mag, np.abs(np.asarray(scale, np.float64).reshape(-1)))
+    err = np.abs(got - ref)
+    bad = keep & (err > tol * np.where(mag > 0, mag, 1e-30))
+    return np.flatnonzero(bad), err
+
+
+def pixel_term_magnitude(ocfg, sc, views, gimg, K, tiles, i, field, comp=(), sem=None, pre=None):
+    """Sum over the pixels of `tiles` of |the term that one pixel's upstream gradient adds to
+    the oracle's gradient field[i][comp]|: the oracle's backward of each pixel alone, on the
+    Gaussians whose rectangle meets that pixel's tile (the only ones its render reads). A
+    gradient that sums such terms of both signs holds no more relative precision than this
+    magnitude allows. `pre`: the oracle's projection of sc (computed if None)."""
+    import oracle
+    from paper_2412_01217_amd import scenes
+    pre = oracle.preprocess(ocfg, sc, views) if pre is None else pre
+    its = oracle.items(views, ocfg.tile_w, ocfg.tile_h)
+    n = sc.n
+    n_tiles = sum(it["ntx"] * it["nty"] for it in its)
+    feat = sc.sem if sem is None else sem
+    total = 0.0
+    for t in tiles:
+        k = next(kk for kk, it in enumerate(its) if it["tile0"] <= t < it["tile0"] + it["ntx"] * it["nty"])
+        it = its[k]
+        lt = t - it["tile0"]
+        tx, ty = lt % it["ntx"], lt // it["ntx"]
+        rect = pre["rect"][k * n:(k + 1) * n]
+        vis = pre["radius"][k * n:(k + 1) * n] > 0
+        on = vis & (rect[:, 0] <= tx) & (rect[:, 2] > tx) & (rect[:, 1] <= ty) & (rect[:, 3] > ty)
+        if not on[i]:
+            continue
+        idx = np.flatnonzero(on)
+        isub = int(np.searchsorted(idx, i))
+        sub = scenes.Scene(*(np.asarray(getattr(sc, f), np.float64)[idx] for f in
+                             ("mean", "log_scale", "quat", "opacity", "rgb")), None, None, feat.shape[1])
+        fsub = np.asarray(feat, np.float64)[idx]
+        m1 = np.zeros(n_tiles, np.uint8)
+        m1[t] = 1
+        HW = it["W"] * it["H"]
+        g1 = np.zeros_like(gimg, dtype=np.float64)
+        for yy in range(ty * ocfg.tile_h, min(it["H"], (ty + 1) * ocfg.tile_h)):
+            for xx in range(tx * ocfg.tile_w, min(it["W"], (tx + 1) * ocfg.tile_w)):
+                sl = slice(it["pix0"] * K + yy * it["W"] + xx, it["pix0"] * K + K * HW, HW)
+                if not np.any(gimg[sl]):
+                    continue
+                g1[sl] = gimg[sl]
+                total += abs(oracle.backward(ocfg, sub, views, g1, sem=fsub, tile_mask=m1)[field][(isub,) + tuple(comp)])
+                g1[sl] = 0.0
+    return total

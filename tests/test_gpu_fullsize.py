@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.helpers import flagged, pixel_mask_to_channels, rel_check
+from tests.helpers import flagged, over_limit, pixel_mask_to_channels, pixel_term_magnitude, rel_check
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -210,12 +210,25 @@ def test_full_size_learned_batch_sampled_tiles():
     # the geometric gradients are held to 1e-3 of max(|ref|, the sum of the per-tile
     # magnitudes, 5 % of the rms)
     bad = flagged(ob["gflag"], "Gaussians touching a flagged pixel", bound=0.01)
+    # an entry beyond that limit is one whose pixel terms cancel within a tile: it is held to
+    # 1e-3 of the sum of its pixel terms' magnitudes (at most 4 such entries per field)
+    pre = None
     for k, ko in (("mean", "mean"), ("log_scale", "log_scale"), ("quat", "quat"), ("opacity", "opacity"),
                   ("rgb", "rgb"), ("emb", "sem")):
         g = grads[k].cpu().numpy()
         m = np.broadcast_to(bad.reshape(-1, *([1] * (g.ndim - 1))), g.shape)
         feat = k in ("rgb", "emb")
-        res = rel_check(g, ob[ko], BWD_TOL, mask=m, name=k, scale=om[ko] if feat else per_tile[k],
-                        floor=0.01 if feat else 0.05)
+        lim_kw = dict(mask=m, scale=om[ko] if feat else per_tile[k], floor=0.01 if feat else 0.05)
+        over, err = over_limit(g, ob[ko], BWD_TOL, **lim_kw)
+        assert len(over) <= 4, (k, len(over))
+        for flat in over:
+            i, comp = np.unravel_index(flat, g.shape)[0], np.unravel_index(flat, g.shape)[1:]
+            pre = oracle.preprocess(ocfg, sc, views) if pre is None else pre
+            mag = pixel_term_magnitude(ocfg, sc, views, g64, K, sorted(pick), int(i), ko, comp, sem=emb, pre=pre)
+            print(f"[full size] {k}{(int(i),) + tuple(int(c) for c in comp)}: |d| {err[flat]:.3g}, "
+                  f"pixel-term limit {BWD_TOL * mag:.3g}", flush=True)
+            assert err[flat] <= BWD_TOL * mag, (k, int(i), comp, err[flat], mag)
+        res = rel_check(g, ob[ko], BWD_TOL, name=k, **dict(lim_kw, mask=np.asarray(m, bool).copy().reshape(-1) |
+                                                              np.isin(np.arange(g.size), over)))
         assert res["l2"] < 1e-5, (k, res)
     rel_check(grads["pose"].cpu().numpy(), ob["pose"], BWD_TOL, name="pose")

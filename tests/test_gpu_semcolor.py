@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_2412_01217_amd import scenes
-from tests.helpers import flagged, rel_check, targets_from_random
+from tests.helpers import flagged, over_limit, pixel_term_magnitude, rel_check, targets_from_random
 from tests.test_gpu_parity import BWD_TOL, FWD_TOL, SSIM_VIEWS, _check_render_fwd, _pipeline, _raster, small_room
 
 pytestmark = pytest.mark.gpu
@@ -65,15 +65,29 @@ def test_semantic_colour_end_to_end(scene):
     cfg.ssim_lambda = 0.2
     cfg.sem_ssim_lambda = 0.2
     raster = _raster()
-    t_rgb, t_depth, t_sem = _sem_targets(views, 4020)
+    ocfg = oracle.Config()
+    r = oracle.render(ocfg, sc, views)
+    _check_render_fwd(sc, views, 3, True)     # the semantic colour image composited like RGB
+    # targets at least 0.02 from the render in every channel, so that the L1 terms' signs are
+    # the same for the single-precision render and the oracle's (R13: a sign at the kink is
+    # a discrete choice); a tenth of the depths missing
+    rng = np.random.default_rng(4020)
+    t_rgb, t_depth, t_sem = [], [], []
+    for it in oracle.items(views):
+        HW = it["W"] * it["H"]
+        im = r["img"][it["pix0"] * 7: it["pix0"] * 7 + 7 * HW].reshape(7, HW)
+        off = lambda m: rng.choice([-1.0, 1.0], size=m.shape) * rng.uniform(0.02, 0.3, size=m.shape)  # noqa: E731
+        t_rgb.append((im[:3] + off(im[:3])).reshape(-1))
+        d = im[3] + off(im[3])
+        d[rng.uniform(size=HW) < 0.1] = 0.0
+        t_depth.append(d)
+        t_sem.append((im[4:] + off(im[4:])).reshape(-1))
+    t_rgb, t_depth, t_sem = (np.concatenate(x).astype(np.float32) for x in (t_rgb, t_depth, t_sem))
     T = dict(rgb=torch.from_numpy(t_rgb).cuda(), depth=torch.from_numpy(t_depth).cuda(),
              sem_color=torch.from_numpy(t_sem).cuda())
     ls, grad = raster.loss(cfg, fr, 0, img, T)
     grads = raster.render_bwd(cfg, g, proj, fr, srt, img, grad)
     torch.cuda.synchronize()
-    ocfg = oracle.Config()
-    r = oracle.render(ocfg, sc, views)
-    _check_render_fwd(sc, views, 3, True)     # the semantic colour image composited like RGB
     ls_ref, gimg = oracle.loss(views, 3, r["img"], t_rgb, t_depth, None, ssim_lambda=0.2, t_sem=t_sem,
                                sem_ssim_lambda=0.2)
     rel_check(ls.cpu().numpy(), ls_ref, FWD_TOL, name="loss")
@@ -81,8 +95,24 @@ def test_semantic_colour_end_to_end(scene):
     mag = oracle.backward(ocfg, sc, views, np.abs(gimg))
     flagged(r["flag"], "pixels")
     bad = flagged(ref["gflag"], "Gaussians touching a flagged pixel", bound=0.15)
+    # An entry beyond 1e-3 is one whose pixel terms cancel: it is held to 1e-3 of the sum of
+    # their magnitudes (at most 4 such entries per field).
+    its = oracle.items(views)
+    n_tiles = sum(it["ntx"] * it["nty"] for it in its)
+    pre = None
     for name in ("mean", "log_scale", "quat", "opacity", "rgb", "sem"):
         got = grads[name].cpu().numpy()
-        m = np.broadcast_to(bad.reshape(-1, *([1] * (got.ndim - 1))), got.shape)
-        rel_check(got, ref[name], BWD_TOL, mask=m, name=name, scale=mag[name] if name in ("rgb", "sem") else None)
+        m = np.asarray(np.broadcast_to(bad.reshape(-1, *([1] * (got.ndim - 1))), got.shape), bool).reshape(-1)
+        kw = dict(mask=m, scale=mag[name] if name in ("rgb", "sem") else None)
+        over, err = over_limit(got, ref[name], BWD_TOL, **kw)
+        assert len(over) <= 4, (name, len(over))
+        for flat in over:
+            ix = np.unravel_index(flat, got.shape)
+            pre = oracle.preprocess(ocfg, sc, views) if pre is None else pre
+            pm = pixel_term_magnitude(ocfg, sc, views, gimg, 7, range(n_tiles), int(ix[0]), name, ix[1:], pre=pre)
+            print(f"[semantic colour] {name}{tuple(int(c) for c in ix)}: |d| {err[flat]:.3g}, "
+                  f"pixel-term limit {BWD_TOL * pm:.3g}", flush=True)
+            assert err[flat] <= BWD_TOL * pm, (name, ix, err[flat], pm)
+        kw["mask"] = m | np.isin(np.arange(m.size), over)
+        rel_check(got, ref[name], BWD_TOL, name=name, **kw)
     rel_check(grads["pose"].cpu().numpy(), ref["pose"], BWD_TOL, name="pose")
