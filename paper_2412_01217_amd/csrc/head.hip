@@ -258,11 +258,14 @@ __device__ __forceinline__ void head_setup(HeadLds& L, int C, const uint16_t* __
 // Steps (1)-(5) for one 64-pixel chunk whose logit gradients are staged in sg [class][pixel].
 // Eb: pixel 0 of plane 0 of the chunk's embedding, plane d at Eb + d es (es = HW in global
 // memory; the row stride when staged in LDS, whose 64 entries per row are all readable);
-// dEb: the chunk's gradient planes (plane d at dEb + d HW).
+// dEb: the chunk's gradient planes (plane d at dEb + d HW). on_in (LDS_E, the fused loss):
+// the ReLU masks its decode formed, [half][hb] bit r for hidden unit drow(r) + 32 hb, in
+// place of step (1)'s recomputation.
 template <bool ADD, bool LDS_E>
 __device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const float* sg, const float* Eb, int64_t es,
                                                     float* dEb, int64_t HW, int nlive, const v4s (&w1a)[2][2],
-                                                    const float (&b1l)[2], HeadAcc& acc) {
+                                                    const float (&b1l)[2], HeadAcc& acc,
+                                                    const uint32_t (*on_in)[2] = nullptr) {
   const int lane = threadIdx.x & 63, half = lane >> 5, l32 = lane & 31;
 #pragma unroll 1
   for (int pb = 0; pb < 2; ++pb) {
@@ -283,20 +286,25 @@ __device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const floa
       split4(e, ehi[ks], elo[ks]);
     }
     uint32_t on[2];   // bit r: hidden unit drow(r) + 32 hb is active at this pixel
+    if constexpr (LDS_E) {
+      on[0] = pb ? on_in[1][0] : on_in[0][0];
+      on[1] = pb ? on_in[1][1] : on_in[0][1];
+    } else {
 #pragma unroll
-    for (int hb = 0; hb < 2; ++hb) {
-      v16f h;
+      for (int hb = 0; hb < 2; ++hb) {
+        v16f h;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) h[r] = L.b1[drow(r, lane) + 32 * hb];
+        for (int r = 0; r < 16; ++r) h[r] = L.b1[drow(r, lane) + 32 * hb];
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        h = mfma(w1a[hb][ks], ehi[ks], h);
-        h = mfma(w1a[hb][ks], elo[ks], h);
+        for (int ks = 0; ks < 2; ++ks) {
+          h = mfma(w1a[hb][ks], ehi[ks], h);
+          h = mfma(w1a[hb][ks], elo[ks], h);
+        }
+        uint32_t bits = 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) bits |= (h[r] > 0.0f ? 1u : 0u) << r;
+        on[hb] = bits;
       }
-      uint32_t bits = 0;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) bits |= (h[r] > 0.0f ? 1u : 0u) << r;
-      on[hb] = bits;
     }
 
     // (2) dH^T = W2^T dlogits^T: A = W2^T (i = hidden l32 + 32 hb, k = class 8 ks + 4 half + j)
@@ -662,8 +670,11 @@ __device__ __forceinline__ void head_loss_chunk(const HeadLds& L, const uint16_t
     }
   }
   // decode and cross-entropy per 32-pixel half: logits^T[cb][.] in D layout, lane l holding
-  // pixel 32 pb + l32, classes drow(r) + 32 cb; each pixel's classes span lanes l32 and l32 + 32
-#pragma unroll 1
+  // pixel 32 pb + l32, classes drow(r) + 32 cb; each pixel's classes span lanes l32 and l32 + 32.
+  // The hidden layer's ReLU masks are kept for the backward (the same D layout); the halves
+  // are unrolled so that the masks stay in registers.
+  uint32_t onb[2][2];
+#pragma unroll
   for (int pb = 0; pb < 2; ++pb) {
     const int q = l32 + 32 * pb;
     const bool qlive = q < nlive;
@@ -689,9 +700,16 @@ __device__ __forceinline__ void head_loss_chunk(const HeadLds& L, const uint16_t
         }
       }
 #pragma unroll
-      for (int hb = 0; hb < 2; ++hb)
+      for (int hb = 0; hb < 2; ++hb) {
+        uint32_t bits = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) H[hb][r] = fmaxf(H[hb][r] + L.b1[drow(r, lane) + 32 * hb], 0.0f);
+        for (int r = 0; r < 16; ++r) {
+          const float pre = H[hb][r] + L.b1[drow(r, lane) + 32 * hb];
+          bits |= (pre > 0.0f ? 1u : 0u) << r;
+          H[hb][r] = fmaxf(pre, 0.0f);
+        }
+        onb[pb][hb] = bits;
+      }
     }
     v16f Lg[2];
 #pragma unroll
@@ -751,7 +769,7 @@ __device__ __forceinline__ void head_loss_chunk(const HeadLds& L, const uint16_t
   }
   wave_fence();
   head_chunk_backward<false, true>(L, sg, &S.E[0][0], kEst, gcolor + ci.pixel_base * K + 4 * HW + ci.local0, HW,
-                                   nlive, w1a, b1l, acc);
+                                   nlive, w1a, b1l, acc, onb);
   wave_fence();
   // loss partial sums: one atomic per wave and quantity (a chunk lies in one item)
   const float a = wave_sum(lr), bsum = wave_sum(ld), c = wave_sum(ls), v = wave_sum(nv);

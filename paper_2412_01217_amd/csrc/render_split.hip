@@ -470,7 +470,7 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
         const int64_t o = sl * kTilePx + tid;
         fs.Te[o] = T;
         const uint32_t lseg = last > (uint32_t)(sg * kSeg) ? last : 0u;
-        fs.info[o] = lseg | (active ? kInfoActive : 0u) | (active & done ? kInfoStopped : 0u);
+        fs.info[o] = lseg | (active ? kInfoActive : 0u) | ((active && done) ? kInfoStopped : 0u);
       }
     }
     if (split && nseg > chunk) continue;   // joined by k_fwd_combine
