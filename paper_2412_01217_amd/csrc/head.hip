@@ -52,6 +52,21 @@ __device__ __forceinline__ void split4(const float* x, v4s& hi, v4s& lo) {
 
 __device__ __forceinline__ v16f mfma(v4s a, v4s b, v16f c) { return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0); }
 
+// Two consecutive k-steps of 32x32x8 as one v_mfma_f32_32x32x16_bf16 (twice the work per
+// instruction on gfx950): lane (l % 32, h = l / 32) supplies k = 8 h + 0..7 of the 16; given
+// k-step pairs whose lane h holds k = 8 (2s) + 4 h + 0..3 and 8 (2s + 1) + 4 h + 0..3 (the
+// layout above), the concatenation [step 2s, step 2s + 1] covers each k of the pair once in
+// both operands, so the product is the same sum over the 16 k.
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ v16f mfma2(v8s a, v8s b, v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ v8s cat(v4s x0, v4s x1) { return __builtin_shufflevector(x0, x1, 0, 1, 2, 3, 4, 5, 6, 7); }
+__device__ __forceinline__ v16f mfma2(v4s a0, v4s a1, v4s b0, v4s b1, v16f c) { return mfma2(cat(a0, a1), cat(b0, b1), c); }
+__device__ __forceinline__ v16f mfma2(v8s a, v4s b0, v4s b1, v16f c) { return mfma2(a, cat(b0, b1), c); }
+__device__ __forceinline__ v16f mfma2(v4s a0, v4s a1, v8s b, v16f c) { return mfma2(cat(a0, a1), b, c); }
+
 __device__ __forceinline__ v16f zero16() {
   v16f z;
 #pragma unroll
@@ -208,10 +223,16 @@ __device__ __forceinline__ bool seek_chunk(const gs_item* __restrict__ items, in
 constexpr int kGst = 65;   // LDS row stride of the staged logit gradients
 
 // The block's shared state of a head backward: transposed weights and the per-wave staging.
-struct HeadLds {
+// The transposed weights' rows are stored with the contraction index k at kperm(k) (bits 2
+// and 3 of k swapped), so that the 8 values a lane supplies to a 32x32x16 product of the
+// k-step pair s (k = 16 s + 4 h + 0..3 and 16 s + 8 + 4 h + 0..3, see mfma2) are contiguous
+// at 16 s + 8 h: one 16-byte LDS read.
+__host__ __device__ constexpr int kperm(int k) { return (k & ~12) | ((k & 4) << 1) | ((k & 8) >> 1); }
+
+struct alignas(16) HeadLds {
   float buf[4 * kHid * kGst];        // per wave [class][pixel]; the block's partial at the end
-  uint16_t w2t[kHid * kWtStride];    // W2^T [hidden][class], classes >= C zero
-  uint16_t w1t[kDin * kWtStride];    // W1^T [d][hidden]
+  uint16_t w2t[kHid * kWtStride];    // W2^T [hidden][kperm(class)], classes >= C zero
+  uint16_t w1t[kDin * kWtStride];    // W1^T [d][kperm(hidden)]
   float b1[kHid];
 };
 
@@ -227,11 +248,11 @@ __device__ __forceinline__ void head_setup(HeadLds& L, int C, const uint16_t* __
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, half = lane >> 5, l32 = lane & 31;
   for (int i = threadIdx.x; i < kHid * kHid; i += 256) {
     const int c = i / kHid, h = i % kHid;
-    L.w2t[h * kWtStride + c] = c < C ? W2[c * kHid + h] : (uint16_t)0;
+    L.w2t[h * kWtStride + kperm(c)] = c < C ? W2[c * kHid + h] : (uint16_t)0;
   }
   for (int i = threadIdx.x; i < kHid * kDin; i += 256) {
     const int h = i / kDin, d = i % kDin;
-    L.w1t[d * kWtStride + h] = W1[h * kDin + d];
+    L.w1t[d * kWtStride + kperm(h)] = W1[h * kDin + d];
   }
   if (threadIdx.x < kHid) L.b1[threadIdx.x] = b1[threadIdx.x];
   float* sg = L.buf + wave * kHid * kGst;
@@ -295,11 +316,8 @@ __device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const floa
         v16f h;
 #pragma unroll
         for (int r = 0; r < 16; ++r) h[r] = L.b1[drow(r, lane) + 32 * hb];
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-          h = mfma(w1a[hb][ks], ehi[ks], h);
-          h = mfma(w1a[hb][ks], elo[ks], h);
-        }
+        h = mfma2(w1a[hb][0], w1a[hb][1], ehi[0], ehi[1], h);
+        h = mfma2(w1a[hb][0], w1a[hb][1], elo[0], elo[1], h);
         uint32_t bits = 0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) bits |= (h[r] > 0.0f ? 1u : 0u) << r;
@@ -310,17 +328,21 @@ __device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const floa
     // (2) dH^T = W2^T dlogits^T: A = W2^T (i = hidden l32 + 32 hb, k = class 8 ks + 4 half + j)
     v16f dHT[2] = {zero16(), zero16()};
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-      float x[4];
+    for (int s2 = 0; s2 < 4; ++s2) {
+      v4s hi[2], lo[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) x[j] = Gq[(8 * ks + j) * kGst];
-      v4s hi, lo;
-      split4(x, hi, lo);
+      for (int u = 0; u < 2; ++u) {
+        const int ks = 2 * s2 + u;
+        float x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = Gq[(8 * ks + j) * kGst];
+        split4(x, hi[u], lo[u]);
+      }
 #pragma unroll
       for (int hb = 0; hb < 2; ++hb) {
-        const v4s a = *reinterpret_cast<const v4s*>(L.w2t + (l32 + 32 * hb) * kWtStride + 8 * ks + 4 * half);
-        dHT[hb] = mfma(a, hi, dHT[hb]);
-        dHT[hb] = mfma(a, lo, dHT[hb]);
+        const v8s a = *reinterpret_cast<const v8s*>(L.w2t + (l32 + 32 * hb) * kWtStride + 16 * s2 + 8 * half);
+        dHT[hb] = mfma2(a, hi[0], hi[1], dHT[hb]);
+        dHT[hb] = mfma2(a, lo[0], lo[1], dHT[hb]);
       }
     }
 #pragma unroll
@@ -333,16 +355,20 @@ __device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const floa
     {
       v16f dE = zero16();
 #pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        v4s a = {0, 0, 0, 0};
-        if (l32 < kDin) a = *reinterpret_cast<const v4s*>(L.w1t + l32 * kWtStride + 8 * ks + 4 * half);
-        float x[4];
+      for (int s2 = 0; s2 < 4; ++s2) {
+        v8s a = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (l32 < kDin) a = *reinterpret_cast<const v8s*>(L.w1t + l32 * kWtStride + 16 * s2 + 8 * half);
+        v4s hi[2], lo[2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = dHT[ks >> 2][4 * (ks & 3) + j];
-        v4s hi, lo;
-        split4(x, hi, lo);
-        dE = mfma(a, hi, dE);
-        dE = mfma(a, lo, dE);
+        for (int u = 0; u < 2; ++u) {
+          const int ks = 2 * s2 + u;
+          float x[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) x[j] = dHT[ks >> 2][4 * (ks & 3) + j];
+          split4(x, hi[u], lo[u]);
+        }
+        dE = mfma2(a, hi[0], hi[1], dE);
+        dE = mfma2(a, lo[0], lo[1], dE);
       }
       // rows 0..15 = d: added to what the caller's gradient holds there, or stored
       if (qlive)
@@ -360,38 +386,40 @@ __device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const floa
     v16f H[2];
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
-      H[hb] = zero16();
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        H[hb] = mfma(ehi[ks], w1a[hb][ks], H[hb]);
-        H[hb] = mfma(elo[ks], w1a[hb][ks], H[hb]);
-      }
+      H[hb] = mfma2(ehi[0], ehi[1], w1a[hb][0], w1a[hb][1], zero16());
+      H[hb] = mfma2(elo[0], elo[1], w1a[hb][0], w1a[hb][1], H[hb]);
 #pragma unroll
       for (int r = 0; r < 16; ++r) H[hb][r] = fmaxf(H[hb][r] + b1l[hb], 0.0f);
     }
     // (5a) dW2[c][h] += sum_p dlogits[c][p] relu(H)[p][h] over the half's pixels
     // p = 32 pb + 8 kk + 4 half + j (registers 4 kk + j): A = dlogits (i = class l32 + 32 cb, k = p)
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int p0 = 32 * pb + 8 * kk + 4 * half;
+    for (int k2 = 0; k2 < 2; ++k2) {
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
-        float x[4];
+        v4s ahi[2], alo[2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = sg[(l32 + 32 * cb) * kGst + p0 + j];
-        acc.B2[cb] += (x[0] + x[1]) + (x[2] + x[3]);
-        v4s ahi, alo;
-        split4(x, ahi, alo);
+        for (int u = 0; u < 2; ++u) {
+          const int p0 = 32 * pb + 8 * (2 * k2 + u) + 4 * half;
+          float x[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) x[j] = sg[(l32 + 32 * cb) * kGst + p0 + j];
+          acc.B2[cb] += (x[0] + x[1]) + (x[2] + x[3]);
+          split4(x, ahi[u], alo[u]);
+        }
 #pragma unroll
         for (int hb = 0; hb < 2; ++hb) {
-          float y[4];
+          v4s bhi[2], blo[2];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) y[j] = H[hb][4 * kk + j];
-          v4s bhi, blo;
-          split4(y, bhi, blo);
-          acc.W2[cb][hb] = mfma(ahi, bhi, acc.W2[cb][hb]);
-          acc.W2[cb][hb] = mfma(ahi, blo, acc.W2[cb][hb]);
-          acc.W2[cb][hb] = mfma(alo, bhi, acc.W2[cb][hb]);
+          for (int u = 0; u < 2; ++u) {
+            float y[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) y[j] = H[hb][4 * (2 * k2 + u) + j];
+            split4(y, bhi[u], blo[u]);
+          }
+          acc.W2[cb][hb] = mfma2(ahi[0], ahi[1], bhi[0], bhi[1], acc.W2[cb][hb]);
+          acc.W2[cb][hb] = mfma2(ahi[0], ahi[1], blo[0], blo[1], acc.W2[cb][hb]);
+          acc.W2[cb][hb] = mfma2(alo[0], alo[1], bhi[0], bhi[1], acc.W2[cb][hb]);
         }
       }
     }
@@ -406,17 +434,21 @@ __device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const floa
     // (4b) dH with pixels in registers: A = dlogits (i = pixel, k = class), B = W2 (j = hidden)
     v16f dH[2] = {zero16(), zero16()};
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-      float x[4];
+    for (int s2 = 0; s2 < 4; ++s2) {
+      v4s hi[2], lo[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) x[j] = Gq[(8 * ks + j) * kGst];
-      v4s hi, lo;
-      split4(x, hi, lo);
+      for (int u = 0; u < 2; ++u) {
+        const int ks = 2 * s2 + u;
+        float x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = Gq[(8 * ks + j) * kGst];
+        split4(x, hi[u], lo[u]);
+      }
 #pragma unroll
       for (int hb = 0; hb < 2; ++hb) {
-        const v4s b = *reinterpret_cast<const v4s*>(L.w2t + (l32 + 32 * hb) * kWtStride + 8 * ks + 4 * half);
-        dH[hb] = mfma(hi, b, dH[hb]);
-        dH[hb] = mfma(lo, b, dH[hb]);
+        const v8s b = *reinterpret_cast<const v8s*>(L.w2t + (l32 + 32 * hb) * kWtStride + 16 * s2 + 8 * half);
+        dH[hb] = mfma2(hi[0], hi[1], b, dH[hb]);
+        dH[hb] = mfma2(lo[0], lo[1], b, dH[hb]);
       }
     }
 #pragma unroll
@@ -426,26 +458,32 @@ __device__ __forceinline__ void head_chunk_backward(const HeadLds& L, const floa
     // (5b) dW1[h][d] += sum_p dH[p][h] [E, 1][p][d]: A = dH (i = hidden l32 + 32 hb, k = p), B = [E, 1] (j = d l32)
     const float* Ed = Eb + (int64_t)min(l32, kDin - 1) * es;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int p0 = 32 * pb + 8 * kk + 4 * half;
-      float e[4];
+    for (int k2 = 0; k2 < 2; ++k2) {
+      v4s bhi[2], blo[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float v = Ed[LDS_E ? p0 + j : min(p0 + j, nlive - 1)];
-        e[j] = p0 + j >= nlive ? 0.0f : (l32 < kDin ? v : (l32 == kDin ? 1.0f : 0.0f));
+      for (int u = 0; u < 2; ++u) {
+        const int p0 = 32 * pb + 8 * (2 * k2 + u) + 4 * half;
+        float e[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float v = Ed[LDS_E ? p0 + j : min(p0 + j, nlive - 1)];
+          e[j] = p0 + j >= nlive ? 0.0f : (l32 < kDin ? v : (l32 == kDin ? 1.0f : 0.0f));
+        }
+        split4(e, bhi[u], blo[u]);
       }
-      v4s bhi, blo;
-      split4(e, bhi, blo);
 #pragma unroll
       for (int hb = 0; hb < 2; ++hb) {
-        float y[4];
+        v4s ahi[2], alo[2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) y[j] = dH[hb][4 * kk + j];
-        v4s ahi, alo;
-        split4(y, ahi, alo);
-        acc.W1[hb] = mfma(ahi, bhi, acc.W1[hb]);
-        acc.W1[hb] = mfma(ahi, blo, acc.W1[hb]);
-        acc.W1[hb] = mfma(alo, bhi, acc.W1[hb]);
+        for (int u = 0; u < 2; ++u) {
+          float y[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) y[j] = dH[hb][4 * (2 * k2 + u) + j];
+          split4(y, ahi[u], alo[u]);
+        }
+        acc.W1[hb] = mfma2(ahi[0], ahi[1], bhi[0], bhi[1], acc.W1[hb]);
+        acc.W1[hb] = mfma2(ahi[0], ahi[1], blo[0], blo[1], acc.W1[hb]);
+        acc.W1[hb] = mfma2(alo[0], alo[1], bhi[0], bhi[1], acc.W1[hb]);
       }
     }
   }
@@ -681,8 +719,7 @@ __device__ __forceinline__ void head_loss_chunk(const HeadLds& L, const uint16_t
     const int y = __shfl(y_own, q, 64);
     v16f H[2];
     {
-#pragma unroll
-      for (int hb = 0; hb < 2; ++hb) H[hb] = zero16();
+      v4s ehi[2], elo[2];
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
         float e[4];
@@ -691,13 +728,12 @@ __device__ __forceinline__ void head_loss_chunk(const HeadLds& L, const uint16_t
           const float v = S.E[8 * ks + 4 * (lane >> 5) + j][q];
           e[j] = qlive ? v : 0.0f;
         }
-        v4s hi, lo;
-        split4(e, hi, lo);
+        split4(e, ehi[ks], elo[ks]);
+      }
 #pragma unroll
-        for (int hb = 0; hb < 2; ++hb) {
-          H[hb] = mfma(w1a[hb][ks], hi, H[hb]);
-          H[hb] = mfma(w1a[hb][ks], lo, H[hb]);
-        }
+      for (int hb = 0; hb < 2; ++hb) {
+        H[hb] = mfma2(w1a[hb][0], w1a[hb][1], ehi[0], ehi[1], zero16());
+        H[hb] = mfma2(w1a[hb][0], w1a[hb][1], elo[0], elo[1], H[hb]);
       }
 #pragma unroll
       for (int hb = 0; hb < 2; ++hb) {
@@ -715,18 +751,23 @@ __device__ __forceinline__ void head_loss_chunk(const HeadLds& L, const uint16_t
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
       Lg[cb] = zero16();
-      const uint16_t* wrow = w2r + (l32 + 32 * cb) * kWtStride + 4 * (lane >> 5);
+      const uint16_t* wrow = w2r + (l32 + 32 * cb) * kWtStride + 8 * (lane >> 5);
 #pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        // A = W2 (i = class l32 + 32 cb, k = hidden 8 ks + 4 (l / 32) + j); rows >= C are zero
-        const v4s a = *reinterpret_cast<const v4s*>(wrow + 8 * ks);
-        float x[4];
+      for (int s2 = 0; s2 < 4; ++s2) {
+        // A = W2 (i = class l32 + 32 cb, k = hidden 8 ks + 4 (l / 32) + j, ks = 2 s2, 2 s2 + 1);
+        // rows >= C are zero
+        const v8s a = *reinterpret_cast<const v8s*>(wrow + 16 * s2);
+        v4s hi[2], lo[2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = H[ks >> 2][4 * (ks & 3) + j];
-        v4s hi, lo;
-        split4(x, hi, lo);
-        Lg[cb] = mfma(a, hi, Lg[cb]);
-        Lg[cb] = mfma(a, lo, Lg[cb]);
+        for (int u = 0; u < 2; ++u) {
+          const int ks = 2 * s2 + u;
+          float x[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) x[j] = H[ks >> 2][4 * (ks & 3) + j];
+          split4(x, hi[u], lo[u]);
+        }
+        Lg[cb] = mfma2(a, hi[0], hi[1], Lg[cb]);
+        Lg[cb] = mfma2(a, lo[0], lo[1], Lg[cb]);
       }
     }
     // softmax over the pixel's classes: this lane's 32, then the partner lane's
@@ -795,7 +836,7 @@ __global__ __launch_bounds__(256, 1) void k_head_loss(const gs_item* __restrict_
                                                       float* __restrict__ loss_slots, float* __restrict__ count_slots,
                                                       float* __restrict__ gcolor, float* __restrict__ partial) {
   __shared__ HeadLds L;
-  __shared__ uint16_t w2r[kHid * kWtStride];   // W2 [class][hidden], rows >= C zero
+  __shared__ __align__(16) uint16_t w2r[kHid * kWtStride];   // W2 [class][kperm(hidden)], rows >= C zero
   __shared__ ChunkStage SA[4];
   __shared__ ChunkStage SB[4];
   const int lane = threadIdx.x & 63;
@@ -803,7 +844,7 @@ __global__ __launch_bounds__(256, 1) void k_head_loss(const gs_item* __restrict_
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int i = threadIdx.x; i < kHid * kHid; i += 256) {
     const int c = i / kHid, h = i % kHid;
-    w2r[c * kWtStride + h] = c < C ? W2[c * kHid + h] : (uint16_t)0;
+    w2r[c * kWtStride + kperm(h)] = c < C ? W2[c * kHid + h] : (uint16_t)0;
   }
   HeadAcc acc;
   v4s w1a[2][2];
