@@ -347,23 +347,64 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const Key* __re
   }
 }
 
-__global__ void k_visible_flags(const int32_t* __restrict__ radius, int64_t E, uint32_t* __restrict__ flags) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < E) flags[e] = radius[e] > 0 ? 1u : 0u;
+// Compaction of the visible entries (radius > 0) in entry order: per block of kCpTile
+// entries (kCpItems consecutive ones per thread) a count, then, after the counts' scan,
+// each block writes its visible entries from its first slot with the in-block prefix.
+constexpr int kCpItems = 16;
+constexpr int kCpTile = 256 * kCpItems;
+
+__device__ __forceinline__ void load_radii(const int32_t* __restrict__ radius, int64_t E, int64_t base,
+                                           int32_t (&r)[kCpItems]) {
+  if (base + kCpItems <= E && (reinterpret_cast<uintptr_t>(radius + base) & 15) == 0) {
+#pragma unroll
+    for (int k = 0; k < kCpItems; k += 4) {
+      const int4 q = *reinterpret_cast<const int4*>(radius + base + k);
+      r[k] = q.x; r[k + 1] = q.y; r[k + 2] = q.z; r[k + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kCpItems; ++k) r[k] = base + k < E ? radius[base + k] : 0;
+  }
 }
 
-// Visible entry e = item * n + g gets the depth-sort key (item << 32) | bits(depth).
-__global__ void k_compact(const int32_t* __restrict__ radius, const float* __restrict__ depth,
-                          const uint32_t* __restrict__ pos, int64_t E, int64_t n, uint64_t* __restrict__ keys,
-                          uint32_t* __restrict__ vals) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E || radius[e] <= 0) return;
-  const uint32_t p = pos[e];
-  const uint64_t item = (uint64_t)(e / n);
-  // a visible entry's depth is above z_near > 0, so its sign bit is 0 (the mask only keeps
-  // an invalid negative depth from reaching the item bits)
-  keys[p] = (item << 31) | (uint64_t)(__float_as_uint(depth[e]) & 0x7fffffffu);
-  vals[p] = (uint32_t)e;
+__global__ __launch_bounds__(256) void k_vis_count(const int32_t* __restrict__ radius, int64_t E,
+                                                   uint32_t* __restrict__ counts) {
+  const int64_t base = (int64_t)blockIdx.x * kCpTile + (int64_t)threadIdx.x * kCpItems;
+  int32_t r[kCpItems];
+  load_radii(radius, E, base, r);
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kCpItems; ++k) c += r[k] > 0 ? 1u : 0u;
+  __shared__ uint32_t sh[4];
+  uint32_t total;
+  block_exclusive_scan(c, total, sh);
+  if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+// Visible entry e = item * n + g gets the depth-sort key (item << 31) | bits(depth).
+__global__ __launch_bounds__(256) void k_compact(const int32_t* __restrict__ radius, const float* __restrict__ depth,
+                                                 int64_t E, int64_t n, const uint32_t* __restrict__ offs,
+                                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int64_t base = (int64_t)blockIdx.x * kCpTile + (int64_t)threadIdx.x * kCpItems;
+  int32_t r[kCpItems];
+  load_radii(radius, E, base, r);
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kCpItems; ++k) c += r[k] > 0 ? 1u : 0u;
+  __shared__ uint32_t sh[4];
+  uint32_t total;
+  uint32_t p = offs[blockIdx.x] + block_exclusive_scan(c, total, sh);
+#pragma unroll
+  for (int k = 0; k < kCpItems; ++k) {
+    if (r[k] <= 0) continue;
+    const int64_t e = base + k;
+    const uint64_t item = (uint64_t)(e / n);
+    // a visible entry's depth is above z_near > 0, so its sign bit is 0 (the mask only keeps
+    // an invalid negative depth from reaching the item bits)
+    keys[p] = (item << 31) | (uint64_t)(__float_as_uint(depth[e]) & 0x7fffffffu);
+    vals[p] = (uint32_t)e;
+    ++p;
+  }
 }
 
 __global__ void k_touched(gs_config cfg, const uint32_t* __restrict__ svals, const uint64_t* count_dev,
@@ -471,7 +512,7 @@ __global__ void k_full_keys(const uint32_t* __restrict__ tkeys, const uint32_t* 
 // Host side.
 // ---------------------------------------------------------------------------
 struct SortWs {
-  uint32_t* flags;     // [E]   visibility flags, then compaction positions
+  uint32_t* flags;     // [E]   per-block visible counts, then the blocks' first slots
   uint32_t* partial;   // [max(E, cap, hist) / 4096 + 2]
   uint64_t* vkeys[2];  // [E]
   uint32_t* vvals[2];  // [E]
@@ -610,12 +651,14 @@ int launch_bin_sort(const gs_config& cfg, const gs_projected& proj, const gs_ite
   uint64_t* d_total = w.counters + 1;
   uint64_t* d_live = w.counters + 2;
   const unsigned eb = (unsigned)std::max<int64_t>(1, ceil_div(E, 256));
-  // 1. compaction of the visible entries
-  hipLaunchKernelGGL(k_visible_flags, dim3(eb), dim3(256), 0, s, proj.radius, E, w.flags);
-  int st = device_scan(w.flags, w.flags, nullptr, E, E, w.partial, n_vis, s);
+  // 1. compaction of the visible entries: block counts (into the flags buffer), their scan
+  // (the total is the visible count), the blocks' ordered writes
+  const int64_t nblk_c = std::max<int64_t>(1, ceil_div(E, kCpTile));
+  hipLaunchKernelGGL(k_vis_count, dim3((unsigned)nblk_c), dim3(256), 0, s, proj.radius, E, w.flags);
+  int st = device_scan(w.flags, w.flags, nullptr, nblk_c, nblk_c, w.partial, n_vis, s);
   if (st) return st;
-  hipLaunchKernelGGL(k_compact, dim3(eb), dim3(256), 0, s, proj.radius, proj.depth, w.flags, E, n, w.vkeys[0],
-                     w.vvals[0]);
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)nblk_c), dim3(256), 0, s, proj.radius, proj.depth, E, n, w.flags,
+                     w.vkeys[0], w.vvals[0]);
   // 2. stable sort of the visible entries by (item, depth)
   int fin = 0;
   st = radix_sort<uint64_t>(w.vkeys[0], w.vkeys[1], w.vvals[0], w.vvals[1], n_vis, E,
