@@ -381,9 +381,14 @@ __global__ __launch_bounds__(256) void k_vis_count(const int32_t* __restrict__ r
   if (threadIdx.x == 0) counts[blockIdx.x] = total;
 }
 
-// Visible entry e = item * n + g gets the depth-sort key (item << 31) | bits(depth).
-__global__ __launch_bounds__(256) void k_compact(const int32_t* __restrict__ radius, const float* __restrict__ depth,
-                                                 int64_t E, int64_t n, const uint32_t* __restrict__ offs,
+// Visible entry e = item * n + g gets the depth-sort key (item << 31) | bits(depth), the low
+// kb bits the sort orders by; with cnt_shift > 0 the entry's tile count rides in the bits
+// from cnt_shift up (never sorted on, carried with the key), so that the duplication's
+// offsets come from the sorted keys in order instead of a gather of every record.
+__global__ __launch_bounds__(256) void k_compact(gs_config cfg, const int32_t* __restrict__ radius,
+                                                 const float* __restrict__ depth, const float* __restrict__ rec,
+                                                 const gs_item* __restrict__ items, int64_t E, int64_t n,
+                                                 int cnt_shift, const uint32_t* __restrict__ offs,
                                                  uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   const int64_t base = (int64_t)blockIdx.x * kCpTile + (int64_t)threadIdx.x * kCpItems;
   int32_t r[kCpItems];
@@ -401,10 +406,25 @@ __global__ __launch_bounds__(256) void k_compact(const int32_t* __restrict__ rad
     const uint64_t item = (uint64_t)(e / n);
     // a visible entry's depth is above z_near > 0, so its sign bit is 0 (the mask only keeps
     // an invalid negative depth from reaching the item bits)
-    keys[p] = (item << 31) | (uint64_t)(__float_as_uint(depth[e]) & 0x7fffffffu);
+    uint64_t key = (item << 31) | (uint64_t)(__float_as_uint(depth[e]) & 0x7fffffffu);
+    if (cnt_shift > 0) {
+      const gs_item it = items[item];
+      const Rect R = tile_rect(cfg, it.tiles_x, it.tiles_y, *reinterpret_cast<const float4*>(rec + (int64_t)kRecFloats * e),
+                               r[k]);
+      key |= (uint64_t)((R.x1 - R.x0) * (R.y1 - R.y0)) << cnt_shift;
+    }
+    keys[p] = key;
     vals[p] = (uint32_t)e;
     ++p;
   }
+}
+
+// Tile counts of the sorted entries from the count carried in their keys.
+__global__ void k_touched_keys(const uint64_t* __restrict__ skeys, const uint64_t* count_dev, int cnt_shift,
+                               uint32_t* __restrict__ touched) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= (int64_t)*count_dev) return;
+  touched[j] = (uint32_t)(skeys[j] >> cnt_shift);
 }
 
 __global__ void k_touched(gs_config cfg, const uint32_t* __restrict__ svals, const uint64_t* count_dev,
@@ -629,8 +649,13 @@ int radix_sort(Key* k0, Key* k1, uint32_t* v0, uint32_t* v1, const uint64_t* cou
   return GS_OK;
 }
 
-// Number of passes radix_sort takes for `bits`-bit keys.
+// Number of passes radix_sort takes for `bits`-bit keys, and the key bits they examine
+// (passes x digit width, at least `bits`).
 int radix_passes(int bits) { return std::max(1, (bits + kDigitMax - 1) / kDigitMax); }
+int radix_covered_bits(int bits) {
+  const int passes = radix_passes(bits);
+  return passes * std::max(8, (bits + passes - 1) / passes);
+}
 
 }  // namespace
 
@@ -653,21 +678,28 @@ int launch_bin_sort(const gs_config& cfg, const gs_projected& proj, const gs_ite
   const unsigned eb = (unsigned)std::max<int64_t>(1, ceil_div(E, 256));
   // 1. compaction of the visible entries: block counts (into the flags buffer), their scan
   // (the total is the visible count), the blocks' ordered writes
+  // the sort key's bits; an entry's tile count (at most the tiles of all items) rides in the
+  // top bits when they lie above every bit the radix passes examine
+  const int kbits = 31 + bits_for((uint64_t)n_items);
+  const int cbits = bits_for((uint64_t)n_tiles + 1);
+  const int cnt_shift = 64 - cbits >= radix_covered_bits(kbits) ? 64 - cbits : 0;
   const int64_t nblk_c = std::max<int64_t>(1, ceil_div(E, kCpTile));
   hipLaunchKernelGGL(k_vis_count, dim3((unsigned)nblk_c), dim3(256), 0, s, proj.radius, E, w.flags);
   int st = device_scan(w.flags, w.flags, nullptr, nblk_c, nblk_c, w.partial, n_vis, s);
   if (st) return st;
-  hipLaunchKernelGGL(k_compact, dim3((unsigned)nblk_c), dim3(256), 0, s, proj.radius, proj.depth, E, n, w.flags,
-                     w.vkeys[0], w.vvals[0]);
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)nblk_c), dim3(256), 0, s, cfg, proj.radius, proj.depth, proj.rec, items,
+                     E, n, cnt_shift, w.flags, w.vkeys[0], w.vvals[0]);
   // 2. stable sort of the visible entries by (item, depth)
   int fin = 0;
-  st = radix_sort<uint64_t>(w.vkeys[0], w.vkeys[1], w.vvals[0], w.vvals[1], n_vis, E,
-                            31 + bits_for((uint64_t)n_items), w, s, &fin);
+  st = radix_sort<uint64_t>(w.vkeys[0], w.vkeys[1], w.vvals[0], w.vvals[1], n_vis, E, kbits, w, s, &fin);
   if (st) return st;
   const uint32_t* svals = w.vvals[fin];
   // 3. duplicates in depth order
-  hipLaunchKernelGGL(k_touched, dim3(eb), dim3(256), 0, s, cfg, svals, n_vis, proj.rec, proj.radius, items, n,
-                     w.touched);
+  if (cnt_shift > 0)
+    hipLaunchKernelGGL(k_touched_keys, dim3(eb), dim3(256), 0, s, w.vkeys[fin], n_vis, cnt_shift, w.touched);
+  else
+    hipLaunchKernelGGL(k_touched, dim3(eb), dim3(256), 0, s, cfg, svals, n_vis, proj.rec, proj.radius, items, n,
+                       w.touched);
   st = device_scan(w.touched, w.touched, n_vis, 0, E, w.partial, d_total, s);
   if (st) return st;
   hipLaunchKernelGGL(k_dup_count, dim3(1), dim3(1), 0, s, d_total, cap, d_live, n_dup_dev, status_dev);
