@@ -83,7 +83,11 @@ def test_graph_replays_match_eager(variant, fwd_chunk, ssim_lambda, sh_degree, s
         # or un-cleared buffer in the graph would show as an O(1) error
         for k in ref:
             if k.startswith("g_"):
-                rel_check(got[k].cpu().numpy(), ref[k].cpu().numpy(), 1e-4, name=f"{k} rep {rep}")
+                # a view's six pose components each sum every Gaussian's share (block sums added
+                # atomically); one component can be a hundredth of the others, so the pose is
+                # measured against a tenth of its rms rather than a hundredth
+                rel_check(got[k].cpu().numpy(), ref[k].cpu().numpy(), 1e-4, name=f"{k} rep {rep}",
+                          floor=0.1 if k == "g_pose" else 0.01)
 
 
 def test_eager_steps_are_deterministic_where_no_atomics():
