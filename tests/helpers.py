@@ -28,6 +28,8 @@ def rel_check(got, ref, tol, mask=None, floor=0.01, name="", scale=None):
     ratio = np.abs(g - r) / (tol * scale)
     worst = float(ratio.max()) if ratio.size else 0.0
     l2 = float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300))
+    if worst > 0.5:   # a near miss is worth seeing in the log even when it passes
+        print(f"[rel_check] {name}: worst {worst:.3g} of the tolerance, l2 {l2:.3g}", flush=True)
     if worst > 1.0:
         idx = np.argsort(-ratio)[:5]
         full = np.flatnonzero(keep)[idx]
