@@ -138,3 +138,27 @@ def pixel_term_magnitude(ocfg, sc, views, gimg, K, tiles, i, field, comp=(), sem
                 total += abs(oracle.backward(ocfg, sub, views, g1, sem=fsub, tile_mask=m1)[field][(isub,) + tuple(comp)])
                 g1[sl] = 0.0
     return total
+
+
+def check_with_pixel_terms(got, ref, tol, name, ocfg, sc, views, gimg, K, sem=None, tiles=None, mask=None,
+                           floor=0.01, scale=None, max_entries=4, pre=None):
+    """rel_check, except that an entry beyond the limit (a sum whose pixel terms cancel) is
+    held to tol times the sum of its pixel terms' magnitudes (pixel_term_magnitude); at most
+    max_entries such entries. tiles: the tiles whose pixels carry upstream gradient (all
+    of the views' tiles if None). Returns the oracle projection used (for reuse)."""
+    import oracle
+    g = np.asarray(got)
+    over, err = over_limit(g, ref, tol, mask=mask, floor=floor, scale=scale)
+    assert len(over) <= max_entries, (name, len(over))
+    if tiles is None:
+        tiles = range(sum(it["ntx"] * it["nty"] for it in oracle.items(views, ocfg.tile_w, ocfg.tile_h)))
+    for flat in over:
+        ix = np.unravel_index(flat, g.shape)
+        pre = oracle.preprocess(ocfg, sc, views) if pre is None else pre
+        pm = pixel_term_magnitude(ocfg, sc, views, gimg, K, tiles, int(ix[0]), name, ix[1:], sem=sem, pre=pre)
+        print(f"[pixel terms] {name}{tuple(int(c) for c in ix)}: |d| {err[flat]:.3g}, limit {tol * pm:.3g}", flush=True)
+        assert err[flat] <= tol * pm, (name, ix, err[flat], pm)
+    m = np.zeros(g.size, bool) if mask is None else np.asarray(mask, bool).reshape(-1).copy()
+    m[over] = True
+    rel_check(g, ref, tol, mask=m, floor=floor, scale=scale, name=name)
+    return pre

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2412_01217_amd import scenes
-from tests.helpers import flagged, pixel_mask_to_channels, rel_check, targets_from_random
+from tests.helpers import check_with_pixel_terms, flagged, pixel_mask_to_channels, rel_check, targets_from_random
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -152,8 +152,11 @@ def test_learned_backward_matches_oracle(variant, C):
     rel_check(grads["emb"].cpu().numpy(), ref["sem"], 1e-3, scale=mag["sem"], name="emb")
     # colour gradients are linear in the upstream gradient: sum_p w |g_p| bounds their terms
     rel_check(grads["rgb"].cpu().numpy(), ref["rgb"], 1e-3, scale=mag["rgb"], name="rgb")
+    # an entry whose pixel terms cancel is held to 1e-3 of their magnitudes (at most 4)
+    pre = None
     for name in ("mean", "log_scale", "quat", "opacity"):
-        rel_check(grads[name].cpu().numpy(), ref[name], 1e-3, name=name)
+        pre = check_with_pixel_terms(grads[name].cpu().numpy(), ref[name], 1e-3, name, oracle.Config(), sc, views,
+                                     gimg, 20, sem=emb, pre=pre)
     habs = oracle.head_backward(np.abs(E), np.abs(W1), np.abs(b1), np.abs(W2), np.abs(dlog))
     for k, kk in (("head_W1", "W1"), ("head_b1", "b1"), ("head_W2", "W2"), ("head_b2", "b2")):
         rel_check(grads[k].cpu().numpy(), hb[kk], 1e-3, scale=habs[kk], name=k)
