@@ -398,41 +398,45 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
         const int cnt = (int)min((uint32_t)kB, b0 - b);
         if (b + kB < b0)
           st.fetch(vals, b + kB, (int)min((uint32_t)kB, b0 - b - kB), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
-        // front-to-back recurrence, branch-free; only T carries from one Gaussian to the next
+        // front-to-back recurrence, branch-free; only T carries from one Gaussian to the next.
+        // A wave whose pixels have all stopped skips it (and the products), leaving its
+        // SIMD's issue slots to the other waves there while the block's other waves go on.
         bool took = false;
         const uint32_t base = b - c.start;
-        // records of the next four Gaussians are read while the current four are used
-        LRec R[4];
+        if (__ballot(!done) != 0ull) {
+          // records of the next four Gaussians are read while the current four are used
+          LRec R[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) R[e] = load_rec(s_rec, e);
+          for (int e = 0; e < 4; ++e) R[e] = load_rec(s_rec, e);
 #pragma unroll
-        for (int q4 = 0; q4 < kB; q4 += 4) {
-          LRec N[4];
-          if (q4 + 4 < kB)
+          for (int q4 = 0; q4 < kB; q4 += 4) {
+            LRec N[4];
+            if (q4 + 4 < kB)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) N[e] = load_rec(s_rec, q4 + 4 + e);
-          __builtin_amdgcn_sched_barrier(0);
-          float wq[4];
+              for (int e = 0; e < 4; ++e) N[e] = load_rec(s_rec, q4 + 4 + e);
+            __builtin_amdgcn_sched_barrier(0);
+            float wq[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int q = q4 + e;
-            float dx, dy, t;
-            const float araw = R[e].c.y * __builtin_amdgcn_exp2f(local_power2(lx, ly, R[e], dx, dy, t));
-            const bool ok = (q < cnt) & !done & (araw >= amin);
-            const float w = fminf(amax, araw) * T;
-            const float Tn = T - w;
-            const bool stop = ok & (Tn < tmin);
-            const bool take = ok & !stop;
-            wq[e] = take ? w : 0.0f;
-            T = take ? Tn : T;
-            done = done | stop;
-            last = take ? base + q + 1 : last;
-            took |= take;
+            for (int e = 0; e < 4; ++e) {
+              const int q = q4 + e;
+              float dx, dy, t;
+              const float araw = R[e].c.y * __builtin_amdgcn_exp2f(local_power2(lx, ly, R[e], dx, dy, t));
+              const bool ok = (q < cnt) & !done & (araw >= amin);
+              const float w = fminf(amax, araw) * T;
+              const float Tn = T - w;
+              const bool stop = ok & (Tn < tmin);
+              const bool take = ok & !stop;
+              wq[e] = take ? w : 0.0f;
+              T = take ? Tn : T;
+              done = done | stop;
+              last = take ? base + q + 1 : last;
+              took |= take;
+            }
+            *reinterpret_cast<float4*>(W + lane * kWs + q4) = make_float4(wq[0], wq[1], wq[2], wq[3]);
+            if (q4 + 4 < kB)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) R[e] = N[e];
           }
-          *reinterpret_cast<float4*>(W + lane * kWs + q4) = make_float4(wq[0], wq[1], wq[2], wq[3]);
-          if (q4 + 4 < kB)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) R[e] = N[e];
         }
         wave_sync();
         if (__ballot(took) == 0ull) continue;
