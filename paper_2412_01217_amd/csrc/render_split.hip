@@ -92,6 +92,23 @@ __device__ __forceinline__ void split8(const float* x, v8bf& hi, v8bf& lo) {
   lo = __builtin_bit_cast(v8bf, make_uint4(l[0], l[1], l[2], l[3]));
 }
 
+// Splits eight floats into three bfloat16 parts, x = hi + mid + lo to about 2^-24 of x
+// (each part the rounding of what the previous ones leave, every remainder exact).
+__device__ __forceinline__ void split8x3(const float* x, v8bf& hi, v8bf& mid, v8bf& lo) {
+  split8(x, hi, mid);
+  const uint4 h = __builtin_bit_cast(uint4, hi), m = __builtin_bit_cast(uint4, mid);
+  const uint32_t hw[4] = {h.x, h.y, h.z, h.w}, mw[4] = {m.x, m.y, m.z, m.w};
+  uint32_t l[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float r0 = (x[2 * k] - __uint_as_float(hw[k] << 16)) - __uint_as_float(mw[k] << 16);
+    const float r1 = (x[2 * k + 1] - __uint_as_float(hw[k] & 0xffff0000u)) - __uint_as_float(mw[k] & 0xffff0000u);
+    l[k] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){r0, r1}, bf2));
+  }
+  lo = __builtin_bit_cast(v8bf, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
+
 // The render record as the compositing loops read it from LDS, 8 floats per Gaussian:
 //   mx, my   mean2d relative to the tile's middle (the centre of its pixel (tw / 2, th / 2)),
 //            so that a pixel's offset is its integer position relative to that pixel minus
@@ -137,6 +154,16 @@ __device__ __forceinline__ v4f mma3(v8bf ah, v8bf al, v8bf bh, v8bf bl, v4f c) {
   c = mma(ah, bh, c);
   c = mma(ah, bl, c);
   c = mma(al, bh, c);
+  return c;
+}
+// Six products of three-part operands: a b to about 2^-24 relative per product term.
+__device__ __forceinline__ v4f mma6(const v8bf (&a)[3], const v8bf (&b)[3], v4f c) {
+  c = mma(a[0], b[0], c);
+  c = mma(a[0], b[1], c);
+  c = mma(a[1], b[0], c);
+  c = mma(a[0], b[2], c);
+  c = mma(a[1], b[1], c);
+  c = mma(a[2], b[0], c);
   return c;
 }
 __device__ __forceinline__ v4f zero4() { return (v4f){0.0f, 0.0f, 0.0f, 0.0f}; }
@@ -791,8 +818,13 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
       if (pu >= c.W || pv >= c.H || ch >= Kr) return 0.0f;
       return gcolor[c.pixel_base * Kr + (int64_t)pv * c.W + pu + ch * c.HW];
     };
-    // G^T as B of GF (k = channel 4 ks + g4, j = pixel 16 pb + l16)
-    float g1[4][KP / 4];
+    // G^T as B of GF (k = channel 4 ks + g4, j = pixel 16 pb + l16); with 32 padded channels
+    // the main pass takes GF on bfloat16 matrix cores instead, each operand in three parts
+    // (single-precision products at a sixth of the 16x16x4 products' matrix-core time):
+    // g3[part][pb], B of 16x16x32 (k = channel 8 g4 + e, j = pixel 16 pb + l16)
+    constexpr bool kGF3 = !SUMMARY && KP == 32;
+    float g1[4][kGF3 ? 1 : KP / 4];
+    v8bf g3[kGF3 ? 4 : 1][3];
     if constexpr (SUMMARY) {
 #pragma unroll
       for (int pb = 0; pb < 4; ++pb)
@@ -830,10 +862,20 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
 #pragma unroll
         for (int j = 0; j < 32; ++j) stg[j * kGst + lane] = gl[j];
         wave_sync();
+        if constexpr (kGF3) {
 #pragma unroll
-        for (int ks = 8 * h; ks < 8 * h + 8; ++ks)
+          for (int pb = 0; pb < 4; ++pb) {
+            float x[8];
 #pragma unroll
-          for (int pb = 0; pb < 4; ++pb) g1[pb][ks] = stg[(4 * ks + g4 - 32 * h) * kGst + 16 * pb + l16];
+            for (int e = 0; e < 8; ++e) x[e] = stg[(8 * g4 + e) * kGst + 16 * pb + l16];
+            split8x3(x, g3[pb][0], g3[pb][1], g3[pb][2]);
+          }
+        } else {
+#pragma unroll
+          for (int ks = 8 * h; ks < 8 * h + 8; ++ks)
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) g1[pb][ks] = stg[(4 * ks + g4 - 32 * h) * kGst + 16 * pb + l16];
+        }
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
@@ -1011,12 +1053,23 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
               v4f gfa[4];
 #pragma unroll
               for (int pb = 0; pb < 4; ++pb) gfa[pb] = zero4();
+              if constexpr (kGF3) {
+                // A = F (i = Gaussian 16 bq + l16, k = channel 8 g4 + e)
+                const float* src = s_f + (16 * bq + l16) * FST + 8 * g4;
+                const float4 f0 = *reinterpret_cast<const float4*>(src), f1 = *reinterpret_cast<const float4*>(src + 4);
+                const float x[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+                v8bf fa[3];
+                split8x3(x, fa[0], fa[1], fa[2]);
 #pragma unroll
-              for (int ks = 0; ks < KP / 4; ++ks) {
-                const float a = s_f[(16 * bq + l16) * FST + 4 * ks + g4];
+                for (int pb = 0; pb < 4; ++pb) gfa[pb] = mma6(fa, g3[pb], gfa[pb]);
+              } else {
 #pragma unroll
-                for (int pb = 0; pb < 4; ++pb)
-                  gfa[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g1[pb][ks], gfa[pb], 0, 0, 0);
+                for (int ks = 0; ks < KP / 4; ++ks) {
+                  const float a = s_f[(16 * bq + l16) * FST + 4 * ks + g4];
+#pragma unroll
+                  for (int pb = 0; pb < 4; ++pb)
+                    gfa[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g1[pb][ks], gfa[pb], 0, 0, 0);
+                }
               }
 #pragma unroll
               for (int pb = 0; pb < 4; ++pb)
