@@ -176,21 +176,35 @@ __device__ __forceinline__ void wave_sync() {
 
 // Batch staging, double-buffered through registers: thread t stages Gaussian q = t / 8
 // of the batch, channels [(t % 8) CPT, +CPT) of its features and, for t % 8 < 2, half of
-// its 8-float record.
+// its 8-float record. The batch's Gaussian ids are loaded a batch earlier than its data
+// (load_ids, then fetch_data), so that the gathers that depend on them issue without
+// waiting for a load.
 template <int NS>
 struct SStage {
   static constexpr int CPT = SShape<NS>::CPT;
   float4 r;
-  uint32_t gid;
+  uint32_t gid, gpre;
   float f[CPT];
 
+  __device__ __forceinline__ void load_ids(const uint32_t* __restrict__ vals, uint32_t b, int cnt) {
+    const int q = threadIdx.x >> 3;
+    gpre = q < cnt ? vals[b + q] : 0u;
+  }
   __device__ __forceinline__ void fetch(const uint32_t* __restrict__ vals, uint32_t b, int cnt, int item, int64_t n,
                                         const float* __restrict__ rec, const float* __restrict__ depth,
                                         const float* __restrict__ rgb, const float* __restrict__ sem,
                                         const uint16_t* __restrict__ emb, int n_sem, int64_t foff) {
+    load_ids(vals, b, cnt);
+    fetch_data(cnt, item, n, rec, depth, rgb, sem, emb, n_sem, foff);
+  }
+  // gathers the data of the batch whose ids load_ids loaded (cnt Gaussians)
+  __device__ __forceinline__ void fetch_data(int cnt, int item, int64_t n, const float* __restrict__ rec,
+                                             const float* __restrict__ depth, const float* __restrict__ rgb,
+                                             const float* __restrict__ sem, const uint16_t* __restrict__ emb,
+                                             int n_sem, int64_t foff) {
     const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
     const bool live = q < cnt;
-    const uint32_t g = live ? vals[b + q] : 0u;
+    const uint32_t g = gpre;
     gid = g;
     const int64_t e = (int64_t)item * n + g;
     r = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -416,15 +430,20 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
       const uint32_t a0 = split ? c.start + sg * kSeg : c.start;
       const uint32_t b0 = split ? min(c.end, a0 + kSeg) : c.end;
       const bool active = !done;
-      if (a0 < b0) st.fetch(vals, a0, (int)min((uint32_t)kB, b0 - a0), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
+      if (a0 < b0) {
+        st.fetch(vals, a0, (int)min((uint32_t)kB, b0 - a0), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
+        if (a0 + kB < b0) st.load_ids(vals, a0 + kB, (int)min((uint32_t)kB, b0 - a0 - kB));
+      }
       for (uint32_t b = a0; b < b0; b += kB) {
         // every wave is past the previous batch's LDS reads; stop once every pixel has
         if (__syncthreads_count(!done) == 0) break;
         st.commit_cols(s_rec, s_f, ox, oy);
         __syncthreads();
         const int cnt = (int)min((uint32_t)kB, b0 - b);
-        if (b + kB < b0)
-          st.fetch(vals, b + kB, (int)min((uint32_t)kB, b0 - b - kB), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
+        if (b + kB < b0) {
+          st.fetch_data((int)min((uint32_t)kB, b0 - b - kB), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
+          if (b + 2 * kB < b0) st.load_ids(vals, b + 2 * kB, (int)min((uint32_t)kB, b0 - b - 2 * kB));
+        }
         // front-to-back recurrence, branch-free; only T carries from one Gaussian to the next.
         // A wave whose pixels have all stopped skips it (and the products), leaving its
         // SIMD's issue slots to the other waves there while the block's other waves go on.
@@ -912,12 +931,14 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
     }
 
     SStage<NS> st;
-    if (b0 > a0) {
-      const int f0 = SUMMARY ? a0 : max(a0, b0 - kB);
-      const int f1 = SUMMARY ? min(b0, a0 + kB) : b0;
-      st.fetch(vals, c.start + f0, f1 - f0, c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
-    }
     const int n_batches = (b0 - a0 + kB - 1) / kB;
+    // list range [lo, hi) of batch bi: the main pass from the back, the summary pass from the front
+    auto batch_lo = [&](int bi) { return SUMMARY ? a0 + bi * kB : max(a0, b0 - (bi + 1) * kB); };
+    auto batch_hi = [&](int bi) { return SUMMARY ? min(b0, a0 + (bi + 1) * kB) : b0 - bi * kB; };
+    if (n_batches > 0) {
+      st.fetch(vals, c.start + batch_lo(0), batch_hi(0) - batch_lo(0), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
+      if (n_batches > 1) st.load_ids(vals, c.start + batch_lo(1), batch_hi(1) - batch_lo(1));
+    }
     // one FP32 atomic per (Gaussian, channel) and (Gaussian, component) of a finished batch
     auto flush = [&](int fb, int fcnt) {
       const float* fdf = s_pool + kWsz + fb * kDsz;
@@ -973,9 +994,7 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
     };
     int prev_cnt = 0;
     for (int bi = 0; bi < n_batches; ++bi) {
-      // main pass: batches from the back; summary pass: from the front
-      const int lo = SUMMARY ? a0 + bi * kB : max(a0, b0 - (bi + 1) * kB);
-      const int hi = SUMMARY ? min(b0, lo + kB) : b0 - bi * kB;
+      const int lo = batch_lo(bi), hi = batch_hi(bi);
       const int cnt = hi - lo;
       const int buf = bi & 1;
       float* const s_df = s_pool + kWsz + buf * kDsz;
@@ -995,9 +1014,8 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
       // recurrence, whose register peak it would otherwise add to
       auto fetch_next = [&]() {
         if (bi + 1 < n_batches) {
-          const int nlo = SUMMARY ? hi : max(a0, lo - kB);
-          const int nhi = SUMMARY ? min(b0, hi + kB) : lo;
-          st.fetch(vals, c.start + nlo, nhi - nlo, c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
+          st.fetch_data(batch_hi(bi + 1) - batch_lo(bi + 1), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
+          if (bi + 2 < n_batches) st.load_ids(vals, c.start + batch_lo(bi + 2), batch_hi(bi + 2) - batch_lo(bi + 2));
         }
       };
       if constexpr (SUMMARY) fetch_next();
