@@ -107,6 +107,8 @@ bool cfg_ok(const gs_config* c) {
   if (!(c->sem_ssim_lambda >= 0.0f && c->sem_ssim_lambda <= 1.0f)) return false;
   if (c->isotropic < 0 || c->isotropic > 1) return false;
   if (c->view_features < 0 || c->view_features > 1) return false;
+  // segments of split lists: the forward's state is sized for 256-entry ones
+  if (c->seg_len != 0 && (c->seg_len < 256 || c->seg_len > (1 << 20) || c->seg_len % 32 != 0)) return false;
   return true;
 }
 
@@ -146,6 +148,7 @@ void gs_config_default(gs_config* c) {
   c->isotropic = 0;
   c->view_features = 0;
   c->sem_ssim_lambda = 0.0f;
+  c->seg_len = 0;
 }
 
 const char* gs_status_string(int s) {

@@ -242,11 +242,13 @@ struct SStage {
 };
 
 // ------------------------------------------------------------------------- forward
-// Long tile lists are cut into segments of kSeg list positions. The reverse pass takes
-// every segment as a work item of its own; the forward walks up to `chunk` consecutive
-// segments of a list in one work item (one sequential transmittance chain), so that
-// only lists longer than a chunk need a starting transmittance from a pre-pass.
-constexpr int kSeg = 256;
+// Long tile lists are cut into segments of seg_len(cfg) list positions. The reverse pass
+// takes every segment as a work item of its own; the forward walks up to `chunk`
+// consecutive segments of a list in one work item (one sequential transmittance chain),
+// so that only lists longer than a chunk need a starting transmittance from a pre-pass.
+// Workspaces are sized for the shortest segments, kSegMin.
+constexpr int kSegMin = 256;
+__host__ __device__ inline int seg_len(const gs_config& cfg) { return cfg.seg_len > 0 ? cfg.seg_len : kSegMin; }
 
 // Segments per forward work item (cfg.fwd_chunk; 0 = the whole list).
 __host__ __device__ inline int fwd_chunk(const gs_config& cfg) { return cfg.fwd_chunk > 0 ? cfg.fwd_chunk : 1 << 16; }
@@ -274,11 +276,11 @@ constexpr uint32_t kInfoActive = 1u << 30, kInfoStopped = 1u << 31, kInfoLast = 
 
 // Segments per tile: every tile is at least one item (it writes the tile's output).
 __global__ __launch_bounds__(256) void k_fseg_count(const uint32_t* __restrict__ ranges, int n_tiles, int order,
-                                                    uint32_t* __restrict__ cnt_ord) {
+                                                    uint32_t seg, uint32_t* __restrict__ cnt_ord) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tiles) return;
   const uint32_t len = ranges[2 * (int64_t)t + 1] - ranges[2 * (int64_t)t];
-  cnt_ord[order ? t : n_tiles - 1 - t] = len <= (uint32_t)kSeg ? 1u : (len + kSeg - 1) / kSeg;
+  cnt_ord[order ? t : n_tiles - 1 - t] = len <= seg ? 1u : (len + seg - 1) / seg;
 }
 
 // Transmittance pre-pass: P of every chunk of a list but the last. Persistent blocks
@@ -310,8 +312,9 @@ __global__ __launch_bounds__(256) void k_fwd_trans(gs_config cfg, const float* _
     tile_pixel(c, tid, u, v);
     const bool inside = u < c.W && v < c.H;
     const float ox = (float)tile_mid_x(c) + 0.5f, oy = (float)tile_mid_y(c) + 0.5f;
-    const uint32_t a0 = c.start + seg * kSeg;
-    const uint32_t b0 = (uint32_t)min((int64_t)c.end, (int64_t)a0 + (int64_t)chunk * kSeg);
+    const int seglen = seg_len(cfg);
+    const uint32_t a0 = c.start + seg * seglen;
+    const uint32_t b0 = (uint32_t)min((int64_t)c.end, (int64_t)a0 + (int64_t)chunk * seglen);
     // thread t < 64 stages half (t % 2) of the record of Gaussian t / 2
     const int q = tid >> 1, part = tid & 1;
     auto fetch = [&](uint32_t b) -> float4 {
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
     const bool inside = u < c.W && v < c.H;
     const float ox = (float)tile_mid_x(c) + 0.5f, oy = (float)tile_mid_y(c) + 0.5f;
     const bool split = SEG && nseg > 1;
-    const int chunk = fwd_chunk(cfg);
+    const int chunk = fwd_chunk(cfg), seglen = seg_len(cfg);
     const int s_hi = split ? min(nseg, seg + chunk) : 1;   // segments [seg, s_hi) of this item
     const int64_t slot0 = (int64_t)wi - seg;                  // the tile's first slot
     v4f acc[CB][4];
@@ -427,8 +430,8 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
     uint32_t last = 0;
     SStage<NS> st;
     for (int sg = seg; sg < s_hi; ++sg) {
-      const uint32_t a0 = split ? c.start + sg * kSeg : c.start;
-      const uint32_t b0 = split ? min(c.end, a0 + kSeg) : c.end;
+      const uint32_t a0 = split ? c.start + sg * seglen : c.start;
+      const uint32_t b0 = split ? min(c.end, a0 + seglen) : c.end;
       const bool active = !done;
       if (a0 < b0) {
         st.fetch(vals, a0, (int)min((uint32_t)kB, b0 - a0), c.item, n, rec, depth, rgb, sem, emb, n_sem, foff);
@@ -519,7 +522,7 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
             }
         const int64_t o = sl * kTilePx + tid;
         fs.Te[o] = T;
-        const uint32_t lseg = last > (uint32_t)(sg * kSeg) ? last : 0u;
+        const uint32_t lseg = last > (uint32_t)(sg * seglen) ? last : 0u;
         fs.info[o] = lseg | (active ? kInfoActive : 0u) | ((active && done) ? kInfoStopped : 0u);
       }
     }
@@ -708,7 +711,7 @@ __constant__ float kGeoScale[6] = {-1.0f / kLog2e, -1.0f / kLog2e, -0.5f, -1.0f,
 __global__ __launch_bounds__(256) void k_seg_count(const gs_item* __restrict__ items, int n_items,
                                                    const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ ncin, int n_tiles, int order, int tws,
-                                                   const uint32_t* __restrict__ ftcnt,
+                                                   uint32_t seg, const uint32_t* __restrict__ ftcnt,
                                                    uint32_t* __restrict__ tile_lmax, uint32_t* __restrict__ cnt_ord) {
   __shared__ uint32_t s_m;
   const int tile = blockIdx.x;
@@ -726,8 +729,8 @@ __global__ __launch_bounds__(256) void k_seg_count(const gs_item* __restrict__ i
   if (threadIdx.x == 0) {
     const uint32_t m = s_m;
     tile_lmax[tile] = m;
-    const bool one = m <= (uint32_t)kSeg || (ftcnt && ftcnt[tile] < 2);
-    cnt_ord[order ? tile : n_tiles - 1 - tile] = m == 0 ? 0u : (one ? 1u : (m + kSeg - 1) / kSeg);
+    const bool one = m <= seg || (ftcnt && ftcnt[tile] < 2);
+    cnt_ord[order ? tile : n_tiles - 1 - tile] = m == 0 ? 0u : (one ? 1u : (m + seg - 1) / seg);
   }
 }
 
@@ -827,8 +830,9 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
     const uint32_t len = c.end - c.start;
     const uint32_t last = inside ? min(ncin[pix], len) : 0u;
     const int lmax = (int)tile_lmax[tile];
-    const int a0 = nseg == 1 ? 0 : seg * kSeg;
-    const int b0 = nseg == 1 ? lmax : min(lmax, a0 + kSeg);
+    const int seglen = seg_len(cfg);
+    const int a0 = nseg == 1 ? 0 : seg * seglen;
+    const int b0 = nseg == 1 ? lmax : min(lmax, a0 + seglen);
 
     // upstream gradient of a wave pixel (0..63) and channel, zero outside the image
     auto gval = [&](int wp, int ch) -> float {
@@ -1196,7 +1200,7 @@ struct SegWs {
 };
 
 size_t seg_layout(int n_tiles, int64_t cap, char* base, SegWs* w) {
-  const int64_t max_segs = (int64_t)n_tiles + ceil_div(cap, kSeg) + 1;
+  const int64_t max_segs = (int64_t)n_tiles + ceil_div(cap, kSegMin) + 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -1238,7 +1242,7 @@ struct FLayout {
 };
 
 size_t fstate_layout(int n_tiles, int64_t cap, int K, char* base, FLayout* w) {
-  const int64_t max_segs = (int64_t)n_tiles + ceil_div(cap, kSeg) + 1;
+  const int64_t max_segs = (int64_t)n_tiles + ceil_div(cap, kSegMin) + 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -1315,7 +1319,8 @@ int launch_fwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected
     return launch_status();
   }
   const unsigned tb = (unsigned)ceil_div(n_tiles, 256);
-  hipLaunchKernelGGL(k_fseg_count, dim3(tb), dim3(256), 0, s, ranges, n_tiles, cfg.tile_order, w.cnt);
+  hipLaunchKernelGGL(k_fseg_count, dim3(tb), dim3(256), 0, s, ranges, n_tiles, cfg.tile_order,
+                     (uint32_t)seg_len(cfg), w.cnt);
   int st = launch_status();
   st = st ? st : scan_u32(w.cnt, w.base, n_tiles, w.partial, w.total, s);
   if (st) return st;
@@ -1345,7 +1350,7 @@ int launch_bwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected
   // with the forward's saved state the segments start from it: no summary pass
   const FState fs = state_of(fwd, n_tiles, 4 + cfg.n_sem).fs;
   hipLaunchKernelGGL(k_seg_count, dim3(n_tiles), dim3(256), 0, s, items, n_items, ranges, fwd.n_contrib, n_tiles,
-                     cfg.tile_order, tile_shift(cfg), fs.tcnt, w.lmax, w.cnt);
+                     cfg.tile_order, tile_shift(cfg), (uint32_t)seg_len(cfg), fs.tcnt, w.lmax, w.cnt);
   int st = launch_status();
   st = st ? st : scan_u32(w.cnt, w.base, n_tiles, w.partial, w.total, s);
   if (st) return st;

@@ -91,8 +91,8 @@ def _sub_scene(sc, idx, emb):
     return s, emb[idx]
 
 
-@pytest.mark.parametrize("fwd_chunk", [0, 1])
-def test_large_sampled_tiles_forward_backward_and_differences(fwd_chunk):
+@pytest.mark.parametrize("fwd_chunk,seg_len", [(0, 0), (1, 0), (0, 4096)])
+def test_large_sampled_tiles_forward_backward_and_differences(fwd_chunk, seg_len):
     from paper_2412_01217_amd import autograd, raster
     sc32, views = scenes.config_large()
     rng = np.random.default_rng(7800 + fwd_chunk)
@@ -101,10 +101,11 @@ def test_large_sampled_tiles_forward_backward_and_differences(fwd_chunk):
     v0 = views[:1]
     its = oracle.items(v0)
     n_items0, P0, tiles0 = oracle.layout(v0)
-    print(f"[large] fwd_chunk {fwd_chunk}: 2M Gaussians, {len(views)} views; sample in view 0 ({P0} px)", flush=True)
+    print(f"[large] fwd_chunk {fwd_chunk}, seg_len {seg_len}: 2M Gaussians, {len(views)} views; sample in view 0 "
+          f"({P0} px)", flush=True)
 
     # GPU: the autograd.Function on the whole workload
-    cfg = raster.config(16, fwd_chunk=fwd_chunk)
+    cfg = raster.config(16, fwd_chunk=fwd_chunk, seg_len=seg_len)
     fr = raster.Frame(cfg, views)
     t = {k: torch.tensor(np.asarray(getattr(sc32, k)), device="cuda", requires_grad=True)
          for k in ("mean", "log_scale", "quat", "opacity", "rgb")}

@@ -44,13 +44,14 @@ CASES = {
 
 
 def _pipeline(sc, views, n_sem, variant=0, split=True, state_capacity=None, fwd_chunk=1, isotropic=False,
-              tile=(16, 16)):
-    """split: forward with its state (long lists in segments of fwd_chunk 256-entry pieces,
+              tile=(16, 16), seg_len=0):
+    """split: forward with its state (long lists in segments of fwd_chunk seg_len-entry pieces,
     0 = whole lists); state_capacity overrides the capacity the state is sized for;
-    isotropic: the primitive of eq. 1-3; tile: the screen tile (width, height)."""
+    isotropic: the primitive of eq. 1-3; tile: the screen tile (width, height); seg_len: list
+    entries per segment (0 = 256)."""
     raster = _raster()
     cfg = raster.config(n_sem, variant=variant, fwd_chunk=fwd_chunk, isotropic=int(isotropic), tile_w=tile[0],
-                        tile_h=tile[1])
+                        tile_h=tile[1], seg_len=seg_len)
     fr = raster.Frame(cfg, views)
     g = raster.to_device(sc)
     proj = raster.preprocess(cfg, g, fr)
@@ -236,9 +237,24 @@ def test_render_fwd_state_too_small():
     _check_render_bwd("room_long_lists", 3, True, fwd_chunk=0, state_capacity=0)
 
 
-def _check_render_fwd(sc, views, variant, split, fwd_chunk=1, state_capacity=None, isotropic=False, tile=(16, 16)):
+@pytest.mark.parametrize("seg_len,fwd_chunk", [(512, 1), (512, 0), (1024, 1), (1024, 2)])
+def test_render_parity_segment_lengths(seg_len, fwd_chunk):
+    """Longer segments of the split lists (the reverse pass's work items and the forward's
+    state points): forward and backward against the oracle on lists several segments long."""
+    sc, views = CASES["room_long_lists"]()
+    _, _, _, _, srt, _ = _pipeline(sc, views, sc.n_classes, 3, True, None, fwd_chunk, seg_len=seg_len)
+    lens = srt.ranges.view(-1, 2)[:, 1] - srt.ranges.view(-1, 2)[:, 0]
+    longest = int(lens.max().item())
+    print(f"[segments] seg_len {seg_len}: longest list {longest}", flush=True)
+    assert longest > 2 * seg_len   # lists of three segments and more
+    _check_render_fwd(sc, views, 3, True, fwd_chunk, seg_len=seg_len)
+    _check_render_bwd("room_long_lists", 3, True, fwd_chunk, seg_len=seg_len)
+
+
+def _check_render_fwd(sc, views, variant, split, fwd_chunk=1, state_capacity=None, isotropic=False, tile=(16, 16),
+                      seg_len=0):
     cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant, split, state_capacity, fwd_chunk,
-                                           isotropic, tile)
+                                           isotropic, tile, seg_len)
     ocfg = oracle.Config(isotropic=isotropic, tile_w=tile[0], tile_h=tile[1])
     ref = oracle.render(ocfg, sc, views)
     # sum_i w_i |f_i|: the magnitude a composited sum with mixed signs is measured against
@@ -340,10 +356,10 @@ def test_render_bwd_single_item_fallback(split):
 
 
 def _check_render_bwd(case, variant, split, fwd_chunk=1, small_workspace=False, state_capacity=None,
-                      isotropic=False, tile=(16, 16)):
+                      isotropic=False, tile=(16, 16), seg_len=0):
     sc, views = CASES[case]()
     cfg, fr, g, proj, srt, img = _pipeline(sc, views, sc.n_classes, variant, split, state_capacity, fwd_chunk,
-                                           isotropic, tile)
+                                           isotropic, tile, seg_len)
     ocfg = oracle.Config(isotropic=isotropic, tile_w=tile[0], tile_h=tile[1])
     raster = _raster()
     ws = None
