@@ -62,7 +62,7 @@ typedef struct gs_config {
                               matrix cores, 3 bfloat16 matrix cores with hi/lo split operands
                               (single-precision accurate to about 2^-16 relative) */
   int32_t tile_order;      /* 0: coarse pyramid levels (longest tile lists) launched first; 1: item order */
-  int32_t fwd_chunk;       /* 1: forward with a state (gs_images.state), variant 3: segments (seg_len)
+  int32_t fwd_chunk;       /* 0: forward with a state (gs_images.state), variant 3: segments (seg_len)
                               walked per work item, 1..65535 (a transmittance pre-pass gives every
                               chunk but a list's first its starting T), or 0 = whole lists */
   float ssim_lambda;       /* 0: weight lambda of the SSIM term of the colour loss (eq. 10, read as
@@ -81,7 +81,7 @@ typedef struct gs_config {
                               targets carry a semantic colour image; the paper trains with 0.2 */
   int32_t seg_len;         /* 0: list positions per segment of a long tile list, variant 3 (a work item
                               of gs_render_bwd, and a point where a forward with a state saves it):
-                              0 = 256, else a multiple of 32 in 256..1048576. Longer segments save
+                              0 = 1024, else a multiple of 32 in 256..1048576. Longer segments save
                               less state and start fewer items; shorter ones balance long lists
                               across the GPU better */
 } gs_config;

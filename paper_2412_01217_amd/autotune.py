@@ -4,7 +4,8 @@ For one workload signature (Gaussian count, channels, items, pixels, tiles) it t
 each candidate launch configuration -- render kernel variant (per-lane FMA, single-precision
 or split-bfloat16 matrix cores), tile launch order (coarse pyramid levels first, or item order),
 the forward's work item (segments of long lists, or whole lists), the segment length (256,
-1024 or 4096 list entries: the reverse pass's work item and the forward's state points) and
+1024 (the default) or 4096 list entries: the reverse pass's work item and the forward's state
+points) and
 the screen tile's shape (256 pixels as 16x16, 32x8, 8x32 or 64x4) -- as HIP graph replays of the whole
 step, keeps the fastest, and caches the choice in a JSON file (GS_AUTOTUNE_CACHE, default
 ~/.cache/gs_autotune.json) keyed by device and signature. Every candidate computes the same
@@ -25,8 +26,8 @@ def _c(variant, tile_order, fwd_chunk, tile_w=16, tile_h=16, seg_len=0):
 
 
 # every candidate sets every key, so that none inherits a value from the previous one
-CANDIDATES = (_c(3, 0, 1), _c(3, 0, 0), _c(3, 0, 1, seg_len=1024), _c(3, 0, 0, seg_len=1024),
-              _c(3, 0, 0, seg_len=4096), _c(3, 1, 1), _c(2, 0, 1), _c(1, 1, 1),
+CANDIDATES = (_c(3, 0, 0), _c(3, 0, 1), _c(3, 0, 1, seg_len=256), _c(3, 0, 0, seg_len=256),
+              _c(3, 0, 0, seg_len=4096), _c(3, 1, 0), _c(2, 0, 1), _c(1, 1, 1),
               _c(3, 0, 1, 32, 8), _c(3, 0, 0, 32, 8), _c(3, 0, 0, 8, 32), _c(3, 0, 0, 64, 4))
 
 

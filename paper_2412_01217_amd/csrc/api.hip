@@ -143,7 +143,7 @@ void gs_config_default(gs_config* c) {
   c->n_sem = 0;
   c->variant = 0;
   c->tile_order = 0;
-  c->fwd_chunk = 1;
+  c->fwd_chunk = 0;
   c->ssim_lambda = 0.0f;
   c->isotropic = 0;
   c->view_features = 0;

@@ -246,9 +246,9 @@ struct SStage {
 // takes every segment as a work item of its own; the forward walks up to `chunk`
 // consecutive segments of a list in one work item (one sequential transmittance chain),
 // so that only lists longer than a chunk need a starting transmittance from a pre-pass.
-// Workspaces are sized for the shortest segments, kSegMin.
-constexpr int kSegMin = 256;
-__host__ __device__ inline int seg_len(const gs_config& cfg) { return cfg.seg_len > 0 ? cfg.seg_len : kSegMin; }
+// Workspaces are sized for the shortest segments, kSegMin; seg_len = 0 selects kSegDefault.
+constexpr int kSegMin = 256, kSegDefault = 1024;
+__host__ __device__ inline int seg_len(const gs_config& cfg) { return cfg.seg_len > 0 ? cfg.seg_len : kSegDefault; }
 
 // Segments per forward work item (cfg.fwd_chunk; 0 = the whole list).
 __host__ __device__ inline int fwd_chunk(const gs_config& cfg) { return cfg.fwd_chunk > 0 ? cfg.fwd_chunk : 1 << 16; }

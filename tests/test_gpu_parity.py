@@ -48,7 +48,7 @@ def _pipeline(sc, views, n_sem, variant=0, split=True, state_capacity=None, fwd_
     """split: forward with its state (long lists in segments of fwd_chunk seg_len-entry pieces,
     0 = whole lists); state_capacity overrides the capacity the state is sized for;
     isotropic: the primitive of eq. 1-3; tile: the screen tile (width, height); seg_len: list
-    entries per segment (0 = 256)."""
+    entries per segment (0 = 1024)."""
     raster = _raster()
     cfg = raster.config(n_sem, variant=variant, fwd_chunk=fwd_chunk, isotropic=int(isotropic), tile_w=tile[0],
                         tile_h=tile[1], seg_len=seg_len)
@@ -209,7 +209,7 @@ def test_bin_sort_capacity_overflow_reports_status():
 
 # (render variant, forward with its state, forward chunk): "split_nostate" is the bfloat16
 # matrix-core path with every tile list composited whole and the reverse pass's own
-# summary pass; with the state, a forward work item walks 1 or 2 segments of 256 entries
+# summary pass; with the state, a forward work item walks 1 or 2 segments of 1024 entries
 # (longer lists start from the transmittance pre-pass) or the whole list (chunk 0)
 VARIANTS = {"valu": (1, False, 1), "mfma": (2, False, 1), "split": (3, True, 1), "split_chunk2": (3, True, 2),
             "split_wholewalk": (3, True, 0), "split_nostate": (3, False, 1)}
@@ -237,7 +237,7 @@ def test_render_fwd_state_too_small():
     _check_render_bwd("room_long_lists", 3, True, fwd_chunk=0, state_capacity=0)
 
 
-@pytest.mark.parametrize("seg_len,fwd_chunk", [(512, 1), (512, 0), (1024, 1), (1024, 2)])
+@pytest.mark.parametrize("seg_len,fwd_chunk", [(256, 1), (256, 0), (256, 2), (512, 1), (512, 0), (1024, 2)])
 def test_render_parity_segment_lengths(seg_len, fwd_chunk):
     """Longer segments of the split lists (the reverse pass's work items and the forward's
     state points): forward and backward against the oracle on lists several segments long."""

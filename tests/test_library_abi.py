@@ -42,7 +42,7 @@ def test_defaults_and_status_strings():
     assert (c.tile_w, c.tile_h) == (16, 16)
     assert c.alpha_min == pytest.approx(1 / 255) and c.alpha_max == pytest.approx(0.99)
     assert c.t_min == pytest.approx(1e-4) and c.z_near == pytest.approx(0.2)
-    assert (c.variant, c.tile_order, c.fwd_chunk, c.ssim_lambda, c.isotropic, c.view_features) == (0, 0, 1, 0.0, 0, 0)
+    assert (c.variant, c.tile_order, c.fwd_chunk, c.ssim_lambda, c.isotropic, c.view_features) == (0, 0, 0, 0.0, 0, 0)
     assert c.sem_ssim_lambda == 0.0 and c.seg_len == 0
     assert lib.gs_status_string(L.GS_ERR_CAPACITY) == b"duplicate capacity exceeded"
     assert lib.gs_version() > 0
@@ -145,7 +145,7 @@ def test_config_rejects_out_of_range_forward_chunk():
 
 
 def test_config_segment_length():
-    # split lists' segments: 0 (256 entries) or a multiple of 32 from 256 (the forward
+    # split lists' segments: 0 (1024 entries) or a multiple of 32 from 256 (the forward
     # state's slots are sized for 256-entry segments) to 2^20
     lib = L.lib()
     c = L.Config()
