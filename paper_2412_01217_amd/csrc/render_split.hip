@@ -149,6 +149,32 @@ __device__ __forceinline__ float local_power2(float lx, float ly, const LRec& r,
   return fminf(__builtin_fmaf(t, dx, (r.c.x * dy) * dy), 0.0f);
 }
 
+// Whether the footprint can reach alpha_min anywhere in the rectangle [x0, x1] x [y0, y1]
+// of tile-local positions (a wave's band of pixel centres): false only if the largest
+// base-2 exponent over the continuous rectangle lies below log2(alpha_min / o) by a margin
+// (0.1, far above the exponent's single-precision rounding), so a pixel of the band never
+// takes the Gaussian. The exponent is concave; its maximum is 0 at the mean if the mean
+// lies in the rectangle, else on an edge, at the edge's own vertex clamped to the edge.
+// A degenerate record (a non-finite maximum) is never skipped.
+__device__ __forceinline__ bool band_reaches(const LRec& r, float x0, float x1, float y0, float y1, float amin) {
+  const float a = r.m.z, b = r.m.w, c = r.c.x;
+  const float X0 = x0 - r.m.x, X1 = x1 - r.m.x, Y0 = y0 - r.m.y, Y1 = y1 - r.m.y;
+  if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return true;
+  // the vertices from approximate reciprocals: the exponent is flat there, so the value at
+  // a slightly moved point differs from the maximum by far less than the margin
+  const float ia = -0.5f * __builtin_amdgcn_rcpf(a), ic = -0.5f * __builtin_amdgcn_rcpf(c);
+  auto along_x = [&](float Y) {   // dy = Y, dx over [X0, X1]
+    const float dx = fminf(X1, fmaxf(X0, b * Y * ia));
+    return (a * dx + b * Y) * dx + c * Y * Y;
+  };
+  auto along_y = [&](float X) {   // dx = X, dy over [Y0, Y1]
+    const float dy = fminf(Y1, fmaxf(Y0, b * X * ic));
+    return (c * dy + b * X) * dy + a * X * X;
+  };
+  const float m = fmaxf(fmaxf(along_x(Y0), along_x(Y1)), fmaxf(along_y(X0), along_y(X1)));
+  return !(m < __log2f(amin) - __log2f(r.c.y) - 0.1f);
+}
+
 __device__ __forceinline__ v4f mma(v8bf a, v8bf b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 __device__ __forceinline__ v4f mma3(v8bf ah, v8bf al, v8bf bh, v8bf bl, v4f c) {
   c = mma(ah, bh, c);
@@ -167,6 +193,15 @@ __device__ __forceinline__ v4f mma6(const v8bf (&a)[3], const v8bf (&b)[3], v4f 
   return c;
 }
 __device__ __forceinline__ v4f zero4() { return (v4f){0.0f, 0.0f, 0.0f, 0.0f}; }
+
+// The next (up to) four set bits of a wave-uniform mask, lowest first (-1 past the last).
+__device__ __forceinline__ void pop4(uint32_t& m, int (&q)[4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    q[e] = m ? __builtin_ctz(m) : -1;
+    m &= m - 1u;
+  }
+}
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -389,6 +424,9 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
   const float amin = cfg.alpha_min, amax = cfg.alpha_max, tmin = cfg.t_min;
   const uint32_t n_work = SEG ? ctl[0] : 1u;
   float* W = s_w[wave];
+  // this wave's band of tile-local pixel positions
+  const float bx0 = (float)(-(1 << (tws - 1))), bx1 = (float)((1 << (tws - 1)) - 1);
+  const float by0 = (float)(((64 * wave) >> tws) - (128 >> tws)), by1 = (float)(((64 * wave + 63) >> tws) - (128 >> tws));
   for (uint32_t round = 0;; ++round) {
     uint32_t wi = 0;
     int tile, seg = 0, nseg = 1;
@@ -452,39 +490,93 @@ __global__ __launch_bounds__(256, 3) void k_render_fwd_split(gs_config cfg, cons
         // SIMD's issue slots to the other waves there while the block's other waves go on.
         bool took = false;
         const uint32_t base = b - c.start;
-        if (__ballot(!done) != 0ull) {
-          // records of the next four Gaussians are read while the current four are used
-          LRec R[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) R[e] = load_rec(s_rec, e);
-#pragma unroll
-          for (int q4 = 0; q4 < kB; q4 += 4) {
-            LRec N[4];
-            if (q4 + 4 < kB)
-#pragma unroll
-              for (int e = 0; e < 4; ++e) N[e] = load_rec(s_rec, q4 + 4 + e);
-            __builtin_amdgcn_sched_barrier(0);
-            float wq[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int q = q4 + e;
-              float dx, dy, t;
-              const float araw = R[e].c.y * __builtin_amdgcn_exp2f(local_power2(lx, ly, R[e], dx, dy, t));
-              const bool ok = (q < cnt) & !done & (araw >= amin);
-              const float w = fminf(amax, araw) * T;
-              const float Tn = T - w;
-              const bool stop = ok & (Tn < tmin);
-              const bool take = ok & !stop;
-              wq[e] = take ? w : 0.0f;
-              T = take ? Tn : T;
-              done = done | stop;
-              last = take ? base + q + 1 : last;
-              took |= take;
+        // with 32 channels, only the Gaussians that can reach a pixel of the wave's band;
+        // with 64 (whose registers are full) every Gaussian of the batch
+        if constexpr (KP <= 32) {
+          if (__ballot(!done) != 0ull) {
+            // the batch's Gaussians that can reach alpha_min somewhere in this wave's band of
+            // pixels (lane q < 32 tests Gaussian q); the others take no pixel of the band
+            bool hit = false;
+            if (lane < kB && lane < cnt) hit = band_reaches(load_rec(s_rec, lane), bx0, bx1, by0, by1, amin);
+            uint32_t m = (uint32_t)__ballot(hit);
+            // their weights only; the rest of the row is zero
+  #pragma unroll
+            for (int q4 = 0; q4 < kB; q4 += 4)
+              *reinterpret_cast<float4*>(W + lane * kWs + q4) = make_float4(0.f, 0.f, 0.f, 0.f);
+            // four at a time in list order, the next four's records read while these are used
+            // (two register sets taking turns)
+            auto load4 = [&](const int (&q)[4], LRec (&R)[4]) {
+  #pragma unroll
+              for (int e = 0; e < 4; ++e) R[e] = load_rec(s_rec, q[e] < 0 ? 0 : q[e]);
+            };
+            auto run4 = [&](const int (&q)[4], const LRec (&R)[4]) {
+  #pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                if (q[e] < 0) break;   // uniform: the last group's missing entries
+                float dx, dy, t;
+                const float araw = R[e].c.y * __builtin_amdgcn_exp2f(local_power2(lx, ly, R[e], dx, dy, t));
+                const bool ok = !done & (araw >= amin);
+                const float w = fminf(amax, araw) * T;
+                const float Tn = T - w;
+                const bool stop = ok & (Tn < tmin);
+                const bool take = ok & !stop;
+                W[lane * kWs + q[e]] = take ? w : 0.0f;
+                T = take ? Tn : T;
+                done = done | stop;
+                last = take ? base + q[e] + 1 : last;
+                took |= take;
+              }
+            };
+            int qa[4], qb[4];
+            LRec RA[4], RB[4];
+            pop4(m, qa);
+            load4(qa, RA);
+            for (;;) {
+              if (qa[0] < 0) break;
+              pop4(m, qb);
+              if (qb[0] >= 0) load4(qb, RB);
+              run4(qa, RA);
+              if (qb[0] < 0) break;
+              pop4(m, qa);
+              if (qa[0] >= 0) load4(qa, RA);
+              run4(qb, RB);
             }
-            *reinterpret_cast<float4*>(W + lane * kWs + q4) = make_float4(wq[0], wq[1], wq[2], wq[3]);
-            if (q4 + 4 < kB)
-#pragma unroll
-              for (int e = 0; e < 4; ++e) R[e] = N[e];
+          }
+        } else {
+          if (__ballot(!done) != 0ull) {
+            // records of the next four Gaussians are read while the current four are used
+            LRec R[4];
+  #pragma unroll
+            for (int e = 0; e < 4; ++e) R[e] = load_rec(s_rec, e);
+  #pragma unroll
+            for (int q4 = 0; q4 < kB; q4 += 4) {
+              LRec N[4];
+              if (q4 + 4 < kB)
+  #pragma unroll
+                for (int e = 0; e < 4; ++e) N[e] = load_rec(s_rec, q4 + 4 + e);
+              __builtin_amdgcn_sched_barrier(0);
+              float wq[4];
+  #pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int q = q4 + e;
+                float dx, dy, t;
+                const float araw = R[e].c.y * __builtin_amdgcn_exp2f(local_power2(lx, ly, R[e], dx, dy, t));
+                const bool ok = (q < cnt) & !done & (araw >= amin);
+                const float w = fminf(amax, araw) * T;
+                const float Tn = T - w;
+                const bool stop = ok & (Tn < tmin);
+                const bool take = ok & !stop;
+                wq[e] = take ? w : 0.0f;
+                T = take ? Tn : T;
+                done = done | stop;
+                last = take ? base + q + 1 : last;
+                took |= take;
+              }
+              *reinterpret_cast<float4*>(W + lane * kWs + q4) = make_float4(wq[0], wq[1], wq[2], wq[3]);
+              if (q4 + 4 < kB)
+  #pragma unroll
+                for (int e = 0; e < 4; ++e) R[e] = N[e];
+            }
           }
         }
         wave_sync();
