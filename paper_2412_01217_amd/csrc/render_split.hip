@@ -900,6 +900,10 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
   const int Kr = 4 + n_sem;
   const float amin = cfg.alpha_min, amax = cfg.alpha_max;
   const uint32_t n_work = ctl[0];
+  // this wave's band of tile-local pixel positions
+  const int tws0 = tile_shift(cfg);
+  const float bx0 = (float)(-(1 << (tws0 - 1))), bx1 = (float)((1 << (tws0 - 1)) - 1);
+  const float by0 = (float)(((64 * wave) >> tws0) - (128 >> tws0)), by1 = (float)(((64 * wave + 63) >> tws0) - (128 >> tws0));
   for (;;) {
     if (tid == 0) s_wi = atomicAdd(&ctl[SUMMARY ? 1 : 2], 1u);
     lds_barrier();
@@ -1116,6 +1120,14 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
       };
       if constexpr (SUMMARY) fetch_next();
       const bool wave_live = __ballot((uint32_t)lo < last) != 0ull;
+      // the batch's Gaussians that can reach alpha_min in this wave's band of pixels (lane
+      // q < 32 tests Gaussian q)
+      uint32_t bmask = 0xffffffffu;
+      if constexpr (!SUMMARY) {
+        bool hit = false;
+        if (wave_live && lane < kB && lane < cnt) hit = band_reaches(load_rec(s_rec, lane), bx0, bx1, by0, by1, amin);
+        bmask = (uint32_t)__ballot(hit);
+      }
       if (!SUMMARY && !wave_live) fetch_next();
       if (wave_live) {
         // GF^T[i][p] in single precision (it decides dL/dalpha, where terms cancel):
@@ -1195,6 +1207,12 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
             bool any = false;
 #pragma unroll
             for (int gb = 16 / GG - 1; gb >= 0; --gb) {
+              // a group none of whose Gaussians can reach the wave's band takes no pixel of it
+              if (((bmask >> (16 * bq + GG * gb)) & ((1u << GG) - 1u)) == 0u) {
+#pragma unroll
+                for (int r = 0; r < GG; ++r) Wp[(GG * gb + r) * kPs + lane] = 0.0f;
+                continue;
+              }
               float V[6 * GG];   // V[6 r + k]: component k of the geometric terms of Gaussian GG gb + r
               bool gact = false;
 #pragma unroll
