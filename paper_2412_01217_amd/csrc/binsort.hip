@@ -390,6 +390,9 @@ __global__ __launch_bounds__(256) void k_compact(gs_config cfg, const int32_t* _
                                                  const gs_item* __restrict__ items, int64_t E, int64_t n,
                                                  int cnt_shift, const uint32_t* __restrict__ offs,
                                                  uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  // the block's visible entries are staged in LDS in order, then written out coalesced
+  __shared__ uint64_t s_key[kCpTile];
+  __shared__ uint32_t s_val[kCpTile];
   const int64_t base = (int64_t)blockIdx.x * kCpTile + (int64_t)threadIdx.x * kCpItems;
   int32_t r[kCpItems];
   load_radii(radius, E, base, r);
@@ -398,12 +401,15 @@ __global__ __launch_bounds__(256) void k_compact(gs_config cfg, const int32_t* _
   for (int k = 0; k < kCpItems; ++k) c += r[k] > 0 ? 1u : 0u;
   __shared__ uint32_t sh[4];
   uint32_t total;
-  uint32_t p = offs[blockIdx.x] + block_exclusive_scan(c, total, sh);
+  uint32_t p = block_exclusive_scan(c, total, sh);
+  // with n >= kCpItems a thread's consecutive entries span at most two items
+  const int64_t item0 = base / n, next0 = (item0 + 1) * n;
+  const bool two = n >= kCpItems;
 #pragma unroll
   for (int k = 0; k < kCpItems; ++k) {
     if (r[k] <= 0) continue;
     const int64_t e = base + k;
-    const uint64_t item = (uint64_t)(e / n);
+    const uint64_t item = (uint64_t)(two ? (e >= next0 ? item0 + 1 : item0) : e / n);
     // a visible entry's depth is above z_near > 0, so its sign bit is 0 (the mask only keeps
     // an invalid negative depth from reaching the item bits)
     uint64_t key = (item << 31) | (uint64_t)(__float_as_uint(depth[e]) & 0x7fffffffu);
@@ -413,9 +419,15 @@ __global__ __launch_bounds__(256) void k_compact(gs_config cfg, const int32_t* _
                                r[k]);
       key |= (uint64_t)((R.x1 - R.x0) * (R.y1 - R.y0)) << cnt_shift;
     }
-    keys[p] = key;
-    vals[p] = (uint32_t)e;
+    s_key[p] = key;
+    s_val[p] = (uint32_t)e;
     ++p;
+  }
+  __syncthreads();
+  const int64_t out0 = offs[blockIdx.x];
+  for (uint32_t i = threadIdx.x; i < total; i += 256) {
+    keys[out0 + i] = s_key[i];
+    vals[out0 + i] = s_val[i];
   }
 }
 
