@@ -471,7 +471,7 @@ __global__ __launch_bounds__(256) void k_duplicate(gs_config cfg, const uint32_t
   uint32_t c = 0;
   if (j < count) {
     const uint32_t e = svals[j];
-    const int64_t item = e / n;
+    const int64_t item = (int64_t)(e / (uint32_t)n);   // entries and n fit 32 bits
     const gs_item it = items[item];
     const Rect R = tile_rect(cfg, it.tiles_x, it.tiles_y, *reinterpret_cast<const float4*>(rec + (int64_t)kRecFloats * e),
                              radius[e]);

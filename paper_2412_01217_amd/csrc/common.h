@@ -86,10 +86,12 @@ __device__ __forceinline__ Rect tile_rect(const gs_config& cfg, int tiles_x, int
     R.x0 = 0; R.y0 = 0; R.x1 = tiles_x; R.y1 = tiles_y;
     return R;
   }
-  R.x0 = min(tiles_x, max(0, (int)floor((mx - r) / cfg.tile_w)));
-  R.y0 = min(tiles_y, max(0, (int)floor((my - r) / cfg.tile_h)));
-  R.x1 = min(tiles_x, max(0, (int)floor((mx + r) / cfg.tile_w) + 1));
-  R.y1 = min(tiles_y, max(0, (int)floor((my + r) / cfg.tile_h) + 1));
+  // tile sides are powers of two, so the products by their reciprocals are the quotients exactly
+  const double iw = 1.0 / 256.0 * (double)(256 / cfg.tile_w), ih = 1.0 / 256.0 * (double)(256 / cfg.tile_h);
+  R.x0 = min(tiles_x, max(0, (int)floor((mx - r) * iw)));
+  R.y0 = min(tiles_y, max(0, (int)floor((my - r) * ih)));
+  R.x1 = min(tiles_x, max(0, (int)floor((mx + r) * iw) + 1));
+  R.y1 = min(tiles_y, max(0, (int)floor((my + r) * ih) + 1));
   return R;
 }
 

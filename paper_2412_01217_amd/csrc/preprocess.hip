@@ -154,10 +154,12 @@ __device__ inline Lvl footprint(const gs_config& cfg, const gs_item& it, const C
     L.rect[0] = 0; L.rect[1] = 0; L.rect[2] = it.tiles_x; L.rect[3] = it.tiles_y;
   } else {
     const double r = L.radius;
-    L.rect[0] = min(it.tiles_x, max(0, (int)floor((L.m2[0] - r) / cfg.tile_w)));
-    L.rect[1] = min(it.tiles_y, max(0, (int)floor((L.m2[1] - r) / cfg.tile_h)));
-    L.rect[2] = min(it.tiles_x, max(0, (int)floor((L.m2[0] + r) / cfg.tile_w) + 1));
-    L.rect[3] = min(it.tiles_y, max(0, (int)floor((L.m2[1] + r) / cfg.tile_h) + 1));
+    // tile sides are powers of two, so the products by their reciprocals are the quotients exactly
+    const double iw = 1.0 / 256.0 * (double)(256 / cfg.tile_w), ih = 1.0 / 256.0 * (double)(256 / cfg.tile_h);
+    L.rect[0] = min(it.tiles_x, max(0, (int)floor((L.m2[0] - r) * iw)));
+    L.rect[1] = min(it.tiles_y, max(0, (int)floor((L.m2[1] - r) * ih)));
+    L.rect[2] = min(it.tiles_x, max(0, (int)floor((L.m2[0] + r) * iw) + 1));
+    L.rect[3] = min(it.tiles_y, max(0, (int)floor((L.m2[1] + r) * ih) + 1));
   }
   L.vis = L.rect[2] > L.rect[0] && L.rect[3] > L.rect[1];
   return L;
