@@ -283,8 +283,13 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const Key* __re
                                                                  const uint64_t* count_dev, int shift, int nblk, int sub,
                                                                  const uint32_t* __restrict__ offs) {
   constexpr int ND = 1 << B;
+  constexpr int DPT = ND / kRadixThreads;   // digits per thread in the per-digit phase
   __shared__ uint32_t cnt[4][ND];
   __shared__ uint32_t run[ND];
+  __shared__ uint32_t delta[ND];            // a digit's output slot minus its staged position
+  __shared__ Key s_k[kRadixTile];           // the sub-tile in digit order
+  __shared__ uint32_t s_v[kRadixTile];
+  __shared__ uint32_t sh[4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t count = (int64_t)*count_dev;
   const int64_t block0 = (int64_t)blockIdx.x * kRadixTile * sub;
@@ -326,24 +331,45 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const Key* __re
       pos[r] = old + rank;
     }
     __syncthreads();
-    // per digit: the sub-tile's first slot, then an exclusive prefix over the four waves
-    for (int d = threadIdx.x; d < ND; d += kRadixThreads) {
-      const uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d], c3 = cnt[3][d];
-      const uint32_t g = run[d];
-      cnt[0][d] = g;
-      cnt[1][d] = g + c0;
-      cnt[2][d] = g + c0 + c1;
-      cnt[3][d] = g + c0 + c1 + c2;
-      run[d] = g + c0 + c1 + c2 + c3;
+    // per digit (thread tid owns DPT consecutive digits): the digit's staged start (a prefix
+    // over the digits), each wave's start within it, and the offset to its output slots
+    uint32_t tot[DPT], s = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int d = threadIdx.x * DPT + j;
+      tot[j] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
+      s += tot[j];
+    }
+    uint32_t all;
+    uint32_t ls = block_exclusive_scan(s, all, sh);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int d = threadIdx.x * DPT + j;
+      const uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d];
+      cnt[0][d] = ls;
+      cnt[1][d] = ls + c0;
+      cnt[2][d] = ls + c0 + c1;
+      cnt[3][d] = ls + c0 + c1 + c2;
+      delta[d] = run[d] - ls;
+      run[d] += tot[j];
+      ls += tot[j];
     }
     __syncthreads();
+    // stage in digit order, then write runs of equal digits to consecutive slots
     for (int r = 0; r < kRadixItems; ++r) {
       if (!ok[r]) continue;
-      const uint32_t dst = cnt[wid][dig[r]] + pos[r];
-      kout[dst] = k[r];
-      vout[dst] = v[r];
+      const uint32_t lp = cnt[wid][dig[r]] + pos[r];
+      s_k[lp] = k[r];
+      s_v[lp] = v[r];
     }
-    __syncthreads();                                  // cnt is cleared for the next sub-tile
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < all; i += kRadixThreads) {
+      const Key kk = s_k[i];
+      const uint32_t dst = i + delta[(uint32_t)(kk >> shift) & (uint32_t)(ND - 1)];
+      kout[dst] = kk;
+      vout[dst] = s_v[i];
+    }
+    __syncthreads();                                  // cnt and the stage are reused by the next sub-tile
   }
 }
 
