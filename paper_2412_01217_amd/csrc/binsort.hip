@@ -485,7 +485,20 @@ __global__ __launch_bounds__(256) void k_duplicate(gs_config cfg, const uint32_t
                                                    const uint64_t* count_dev, const uint32_t* __restrict__ offs,
                                                    const float* __restrict__ rec, const int32_t* __restrict__ radius,
                                                    const gs_item* __restrict__ items, int64_t n, int64_t cap,
-                                                   uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
+                                                   uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals,
+                                                   const uint64_t* __restrict__ dtotal, uint64_t* __restrict__ live,
+                                                   int64_t* __restrict__ n_dup_out, int32_t* __restrict__ status,
+                                                   uint32_t* __restrict__ ranges, int64_t rn) {
+  // (also: the duplicate count clamped to the capacity, with its status, and the tile ranges
+  // cleared for the range pass after the tile sort)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint64_t D = *dtotal;
+    *live = D > (uint64_t)cap ? (uint64_t)cap : D;
+    if (n_dup_out) *n_dup_out = (int64_t)D;
+    if (status) *status = D > (uint64_t)cap ? GS_ERR_CAPACITY : GS_OK;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rn; i += (int64_t)gridDim.x * blockDim.x)
+    ranges[i] = 0u;
   __shared__ uint32_t s_pre[4][64];   // inclusive prefix of the wave's tile counts
   __shared__ int4 s_rect[4][64];      // x0, width, tiles_x, id of tile (0, y0) of the item
   __shared__ uint32_t s_g[4][64];     // Gaussian index
@@ -532,19 +545,6 @@ __global__ __launch_bounds__(256) void k_duplicate(gs_config cfg, const uint32_t
     tkeys[pos] = (uint32_t)(r.w + row * r.z + r.x + col);
     tvals[pos] = s_g[wid][lo];
   }
-}
-
-// Clamp the duplicate count to the capacity and report the status.
-__global__ void k_dup_count(const uint64_t* total, int64_t cap, uint64_t* live, int64_t* n_dup_out, int32_t* status) {
-  const uint64_t D = *total;
-  *live = D > (uint64_t)cap ? (uint64_t)cap : D;
-  if (n_dup_out) *n_dup_out = (int64_t)D;
-  if (status) *status = D > (uint64_t)cap ? GS_ERR_CAPACITY : GS_OK;
-}
-
-__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ tkeys, const uint64_t* count_dev, uint32_t* __restrict__ ranges) {
@@ -740,21 +740,19 @@ int launch_bin_sort(const gs_config& cfg, const gs_projected& proj, const gs_ite
                        w.touched);
   st = device_scan(w.touched, w.touched, n_vis, 0, E, w.partial, d_total, s);
   if (st) return st;
-  hipLaunchKernelGGL(k_dup_count, dim3(1), dim3(1), 0, s, d_total, cap, d_live, n_dup_dev, status_dev);
   // the tile sort must end in the caller's vals: start there after an even pass count
   const int tbits = std::max(1, bits_for((uint64_t)n_tiles));
   const int passes = radix_passes(tbits);
   uint32_t* v_first = (passes % 2 == 0) ? vals : w.tvals;
   uint32_t* v_other = (passes % 2 == 0) ? w.tvals : vals;
   hipLaunchKernelGGL(k_duplicate, dim3((unsigned)std::max<int64_t>(1, ceil_div(E, 256))), dim3(256), 0, s, cfg, svals,
-                     n_vis, w.touched, proj.rec, proj.radius, items, n, cap, w.tkeys[0], v_first);
+                     n_vis, w.touched, proj.rec, proj.radius, items, n, cap, w.tkeys[0], v_first, d_total, d_live,
+                     n_dup_dev, status_dev, ranges, 2ll * n_tiles);
   // 4. stable sort of the duplicates by tile
   st = radix_sort<uint32_t>(w.tkeys[0], w.tkeys[1], v_first, v_other, d_live, cap, tbits, w, s, &fin);
   if (st) return st;
   const uint32_t* tk = w.tkeys[fin];
   // 5. tile ranges
-  const int64_t rn = 2ll * n_tiles;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::max<int64_t>(1, ceil_div(rn, 256))), dim3(256), 0, s, ranges, rn, 0u);
   const unsigned cb = (unsigned)std::max<int64_t>(1, ceil_div(cap, 256));
   hipLaunchKernelGGL(k_ranges, dim3(cb), dim3(256), 0, s, tk, d_live, ranges);
   if (keys)
