@@ -84,6 +84,12 @@ typedef struct gs_config {
                               0 = 1024, else a multiple of 32 in 256..1048576. Longer segments save
                               less state and start fewer items; shorter ones balance long lists
                               across the GPU better */
+  int32_t sort_mode;       /* 0: how gs_bin_sort orders the duplicates (the result is the same):
+                              1 = radix passes (entries by (item, depth), then duplicates by tile);
+                              2 = buckets: one counting pass by tile, then each tile's list sorted
+                              by (depth, index) in LDS (few launches; made for short lists; up to
+                              12288 tiles, else GS_ERR_UNSUPPORTED); 0 = automatic (2 up to 12288
+                              tiles and 2^22 (item, Gaussian) entries, else 1) */
 } gs_config;
 
 /* One camera view: world -> camera transform x_c = R x_w + t (OpenCV axes,
@@ -226,7 +232,8 @@ int gs_preprocess(const gs_config* cfg, const gs_gaussians* g, const gs_view* vi
  * Every entry with radius > 0 must have depth > 0 (gs_preprocess gives depth > z_near).
  * n_dup_dev (device int64) receives the duplicate count. If it exceeds dup_capacity,
  * status_dev (device int32) is set to GS_ERR_CAPACITY and nothing past the capacity
- * is written; otherwise status_dev is set to GS_OK. */
+ * is written (the lists are then incomplete); otherwise status_dev is set
+ * to GS_OK. cfg->sort_mode picks the method; the workspace size covers both. */
 int gs_bin_sort(const gs_config* cfg, const gs_projected* proj, const gs_item* items_dev, int32_t n_items,
                 int64_t n_gauss, int32_t n_tiles, int64_t dup_capacity, void* workspace, size_t ws_bytes,
                 uint64_t* keys, uint32_t* vals, uint32_t* ranges, int64_t* n_dup_dev, int32_t* status_dev,

@@ -40,7 +40,7 @@ class Config(ctypes.Structure):
                 ("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("guard", c_float),
                 ("full_rect", c_int32), ("n_sem", c_int32), ("variant", c_int32), ("tile_order", c_int32),
                 ("fwd_chunk", c_int32), ("ssim_lambda", c_float), ("isotropic", c_int32),
-                ("view_features", c_int32), ("sem_ssim_lambda", c_float), ("seg_len", c_int32)]
+                ("view_features", c_int32), ("sem_ssim_lambda", c_float), ("seg_len", c_int32), ("sort_mode", c_int32)]
 
 
 class View(ctypes.Structure):

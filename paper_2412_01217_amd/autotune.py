@@ -7,7 +7,9 @@ the forward's work item (segments of long lists, or whole lists), the segment le
 1024 (the default) or 4096 list entries: the reverse pass's work item and the forward's state
 points) and
 the screen tile's shape (256 pixels as 16x16, 32x8, 8x32 or 64x4) -- as HIP graph replays of the whole
-step, keeps the fastest, and caches the choice in a JSON file (GS_AUTOTUNE_CACHE, default
+step, keeps the fastest, then times that configuration with each bin-sort method (radix
+passes, or buckets with per-tile sorts in LDS, gs_config.sort_mode 1 and 2) and keeps the
+faster, and caches the choice in a JSON file (GS_AUTOTUNE_CACHE, default
 ~/.cache/gs_autotune.json) keyed by device and signature. Every candidate computes the same
 result; only the schedule (and, with the tile shape, the binning) differs. A candidate with
 another tile shape needs the item table of that shape: make_step builds its step on
@@ -22,7 +24,11 @@ import torch
 
 def _c(variant, tile_order, fwd_chunk, tile_w=16, tile_h=16, seg_len=0):
     return {"variant": variant, "tile_order": tile_order, "fwd_chunk": fwd_chunk, "tile_w": tile_w, "tile_h": tile_h,
-            "seg_len": seg_len}
+            "seg_len": seg_len, "sort_mode": 0}
+
+
+# gs_config.sort_mode 2 (buckets) handles frames of up to this many tiles
+BUCKET_MAX_TILES = 12288
 
 
 # every candidate sets every key, so that none inherits a value from the previous one
@@ -114,6 +120,20 @@ def tune(make_step, cfg, frame, n: int, candidates=CANDIDATES, reps=5, use_cache
         del step
     for k, v in best.items():
         setattr(cfg, k, v)
+    if frame_for(cfg, frame).n_tiles <= BUCKET_MAX_TILES:
+        base = ",".join(f"{k}={v}" for k, v in best.items() if k != "sort_mode")
+        best_t = float("inf")
+        pick = dict(best)
+        for mode in (1, 2):
+            cfg.sort_mode = mode
+            step = make_step(cfg)
+            t = time_step(step, reps=reps)
+            times[f"{base},sort_mode={mode}"] = t
+            if t < best_t:
+                best_t, pick = t, dict(best, sort_mode=mode)
+            del step
+        best = pick
+        cfg.sort_mode = best["sort_mode"]
     db[key] = {"choice": best, "times_ms": times}
     if use_cache:
         _store(db)

@@ -22,7 +22,7 @@ int launch_preprocess(const gs_config&, const gs_gaussians&, const gs_view*, int
                       hipStream_t);
 int launch_preprocess_bwd(const gs_config&, const gs_gaussians&, const gs_view*, int, const gs_item*, const float*,
                           const int32_t*, const gs_grads&, hipStream_t);
-size_t bin_sort_workspace(int64_t E, int64_t cap);
+size_t bin_sort_workspace(int64_t E, int64_t cap, int64_t n_tiles);
 int launch_bin_sort(const gs_config&, const gs_projected&, const gs_item*, int, int64_t, int, int64_t, void*, uint64_t*,
                     uint32_t*, uint32_t*, int64_t*, int32_t*, hipStream_t);
 #define GS_RENDER_FWD_ARGS                                                                                 \
@@ -109,6 +109,7 @@ bool cfg_ok(const gs_config* c) {
   if (c->view_features < 0 || c->view_features > 1) return false;
   // segments of split lists: the forward's state is sized for 256-entry ones
   if (c->seg_len != 0 && (c->seg_len < 256 || c->seg_len > (1 << 20) || c->seg_len % 32 != 0)) return false;
+  if (c->sort_mode < 0 || c->sort_mode > 2) return false;
   return true;
 }
 
@@ -149,6 +150,7 @@ void gs_config_default(gs_config* c) {
   c->view_features = 0;
   c->sem_ssim_lambda = 0.0f;
   c->seg_len = 0;
+  c->sort_mode = 0;
 }
 
 const char* gs_status_string(int s) {
@@ -211,7 +213,7 @@ int gs_workspace_size(int kind, const gs_config* cfg, int32_t n_items, int64_t n
     return GS_ERR_INVALID_ARG;
   switch (kind) {
     case GS_WS_BIN_SORT:
-      *bytes = bin_sort_workspace((int64_t)n_items * n_gauss, dup_capacity);
+      *bytes = bin_sort_workspace((int64_t)n_items * n_gauss, dup_capacity, n_tiles);
       return GS_OK;
     case GS_WS_RENDER_BWD:
       *bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)n_gauss) + align_up(head_bwd_workspace()) +
@@ -246,7 +248,7 @@ int gs_bin_sort(const gs_config* cfg, const gs_projected* proj, const gs_item* i
   if (n_tiles == 0) return GS_OK;
   if (!items_dev || !vals || !ranges) return GS_ERR_INVALID_ARG;
   if (n_items > 0 && n_gauss > 0 && (!proj->rec || !proj->depth || !proj->radius)) return GS_ERR_INVALID_ARG;
-  if (ws_bytes < bin_sort_workspace((int64_t)n_items * n_gauss, dup_capacity) || !workspace) return GS_ERR_WORKSPACE;
+  if (ws_bytes < bin_sort_workspace((int64_t)n_items * n_gauss, dup_capacity, n_tiles) || !workspace) return GS_ERR_WORKSPACE;
   return launch_bin_sort(*cfg, *proj, items_dev, n_items, n_gauss, n_tiles, dup_capacity, workspace, keys, vals, ranges,
                          n_dup_dev, status_dev, (hipStream_t)stream);
 }

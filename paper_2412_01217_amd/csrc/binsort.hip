@@ -15,6 +15,9 @@
 // capacity and blocks past the live count exit early.
 #include "common.h"
 
+#include <algorithm>
+#include <cmath>
+
 namespace gs {
 namespace {
 
@@ -567,6 +570,388 @@ __global__ void k_full_keys(const uint32_t* __restrict__ tkeys, const uint32_t* 
 }
 
 // ---------------------------------------------------------------------------
+// Bucket path (short tile lists): a counting sort of the duplicates by tile in one pass,
+// then every tile's list sorted by its (depth bits, Gaussian index) keys in LDS.
+//
+// Block b of the two pair kernels takes the same entries. The first counts the block's
+// duplicates per tile with LDS atomics and writes the counts tile-major; their exclusive scan
+// gives every (tile, block) its first slot, tile t's list starting at the slot of (t, 0). The
+// second kernel hands each duplicate the next slot of its (tile, block) from an LDS counter,
+// in whatever order the LDS atomics serve the lanes, and stores its key there. The per-tile
+// sort then puts every list in (depth, index) order: the key is unique within a tile (a
+// Gaussian meets a tile of its item once), so the order in which slots were taken does not
+// show in the result, which is the (tile, depth, index) order of the radix path exactly.
+// ---------------------------------------------------------------------------
+constexpr int kBkThreads = 1024;
+constexpr int kBkWaves = kBkThreads / 64;
+constexpr int kBkMaxTiles = 12288;   // tile counters a block keeps in LDS (48 KB)
+
+template <bool COUNT>
+__global__ __launch_bounds__(kBkThreads) void k_bucket_pairs(gs_config cfg, const int32_t* __restrict__ radius,
+                                                             const float* __restrict__ depth,
+                                                             const float* __restrict__ rec,
+                                                             const gs_item* __restrict__ items, int64_t E, int64_t n,
+                                                             int n_tiles, int nblk, uint32_t* __restrict__ hist,
+                                                             int64_t cap, uint64_t* __restrict__ tmp,
+                                                             const uint64_t* __restrict__ dtotal,
+                                                             int64_t* __restrict__ n_dup_out,
+                                                             int32_t* __restrict__ status) {
+  __shared__ uint32_t s_cnt[kBkMaxTiles];      // per tile: the block's count, or its next slot
+  __shared__ uint32_t s_pre[kBkWaves][64];     // inclusive prefix of the wave's tile counts
+  __shared__ int4 s_rect[kBkWaves][64];        // x0, width, tiles_x, id of tile (0, y0) of the item
+  __shared__ uint64_t s_key[kBkWaves][64];     // the entry's key within its tiles (scatter)
+  const int b = blockIdx.x;
+  for (int t = threadIdx.x; t < n_tiles; t += kBkThreads) s_cnt[t] = COUNT ? 0u : hist[(int64_t)t * nblk + b];
+  if (!COUNT && b == 0 && threadIdx.x == 0) {
+    const uint64_t D = *dtotal;
+    if (n_dup_out) *n_dup_out = (int64_t)D;
+    if (status) *status = D > (uint64_t)cap ? GS_ERR_CAPACITY : GS_OK;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t n_groups = (E + 63) >> 6, stride = (int64_t)nblk * kBkWaves;
+  // groups of 64 consecutive entries, the block's waves on consecutive groups in each round;
+  // the radii of a wave's next group are loaded one group ahead
+  int64_t grp = (int64_t)b * kBkWaves + wid;
+  int r_next = grp * 64 + lane < E ? radius[grp * 64 + lane] : 0;
+  for (; grp < n_groups; grp += stride) {
+    const int64_t e = grp * 64 + lane;
+    const int r = r_next;
+    const int64_t en = (grp + stride) * 64 + lane;
+    r_next = en < E ? radius[en] : 0;
+    uint32_t c = 0;
+    int4 rc = make_int4(0, 1, 0, 0);
+    uint64_t key = 0;
+    if (e < E) {
+      if (r > 0) {
+        const uint32_t item = (uint32_t)e / (uint32_t)n;   // entries fit 32 bits
+        const gs_item it = items[item];
+        const Rect R = tile_rect(cfg, it.tiles_x, it.tiles_y,
+                                 *reinterpret_cast<const float4*>(rec + (int64_t)kRecFloats * e), r);
+        const int w = R.x1 - R.x0;
+        c = (uint32_t)(w * (R.y1 - R.y0));
+        rc = make_int4(R.x0, w, it.tiles_x, it.tile_base + R.y0 * it.tiles_x);
+        // a visible depth is above z_near > 0 (the mask keeps the sign bit out of the order)
+        if (!COUNT)
+          key = ((uint64_t)(__float_as_uint(depth[e]) & 0x7fffffffu) << 32) |
+                (uint64_t)((uint32_t)e - item * (uint32_t)n);
+      }
+    }
+    uint32_t inc = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t t = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += t;
+    }
+    // (the previous group's reads of the wave's slots are done: a wave's LDS operations
+    // complete in order)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    s_pre[wid][lane] = inc;
+    s_rect[wid][lane] = rc;
+    if (!COUNT) s_key[wid][lane] = key;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t total = __shfl(inc, 63, 64);
+    for (uint32_t k = lane; k < total; k += 64) {
+      int lo = 0, hi = 63;   // first entry whose inclusive prefix exceeds k
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_pre[wid][mid] > k) hi = mid; else lo = mid + 1;
+      }
+      const uint32_t m = k - (lo > 0 ? s_pre[wid][lo - 1] : 0u);
+      const int4 rr = s_rect[wid][lo];
+      const int row = (int)(m / (uint32_t)rr.y), col = (int)m - row * rr.y;
+      const int tile = rr.w + row * rr.z + rr.x + col;
+      const uint32_t pos = atomicAdd(&s_cnt[tile], 1u);
+      if (!COUNT && (int64_t)pos < cap) tmp[pos] = s_key[wid][lo];
+    }
+  }
+  if (COUNT) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < n_tiles; t += kBkThreads) hist[(int64_t)t * nblk + b] = s_cnt[t];
+  }
+}
+
+// Tile t's list: [offs[t * nblk], offs[(t + 1) * nblk]) (the duplicate total past the last
+// tile), clamped to the capacity; a negative length (wrapped 32-bit slots past the capacity)
+// reads as empty.
+__device__ __forceinline__ void tile_span(const uint32_t* offs, int nblk, int n_tiles, const uint64_t* dtotal,
+                                          int64_t cap, int t, int64_t& start, int64_t& len) {
+  const int64_t a = offs[(int64_t)t * nblk];
+  const int64_t b = t + 1 < n_tiles ? (int64_t)offs[(int64_t)(t + 1) * nblk] : (int64_t)*dtotal;
+  start = min(a, cap);
+  len = min(b, cap) - start;
+}
+
+// Per-tile sort by rank. The list is cut into sub-lists of 256 keys; a wave owns whole
+// sub-lists (sub-list c: wave c mod W, lane l holding its keys l, l + 64, l + 128, l + 192),
+// so one broadcast LDS read of a sub-list key serves four comparisons per lane: a key's rank
+// within its sub-list is the number of smaller keys there. The sub-lists are then written
+// sorted, and the rank of the key at sorted position j in the whole list is j plus, for every
+// other sub-list, the number of its keys below the key (a binary search). Lists of up to CH
+// keys; T threads (W = T / 64).
+constexpr int kSub = 256;
+
+template <int T, int CH>
+__device__ __forceinline__ void rank_sort_tile(uint64_t* s, const uint64_t* __restrict__ g, int L, int t,
+                                               int64_t start, const float* __restrict__ depth,
+                                               const gs_item* __restrict__ items, int n_items, int64_t n,
+                                               uint32_t* __restrict__ vals, uint64_t* __restrict__ keys) {
+  constexpr int W = T / 64, NS = CH / (kSub * W), R = kSub / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < L; i += T) s[i] = g[i];
+  __syncthreads();
+  const int nsub = (L + kSub - 1) / kSub;
+  uint64_t k[NS][R];
+  uint32_t rk[NS][R];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int c = wid + q * W, c0 = c * kSub, cl = min(kSub, L - c0);   // cl <= 0: no sub-list
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = lane + 64 * r;
+      k[q][r] = j < cl ? s[c0 + j] : ~0ull;
+      rk[q][r] = 0;
+    }
+    if (cl <= 0) continue;   // uniform over the wave
+    // eight keys per round, read before any is compared (one LDS wait per round)
+    int j = 0;
+    for (; j + 8 <= cl; j += 8) {
+      uint64_t a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = s[c0 + j + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) rk[q][r] += (uint32_t)(a[u] < k[q][r]);
+    }
+    for (; j < cl; ++j) {
+      const uint64_t a0 = s[c0 + j];
+#pragma unroll
+      for (int r = 0; r < R; ++r) rk[q][r] += (uint32_t)(a0 < k[q][r]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int c0 = (wid + q * W) * kSub, cl = min(kSub, L - c0);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (lane + 64 * r < cl) s[c0 + rk[q][r]] = k[q][r];
+  }
+  __syncthreads();
+  const int64_t item = keys ? item_of_tile(items, n_items, t) : 0;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int own = wid + q * W, c0 = own * kSub, cl = min(kSub, L - c0);
+    if (cl <= 0) continue;   // uniform over the wave
+    // lane l now takes positions 4 l .. 4 l + 3 of the sorted sub-list: neighbouring lanes
+    // search for neighbouring keys, so their LDS reads mostly meet at the same addresses
+    uint32_t rank[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = lane * R + r;
+      rank[r] = (uint32_t)j;
+      k[q][r] = j < cl ? s[c0 + j] : ~0ull;
+    }
+    // the other sub-lists four at a time, the 4 x R searches in lockstep (branch-free lower
+    // bound by binary lifting: pos grows by each power of two while the key at pos + step - 1
+    // is below the searched key), so that their LDS reads overlap
+    for (int cg = 0; cg < nsub; cg += 4) {
+      int nn[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = cg + u;
+        nn[u] = (c < nsub && c != own) ? min(kSub, L - c * kSub) : 0;
+      }
+      int pos[4][R];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) pos[u][r] = 0;
+#pragma unroll
+      for (int step = kSub; step >= 1; step >>= 1) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int p = pos[u][r] + step;
+            if (p <= nn[u] && s[(cg + u) * kSub + p - 1] < k[q][r]) pos[u][r] = p;
+          }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) rank[r] += (uint32_t)pos[u][r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (lane * R + r >= cl) continue;
+      const uint64_t key = k[q][r];
+      const uint32_t gi = (uint32_t)key;
+      vals[start + rank[r]] = gi;
+      if (keys) {
+        const uint32_t db = gi < (uint64_t)n ? __float_as_uint(depth[item * n + gi]) : 0u;
+        keys[start + rank[r]] = ((uint64_t)(uint32_t)t << 32) | (uint64_t)db;
+      }
+    }
+  }
+}
+
+// Lists longer than the long kernel's CH: the all-ascending form of Batcher's bitonic network
+// (every compare-exchange puts the smaller key at the lower position; a merge of two sorted
+// halves of k keys starts by comparing position i with its mirror k - 1 - i), in place in the
+// scatter buffer. Positions past the list count as +inf and never move, so a list of L keys
+// is sorted as the next power of two with only its first L positions touched. Steps over
+// pairs closer than CH / 2 run chunk by chunk in LDS, the others in global memory.
+template <int T>
+__device__ __forceinline__ void bt_step(uint64_t* s, int m, int h, bool flip) {
+  for (int p = threadIdx.x; p < (m >> 1); p += T) {
+    const int q = p & (h - 1), b = (p - q) << 1;
+    const int lo = b + q, hi = flip ? b + 2 * h - 1 - q : lo + h;
+    const uint64_t x = s[lo], y = s[hi];
+    if (y < x) {
+      s[lo] = y;
+      s[hi] = x;
+    }
+  }
+}
+
+// Steps h = h0, h0 / 2, ..., 1 of merge stage k (a step with h == k / 2 is the flip) on an
+// LDS chunk of m keys. Thread t takes pairs t + T r, so for h <= 64 wave w only touches keys
+// 128 w + 2 T r .. + 127: two such steps in a row need only the wave's own ordering.
+template <int T>
+__device__ __forceinline__ void bt_stage(uint64_t* s, int m, int64_t k, int h0, bool& wide) {
+  for (int h = h0; h >= 1; h >>= 1) {
+    const bool w = h >= 128;
+    if (w || wide) {
+      __syncthreads();
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    wide = w;
+    bt_step<T>(s, m, h, (int64_t)h == (k >> 1));
+  }
+}
+
+template <int T, int CH>
+__device__ void bitonic_tile(uint64_t* s, uint64_t* g, int64_t L) {
+  int64_t m = 1;
+  while (m < L) m <<= 1;
+  auto chunk = [&](int64_t c0, int64_t k, int h0) {
+    for (int i = threadIdx.x; i < CH; i += T) s[i] = c0 + i < L ? g[c0 + i] : ~0ull;
+    bool wide = true;
+    if (h0 == 0) {
+      for (int kk = 2; kk <= CH; kk <<= 1) bt_stage<T>(s, CH, kk, kk >> 1, wide);
+    } else {
+      bt_stage<T>(s, CH, k, h0, wide);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < CH; i += T)
+      if (c0 + i < L) g[c0 + i] = s[i];
+    __syncthreads();
+  };
+  for (int64_t c0 = 0; c0 < L; c0 += CH) chunk(c0, 0, 0);   // every chunk sorted
+  for (int64_t k = 2 * CH; k <= m; k <<= 1) {
+    for (int64_t h = k >> 1; h >= CH; h >>= 1) {
+      const bool flip = h == (k >> 1);
+      for (int64_t p = threadIdx.x; p < (m >> 1); p += T) {
+        const int64_t q = p & (h - 1), b = (p - q) << 1;
+        const int64_t lo = b + q, hi = flip ? b + 2 * h - 1 - q : lo + h;
+        if (hi >= L) continue;   // the partner is +inf: nothing moves
+        const uint64_t x = g[lo], y = g[hi];
+        if (y < x) {
+          g[lo] = y;
+          g[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+    for (int64_t c0 = 0; c0 < L; c0 += CH) chunk(c0, k, CH >> 1);
+  }
+}
+
+// Short lists (up to 1024 keys), one block per tile; also writes every tile's range.
+constexpr int kShortKeys = 1024;
+constexpr int kLongThreads = 1024;
+constexpr int kLongKeys = 8192;
+
+__global__ __launch_bounds__(256) void k_tile_sort_short(const uint32_t* __restrict__ offs, int nblk, int n_tiles,
+                                                         const uint64_t* __restrict__ dtotal, int64_t cap,
+                                                         const uint64_t* __restrict__ tmp,
+                                                         const float* __restrict__ depth,
+                                                         const gs_item* __restrict__ items, int n_items, int64_t n,
+                                                         uint32_t* __restrict__ ranges, uint32_t* __restrict__ vals,
+                                                         uint64_t* __restrict__ keys) {
+  __shared__ __align__(16) uint64_t s[kShortKeys];
+  const int t = blockIdx.x;
+  int64_t start, L;
+  tile_span(offs, nblk, n_tiles, dtotal, cap, t, start, L);
+  if (threadIdx.x == 0) {
+    ranges[2 * (int64_t)t] = L > 0 ? (uint32_t)start : 0u;
+    ranges[2 * (int64_t)t + 1] = L > 0 ? (uint32_t)(start + L) : 0u;
+  }
+  if (L <= 0 || L > kShortKeys) return;
+  rank_sort_tile<256, kShortKeys>(s, tmp + start, (int)L, t, start, depth, items, n_items, n, vals, keys);
+}
+
+// Longer lists: blocks of 1024 threads walk the tiles; up to 8192 keys by rank, beyond that
+// the bitonic network.
+__global__ __launch_bounds__(kLongThreads) void k_tile_sort_long(const uint32_t* __restrict__ offs, int nblk,
+                                                                 int n_tiles, const uint64_t* __restrict__ dtotal,
+                                                                 int64_t cap, uint64_t* tmp,
+                                                                 const float* __restrict__ depth,
+                                                                 const gs_item* __restrict__ items, int n_items,
+                                                                 int64_t n, uint32_t* __restrict__ vals,
+                                                                 uint64_t* __restrict__ keys) {
+  __shared__ __align__(16) uint64_t s[kLongKeys];
+  __shared__ int s_list[kLongThreads];
+  __shared__ int s_n;
+  // the block's tiles are blockIdx.x + gridDim.x i: their spans are read in parallel, the long
+  // ones listed in LDS (kLongThreads per round)
+  for (int64_t t0 = blockIdx.x; t0 < n_tiles; t0 += (int64_t)gridDim.x * kLongThreads) {
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const int64_t tt = t0 + (int64_t)gridDim.x * threadIdx.x;
+    if (tt < n_tiles) {
+      int64_t st, ln;
+      tile_span(offs, nblk, n_tiles, dtotal, cap, (int)tt, st, ln);
+      if (ln > kShortKeys) s_list[atomicAdd(&s_n, 1)] = (int)tt;
+    }
+    __syncthreads();
+    const int nl = s_n;
+    for (int li = 0; li < nl; ++li) {
+      const int t = s_list[li];
+      int64_t start, L;
+      tile_span(offs, nblk, n_tiles, dtotal, cap, t, start, L);
+      if (L <= kLongKeys) {
+        rank_sort_tile<kLongThreads, kLongKeys>(s, tmp + start, (int)L, t, start, depth, items, n_items, n, vals,
+                                                keys);
+      } else {
+        uint64_t* g = tmp + start;
+        bitonic_tile<kLongThreads, kLongKeys>(s, g, L);
+        const int64_t item = keys ? item_of_tile(items, n_items, t) : 0;
+        for (int64_t i = threadIdx.x; i < L; i += kLongThreads) {
+          const uint64_t key = g[i];
+          const uint32_t gi = (uint32_t)key;
+          vals[start + i] = gi;
+          if (keys) {
+            const uint32_t db = gi < (uint64_t)n ? __float_as_uint(depth[item * n + gi]) : 0u;
+            keys[start + i] = ((uint64_t)(uint32_t)t << 32) | (uint64_t)db;
+          }
+        }
+      }
+      __syncthreads();   // s is reused by the block's next tile
+    }
+    __syncthreads();     // s_n and s_list are rewritten by the next round
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 struct SortWs {
@@ -697,7 +1082,90 @@ int radix_covered_bits(int bits) {
 
 }  // namespace
 
-size_t bin_sort_workspace(int64_t E, int64_t cap) { return plan_sort(E, cap, nullptr).bytes; }
+// Bucket path: block count of the pair kernels. Every block writes (and the scan reads) one
+// counter per tile, while fewer blocks leave each wave more groups of entries to walk one
+// after another; the two costs balance near 11 sqrt(E / tiles) blocks (at most 512, two per
+// compute unit, and at most 2^22 counters).
+int bucket_blocks(int64_t E, int64_t n_tiles) {
+  const int64_t groups = ceil_div(std::max<int64_t>(E, 1), 64);
+  const double bal = 11.0 * std::sqrt((double)std::max<int64_t>(E, 1) / (double)std::max<int64_t>(n_tiles, 1));
+  int64_t nb = std::min<int64_t>({(int64_t)512, ceil_div(groups, kBkWaves), std::max<int64_t>(16, (int64_t)bal)});
+  nb = std::min<int64_t>(nb, ((int64_t)1 << 22) / std::max<int64_t>(n_tiles, 1));
+  return (int)std::max<int64_t>(1, nb);
+}
+
+struct BucketWs {
+  uint32_t* hist;      // [n_tiles * nblk]
+  uint32_t* partial;   // scan partials
+  uint64_t* tmp;       // [cap]
+  uint64_t* counters;  // [0]: duplicate total
+  int nblk;
+  int64_t hist_n;
+  size_t bytes;
+};
+
+BucketWs plan_bucket(int64_t E, int64_t n_tiles, int64_t cap, void* base) {
+  BucketWs w{};
+  w.nblk = bucket_blocks(E, n_tiles);
+  w.hist_n = std::max<int64_t>(n_tiles, 0) * w.nblk;
+  const int64_t np = ceil_div(std::max<int64_t>(w.hist_n, 1), kScanTile) + 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const size_t o_hist = take(4 * (size_t)std::max<int64_t>(w.hist_n, 1)), o_part = take(4 * (size_t)np),
+               o_tmp = take(8 * (size_t)std::max<int64_t>(cap, 1)), o_cnt = take(8 * 4);
+  w.bytes = off;
+  if (base) {
+    char* b = static_cast<char*>(base);
+    w.hist = (uint32_t*)(b + o_hist);
+    w.partial = (uint32_t*)(b + o_part);
+    w.tmp = (uint64_t*)(b + o_tmp);
+    w.counters = (uint64_t*)(b + o_cnt);
+  }
+  return w;
+}
+
+// Automatic choice: the bucket path up to this many (item, Gaussian) entries (and up to
+// kBkMaxTiles tiles). Its per-tile sorts cost more than linear time in a list's length, and
+// the lists grow with the scene; the radix path's passes cost the same per duplicate whatever
+// the lists. (The autotuner times both methods on the workload itself.)
+constexpr int64_t kBucketMaxEntries = (int64_t)1 << 22;
+
+bool bucket_path(const gs_config& cfg, int64_t E, int n_tiles) {
+  if (n_tiles > kBkMaxTiles) return false;
+  return cfg.sort_mode == 2 || (cfg.sort_mode == 0 && E <= kBucketMaxEntries);
+}
+
+int launch_bucket_sort(const gs_config& cfg, const gs_projected& proj, const gs_item* items, int n_items, int64_t n,
+                       int n_tiles, int64_t cap, void* ws, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                       int64_t* n_dup_dev, int32_t* status_dev, hipStream_t s) {
+  const int64_t E = (int64_t)n_items * n;
+  BucketWs w = plan_bucket(E, n_tiles, cap, ws);
+  uint64_t* d_total = w.counters;
+  hipLaunchKernelGGL(k_bucket_pairs<true>, dim3(w.nblk), dim3(kBkThreads), 0, s, cfg, proj.radius, proj.depth,
+                     proj.rec, items, E, n, n_tiles, w.nblk, w.hist, cap, w.tmp, (const uint64_t*)nullptr,
+                     (int64_t*)nullptr, (int32_t*)nullptr);
+  const int st = device_scan(w.hist, w.hist, nullptr, w.hist_n, w.hist_n, w.partial, d_total, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_bucket_pairs<false>, dim3(w.nblk), dim3(kBkThreads), 0, s, cfg, proj.radius, proj.depth,
+                     proj.rec, items, E, n, n_tiles, w.nblk, w.hist, cap, w.tmp, (const uint64_t*)d_total, n_dup_dev,
+                     status_dev);
+  if (n_tiles > 0) {
+    hipLaunchKernelGGL(k_tile_sort_short, dim3((unsigned)n_tiles), dim3(256), 0, s, w.hist, w.nblk, n_tiles,
+                       (const uint64_t*)d_total, cap, w.tmp, proj.depth, items, n_items, n, ranges, vals, keys);
+    hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)std::min(n_tiles, 512)), dim3(kLongThreads), 0, s, w.hist,
+                       w.nblk, n_tiles, (const uint64_t*)d_total, cap, w.tmp, proj.depth, items, n_items, n, vals,
+                       keys);
+  }
+  return launch_status();
+}
+
+size_t bin_sort_workspace(int64_t E, int64_t cap, int64_t n_tiles) {
+  return std::max(plan_sort(E, cap, nullptr).bytes, plan_bucket(E, n_tiles, cap, nullptr).bytes);
+}
 
 int64_t scan_partials_needed(int64_t n) { return ceil_div(std::max<int64_t>(n, 1), kScanTile) + 2; }
 
@@ -709,6 +1177,10 @@ int launch_bin_sort(const gs_config& cfg, const gs_projected& proj, const gs_ite
                     int n_tiles, int64_t cap, void* ws, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                     int64_t* n_dup_dev, int32_t* status_dev, hipStream_t s) {
   const int64_t E = (int64_t)n_items * n;
+  if (cfg.sort_mode == 2 && n_tiles > kBkMaxTiles) return GS_ERR_UNSUPPORTED;
+  if (bucket_path(cfg, E, n_tiles))
+    return launch_bucket_sort(cfg, proj, items, n_items, n, n_tiles, cap, ws, keys, vals, ranges, n_dup_dev,
+                              status_dev, s);
   SortWs w = plan_sort(E, cap, ws);
   uint64_t* n_vis = w.counters + 0;
   uint64_t* d_total = w.counters + 1;

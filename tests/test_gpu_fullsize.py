@@ -10,6 +10,8 @@
   gradient confined to them;
 - the loss with the SSIM term over the full room pyramid.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -70,6 +72,19 @@ def test_full_size_sort_and_sampled_tiles(name):
     assert D == len(vals) and D > 100_000
     np.testing.assert_array_equal(st.sorter.vals[:D].cpu().numpy().view(np.uint32), vals)
     np.testing.assert_array_equal(st.sorter.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), ranges)
+    # both sort methods (gs_config.sort_mode 1: radix passes, 2: bucket path) on the same
+    # projections
+    for mode in (1, 2):
+        cfg = type(st.cfg)()
+        ctypes.memmove(ctypes.byref(cfg), ctypes.byref(st.cfg), ctypes.sizeof(cfg))
+        cfg.sort_mode = mode
+        other = raster.Sorter(cfg, st.frame, sc.n, st.sorter.capacity).run(st.proj)
+        torch.cuda.synchronize()
+        print(f"[full size] {name}: sort_mode {mode}", flush=True)
+        assert int(other.status.item()) == 0 and int(other.n_dup.item()) == D
+        np.testing.assert_array_equal(other.vals[:D].cpu().numpy().view(np.uint32), vals)
+        np.testing.assert_array_equal(other.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), ranges)
+        del other
 
     # sampled tiles: the longest lists and random ones
     its = oracle.items(views, *tile)

@@ -103,9 +103,9 @@ def test_preprocess_parity(case, isotropic):
     np.testing.assert_array_equal(depth[vis], ref["depth"][vis].astype(np.float32))
 
 
-def _check_sort(views, n, hi, lo, radius, depth, tile=(16, 16)):
+def _check_sort(views, n, hi, lo, radius, depth, tile=(16, 16), sort_mode=0):
     raster = _raster()
-    cfg = raster.config(0, tile_w=tile[0], tile_h=tile[1])
+    cfg = raster.config(0, tile_w=tile[0], tile_h=tile[1], sort_mode=sort_mode)
     fr = raster.Frame(cfg, views)
     E = fr.n_items * n
     rec = np.zeros((E, 8), np.float32)
@@ -126,40 +126,66 @@ def _check_sort(views, n, hi, lo, radius, depth, tile=(16, 16)):
     return D
 
 
+# gs_config.sort_mode: 1 radix passes, 2 bucket path (one counting pass by tile, then per-tile
+# depth sorts in LDS)
+SORT_MODES = [1, 2]
+
+
+@pytest.mark.parametrize("sort_mode", SORT_MODES)
 @pytest.mark.parametrize("seed,ties", [(1, True), (2, False), (3, True)])
-def test_bin_sort_bit_exact_synthetic(seed, ties):
+def test_bin_sort_bit_exact_synthetic(seed, ties, sort_mode):
     views = [scenes.identity_view(200, 120, levels=2), scenes.identity_view(64, 48, levels=1),
              scenes.identity_view(100, 70, levels=1)]
     sizes = [(it["W"], it["H"]) for it in oracle.items(views)]
     n = 3000
     hi, lo, radius, depth = scenes.synthetic_projection(sizes, n, seed=5000 + seed, tie_depths=ties)
-    assert _check_sort(views, n, hi, lo, radius, depth) > 10000
+    assert _check_sort(views, n, hi, lo, radius, depth, sort_mode=sort_mode) > 10000
 
 
-def test_bin_sort_bit_exact_on_oracle_projection():
+@pytest.mark.parametrize("sort_mode", SORT_MODES)
+def test_bin_sort_bit_exact_on_oracle_projection(sort_mode):
     # inputs: the oracle's own projection of a room scene, rounded to single precision
     sc, views = small_room(n=20000)
     ref = oracle.preprocess(oracle.Config(), sc, views)
     hi = ref["m2"].astype(np.float32)
     lo = (ref["m2"] - hi.astype(np.float64)).astype(np.float32)
-    _check_sort(views, sc.n, hi, lo, ref["radius"].astype(np.int32), ref["depth"].astype(np.float32))
+    _check_sort(views, sc.n, hi, lo, ref["radius"].astype(np.int32), ref["depth"].astype(np.float32),
+                sort_mode=sort_mode)
+
+
+@pytest.mark.parametrize("sort_mode", SORT_MODES)
+@pytest.mark.parametrize("n", [12000, 40000])
+def test_bin_sort_bit_exact_long_lists(n, sort_mode):
+    """A 64 x 48 image (12 tiles) under thousands of Gaussians of radius up to 40 px, depths
+    from a small set (index tie-breaks): tile lists of several thousand entries. The bucket
+    path (sort_mode 2) sorts lists of 1025 to 8192 keys by rank in its long-list kernel and
+    longer ones (n = 40000: above 16384) with the bitonic network in global memory."""
+    views = [scenes.identity_view(64, 48, levels=1)]
+    hi, lo, radius, depth = scenes.synthetic_projection([(64, 48)], n, seed=5030 + n, tie_depths=True)
+    _check_sort(views, n, hi, lo, radius, depth, sort_mode=sort_mode)
+    _, _, ranges = oracle.sort_stage(views, n, hi, lo, radius, depth)
+    longest = int((ranges[:, 1] - ranges[:, 0]).max())
+    print(f"[long lists] n {n}: longest list {longest}", flush=True)
+    assert longest > (4096 if n < 20000 else 16384)
 
 
 # 256-pixel tiles other than 16 x 16 (the autotuner's tile shapes)
 TILE_SHAPES = [(32, 8), (8, 32), (64, 4)]
 
 
+@pytest.mark.parametrize("sort_mode", SORT_MODES)
 @pytest.mark.parametrize("tile", TILE_SHAPES)
-def test_bin_sort_bit_exact_tile_shapes(tile):
+def test_bin_sort_bit_exact_tile_shapes(tile, sort_mode):
     views = [scenes.identity_view(200, 120, levels=2), scenes.identity_view(100, 70, levels=1)]
     sizes = [(it["W"], it["H"]) for it in oracle.items(views)]
     hi, lo, radius, depth = scenes.synthetic_projection(sizes, 3000, seed=5020, tie_depths=True)
-    assert _check_sort(views, 3000, hi, lo, radius, depth, tile) > 10000
+    assert _check_sort(views, 3000, hi, lo, radius, depth, tile, sort_mode) > 10000
     sc, views = small_room(n=20000)
     ref = oracle.preprocess(oracle.Config(tile_w=tile[0], tile_h=tile[1]), sc, views)
     hi = ref["m2"].astype(np.float32)
     lo = (ref["m2"] - hi.astype(np.float64)).astype(np.float32)
-    _check_sort(views, sc.n, hi, lo, ref["radius"].astype(np.int32), ref["depth"].astype(np.float32), tile)
+    _check_sort(views, sc.n, hi, lo, ref["radius"].astype(np.int32), ref["depth"].astype(np.float32), tile,
+                sort_mode)
 
 
 @pytest.mark.parametrize("tile", TILE_SHAPES)
@@ -186,12 +212,13 @@ def test_render_parity_tile_shapes(case, tile, variant):
     _check_render_bwd(case, *VARIANTS[variant], tile=tile)
 
 
-def test_bin_sort_capacity_overflow_reports_status():
+@pytest.mark.parametrize("sort_mode", SORT_MODES)
+def test_bin_sort_capacity_overflow_reports_status(sort_mode):
     raster = _raster()
     views = [scenes.identity_view(128, 96)]
     n = 500
     hi, lo, radius, depth = scenes.synthetic_projection([(128, 96)], n, seed=5010)
-    cfg = raster.config(0)
+    cfg = raster.config(0, sort_mode=sort_mode)
     fr = raster.Frame(cfg, views)
     rec = np.zeros((n, 8), np.float32)
     rec[:, 0:2], rec[:, 2:4] = hi, lo

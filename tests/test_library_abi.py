@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(L.Config) == 72
+    assert ctypes.sizeof(L.Config) == 76
     assert ctypes.sizeof(L.Targets) == 32
     assert ctypes.sizeof(L.Images) == 56
     assert ctypes.sizeof(L.View) == 56
@@ -43,7 +43,7 @@ def test_defaults_and_status_strings():
     assert c.alpha_min == pytest.approx(1 / 255) and c.alpha_max == pytest.approx(0.99)
     assert c.t_min == pytest.approx(1e-4) and c.z_near == pytest.approx(0.2)
     assert (c.variant, c.tile_order, c.fwd_chunk, c.ssim_lambda, c.isotropic, c.view_features) == (0, 0, 0, 0.0, 0, 0)
-    assert c.sem_ssim_lambda == 0.0 and c.seg_len == 0
+    assert c.sem_ssim_lambda == 0.0 and c.seg_len == 0 and c.sort_mode == 0
     assert lib.gs_status_string(L.GS_ERR_CAPACITY) == b"duplicate capacity exceeded"
     assert lib.gs_version() > 0
 
@@ -158,6 +158,26 @@ def test_config_segment_length():
     for good in (0, 256, 288, 1024, 4096, 1 << 20):
         c.seg_len = good
         assert lib.gs_workspace_size(L.GS_WS_LOSS, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == 0, good
+
+
+def test_config_sort_mode_and_workspace():
+    # 0 automatic, 1 radix passes, 2 bucket path; the bin-sort workspace covers both methods:
+    # at least the bucket path's 8-byte scatter keys
+    lib = L.lib()
+    c = L.Config()
+    lib.gs_config_default(ctypes.byref(c))
+    b = ctypes.c_size_t()
+    for bad in (-1, 3):
+        c.sort_mode = bad
+        assert lib.gs_workspace_size(L.GS_WS_BIN_SORT, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == \
+            L.GS_ERR_INVALID_ARG, bad
+    sizes = []
+    for good in (0, 1, 2):
+        c.sort_mode = good
+        assert lib.gs_workspace_size(L.GS_WS_BIN_SORT, ctypes.byref(c), 3, 1000, 50000, 10 ** 6, 100,
+                                     ctypes.byref(b)) == 0
+        sizes.append(b.value)
+    assert sizes[0] == sizes[1] == sizes[2] >= 8 * 10 ** 6
 
 
 def test_config_rejects_ssim_weight_outside_unit_interval():
