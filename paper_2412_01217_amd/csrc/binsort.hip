@@ -685,77 +685,111 @@ __device__ __forceinline__ void tile_span(const uint32_t* offs, int nblk, int n_
   len = min(b, cap) - start;
 }
 
-// Per-tile sort by rank. The list is cut into sub-lists of 256 keys; a wave owns whole
-// sub-lists (sub-list c: wave c mod W, lane l holding its keys l, l + 64, l + 128, l + 192),
-// so one broadcast LDS read of a sub-list key serves four comparisons per lane: a key's rank
-// within its sub-list is the number of smaller keys there. The sub-lists are then written
-// sorted, and the rank of the key at sorted position j in the whole list is j plus, for every
-// other sub-list, the number of its keys below the key (a binary search). Lists of up to CH
-// keys; T threads (W = T / 64).
+// Per-tile sort. The list is cut into sub-lists of 256 keys; a wave owns whole sub-lists
+// (sub-list c: wave c mod W), which it sorts in registers with Batcher's bitonic network,
+// four keys per lane (lane l ends with sorted positions 4 l .. 4 l + 3; steps between lanes
+// exchange keys by shuffles). A list of one sub-list is then written out directly. Otherwise
+// the sorted sub-lists go to LDS, and the rank of the key at sorted position j in the whole
+// list is j plus, for every other sub-list, the number of its keys below the key (a binary
+// search). Lists of up to CH keys; T threads (W = T / 64).
 constexpr int kSub = 256;
 
-template <int T, int CH>
-__device__ __forceinline__ void rank_sort_tile(uint64_t* s, const uint64_t* __restrict__ g, int L, int t,
-                                               int64_t start, const float* __restrict__ depth,
-                                               const gs_item* __restrict__ items, int n_items, int64_t n,
-                                               uint32_t* __restrict__ vals, uint64_t* __restrict__ keys) {
-  constexpr int W = T / 64, NS = CH / (kSub * W), R = kSub / 64;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < L; i += T) s[i] = g[i];
-  __syncthreads();
-  const int nsub = (L + kSub - 1) / kSub;
-  uint64_t k[NS][R];
-  uint32_t rk[NS][R];
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of the wave's 256 keys, lane l holding positions 4 l + r in v[r].
+// Stage (k, j) pairs position i with i ^ j; the pair's lower position takes the smaller key
+// when i & k is 0 (an ascending run), the larger one otherwise.
+__device__ __forceinline__ void wave_sort256(uint64_t (&v)[4]) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int q = 0; q < NS; ++q) {
-    const int c = wid + q * W, c0 = c * kSub, cl = min(kSub, L - c0);   // cl <= 0: no sub-list
+  for (int k = 2; k <= 256; k <<= 1) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int j = lane + 64 * r;
-      k[q][r] = j < cl ? s[c0 + j] : ~0ull;
-      rk[q][r] = 0;
-    }
-    if (cl <= 0) continue;   // uniform over the wave
-    // eight keys per round, read before any is compared (one LDS wait per round)
-    int j = 0;
-    for (; j + 8 <= cl; j += 8) {
-      uint64_t a[8];
+    for (int j = k >> 1; j >= 1; j >>= 1) {
+      if (j >= 4) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = s[c0 + j + u];
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * lane + r;
+          const uint64_t o = shfl_xor64(v[r], j >> 2);   // position i ^ j: lane ^ (j / 4), same r
+          const bool lt = v[r] < o;
+          const bool want_min = ((i & j) == 0) == ((i & k) == 0);
+          v[r] = (lt == want_min) ? v[r] : o;
+        }
+      } else {
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int r = 0; r < R; ++r) rk[q][r] += (uint32_t)(a[u] < k[q][r]);
-    }
-    for (; j < cl; ++j) {
-      const uint64_t a0 = s[c0 + j];
-#pragma unroll
-      for (int r = 0; r < R; ++r) rk[q][r] += (uint32_t)(a0 < k[q][r]);
+        for (int r = 0; r < 4; ++r) {
+          const int p = r ^ j;
+          if (p < r) continue;   // each in-lane pair once, at its lower position
+          const bool up = ((4 * lane + r) & k) == 0;
+          const uint64_t x = v[r], y = v[p];
+          const bool sw = up ? (y < x) : (x < y);
+          v[r] = sw ? y : x;
+          v[p] = sw ? x : y;
+        }
+      }
     }
   }
-  __syncthreads();
+}
+
+template <int T, int CH>
+__device__ __forceinline__ void sort_tile(uint64_t* s, const uint64_t* __restrict__ g, int L, int t, int64_t start,
+                                          const float* __restrict__ depth, const gs_item* __restrict__ items,
+                                          int n_items, int64_t n, uint32_t* __restrict__ vals,
+                                          uint64_t* __restrict__ keys) {
+  constexpr int W = T / 64, NS = CH / (kSub * W), R = kSub / 64;
+  static_assert(R == 4, "four keys per lane");
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nsub = (L + kSub - 1) / kSub;
+  uint64_t k[NS][R];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int c0 = (wid + q * W) * kSub, cl = min(kSub, L - c0);   // cl <= 0: no sub-list
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = lane * R + r;
+      k[q][r] = j < cl ? g[c0 + j] : ~0ull;   // past the list: +inf, sorted to the end
+    }
+    if (cl > 0) wave_sort256(k[q]);   // uniform over the wave
+  }
+  const int64_t item = keys ? item_of_tile(items, n_items, t) : 0;
+  if (nsub == 1) {
+    if (wid == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int j = lane * R + r;
+        if (j >= L) continue;
+        const uint32_t gi = (uint32_t)k[0][r];
+        vals[start + j] = gi;
+        if (keys) {
+          const uint32_t db = gi < (uint64_t)n ? __float_as_uint(depth[item * n + gi]) : 0u;
+          keys[start + j] = ((uint64_t)(uint32_t)t << 32) | (uint64_t)db;
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < NS; ++q) {
     const int c0 = (wid + q * W) * kSub, cl = min(kSub, L - c0);
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (lane + 64 * r < cl) s[c0 + rk[q][r]] = k[q][r];
+    for (int r = 0; r < R; ++r) {
+      const int j = lane * R + r;
+      if (j < cl) s[c0 + j] = k[q][r];
+    }
   }
   __syncthreads();
-  const int64_t item = keys ? item_of_tile(items, n_items, t) : 0;
 #pragma unroll
   for (int q = 0; q < NS; ++q) {
     const int own = wid + q * W, c0 = own * kSub, cl = min(kSub, L - c0);
     if (cl <= 0) continue;   // uniform over the wave
-    // lane l now takes positions 4 l .. 4 l + 3 of the sorted sub-list: neighbouring lanes
-    // search for neighbouring keys, so their LDS reads mostly meet at the same addresses
+    // lane l holds positions 4 l .. 4 l + 3 of the sorted sub-list: neighbouring lanes search
+    // for neighbouring keys, so their LDS reads mostly meet at the same addresses
     uint32_t rank[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int j = lane * R + r;
-      rank[r] = (uint32_t)j;
-      k[q][r] = j < cl ? s[c0 + j] : ~0ull;
-    }
+    for (int r = 0; r < R; ++r) rank[r] = (uint32_t)(lane * R + r);
     // the other sub-lists four at a time, the 4 x R searches in lockstep (branch-free lower
     // bound by binary lifting: pos grows by each power of two while the key at pos + step - 1
     // is below the searched key), so that their LDS reads overlap
@@ -789,8 +823,7 @@ __device__ __forceinline__ void rank_sort_tile(uint64_t* s, const uint64_t* __re
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (lane * R + r >= cl) continue;
-      const uint64_t key = k[q][r];
-      const uint32_t gi = (uint32_t)key;
+      const uint32_t gi = (uint32_t)k[q][r];
       vals[start + rank[r]] = gi;
       if (keys) {
         const uint32_t db = gi < (uint64_t)n ? __float_as_uint(depth[item * n + gi]) : 0u;
@@ -896,7 +929,7 @@ __global__ __launch_bounds__(256) void k_tile_sort_short(const uint32_t* __restr
     ranges[2 * (int64_t)t + 1] = L > 0 ? (uint32_t)(start + L) : 0u;
   }
   if (L <= 0 || L > kShortKeys) return;
-  rank_sort_tile<256, kShortKeys>(s, tmp + start, (int)L, t, start, depth, items, n_items, n, vals, keys);
+  sort_tile<256, kShortKeys>(s, tmp + start, (int)L, t, start, depth, items, n_items, n, vals, keys);
 }
 
 // Longer lists: blocks of 1024 threads walk the tiles; up to 8192 keys by rank, beyond that
@@ -929,8 +962,7 @@ __global__ __launch_bounds__(kLongThreads) void k_tile_sort_long(const uint32_t*
       int64_t start, L;
       tile_span(offs, nblk, n_tiles, dtotal, cap, t, start, L);
       if (L <= kLongKeys) {
-        rank_sort_tile<kLongThreads, kLongKeys>(s, tmp + start, (int)L, t, start, depth, items, n_items, n, vals,
-                                                keys);
+        sort_tile<kLongThreads, kLongKeys>(s, tmp + start, (int)L, t, start, depth, items, n_items, n, vals, keys);
       } else {
         uint64_t* g = tmp + start;
         bitonic_tile<kLongThreads, kLongKeys>(s, g, L);
