@@ -610,32 +610,41 @@ __global__ __launch_bounds__(kBkThreads) void k_bucket_pairs(gs_config cfg, cons
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t n_groups = (E + 63) >> 6, stride = (int64_t)nblk * kBkWaves;
-  // groups of 64 consecutive entries, the block's waves on consecutive groups in each round;
-  // the radii of a wave's next group are loaded one group ahead
+  // groups of 64 consecutive entries, the block's waves on consecutive groups in each round.
+  // Loads run ahead of use: a group's records (and depths) are loaded one group ahead, from
+  // radii loaded two groups ahead, so that a group's work waits on no memory round trip.
   int64_t grp = (int64_t)b * kBkWaves + wid;
-  int r_next = grp * 64 + lane < E ? radius[grp * 64 + lane] : 0;
+  auto radius_of = [&](int64_t gq) { return gq * 64 + lane < E ? radius[gq * 64 + lane] : 0; };
+  auto rec_of = [&](int64_t gq, int r) {
+    return r > 0 ? *reinterpret_cast<const float4*>(rec + (int64_t)kRecFloats * (gq * 64 + lane))
+                 : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  auto depth_of = [&](int64_t gq, int r) { return (!COUNT && r > 0) ? depth[gq * 64 + lane] : 0.f; };
+  int r1 = radius_of(grp), r2 = radius_of(grp + stride);
+  float4 m1 = rec_of(grp, r1);
+  float d1 = depth_of(grp, r1);
   for (; grp < n_groups; grp += stride) {
     const int64_t e = grp * 64 + lane;
-    const int r = r_next;
-    const int64_t en = (grp + stride) * 64 + lane;
-    r_next = en < E ? radius[en] : 0;
+    const int r = r1;
+    const float4 mr = m1;
+    const float dr = d1;
+    r1 = r2;
+    m1 = rec_of(grp + stride, r1);
+    d1 = depth_of(grp + stride, r1);
+    r2 = radius_of(grp + 2 * stride);
     uint32_t c = 0;
     int4 rc = make_int4(0, 1, 0, 0);
     uint64_t key = 0;
-    if (e < E) {
-      if (r > 0) {
-        const uint32_t item = (uint32_t)e / (uint32_t)n;   // entries fit 32 bits
-        const gs_item it = items[item];
-        const Rect R = tile_rect(cfg, it.tiles_x, it.tiles_y,
-                                 *reinterpret_cast<const float4*>(rec + (int64_t)kRecFloats * e), r);
-        const int w = R.x1 - R.x0;
-        c = (uint32_t)(w * (R.y1 - R.y0));
-        rc = make_int4(R.x0, w, it.tiles_x, it.tile_base + R.y0 * it.tiles_x);
-        // a visible depth is above z_near > 0 (the mask keeps the sign bit out of the order)
-        if (!COUNT)
-          key = ((uint64_t)(__float_as_uint(depth[e]) & 0x7fffffffu) << 32) |
-                (uint64_t)((uint32_t)e - item * (uint32_t)n);
-      }
+    if (r > 0) {   // (r is 0 past the entries)
+      const uint32_t item = (uint32_t)e / (uint32_t)n;   // entries fit 32 bits
+      const gs_item it = items[item];
+      const Rect R = tile_rect(cfg, it.tiles_x, it.tiles_y, mr, r);
+      const int w = R.x1 - R.x0;
+      c = (uint32_t)(w * (R.y1 - R.y0));
+      rc = make_int4(R.x0, w, it.tiles_x, it.tile_base + R.y0 * it.tiles_x);
+      // a visible depth is above z_near > 0 (the mask keeps the sign bit out of the order)
+      if (!COUNT)
+        key = ((uint64_t)(__float_as_uint(dr) & 0x7fffffffu) << 32) | (uint64_t)((uint32_t)e - item * (uint32_t)n);
     }
     uint32_t inc = c;
 #pragma unroll

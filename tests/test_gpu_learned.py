@@ -273,3 +273,18 @@ def test_fused_and_unfused_learned_steps_agree():
         a, b = out[0][1][k], out[1][1][k]
         scale = max(float(np.abs(b).max()), 1e-20)
         assert float(np.abs(a - b).max()) <= 1e-4 * scale, k
+
+
+def test_trained_head_reaches_99_percent_agreement():
+    """The agreement the benchmark reports, asserted: the embedding and the 16 -> 64 -> 52 head
+    trained for 2000 steps (a fresh random 640x480 view with 3 levels per step) on the
+    500k-Gaussian room with 52 classes; the learned render's per-pixel argmax agrees with the
+    plain 52-class render's on at least 99 % of the pixels of 16 held-out views."""
+    import bench
+    sc, _ = scenes.config_learned()
+    test_views = scenes.room_views(sc, 16, 640, 480, levels=3, seed=scenes.SEED_VIEWS + 61)
+    rep, _, _ = bench.train_head(sc, "cuda:0", 2000, test_views, 10000)
+    print(f"[learned] agreement {rep['argmax_agreement']:.4f} on {rep['heldout_pixels']} held-out pixels "
+          f"(untrained {rep['head_training']['agreement_untrained']:.4f}), {rep['head_training']['seconds']:.1f} s",
+          flush=True)
+    assert rep["argmax_agreement"] >= 0.99
