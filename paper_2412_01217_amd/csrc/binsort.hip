@@ -261,20 +261,21 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const Key* __restr
   const int64_t count = (int64_t)*count_dev;
   const int64_t base = (int64_t)blockIdx.x * kRadixTile * sub;
   const int64_t end = min(count, base + (int64_t)kRadixTile * sub);
-  const uint64_t lt = lanemask_lt();
   // every block writes its counts (zeros past the live keys): the scan reads them all
   for (int64_t i0 = base + (threadIdx.x & ~63); i0 < end; i0 += kRadixThreads) {
     const int64_t idx = i0 + (threadIdx.x & 63);
     const bool ok = idx < end;
     const uint32_t d = ok ? (uint32_t)(keys[idx] >> shift) & (uint32_t)(ND - 1) : 0u;
-    // one LDS atomic per distinct digit of the wave: keys of one pass share few digits
-    uint64_t peers = __ballot(ok);
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const uint64_t m = __ballot((d >> b) & 1u);
-      peers &= ((d >> b) & 1u) ? m : ~m;
+    // one LDS atomic per key, or one for the whole wave when all its keys share the digit (the
+    // top digits of sorted or tied keys); grouping equal digits by ballots cost more than the
+    // atomics' bank conflicts save
+    const uint64_t act = __ballot(ok);
+    const uint32_t d0 = (uint32_t)__shfl((int)d, 0, 64);
+    if (__ballot(ok && d == d0) == act && (act & 1ull)) {
+      if ((threadIdx.x & 63) == 0) atomicAdd(&h[d0], (uint32_t)__popcll(act));
+    } else if (ok) {
+      atomicAdd(&h[d], 1u);
     }
-    if (ok && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
   }
   __syncthreads();
   for (int d = threadIdx.x; d < ND; d += kRadixThreads) hist[(int64_t)d * nblk + blockIdx.x] = h[d];
