@@ -143,8 +143,8 @@ typedef struct gs_images {
   int64_t n_pixels;      /* P, the total pixel count of all items (read in learned mode) */
   /* Forward output, optional (NULL: none; ignored by render variants 1 and 2): a caller
    * buffer of state_bytes >= gs_workspace_size(GS_WS_RENDER_STATE) bytes. With it, the
-   * forward cuts tile lists longer than 256 entries into 256-entry segments composited
-   * in parallel (a transmittance pre-pass gives each its starting T) and keeps, per
+   * forward cuts tile lists into segments of cfg->seg_len entries, walked fwd_chunk at a
+   * time (a transmittance pre-pass gives each work item its starting T), and keeps, per
    * segment and pixel, what the reverse pass needs to start a segment: gs_render_bwd
    * given these images then skips its summary pass. Overwritten by every forward; read
    * by the backward, which must get the same images. */
@@ -207,8 +207,11 @@ int gs_make_items(const gs_config* cfg, int32_t n_views, gs_view* views, const i
 
 /* Bytes of caller workspace a call needs (kind = gs_workspace_kind). GS_WS_RENDER_STATE
  * (the optional gs_images.state of a forward) depends on n_tiles, dup_capacity (the
- * bin_sort capacity the lists come from) and cfg->n_sem; a smaller buffer still works
- * when the lists' segments fit it, and makes every tile one item when they do not. */
+ * bin_sort capacity the lists come from), cfg->n_sem and cfg->seg_len; GS_WS_RENDER_BWD
+ * on n_items * n_gauss, n_tiles, dup_capacity and cfg->seg_len. Both hold at most one
+ * segment per tile more than dup_capacity / seg_len, so a buffer sized for one segment
+ * length holds fewer segments of a shorter one. A smaller buffer still works when the
+ * lists' segments fit it, and makes every tile one item when they do not. */
 int gs_workspace_size(int kind, const gs_config* cfg, int32_t n_items, int64_t n_gauss, int32_t n_tiles,
                       int64_t dup_capacity, int64_t n_pixels, size_t* bytes);
 

@@ -39,10 +39,11 @@ int launch_render_fwd_split(GS_RENDER_FWD_ARGS);
 int launch_render_bwd_split(const gs_config&, const gs_gaussians&, const gs_projected&, const gs_item*, int, int,
                             const uint32_t*, const uint32_t*, const gs_images&, const gs_images&, float*,
                             const gs_grads&, void*, int64_t, hipStream_t);
-size_t render_seg_workspace(int n_tiles, int64_t dup_capacity);
-int64_t render_seg_capacity(int n_tiles, size_t bytes);
-size_t render_state_bytes(int n_tiles, int64_t dup_capacity, int K);
-int64_t render_state_capacity(int n_tiles, int K, size_t bytes);
+size_t render_seg_workspace(int n_tiles, int64_t dup_capacity, int seg);
+int64_t render_seg_capacity(int n_tiles, int seg, size_t bytes);
+int render_seg_len(const gs_config& cfg);
+size_t render_state_bytes(int n_tiles, int64_t dup_capacity, int K, int seg);
+int64_t render_state_capacity(int n_tiles, int K, int seg, size_t bytes);
 
 // Render kernel variants: 1 = per-lane FMA accumulation (VALU), 2 = single-precision
 // matrix-core channel contraction, 3 = every contraction on the bfloat16 matrix cores with
@@ -217,13 +218,13 @@ int gs_workspace_size(int kind, const gs_config* cfg, int32_t n_items, int64_t n
       return GS_OK;
     case GS_WS_RENDER_BWD:
       *bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)n_gauss) + align_up(head_bwd_workspace()) +
-               render_seg_workspace(n_tiles, dup_capacity);
+               render_seg_workspace(n_tiles, dup_capacity, render_seg_len(*cfg));
       return GS_OK;
     case GS_WS_LOSS:
       *bytes = align_up(loss_workspace(n_items));
       return GS_OK;
     case GS_WS_RENDER_STATE:
-      *bytes = render_state_bytes(n_tiles, dup_capacity, 4 + cfg->n_sem);
+      *bytes = render_state_bytes(n_tiles, dup_capacity, 4 + cfg->n_sem, render_seg_len(*cfg));
       return GS_OK;
     default:
       return GS_ERR_INVALID_ARG;
@@ -265,7 +266,8 @@ int gs_render_fwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   if (!learned && cfg->n_sem > 0 && g->n > 0 && !g->sem) return GS_ERR_INVALID_ARG;
   if (n_tiles > 0) {
     if (!items_dev || !vals || !ranges || !out->color || !out->T || !out->n_contrib) return GS_ERR_INVALID_ARG;
-    if (out->state && render_state_capacity(n_tiles, 4 + cfg->n_sem, out->state_bytes) < 0) return GS_ERR_WORKSPACE;
+    if (out->state && render_state_capacity(n_tiles, 4 + cfg->n_sem, render_seg_len(*cfg), out->state_bytes) < 0)
+      return GS_ERR_WORKSPACE;
   }
   hipStream_t s = (hipStream_t)stream;
   int st = launch_render_fwd(*cfg, *g, *proj, items_dev, n_items, n_tiles, vals, ranges, *out, s);
@@ -384,14 +386,15 @@ int gs_render_bwd(const gs_config* cfg, const gs_gaussians* g, const gs_projecte
   const bool render = g->n > 0 && n_tiles > 0;
   if (render) {
     if (!items_dev || !vals || !ranges || !fwd->T || !fwd->n_contrib || !grad_in->color) return GS_ERR_INVALID_ARG;
-    if (fwd->state && render_state_capacity(n_tiles, 4 + cfg->n_sem, fwd->state_bytes) < 0) return GS_ERR_WORKSPACE;
+    if (fwd->state && render_state_capacity(n_tiles, 4 + cfg->n_sem, render_seg_len(*cfg), fwd->state_bytes) < 0)
+      return GS_ERR_WORKSPACE;
   }
   const size_t rec_bytes = align_up(sizeof(float) * kSortBwdRecord * (size_t)n_items * (size_t)g->n);
   const size_t head_bytes = align_up(head_bwd_workspace());
   if (!workspace || ws_bytes < rec_bytes + head_bytes) return GS_ERR_WORKSPACE;
   // the rest holds the segment work list of the reverse pass, sized for a duplicate
   // capacity (0 still works: every tile is then one work item)
-  const int64_t cap = render_seg_capacity(n_tiles, ws_bytes - rec_bytes - head_bytes);
+  const int64_t cap = render_seg_capacity(n_tiles, render_seg_len(*cfg), ws_bytes - rec_bytes - head_bytes);
   if (cap < 0) return GS_ERR_WORKSPACE;
   void* seg_ws = (char*)workspace + rec_bytes + head_bytes;
   hipStream_t s = (hipStream_t)stream;

@@ -281,8 +281,10 @@ struct SStage {
 // takes every segment as a work item of its own; the forward walks up to `chunk`
 // consecutive segments of a list in one work item (one sequential transmittance chain),
 // so that only lists longer than a chunk need a starting transmittance from a pre-pass.
-// Workspaces are sized for the shortest segments, kSegMin; seg_len = 0 selects kSegDefault.
-constexpr int kSegMin = 256, kSegDefault = 1024;
+// The forward state and the reverse pass's segment list are sized for the configured length
+// (at most one segment per tile more than the duplicates over it); seg_len = 0 selects
+// kSegDefault.
+constexpr int kSegDefault = 1024;
 __host__ __device__ inline int seg_len(const gs_config& cfg) { return cfg.seg_len > 0 ? cfg.seg_len : kSegDefault; }
 
 // Segments per forward work item (cfg.fwd_chunk; 0 = the whole list).
@@ -1300,7 +1302,8 @@ __global__ __launch_bounds__(256, 2) void k_render_bwd_split(gs_config cfg, cons
   }
 }
 
-// Caller workspace of the reverse pass: the segment work list, sized for `cap` duplicates.
+// Caller workspace of the reverse pass: the segment work list, sized for `cap` duplicates in
+// segments of `seg` list positions (at most one more segment per tile than cap / seg).
 struct SegWs {
   uint32_t *lmax, *cnt, *base, *partial, *ctl;
   uint64_t* total;
@@ -1309,8 +1312,8 @@ struct SegWs {
   int64_t max_segs;
 };
 
-size_t seg_layout(int n_tiles, int64_t cap, char* base, SegWs* w) {
-  const int64_t max_segs = (int64_t)n_tiles + ceil_div(cap, kSegMin) + 1;
+size_t seg_layout(int n_tiles, int64_t cap, int seg, char* base, SegWs* w) {
+  const int64_t max_segs = (int64_t)n_tiles + ceil_div(cap, seg) + 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -1341,8 +1344,8 @@ size_t seg_layout(int n_tiles, int64_t cap, char* base, SegWs* w) {
   return off;
 }
 
-// Caller buffer of a splitting forward (its saved state), sized for `cap` duplicates and
-// K channels.
+// Caller buffer of a splitting forward (its saved state), sized for `cap` duplicates, K
+// channels and segments of `seg` list positions.
 struct FLayout {
   FState fs;
   uint32_t *cnt, *base, *partial, *ctl;
@@ -1351,8 +1354,8 @@ struct FLayout {
   int64_t max_segs;
 };
 
-size_t fstate_layout(int n_tiles, int64_t cap, int K, char* base, FLayout* w) {
-  const int64_t max_segs = (int64_t)n_tiles + ceil_div(cap, kSegMin) + 1;
+size_t fstate_layout(int n_tiles, int64_t cap, int K, int seg, char* base, FLayout* w) {
+  const int64_t max_segs = (int64_t)n_tiles + ceil_div(cap, seg) + 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -1391,18 +1394,20 @@ size_t fstate_layout(int n_tiles, int64_t cap, int K, char* base, FLayout* w) {
 
 }  // namespace
 
-size_t render_state_bytes(int n_tiles, int64_t dup_capacity, int K) {
-  return fstate_layout(n_tiles, std::max<int64_t>(dup_capacity, 0), K, nullptr, nullptr);
+int render_seg_len(const gs_config& cfg) { return seg_len(cfg); }
+
+size_t render_state_bytes(int n_tiles, int64_t dup_capacity, int K, int seg) {
+  return fstate_layout(n_tiles, std::max<int64_t>(dup_capacity, 0), K, seg, nullptr, nullptr);
 }
 
 // Largest duplicate capacity whose forward state fits in `bytes` (-1 if none does).
-int64_t render_state_capacity(int n_tiles, int K, size_t bytes) {
-  if (render_state_bytes(n_tiles, 0, K) > bytes) return -1;
+int64_t render_state_capacity(int n_tiles, int K, int seg, size_t bytes) {
+  if (render_state_bytes(n_tiles, 0, K, seg) > bytes) return -1;
   int64_t lo = 0, hi = 1;
-  while (hi < ((int64_t)1 << 40) && render_state_bytes(n_tiles, hi, K) <= bytes) hi *= 2;
+  while (hi < ((int64_t)1 << 40) && render_state_bytes(n_tiles, hi, K, seg) <= bytes) hi *= 2;
   while (hi - lo > 1) {
     const int64_t mid = lo + (hi - lo) / 2;
-    if (render_state_bytes(n_tiles, mid, K) <= bytes) lo = mid; else hi = mid;
+    if (render_state_bytes(n_tiles, mid, K, seg) <= bytes) lo = mid; else hi = mid;
   }
   return lo;
 }
@@ -1410,18 +1415,18 @@ int64_t render_state_capacity(int n_tiles, int K, size_t bytes) {
 namespace {
 
 // Forward state of images `im` (fs.tcnt == nullptr if there is none).
-FLayout state_of(const gs_images& im, int n_tiles, int K) {
+FLayout state_of(const gs_images& im, int n_tiles, int K, int seg) {
   FLayout w{};
   if (!im.state) return w;
-  const int64_t cap = render_state_capacity(n_tiles, K, im.state_bytes);
-  if (cap >= 0) fstate_layout(n_tiles, cap, K, (char*)im.state, &w);
+  const int64_t cap = render_state_capacity(n_tiles, K, seg, im.state_bytes);
+  if (cap >= 0) fstate_layout(n_tiles, cap, K, seg, (char*)im.state, &w);
   return w;
 }
 
 template <int NS>
 int launch_fwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected& p, const gs_item* items, int n_items,
                  int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& out, hipStream_t s) {
-  const FLayout w = state_of(out, n_tiles, 4 + cfg.n_sem);
+  const FLayout w = state_of(out, n_tiles, 4 + cfg.n_sem, seg_len(cfg));
   if (!w.fs.tcnt) {
     hipLaunchKernelGGL((k_render_fwd_split<NS, false>), dim3(n_tiles), dim3(256), 0, s, cfg, g.rgb, g.sem, g.emb,
                        cfg.n_sem, p.rec, p.depth, g.n, items, n_items, vals, ranges, out.color, out.T, out.n_contrib,
@@ -1456,9 +1461,9 @@ int launch_bwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected
                  int n_tiles, const uint32_t* vals, const uint32_t* ranges, const gs_images& fwd,
                  const gs_images& gin, float* g2d, const gs_grads& gr, void* seg_ws, int64_t cap, hipStream_t s) {
   SegWs w;
-  seg_layout(n_tiles, cap, (char*)seg_ws, &w);
+  seg_layout(n_tiles, cap, seg_len(cfg), (char*)seg_ws, &w);
   // with the forward's saved state the segments start from it: no summary pass
-  const FState fs = state_of(fwd, n_tiles, 4 + cfg.n_sem).fs;
+  const FState fs = state_of(fwd, n_tiles, 4 + cfg.n_sem, seg_len(cfg)).fs;
   hipLaunchKernelGGL(k_seg_count, dim3(n_tiles), dim3(256), 0, s, items, n_items, ranges, fwd.n_contrib, n_tiles,
                      cfg.tile_order, tile_shift(cfg), (uint32_t)seg_len(cfg), fs.tcnt, w.lmax, w.cnt);
   int st = launch_status();
@@ -1481,18 +1486,18 @@ int launch_bwd_s(const gs_config& cfg, const gs_gaussians& g, const gs_projected
 
 }  // namespace
 
-size_t render_seg_workspace(int n_tiles, int64_t dup_capacity) {
-  return seg_layout(n_tiles, std::max<int64_t>(dup_capacity, 0), nullptr, nullptr);
+size_t render_seg_workspace(int n_tiles, int64_t dup_capacity, int seg) {
+  return seg_layout(n_tiles, std::max<int64_t>(dup_capacity, 0), seg, nullptr, nullptr);
 }
 
 // Largest duplicate capacity whose segment workspace fits in `bytes` (-1 if none does).
-int64_t render_seg_capacity(int n_tiles, size_t bytes) {
-  if (render_seg_workspace(n_tiles, 0) > bytes) return -1;
+int64_t render_seg_capacity(int n_tiles, int seg, size_t bytes) {
+  if (render_seg_workspace(n_tiles, 0, seg) > bytes) return -1;
   int64_t lo = 0, hi = 1;
-  while (hi < ((int64_t)1 << 40) && render_seg_workspace(n_tiles, hi) <= bytes) hi *= 2;
+  while (hi < ((int64_t)1 << 40) && render_seg_workspace(n_tiles, hi, seg) <= bytes) hi *= 2;
   while (hi - lo > 1) {
     const int64_t mid = lo + (hi - lo) / 2;
-    if (render_seg_workspace(n_tiles, mid) <= bytes) lo = mid; else hi = mid;
+    if (render_seg_workspace(n_tiles, mid, seg) <= bytes) lo = mid; else hi = mid;
   }
   return lo;
 }

@@ -117,10 +117,19 @@ def test_forward_state_size_and_host_check():
     assert lib.gs_workspace_size(L.GS_WS_RENDER_STATE, ctypes.byref(c), 3, 100, 40, 10000, 0, ctypes.byref(b1)) == 0
     c.n_sem = 20
     assert lib.gs_workspace_size(L.GS_WS_RENDER_STATE, ctypes.byref(c), 3, 100, 40, 10000, 0, ctypes.byref(b2)) == 0
-    # one slot per tile (and one spare) at capacity 0, 40 more segments at 10000 duplicates
-    assert b0.value >= 41 * 256 * 4 * (4 + 12 + 3)
-    assert b1.value - b0.value >= 40 * 256 * 4 * (4 + 12 + 3)
+    # one slot per tile (and one spare) at capacity 0, ceil(10000 / 1024) = 10 more segments
+    # of the default length at 10000 duplicates
+    slot = 256 * 4 * (4 + 12 + 3)
+    assert b0.value >= 41 * slot
+    assert 10 * slot <= b1.value - b0.value < 11 * slot
     assert b2.value > b1.value
+    # sized for the configured segment length: 40 more at 256 entries, 3 more at 4096
+    for seg, more in ((256, 40), (4096, 3)):
+        c.n_sem, c.seg_len = 12, seg
+        bs = ctypes.c_size_t()
+        assert lib.gs_workspace_size(L.GS_WS_RENDER_STATE, ctypes.byref(c), 3, 100, 40, 10000, 0, ctypes.byref(bs)) == 0
+        assert more * slot <= bs.value - b0.value < (more + 1) * slot, seg
+    c.seg_len = 0
     c.n_sem = 12
     fake = ctypes.c_void_p(256)
     g = L.Gaussians(10, fake, fake, fake, fake, fake, fake, None)
@@ -145,8 +154,8 @@ def test_config_rejects_out_of_range_forward_chunk():
 
 
 def test_config_segment_length():
-    # split lists' segments: 0 (1024 entries) or a multiple of 32 from 256 (the forward
-    # state's slots are sized for 256-entry segments) to 2^20
+    # split lists' segments: 0 (1024 entries) or a multiple of 32 from 256 to 2^20; the
+    # reverse pass's workspace holds more segments, so is larger, for shorter ones
     lib = L.lib()
     c = L.Config()
     lib.gs_config_default(ctypes.byref(c))
@@ -158,6 +167,13 @@ def test_config_segment_length():
     for good in (0, 256, 288, 1024, 4096, 1 << 20):
         c.seg_len = good
         assert lib.gs_workspace_size(L.GS_WS_LOSS, ctypes.byref(c), 1, 10, 4, 100, 100, ctypes.byref(b)) == 0, good
+    sizes = []
+    for seg in (256, 1024, 4096):
+        c.seg_len = seg
+        assert lib.gs_workspace_size(L.GS_WS_RENDER_BWD, ctypes.byref(c), 3, 1000, 40, 10 ** 6, 100,
+                                     ctypes.byref(b)) == 0
+        sizes.append(b.value)
+    assert sizes[0] > sizes[1] > sizes[2]
 
 
 def test_config_sort_mode_and_workspace():
