@@ -542,8 +542,13 @@ int gs_graph_end(void* stream, void** graph_exec) {
   if (st) return st;
   hipGraphExec_t exec = nullptr;
   st = hip_status(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  hipGraphDestroy(graph);
+  // the captured graph is not needed once instantiated
+  const int dst = hip_status(hipGraphDestroy(graph));
   if (st) return st;
+  if (dst) {
+    (void)hipGraphExecDestroy(exec);
+    return dst;
+  }
   *graph_exec = (void*)exec;
   return GS_OK;
 }
